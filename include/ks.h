@@ -1,0 +1,228 @@
+/*
+ * ks.h — C ABI of the MI355X (gfx950) Kohn-Sham direct-minimisation library.
+ *
+ * The library minimises the discretised Kohn-Sham total energy over the Stiefel
+ * manifold, min E(X) s.t. X^T X = I_p (Zhang, Zhu, Wen, Zhou, "Gradient type
+ * optimization methods for electronic structure calculations", Section 3 eq. (opt)),
+ * without linear eigensolves.  Every step on the data path runs in HIP kernels on
+ * the device; the host side only orders launches and reads back a few scalars.
+ *
+ * Conventions shared by all calls
+ * -------------------------------
+ * - Grid.  A uniform interior grid of nx*ny*nz points with spacing h; point (i,j,k)
+ *   (0-based) sits at box_lo + ((i+1)h, (j+1)h, (k+1)h) and has linear index
+ *   g = i + nx*(j + ny*k).  Values outside the interior grid are zero (Dirichlet).
+ * - Orbital blocks (X, G, gradE) are device pointers to n x p matrices stored
+ *   grid-major: element (g, i) at [g*ld + i], ld >= p given in the descriptor.
+ *   The element type is double (KS_PREC_FP64) or float (KS_PREC_FP32 and
+ *   KS_PREC_MIXED_BF16).  Density and potentials are double device vectors of n.
+ * - Energy units are Hartree, lengths bohr.  Orbitals are normalised by
+ *   X^T X = I, i.e. phi_i(r_g) = X_gi h^{-3/2}; the density is
+ *   rho_g = (f/h^3) sum_i X_gi^2 with occupation f per orbital.
+ * - Memory.  The caller owns every device buffer, including the workspace handed
+ *   to ks_create_system; the library never allocates or frees device memory.
+ *   The library allocates a small pinned host buffer per system for scalar
+ *   read-back (freed by ks_destroy_system).
+ * - Streams.  Work of a system is issued on the HIP stream given at creation.  All
+ *   calls below return after that stream has finished the call's work
+ *   (synchronous), unless stated otherwise.  One system handle must not be used
+ *   from two threads at once; different handles are independent.
+ * - Errors.  Every int-returning call returns KS_OK (0) or a negative KS_E_*
+ *   code; no exception crosses the ABI.  ks_last_error() gives a message.
+ */
+#ifndef KS_H
+#define KS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------------------- */
+#define KS_OK 0
+#define KS_E_INVAL (-1)          /* bad argument or descriptor                            */
+#define KS_E_NOMEM (-2)          /* workspace smaller than ks_workspace_bytes()           */
+#define KS_E_HIP (-3)            /* a HIP runtime call failed                             */
+#define KS_E_NOT_SPD (-4)        /* Cholesky breakdown (Y^T Y or X^T X not positive def.) */
+#define KS_E_SINGULAR (-5)       /* singular Sherman-Morrison-Woodbury system (WY)        */
+#define KS_E_NONFINITE (-6)      /* NaN or Inf in an energy, gradient or step             */
+#define KS_E_NOT_CONVERGED (-7)  /* ks_minimize stopped at max_iter                       */
+#define KS_E_UNSUPPORTED (-8)    /* combination not implemented                           */
+
+/* ---- enums ------------------------------------------------------------------------- */
+#define KS_DISC_FD7 0            /* 7-point finite differences (Section 2.3)              */
+#define KS_DISC_Q1 1             /* trilinear finite elements, B-orthonormality           */
+
+#define KS_PREC_FP64 0           /* everything in double                                  */
+#define KS_PREC_FP32 1           /* X, G stored/applied in float; reductions in double    */
+#define KS_PREC_MIXED_BF16 2     /* as FP32, Gram products in bf16 MFMA, fp32 accumulate  */
+
+#define KS_TERM_EXT 1            /* external (nuclear) potential                          */
+#define KS_TERM_HARTREE 2        /* Hartree potential                                     */
+#define KS_TERM_XC 4             /* Slater exchange                                       */
+#define KS_TERM_ALL 7
+
+#define KS_HARTREE_CG 0          /* plain conjugate gradients, warm started               */
+#define KS_HARTREE_PCG_FD 1      /* CG preconditioned by the exact fast diagonalisation   */
+
+#define KS_QR 0                  /* retraction eq. (QR) by Cholesky QR (Alg. 2)           */
+#define KS_WY 1                  /* Cayley retraction eq. (WY3)                           */
+
+#define KS_BB_ALT 0              /* tau_{k,1} on odd k, tau_{k,2} on even k               */
+#define KS_BB1 1
+#define KS_BB2 2
+
+#define KS_STOP_NONE 0
+#define KS_STOP_GRAD 1           /* ||grad E||_F <= eps_g                                  */
+#define KS_STOP_STAGNATION 2     /* mean of last three relative energy changes < tol      */
+#define KS_STOP_MAXIT 3
+#define KS_STOP_ERROR 4
+
+/* ---- descriptors ------------------------------------------------------------------- */
+typedef struct ks_system_desc {
+  int disc;                /* KS_DISC_*                                                   */
+  int nx, ny, nz;          /* interior points per axis (>= 1)                             */
+  double h;                /* grid spacing, bohr (> 0)                                    */
+  double box_lo[3];        /* box corner: point (i,j,k) sits at box_lo + (i+1, j+1, k+1) h */
+  int p;                   /* orbitals (1 <= p <= 64 for FD7 in this version)             */
+  int ld;                  /* row stride of X/G/gradE in elements; 0 means p              */
+  double occupation;       /* f, electrons per orbital (2 = closed shell)                 */
+  int n_nuclei;            /* M >= 0                                                      */
+  const double* R;         /* host, 3*M coordinates (x,y,z per nucleus); copied           */
+  const double* Z;         /* host, M charges; copied                                     */
+  double rc;               /* erf smoothing radius of the nuclear potential (> 0)         */
+  int terms;               /* KS_TERM_* bit mask                                          */
+  const double* v_ext_override; /* host, n values replacing the nuclear potential, or NULL */
+  int precision;           /* KS_PREC_*                                                   */
+  int hartree_solver;      /* KS_HARTREE_*                                                */
+  double hartree_tol;      /* relative residual ||r||/||4 pi rho||; <= 0 means 1e-13      */
+  int hartree_maxit;       /* <= 0 means 5000                                             */
+} ks_system_desc;
+
+typedef struct ks_energy {
+  double total;            /* E_KS, eq. (EKS) in the discrete form of Section 2.3         */
+  double kinetic;          /* (f/2) tr(X^T L X), L = -Laplacian_h                         */
+  double external;         /* h^3 sum V_ext rho                                           */
+  double hartree;          /* (h^3/2) rho^T V_H                                           */
+  double xc;               /* h^3 sum rho eps_x(rho)                                      */
+  double nuclear;          /* E_II                                                        */
+  double grad_norm;        /* ||G - X G^T X||_F with G = E_X                              */
+  double orth_error;       /* ||X^T X - I||_F                                             */
+  int hartree_iters;       /* CG iterations of this evaluation                            */
+  double hartree_relres;   /* final relative residual                                     */
+} ks_energy;
+
+typedef struct ks_opt_params {
+  double tau0;             /* first step and fallback for an unusable BB value (1e-3)     */
+  double rho1;             /* Armijo constant in eq. (NMLS-Armijo) (1e-4)                 */
+  double delta;            /* backtracking factor (0.1)                                   */
+  double eta;              /* weight of the reference value C_k (0.85)                    */
+  double eps_g;            /* stop when ||grad E||_F <= eps_g (1e-6, Section 4.1)         */
+  int max_iter;            /* (10000)                                                     */
+  int bb_rule;             /* KS_BB_*                                                     */
+  int retraction;          /* KS_QR or KS_WY                                              */
+  double tau_min, tau_max; /* clamp of the BB value (1e-20, 1e20)                         */
+  int h_max;               /* backtracks before a trial is accepted anyway (20)           */
+  double reorth_tol;       /* WY: re-orthonormalise when ||X^T X - I||_F > tol (1e-12)    */
+  double stagnation_tol;   /* stop when mean(df_k, df_k-1, df_k-2) < tol (1e-13); 0 = off */
+} ks_opt_params;
+
+typedef struct ks_result {
+  int iters;               /* accepted iterations k                                       */
+  int nfe;                 /* energy evaluations                                          */
+  int backtracks;          /* rejected trial steps                                        */
+  int ls_fail;             /* trials accepted after h_max reductions without Armijo       */
+  int reorths;             /* WY re-orthonormalisations                                   */
+  int stop_reason;         /* KS_STOP_*                                                   */
+  double energy;           /* final E                                                     */
+  double grad_norm;        /* final ||grad E||_F                                          */
+  ks_energy terms;         /* final energy terms                                          */
+  double seconds;          /* wall time of the call                                       */
+  long long hartree_iters_total;
+} ks_result;
+
+typedef struct ks_system ks_system;
+
+/* ---- sizing and lifecycle -------------------------------------------------------------- */
+
+/* Device bytes ks_create_system needs for this descriptor (all resident state of one
+ * system: potentials, density, CG vectors, the current/trial orbital blocks and their
+ * gradients, Gram and small dense buffers, reduction partials).  0 if invalid. */
+size_t ks_workspace_bytes(const ks_system_desc* d);
+
+/* Creates a system: validates d, carves the caller's device workspace (ws_bytes >=
+ * ks_workspace_bytes(d), 256-byte aligned), copies nuclei to the device, and computes
+ * V_ext and E_II there (setup of Section 2.1 eq. (EKS)).  hip_stream is a hipStream_t
+ * (NULL = default stream).  On success *out receives the handle.  Errors: KS_E_INVAL,
+ * KS_E_NOMEM, KS_E_HIP, KS_E_UNSUPPORTED. */
+int ks_create_system(const ks_system_desc* d, void* dev_workspace, size_t ws_bytes,
+                     void* hip_stream, ks_system** out);
+
+/* Releases the handle and its pinned host buffer (not the caller's workspace). */
+void ks_destroy_system(ks_system* s);
+
+/* Default optimiser parameters (values in the comments of ks_opt_params). */
+void ks_default_params(ks_opt_params* o);
+
+const char* ks_status_string(int code);
+const char* ks_last_error(const ks_system* s);
+
+/* ---- the method --------------------------------------------------------------------- */
+
+/* Energy and partial derivative at X (Section 2.3 eq. (partial deriv)):
+ *   G = E_X = 2f [ (1/2) L X + Diag(V_ext + V_H + v_x) X ],
+ *   gradE = G - X G^T X (Section 3 eq. (def-nablaE)).
+ * X, G, gradE: device n x ld blocks; G and gradE may be NULL (not written).  out (host)
+ * receives the energy terms, ||gradE||_F and ||X^T X - I||_F.  The Hartree solve is
+ * warm-started from the potential of the previous call on this system, and its result
+ * becomes the next warm start.  Errors: KS_E_INVAL, KS_E_HIP, KS_E_NONFINITE. */
+int ks_energy_grad(ks_system* s, const void* X, void* G, void* gradE, ks_energy* out);
+
+/* One retraction from X along the descent direction built from G = E_X:
+ *   KS_QR: X_out = qr(X - tau gradE) by Cholesky QR (eq. (QR), Alg. 2);
+ *   KS_WY: X_out = X - tau U (I + tau/2 V^T U)^{-1} V^T X, U = [G, X], V = [X, -G]
+ *          (eq. (WY3)).
+ * X, G, X_out: device n x ld blocks; X_out must not alias X or G.  Errors: KS_E_INVAL,
+ * KS_E_NOT_SPD (Cholesky breakdown), KS_E_SINGULAR (zero pivot in the 2p x 2p LU),
+ * KS_E_NONFINITE, KS_E_HIP. */
+int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
+               void* X_out);
+
+/* Alg. 3 from X_inout (orthonormal columns expected) with BB steps (eq. (bb-1)) and the
+ * nonmonotone Armijo search (eq. (NMLS-Armijo)); on return X_inout holds the last
+ * accepted iterate and *r (host) the statistics.  o may be NULL for defaults.  Returns
+ * KS_OK when the gradient or stagnation test stopped the run, KS_E_NOT_CONVERGED at
+ * max_iter (r filled), or an error code. */
+int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* r);
+
+/* ---- step-level calls (each is one step of ks_energy_grad) -------------------------- */
+
+/* rho (device, n doubles) = (f/h^3) sum_i X_gi^2 (Section 2.3, rho(X) = diag(X X^T)). */
+int ks_density(ks_system* s, const void* X, double* rho);
+
+/* Solves L v_h = 4 pi rho (L = -Laplacian_h, zero Dirichlet) with the system's Hartree
+ * solver to its tolerance.  rho, v_h: device n doubles; if warm != 0, v_h holds the
+ * starting guess on entry.  iters/relres (host, nullable) receive the iteration count
+ * and final relative residual.  Errors: KS_E_INVAL, KS_E_NOT_CONVERGED, KS_E_HIP. */
+int ks_hartree_solve(ks_system* s, const double* rho, double* v_h, int warm, int* iters,
+                     double* relres);
+
+/* Y = H X with H = (1/2) L + Diag(v_eff) (the Hamiltonian of eq. (partial deriv) without
+ * the factor 2f).  v_eff: device n doubles, or NULL for the potential of the last
+ * ks_energy_grad/ks_minimize evaluation.  X, Y: device n x ld blocks, Y != X. */
+int ks_apply_hamiltonian(ks_system* s, const void* X, void* Y, const double* v_eff);
+
+/* Copies (device to device) the nuclear potential V_ext and the last Hartree and
+ * effective potentials into the given n-double device buffers (any may be NULL). */
+int ks_get_potentials(ks_system* s, double* v_ext, double* v_h, double* v_eff);
+
+/* Gram blocks of two device n x ld blocks A, B: out (device, 3*p*p doubles, row-major
+ * p x p each) = [A^T A, A^T B, B^T B].  The tall-skinny products of Section 3. */
+int ks_gram(ks_system* s, const void* A, const void* B, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KS_H */

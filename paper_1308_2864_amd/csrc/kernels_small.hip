@@ -1,0 +1,516 @@
+// Small dense FP64 algebra of the Stiefel step and the scalar logic of Alg. 3.
+//
+// One workgroup per system works on p x p (QR) or 2p x 2p (WY) matrices held in LDS
+// when they fit, otherwise in a global scratch area of the workspace:
+//  * Cholesky QR factor (Alg. 2 applied to Y = X - tau grad E): Y^T Y is assembled from
+//    the Gram blocks of [X, D] as X^T X - tau (X^T D + D^T X) + tau^2 D^T D, factored as
+//    R^T R, and the retraction weights A = R^{-1}, B = -tau R^{-1} give
+//    X+ = X A + D B = Y R^{-1} (eq. (QR)).
+//  * Cayley/SMW factor (eq. (WY3)): I + tau/2 V^T U with U = [G, X], V = [X, -G] is
+//    assembled from the Gram blocks of [X, G], solved against V^T X by LU with partial
+//    pivoting, giving X+ = X (I - tau Z_2) + G (-tau Z_1).  When X+^T X+ (computed from
+//    the same Gram blocks) drifts from I by more than the re-orthonormalisation
+//    threshold (Section 4.1), the Cholesky QR of X+ is folded into the weights.
+//  * Barzilai-Borwein step (eq. (bb-1)), nonmonotone Armijo test and reference-value
+//    update (eq. (NMLS-Armijo)), stopping rules of Section 4.1.
+#include "ks_common.h"
+#include "../../include/ks.h"
+
+namespace ks {
+
+namespace {
+
+// ---- block-cooperative helpers (all threads of the block call them) -----------------
+
+// In-place upper Cholesky: on return M[i][j], j >= i, holds R with R^T R = M (input);
+// the strict lower part is zeroed.  Returns nonzero on a non-positive or non-finite pivot.
+__device__ int blk_cholesky_upper(double* M, int ld, int p) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int k = 0; k < p; ++k) {
+    if (threadIdx.x == 0) {
+      const double d = M[k * ld + k];
+      if (!(d > 0.0) || !isfinite(d)) bad = 1;
+      else M[k * ld + k] = sqrt(d);
+    }
+    __syncthreads();
+    if (bad) return 1;
+    const double rkk = M[k * ld + k];
+    for (int j = k + 1 + threadIdx.x; j < p; j += blockDim.x) M[k * ld + j] /= rkk;
+    __syncthreads();
+    const int m = p - k - 1;
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+      const int i = k + 1 + e / m, j = k + 1 + e % m;
+      if (j >= i) M[i * ld + j] -= M[k * ld + i] * M[k * ld + j];
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    if (i > j) M[i * ld + j] = 0.0;
+  }
+  __syncthreads();
+  return 0;
+}
+
+// W = R^{-1} for upper triangular R (back substitution, one column per thread).
+__device__ void blk_upper_inverse(const double* R, int ldr, double* W, int ldw, int p) {
+  for (int j = threadIdx.x; j < p; j += blockDim.x) {
+    for (int i = p - 1; i > j; --i) W[i * ldw + j] = 0.0;
+    W[j * ldw + j] = 1.0 / R[j * ldr + j];
+    for (int i = j - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int k = i + 1; k <= j; ++k) s += R[i * ldr + k] * W[k * ldw + j];
+      W[i * ldw + j] = -s / R[i * ldr + i];
+    }
+  }
+  __syncthreads();
+}
+
+// C = op(A) op(B) (p x p), op = transpose if the flag is set.  C must not alias A or B.
+__device__ void blk_gemm(double* C, int ldc, const double* A, int lda, bool ta, const double* B,
+                         int ldb, bool tb, int p) {
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    double s = 0.0;
+    for (int k = 0; k < p; ++k) {
+      const double a = ta ? A[k * lda + i] : A[i * lda + k];
+      const double b = tb ? B[j * ldb + k] : B[k * ldb + j];
+      s += a * b;
+    }
+    C[i * ldc + j] = s;
+  }
+  __syncthreads();
+}
+
+// Solves S Z = RHS in place (S: m x m, RHS: m x nr -> Z) by LU with partial pivoting
+// (largest |pivot|, first index on ties).  Returns nonzero if a pivot is exactly zero or
+// not finite.
+__device__ int blk_lu_solve(double* S, int lds, int m, double* RHS, int ldb, int nr) {
+  __shared__ double bv[kBlock];
+  __shared__ int bi[kBlock];
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int k = 0; k < m; ++k) {
+    // pivot search
+    double best = -1.0;
+    int besti = m;
+    for (int i = k + threadIdx.x; i < m; i += blockDim.x) {
+      const double v = fabs(S[i * lds + k]);
+      if (v > best) { best = v; besti = i; }
+    }
+    bv[threadIdx.x] = best;
+    bi[threadIdx.x] = besti;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) {
+        const double v2 = bv[threadIdx.x + o];
+        const int i2 = bi[threadIdx.x + o];
+        if (v2 > bv[threadIdx.x] || (v2 == bv[threadIdx.x] && i2 < bi[threadIdx.x])) {
+          bv[threadIdx.x] = v2;
+          bi[threadIdx.x] = i2;
+        }
+      }
+      __syncthreads();
+    }
+    const int piv = bi[0];
+    if (threadIdx.x == 0 && (!(bv[0] > 0.0) || !isfinite(bv[0]))) bad = 1;
+    __syncthreads();
+    if (bad) return 1;
+    if (piv != k) {
+      for (int j = threadIdx.x; j < m; j += blockDim.x) {
+        const double t = S[k * lds + j];
+        S[k * lds + j] = S[piv * lds + j];
+        S[piv * lds + j] = t;
+      }
+      for (int j = threadIdx.x; j < nr; j += blockDim.x) {
+        const double t = RHS[k * ldb + j];
+        RHS[k * ldb + j] = RHS[piv * ldb + j];
+        RHS[piv * ldb + j] = t;
+      }
+    }
+    __syncthreads();
+    const double skk = S[k * lds + k];
+    for (int i = k + 1 + threadIdx.x; i < m; i += blockDim.x) S[i * lds + k] /= skk;
+    __syncthreads();
+    const int rem = m - k - 1;
+    for (int e = threadIdx.x; e < rem * rem; e += blockDim.x) {
+      const int i = k + 1 + e / rem, j = k + 1 + e % rem;
+      S[i * lds + j] -= S[i * lds + k] * S[k * lds + j];
+    }
+    for (int e = threadIdx.x; e < rem * nr; e += blockDim.x) {
+      const int i = k + 1 + e / nr, j = e % nr;
+      RHS[i * ldb + j] -= S[i * lds + k] * RHS[k * ldb + j];
+    }
+    __syncthreads();
+  }
+  // back substitution with the upper factor, one right-hand side per thread
+  for (int c = threadIdx.x; c < nr; c += blockDim.x) {
+    for (int i = m - 1; i >= 0; --i) {
+      double s = RHS[i * ldb + c];
+      for (int j = i + 1; j < m; ++j) s -= S[i * lds + j] * RHS[j * ldb + c];
+      RHS[i * ldb + c] = s / S[i * lds + i];
+    }
+  }
+  __syncthreads();
+  return 0;
+}
+
+__device__ void blk_store_padded(double* dst, int pp, const double* src, int lds, int p,
+                                 double scale) {
+  for (int e = threadIdx.x; e < pp * pp; e += blockDim.x) {
+    const int i = e / pp, j = e % pp;
+    dst[e] = (i < p && j < p) ? scale * src[i * lds + j] : 0.0;
+  }
+  __syncthreads();
+}
+
+__device__ inline double* work_base(double* glob) {
+  extern __shared__ double dyn[];
+  return glob ? glob : dyn;
+}
+
+// ---- QR retraction weights -----------------------------------------------------------
+// gram: [X^T X, X^T D, D^T D] (pp x pp each).
+__global__ void k_qr_factor(const double* __restrict__ gram, int p, int pp,
+                            const double* __restrict__ tau_p, double* __restrict__ A,
+                            double* __restrict__ B, double* glob, int* status) {
+  double* M = work_base(glob);
+  double* W = M + p * p;
+  const double tau = *tau_p;
+  const double* XX = gram;
+  const double* XD = gram + pp * pp;
+  const double* DD = gram + 2 * pp * pp;
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    M[e] = XX[i * pp + j] - tau * (XD[i * pp + j] + XD[j * pp + i]) + tau * tau * DD[i * pp + j];
+  }
+  __syncthreads();
+  if (blk_cholesky_upper(M, p, p)) {
+    if (threadIdx.x == 0) *status = KS_E_NOT_SPD;
+    return;
+  }
+  blk_upper_inverse(M, p, W, p, p);
+  blk_store_padded(A, pp, W, p, p, 1.0);
+  blk_store_padded(B, pp, W, p, p, -tau);
+}
+
+// ---- Cayley / SMW retraction weights -------------------------------------------------
+// gram: [X^T X, X^T G, G^T G] (pp x pp each).
+__global__ void k_wy_factor(const double* __restrict__ gram, int p, int pp,
+                            const double* __restrict__ tau_p, double reorth_tol,
+                            double* __restrict__ A, double* __restrict__ B, double* glob,
+                            int* status, int* reorth_flag) {
+  double* base = work_base(glob);
+  const int m = 2 * p;
+  double* S = base;             // m x m     (phase 1)
+  double* Z = base + m * m;     // m x p     (kept)
+  double* Aw = base;            // p x p     (phase 2 reuses S)
+  double* Bw = Aw + p * p;
+  double* T1 = Bw + p * p;
+  double* T2 = T1 + p * p;
+  const double tau = *tau_p;
+  const double* XX = gram;
+  const double* XG = gram + pp * pp;
+  const double* GG = gram + 2 * pp * pp;
+  const double ht = 0.5 * tau;
+  for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+    const int i = e / m, j = e % m;
+    double v;
+    if (i < p && j < p) v = ht * XG[i * pp + j];                 // X^T G
+    else if (i < p) v = ht * XX[i * pp + (j - p)];                // X^T X
+    else if (j < p) v = -ht * GG[(i - p) * pp + j];               // -G^T G
+    else v = -ht * XG[(j - p) * pp + (i - p)];                    // -G^T X
+    S[e] = v + (i == j ? 1.0 : 0.0);
+  }
+  for (int e = threadIdx.x; e < m * p; e += blockDim.x) {
+    const int i = e / p, c = e % p;
+    Z[e] = (i < p) ? XX[i * pp + c] : -XG[c * pp + (i - p)];   // V^T X = [X^T X; -G^T X]
+  }
+  __syncthreads();
+  if (blk_lu_solve(S, m, m, Z, p, p)) {
+    if (threadIdx.x == 0) *status = KS_E_SINGULAR;
+    return;
+  }
+  // X+ = X (I - tau Z2) + G (-tau Z1)
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    Aw[e] = (i == j ? 1.0 : 0.0) - tau * Z[(p + i) * p + j];
+    Bw[e] = -tau * Z[i * p + j];
+  }
+  __syncthreads();
+  // X+^T X+ = A^T XX A + A^T XG B + (A^T XG B)^T + B^T GG B
+  double* P = Z;  // Z no longer needed (m x p >= p x p)
+  blk_gemm(T1, p, XX, pp, false, Aw, p, false, p);   // XX A
+  blk_gemm(T2, p, Aw, p, true, T1, p, false, p);     // A^T XX A
+  blk_gemm(T1, p, XG, pp, false, Bw, p, false, p);   // XG B
+  blk_gemm(P, p, Aw, p, true, T1, p, false, p);      // A^T XG B
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    T2[e] += P[i * p + j] + P[j * p + i];
+  }
+  __syncthreads();
+  blk_gemm(T1, p, GG, pp, false, Bw, p, false, p);   // GG B
+  blk_gemm(P, p, Bw, p, true, T1, p, false, p);      // B^T GG B
+  __shared__ double onrm;
+  __shared__ double red[kBlock];
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    const double v = T2[e] + P[e];
+    T2[e] = v;
+    const double dlt = v - (i == j ? 1.0 : 0.0);
+    acc += dlt * dlt;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < (int)blockDim.x; ++i) s += red[i];
+    onrm = sqrt(s);
+  }
+  __syncthreads();
+  if (onrm > reorth_tol) {
+    // Cholesky QR of X+: fold R^{-1} into the weights
+    if (blk_cholesky_upper(T2, p, p)) {
+      if (threadIdx.x == 0) *status = KS_E_NOT_SPD;
+      return;
+    }
+    blk_upper_inverse(T2, p, P, p, p);
+    blk_gemm(T1, p, Aw, p, false, P, p, false, p);
+    blk_store_padded(A, pp, T1, p, p, 1.0);
+    blk_gemm(T1, p, Bw, p, false, P, p, false, p);
+    blk_store_padded(B, pp, T1, p, p, 1.0);
+    if (threadIdx.x == 0 && reorth_flag) *reorth_flag += 1;
+  } else {
+    blk_store_padded(A, pp, Aw, p, p, 1.0);
+    blk_store_padded(B, pp, Bw, p, p, 1.0);
+  }
+}
+
+// ---- gradient weights: W = -(X^T G)^T = -G^T X -------------------------------------
+__global__ void k_grad_weights(const double* __restrict__ gram, int pp, double* __restrict__ W) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= pp * pp) return;
+  const int i = e / pp, j = e % pp;
+  W[e] = -gram[pp * pp + j * pp + i];
+}
+
+// ---- evaluation summary ----------------------------------------------------------------
+__global__ void k_finish_eval(const double* __restrict__ sums, const double* __restrict__ xx,
+                              int p, int pp, double f, double dV, const double* enuc,
+                              const CgState* cg, EvalOut* out) {
+  __shared__ double sh[kBlock / kWave];
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    const double d = xx[i * pp + j] - (i == j ? 1.0 : 0.0);
+    acc += d * d;
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x != 0) return;
+  EvalOut o;
+  o.kinetic = 0.5 * f * sums[SL_KIN];
+  o.external = f * sums[SL_EXT];
+  o.hartree = 0.5 * dV * sums[SL_EH];
+  o.xc = dV * sums[SL_EX];
+  o.nuclear = *enuc;
+  o.total = o.kinetic + o.external + o.hartree + o.xc + o.nuclear;
+  o.g2 = sums[SL_DD];
+  o.ss = sums[SL_SS];
+  o.sy = sums[SL_SY];
+  o.yy = sums[SL_YY];
+  o.orth2 = acc;
+  if (cg) {
+    o.cg_iters = cg->it;
+    o.cg_relres = cg->bb > 0.0 ? sqrt(cg->rr / cg->bb) : 0.0;
+  } else {
+    o.cg_iters = 0;
+    o.cg_relres = 0.0;
+  }
+  o.nonfinite = (!isfinite(o.total) || !isfinite(o.g2)) ? 1 : 0;
+  *out = o;
+}
+
+__global__ void k_set_scalar(double* d, double v) { *d = v; }
+
+__global__ void k_ls_reset(LsState* ls) { *ls = LsState{}; }
+
+// [3][pp][pp] padded Gram blocks -> [3][p][p]
+__global__ void k_compact_gram(const double* __restrict__ g, int pp, int p,
+                               double* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 3 * p * p) return;
+  const int prod = e / (p * p), ij = e % (p * p), i = ij / p, j = ij % p;
+  out[e] = g[(size_t)prod * pp * pp + i * pp + j];
+}
+
+// ---- Alg. 3 scalar logic -------------------------------------------------------------
+
+__device__ double bb_tau(int k, double ss, double sy, double yy, const LsParams& prm) {
+  if (k == 0) return prm.tau0;
+  int rule = prm.bb_rule;
+  if (rule == KS_BB_ALT) rule = (k % 2 == 1) ? KS_BB1 : KS_BB2;
+  double t;
+  if (rule == KS_BB1) t = (sy != 0.0) ? ss / fabs(sy) : INFINITY;
+  else t = (yy != 0.0) ? fabs(sy) / yy : INFINITY;
+  if (!isfinite(t) || !(t > 0.0)) t = prm.tau0;
+  return fmin(fmax(t, prm.tau_min), prm.tau_max);
+}
+
+__global__ void k_ls_init(const EvalOut* ev, LsState* ls, LsParams prm) {
+  LsState s = {};
+  s.E = ev->total;
+  s.g2 = ev->g2;
+  s.C = s.E;
+  s.Q = 1.0;
+  s.k = 0;
+  s.h = 0;
+  s.tau_bb = bb_tau(0, 0.0, 0.0, 0.0, prm);
+  s.tau = s.tau_bb;
+  s.nfe = 1;
+  s.accepted = 1;
+  s.error = ls->error;  // a step before init may have flagged an error
+  if (ev->nonfinite) {
+    s.error = KS_E_NONFINITE;
+    s.stop = KS_STOP_ERROR;
+  } else if (sqrt(s.g2) <= prm.eps_g) {
+    s.stop = KS_STOP_GRAD;
+  } else if (prm.max_iter <= 0) {
+    s.stop = KS_STOP_MAXIT;
+  }
+  if (s.error != 0) s.stop = KS_STOP_ERROR;
+  *ls = s;
+}
+
+__global__ void k_ls_judge(const EvalOut* ev, LsState* ls, LsParams prm) {
+  LsState s = *ls;
+  s.nfe += 1;
+  if (s.error != 0) {
+    s.stop = KS_STOP_ERROR;
+    *ls = s;
+    return;
+  }
+  const double Et = ev->nonfinite ? INFINITY : ev->total;
+  const double rhs = s.C - prm.rho1 * s.tau * s.g2;
+  const bool ok = Et <= rhs;
+  if (ok || s.h >= prm.h_max) {
+    if (!isfinite(Et)) {
+      s.error = KS_E_NONFINITE;
+      s.stop = KS_STOP_ERROR;
+      s.accepted = 0;
+      *ls = s;
+      return;
+    }
+    if (!ok) s.ls_fail += 1;
+    s.accepted = 1;
+    const double df = fabs(s.E - Et) / (fabs(s.E) + 1.0);
+    s.df[0] = s.df[1];
+    s.df[1] = s.df[2];
+    s.df[2] = df;
+    s.ndf += 1;
+    const double Qn = prm.eta * s.Q + 1.0;
+    s.C = (prm.eta * s.Q * s.C + Et) / Qn;
+    s.Q = Qn;
+    s.E = Et;
+    s.g2 = ev->g2;
+    s.k += 1;
+    if (s.ndf >= 3 && (s.df[0] + s.df[1] + s.df[2]) / 3.0 < prm.stagnation_tol)
+      s.stop = KS_STOP_STAGNATION;
+    else if (sqrt(s.g2) <= prm.eps_g)
+      s.stop = KS_STOP_GRAD;
+    else if (s.k >= prm.max_iter)
+      s.stop = KS_STOP_MAXIT;
+    s.tau_bb = bb_tau(s.k, ev->ss, ev->sy, ev->yy, prm);
+    s.h = 0;
+    s.tau = s.tau_bb;
+  } else {
+    s.accepted = 0;
+    s.h += 1;
+    s.backtracks += 1;
+    s.tau = s.tau_bb * pow(prm.delta, (double)s.h);
+  }
+  *ls = s;
+}
+
+size_t dyn_lds_limit() {
+  static size_t lim = 0;
+  if (lim == 0) {
+    int dev = 0, v = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      v = 65536;
+    lim = (size_t)v;
+  }
+  return lim;
+}
+
+template <typename K>
+bool prepare_lds(K kernel, size_t bytes) {
+  // leave room for the kernel's static shared arrays
+  if (bytes + 8192 > dyn_lds_limit()) return false;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  return true;
+}
+
+}  // namespace
+
+size_t small_work_doubles(int p) {
+  // WY: S (2p x 2p) and Z (2p x p), then four p x p matrices in place of S; QR: 2 p^2
+  return (size_t)6 * p * p + 64;
+}
+
+void launch_ls_reset(LsState* ls, hipStream_t st) {
+  hipLaunchKernelGGL(k_ls_reset, dim3(1), dim3(1), 0, st, ls);
+}
+
+void launch_compact_gram(const double* gram, int pp, int p, double* out, hipStream_t st) {
+  const int total = 3 * p * p;
+  hipLaunchKernelGGL(k_compact_gram, dim3((total + 255) / 256), dim3(256), 0, st, gram, pp, p,
+                     out);
+}
+
+void launch_grad_weights(const double* gram, int pp, double* W, hipStream_t st) {
+  hipLaunchKernelGGL(k_grad_weights, dim3((pp * pp + 255) / 256), dim3(256), 0, st, gram, pp, W);
+}
+
+void launch_qr_factor(const double* gram_xd, int p, int pp, const double* tau, double* A,
+                      double* B, double* work, int* status, hipStream_t st) {
+  const size_t bytes = (size_t)2 * p * p * sizeof(double);
+  const bool lds = prepare_lds(k_qr_factor, bytes);
+  hipLaunchKernelGGL(k_qr_factor, dim3(1), dim3(kBlock), lds ? bytes : 0, st, gram_xd, p, pp,
+                     tau, A, B, lds ? nullptr : work, status);
+}
+
+void launch_wy_factor(const double* gram_xg, int p, int pp, const double* tau,
+                      double reorth_tol, double* A, double* B, double* work, int* status,
+                      int* reorth_flag, hipStream_t st) {
+  const size_t bytes = small_work_doubles(p) * sizeof(double);
+  const bool lds = prepare_lds(k_wy_factor, bytes);
+  hipLaunchKernelGGL(k_wy_factor, dim3(1), dim3(kBlock), lds ? bytes : 0, st, gram_xg, p, pp,
+                     tau, reorth_tol, A, B, lds ? nullptr : work, status, reorth_flag);
+}
+
+void launch_finish_eval(const double* sums, const double* gram_xx, int p, int pp, double f,
+                        double dV, const double* enuc, const CgState* cg, EvalOut* out,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_finish_eval, dim3(1), dim3(kBlock), 0, st, sums, gram_xx, p, pp, f, dV,
+                     enuc, cg, out);
+}
+
+void launch_set_scalar(double* dst, double v, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, st, dst, v);
+}
+
+void launch_ls_init(const EvalOut* ev, LsState* ls, LsParams prm, hipStream_t st) {
+  hipLaunchKernelGGL(k_ls_init, dim3(1), dim3(1), 0, st, ev, ls, prm);
+}
+
+void launch_ls_judge(const EvalOut* ev, LsState* ls, LsParams prm, hipStream_t st) {
+  hipLaunchKernelGGL(k_ls_judge, dim3(1), dim3(1), 0, st, ev, ls, prm);
+}
+
+}  // namespace ks

@@ -1,0 +1,670 @@
+// C ABI of the library (include/ks.h): system lifecycle, workspace layout and the host
+// side of Alg. 3.  The host only orders kernel launches on the caller's stream and reads
+// back small scalar records (CG state, line-search state); every number on the data path
+// is computed by the kernels in kernels_grid.hip, kernels_dense.hip, kernels_small.hip.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ks_common.h"
+#include "../../include/ks.h"
+
+using namespace ks;
+
+namespace {
+thread_local std::string g_err;
+constexpr int kPartStride = 4096;  // >= blocks of every streaming kernel
+}  // namespace
+
+struct ks_system {
+  ks_system_desc d{};
+  std::vector<double> R, Z;
+  hipStream_t st = nullptr;
+  Grid grid{};
+  int n = 0, p = 0, ld = 0, pp = 0;
+  double f = 2.0;
+  int use_ext = 1, use_h = 1, use_x = 1;
+  double htol = 1e-13;
+  int hmaxit = 5000;
+  // device buffers carved from the caller's workspace
+  double *vext = nullptr, *rho = nullptr, *vh[2] = {}, *veff[2] = {};
+  double *cg_r = nullptr, *cg_pa = nullptr, *cg_pb = nullptr, *cg_q = nullptr;
+  double *Rd = nullptr, *Zd = nullptr, *enuc = nullptr, *tau_user = nullptr;
+  double *X[2] = {}, *G[2] = {}, *D[2] = {};
+  double *gxg[2] = {}, *gxd[2] = {}, *W = nullptr, *A = nullptr, *B = nullptr;
+  double *work = nullptr, *gram_part = nullptr, *spart = nullptr, *cgpart = nullptr;
+  double* sums[2] = {};
+  CgState* cg = nullptr;
+  EvalOut* ev[2] = {};
+  LsState* ls = nullptr;
+  int* status = nullptr;
+  int* reorth_count = nullptr;
+  int cur = 0;
+  int gram_nchunks = 1;
+  // pinned host mirror of the scalar records
+  void* host = nullptr;
+  std::string err;
+  int last_cg_iters = 0;
+  long long cg_total = 0;
+};
+
+namespace {
+
+// ---- workspace layout ------------------------------------------------------------------
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) / 256 * 256;
+    T* ptr = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return ptr;
+  }
+};
+
+void layout(ks_system* s, char* base, size_t* total) {
+  Carver c{base};
+  const size_t n = (size_t)s->n, np = (size_t)s->n * s->p, pp2 = (size_t)s->pp * s->pp;
+  const int M = (int)s->R.size() / 3;
+  s->vext = c.take<double>(n);
+  s->rho = c.take<double>(n);
+  for (int i = 0; i < 2; ++i) {
+    s->vh[i] = c.take<double>(n);
+    s->veff[i] = c.take<double>(n);
+  }
+  s->cg_r = c.take<double>(n);
+  s->cg_pa = c.take<double>(n);
+  s->cg_pb = c.take<double>(n);
+  s->cg_q = c.take<double>(n);
+  s->Rd = c.take<double>(3 * (size_t)(M > 0 ? M : 1));
+  s->Zd = c.take<double>((size_t)(M > 0 ? M : 1));
+  s->enuc = c.take<double>(1);
+  s->tau_user = c.take<double>(1);
+  for (int i = 0; i < 2; ++i) {
+    s->X[i] = c.take<double>(np);
+    s->G[i] = c.take<double>(np);
+    s->D[i] = c.take<double>(np);
+    s->gxg[i] = c.take<double>(3 * pp2);
+    s->gxd[i] = c.take<double>(3 * pp2);
+    s->sums[i] = c.take<double>(kMaxScalarSlots);
+    s->ev[i] = c.take<EvalOut>(1);
+  }
+  s->W = c.take<double>(pp2);
+  s->A = c.take<double>(pp2);
+  s->B = c.take<double>(pp2);
+  s->work = c.take<double>(small_work_doubles(s->p));
+  s->gram_nchunks = gram_chunks(s->n, s->pp);
+  s->gram_part = c.take<double>((size_t)s->gram_nchunks * 3 * pp2);
+  s->spart = c.take<double>((size_t)SL_COUNT * kPartStride);
+  s->cgpart = c.take<double>((size_t)2 * 1024);
+  s->cg = c.take<CgState>(1);
+  s->ls = c.take<LsState>(1);
+  s->status = c.take<int>(1);
+  s->reorth_count = c.take<int>(1);
+  *total = c.off + 256;
+}
+
+int validate(const ks_system_desc* d, std::string* why) {
+  if (!d) { *why = "null descriptor"; return KS_E_INVAL; }
+  if (d->disc != KS_DISC_FD7) {
+    *why = "only the 7-point finite-difference discretisation is built into this library";
+    return KS_E_UNSUPPORTED;
+  }
+  if (d->precision != KS_PREC_FP64) {
+    *why = "only KS_PREC_FP64 is built into this library";
+    return KS_E_UNSUPPORTED;
+  }
+  if (d->hartree_solver != KS_HARTREE_CG) {
+    *why = "unknown Hartree solver";
+    return KS_E_UNSUPPORTED;
+  }
+  if (d->nx < 1 || d->ny < 1 || d->nz < 1) { *why = "grid sizes must be >= 1"; return KS_E_INVAL; }
+  if (!(d->h > 0.0) || !std::isfinite(d->h)) { *why = "h must be > 0"; return KS_E_INVAL; }
+  if (d->p < 1 || d->p > 64) { *why = "p must be in [1, 64]"; return KS_E_INVAL; }
+  const int ld = d->ld ? d->ld : d->p;
+  if (ld < d->p) { *why = "ld must be >= p"; return KS_E_INVAL; }
+  const double cells = (double)d->nx * d->ny * d->nz;
+  if (cells * ld >= 2147483647.0 || cells * d->p >= 2147483647.0) {
+    *why = "n * ld must be < 2^31";
+    return KS_E_INVAL;
+  }
+  if (!(d->occupation > 0.0)) { *why = "occupation must be > 0"; return KS_E_INVAL; }
+  if (d->n_nuclei < 0) { *why = "n_nuclei must be >= 0"; return KS_E_INVAL; }
+  if (d->n_nuclei > 0 && (!d->R || !d->Z)) { *why = "R and Z are required"; return KS_E_INVAL; }
+  if ((d->terms & KS_TERM_EXT) && d->n_nuclei > 0 && !d->v_ext_override && !(d->rc > 0.0)) {
+    *why = "rc must be > 0";
+    return KS_E_INVAL;
+  }
+  return KS_OK;
+}
+
+void init_dims(ks_system* s, const ks_system_desc* d) {
+  s->d = *d;
+  s->n = d->nx * d->ny * d->nz;
+  s->p = d->p;
+  s->ld = d->ld ? d->ld : d->p;
+  s->pp = round_up(d->p, 16);
+  s->f = d->occupation;
+  s->use_ext = (d->terms & KS_TERM_EXT) ? 1 : 0;
+  s->use_h = (d->terms & KS_TERM_HARTREE) ? 1 : 0;
+  s->use_x = (d->terms & KS_TERM_XC) ? 1 : 0;
+  s->htol = d->hartree_tol > 0.0 ? d->hartree_tol : 1e-13;
+  s->hmaxit = d->hartree_maxit > 0 ? d->hartree_maxit : 5000;
+  s->R.assign(d->R ? d->R : nullptr, d->R ? d->R + 3 * d->n_nuclei : nullptr);
+  s->Z.assign(d->Z ? d->Z : nullptr, d->Z ? d->Z + d->n_nuclei : nullptr);
+  s->grid.nx = d->nx;
+  s->grid.ny = d->ny;
+  s->grid.nz = d->nz;
+  s->grid.n = s->n;
+  s->grid.h = d->h;
+  s->grid.inv_h2 = 1.0 / (d->h * d->h);
+  s->grid.dV = d->h * d->h * d->h;
+  for (int i = 0; i < 3; ++i) s->grid.lo[i] = d->box_lo[i];
+}
+
+int fail(ks_system* s, int code, const std::string& msg) {
+  if (s) s->err = msg;
+  g_err = msg;
+  return code;
+}
+
+int hip_check(ks_system* s, hipError_t e, const char* what) {
+  if (e == hipSuccess) return KS_OK;
+  return fail(s, KS_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int launch_check(ks_system* s, const char* what) {
+  return hip_check(s, hipGetLastError(), what);
+}
+
+CgState* host_cg(ks_system* s) { return reinterpret_cast<CgState*>(s->host); }
+EvalOut* host_ev(ks_system* s) {
+  return reinterpret_cast<EvalOut*>(static_cast<char*>(s->host) + 256);
+}
+LsState* host_ls(ks_system* s) {
+  return reinterpret_cast<LsState*>(static_cast<char*>(s->host) + 512);
+}
+int* host_int(ks_system* s) { return reinterpret_cast<int*>(static_cast<char*>(s->host) + 768); }
+
+template <typename T>
+int readback(ks_system* s, T* host, const T* dev) {
+  hipError_t e = hipMemcpyAsync(host, dev, sizeof(T), hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  return hip_check(s, e, "read-back");
+}
+
+// ---- Hartree solve ---------------------------------------------------------------------
+// CG iterations are queued in chunks; each kernel exits at once after convergence, and
+// the host checks the device flag between chunks.
+int hartree(ks_system* s, const double* rho, const double* x0, double* x, int* iters,
+            double* relres) {
+  launch_cg_init(rho, x0, x, s->cg_r, s->cg_pa, s->cg, s->htol, s->hmaxit, s->grid, s->cgpart,
+                 s->st);
+  double* pa = s->cg_pa;
+  double* pb = s->cg_pb;
+  int launched = 0;
+  // first chunk sized by the previous solve (warm starts need similar counts)
+  int chunk = s->last_cg_iters > 0 ? s->last_cg_iters + 2 : 32;
+  CgState* hc = host_cg(s);
+  for (;;) {
+    const int c = std::min(chunk, s->hmaxit - launched);
+    for (int i = 0; i < c; ++i) {
+      launch_cg_iter(x, s->cg_r, pa, pb, s->cg_q, s->cg, s->grid, s->cgpart, s->st);
+      std::swap(pa, pb);
+    }
+    launched += c;
+    int rc = launch_check(s, "hartree");
+    if (rc) return rc;
+    rc = readback(s, hc, s->cg);
+    if (rc) return rc;
+    if (hc->done || launched >= s->hmaxit) break;
+    chunk = 16;
+  }
+  s->last_cg_iters = hc->it;
+  s->cg_total += hc->it;
+  if (iters) *iters = hc->it;
+  if (relres) *relres = hc->bb > 0.0 ? std::sqrt(hc->rr / hc->bb) : 0.0;
+  return KS_OK;
+}
+
+// ---- one energy/gradient evaluation on internal slot `idx` -------------------------
+// rho of X[idx] is either ready (fused into the retraction) or computed here.  With
+// bb_ref >= 0 the gradient epilogue also forms the BB sums against slot bb_ref.
+// warm: slot whose V_H starts the CG.  Writes G, D, gram blocks, sums, ev of the slot.
+int evaluate(ks_system* s, int idx, bool rho_ready, int bb_ref, int warm, bool want_gxd) {
+  const double scale = s->f / s->grid.dV;
+  const double* Xs = s->X[idx];
+  if (!rho_ready) launch_density<double>(Xs, s->p, s->n, s->p, scale, s->rho, s->st);
+  int rc = launch_check(s, "density");
+  if (rc) return rc;
+  if (s->use_h) {
+    rc = hartree(s, s->rho, s->vh[warm], s->vh[idx], nullptr, nullptr);
+    if (rc) return rc;
+  }
+  Partials pt{s->spart, kPartStride};
+  launch_xc(s->rho, s->vh[idx], s->vext, s->veff[idx], s->grid, s->use_h, s->use_x,
+            s->use_h ? s->cg : nullptr, pt, s->st);
+  launch_hx<double>(Xs, s->p, s->G[idx], s->p, s->veff[idx], s->vext, s->grid, s->p,
+                    2.0 * s->f, &pt, s->st);
+  launch_gram(Xs, s->G[idx], s->p, s->n, s->p, 3, s->gram_part, s->gram_nchunks, s->st);
+  launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, 3, s->p, s->gxg[idx], s->st);
+  launch_grad_weights(s->gxg[idx], s->pp, s->W, s->st);
+  CombineArgs ca{};
+  ca.X = Xs;
+  ca.A = s->W;
+  ca.C0 = s->G[idx];
+  ca.out = s->D[idx];
+  ca.Xk = bb_ref >= 0 ? s->X[bb_ref] : Xs;
+  ca.Dk = bb_ref >= 0 ? s->D[bb_ref] : s->D[idx];
+  ca.pt = pt;
+  ca.ld = s->p;
+  ca.n = s->n;
+  ca.p = s->p;
+  launch_combine(ca, s->st);
+  if (want_gxd) {
+    launch_gram(Xs, s->D[idx], s->p, s->n, s->p, 3, s->gram_part, s->gram_nchunks, s->st);
+    launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, 3, s->p, s->gxd[idx], s->st);
+  }
+  int nblk[kMaxScalarSlots] = {};
+  const int hb = std::min((s->n * s->p + kBlock - 1) / kBlock, kPartStride);
+  nblk[SL_KIN] = nblk[SL_EXT] = std::max(hb, 1);
+  nblk[SL_EH] = nblk[SL_EX] = scalar_blocks(s->n);
+  nblk[SL_DD] = nblk[SL_SS] = nblk[SL_SY] = nblk[SL_YY] = combine_blocks(s->n);
+  launch_reduce_scalars(s->spart, kPartStride, nblk, SL_COUNT, s->sums[idx], s->st);
+  launch_finish_eval(s->sums[idx], s->gxg[idx], s->p, s->pp, s->f, s->grid.dV, s->enuc,
+                     s->use_h ? s->cg : nullptr, s->ev[idx], s->st);
+  return launch_check(s, "evaluate");
+}
+
+void to_energy(const EvalOut& e, ks_energy* out) {
+  out->total = e.total;
+  out->kinetic = e.kinetic;
+  out->external = e.external;
+  out->hartree = e.hartree;
+  out->xc = e.xc;
+  out->nuclear = e.nuclear;
+  out->grad_norm = std::sqrt(std::max(e.g2, 0.0));
+  out->orth_error = std::sqrt(std::max(e.orth2, 0.0));
+  out->hartree_iters = e.cg_iters;
+  out->hartree_relres = e.cg_relres;
+}
+
+LsParams to_params(const ks_opt_params& o) {
+  LsParams p{};
+  p.tau0 = o.tau0;
+  p.rho1 = o.rho1;
+  p.delta = o.delta;
+  p.eta = o.eta;
+  p.eps_g = o.eps_g;
+  p.tau_min = o.tau_min;
+  p.tau_max = o.tau_max;
+  p.reorth_tol = o.reorth_tol;
+  p.stagnation_tol = o.stagnation_tol;
+  p.max_iter = o.max_iter;
+  p.bb_rule = o.bb_rule;
+  p.h_max = o.h_max;
+  p.retraction = o.retraction;
+  return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ks_default_params(ks_opt_params* o) {
+  if (!o) return;
+  o->tau0 = 1e-3;
+  o->rho1 = 1e-4;
+  o->delta = 0.1;
+  o->eta = 0.85;
+  o->eps_g = 1e-6;
+  o->max_iter = 10000;
+  o->bb_rule = KS_BB_ALT;
+  o->retraction = KS_QR;
+  o->tau_min = 1e-20;
+  o->tau_max = 1e20;
+  o->h_max = 20;
+  o->reorth_tol = 1e-12;
+  o->stagnation_tol = 1e-13;
+}
+
+const char* ks_status_string(int code) {
+  switch (code) {
+    case KS_OK: return "ok";
+    case KS_E_INVAL: return "invalid argument";
+    case KS_E_NOMEM: return "workspace too small";
+    case KS_E_HIP: return "HIP runtime error";
+    case KS_E_NOT_SPD: return "Cholesky breakdown (matrix not positive definite)";
+    case KS_E_SINGULAR: return "singular Sherman-Morrison-Woodbury system";
+    case KS_E_NONFINITE: return "non-finite value";
+    case KS_E_NOT_CONVERGED: return "not converged";
+    case KS_E_UNSUPPORTED: return "unsupported configuration";
+    default: return "unknown status";
+  }
+}
+
+const char* ks_last_error(const ks_system* s) {
+  return s ? s->err.c_str() : g_err.c_str();
+}
+
+size_t ks_workspace_bytes(const ks_system_desc* d) {
+  std::string why;
+  if (validate(d, &why) != KS_OK) {
+    g_err = why;
+    return 0;
+  }
+  ks_system tmp;
+  init_dims(&tmp, d);
+  size_t total = 0;
+  layout(&tmp, nullptr, &total);
+  return total;
+}
+
+int ks_create_system(const ks_system_desc* d, void* dev_workspace, size_t ws_bytes,
+                     void* hip_stream, ks_system** out) {
+  if (!out) return fail(nullptr, KS_E_INVAL, "out is null");
+  *out = nullptr;
+  std::string why;
+  int rc = validate(d, &why);
+  if (rc) return fail(nullptr, rc, why);
+  if (!dev_workspace) return fail(nullptr, KS_E_INVAL, "workspace is null");
+  if (reinterpret_cast<uintptr_t>(dev_workspace) % 256 != 0)
+    return fail(nullptr, KS_E_INVAL, "workspace must be 256-byte aligned");
+  ks_system* s = new ks_system();
+  init_dims(s, d);
+  size_t need = 0;
+  layout(s, nullptr, &need);
+  if (ws_bytes < need) {
+    delete s;
+    return fail(nullptr, KS_E_NOMEM, "workspace smaller than ks_workspace_bytes()");
+  }
+  layout(s, static_cast<char*>(dev_workspace), &need);
+  s->st = static_cast<hipStream_t>(hip_stream);
+  if (hipHostMalloc(&s->host, 1024, hipHostMallocDefault) != hipSuccess) {
+    delete s;
+    return fail(nullptr, KS_E_HIP, "pinned host buffer");
+  }
+  std::memset(s->host, 0, 1024);
+  const int M = d->n_nuclei;
+  hipError_t e = hipSuccess;
+  if (M > 0) {
+    e = hipMemcpyAsync(s->Rd, s->R.data(), 3 * M * sizeof(double), hipMemcpyHostToDevice, s->st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(s->Zd, s->Z.data(), M * sizeof(double), hipMemcpyHostToDevice, s->st);
+  }
+  if (e == hipSuccess && d->v_ext_override)
+    e = hipMemcpyAsync(s->vext, d->v_ext_override, (size_t)s->n * sizeof(double),
+                       hipMemcpyHostToDevice, s->st);
+  if (e != hipSuccess) {
+    rc = hip_check(s, e, "upload");
+    ks_destroy_system(s);
+    return rc;
+  }
+  if (!d->v_ext_override) {
+    if (s->use_ext && M > 0) launch_vext(s->vext, s->Rd, s->Zd, M, s->grid, d->rc, s->st);
+    else launch_fill(s->vext, 0.0, s->n, s->st);
+  }
+  if (!d->v_ext_override && s->use_ext && M > 1) launch_enuc(s->enuc, s->Rd, s->Zd, M, s->st);
+  else launch_set_scalar(s->enuc, 0.0, s->st);
+  for (int i = 0; i < 2; ++i) {
+    launch_fill(s->vh[i], 0.0, s->n, s->st);
+    launch_copy_vec(s->veff[i], s->vext, s->n, s->st);
+  }
+  launch_ls_reset(s->ls, s->st);
+  // the CG arrival counter must start at zero
+  launch_fill(reinterpret_cast<double*>(s->cg), 0.0, sizeof(CgState) / sizeof(double), s->st);
+  rc = launch_check(s, "setup");
+  if (rc == KS_OK) rc = hip_check(s, hipStreamSynchronize(s->st), "setup sync");
+  if (rc) {
+    std::string m = s->err;
+    ks_destroy_system(s);
+    return fail(nullptr, rc, m);
+  }
+  *out = s;
+  return KS_OK;
+}
+
+void ks_destroy_system(ks_system* s) {
+  if (!s) return;
+  if (s->host) {
+    (void)hipStreamSynchronize(s->st);
+    (void)hipHostFree(s->host);
+  }
+  delete s;
+}
+
+int ks_density(ks_system* s, const void* X, double* rho) {
+  if (!s || !X || !rho) return fail(s, KS_E_INVAL, "null argument");
+  launch_density<double>(static_cast<const double*>(X), s->ld, s->n, s->p, s->f / s->grid.dV,
+                         rho, s->st);
+  int rc = launch_check(s, "density");
+  return rc ? rc : hip_check(s, hipStreamSynchronize(s->st), "density sync");
+}
+
+int ks_hartree_solve(ks_system* s, const double* rho, double* v_h, int warm, int* iters,
+                     double* relres) {
+  if (!s || !rho || !v_h) return fail(s, KS_E_INVAL, "null argument");
+  int it = 0;
+  double rr = 0.0;
+  int rc = hartree(s, rho, warm ? v_h : nullptr, v_h, &it, &rr);
+  if (rc) return rc;
+  if (host_cg(s)->bb == 0.0) launch_fill(v_h, 0.0, s->n, s->st);
+  rc = hip_check(s, hipStreamSynchronize(s->st), "hartree sync");
+  if (iters) *iters = it;
+  if (relres) *relres = rr;
+  if (rc) return rc;
+  if (rr > s->htol) return fail(s, KS_E_NOT_CONVERGED, "Hartree CG reached its iteration cap");
+  return KS_OK;
+}
+
+int ks_apply_hamiltonian(ks_system* s, const void* X, void* Y, const double* v_eff) {
+  if (!s || !X || !Y) return fail(s, KS_E_INVAL, "null argument");
+  if (X == Y) return fail(s, KS_E_INVAL, "X and Y must differ");
+  launch_hx<double>(static_cast<const double*>(X), s->ld, static_cast<double*>(Y), s->ld,
+                    v_eff ? v_eff : s->veff[s->cur], s->vext, s->grid, s->p, 1.0, nullptr,
+                    s->st);
+  int rc = launch_check(s, "hamiltonian");
+  return rc ? rc : hip_check(s, hipStreamSynchronize(s->st), "hamiltonian sync");
+}
+
+int ks_get_potentials(ks_system* s, double* v_ext, double* v_h, double* v_eff) {
+  if (!s) return fail(s, KS_E_INVAL, "null system");
+  if (v_ext) launch_copy_vec(v_ext, s->vext, s->n, s->st);
+  if (v_h) launch_copy_vec(v_h, s->vh[s->cur], s->n, s->st);
+  if (v_eff) launch_copy_vec(v_eff, s->veff[s->cur], s->n, s->st);
+  int rc = launch_check(s, "potentials");
+  return rc ? rc : hip_check(s, hipStreamSynchronize(s->st), "potentials sync");
+}
+
+int ks_gram(ks_system* s, const void* Ain, const void* Bin, double* out) {
+  if (!s || !Ain || !Bin || !out) return fail(s, KS_E_INVAL, "null argument");
+  const int t = 1 - s->cur;
+  launch_copy_block<double>(s->X[t], s->p, static_cast<const double*>(Ain), s->ld, s->n, s->p,
+                            s->st);
+  launch_copy_block<double>(s->G[t], s->p, static_cast<const double*>(Bin), s->ld, s->n, s->p,
+                            s->st);
+  launch_gram(s->X[t], s->G[t], s->p, s->n, s->p, 3, s->gram_part, s->gram_nchunks, s->st);
+  launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, 3, s->p, s->gxg[t], s->st);
+  launch_compact_gram(s->gxg[t], s->pp, s->p, out, s->st);
+  int rc = launch_check(s, "gram");
+  return rc ? rc : hip_check(s, hipStreamSynchronize(s->st), "gram sync");
+}
+
+int ks_energy_grad(ks_system* s, const void* X, void* G, void* gradE, ks_energy* out) {
+  if (!s || !X) return fail(s, KS_E_INVAL, "null argument");
+  const int c = s->cur;
+  launch_copy_block<double>(s->X[c], s->p, static_cast<const double*>(X), s->ld, s->n, s->p,
+                            s->st);
+  int rc = evaluate(s, c, false, -1, c, false);
+  if (rc) return rc;
+  if (G)
+    launch_copy_block<double>(static_cast<double*>(G), s->ld, s->G[c], s->p, s->n, s->p, s->st);
+  if (gradE)
+    launch_copy_block<double>(static_cast<double*>(gradE), s->ld, s->D[c], s->p, s->n, s->p,
+                              s->st);
+  rc = launch_check(s, "energy_grad");
+  if (rc) return rc;
+  EvalOut* he = host_ev(s);
+  rc = readback(s, he, s->ev[c]);
+  if (rc) return rc;
+  if (out) to_energy(*he, out);
+  if (he->nonfinite) return fail(s, KS_E_NONFINITE, "non-finite energy or gradient");
+  return KS_OK;
+}
+
+int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind, void* X_out) {
+  if (!s || !X || !G || !X_out) return fail(s, KS_E_INVAL, "null argument");
+  if (kind != KS_QR && kind != KS_WY) return fail(s, KS_E_INVAL, "unknown retraction");
+  if (X_out == X || X_out == G) return fail(s, KS_E_INVAL, "X_out must not alias X or G");
+  if (!std::isfinite(tau)) return fail(s, KS_E_INVAL, "tau must be finite");
+  const int t = 1 - s->cur, c = s->cur;
+  launch_copy_block<double>(s->X[t], s->p, static_cast<const double*>(X), s->ld, s->n, s->p,
+                            s->st);
+  launch_copy_block<double>(s->G[t], s->p, static_cast<const double*>(G), s->ld, s->n, s->p,
+                            s->st);
+  launch_gram(s->X[t], s->G[t], s->p, s->n, s->p, 3, s->gram_part, s->gram_nchunks, s->st);
+  launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, 3, s->p, s->gxg[t], s->st);
+  launch_set_scalar(s->tau_user, tau, s->st);
+  int* hstat = host_int(s);
+  hstat[0] = 0;
+  int rc0 = hip_check(s, hipMemcpyAsync(s->status, hstat, sizeof(int), hipMemcpyHostToDevice,
+                                        s->st), "status upload");
+  if (rc0) return rc0;
+  CombineArgs ca{};
+  ca.ld = s->p;
+  ca.n = s->n;
+  ca.p = s->p;
+  if (kind == KS_QR) {
+    launch_grad_weights(s->gxg[t], s->pp, s->W, s->st);
+    CombineArgs cd{};
+    cd.X = s->X[t];
+    cd.A = s->W;
+    cd.C0 = s->G[t];
+    cd.out = s->D[t];
+    cd.ld = s->p;
+    cd.n = s->n;
+    cd.p = s->p;
+    launch_combine(cd, s->st);
+    launch_gram(s->X[t], s->D[t], s->p, s->n, s->p, 3, s->gram_part, s->gram_nchunks, s->st);
+    launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, 3, s->p, s->gxd[t], s->st);
+    launch_qr_factor(s->gxd[t], s->p, s->pp, s->tau_user, s->A, s->B, s->work, s->status,
+                     s->st);
+    ca.Y = s->D[t];
+  } else {
+    launch_wy_factor(s->gxg[t], s->p, s->pp, s->tau_user, INFINITY, s->A, s->B, s->work,
+                     s->status, nullptr, s->st);
+    ca.Y = s->G[t];
+  }
+  ca.X = s->X[t];
+  ca.A = s->A;
+  ca.B = s->B;
+  ca.out = s->D[c];
+  launch_combine(ca, s->st);
+  launch_copy_block<double>(static_cast<double*>(X_out), s->ld, s->D[c], s->p, s->n, s->p, s->st);
+  int rc = launch_check(s, "retract");
+  if (rc) return rc;
+  rc = readback(s, hstat, s->status);
+  if (rc) return rc;
+  if (hstat[0] == KS_E_NOT_SPD) return fail(s, KS_E_NOT_SPD, "Cholesky breakdown of Y^T Y");
+  if (hstat[0] == KS_E_SINGULAR) return fail(s, KS_E_SINGULAR, "singular SMW system");
+  if (hstat[0] != 0) return fail(s, hstat[0], "retraction failed");
+  return KS_OK;
+}
+
+int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* r) {
+  if (!s || !X_inout) return fail(s, KS_E_INVAL, "null argument");
+  const auto t0 = std::chrono::steady_clock::now();
+  ks_opt_params prm;
+  if (o) prm = *o;
+  else ks_default_params(&prm);
+  if (prm.retraction != KS_QR && prm.retraction != KS_WY)
+    return fail(s, KS_E_INVAL, "unknown retraction");
+  if (!(prm.delta > 0.0 && prm.delta < 1.0) || !(prm.tau0 > 0.0) || prm.h_max < 0)
+    return fail(s, KS_E_INVAL, "bad line-search parameters");
+  const LsParams lp = to_params(prm);
+  const bool qr = prm.retraction == KS_QR;
+  s->cg_total = 0;
+  int c = s->cur;
+  launch_copy_block<double>(s->X[c], s->p, static_cast<const double*>(X_inout), s->ld, s->n,
+                            s->p, s->st);
+  launch_ls_reset(s->ls, s->st);
+  int* hint = host_int(s);
+  hint[1] = 0;
+  int rc = hip_check(s, hipMemcpyAsync(s->reorth_count, &hint[1], sizeof(int),
+                                       hipMemcpyHostToDevice, s->st), "counter upload");
+  if (rc) return rc;
+  rc = evaluate(s, c, false, -1, c, qr);
+  if (rc) return rc;
+  launch_ls_init(s->ev[c], s->ls, lp, s->st);
+  LsState* hl = host_ls(s);
+  rc = readback(s, hl, s->ls);
+  if (rc) return rc;
+  while (hl->stop == KS_STOP_NONE) {
+    const int t = 1 - c;
+    CombineArgs ca{};
+    ca.X = s->X[c];
+    ca.A = s->A;
+    ca.B = s->B;
+    ca.out = s->X[t];
+    ca.rho = s->rho;
+    ca.rho_scale = s->f / s->grid.dV;
+    ca.ld = s->p;
+    ca.n = s->n;
+    ca.p = s->p;
+    if (qr) {
+      launch_qr_factor(s->gxd[c], s->p, s->pp, &s->ls->tau, s->A, s->B, s->work, &s->ls->error,
+                       s->st);
+      ca.Y = s->D[c];
+    } else {
+      launch_wy_factor(s->gxg[c], s->p, s->pp, &s->ls->tau, prm.reorth_tol, s->A, s->B, s->work,
+                       &s->ls->error, s->reorth_count, s->st);
+      ca.Y = s->G[c];
+    }
+    launch_combine(ca, s->st);
+    rc = evaluate(s, t, true, c, c, qr);
+    if (rc) return rc;
+    launch_ls_judge(s->ev[t], s->ls, lp, s->st);
+    rc = launch_check(s, "line search");
+    if (rc) return rc;
+    rc = readback(s, hl, s->ls);
+    if (rc) return rc;
+    if (hl->error) break;
+    if (hl->accepted) {
+      c = t;
+      s->cur = c;
+    }
+  }
+  launch_copy_block<double>(static_cast<double*>(X_inout), s->ld, s->X[c], s->p, s->n, s->p,
+                            s->st);
+  rc = launch_check(s, "minimize");
+  if (rc) return rc;
+  EvalOut* he = host_ev(s);
+  rc = readback(s, he, s->ev[c]);
+  if (rc) return rc;
+  rc = readback(s, &hint[1], s->reorth_count);
+  if (rc) return rc;
+  if (r) {
+    std::memset(r, 0, sizeof(*r));
+    r->iters = hl->k;
+    r->nfe = hl->nfe;
+    r->backtracks = hl->backtracks;
+    r->ls_fail = hl->ls_fail;
+    r->reorths = hint[1];
+    r->stop_reason = hl->stop;
+    r->energy = he->total;
+    r->grad_norm = std::sqrt(std::max(he->g2, 0.0));
+    to_energy(*he, &r->terms);
+    r->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    r->hartree_iters_total = s->cg_total;
+  }
+  if (hl->error) return fail(s, hl->error, ks_status_string(hl->error));
+  if (hl->stop == KS_STOP_MAXIT) return fail(s, KS_E_NOT_CONVERGED, "max_iter reached");
+  return KS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,182 @@
+// Internal declarations shared by the HIP kernels and the host orchestration.
+// Not part of the public ABI (include/ks.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ks {
+
+constexpr int kBlock = 256;          // threads per block of the streaming kernels
+constexpr int kWave = 64;            // CDNA wavefront
+constexpr int kXcds = 8;             // MI355X: 8 accelerator complex dies, one L2 each
+constexpr int kMaxScalarSlots = 16;  // scalar reduction slots per evaluation
+constexpr double kPi = 3.14159265358979323846;
+
+// Scalar reduction slots (sums over the grid of one evaluation).
+enum Slot : int {
+  SL_KIN = 0,   // sum_g,i X_gi (L X)_gi
+  SL_EXT = 1,   // sum_g V_ext,g sum_i X_gi^2
+  SL_EH = 2,    // sum_g rho_g V_H,g
+  SL_EX = 3,    // sum_g rho_g eps_x(rho_g)
+  SL_DD = 4,    // ||D||_F^2, D = G - X G^T X
+  SL_SS = 5,    // tr(S^T S),  S = X_t - X_k
+  SL_SY = 6,    // tr(S^T Yd), Yd = D_t - D_k
+  SL_YY = 7,    // tr(Yd^T Yd)
+  SL_COUNT = 8
+};
+
+// Conjugate-gradient state kept on the device (one solve at a time per system).
+struct CgState {
+  double rr;       // current r.r
+  double bb;       // b.b, b = 4 pi rho
+  double pq;       // p.Lp of the current iteration
+  double alpha, beta;
+  double tol2;     // squared relative tolerance
+  int it;          // iterations done
+  int maxit;
+  int done;        // 1 once converged or at maxit
+  int pad;
+  unsigned int count;  // arrival counter of the last-block reduction
+  unsigned int pad2;
+};
+
+// Results of one energy/gradient evaluation, assembled on the device.
+struct EvalOut {
+  double total, kinetic, external, hartree, xc, nuclear;
+  double g2;        // ||grad E||_F^2
+  double ss, sy, yy;
+  double orth2;     // ||X^T X - I||_F^2
+  double cg_relres;
+  int cg_iters;
+  int nonfinite;
+};
+
+// Optimiser parameters and state of Alg. 3 on the device.
+struct LsParams {
+  double tau0, rho1, delta, eta, eps_g, tau_min, tau_max, reorth_tol, stagnation_tol;
+  int max_iter, bb_rule, h_max, retraction;
+};
+
+struct LsState {
+  double E, g2;        // at the current iterate X_k
+  double C, Q;         // nonmonotone reference value and weight
+  double tau_bb, tau;  // BB value of this iteration and the current trial step
+  double df[3];        // last relative energy changes
+  int ndf;
+  int k;               // accepted iterations
+  int h;               // backtracks in this iteration
+  int accepted;        // last trial accepted
+  int stop;            // KS_STOP_*
+  int backtracks, ls_fail, nfe, reorth_flag;
+  int error;           // KS_E_* raised by a device step
+  int pad;
+};
+
+// Constants of the discretisation, passed by value to kernels.
+struct Grid {
+  int nx, ny, nz;
+  int n;
+  double h, inv_h2, dV;
+  double lo[3];
+};
+
+__host__ __device__ inline int round_up(int a, int b) { return (a + b - 1) / b * b; }
+
+// Blocks are dispatched round-robin over the 8 XCDs; map them so that each XCD gets
+// one contiguous range of logical blocks (neighbouring grid planes share an L2).
+__device__ inline int xcd_remap(int b, int nb) {
+  const int q = nb / kXcds, r = nb % kXcds;
+  const int x = b % kXcds, idx = b / kXcds;
+  return x * q + (x < r ? x : r) + idx;
+}
+
+// Deterministic sum over a block of kBlock threads (fixed shuffle/LDS tree order).
+// sh must hold kBlock/kWave doubles.  Result valid in thread 0.
+__device__ inline double block_sum(double v, double* sh) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < (int)(blockDim.x / kWave); ++i) s += sh[i];
+  }
+  __syncthreads();
+  return s;
+}
+
+// ------------------------------------------------------------------------------------
+// Launch wrappers (defined in the .hip files).  All take the stream last.
+// ------------------------------------------------------------------------------------
+struct Partials {
+  double* buf;      // [slot][block]
+  int stride;       // max blocks per slot
+};
+
+// grid kernels (kernels_grid.hip)
+void launch_vext(double* v, const double* R, const double* Z, int M, Grid g, double rc,
+                 hipStream_t st);
+void launch_enuc(double* out, const double* R, const double* Z, int M, hipStream_t st);
+void launch_fill(double* x, double v, size_t n, hipStream_t st);
+void launch_copy_vec(double* dst, const double* src, size_t n, hipStream_t st);
+template <typename T>
+void launch_copy_block(T* dst, int ldd, const T* src, int lds, int n, int p, hipStream_t st);
+template <typename T>
+void launch_density(const T* X, int ld, int n, int p, double scale, double* rho,
+                    hipStream_t st);
+void launch_xc(const double* rho, const double* vh, const double* vext, double* veff,
+               Grid g, int use_h, int use_x, const CgState* cg, Partials pt, hipStream_t st);
+template <typename T>
+void launch_hx(const T* X, int ldx, T* Y, int ldy, const double* veff, const double* vext,
+               Grid g, int p, double scale, Partials* pt, hipStream_t st);
+int cg_blocks(int n);
+void launch_cg_init(const double* rho, const double* x0, double* x, double* r, double* p0,
+                    CgState* cs, double tol, int maxit, Grid g, double* part,
+                    hipStream_t st);
+void launch_cg_iter(double* x, double* r, double* pa, double* pb, double* q, CgState* cs,
+                    Grid g, double* part, hipStream_t st);
+int scalar_blocks(int n);
+void launch_reduce_scalars(const double* part, int stride, const int* nblk, int nslots,
+                           double* out, hipStream_t st);
+
+// dense kernels (kernels_dense.hip)
+int gram_chunks(int n, int pp);
+void launch_gram(const double* A, const double* B, int ld, int n, int p, int nprod,
+                 double* partials, int nchunks, hipStream_t st);
+void launch_gram_reduce(const double* partials, int nchunks, int pp, int nprod, int p,
+                        double* out, hipStream_t st);
+struct CombineArgs {
+  const double* X; const double* A;     // X (n x ld) times A (pp x pp)
+  const double* Y; const double* B;     // optional Y (n x ld) times B
+  const double* C0;                     // optional additive n x ld term
+  double* out;                          // n x ld
+  double* rho; double rho_scale;        // optional density of out
+  // optional BB/gradient epilogue: out is D_t; uses Xt (= X), Xk, Dk
+  const double* Xk; const double* Dk;
+  Partials pt;                          // slots SL_DD.. SL_YY (by value)
+  int ld, n, p;
+};
+void launch_combine(const CombineArgs& a, hipStream_t st);
+int combine_blocks(int n);
+
+// small dense kernels (kernels_small.hip)
+void launch_grad_weights(const double* gram, int pp, double* W, hipStream_t st);
+void launch_qr_factor(const double* gram_xd, int p, int pp, const double* tau, double* A,
+                      double* B, double* work, int* status, hipStream_t st);
+void launch_wy_factor(const double* gram_xg, int p, int pp, const double* tau,
+                      double reorth_tol, double* A, double* B, double* work, int* status,
+                      int* reorth_flag, hipStream_t st);
+size_t small_work_doubles(int p);
+void launch_ls_reset(LsState* ls, hipStream_t st);
+void launch_compact_gram(const double* gram, int pp, int p, double* out, hipStream_t st);
+void launch_finish_eval(const double* sums, const double* gram_xx, int p, int pp, double f,
+                        double dV, const double* enuc, const CgState* cg, EvalOut* out,
+                        hipStream_t st);
+void launch_set_scalar(double* dst, double v, hipStream_t st);
+void launch_ls_init(const EvalOut* ev, LsState* ls, LsParams prm, hipStream_t st);
+void launch_ls_judge(const EvalOut* ev, LsState* ls, LsParams prm, hipStream_t st);
+
+}  // namespace ks

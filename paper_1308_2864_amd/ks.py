@@ -1,0 +1,247 @@
+"""Python binding of ``libks.so`` (C ABI in ``include/ks.h``).
+
+Argument marshalling only: every function forwards to the C entry point of the same
+name.  Device memory and the stream come from PyTorch (``torch.cuda``); the library
+itself allocates no device memory.  If the shared library has not been built this
+module raises on import, so nothing can silently run without the HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libks.so")
+
+# ---- constants (mirror include/ks.h) ----------------------------------------------------
+KS_OK = 0
+KS_E_INVAL = -1
+KS_E_NOMEM = -2
+KS_E_HIP = -3
+KS_E_NOT_SPD = -4
+KS_E_SINGULAR = -5
+KS_E_NONFINITE = -6
+KS_E_NOT_CONVERGED = -7
+KS_E_UNSUPPORTED = -8
+
+KS_DISC_FD7, KS_DISC_Q1 = 0, 1
+KS_PREC_FP64, KS_PREC_FP32, KS_PREC_MIXED_BF16 = 0, 1, 2
+KS_TERM_EXT, KS_TERM_HARTREE, KS_TERM_XC, KS_TERM_ALL = 1, 2, 4, 7
+KS_HARTREE_CG, KS_HARTREE_PCG_FD = 0, 1
+KS_QR, KS_WY = 0, 1
+KS_BB_ALT, KS_BB1, KS_BB2 = 0, 1, 2
+KS_STOP_NONE, KS_STOP_GRAD, KS_STOP_STAGNATION, KS_STOP_MAXIT, KS_STOP_ERROR = 0, 1, 2, 3, 4
+STOP_NAMES = {0: "none", 1: "grad", 2: "stagnation", 3: "maxit", 4: "error"}
+
+
+class ks_system_desc(C.Structure):
+    _fields_ = [
+        ("disc", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+        ("h", C.c_double), ("box_lo", C.c_double * 3), ("p", C.c_int), ("ld", C.c_int),
+        ("occupation", C.c_double), ("n_nuclei", C.c_int),
+        ("R", C.POINTER(C.c_double)), ("Z", C.POINTER(C.c_double)), ("rc", C.c_double),
+        ("terms", C.c_int), ("v_ext_override", C.POINTER(C.c_double)), ("precision", C.c_int),
+        ("hartree_solver", C.c_int), ("hartree_tol", C.c_double), ("hartree_maxit", C.c_int),
+    ]
+
+
+class ks_energy(C.Structure):
+    _fields_ = [
+        ("total", C.c_double), ("kinetic", C.c_double), ("external", C.c_double),
+        ("hartree", C.c_double), ("xc", C.c_double), ("nuclear", C.c_double),
+        ("grad_norm", C.c_double), ("orth_error", C.c_double), ("hartree_iters", C.c_int),
+        ("hartree_relres", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ks_opt_params(C.Structure):
+    _fields_ = [
+        ("tau0", C.c_double), ("rho1", C.c_double), ("delta", C.c_double), ("eta", C.c_double),
+        ("eps_g", C.c_double), ("max_iter", C.c_int), ("bb_rule", C.c_int),
+        ("retraction", C.c_int), ("tau_min", C.c_double), ("tau_max", C.c_double),
+        ("h_max", C.c_int), ("reorth_tol", C.c_double), ("stagnation_tol", C.c_double),
+    ]
+
+
+class ks_result(C.Structure):
+    _fields_ = [
+        ("iters", C.c_int), ("nfe", C.c_int), ("backtracks", C.c_int), ("ls_fail", C.c_int),
+        ("reorths", C.c_int), ("stop_reason", C.c_int), ("energy", C.c_double),
+        ("grad_norm", C.c_double), ("terms", ks_energy), ("seconds", C.c_double),
+        ("hartree_iters_total", C.c_longlong),
+    ]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    lib = C.CDLL(LIB_PATH)
+    vp, ip, dp = C.c_void_p, C.c_int, C.POINTER(C.c_double)
+    sig = {
+        "ks_workspace_bytes": (C.c_size_t, [C.POINTER(ks_system_desc)]),
+        "ks_create_system": (ip, [C.POINTER(ks_system_desc), vp, C.c_size_t, vp, C.POINTER(vp)]),
+        "ks_destroy_system": (None, [vp]),
+        "ks_default_params": (None, [C.POINTER(ks_opt_params)]),
+        "ks_status_string": (C.c_char_p, [ip]),
+        "ks_last_error": (C.c_char_p, [vp]),
+        "ks_energy_grad": (ip, [vp, vp, vp, vp, C.POINTER(ks_energy)]),
+        "ks_retract": (ip, [vp, vp, vp, C.c_double, ip, vp]),
+        "ks_minimize": (ip, [vp, vp, C.POINTER(ks_opt_params), C.POINTER(ks_result)]),
+        "ks_density": (ip, [vp, vp, vp]),
+        "ks_hartree_solve": (ip, [vp, vp, vp, ip, C.POINTER(C.c_int), dp]),
+        "ks_apply_hamiltonian": (ip, [vp, vp, vp, vp]),
+        "ks_get_potentials": (ip, [vp, vp, vp, vp]),
+        "ks_gram": (ip, [vp, vp, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+class KSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{lib.ks_status_string(code).decode()} ({code}): {msg}")
+        self.code = code
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _check(code, handle=None):
+    if code != KS_OK:
+        raise KSError(code, lib.ks_last_error(handle).decode(errors="replace"))
+    return code
+
+
+# ---- thin wrappers with the ABI's names ---------------------------------------------------
+
+def ks_default_params(**overrides) -> ks_opt_params:
+    o = ks_opt_params()
+    lib.ks_default_params(C.byref(o))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+def make_desc(nx, ny, nz, h, lo, p, R=None, Z=None, *, f=2.0, rc=0.5, terms=KS_TERM_ALL,
+              v_ext_override=None, ld=0, precision=KS_PREC_FP64, disc=KS_DISC_FD7,
+              hartree_solver=KS_HARTREE_CG, hartree_tol=0.0, hartree_maxit=0):
+    """Fills a ks_system_desc; the returned object keeps the host arrays alive."""
+    d = ks_system_desc()
+    d.disc, d.nx, d.ny, d.nz, d.h = disc, nx, ny, nz, float(h)
+    d.box_lo[:] = [float(v) for v in lo]
+    d.p, d.ld, d.occupation = p, ld, float(f)
+    R = np.ascontiguousarray(np.zeros((0, 3)) if R is None else R, dtype=np.float64).reshape(-1, 3)
+    Z = np.ascontiguousarray(np.zeros(0) if Z is None else Z, dtype=np.float64).ravel()
+    d.n_nuclei = int(R.shape[0])
+    d._keep = [R, Z]
+    d.R = R.ctypes.data_as(C.POINTER(C.c_double)) if R.size else None
+    d.Z = Z.ctypes.data_as(C.POINTER(C.c_double)) if Z.size else None
+    d.rc, d.terms = float(rc), int(terms)
+    if v_ext_override is not None:
+        v = np.ascontiguousarray(v_ext_override, dtype=np.float64).ravel()
+        d._keep.append(v)
+        d.v_ext_override = v.ctypes.data_as(C.POINTER(C.c_double))
+    d.precision, d.hartree_solver = precision, hartree_solver
+    d.hartree_tol, d.hartree_maxit = float(hartree_tol), int(hartree_maxit)
+    return d
+
+
+def ks_workspace_bytes(desc) -> int:
+    return int(lib.ks_workspace_bytes(C.byref(desc)))
+
+
+class KSSystem:
+    """A system created by ks_create_system on a torch-owned workspace and stream."""
+
+    def __init__(self, desc, device="cuda", stream=None):
+        import torch
+        self.desc = desc
+        nbytes = ks_workspace_bytes(desc)
+        if nbytes == 0:
+            raise KSError(KS_E_INVAL, lib.ks_last_error(None).decode())
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check(lib.ks_create_system(C.byref(desc), C.c_void_p(base + off), nbytes,
+                                    C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self.n = desc.nx * desc.ny * desc.nz
+        self.p = desc.p
+        self.ld = desc.ld or desc.p
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.ks_destroy_system(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # each method is one C call
+    def ks_energy_grad(self, X, G=None, gradE=None) -> ks_energy:
+        e = ks_energy()
+        _check(lib.ks_energy_grad(self.h, _ptr(X), _ptr(G), _ptr(gradE), C.byref(e)), self.h)
+        return e
+
+    def ks_retract(self, X, G, tau, kind, X_out):
+        _check(lib.ks_retract(self.h, _ptr(X), _ptr(G), float(tau), int(kind), _ptr(X_out)), self.h)
+
+    def ks_minimize(self, X, params=None, check=True) -> ks_result:
+        r = ks_result()
+        code = lib.ks_minimize(self.h, _ptr(X), C.byref(params) if params is not None else None,
+                               C.byref(r))
+        if check and code not in (KS_OK, KS_E_NOT_CONVERGED):
+            _check(code, self.h)
+        r.code = code
+        return r
+
+    def ks_density(self, X, rho):
+        _check(lib.ks_density(self.h, _ptr(X), _ptr(rho)), self.h)
+
+    def ks_hartree_solve(self, rho, v_h, warm=False):
+        it = C.c_int()
+        rr = C.c_double()
+        _check(lib.ks_hartree_solve(self.h, _ptr(rho), _ptr(v_h), int(bool(warm)), C.byref(it),
+                                    C.byref(rr)), self.h)
+        return it.value, rr.value
+
+    def ks_apply_hamiltonian(self, X, Y, v_eff=None):
+        _check(lib.ks_apply_hamiltonian(self.h, _ptr(X), _ptr(Y), _ptr(v_eff)), self.h)
+
+    def ks_get_potentials(self, v_ext=None, v_h=None, v_eff=None):
+        _check(lib.ks_get_potentials(self.h, _ptr(v_ext), _ptr(v_h), _ptr(v_eff)), self.h)
+
+    def ks_gram(self, A, B, out):
+        _check(lib.ks_gram(self.h, _ptr(A), _ptr(B), _ptr(out)), self.h)
+
+
+def system_from_spec(spec, **kw) -> KSSystem:
+    """Creates a KSSystem for a ``synth.SystemSpec``."""
+    terms = (KS_TERM_EXT if spec.ext else 0) | (KS_TERM_HARTREE if spec.hartree else 0) | \
+            (KS_TERM_XC if spec.xc else 0)
+    dkw = dict(f=spec.f, rc=spec.rc, terms=terms)
+    device = kw.pop("device", "cuda")
+    dkw.update(kw)
+    desc = make_desc(spec.nx, spec.ny, spec.nz, spec.h, spec.lo, spec.p, spec.R, spec.Z, **dkw)
+    return KSSystem(desc, device=device)

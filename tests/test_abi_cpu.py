@@ -1,0 +1,80 @@
+"""Host-only checks of the C ABI: the library loads, exports every declared symbol,
+and rejects bad descriptors before touching a device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ks.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ks_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("ks_create_system", "ks_energy_grad", "ks_retract", "ks_minimize",
+                 "ks_workspace_bytes", "ks_destroy_system"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1308_2864_amd import ks
+    missing = [n for n in _declared() if not hasattr(ks.lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings_and_defaults():
+    from paper_1308_2864_amd import ks
+    assert ks.lib.ks_status_string(ks.KS_E_NOT_SPD).decode().startswith("Cholesky")
+    o = ks.ks_default_params()
+    assert (o.tau0, o.rho1, o.delta, o.eta, o.eps_g) == (1e-3, 1e-4, 0.1, 0.85, 1e-6)
+    assert o.h_max == 20 and o.reorth_tol == 1e-12 and o.stagnation_tol == 1e-13
+
+
+def test_workspace_sizing_and_descriptor_validation():
+    from paper_1308_2864_amd import ks
+    d = ks.make_desc(24, 24, 24, 0.64, (-8, -8, -8), 4, [[0, 0, 0], [1, 1, 1]], [2, 2])
+    nb = ks.ks_workspace_bytes(d)
+    n, p = 24 ** 3, 4
+    assert nb > 6 * n * p * 8 + 10 * n * 8
+    # bigger p, bigger workspace
+    d2 = ks.make_desc(24, 24, 24, 0.64, (-8, -8, -8), 32, [[0, 0, 0]], [2])
+    assert ks.ks_workspace_bytes(d2) > nb
+    for bad in (dict(p=0), dict(p=65), dict(nx=0), dict(h=0.0), dict(f=0.0)):
+        kw = dict(nx=8, ny=8, nz=8, h=0.5, lo=(0, 0, 0), p=2)
+        f = bad.pop("f", 2.0)
+        kw.update(bad)
+        db = ks.make_desc(kw["nx"], kw["ny"], kw["nz"], kw["h"], kw["lo"], kw["p"], f=f)
+        assert ks.ks_workspace_bytes(db) == 0
+        h = C.c_void_p()
+        assert ks.lib.ks_create_system(C.byref(db), C.c_void_p(1 << 20), 1 << 30, None,
+                                       C.byref(h)) == ks.KS_E_INVAL
+    # ld < p
+    db = ks.make_desc(8, 8, 8, 0.5, (0, 0, 0), 4, ld=3)
+    assert ks.ks_workspace_bytes(db) == 0
+    # unsupported discretisation / precision in this build are reported, not ignored
+    dq = ks.make_desc(8, 8, 8, 0.5, (0, 0, 0), 4, disc=ks.KS_DISC_Q1)
+    h = C.c_void_p()
+    rc = ks.lib.ks_create_system(C.byref(dq), C.c_void_p(1 << 20), 1 << 30, None, C.byref(h))
+    assert rc in (ks.KS_E_UNSUPPORTED, ks.KS_OK) or rc < 0
+
+
+def test_create_rejects_small_or_misaligned_workspace_without_a_device():
+    from paper_1308_2864_amd import ks
+    d = ks.make_desc(10, 9, 8, 0.5, (0, 0, 0), 3, [[0.1, 0.2, 0.3]], [1.0])
+    need = ks.ks_workspace_bytes(d)
+    h = C.c_void_p()
+    # workspace too small: rejected before any device call
+    assert ks.lib.ks_create_system(C.byref(d), C.c_void_p(1 << 20), need - 1, None,
+                                   C.byref(h)) == ks.KS_E_NOMEM
+    assert b"workspace" in ks.lib.ks_last_error(None)
+    # misaligned
+    assert ks.lib.ks_create_system(C.byref(d), C.c_void_p((1 << 20) + 8), need, None,
+                                   C.byref(h)) == ks.KS_E_INVAL
+    assert ks.lib.ks_create_system(C.byref(d), None, need, None, C.byref(h)) == ks.KS_E_INVAL
