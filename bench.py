@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Benchmark: converged Kohn-Sham solves per second on one MI355X.
+
+One step is one full run of Alg. 3 (energy/gradient assembly, BB step, nonmonotone
+search, retraction) from the seeded start X0 to the stopping rule of Section 4.1
+(||grad E||_F <= 1e-6 or energy stagnation), on the FP64 workload of a 64^3 grid
+(h = 0.3 bohr, n = 262144), p = 32 orbitals and 16 nuclei.  X0 is resident in HBM
+before the timed region; each step copies it into the working block on the device.
+
+Prints one JSON line.  Also reported: per-phase device time from the library's event
+timers, the roofline of the dominant single kernel, the Hamiltonian SpMM bandwidth, and
+the CPU oracle timed on a bounded sample of the same solve.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("converged KS solves/sec + p50/p99 latency, FP32/BF16 vs FP64 at 1e-6 Ha; "
+          "SpMM GB/s")
+HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+
+
+def phase_bytes(n, p, w=8):
+    """Algorithmic HBM bytes of one occurrence of each single-kernel phase."""
+    np_ = n * p * w
+    return {
+        "hamiltonian": 2 * np_ + 16 * n,   # read X, write G, read V_eff and V_ext
+        "gram": 2 * np_,                   # read X and G (or D)
+        "gradient": 5 * np_,               # read G, X, X_k, D_k; write D
+        "retract": 3 * np_ + 8 * n,        # read X, Y; write X+ and rho
+    }
+
+
+def cpu_baseline(spec, X0, gpu_iters, iters):
+    """Times the oracle on a bounded prefix of the same solve; extrapolates to solves/s."""
+    import numpy as np
+    from oracle import optm
+    from oracle.ks import KSSystemFD
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count() or 1
+    orc = KSSystemFD(spec.nx, spec.ny, spec.nz, spec.h, spec.lo, spec.p, spec.R, spec.Z,
+                     f=spec.f, rc=spec.rc)
+    t0 = time.perf_counter()
+    res = optm.minimize(orc.energy_grad, np.array(X0), optm.Params(max_iter=iters))
+    el = time.perf_counter() - t0
+    per_iter = el / max(res.iters, 1)
+    est = per_iter * gpu_iters
+    return {
+        "value": 1.0 / est, "unit": "solves/s", "cores": int(cores), "kind": "oracle",
+        "sample": (f"FP64 oracle Alg. 3 on the same 64^3, p=32 solve from the same X0, "
+                   f"{res.iters} iterations ({res.nfe} energy evaluations incl. the cold "
+                   f"first Hartree solve) in {el:.1f} s = {per_iter:.2f} s/iteration; "
+                   f"solves/s extrapolated with the GPU run's {gpu_iters} iterations per solve"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--retraction", choices=["qr", "wy"], default="qr")
+    ap.add_argument("--hartree", choices=["cg", "pcg_fd"], default="pcg_fd")
+    ap.add_argument("--cpu-iters", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--max-iter", type=int, default=10000,
+                    help="iteration cap (profiling runs only; the metric needs the default)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU; this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1308_2864_amd import ks, synth
+
+    spec = synth.make_config("c2", args.seed)
+    X0h = synth.make_x0(spec, args.seed)
+    print(f"# bench: workload {spec.name}, n={spec.n}, p={spec.p}, steps={args.steps}, "
+          f"warmup={args.warmup}", file=sys.stderr, flush=True)
+    solver = ks.KS_HARTREE_CG if args.hartree == "cg" else ks.KS_HARTREE_PCG_FD
+    sysg = ks.system_from_spec(spec, hartree_solver=solver)
+    X0 = torch.tensor(X0h, dtype=torch.float64, device="cuda")
+    X = torch.empty_like(X0)
+    prm = ks.ks_default_params(retraction=ks.KS_QR if args.retraction == "qr" else ks.KS_WY,
+                               max_iter=args.max_iter)
+
+    def step():
+        X.copy_(X0)
+        return sysg.ks_minimize(X, prm)
+
+    for i in range(args.warmup):
+        r = step()
+        print(f"# warmup {i}: {r.iters} it, E={r.energy:.10f}, {r.seconds:.3f} s",
+              file=sys.stderr, flush=True)
+
+    sysg.ks_enable_timers(True)
+    sysg.ks_read_timers(reset=True)
+    torch.cuda.synchronize()
+    lat, results = [], []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        a = time.perf_counter()
+        r = step()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - a)
+        results.append(r)
+        print(f"# step {i}: {r.iters} it, {r.nfe} evals, stop={ks.STOP_NAMES[r.stop_reason]}, "
+              f"E={r.energy:.12f}, |grad|={r.grad_norm:.2e}, hartree it "
+              f"{r.hartree_iters_total}, {lat[-1]:.3f} s",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    phases = sysg.ks_read_timers(reset=True)
+    sysg.ks_enable_timers(False)
+
+    converged = sum(1 for r in results if r.stop_reason in (ks.KS_STOP_GRAD,
+                                                            ks.KS_STOP_STAGNATION))
+    value = converged / elapsed
+    lat_ms = sorted(1e3 * v for v in lat)
+
+    def pct(q):
+        if not lat_ms:
+            return None
+        k = min(len(lat_ms) - 1, max(0, int(math.ceil(q / 100.0 * len(lat_ms))) - 1))
+        return lat_ms[k]
+
+    # per-phase achieved bandwidth from the live timers; dominant single kernel
+    pb = phase_bytes(spec.n, spec.p)
+    phase_out = {}
+    for name, (ms, cnt) in phases.items():
+        ent = {"ms": round(ms, 3), "count": int(cnt)}
+        if cnt and name in pb:
+            ent["avg_us"] = round(1e3 * ms / cnt, 2)
+            ent["GBps"] = round(pb[name] * cnt / (ms * 1e-3) / 1e9, 1)
+        phase_out[name] = ent
+    single = [k for k in pb if phases[k][1] > 0]
+    dom = max(single, key=lambda k: phases[k][0])
+    ms, cnt = phases[dom]
+    avg_s = ms * 1e-3 / cnt
+    achieved = pb[dom] / avg_s / 1e9
+    kernel_names = {"hamiltonian": "k_hx<double,true>", "gram": "k_gram<2,true>",
+                    "gradient": "k_combine<2,false,true,false,true>",
+                    "retract": "k_combine<2,true,false,true,false>"}
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": kernel_names[dom], "phase": dom,
+                "bytes_per_launch": pb[dom], "avg_launch_us": round(avg_s * 1e6, 2)}
+    spmm = phase_out.get("hamiltonian", {}).get("GBps")
+
+    iters = int(np.median([r.iters for r in results])) if results else 0
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(spec, X0h, iters, args.cpu_iters)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / max(args.steps, 1), 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{spec.name} FP64 {args.retraction.upper()} (configs[1])",
+                   "grid": [spec.nx, spec.ny, spec.nz], "h": spec.h, "p": spec.p,
+                   "nuclei": spec.M, "eps_g": prm.eps_g, "retraction": args.retraction,
+                   "hartree": args.hartree,
+                   "seed": args.seed},
+        "p50_ms": pct(50), "p99_ms": pct(99),
+        "converged": converged,
+        "iterations": iters,
+        "energy": results[-1].energy if results else None,
+        "grad_norm": results[-1].grad_norm if results else None,
+        "spmm_GBps": spmm,
+        "phases": phase_out,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

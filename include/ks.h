@@ -143,6 +143,23 @@ typedef struct ks_result {
   long long hartree_iters_total;
 } ks_result;
 
+/* Phases of the device timeline measured by the optional timers (ks_enable_timers).
+ * The single-kernel phases bracket exactly one kernel per occurrence. */
+#define KS_PH_HARTREE 0          /* one Hartree solve (all CG kernels of it)              */
+#define KS_PH_XC 1               /* exchange and effective potential (one kernel)         */
+#define KS_PH_HAMILTONIAN 2      /* G = 2f H X with energy partials (one kernel)          */
+#define KS_PH_GRAM 3             /* Gram blocks of [X, G] or [X, D] (one kernel)          */
+#define KS_PH_GRADIENT 4         /* grad E = G - X G^T X with BB sums (one kernel)        */
+#define KS_PH_RETRACT 5          /* X+ = X A + Y B with fused density (one kernel)        */
+#define KS_PH_SMALL 6            /* reductions, small dense factors, line-search logic    */
+#define KS_PH_DENSITY 7          /* stand-alone density (first evaluation)                */
+#define KS_NPHASES 8
+
+typedef struct ks_phase_times {
+  double ms[KS_NPHASES];        /* accumulated device time per phase, milliseconds       */
+  long long count[KS_NPHASES];  /* occurrences                                           */
+} ks_phase_times;
+
 typedef struct ks_system ks_system;
 
 /* ---- sizing and lifecycle -------------------------------------------------------------- */
@@ -192,7 +209,8 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
 
 /* Alg. 3 from X_inout (orthonormal columns expected) with BB steps (eq. (bb-1)) and the
  * nonmonotone Armijo search (eq. (NMLS-Armijo)); on return X_inout holds the last
- * accepted iterate and *r (host) the statistics.  o may be NULL for defaults.  Returns
+ * accepted iterate and *r (host) the statistics.  The first Hartree solve of a run
+ * starts from V_H = 0, so the result depends only on X_inout and the parameters.  o may be NULL for defaults.  Returns
  * KS_OK when the gradient or stagnation test stopped the run, KS_E_NOT_CONVERGED at
  * max_iter (r filled), or an error code. */
 int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* r);
@@ -221,6 +239,17 @@ int ks_get_potentials(ks_system* s, double* v_ext, double* v_h, double* v_eff);
 /* Gram blocks of two device n x ld blocks A, B: out (device, 3*p*p doubles, row-major
  * p x p each) = [A^T A, A^T B, B^T B].  The tall-skinny products of Section 3. */
 int ks_gram(ks_system* s, const void* A, const void* B, double* out);
+
+/* ---- instrumentation ------------------------------------------------------------------ */
+
+/* Turns the phase timers on (on != 0) or off.  While on, the library records a pair of
+ * HIP events on the system's stream around every phase of the timeline above and
+ * accumulates their elapsed times at the next synchronisation point.  Off by default;
+ * the timers add two event records per phase. */
+int ks_enable_timers(ks_system* s, int on);
+
+/* Copies the accumulated phase times into *out (host); reset != 0 clears them. */
+int ks_read_timers(ks_system* s, ks_phase_times* out, int reset);
 
 #ifdef __cplusplus
 }

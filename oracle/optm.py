@@ -108,8 +108,12 @@ def bb_step(k, ss, sy, yy, p: Params):
     return min(max(tau, p.tau_min), p.tau_max)
 
 
-def minimize(energy_grad: Callable, X0, params: Params = Params(), manifold=None, vh0=None):
-    """Run Alg. 3 from X0.  energy_grad(X, vh_warm) -> (Energy, E_X, vh)."""
+def minimize(energy_grad: Callable, X0, params: Params = Params(), manifold=None, vh0=None,
+             callback=None):
+    """Run Alg. 3 from X0.  energy_grad(X, vh_warm) -> (Energy, E_X, vh).
+
+    callback(k, E, gnorm), if given, is called after every accepted iteration.
+    """
     mf = manifold or EuclideanStiefel()
     p = params
     X = np.array(X0, dtype=np.float64)
@@ -163,6 +167,8 @@ def minimize(energy_grad: Callable, X0, params: Params = Params(), manifold=None
         g2 = mf.inner(D, D)
         k += 1
         dfs.append(df)
+        if callback is not None:
+            callback(k, E, math.sqrt(g2))
         if len(dfs) >= 3 and (dfs[-1] + dfs[-2] + dfs[-3]) / 3.0 < p.stagnation_tol:
             stop = "stagnation"
             break

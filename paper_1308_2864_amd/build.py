@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libks.so")
 
-SOURCES = ["ks_api.hip", "kernels_grid.hip", "kernels_dense.hip", "kernels_small.hip"]
+SOURCES = ["ks_api.hip", "kernels_grid.hip", "kernels_poisson.hip", "kernels_dense.hip",
+           "kernels_small.hip"]
 
 ARCH = os.environ.get("KS_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
@@ -49,7 +50,7 @@ def _compile(src, verbose):
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
-    with concurrent.futures.ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(5, len(SOURCES))) as ex:
         results = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     for _, warn in results:
         if warn and verbose:

@@ -187,161 +187,6 @@ __global__ void k_hx(const T* __restrict__ X, int ldx, T* __restrict__ Y, int ld
   }
 }
 
-// ---- Hartree: conjugate gradients on L v = 4 pi rho ---------------------------------
-// The scalars alpha, beta, r.r live in CgState.  Each reduction is finished by the last
-// block to arrive (fixed summation order over the per-block partials), so one CG
-// iteration is two launches.  Every kernel returns at once when the solve is done, so
-// the host can queue iterations ahead of the convergence check.
-
-__device__ inline double lap_at(const double* __restrict__ u, int g, int i, int j, int k,
-                                const Grid& gr) {
-  double nb = 0.0;
-  if (i > 0) nb += u[g - 1];
-  if (i < gr.nx - 1) nb += u[g + 1];
-  if (j > 0) nb += u[g - gr.nx];
-  if (j < gr.ny - 1) nb += u[g + gr.nx];
-  const int sz = gr.nx * gr.ny;
-  if (k > 0) nb += u[g - sz];
-  if (k < gr.nz - 1) nb += u[g + sz];
-  return (6.0 * u[g] - nb) * gr.inv_h2;
-}
-
-// Fixed-order sum of part[0..nb) by one block; result valid in thread 0.
-__device__ inline double last_block_sum(const double* part, int nb, double* sh) {
-  double v = 0.0;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) v += part[i];
-  return block_sum(v, sh);
-}
-
-// Returns true in every thread of the block that arrives last.
-__device__ inline bool arrive_last(unsigned int* count) {
-  __shared__ int last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned int prev = atomicAdd(count, 1u);
-    last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (last) __threadfence();
-  return last != 0;
-}
-
-__global__ void k_cg_init(const double* __restrict__ rho, const double* __restrict__ x0,
-                          double* __restrict__ x, double* __restrict__ r,
-                          double* __restrict__ p0, CgState* cs, double tol, int maxit, Grid gr,
-                          double* __restrict__ part) {
-  __shared__ double sh[kBlock / kWave];
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  size_t beg, end;
-  block_range((size_t)gr.n, lb, gridDim.x, &beg, &end);
-  double rr = 0.0, bb = 0.0;
-  for (size_t gg = beg + threadIdx.x; gg < end; gg += blockDim.x) {
-    const int g = (int)gg;
-    const int i = g % gr.nx, j = (g / gr.nx) % gr.ny, k = g / (gr.nx * gr.ny);
-    const double b = 4.0 * kPi * rho[g];
-    const double ri = x0 ? b - lap_at(x0, g, i, j, k, gr) : b;
-    x[g] = x0 ? x0[g] : 0.0;
-    r[g] = ri;
-    p0[g] = 0.0;
-    rr += ri * ri;
-    bb += b * b;
-  }
-  rr = block_sum(rr, sh);
-  bb = block_sum(bb, sh);
-  if (threadIdx.x == 0) {
-    part[lb] = rr;
-    part[gridDim.x + lb] = bb;
-  }
-  if (arrive_last(&cs->count)) {
-    const double trr = last_block_sum(part, gridDim.x, sh);
-    const double tbb = last_block_sum(part + gridDim.x, gridDim.x, sh);
-    if (threadIdx.x == 0) {
-      cs->rr = trr;
-      cs->bb = tbb;
-      cs->tol2 = tol * tol;
-      cs->beta = 0.0;
-      cs->alpha = 0.0;
-      cs->it = 0;
-      cs->maxit = maxit;
-      cs->done = (tbb == 0.0 || !isfinite(trr) || !isfinite(tbb) || trr <= tol * tol * tbb)
-                     ? 1 : 0;
-      cs->count = 0;
-    }
-  }
-}
-
-// pn = r + beta*po ; q = L pn ; partial pn.q ; last block: alpha = rr/pq
-__global__ void k_cg_dir(const double* __restrict__ r, const double* __restrict__ po,
-                         double* __restrict__ pn, double* __restrict__ q, CgState* cs, Grid gr,
-                         double* __restrict__ part) {
-  __shared__ double sh[kBlock / kWave];
-  if (cs->done) return;
-  const double beta = cs->beta;
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  size_t beg, end;
-  block_range((size_t)gr.n, lb, gridDim.x, &beg, &end);
-  const int sz = gr.nx * gr.ny;
-  double pq = 0.0;
-  for (size_t gg = beg + threadIdx.x; gg < end; gg += blockDim.x) {
-    const int g = (int)gg;
-    const int i = g % gr.nx, j = (g / gr.nx) % gr.ny, k = g / sz;
-    const double pc = r[g] + beta * po[g];
-    double nb = 0.0;
-    if (i > 0) nb += r[g - 1] + beta * po[g - 1];
-    if (i < gr.nx - 1) nb += r[g + 1] + beta * po[g + 1];
-    if (j > 0) nb += r[g - gr.nx] + beta * po[g - gr.nx];
-    if (j < gr.ny - 1) nb += r[g + gr.nx] + beta * po[g + gr.nx];
-    if (k > 0) nb += r[g - sz] + beta * po[g - sz];
-    if (k < gr.nz - 1) nb += r[g + sz] + beta * po[g + sz];
-    const double qq = (6.0 * pc - nb) * gr.inv_h2;
-    pn[g] = pc;
-    q[g] = qq;
-    pq += pc * qq;
-  }
-  pq = block_sum(pq, sh);
-  if (threadIdx.x == 0) part[lb] = pq;
-  if (arrive_last(&cs->count)) {
-    const double t = last_block_sum(part, gridDim.x, sh);
-    if (threadIdx.x == 0) {
-      cs->pq = t;
-      cs->alpha = cs->rr / t;
-      cs->count = 0;
-    }
-  }
-}
-
-// x += alpha p ; r -= alpha q ; partial r.r ; last block: beta, convergence
-__global__ void k_cg_upd(double* __restrict__ x, double* __restrict__ r,
-                         const double* __restrict__ pn, const double* __restrict__ q,
-                         CgState* cs, Grid gr, double* __restrict__ part) {
-  __shared__ double sh[kBlock / kWave];
-  if (cs->done) return;
-  const double alpha = cs->alpha;
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  size_t beg, end;
-  block_range((size_t)gr.n, lb, gridDim.x, &beg, &end);
-  double rr = 0.0;
-  for (size_t g = beg + threadIdx.x; g < end; g += blockDim.x) {
-    x[g] += alpha * pn[g];
-    const double rn = r[g] - alpha * q[g];
-    r[g] = rn;
-    rr += rn * rn;
-  }
-  rr = block_sum(rr, sh);
-  if (threadIdx.x == 0) part[gridDim.x + lb] = rr;
-  if (arrive_last(&cs->count)) {
-    const double t = last_block_sum(part + gridDim.x, gridDim.x, sh);
-    if (threadIdx.x == 0) {
-      cs->beta = t / cs->rr;
-      cs->rr = t;
-      cs->it += 1;
-      cs->done = (!isfinite(t) || t <= cs->tol2 * cs->bb || cs->it >= cs->maxit) ? 1 : 0;
-      cs->count = 0;
-    }
-  }
-}
-
 // ---- fixed-order reduction of per-block partials: one block per slot ---------------
 
 struct NBlk {
@@ -427,24 +272,6 @@ template void launch_hx<float>(const float*, int, float*, int, const double*, co
                                Grid, int, double, Partials*, hipStream_t);
 
 int hx_blocks(size_t work) { return stream_blocks(work); }
-
-int cg_blocks(int n) {
-  int b = (n + kBlock - 1) / kBlock;
-  return b < 1024 ? (b < 1 ? 1 : b) : 1024;
-}
-
-void launch_cg_init(const double* rho, const double* x0, double* x, double* r, double* p0,
-                    CgState* cs, double tol, int maxit, Grid g, double* part, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_init, dim3(cg_blocks(g.n)), dim3(kBlock), 0, st, rho, x0, x, r, p0,
-                     cs, tol, maxit, g, part);
-}
-
-void launch_cg_iter(double* x, double* r, double* pa, double* pb, double* q, CgState* cs,
-                    Grid g, double* part, hipStream_t st) {
-  const int nb = cg_blocks(g.n);
-  hipLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(kBlock), 0, st, r, pa, pb, q, cs, g, part);
-  hipLaunchKernelGGL(k_cg_upd, dim3(nb), dim3(kBlock), 0, st, x, r, pb, q, cs, g, part);
-}
 
 void launch_reduce_scalars(const double* part, int stride, const int* nblk, int nslots,
                            double* out, hipStream_t st) {

@@ -31,7 +31,9 @@ struct ks_system {
   int hmaxit = 5000;
   // device buffers carved from the caller's workspace
   double *vext = nullptr, *rho = nullptr, *vh[2] = {}, *veff[2] = {};
-  double *cg_r = nullptr, *cg_pa = nullptr, *cg_pb = nullptr, *cg_q = nullptr;
+  double *cg_r = nullptr, *cg_pa = nullptr, *cg_pb = nullptr, *cg_q = nullptr, *cg_z = nullptr;
+  double *fdS[3] = {}, *fdL[3] = {};
+  int solver = KS_HARTREE_CG;
   double *Rd = nullptr, *Zd = nullptr, *enuc = nullptr, *tau_user = nullptr;
   double *X[2] = {}, *G[2] = {}, *D[2] = {};
   double *gxg[2] = {}, *gxd[2] = {}, *W = nullptr, *A = nullptr, *B = nullptr;
@@ -49,6 +51,17 @@ struct ks_system {
   std::string err;
   int last_cg_iters = 0;
   long long cg_total = 0;
+  // optional phase timers
+  struct Pending {
+    hipEvent_t a, b;
+    int ph;
+  };
+  bool timers = false;
+  std::vector<hipEvent_t> ev_free;
+  std::vector<Pending> ev_pend;
+  Pending ev_open[KS_NPHASES] = {};
+  double ph_ms[KS_NPHASES] = {};
+  long long ph_n[KS_NPHASES] = {};
 };
 
 namespace {
@@ -81,6 +94,12 @@ void layout(ks_system* s, char* base, size_t* total) {
   s->cg_pa = c.take<double>(n);
   s->cg_pb = c.take<double>(n);
   s->cg_q = c.take<double>(n);
+  s->cg_z = c.take<double>(n);
+  const int dims[3] = {s->grid.nx, s->grid.ny, s->grid.nz};
+  for (int a = 0; a < 3; ++a) {
+    s->fdS[a] = c.take<double>((size_t)dims[a] * dims[a]);
+    s->fdL[a] = c.take<double>((size_t)dims[a]);
+  }
   s->Rd = c.take<double>(3 * (size_t)(M > 0 ? M : 1));
   s->Zd = c.take<double>((size_t)(M > 0 ? M : 1));
   s->enuc = c.take<double>(1);
@@ -101,7 +120,7 @@ void layout(ks_system* s, char* base, size_t* total) {
   s->gram_nchunks = gram_chunks(s->n, s->pp);
   s->gram_part = c.take<double>((size_t)s->gram_nchunks * 3 * pp2);
   s->spart = c.take<double>((size_t)SL_COUNT * kPartStride);
-  s->cgpart = c.take<double>((size_t)2 * 1024);
+  s->cgpart = c.take<double>(hartree_part_doubles());
   s->cg = c.take<CgState>(1);
   s->ls = c.take<LsState>(1);
   s->status = c.take<int>(1);
@@ -119,8 +138,13 @@ int validate(const ks_system_desc* d, std::string* why) {
     *why = "only KS_PREC_FP64 is built into this library";
     return KS_E_UNSUPPORTED;
   }
-  if (d->hartree_solver != KS_HARTREE_CG) {
+  if (d->hartree_solver != KS_HARTREE_CG && d->hartree_solver != KS_HARTREE_PCG_FD) {
     *why = "unknown Hartree solver";
+    return KS_E_UNSUPPORTED;
+  }
+  if (d->hartree_solver == KS_HARTREE_PCG_FD &&
+      (d->nx > 128 || d->ny > 128 || d->nz > 128)) {
+    *why = "the fast-diagonalisation preconditioner needs every grid side <= 128";
     return KS_E_UNSUPPORTED;
   }
   if (d->nx < 1 || d->ny < 1 || d->nz < 1) { *why = "grid sizes must be >= 1"; return KS_E_INVAL; }
@@ -155,6 +179,7 @@ void init_dims(ks_system* s, const ks_system_desc* d) {
   s->use_x = (d->terms & KS_TERM_XC) ? 1 : 0;
   s->htol = d->hartree_tol > 0.0 ? d->hartree_tol : 1e-13;
   s->hmaxit = d->hartree_maxit > 0 ? d->hartree_maxit : 5000;
+  s->solver = d->hartree_solver;
   s->R.assign(d->R ? d->R : nullptr, d->R ? d->R + 3 * d->n_nuclei : nullptr);
   s->Z.assign(d->Z ? d->Z : nullptr, d->Z ? d->Z + d->n_nuclei : nullptr);
   s->grid.nx = d->nx;
@@ -191,11 +216,73 @@ LsState* host_ls(ks_system* s) {
 }
 int* host_int(ks_system* s) { return reinterpret_cast<int*>(static_cast<char*>(s->host) + 768); }
 
+void harvest(ks_system* s);
+
 template <typename T>
 int readback(ks_system* s, T* host, const T* dev) {
   hipError_t e = hipMemcpyAsync(host, dev, sizeof(T), hipMemcpyDeviceToHost, s->st);
   if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  if (e == hipSuccess && s->timers) harvest(s);
   return hip_check(s, e, "read-back");
+}
+
+// ---- phase timers -----------------------------------------------------------------------
+
+hipEvent_t take_event(ks_system* s) {
+  if (s->ev_free.empty()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  hipEvent_t e = s->ev_free.back();
+  s->ev_free.pop_back();
+  return e;
+}
+
+void tbeg(ks_system* s, int ph) {
+  if (!s->timers) return;
+  ks_system::Pending p{take_event(s), take_event(s), ph};
+  if (p.a) (void)hipEventRecord(p.a, s->st);
+  s->ev_open[ph] = p;
+}
+
+// (Re)records the end event of an open phase.
+void tmark(ks_system* s, int ph) {
+  if (!s->timers || !s->ev_open[ph].b) return;
+  (void)hipEventRecord(s->ev_open[ph].b, s->st);
+}
+
+// Closes an open phase whose end event has been recorded.
+void tcommit(ks_system* s, int ph) {
+  if (!s->timers) return;
+  ks_system::Pending p = s->ev_open[ph];
+  if (!p.a || !p.b) return;
+  s->ev_pend.push_back(p);
+  s->ev_open[ph] = ks_system::Pending{};
+}
+
+void tend(ks_system* s, int ph) {
+  tmark(s, ph);
+  tcommit(s, ph);
+}
+
+// Accumulates every finished pair (called after stream synchronisations).
+void harvest(ks_system* s) {
+  std::vector<ks_system::Pending> keep;
+  for (auto& p : s->ev_pend) {
+    if (hipEventQuery(p.b) != hipSuccess) {
+      keep.push_back(p);
+      continue;
+    }
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      s->ph_ms[p.ph] += ms;
+      s->ph_n[p.ph] += 1;
+    }
+    s->ev_free.push_back(p.a);
+    s->ev_free.push_back(p.b);
+  }
+  s->ev_pend.swap(keep);
 }
 
 // ---- Hartree solve ---------------------------------------------------------------------
@@ -203,27 +290,37 @@ int readback(ks_system* s, T* host, const T* dev) {
 // the host checks the device flag between chunks.
 int hartree(ks_system* s, const double* rho, const double* x0, double* x, int* iters,
             double* relres) {
-  launch_cg_init(rho, x0, x, s->cg_r, s->cg_pa, s->cg, s->htol, s->hmaxit, s->grid, s->cgpart,
-                 s->st);
+  tbeg(s, KS_PH_HARTREE);
+  const bool pcg = s->solver == KS_HARTREE_PCG_FD;
+  launch_hartree_init(rho, x0, x, s->cg_r, s->cg_pa, s->cg, s->htol, s->hmaxit, s->grid,
+                      s->cgpart, s->st);
+  FdOps fd{s->fdS[0], s->fdS[1], s->fdS[2], s->fdL[0], s->fdL[1], s->fdL[2]};
   double* pa = s->cg_pa;
   double* pb = s->cg_pb;
   int launched = 0;
-  // first chunk sized by the previous solve (warm starts need similar counts)
-  int chunk = s->last_cg_iters > 0 ? s->last_cg_iters + 2 : 32;
+  // first chunk sized by the previous solve (warm starts need similar counts); with the
+  // exact preconditioner one or two iterations suffice
+  int chunk = pcg ? 2 : (s->last_cg_iters > 0 ? s->last_cg_iters + 2 : 32);
   CgState* hc = host_cg(s);
   for (;;) {
     const int c = std::min(chunk, s->hmaxit - launched);
     for (int i = 0; i < c; ++i) {
-      launch_cg_iter(x, s->cg_r, pa, pb, s->cg_q, s->cg, s->grid, s->cgpart, s->st);
+      if (pcg) launch_fd_apply(s->cg_r, s->cg_z, fd, s->grid, s->cg, s->cgpart, s->st);
+      launch_hartree_iter(x, s->cg_r, s->cg_z, pa, pb, s->cg_q, s->cg, s->grid, s->cgpart,
+                          pcg ? 1 : 0, s->st);
       std::swap(pa, pb);
     }
     launched += c;
+    tmark(s, KS_PH_HARTREE);
     int rc = launch_check(s, "hartree");
     if (rc) return rc;
     rc = readback(s, hc, s->cg);
     if (rc) return rc;
-    if (hc->done || launched >= s->hmaxit) break;
-    chunk = 16;
+    if (hc->done || launched >= s->hmaxit) {
+      tcommit(s, KS_PH_HARTREE);
+      break;
+    }
+    chunk = pcg ? 2 : 16;
   }
   s->last_cg_iters = hc->it;
   s->cg_total += hc->it;
@@ -239,7 +336,11 @@ int hartree(ks_system* s, const double* rho, const double* x0, double* x, int* i
 int evaluate(ks_system* s, int idx, bool rho_ready, int bb_ref, int warm, bool want_gxd) {
   const double scale = s->f / s->grid.dV;
   const double* Xs = s->X[idx];
-  if (!rho_ready) launch_density<double>(Xs, s->p, s->n, s->p, scale, s->rho, s->st);
+  if (!rho_ready) {
+    tbeg(s, KS_PH_DENSITY);
+    launch_density<double>(Xs, s->p, s->n, s->p, scale, s->rho, s->st);
+    tend(s, KS_PH_DENSITY);
+  }
   int rc = launch_check(s, "density");
   if (rc) return rc;
   if (s->use_h) {
@@ -247,13 +348,21 @@ int evaluate(ks_system* s, int idx, bool rho_ready, int bb_ref, int warm, bool w
     if (rc) return rc;
   }
   Partials pt{s->spart, kPartStride};
+  tbeg(s, KS_PH_XC);
   launch_xc(s->rho, s->vh[idx], s->vext, s->veff[idx], s->grid, s->use_h, s->use_x,
             s->use_h ? s->cg : nullptr, pt, s->st);
+  tend(s, KS_PH_XC);
+  tbeg(s, KS_PH_HAMILTONIAN);
   launch_hx<double>(Xs, s->p, s->G[idx], s->p, s->veff[idx], s->vext, s->grid, s->p,
                     2.0 * s->f, &pt, s->st);
+  tend(s, KS_PH_HAMILTONIAN);
+  tbeg(s, KS_PH_GRAM);
   launch_gram(Xs, s->G[idx], s->p, s->n, s->p, 3, s->gram_part, s->gram_nchunks, s->st);
+  tend(s, KS_PH_GRAM);
+  tbeg(s, KS_PH_SMALL);
   launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, 3, s->p, s->gxg[idx], s->st);
   launch_grad_weights(s->gxg[idx], s->pp, s->W, s->st);
+  tend(s, KS_PH_SMALL);
   CombineArgs ca{};
   ca.X = Xs;
   ca.A = s->W;
@@ -265,11 +374,16 @@ int evaluate(ks_system* s, int idx, bool rho_ready, int bb_ref, int warm, bool w
   ca.ld = s->p;
   ca.n = s->n;
   ca.p = s->p;
+  tbeg(s, KS_PH_GRADIENT);
   launch_combine(ca, s->st);
+  tend(s, KS_PH_GRADIENT);
   if (want_gxd) {
+    tbeg(s, KS_PH_GRAM);
     launch_gram(Xs, s->D[idx], s->p, s->n, s->p, 3, s->gram_part, s->gram_nchunks, s->st);
+    tend(s, KS_PH_GRAM);
     launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, 3, s->p, s->gxd[idx], s->st);
   }
+  tbeg(s, KS_PH_SMALL);
   int nblk[kMaxScalarSlots] = {};
   const int hb = std::min((s->n * s->p + kBlock - 1) / kBlock, kPartStride);
   nblk[SL_KIN] = nblk[SL_EXT] = std::max(hb, 1);
@@ -278,6 +392,7 @@ int evaluate(ks_system* s, int idx, bool rho_ready, int bb_ref, int warm, bool w
   launch_reduce_scalars(s->spart, kPartStride, nblk, SL_COUNT, s->sums[idx], s->st);
   launch_finish_eval(s->sums[idx], s->gxg[idx], s->p, s->pp, s->f, s->grid.dV, s->enuc,
                      s->use_h ? s->cg : nullptr, s->ev[idx], s->st);
+  tend(s, KS_PH_SMALL);
   return launch_check(s, "evaluate");
 }
 
@@ -415,6 +530,8 @@ int ks_create_system(const ks_system_desc* d, void* dev_workspace, size_t ws_byt
     launch_fill(s->vh[i], 0.0, s->n, s->st);
     launch_copy_vec(s->veff[i], s->vext, s->n, s->st);
   }
+  const int dims[3] = {s->grid.nx, s->grid.ny, s->grid.nz};
+  for (int a = 0; a < 3; ++a) launch_fd_setup(s->fdS[a], s->fdL[a], dims[a], s->grid.h, s->st);
   launch_ls_reset(s->ls, s->st);
   // the CG arrival counter must start at zero
   launch_fill(reinterpret_cast<double*>(s->cg), 0.0, sizeof(CgState) / sizeof(double), s->st);
@@ -435,7 +552,42 @@ void ks_destroy_system(ks_system* s) {
     (void)hipStreamSynchronize(s->st);
     (void)hipHostFree(s->host);
   }
+  for (auto& p : s->ev_pend) {
+    s->ev_free.push_back(p.a);
+    s->ev_free.push_back(p.b);
+  }
+  for (auto& p : s->ev_open) {
+    if (p.a) s->ev_free.push_back(p.a);
+    if (p.b) s->ev_free.push_back(p.b);
+  }
+  for (hipEvent_t e : s->ev_free) (void)hipEventDestroy(e);
   delete s;
+}
+
+int ks_enable_timers(ks_system* s, int on) {
+  if (!s) return fail(s, KS_E_INVAL, "null system");
+  s->timers = on != 0;
+  return KS_OK;
+}
+
+int ks_read_timers(ks_system* s, ks_phase_times* out, int reset) {
+  if (!s) return fail(s, KS_E_INVAL, "null system");
+  int rc = hip_check(s, hipStreamSynchronize(s->st), "timer sync");
+  if (rc) return rc;
+  harvest(s);
+  if (out) {
+    for (int i = 0; i < KS_NPHASES; ++i) {
+      out->ms[i] = s->ph_ms[i];
+      out->count[i] = s->ph_n[i];
+    }
+  }
+  if (reset) {
+    for (int i = 0; i < KS_NPHASES; ++i) {
+      s->ph_ms[i] = 0.0;
+      s->ph_n[i] = 0;
+    }
+  }
+  return KS_OK;
 }
 
 int ks_density(ks_system* s, const void* X, double* rho) {
@@ -598,6 +750,8 @@ int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* 
   int rc = hip_check(s, hipMemcpyAsync(s->reorth_count, &hint[1], sizeof(int),
                                        hipMemcpyHostToDevice, s->st), "counter upload");
   if (rc) return rc;
+  // the first Hartree solve starts from V_H = 0, so a run depends only on X_inout
+  launch_fill(s->vh[c], 0.0, s->n, s->st);
   rc = evaluate(s, c, false, -1, c, qr);
   if (rc) return rc;
   launch_ls_init(s->ev[c], s->ls, lp, s->st);
@@ -616,6 +770,7 @@ int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* 
     ca.ld = s->p;
     ca.n = s->n;
     ca.p = s->p;
+    tbeg(s, KS_PH_SMALL);
     if (qr) {
       launch_qr_factor(s->gxd[c], s->p, s->pp, &s->ls->tau, s->A, s->B, s->work, &s->ls->error,
                        s->st);
@@ -625,10 +780,15 @@ int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* 
                        &s->ls->error, s->reorth_count, s->st);
       ca.Y = s->G[c];
     }
+    tend(s, KS_PH_SMALL);
+    tbeg(s, KS_PH_RETRACT);
     launch_combine(ca, s->st);
+    tend(s, KS_PH_RETRACT);
     rc = evaluate(s, t, true, c, c, qr);
     if (rc) return rc;
+    tbeg(s, KS_PH_SMALL);
     launch_ls_judge(s->ev[t], s->ls, lp, s->st);
+    tend(s, KS_PH_SMALL);
     rc = launch_check(s, "line search");
     if (rc) return rc;
     rc = readback(s, hl, s->ls);

@@ -34,6 +34,7 @@ struct CgState {
   double pq;       // p.Lp of the current iteration
   double alpha, beta;
   double tol2;     // squared relative tolerance
+  double rz;       // r.z of the preconditioned iteration
   int it;          // iterations done
   int maxit;
   int done;        // 1 once converged or at maxit
@@ -132,15 +133,25 @@ void launch_xc(const double* rho, const double* vh, const double* vext, double* 
 template <typename T>
 void launch_hx(const T* X, int ldx, T* Y, int ldy, const double* veff, const double* vext,
                Grid g, int p, double scale, Partials* pt, hipStream_t st);
-int cg_blocks(int n);
-void launch_cg_init(const double* rho, const double* x0, double* x, double* r, double* p0,
-                    CgState* cs, double tol, int maxit, Grid g, double* part,
-                    hipStream_t st);
-void launch_cg_iter(double* x, double* r, double* pa, double* pb, double* q, CgState* cs,
-                    Grid g, double* part, hipStream_t st);
 int scalar_blocks(int n);
 void launch_reduce_scalars(const double* part, int stride, const int* nblk, int nslots,
                            double* out, hipStream_t st);
+
+// Hartree solver (kernels_poisson.hip)
+struct FdOps {
+  const double *Sx, *Sy, *Sz;   // sine-transform matrices per axis
+  const double *lx, *ly, *lz;   // their eigenvalues of -d^2/dx^2 (already / h^2)
+};
+size_t hartree_part_doubles();
+void launch_fd_setup(double* S, double* lam, int N, double h, hipStream_t st);
+void launch_hartree_init(const double* rho, const double* x0, double* x, double* r, double* p0,
+                         CgState* cs, double tol, int maxit, Grid g, double* part,
+                         hipStream_t st);
+void launch_fd_apply(const double* r, double* z, const FdOps& fd, Grid g, const CgState* cs,
+                     double* part, hipStream_t st);
+void launch_hartree_iter(double* x, double* r, const double* z, double* pa, double* pb,
+                         double* q, CgState* cs, Grid g, double* part, int pcg,
+                         hipStream_t st);
 
 // dense kernels (kernels_dense.hip)
 int gram_chunks(int n, int pp);

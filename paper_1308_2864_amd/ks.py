@@ -33,6 +33,8 @@ KS_HARTREE_CG, KS_HARTREE_PCG_FD = 0, 1
 KS_QR, KS_WY = 0, 1
 KS_BB_ALT, KS_BB1, KS_BB2 = 0, 1, 2
 KS_STOP_NONE, KS_STOP_GRAD, KS_STOP_STAGNATION, KS_STOP_MAXIT, KS_STOP_ERROR = 0, 1, 2, 3, 4
+PHASES = ["hartree", "xc", "hamiltonian", "gram", "gradient", "retract", "small", "density"]
+KS_NPHASES = len(PHASES)
 STOP_NAMES = {0: "none", 1: "grad", 2: "stagnation", 3: "maxit", 4: "error"}
 
 
@@ -77,6 +79,13 @@ class ks_result(C.Structure):
     ]
 
 
+class ks_phase_times(C.Structure):
+    _fields_ = [("ms", C.c_double * 8), ("count", C.c_longlong * 8)]
+
+    def as_dict(self):
+        return {name: (self.ms[i], self.count[i]) for i, name in enumerate(PHASES)}
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
@@ -97,6 +106,8 @@ def _load():
         "ks_apply_hamiltonian": (ip, [vp, vp, vp, vp]),
         "ks_get_potentials": (ip, [vp, vp, vp, vp]),
         "ks_gram": (ip, [vp, vp, vp, vp]),
+        "ks_enable_timers": (ip, [vp, ip]),
+        "ks_read_timers": (ip, [vp, C.POINTER(ks_phase_times), ip]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -234,6 +245,14 @@ class KSSystem:
 
     def ks_gram(self, A, B, out):
         _check(lib.ks_gram(self.h, _ptr(A), _ptr(B), _ptr(out)), self.h)
+
+    def ks_enable_timers(self, on=True):
+        _check(lib.ks_enable_timers(self.h, int(bool(on))), self.h)
+
+    def ks_read_timers(self, reset=False) -> dict:
+        t = ks_phase_times()
+        _check(lib.ks_read_timers(self.h, C.byref(t), int(bool(reset))), self.h)
+        return t.as_dict()
 
 
 def system_from_spec(spec, **kw) -> KSSystem:

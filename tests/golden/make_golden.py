@@ -4,7 +4,9 @@ Every value here is either a closed form of the discretised problem or the outpu
 of the FP64 oracle (``oracle/``); nothing comes from the GPU path.
 
     python tests/golden/make_golden.py box          # closed forms (seconds)
-    python tests/golden/make_golden.py c1           # oracle minimisation of c1 (minutes)
+    python tests/golden/make_golden.py c1 0 qr 1e-7        # oracle minimisation of c1
+    python tests/golden/make_golden.py c2 0 qr 1e-6 1e-13  # c2 with the Section 4.1 stops
+    python tests/golden/make_golden.py gap c1              # spectral gap at the c1 minimiser
 """
 import math
 import os
@@ -31,7 +33,7 @@ def box():
         fh.write(f"E_box = {repr(float(lam[:4].sum()))}\n")
 
 
-def oracle_run(cfg, seed=0, kind="qr", eps_g=1e-8):
+def oracle_run(cfg, seed=0, kind="qr", eps_g=1e-8, stagnation_tol=0.0):
     from oracle import optm
     from oracle.ks import KSSystemFD
     from paper_1308_2864_amd import synth
@@ -41,26 +43,65 @@ def oracle_run(cfg, seed=0, kind="qr", eps_g=1e-8):
                       f=spec.f, rc=spec.rc)
     X0 = synth.make_x0(spec, seed)
     t = time.time()
+    def progress(k, E, g):
+        if k % 100 == 0:
+            print(f"  k={k} E={E:.12f} |grad|={g:.3e} t={time.time() - t:.0f}s", flush=True)
+
     res = optm.minimize(sysk.energy_grad, X0, optm.Params(retraction=kind, eps_g=eps_g,
-                                                          stagnation_tol=0.0, max_iter=20000))
+                                                          stagnation_tol=stagnation_tol,
+                                                          max_iter=20000),
+                        callback=progress)
     el = time.time() - t
     fn = os.path.join(HERE, f"oracle_{cfg}_s{seed}_{kind}.txt")
     with open(fn, "w") as fh:
         fh.write(f"# FP64 oracle, Alg. 3 with the {kind.upper()} retraction, config {cfg} seed {seed},\n")
-        fh.write(f"# eps_g = {eps_g}, stagnation test off; {res.iters} iterations, {el:.0f} s.\n")
-        fh.write(f"E = {repr(res.E)}\n")
-        fh.write(f"gnorm = {repr(res.gnorm)}\n")
+        fh.write(f"# eps_g = {eps_g}, stagnation tol = {stagnation_tol}; stopped by {res.stop} "
+                 f"after {res.iters} iterations, {el:.0f} s.\n")
+        fh.write(f"E = {repr(float(res.E))}\n")
+        fh.write(f"gnorm = {repr(float(res.gnorm))}\n")
         fh.write(f"iters = {res.iters}\n")
         for nm in ("kinetic", "external", "hartree", "xc", "nuclear"):
             fh.write(f"{nm} = {repr(float(getattr(res.energy, nm)))}\n")
-    np.save(os.path.join(HERE, f"oracle_{cfg}_s{seed}_{kind}_X.npy"), res.X) if cfg == "c1" else None
+    if cfg == "c1":
+        np.save(os.path.join(HERE, f"oracle_{cfg}_s{seed}_{kind}_X.npy"), res.X)
+        with open(fn, "a") as fh:
+            fh.write(f"gap = {repr(spectral_gap(sysk, res.X))}\n")
     print(fn, res.E, res.gnorm, res.iters, res.stop, el)
+
+
+def spectral_gap(sysk, X):
+    """lambda_{p+1} - lambda_p of H(rho(X)) (Lanczos, scipy eigsh), the Davis-Kahan gap."""
+    import scipy.sparse.linalg as spla
+    veff = sysk.effective_potential(X)
+    op = spla.LinearOperator((sysk.n, sysk.n), dtype=float,
+                             matvec=lambda v: sysk.hamiltonian_apply(v.reshape(-1, 1), veff).ravel())
+    w = np.sort(spla.eigsh(op, k=X.shape[1] + 3, which="SA", tol=1e-12)[0])
+    p = X.shape[1]
+    return float(w[p] - w[p - 1])
+
+
+def add_gap(cfg, seed=0, kind="qr"):
+    """Appends the spectral gap at a stored c1 minimiser to its reference file."""
+    from oracle.ks import KSSystemFD
+    from paper_1308_2864_amd import synth
+    spec = synth.make_config(cfg, seed)
+    sysk = KSSystemFD(spec.nx, spec.ny, spec.nz, spec.h, spec.lo, spec.p, spec.R, spec.Z,
+                      f=spec.f, rc=spec.rc)
+    X = np.load(os.path.join(HERE, f"oracle_{cfg}_s{seed}_{kind}_X.npy"))
+    fn = os.path.join(HERE, f"oracle_{cfg}_s{seed}_{kind}.txt")
+    lines = [l for l in open(fn) if not l.startswith("gap")]
+    lines.append(f"gap = {repr(spectral_gap(sysk, X))}\n")
+    open(fn, "w").writelines(lines)
 
 
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "box"
     if what == "box":
         box()
+    elif what == "gap":
+        add_gap(sys.argv[2])
     else:
         oracle_run(what, int(sys.argv[2]) if len(sys.argv) > 2 else 0,
-                   sys.argv[3] if len(sys.argv) > 3 else "qr")
+                   sys.argv[3] if len(sys.argv) > 3 else "qr",
+                   float(sys.argv[4]) if len(sys.argv) > 4 else 1e-8,
+                   float(sys.argv[5]) if len(sys.argv) > 5 else 0.0)
