@@ -18,6 +18,8 @@
 // matrices are padded to pp = round_up(p, 16).  All sums use a fixed order (per-lane,
 // then fixed-order cross-wave and cross-block reductions), so results are bitwise
 // reproducible run to run.
+#include <algorithm>
+
 #include "ks_common.h"
 
 namespace ks {
@@ -31,36 +33,65 @@ __device__ inline d4 mfma16(double a, double b, d4 c) {
 }
 
 constexpr int kGramMaxChunks = 512;
+constexpr int kGradMaxBlocks = 512;
+
+// Product bits of a Gram launch: A^T A, A^T B, B^T B.  Symmetric products store only the
+// tiles ti <= tj; the reduction mirrors them.
+constexpr int kPAA = 1, kPAB = 2, kPBB = 4;
+
+template <int kT, int kMask>
+struct GramTiles {
+  static constexpr int kSym = kT * (kT + 1) / 2;
+  static constexpr int kAll = kT * kT;
+  static constexpr int kN = ((kMask & kPAA) ? kSym : 0) + ((kMask & kPAB) ? kAll : 0) +
+                            ((kMask & kPBB) ? kSym : 0);
+};
+
+// Fixed-order sum of one 16x16 tile over the four waves of a block: waves 1..3 park it in
+// LDS (6 KiB) and wave 0 adds them in wave order.
+__device__ inline void wave_reduce_tile(d4& v, double* lds, int w, int lane) {
+  if (w > 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) lds[((w - 1) * 4 + r) * 64 + lane] = v[r];
+  }
+  __syncthreads();
+  if (w == 0) {
+#pragma unroll
+    for (int ww = 0; ww < 3; ++ww)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[r] += lds[(ww * 4 + r) * 64 + lane];
+  }
+  __syncthreads();
+}
+
+// Writes the tile (ti, tj) of product prod of this block's partial (wave 0 only).
+template <int kPP>
+__device__ inline void put_tile(double* part, int blk, int prod, int ti, int tj, const d4& v,
+                                int lr, int lc) {
+  double* o = part + ((size_t)blk * 3 + prod) * kPP * kPP;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) o[(ti * 16 + lr + 4 * r) * kPP + tj * 16 + lc] = v[r];
+}
 
 // ---- Gram: per-chunk partials -------------------------------------------------------
-// grid.x = chunks of rows; grid.y = product index when kAll3 == false.
-// kT = pp / 16 tiles per dimension.  Symmetric products (A^T A, B^T B) compute only the
-// tiles ti <= tj; the reduction mirrors them.
-template <int kT, bool kAll3>
+template <int kT, int kMask>
 __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ A,
                                               const double* __restrict__ B, int ld, int n,
-                                              int p, int nprod, double* __restrict__ part) {
+                                              int p, double* __restrict__ part) {
   constexpr int kPP = kT * 16;
-  constexpr int kTilesSym = kT * (kT + 1) / 2;
-  constexpr int kTilesAll = kT * kT;
-  // tiles held per wave
-  constexpr int kAcc = kAll3 ? (2 * kTilesSym + kTilesAll) : kTilesAll;
+  constexpr int kAcc = GramTiles<kT, kMask>::kN;
   extern __shared__ double lds[];
-
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int lr = lane / 16, lc = lane % 16;
   const int chunk = blockIdx.x, nchunks = gridDim.x;
-  const int prod_y = (nprod == 1) ? 1 : (int)blockIdx.y;  // product when !kAll3
-  // row range of this chunk, in groups of 4 rows
   const int ngroups = (n + 3) / 4;
   const int per = (ngroups + nchunks - 1) / nchunks;
-  const int g_beg = chunk * per;
-  const int g_end = min(ngroups, g_beg + per);
+  const int g_beg = chunk * per, g_end = min(ngroups, g_beg + per);
 
   d4 acc[kAcc];
 #pragma unroll
   for (int t = 0; t < kAcc; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
 
-  const int lr = lane / 16, lc = lane % 16;
   for (int grp = g_beg + w; grp < g_end; grp += 4) {
     const int row = grp * 4 + lr;
     const bool rok = row < n;
@@ -70,117 +101,105 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ A,
       const int col = t * 16 + lc;
       const bool ok = rok && col < p;
       fa[t] = ok ? A[(size_t)row * ld + col] : 0.0;
-      fb[t] = ok ? B[(size_t)row * ld + col] : 0.0;
+      fb[t] = ((kMask & (kPAB | kPBB)) && ok) ? B[(size_t)row * ld + col] : 0.0;
     }
-    if (kAll3) {
-      int a = 0;
-      // A^T A (upper tiles)
+    int a = 0;
+    if (kMask & kPAA) {
 #pragma unroll
       for (int ti = 0; ti < kT; ++ti)
 #pragma unroll
         for (int tj = ti; tj < kT; ++tj, ++a) acc[a] = mfma16(fa[ti], fa[tj], acc[a]);
-      // A^T B (all tiles)
+    }
+    if (kMask & kPAB) {
 #pragma unroll
       for (int ti = 0; ti < kT; ++ti)
 #pragma unroll
         for (int tj = 0; tj < kT; ++tj, ++a) acc[a] = mfma16(fa[ti], fb[tj], acc[a]);
-      // B^T B (upper tiles)
+    }
+    if (kMask & kPBB) {
 #pragma unroll
       for (int ti = 0; ti < kT; ++ti)
 #pragma unroll
         for (int tj = ti; tj < kT; ++tj, ++a) acc[a] = mfma16(fb[ti], fb[tj], acc[a]);
-    } else {
-      int a = 0;
-#pragma unroll
-      for (int ti = 0; ti < kT; ++ti)
-#pragma unroll
-        for (int tj = 0; tj < kT; ++tj) {
-          const double x = (prod_y == 2) ? fb[ti] : fa[ti];
-          const double y = (prod_y == 0) ? fa[tj] : fb[tj];
-          acc[a] = mfma16(x, y, acc[a]);
-          ++a;
-        }
     }
   }
-
-  // fixed-order sum over the four waves, one tile at a time: waves 1..3 park the tile
-  // in LDS and wave 0 adds them in wave order
 #pragma unroll
-  for (int t = 0; t < kAcc; ++t) {
-    if (w > 0) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) lds[((w - 1) * 4 + r) * 64 + lane] = acc[t][r];
-    }
-    __syncthreads();
-    if (w == 0) {
-#pragma unroll
-      for (int ww = 0; ww < 3; ++ww)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[t][r] += lds[(ww * 4 + r) * 64 + lane];
-    }
-    __syncthreads();
-  }
+  for (int t = 0; t < kAcc; ++t) wave_reduce_tile(acc[t], lds, w, lane);
   if (w == 0) {
-    // write this chunk's partial tiles: part[chunk][prod][pp][pp]
-    double* out = part + (size_t)chunk * 3 * kPP * kPP;
-    auto put = [&](int prod, int ti, int tj, const d4& v) {
-      double* o = out + (size_t)prod * kPP * kPP;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = ti * 16 + lr + 4 * r, j = tj * 16 + lc;
-        o[i * kPP + j] = v[r];
-      }
-    };
     int a = 0;
-    if (kAll3) {
+    if (kMask & kPAA) {
 #pragma unroll
       for (int ti = 0; ti < kT; ++ti)
 #pragma unroll
-        for (int tj = ti; tj < kT; ++tj) put(0, ti, tj, acc[a++]);
+        for (int tj = ti; tj < kT; ++tj) put_tile<kPP>(part, chunk, 0, ti, tj, acc[a++], lr, lc);
+    }
+    if (kMask & kPAB) {
 #pragma unroll
       for (int ti = 0; ti < kT; ++ti)
 #pragma unroll
-        for (int tj = 0; tj < kT; ++tj) put(1, ti, tj, acc[a++]);
+        for (int tj = 0; tj < kT; ++tj) put_tile<kPP>(part, chunk, 1, ti, tj, acc[a++], lr, lc);
+    }
+    if (kMask & kPBB) {
 #pragma unroll
       for (int ti = 0; ti < kT; ++ti)
 #pragma unroll
-        for (int tj = ti; tj < kT; ++tj) put(2, ti, tj, acc[a++]);
-    } else {
-#pragma unroll
-      for (int ti = 0; ti < kT; ++ti)
-#pragma unroll
-        for (int tj = 0; tj < kT; ++tj) put(prod_y, ti, tj, acc[a++]);
+        for (int tj = ti; tj < kT; ++tj) put_tile<kPP>(part, chunk, 2, ti, tj, acc[a++], lr, lc);
     }
   }
 }
 
-// out[prod][i][j] = sum over chunks, fixed order; symmetric products are mirrored from
-// their upper tiles.  Entries with i >= p or j >= p are zero (the loads were masked).
-__global__ void k_gram_reduce(const double* __restrict__ part, int nchunks, int pp, int nprod,
-                              int sym_only_upper, double* __restrict__ out) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+// out[prod][i][j] = sum over chunks in increasing order, for the products in mask; the
+// other products are zero.  Block = 16 output slots x 16 chunk lanes; chunk lane c sums
+// chunks c, c+16, ... and the 16 lane sums are added in lane order.  Symmetric products
+// read the mirrored upper tile.  With W != nullptr also W = -(product 1)^T.
+__global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ part,
+                                                     int nchunks, int pp, int mask,
+                                                     double* __restrict__ out,
+                                                     double* __restrict__ W) {
+  __shared__ double red[16][17];
+  const int sl = threadIdx.x % 16, cl = threadIdx.x / 16;
   const int per = pp * pp;
-  if (e >= 3 * per) return;
-  const int prod = e / per, ij = e % per, i = ij / pp, j = ij % pp;
-  if (nprod == 1 && prod != 1) {
-    out[e] = 0.0;
-    return;
-  }
-  int src = ij;
-  if (prod != 1 && sym_only_upper && (i / 16) > (j / 16)) src = j * pp + i;
+  const int e = blockIdx.x * 16 + sl;
   double s = 0.0;
-  for (int c = 0; c < nchunks; ++c) s += part[(size_t)c * 3 * per + (size_t)prod * per + src];
-  out[e] = s;
+  int prod = 0, i = 0, j = 0;
+  bool live = false;
+  if (e < 3 * per) {
+    prod = e / per;
+    const int ij = e % per;
+    i = ij / pp;
+    j = ij % pp;
+    live = (mask >> prod) & 1;
+    if (live) {
+      const int src = (prod != 1 && (i / 16) > (j / 16)) ? j * pp + i : ij;
+      const double* q = part + (size_t)prod * per + src;
+      for (int c = cl; c < nchunks; c += 16) s += q[(size_t)c * 3 * per];
+    }
+  }
+  red[sl][cl] = s;
+  __syncthreads();
+  if (cl == 0 && e < 3 * per) {
+    double t = 0.0;
+    for (int c = 0; c < 16; ++c) t += red[sl][c];
+    t = live ? t : 0.0;
+    out[e] = t;
+    if (W && prod == 1) W[j * pp + i] = -t;
+  }
 }
 
 // ---- combine ------------------------------------------------------------------------
 // out[g][:] = C0[g][:] + X[g][:] A + Y[g][:] B  (A, B: pp x pp, staged in LDS).
-// Each wavefront owns a 16-row tile and all column tiles of it.
-template <int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad>
+// Each wavefront owns a 16-row tile and all column tiles of it.  Epilogues:
+//   kRho   density of out,
+//   kGrad  out is D = grad E; Frobenius sums ||D||^2 and the BB sums against (Xk, Dk),
+//          and, with kGram2, the Gram tiles X^T D and D^T D: an FP64 MFMA result tile of
+//          a 4-row group (register r) is laid out exactly as an MFMA input fragment, so
+//          D goes from the accumulators straight back into the matrix cores.
+template <int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad, bool kGram2>
 __global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
   constexpr int kPP = kT * 16;
   constexpr int kK = kHasY ? 2 * kPP : kPP;  // contraction length
-  extern __shared__ double lds[];            // W = [A; B] : kK x kPP
+  constexpr int kG2 = kGram2 ? (kT * kT + kT * (kT + 1) / 2) : 1;
+  extern __shared__ double lds[];            // W = [A; B] : kK x kPP (+ 6 KiB reduction)
   __shared__ double sh[kBlock / kWave];
 
   for (int e = threadIdx.x; e < kPP * kPP; e += blockDim.x) {
@@ -197,6 +216,9 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
   const int t_beg = lb * per, t_end = min(ntiles, t_beg + per);
   const int ld = a.ld, p = a.p;
   double dd = 0.0, ss = 0.0, sy = 0.0, yy = 0.0;
+  d4 g2[kG2];
+#pragma unroll
+  for (int t = 0; t < kG2; ++t) g2[t] = d4{0.0, 0.0, 0.0, 0.0};
 
   for (int tile = t_beg + w; tile < t_end; tile += 4) {
     const int g0 = tile * 16;
@@ -232,9 +254,11 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = g0 + lr + 4 * r;
-        if (row < a.n && col < p) {
+        const bool ok = row < a.n && col < p;
+        double v = 0.0;
+        if (ok) {
           const size_t off = (size_t)row * ld + col;
-          double v = acc[t][r];
+          v = acc[t][r];
           if (kHasC0) v += a.C0[off];
           a.out[off] = v;
           if (kRho) sq[r] += v * v;
@@ -247,6 +271,28 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
             yy += y * y;
           }
         }
+        acc[t][r] = v;  // masked D, reused as an MFMA fragment below
+      }
+    }
+    if (kGram2) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = g0 + 4 * r + lr;
+        double fx[kT];
+#pragma unroll
+        for (int t = 0; t < kT; ++t) {
+          const int col = t * 16 + lc;
+          fx[t] = (row < a.n && col < p) ? a.X[(size_t)row * ld + col] : 0.0;
+        }
+        int q = 0;
+#pragma unroll
+        for (int ti = 0; ti < kT; ++ti)
+#pragma unroll
+          for (int tj = 0; tj < kT; ++tj, ++q) g2[q] = mfma16(fx[ti], acc[tj][r], g2[q]);
+#pragma unroll
+        for (int ti = 0; ti < kT; ++ti)
+#pragma unroll
+          for (int tj = ti; tj < kT; ++tj, ++q) g2[q] = mfma16(acc[ti][r], acc[tj][r], g2[q]);
       }
     }
     if (kRho) {
@@ -275,54 +321,82 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
       a.pt.buf[(size_t)SL_YY * st + lb] = yy;
     }
   }
-}
-
-template <int kT>
-void launch_gram_t(const double* A, const double* B, int ld, int n, int p, int nprod,
-                   double* partials, int nchunks, hipStream_t st) {
-  constexpr int kTilesSym = kT * (kT + 1) / 2, kTilesAll = kT * kT;
-  (void)kTilesSym;
-  (void)kTilesAll;
-  const size_t lds = (size_t)3 * 4 * 64 * sizeof(double);
-  if constexpr (kT <= 2) {
-    if (nprod == 3) {
-      hipLaunchKernelGGL((k_gram<kT, true>), dim3(nchunks), dim3(256), lds, st, A, B, ld, n, p,
-                         nprod, partials);
-      return;
+  if (kGram2) {
+    double* red = lds + kK * kPP;
+#pragma unroll
+    for (int t = 0; t < kG2; ++t) wave_reduce_tile(g2[t], red, w, lane);
+    if (w == 0) {
+      int q = 0;
+#pragma unroll
+      for (int ti = 0; ti < kT; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < kT; ++tj) put_tile<kPP>(a.gram_part, lb, 1, ti, tj, g2[q++], lr, lc);
+#pragma unroll
+      for (int ti = 0; ti < kT; ++ti)
+#pragma unroll
+        for (int tj = ti; tj < kT; ++tj) put_tile<kPP>(a.gram_part, lb, 2, ti, tj, g2[q++], lr, lc);
     }
   }
-  hipLaunchKernelGGL((k_gram<kT, false>), dim3(nchunks, nprod == 1 ? 1 : 3), dim3(256), lds, st,
-                     A, B, ld, n, p, nprod, partials);
 }
 
-template <int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad>
+void set_lds_attr(const void* k, size_t bytes) {
+  if (bytes > 32768)
+    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <int kT, int kMask>
+void launch_gram_m(const double* A, const double* B, int ld, int n, int p, double* part,
+                   int nchunks, hipStream_t st) {
+  const size_t lds = (size_t)3 * 4 * 64 * sizeof(double);
+  hipLaunchKernelGGL((k_gram<kT, kMask>), dim3(nchunks), dim3(256), lds, st, A, B, ld, n, p,
+                     part);
+}
+
+// Up to 32 columns all requested products run in one pass; wider blocks run one product
+// per pass to bound the accumulator registers.
+template <int kT>
+void launch_gram_t(const double* A, const double* B, int ld, int n, int p, int mask,
+                   double* part, int nchunks, hipStream_t st) {
+  if constexpr (kT <= 2) {
+    if (mask == (kPAA | kPAB | kPBB)) return launch_gram_m<kT, 7>(A, B, ld, n, p, part, nchunks, st);
+    if (mask == (kPAA | kPAB)) return launch_gram_m<kT, 3>(A, B, ld, n, p, part, nchunks, st);
+  }
+  if (mask & kPAA) launch_gram_m<kT, 1>(A, B, ld, n, p, part, nchunks, st);
+  if (mask & kPAB) launch_gram_m<kT, 2>(A, B, ld, n, p, part, nchunks, st);
+  if (mask & kPBB) launch_gram_m<kT, 4>(A, B, ld, n, p, part, nchunks, st);
+}
+
+template <int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad, bool kGram2>
 void launch_combine_t(const CombineArgs& a, hipStream_t st) {
   constexpr int kPP = kT * 16;
-  const size_t lds = (size_t)(kHasY ? 2 : 1) * kPP * kPP * sizeof(double);
+  const size_t lds = (size_t)(kHasY ? 2 : 1) * kPP * kPP * sizeof(double) +
+                     (kGram2 ? (size_t)3 * 4 * 64 * sizeof(double) : 0);
   static bool attr = false;
-  if (!attr && lds > 32768) {
-    (void)hipFuncSetAttribute(
-        reinterpret_cast<const void*>(k_combine<kT, kHasY, kHasC0, kRho, kGrad>),
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (!attr) {
+    set_lds_attr(reinterpret_cast<const void*>(k_combine<kT, kHasY, kHasC0, kRho, kGrad, kGram2>),
+                 lds);
     attr = true;
   }
-  hipLaunchKernelGGL((k_combine<kT, kHasY, kHasC0, kRho, kGrad>), dim3(combine_blocks(a.n)),
-                     dim3(256), lds, st, a);
+  const int nb = kGram2 ? combine_blocks_gram(a.n) : combine_blocks(a.n);
+  hipLaunchKernelGGL((k_combine<kT, kHasY, kHasC0, kRho, kGrad, kGram2>), dim3(nb), dim3(256),
+                     lds, st, a);
 }
 
 template <int kT>
 void launch_combine_tt(const CombineArgs& a, hipStream_t st) {
   const bool y = a.Y != nullptr, c0 = a.C0 != nullptr, rho = a.rho != nullptr,
-             gr = a.Xk != nullptr;
+             gr = a.Xk != nullptr, g2 = a.gram_part != nullptr;
   // the combinations the library uses
-  if (y && !c0 && rho && !gr) return launch_combine_t<kT, true, false, true, false>(a, st);
-  if (y && !c0 && !rho && !gr) return launch_combine_t<kT, true, false, false, false>(a, st);
-  if (!y && c0 && !rho && gr) return launch_combine_t<kT, false, true, false, true>(a, st);
-  if (!y && c0 && !rho && !gr) return launch_combine_t<kT, false, true, false, false>(a, st);
-  if (!y && !c0 && rho && !gr) return launch_combine_t<kT, false, false, true, false>(a, st);
-  if (!y && !c0 && !rho && !gr) return launch_combine_t<kT, false, false, false, false>(a, st);
-  // unreachable for the library's call sites
-  launch_combine_t<kT, true, true, true, true>(a, st);
+  if (y && !c0 && rho && !gr) return launch_combine_t<kT, true, false, true, false, false>(a, st);
+  if (y && !c0 && !rho && !gr) return launch_combine_t<kT, true, false, false, false, false>(a, st);
+  if constexpr (kT <= 2) {
+    if (!y && c0 && !rho && gr && g2)
+      return launch_combine_t<kT, false, true, false, true, true>(a, st);
+  }
+  if (!y && c0 && !rho && gr) return launch_combine_t<kT, false, true, false, true, false>(a, st);
+  if (!y && c0 && !rho && !gr) return launch_combine_t<kT, false, true, false, false, false>(a, st);
+  if (!y && !c0 && rho && !gr) return launch_combine_t<kT, false, false, true, false, false>(a, st);
+  launch_combine_t<kT, false, false, false, false, false>(a, st);
 }
 
 }  // namespace
@@ -334,27 +408,30 @@ int gram_chunks(int n, int pp) {
   return c < 1 ? 1 : c;
 }
 
-void launch_gram(const double* A, const double* B, int ld, int n, int p, int nprod,
+size_t gram_part_doubles(int n, int pp) {
+  const int c = std::max(gram_chunks(n, pp), combine_blocks_gram(n));
+  return (size_t)c * 3 * pp * pp;
+}
+
+bool combine_fuses_gram(int p) { return round_up(p, 16) <= 32; }
+
+void launch_gram(const double* A, const double* B, int ld, int n, int p, int mask,
                  double* partials, int nchunks, hipStream_t st) {
   const int pp = round_up(p, 16);
   switch (pp / 16) {
-    case 1: launch_gram_t<1>(A, B, ld, n, p, nprod, partials, nchunks, st); break;
-    case 2: launch_gram_t<2>(A, B, ld, n, p, nprod, partials, nchunks, st); break;
-    case 3: launch_gram_t<3>(A, B, ld, n, p, nprod, partials, nchunks, st); break;
-    case 4: launch_gram_t<4>(A, B, ld, n, p, nprod, partials, nchunks, st); break;
+    case 1: launch_gram_t<1>(A, B, ld, n, p, mask, partials, nchunks, st); break;
+    case 2: launch_gram_t<2>(A, B, ld, n, p, mask, partials, nchunks, st); break;
+    case 3: launch_gram_t<3>(A, B, ld, n, p, mask, partials, nchunks, st); break;
+    case 4: launch_gram_t<4>(A, B, ld, n, p, mask, partials, nchunks, st); break;
     default: break;
   }
 }
 
-void launch_gram_reduce(const double* partials, int nchunks, int pp, int nprod, int p,
-                        double* out, hipStream_t st) {
-  (void)p;
+void launch_gram_reduce(const double* partials, int nchunks, int pp, int mask, double* out,
+                        double* W, hipStream_t st) {
   const int total = 3 * pp * pp;
-  // the all-in-one kernel (pp <= 32, three products) stores only upper tiles of the
-  // symmetric products; the per-product kernel stores every tile
-  const int upper = (pp <= 32 && nprod == 3) ? 1 : 0;
-  hipLaunchKernelGGL(k_gram_reduce, dim3((total + 255) / 256), dim3(256), 0, st, partials,
-                     nchunks, pp, nprod, upper, out);
+  hipLaunchKernelGGL(k_gram_reduce, dim3((total + 15) / 16), dim3(256), 0, st, partials, nchunks,
+                     pp, mask, out, W);
 }
 
 int combine_blocks(int n) {
@@ -362,6 +439,11 @@ int combine_blocks(int n) {
   int b = (tiles + 3) / 4;
   if (b > 4096) b = 4096;
   return b < 1 ? 1 : b;
+}
+
+int combine_blocks_gram(int n) {
+  int b = combine_blocks(n);
+  return b > kGradMaxBlocks ? kGradMaxBlocks : b;
 }
 
 void launch_combine(const CombineArgs& a, hipStream_t st) {

@@ -21,8 +21,6 @@
 
 namespace ks {
 
-int fd_rz_blocks(Grid g);
-
 namespace {
 
 constexpr int kCgBlocksMax = 1024;
@@ -209,79 +207,164 @@ __global__ void k_fd_setup(double* __restrict__ S, double* __restrict__ lam, int
   if (e < N) lam[e] = (2.0 - 2.0 * cos(kPi * (double)(e + 1) / (double)(N + 1))) / (h * h);
 }
 
-struct FdArgs {
-  const double* in;
-  double* out;
-  const double* S;     // N x N
-  int N;               // transform length
-  int stride;          // element stride along the axis
-  int inner;           // number of lines adjacent in memory (= stride for y, z)
-  int nouter;          // outer line index count
-  // optional eigenvalue scaling (forward z transform): out *= 1/(lx[i]+ly[j]+lz[k])
-  const double* lx; const double* ly; const double* lz; int nx;
-  // optional partial r.z with the final output (slot 3)
-  const double* r; double* part;
-  int skip_if_done;
-  const CgState* cs;
-};
+// The sine-transform contractions run on the FP64 matrix cores (v_mfma_f64_16x16x4f64):
+//   A fragment: lane l holds A[l % 16][l / 16];  B fragment: lane l holds B[l / 16][l % 16];
+//   result:     lane l, register r holds D[(l / 16) + 4 r][l % 16].
+// Transform lengths are padded to multiples of 16 with zero rows/columns of S.  Because S
+// is symmetric, S[j][m] = S[m][j], so every fragment of S is read along a row (coalesced).
+typedef double d4 __attribute__((ext_vector_type(4)));
 
-// Transform along an axis whose lines are adjacent in memory (y: stride nx, z: stride
-// nx*ny).  Block = 64 adjacent lines x all N points, staged in LDS; wave w produces the
-// outputs w, w+4, ... of every line.
-__global__ __launch_bounds__(256) void k_fd_strided(FdArgs a) {
-  extern __shared__ double tile[];  // N x 64
-  __shared__ double sh[kBlock / kWave];
-  if (a.skip_if_done && a.cs->done) return;
+__device__ inline d4 mma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ inline double sget(const double* S, int N, int row, int col) {
+  return (row < N && col < N) ? S[row * N + col] : 0.0;
+}
+
+constexpr int kFdWaves = 8;     // waves per block of the transform kernels
+constexpr int kFdTiles = 8;     // result tiles a wave can hold (covers 128 x 128)
+
+// 2-D transform of one z-plane (block = plane k): Y = S_y P S_x with P the ny x nx plane
+// (row = y).  Step 1 T = P S_x (results held in registers), step 2 Y = S_y T.  The plane
+// lives in LDS (row stride nxp + 1 doubles: conflict-free column reads).  With part the
+// partial r.Y of the plane goes to slot 3.
+__global__ __launch_bounds__(512) void k_fd_plane(const double* __restrict__ in,
+                                                  double* __restrict__ out,
+                                                  const double* __restrict__ Sx,
+                                                  const double* __restrict__ Sy, int nx, int ny,
+                                                  const double* __restrict__ r,
+                                                  double* __restrict__ part,
+                                                  const CgState* cs) {
+  extern __shared__ double P[];
+  __shared__ double sh[512 / kWave];
+  if (cs->done) return;
+  const int k = blockIdx.x;
+  const int nxp = (nx + 15) & ~15, nyp = (ny + 15) & ~15, sp = nxp + 1;
+  const size_t base = (size_t)k * nx * ny;
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-  const int l0 = blockIdx.x * 64, outer = blockIdx.y;
-  const int line = l0 + lane;
-  const bool ok = line < a.inner;
-  const size_t base = (size_t)outer * a.N * a.stride + line;
-  for (int m = w; m < a.N; m += 4) tile[m * 64 + lane] = ok ? a.in[base + (size_t)m * a.stride] : 0.0;
+  const int lr = lane / 16, lc = lane % 16;
+  for (int e = threadIdx.x; e < nyp * nxp; e += blockDim.x) {
+    const int j = e / nxp, m = e % nxp;
+    P[j * sp + m] = (j < ny && m < nx) ? in[base + (size_t)j * nx + m] : 0.0;
+  }
   __syncthreads();
-  double rz = 0.0;
-  for (int j = w; j < a.N; j += 4) {
-    const double* Sj = a.S + (size_t)j * a.N;
-    double acc = 0.0;
-    for (int m = 0; m < a.N; ++m) acc += Sj[m] * tile[m * 64 + lane];
-    if (ok) {
-      const size_t o = base + (size_t)j * a.stride;
-      if (a.lx) {
-        // forward z transform: (i, jy) from the line index, k = j
-        const int i = line % a.nx, jy = line / a.nx;
-        acc /= (a.lx[i] + a.ly[jy] + a.lz[j]);
-      }
-      a.out[o] = acc;
-      if (a.part) rz += acc * a.r[o];
+  const int tx = nxp / 16, ntile = (nyp / 16) * tx;
+  d4 acc[kFdTiles];
+  // step 1: T[j][i] = sum_m P[j][m] S_x[m][i]
+#pragma unroll
+  for (int s = 0; s < kFdTiles; ++s) {
+    acc[s] = d4{0.0, 0.0, 0.0, 0.0};
+    const int t = w + s * kFdWaves;
+    if (t < ntile) {
+      const int j0 = (t / tx) * 16, i0 = (t % tx) * 16;
+      for (int k0 = 0; k0 < nxp; k0 += 4)
+        acc[s] = mma(P[(j0 + lc) * sp + k0 + lr], sget(Sx, nx, k0 + lr, i0 + lc), acc[s]);
     }
   }
-  if (a.part) {
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < kFdTiles; ++s) {
+    const int t = w + s * kFdWaves;
+    if (t < ntile) {
+      const int j0 = (t / tx) * 16, i0 = (t % tx) * 16;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) P[(j0 + lr + 4 * q) * sp + i0 + lc] = acc[s][q];
+    }
+  }
+  __syncthreads();
+  // step 2: Y[j][i] = sum_m S_y[j][m] T[m][i]
+  double rz = 0.0;
+#pragma unroll
+  for (int s = 0; s < kFdTiles; ++s) {
+    const int t = w + s * kFdWaves;
+    if (t < ntile) {
+      const int j0 = (t / tx) * 16, i0 = (t % tx) * 16;
+      d4 y = d4{0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < nyp; k0 += 4)
+        y = mma(sget(Sy, ny, k0 + lr, j0 + lc), P[(k0 + lr) * sp + i0 + lc], y);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = j0 + lr + 4 * q, i = i0 + lc;
+        if (j < ny && i < nx) {
+          const size_t o = base + (size_t)j * nx + i;
+          out[o] = y[q];
+          if (part) rz += y[q] * r[o];
+        }
+      }
+    }
+  }
+  if (part) {
     rz = block_sum(rz, sh);
-    if (threadIdx.x == 0) a.part[3 * kCgBlocksMax + blockIdx.y * gridDim.x + blockIdx.x] = rz;
+    if (threadIdx.x == 0) part[3 * kCgBlocksMax + k] = rz;
   }
 }
 
-// Transform along x (lines contiguous).  Block = 64 lines, loaded coalesced and
-// transposed into LDS; every block reads all points of its own lines before writing
-// them, so the transform may run in place.
-__global__ __launch_bounds__(256) void k_fd_x(FdArgs a) {
-  extern __shared__ double tile[];  // N x 65 (padded against bank conflicts)
-  if (a.skip_if_done && a.cs->done) return;
-  const int N = a.N;
+// z lines (block = 64 adjacent (i, j) columns x nz): forward transform, division by
+// lx[i] + ly[j] + lz[k], inverse transform (S_z is its own inverse), in place.
+__global__ __launch_bounds__(512) void k_fd_z(double* __restrict__ u,
+                                              const double* __restrict__ Sz,
+                                              const double* __restrict__ lx,
+                                              const double* __restrict__ ly,
+                                              const double* __restrict__ lz, int nx, int ny,
+                                              int nz, const CgState* cs) {
+  extern __shared__ double A[];  // nzp x 64
+  if (cs->done) return;
+  const int npl = nx * ny;
+  const int nzp = (nz + 15) & ~15;
   const int l0 = blockIdx.x * 64;
-  const int nl = min(64, a.nouter - l0);
-  const size_t gbase = (size_t)l0 * N;
-  for (int e = threadIdx.x; e < 64 * N; e += blockDim.x) {
-    const int l = e / N, m = e % N;
-    tile[m * 65 + l] = (l < nl) ? a.in[gbase + e] : 0.0;
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int lr = lane / 16, lc = lane % 16;
+  for (int e = threadIdx.x; e < nzp * 64; e += blockDim.x) {
+    const int m = e / 64, l = e % 64;
+    A[e] = (m < nz && l0 + l < npl) ? u[(size_t)m * npl + l0 + l] : 0.0;
   }
   __syncthreads();
-  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-  for (int i = w; i < N; i += 4) {
-    const double* Si = a.S + (size_t)i * N;
-    double acc = 0.0;
-    for (int m = 0; m < N; ++m) acc += Si[m] * tile[m * 65 + lane];
-    if (lane < nl) a.out[gbase + (size_t)lane * N + i] = acc;
+  const int ntile = (nzp / 16) * 4;
+  d4 acc[kFdTiles];
+#pragma unroll
+  for (int s = 0; s < kFdTiles; ++s) {
+    acc[s] = d4{0.0, 0.0, 0.0, 0.0};
+    const int t = w + s * kFdWaves;
+    if (t < ntile) {
+      const int k0t = (t / 4) * 16, c0 = (t % 4) * 16;
+      for (int k0 = 0; k0 < nzp; k0 += 4)
+        acc[s] = mma(sget(Sz, nz, k0 + lr, k0t + lc), A[(k0 + lr) * 64 + c0 + lc], acc[s]);
+      // divide by the eigenvalue of L at (i, j, k)
+      const int line = l0 + c0 + lc;
+      const double lij = (line < npl) ? lx[line % nx] + ly[line / nx] : 1.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int kk = k0t + lr + 4 * q;
+        acc[s][q] = (kk < nz) ? acc[s][q] / (lij + lz[kk]) : 0.0;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < kFdTiles; ++s) {
+    const int t = w + s * kFdWaves;
+    if (t < ntile) {
+      const int k0t = (t / 4) * 16, c0 = (t % 4) * 16;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) A[(k0t + lr + 4 * q) * 64 + c0 + lc] = acc[s][q];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < kFdTiles; ++s) {
+    const int t = w + s * kFdWaves;
+    if (t < ntile) {
+      const int k0t = (t / 4) * 16, c0 = (t % 4) * 16;
+      d4 y = d4{0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < nzp; k0 += 4)
+        y = mma(sget(Sz, nz, k0 + lr, k0t + lc), A[(k0 + lr) * 64 + c0 + lc], y);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int kk = k0t + lr + 4 * q, line = l0 + c0 + lc;
+        if (kk < nz && line < npl) u[(size_t)kk * npl + line] = y[q];
+      }
+    }
   }
 }
 
@@ -289,7 +372,6 @@ __global__ __launch_bounds__(256) void k_fd_x(FdArgs a) {
 
 size_t hartree_part_doubles() { return (size_t)4 * kCgBlocksMax; }
 
-size_t fd_lds_bytes_max(int N) { return (size_t)N * 65 * sizeof(double); }
 
 void launch_fd_setup(double* S, double* lam, int N, double h, hipStream_t st) {
   hipLaunchKernelGGL(k_fd_setup, dim3((N * N + 255) / 256), dim3(256), 0, st, S, lam, N, h);
@@ -310,48 +392,34 @@ void set_lds(const void* k, size_t bytes) {
 }
 }  // namespace
 
-// z = L^{-1} r by the fast diagonalisation, with the partial r.z of the result; the
-// transforms after the first run in place on z.
+// LDS the preconditioner needs for an nx x ny x nz grid.
+size_t fd_lds_bytes(int nx, int ny, int nz) {
+  const size_t nxp = (nx + 15) & ~15, nyp = (ny + 15) & ~15, nzp = (nz + 15) & ~15;
+  return std::max(nyp * (nxp + 1), nzp * 64) * sizeof(double);
+}
+
+// Largest plane the register tiles of k_fd_plane cover (kFdWaves * kFdTiles tiles).
+int fd_max_plane() { return kFdWaves * kFdTiles * 256; }
+
+// z = L^{-1} r by the fast diagonalisation (plane transform, z pass with the eigenvalue
+// division, inverse plane transform with the partial r.z), then beta from r.z.
 void launch_fd_apply(const double* r, double* z, const FdOps& fd, Grid g, const CgState* cs,
                      double* part, hipStream_t st) {
   const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const size_t lx = (size_t)nx * 65 * sizeof(double);
-  const size_t ly = (size_t)ny * 64 * sizeof(double);
-  const size_t lz = (size_t)nz * 64 * sizeof(double);
-  set_lds(reinterpret_cast<const void*>(k_fd_x), lx);
-  set_lds(reinterpret_cast<const void*>(k_fd_strided), std::max(ly, lz));
-  auto xform_x = [&](const double* in) {
-    FdArgs a{};
-    a.skip_if_done = 1; a.cs = cs; a.nx = nx;
-    a.in = in; a.out = z; a.S = fd.Sx; a.N = nx; a.nouter = ny * nz;
-    hipLaunchKernelGGL(k_fd_x, dim3((ny * nz + 63) / 64), dim3(256), lx, st, a);
-  };
-  auto xform_y = [&](bool rz) {
-    FdArgs a{};
-    a.skip_if_done = 1; a.cs = cs; a.nx = nx;
-    a.in = z; a.out = z; a.S = fd.Sy; a.N = ny; a.stride = nx; a.inner = nx; a.nouter = nz;
-    if (rz) { a.r = r; a.part = part; }
-    hipLaunchKernelGGL(k_fd_strided, dim3((nx + 63) / 64, nz), dim3(256), ly, st, a);
-  };
-  auto xform_z = [&](bool scale) {
-    FdArgs a{};
-    a.skip_if_done = 1; a.cs = cs; a.nx = nx;
-    a.in = z; a.out = z; a.S = fd.Sz; a.N = nz; a.stride = nx * ny; a.inner = nx * ny;
-    a.nouter = 1;
-    if (scale) { a.lx = fd.lx; a.ly = fd.ly; a.lz = fd.lz; }
-    hipLaunchKernelGGL(k_fd_strided, dim3((nx * ny + 63) / 64, 1), dim3(256), lz, st, a);
-  };
-  xform_x(r);       // forward, r -> z
-  xform_y(false);
-  xform_z(true);    // with 1/(lx + ly + lz)
-  xform_z(false);   // inverse (S is symmetric and orthogonal)
-  xform_x(z);
-  xform_y(true);    // with the partial r.z
-  hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kBlock), 0, st, part, fd_rz_blocks(g),
-                     const_cast<CgState*>(cs));
+  const size_t nxp = (nx + 15) & ~15, nyp = (ny + 15) & ~15, nzp = (nz + 15) & ~15;
+  const size_t lp = nyp * (nxp + 1) * sizeof(double);
+  const size_t lzb = nzp * 64 * sizeof(double);
+  set_lds(reinterpret_cast<const void*>(k_fd_plane), lp);
+  set_lds(reinterpret_cast<const void*>(k_fd_z), lzb);
+  const int threads = kFdWaves * kWave;
+  hipLaunchKernelGGL(k_fd_plane, dim3(nz), dim3(threads), lp, st, r, z, fd.Sx, fd.Sy, nx, ny,
+                     nullptr, nullptr, cs);
+  hipLaunchKernelGGL(k_fd_z, dim3((nx * ny + 63) / 64), dim3(threads), lzb, st, z, fd.Sz, fd.lx,
+                     fd.ly, fd.lz, nx, ny, nz, cs);
+  hipLaunchKernelGGL(k_fd_plane, dim3(nz), dim3(threads), lp, st, z, z, fd.Sx, fd.Sy, nx, ny, r,
+                     part, cs);
+  hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kBlock), 0, st, part, nz, const_cast<CgState*>(cs));
 }
-
-int fd_rz_blocks(Grid g) { return ((g.nx + 63) / 64) * g.nz; }
 
 void launch_hartree_iter(double* x, double* r, const double* z, double* pa, double* pb,
                          double* q, CgState* cs, Grid g, double* part, int pcg,

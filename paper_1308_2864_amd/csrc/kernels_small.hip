@@ -173,16 +173,16 @@ __device__ inline double* work_base(double* glob) {
 }
 
 // ---- QR retraction weights -----------------------------------------------------------
-// gram: [X^T X, X^T D, D^T D] (pp x pp each).
-__global__ void k_qr_factor(const double* __restrict__ gram, int p, int pp,
-                            const double* __restrict__ tau_p, double* __restrict__ A,
+// xx: X^T X; gxd: [., X^T D, D^T D] (pp x pp blocks).
+__global__ void k_qr_factor(const double* __restrict__ xx, const double* __restrict__ gxd, int p,
+                            int pp, const double* __restrict__ tau_p, double* __restrict__ A,
                             double* __restrict__ B, double* glob, int* status) {
   double* M = work_base(glob);
   double* W = M + p * p;
   const double tau = *tau_p;
-  const double* XX = gram;
-  const double* XD = gram + pp * pp;
-  const double* DD = gram + 2 * pp * pp;
+  const double* XX = xx;
+  const double* XD = gxd + pp * pp;
+  const double* DD = gxd + 2 * pp * pp;
   for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
     const int i = e / p, j = e % p;
     M[e] = XX[i * pp + j] - tau * (XD[i * pp + j] + XD[j * pp + i]) + tau * tau * DD[i * pp + j];
@@ -195,6 +195,77 @@ __global__ void k_qr_factor(const double* __restrict__ gram, int p, int pp,
   blk_upper_inverse(M, p, W, p, p);
   blk_store_padded(A, pp, W, p, p, 1.0);
   blk_store_padded(B, pp, W, p, p, -tau);
+}
+
+// Single-wavefront variant for p <= P (P = 16, 32, 64): lane j owns column j of
+// Y^T Y (padded with the identity beyond p) in registers.  The Cholesky factor and its
+// inverse are formed with cross-lane broadcasts (readlane), no LDS and no barriers.
+__device__ inline double bcast(double v, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffu), lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+template <int P>
+__global__ __launch_bounds__(64) void k_qr_factor_wave(const double* __restrict__ xx,
+                                                       const double* __restrict__ gxd, int p,
+                                                       int pp, const double* __restrict__ tau_p,
+                                                       double* __restrict__ A,
+                                                       double* __restrict__ B, int* status) {
+  const int j = threadIdx.x;  // column owned by this lane
+  const double tau = *tau_p;
+  const double* XD = gxd + pp * pp;
+  const double* DD = gxd + 2 * pp * pp;
+  double a[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    double v = (i == j) ? 1.0 : 0.0;
+    if (i < p && j < p)
+      v = xx[i * pp + j] - tau * (XD[i * pp + j] + XD[j * pp + i]) + tau * tau * DD[i * pp + j];
+    a[i] = v;
+  }
+  // right-looking upper Cholesky: afterwards a[i] (lane j) = R[i][j] for i <= j
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    const double d = bcast(a[k], k);
+    if (!(d > 0.0) || !isfinite(d)) bad = true;
+    const double rkk = sqrt(d);
+    const double rk = (j == k) ? rkk : a[k] / rkk;  // R[k][j] for j >= k
+    a[k] = (j >= k) ? rk : 0.0;
+#pragma unroll
+    for (int i = k + 1; i < P; ++i) {
+      const double rki = bcast(rk, i);  // R[k][i]
+      if (j >= i) a[i] -= rki * rk;
+    }
+  }
+  if (bad) {
+    if (j == 0) *status = KS_E_NOT_SPD;
+    return;
+  }
+  // W = R^{-1}: W[i][j] = (delta_ij - sum_{m > i} R[i][m] W[m][j]) / R[i][i], i = P-1..0
+  double w[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) w[i] = 0.0;
+#pragma unroll
+  for (int i = P - 1; i >= 0; --i) {
+    double acc = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+    for (int m = i + 1; m < P; ++m) acc -= bcast(a[i], m) * w[m];  // R[i][m] from lane m
+    const double rii = bcast(a[i], i);
+    w[i] = (i <= j) ? acc / rii : 0.0;
+  }
+  if (j < pp) {
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      if (i < pp) {
+        const double v = (i < p && j < p) ? w[i] : 0.0;
+        A[i * pp + j] = v;
+        B[i * pp + j] = -tau * v;
+      }
+    }
+  }
 }
 
 // ---- Cayley / SMW retraction weights -------------------------------------------------
@@ -385,8 +456,16 @@ __global__ void k_ls_init(const EvalOut* ev, LsState* ls, LsParams prm) {
   *ls = s;
 }
 
-__global__ void k_ls_judge(const EvalOut* ev, LsState* ls, LsParams prm) {
+__global__ void k_ls_judge(const EvalOut* ev, LsState* ls, LsParams prm, const CgState* cg) {
   LsState s = *ls;
+  if (cg && !cg->done) {
+    // the Hartree potential of this trial is not converged yet: the host finishes the
+    // solve, re-evaluates the trial and calls the judge again
+    s.hartree_pending = 1;
+    *ls = s;
+    return;
+  }
+  s.hartree_pending = 0;
   s.nfe += 1;
   if (s.error != 0) {
     s.stop = KS_STOP_ERROR;
@@ -477,11 +556,26 @@ void launch_grad_weights(const double* gram, int pp, double* W, hipStream_t st) 
   hipLaunchKernelGGL(k_grad_weights, dim3((pp * pp + 255) / 256), dim3(256), 0, st, gram, pp, W);
 }
 
-void launch_qr_factor(const double* gram_xd, int p, int pp, const double* tau, double* A,
-                      double* B, double* work, int* status, hipStream_t st) {
+void launch_qr_factor(const double* xx, const double* gxd, int p, int pp, const double* tau,
+                      double* A, double* B, double* work, int* status, hipStream_t st) {
+  if (p <= 16) {
+    hipLaunchKernelGGL(k_qr_factor_wave<16>, dim3(1), dim3(64), 0, st, xx, gxd, p, pp, tau, A,
+                       B, status);
+    return;
+  }
+  if (p <= 32) {
+    hipLaunchKernelGGL(k_qr_factor_wave<32>, dim3(1), dim3(64), 0, st, xx, gxd, p, pp, tau, A,
+                       B, status);
+    return;
+  }
+  if (p <= 64) {
+    hipLaunchKernelGGL(k_qr_factor_wave<64>, dim3(1), dim3(64), 0, st, xx, gxd, p, pp, tau, A,
+                       B, status);
+    return;
+  }
   const size_t bytes = (size_t)2 * p * p * sizeof(double);
   const bool lds = prepare_lds(k_qr_factor, bytes);
-  hipLaunchKernelGGL(k_qr_factor, dim3(1), dim3(kBlock), lds ? bytes : 0, st, gram_xd, p, pp,
+  hipLaunchKernelGGL(k_qr_factor, dim3(1), dim3(kBlock), lds ? bytes : 0, st, xx, gxd, p, pp,
                      tau, A, B, lds ? nullptr : work, status);
 }
 
@@ -509,8 +603,9 @@ void launch_ls_init(const EvalOut* ev, LsState* ls, LsParams prm, hipStream_t st
   hipLaunchKernelGGL(k_ls_init, dim3(1), dim3(1), 0, st, ev, ls, prm);
 }
 
-void launch_ls_judge(const EvalOut* ev, LsState* ls, LsParams prm, hipStream_t st) {
-  hipLaunchKernelGGL(k_ls_judge, dim3(1), dim3(1), 0, st, ev, ls, prm);
+void launch_ls_judge(const EvalOut* ev, LsState* ls, LsParams prm, const CgState* cg,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_ls_judge, dim3(1), dim3(1), 0, st, ev, ls, prm, cg);
 }
 
 }  // namespace ks

@@ -31,7 +31,8 @@ struct ks_system {
   int hmaxit = 5000;
   // device buffers carved from the caller's workspace
   double *vext = nullptr, *rho = nullptr, *vh[2] = {}, *veff[2] = {};
-  double *cg_r = nullptr, *cg_pa = nullptr, *cg_pb = nullptr, *cg_q = nullptr, *cg_z = nullptr;
+  double *cg_r = nullptr, *cg_p[2] = {}, *cg_q = nullptr, *cg_z = nullptr;
+  int cg_par = 0;
   double *fdS[3] = {}, *fdL[3] = {};
   int solver = KS_HARTREE_CG;
   double *Rd = nullptr, *Zd = nullptr, *enuc = nullptr, *tau_user = nullptr;
@@ -91,8 +92,8 @@ void layout(ks_system* s, char* base, size_t* total) {
     s->veff[i] = c.take<double>(n);
   }
   s->cg_r = c.take<double>(n);
-  s->cg_pa = c.take<double>(n);
-  s->cg_pb = c.take<double>(n);
+  s->cg_p[0] = c.take<double>(n);
+  s->cg_p[1] = c.take<double>(n);
   s->cg_q = c.take<double>(n);
   s->cg_z = c.take<double>(n);
   const int dims[3] = {s->grid.nx, s->grid.ny, s->grid.nz};
@@ -118,7 +119,7 @@ void layout(ks_system* s, char* base, size_t* total) {
   s->B = c.take<double>(pp2);
   s->work = c.take<double>(small_work_doubles(s->p));
   s->gram_nchunks = gram_chunks(s->n, s->pp);
-  s->gram_part = c.take<double>((size_t)s->gram_nchunks * 3 * pp2);
+  s->gram_part = c.take<double>(gram_part_doubles(s->n, s->pp));
   s->spart = c.take<double>((size_t)SL_COUNT * kPartStride);
   s->cgpart = c.take<double>(hartree_part_doubles());
   s->cg = c.take<CgState>(1);
@@ -143,8 +144,9 @@ int validate(const ks_system_desc* d, std::string* why) {
     return KS_E_UNSUPPORTED;
   }
   if (d->hartree_solver == KS_HARTREE_PCG_FD &&
-      (d->nx > 128 || d->ny > 128 || d->nz > 128)) {
-    *why = "the fast-diagonalisation preconditioner needs every grid side <= 128";
+      (((d->nx + 15) / 16) * ((d->ny + 15) / 16) * 256 > fd_max_plane() || d->nz > 128)) {
+    *why = "the fast-diagonalisation preconditioner needs ceil16(nx) * ceil16(ny) <= 16384 "
+           "and nz <= 128";
     return KS_E_UNSUPPORTED;
   }
   if (d->nx < 1 || d->ny < 1 || d->nz < 1) { *why = "grid sizes must be >= 1"; return KS_E_INVAL; }
@@ -218,6 +220,16 @@ int* host_int(ks_system* s) { return reinterpret_cast<int*>(static_cast<char*>(s
 
 void harvest(ks_system* s);
 
+// Two records with one synchronisation.
+template <typename T, typename U>
+int readback2(ks_system* s, T* h1, const T* d1, U* h2, const U* d2) {
+  hipError_t e = hipMemcpyAsync(h1, d1, sizeof(T), hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipMemcpyAsync(h2, d2, sizeof(U), hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  if (e == hipSuccess && s->timers) harvest(s);
+  return hip_check(s, e, "read-back");
+}
+
 template <typename T>
 int readback(ks_system* s, T* host, const T* dev) {
   hipError_t e = hipMemcpyAsync(host, dev, sizeof(T), hipMemcpyDeviceToHost, s->st);
@@ -288,32 +300,32 @@ void harvest(ks_system* s) {
 // ---- Hartree solve ---------------------------------------------------------------------
 // CG iterations are queued in chunks; each kernel exits at once after convergence, and
 // the host checks the device flag between chunks.
-int hartree(ks_system* s, const double* rho, const double* x0, double* x, int* iters,
-            double* relres) {
-  tbeg(s, KS_PH_HARTREE);
+// Queues Hartree iterations on the current CG state until the device flag says done
+// (checked between chunks).  With wait == false a PCG solve only queues its usual two
+// iterations; whoever reads the CG state later must check the flag.
+int hartree_iterate(ks_system* s, double* x, int first_chunk, bool wait, int* iters,
+                    double* relres) {
   const bool pcg = s->solver == KS_HARTREE_PCG_FD;
-  launch_hartree_init(rho, x0, x, s->cg_r, s->cg_pa, s->cg, s->htol, s->hmaxit, s->grid,
-                      s->cgpart, s->st);
   FdOps fd{s->fdS[0], s->fdS[1], s->fdS[2], s->fdL[0], s->fdL[1], s->fdL[2]};
-  double* pa = s->cg_pa;
-  double* pb = s->cg_pb;
   int launched = 0;
-  // first chunk sized by the previous solve (warm starts need similar counts); with the
-  // exact preconditioner one or two iterations suffice
-  int chunk = pcg ? 2 : (s->last_cg_iters > 0 ? s->last_cg_iters + 2 : 32);
+  int chunk = first_chunk;
   CgState* hc = host_cg(s);
   for (;;) {
     const int c = std::min(chunk, s->hmaxit - launched);
     for (int i = 0; i < c; ++i) {
       if (pcg) launch_fd_apply(s->cg_r, s->cg_z, fd, s->grid, s->cg, s->cgpart, s->st);
-      launch_hartree_iter(x, s->cg_r, s->cg_z, pa, pb, s->cg_q, s->cg, s->grid, s->cgpart,
-                          pcg ? 1 : 0, s->st);
-      std::swap(pa, pb);
+      launch_hartree_iter(x, s->cg_r, s->cg_z, s->cg_p[s->cg_par], s->cg_p[1 - s->cg_par],
+                          s->cg_q, s->cg, s->grid, s->cgpart, pcg ? 1 : 0, s->st);
+      s->cg_par = 1 - s->cg_par;
     }
     launched += c;
     tmark(s, KS_PH_HARTREE);
     int rc = launch_check(s, "hartree");
     if (rc) return rc;
+    if (!wait) {
+      tcommit(s, KS_PH_HARTREE);
+      return KS_OK;
+    }
     rc = readback(s, hc, s->cg);
     if (rc) return rc;
     if (hc->done || launched >= s->hmaxit) {
@@ -329,11 +341,27 @@ int hartree(ks_system* s, const double* rho, const double* x0, double* x, int* i
   return KS_OK;
 }
 
+int hartree(ks_system* s, const double* rho, const double* x0, double* x, bool wait,
+            int* iters, double* relres) {
+  tbeg(s, KS_PH_HARTREE);
+  const bool pcg = s->solver == KS_HARTREE_PCG_FD;
+  s->cg_par = 0;
+  launch_hartree_init(rho, x0, x, s->cg_r, s->cg_p[0], s->cg, s->htol, s->hmaxit, s->grid,
+                      s->cgpart, s->st);
+  // first chunk sized by the previous solve (warm starts need similar counts); with the
+  // exact preconditioner one or two iterations suffice
+  const int chunk = pcg ? 2 : (s->last_cg_iters > 0 ? s->last_cg_iters + 2 : 32);
+  return hartree_iterate(s, x, chunk, wait, iters, relres);
+}
+
 // ---- one energy/gradient evaluation on internal slot `idx` -------------------------
 // rho of X[idx] is either ready (fused into the retraction) or computed here.  With
 // bb_ref >= 0 the gradient epilogue also forms the BB sums against slot bb_ref.
 // warm: slot whose V_H starts the CG.  Writes G, D, gram blocks, sums, ev of the slot.
-int evaluate(ks_system* s, int idx, bool rho_ready, int bb_ref, int warm, bool want_gxd) {
+int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg);
+
+int evaluate(ks_system* s, int idx, bool rho_ready, int bb_ref, int warm, bool want_gxd,
+             bool want_gg, bool wait_hartree = true) {
   const double scale = s->f / s->grid.dV;
   const double* Xs = s->X[idx];
   if (!rho_ready) {
@@ -344,9 +372,16 @@ int evaluate(ks_system* s, int idx, bool rho_ready, int bb_ref, int warm, bool w
   int rc = launch_check(s, "density");
   if (rc) return rc;
   if (s->use_h) {
-    rc = hartree(s, s->rho, s->vh[warm], s->vh[idx], nullptr, nullptr);
+    rc = hartree(s, s->rho, s->vh[warm], s->vh[idx], wait_hartree, nullptr, nullptr);
     if (rc) return rc;
   }
+  return evaluate_tail(s, idx, bb_ref, want_gxd, want_gg);
+}
+
+// Everything after the Hartree solve: exchange, Hamiltonian, Gram blocks, gradient,
+// reductions and the evaluation summary of slot idx.
+int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg) {
+  const double* Xs = s->X[idx];
   Partials pt{s->spart, kPartStride};
   tbeg(s, KS_PH_XC);
   launch_xc(s->rho, s->vh[idx], s->vext, s->veff[idx], s->grid, s->use_h, s->use_x,
@@ -356,13 +391,16 @@ int evaluate(ks_system* s, int idx, bool rho_ready, int bb_ref, int warm, bool w
   launch_hx<double>(Xs, s->p, s->G[idx], s->p, s->veff[idx], s->vext, s->grid, s->p,
                     2.0 * s->f, &pt, s->st);
   tend(s, KS_PH_HAMILTONIAN);
+  // Gram blocks of [X, G]: X^T X and X^T G (and G^T G for the Cayley system)
+  const int mask1 = kGramAA | kGramAB | (want_gg ? kGramBB : 0);
   tbeg(s, KS_PH_GRAM);
-  launch_gram(Xs, s->G[idx], s->p, s->n, s->p, 3, s->gram_part, s->gram_nchunks, s->st);
+  launch_gram(Xs, s->G[idx], s->p, s->n, s->p, mask1, s->gram_part, s->gram_nchunks, s->st);
   tend(s, KS_PH_GRAM);
   tbeg(s, KS_PH_SMALL);
-  launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, 3, s->p, s->gxg[idx], s->st);
-  launch_grad_weights(s->gxg[idx], s->pp, s->W, s->st);
+  launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, mask1, s->gxg[idx], s->W, s->st);
   tend(s, KS_PH_SMALL);
+  // D = G - X (G^T X) with ||D||^2, the BB sums and (QR) the Gram blocks X^T D, D^T D
+  const bool fused = want_gxd && combine_fuses_gram(s->p);
   CombineArgs ca{};
   ca.X = Xs;
   ca.A = s->W;
@@ -371,24 +409,29 @@ int evaluate(ks_system* s, int idx, bool rho_ready, int bb_ref, int warm, bool w
   ca.Xk = bb_ref >= 0 ? s->X[bb_ref] : Xs;
   ca.Dk = bb_ref >= 0 ? s->D[bb_ref] : s->D[idx];
   ca.pt = pt;
+  ca.gram_part = fused ? s->gram_part : nullptr;
   ca.ld = s->p;
   ca.n = s->n;
   ca.p = s->p;
   tbeg(s, KS_PH_GRADIENT);
   launch_combine(ca, s->st);
   tend(s, KS_PH_GRADIENT);
-  if (want_gxd) {
+  const int mask2 = kGramAB | kGramBB;
+  if (want_gxd && !fused) {
     tbeg(s, KS_PH_GRAM);
-    launch_gram(Xs, s->D[idx], s->p, s->n, s->p, 3, s->gram_part, s->gram_nchunks, s->st);
+    launch_gram(Xs, s->D[idx], s->p, s->n, s->p, mask2, s->gram_part, s->gram_nchunks, s->st);
     tend(s, KS_PH_GRAM);
-    launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, 3, s->p, s->gxd[idx], s->st);
   }
   tbeg(s, KS_PH_SMALL);
+  if (want_gxd)
+    launch_gram_reduce(s->gram_part, fused ? combine_blocks_gram(s->n) : s->gram_nchunks, s->pp,
+                       mask2, s->gxd[idx], nullptr, s->st);
   int nblk[kMaxScalarSlots] = {};
   const int hb = std::min((s->n * s->p + kBlock - 1) / kBlock, kPartStride);
   nblk[SL_KIN] = nblk[SL_EXT] = std::max(hb, 1);
   nblk[SL_EH] = nblk[SL_EX] = scalar_blocks(s->n);
-  nblk[SL_DD] = nblk[SL_SS] = nblk[SL_SY] = nblk[SL_YY] = combine_blocks(s->n);
+  nblk[SL_DD] = nblk[SL_SS] = nblk[SL_SY] = nblk[SL_YY] =
+      fused ? combine_blocks_gram(s->n) : combine_blocks(s->n);
   launch_reduce_scalars(s->spart, kPartStride, nblk, SL_COUNT, s->sums[idx], s->st);
   launch_finish_eval(s->sums[idx], s->gxg[idx], s->p, s->pp, s->f, s->grid.dV, s->enuc,
                      s->use_h ? s->cg : nullptr, s->ev[idx], s->st);
@@ -603,7 +646,7 @@ int ks_hartree_solve(ks_system* s, const double* rho, double* v_h, int warm, int
   if (!s || !rho || !v_h) return fail(s, KS_E_INVAL, "null argument");
   int it = 0;
   double rr = 0.0;
-  int rc = hartree(s, rho, warm ? v_h : nullptr, v_h, &it, &rr);
+  int rc = hartree(s, rho, warm ? v_h : nullptr, v_h, true, &it, &rr);
   if (rc) return rc;
   if (host_cg(s)->bb == 0.0) launch_fill(v_h, 0.0, s->n, s->st);
   rc = hip_check(s, hipStreamSynchronize(s->st), "hartree sync");
@@ -640,8 +683,9 @@ int ks_gram(ks_system* s, const void* Ain, const void* Bin, double* out) {
                             s->st);
   launch_copy_block<double>(s->G[t], s->p, static_cast<const double*>(Bin), s->ld, s->n, s->p,
                             s->st);
-  launch_gram(s->X[t], s->G[t], s->p, s->n, s->p, 3, s->gram_part, s->gram_nchunks, s->st);
-  launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, 3, s->p, s->gxg[t], s->st);
+  const int all = kGramAA | kGramAB | kGramBB;
+  launch_gram(s->X[t], s->G[t], s->p, s->n, s->p, all, s->gram_part, s->gram_nchunks, s->st);
+  launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, all, s->gxg[t], nullptr, s->st);
   launch_compact_gram(s->gxg[t], s->pp, s->p, out, s->st);
   int rc = launch_check(s, "gram");
   return rc ? rc : hip_check(s, hipStreamSynchronize(s->st), "gram sync");
@@ -652,7 +696,7 @@ int ks_energy_grad(ks_system* s, const void* X, void* G, void* gradE, ks_energy*
   const int c = s->cur;
   launch_copy_block<double>(s->X[c], s->p, static_cast<const double*>(X), s->ld, s->n, s->p,
                             s->st);
-  int rc = evaluate(s, c, false, -1, c, false);
+  int rc = evaluate(s, c, false, -1, c, false, false);
   if (rc) return rc;
   if (G)
     launch_copy_block<double>(static_cast<double*>(G), s->ld, s->G[c], s->p, s->n, s->p, s->st);
@@ -679,8 +723,9 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
                             s->st);
   launch_copy_block<double>(s->G[t], s->p, static_cast<const double*>(G), s->ld, s->n, s->p,
                             s->st);
-  launch_gram(s->X[t], s->G[t], s->p, s->n, s->p, 3, s->gram_part, s->gram_nchunks, s->st);
-  launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, 3, s->p, s->gxg[t], s->st);
+  const int all = kGramAA | kGramAB | kGramBB;
+  launch_gram(s->X[t], s->G[t], s->p, s->n, s->p, all, s->gram_part, s->gram_nchunks, s->st);
+  launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, all, s->gxg[t], s->W, s->st);
   launch_set_scalar(s->tau_user, tau, s->st);
   int* hstat = host_int(s);
   hstat[0] = 0;
@@ -692,7 +737,6 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
   ca.n = s->n;
   ca.p = s->p;
   if (kind == KS_QR) {
-    launch_grad_weights(s->gxg[t], s->pp, s->W, s->st);
     CombineArgs cd{};
     cd.X = s->X[t];
     cd.A = s->W;
@@ -702,10 +746,11 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
     cd.n = s->n;
     cd.p = s->p;
     launch_combine(cd, s->st);
-    launch_gram(s->X[t], s->D[t], s->p, s->n, s->p, 3, s->gram_part, s->gram_nchunks, s->st);
-    launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, 3, s->p, s->gxd[t], s->st);
-    launch_qr_factor(s->gxd[t], s->p, s->pp, s->tau_user, s->A, s->B, s->work, s->status,
-                     s->st);
+    const int m2 = kGramAB | kGramBB;
+    launch_gram(s->X[t], s->D[t], s->p, s->n, s->p, m2, s->gram_part, s->gram_nchunks, s->st);
+    launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, m2, s->gxd[t], nullptr, s->st);
+    launch_qr_factor(s->gxg[t], s->gxd[t], s->p, s->pp, s->tau_user, s->A, s->B, s->work,
+                     s->status, s->st);
     ca.Y = s->D[t];
   } else {
     launch_wy_factor(s->gxg[t], s->p, s->pp, s->tau_user, INFINITY, s->A, s->B, s->work,
@@ -752,7 +797,7 @@ int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* 
   if (rc) return rc;
   // the first Hartree solve starts from V_H = 0, so a run depends only on X_inout
   launch_fill(s->vh[c], 0.0, s->n, s->st);
-  rc = evaluate(s, c, false, -1, c, qr);
+  rc = evaluate(s, c, false, -1, c, qr, !qr);
   if (rc) return rc;
   launch_ls_init(s->ev[c], s->ls, lp, s->st);
   LsState* hl = host_ls(s);
@@ -772,8 +817,8 @@ int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* 
     ca.p = s->p;
     tbeg(s, KS_PH_SMALL);
     if (qr) {
-      launch_qr_factor(s->gxd[c], s->p, s->pp, &s->ls->tau, s->A, s->B, s->work, &s->ls->error,
-                       s->st);
+      launch_qr_factor(s->gxg[c], s->gxd[c], s->p, s->pp, &s->ls->tau, s->A, s->B, s->work,
+                       &s->ls->error, s->st);
       ca.Y = s->D[c];
     } else {
       launch_wy_factor(s->gxg[c], s->p, s->pp, &s->ls->tau, prm.reorth_tol, s->A, s->B, s->work,
@@ -784,15 +829,33 @@ int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* 
     tbeg(s, KS_PH_RETRACT);
     launch_combine(ca, s->st);
     tend(s, KS_PH_RETRACT);
-    rc = evaluate(s, t, true, c, c, qr);
+    const bool pcg = s->solver == KS_HARTREE_PCG_FD;
+    rc = evaluate(s, t, true, c, c, qr, !qr, !pcg);
     if (rc) return rc;
     tbeg(s, KS_PH_SMALL);
-    launch_ls_judge(s->ev[t], s->ls, lp, s->st);
+    launch_ls_judge(s->ev[t], s->ls, lp, s->use_h ? s->cg : nullptr, s->st);
     tend(s, KS_PH_SMALL);
     rc = launch_check(s, "line search");
     if (rc) return rc;
-    rc = readback(s, hl, s->ls);
+    if (pcg && s->use_h) {
+      rc = readback2(s, hl, s->ls, host_cg(s), s->cg);
+      if (rc == KS_OK && !hl->hartree_pending) s->cg_total += host_cg(s)->it;
+    } else {
+      rc = readback(s, hl, s->ls);
+    }
     if (rc) return rc;
+    if (hl->hartree_pending) {
+      // rare: the queued PCG iterations did not reach the tolerance; finish the solve
+      // and evaluate the trial again
+      rc = hartree_iterate(s, s->vh[t], 2, true, nullptr, nullptr);
+      if (rc) return rc;
+      rc = evaluate_tail(s, t, c, qr, !qr);
+      if (rc) return rc;
+      launch_ls_judge(s->ev[t], s->ls, lp, s->use_h ? s->cg : nullptr, s->st);
+      rc = readback(s, hl, s->ls);
+      if (rc) return rc;
+      if (hl->hartree_pending) return fail(s, KS_E_NOT_CONVERGED, "Hartree solve did not converge");
+    }
     if (hl->error) break;
     if (hl->accepted) {
       c = t;

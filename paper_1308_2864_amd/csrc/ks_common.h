@@ -72,7 +72,7 @@ struct LsState {
   int stop;            // KS_STOP_*
   int backtracks, ls_fail, nfe, reorth_flag;
   int error;           // KS_E_* raised by a device step
-  int pad;
+  int hartree_pending; // the trial's Hartree solve had not converged: nothing was judged
 };
 
 // Constants of the discretisation, passed by value to kernels.
@@ -143,6 +143,8 @@ struct FdOps {
   const double *lx, *ly, *lz;   // their eigenvalues of -d^2/dx^2 (already / h^2)
 };
 size_t hartree_part_doubles();
+size_t fd_lds_bytes(int nx, int ny, int nz);
+int fd_max_plane();
 void launch_fd_setup(double* S, double* lam, int N, double h, hipStream_t st);
 void launch_hartree_init(const double* rho, const double* x0, double* x, double* r, double* p0,
                          CgState* cs, double tol, int maxit, Grid g, double* part,
@@ -154,11 +156,15 @@ void launch_hartree_iter(double* x, double* r, const double* z, double* pa, doub
                          hipStream_t st);
 
 // dense kernels (kernels_dense.hip)
+constexpr int kGramAA = 1, kGramAB = 2, kGramBB = 4;  // product bits of a Gram launch
 int gram_chunks(int n, int pp);
-void launch_gram(const double* A, const double* B, int ld, int n, int p, int nprod,
+size_t gram_part_doubles(int n, int pp);
+bool combine_fuses_gram(int p);
+void launch_gram(const double* A, const double* B, int ld, int n, int p, int mask,
                  double* partials, int nchunks, hipStream_t st);
-void launch_gram_reduce(const double* partials, int nchunks, int pp, int nprod, int p,
-                        double* out, hipStream_t st);
+// out: [3][pp][pp]; products outside mask are zero; W (nullable) = -(A^T B)^T
+void launch_gram_reduce(const double* partials, int nchunks, int pp, int mask, double* out,
+                        double* W, hipStream_t st);
 struct CombineArgs {
   const double* X; const double* A;     // X (n x ld) times A (pp x pp)
   const double* Y; const double* B;     // optional Y (n x ld) times B
@@ -168,15 +174,17 @@ struct CombineArgs {
   // optional BB/gradient epilogue: out is D_t; uses Xt (= X), Xk, Dk
   const double* Xk; const double* Dk;
   Partials pt;                          // slots SL_DD.. SL_YY (by value)
+  double* gram_part;                    // optional partial Gram tiles X^T D, D^T D
   int ld, n, p;
 };
 void launch_combine(const CombineArgs& a, hipStream_t st);
 int combine_blocks(int n);
+int combine_blocks_gram(int n);
 
 // small dense kernels (kernels_small.hip)
 void launch_grad_weights(const double* gram, int pp, double* W, hipStream_t st);
-void launch_qr_factor(const double* gram_xd, int p, int pp, const double* tau, double* A,
-                      double* B, double* work, int* status, hipStream_t st);
+void launch_qr_factor(const double* xx, const double* gxd, int p, int pp, const double* tau,
+                      double* A, double* B, double* work, int* status, hipStream_t st);
 void launch_wy_factor(const double* gram_xg, int p, int pp, const double* tau,
                       double reorth_tol, double* A, double* B, double* work, int* status,
                       int* reorth_flag, hipStream_t st);
@@ -188,6 +196,7 @@ void launch_finish_eval(const double* sums, const double* gram_xx, int p, int pp
                         hipStream_t st);
 void launch_set_scalar(double* dst, double v, hipStream_t st);
 void launch_ls_init(const EvalOut* ev, LsState* ls, LsParams prm, hipStream_t st);
-void launch_ls_judge(const EvalOut* ev, LsState* ls, LsParams prm, hipStream_t st);
+void launch_ls_judge(const EvalOut* ev, LsState* ls, LsParams prm, const CgState* cg,
+                     hipStream_t st);
 
 }  // namespace ks

@@ -401,13 +401,37 @@ def test_minimize_c1_matches_oracle_reference(kind, solver):
         retraction=K.KS_QR if kind == "qr" else K.KS_WY))
     assert r.stop_reason == K.KS_STOP_GRAD
     assert abs(r.energy - gold["E"]) <= 1e-10 * abs(gold["E"])
+    # The occupied subspace of c1 is ill-determined at ||grad E|| = 1e-7 (gap ~8e-3 Ha and a
+    # softer nonlinear Hessian), so compare what is unique -- the energy above and the
+    # occupied Ritz values -- and check that the GPU point is a stationary point of the same
+    # kind as the oracle's: every occupied Ritz value is an eigenvalue of its own H(rho).
+    # (From this seed Alg. 3 -- oracle and GPU alike -- ends at a stationary point that
+    # occupies levels 1, 2, 3 and 5 of H(rho); the theory of Alg. 3 promises stationarity,
+    # not the aufbau occupation.)
+    import scipy.sparse.linalg as spla
     Xref = np.load(os.path.join(GOLDEN, "oracle_c1_s0_qr_X.npy"))
     Xg = host(X)
-    # Davis-Kahan: each occupied subspace is within ||grad E||/(2 f gap) of the exact one;
-    # the gap of c1 is small (about 8e-3 Ha), so the bound, not 1e-6, sets the tolerance.
-    # Factor 4 covers the softening of the nonlinear Hessian relative to the linear gap.
-    tol = 4.0 * math.sqrt(2.0) * (r.grad_norm + gold["gnorm"]) / (2.0 * spec.f * gold["gap"])
-    assert np.linalg.norm(Xg @ Xg.T - Xref @ Xref.T) <= max(tol, 1e-6)
+    orc = oracle_fd(spec)
+
+    def ritz_and_resid(Xa):
+        veff = orc.effective_potential(Xa)
+        HX = orc.hamiltonian_apply(Xa, veff)
+        T = Xa.T @ HX
+        return np.linalg.eigvalsh(0.5 * (T + T.T)), np.linalg.norm(HX - Xa @ T), veff
+
+    rg, resid, veff = ritz_and_resid(Xg)
+    rr, _, _ = ritz_and_resid(Xref)
+    assert resid <= 1.01 * r.grad_norm / (2 * spec.f) + 1e-12
+    assert np.max(np.abs(rg - rr)) <= 1e-7
+    # lowest p + 2 eigenvalues of H(rho(X_gpu)) by LOBPCG started from [X_gpu, random]
+    op = spla.LinearOperator((orc.n, orc.n), dtype=float,
+                             matmat=lambda V: orc.hamiltonian_apply(V, veff),
+                             matvec=lambda v: orc.hamiltonian_apply(v.reshape(-1, 1), veff).ravel())
+    B0 = np.hstack([Xg, np.random.default_rng(5).standard_normal((orc.n, 2))])
+    w, _ = spla.lobpcg(op, B0, largest=False, tol=1e-9, maxiter=2000)
+    w = np.sort(w)
+    for lam in rg:
+        assert np.min(np.abs(w - lam)) <= 1e-6
 
 
 def test_minimize_stop_rules():
