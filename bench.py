@@ -73,6 +73,8 @@ def main():
     ap.add_argument("--hartree", choices=["cg", "pcg_fd"], default="pcg_fd")
     ap.add_argument("--cpu-iters", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp32-steps", type=int, default=3,
+                    help="timed solves of the FP32-storage leg (0 = skip)")
     ap.add_argument("--max-iter", type=int, default=10000,
                     help="iteration cap (profiling runs only; the metric needs the default)")
     args = ap.parse_args()
@@ -161,6 +163,48 @@ def main():
     spmm = phase_out.get("hamiltonian", {}).get("GBps")
 
     iters = int(np.median([r.iters for r in results])) if results else 0
+
+    # FP32 storage leg: the same solve with X, G, D in float (products still in FP64)
+    fp32 = None
+    if args.fp32_steps > 0:
+        sys32 = ks.system_from_spec(spec, hartree_solver=solver, precision=ks.KS_PREC_FP32)
+        X032 = X0.float()
+        X32 = torch.empty_like(X032)
+        prm32 = ks.ks_default_params(retraction=prm.retraction, max_iter=args.max_iter)
+        X32.copy_(X032)
+        sys32.ks_minimize(X32, prm32)  # warm-up
+        torch.cuda.synchronize()
+        t32 = time.perf_counter()
+        r32 = None
+        lat32 = []
+        for i in range(args.fp32_steps):
+            a = time.perf_counter()
+            X32.copy_(X032)
+            r32 = sys32.ks_minimize(X32, prm32)
+            torch.cuda.synchronize()
+            lat32.append(time.perf_counter() - a)
+        el32 = time.perf_counter() - t32
+        e64 = results[-1].energy
+        # FP64 polish from the FP32 result: the FP32 iterate stalls once tau*D falls below
+        # the float resolution of X; a few FP64 iterations finish the solve
+        Xp = X32.double()
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        rp = sysg.ks_minimize(Xp, prm)
+        torch.cuda.synchronize()
+        tpol = time.perf_counter() - tp
+        fp32 = {"value": round(args.fp32_steps / el32, 4), "unit": "solves/s",
+                "ms_per_step": round(1e3 * el32 / args.fp32_steps, 3),
+                "iterations": r32.iters, "stop": ks.STOP_NAMES[r32.stop_reason],
+                "energy": r32.energy, "abs_error_vs_fp64_Ha": abs(r32.energy - e64),
+                "within_1e-6_Ha": abs(r32.energy - e64) <= 1e-6,
+                "fp64_polish": {"iterations": rp.iters, "ms": round(1e3 * tpol, 3),
+                                "energy": rp.energy,
+                                "abs_error_vs_fp64_Ha": abs(rp.energy - e64),
+                                "solves_per_s_fp32_plus_polish":
+                                    round(1.0 / (el32 / args.fp32_steps + tpol), 4)}}
+        print(f"# fp32: {r32.iters} it, E={r32.energy:.12f}, |E-E64|={abs(r32.energy - e64):.2e}, "
+              f"{1e3 * el32 / args.fp32_steps:.1f} ms/solve", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
@@ -190,6 +234,7 @@ def main():
         "energy": results[-1].energy if results else None,
         "grad_norm": results[-1].grad_norm if results else None,
         "spmm_GBps": spmm,
+        "fp32": fp32,
         "phases": phase_out,
         "roofline": roofline,
         "cpu_baseline": cpu,

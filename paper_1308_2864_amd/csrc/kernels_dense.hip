@@ -74,10 +74,9 @@ __device__ inline void put_tile(double* part, int blk, int prod, int ti, int tj,
 }
 
 // ---- Gram: per-chunk partials -------------------------------------------------------
-template <int kT, int kMask>
-__global__ __launch_bounds__(256) void k_gram(const double* __restrict__ A,
-                                              const double* __restrict__ B, int ld, int n,
-                                              int p, double* __restrict__ part) {
+template <typename T, int kT, int kMask>
+__global__ __launch_bounds__(256) void k_gram(const T* __restrict__ A, const T* __restrict__ B,
+                                              int ld, int n, int p, double* __restrict__ part) {
   constexpr int kPP = kT * 16;
   constexpr int kAcc = GramTiles<kT, kMask>::kN;
   extern __shared__ double lds[];
@@ -100,8 +99,8 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ A,
     for (int t = 0; t < kT; ++t) {
       const int col = t * 16 + lc;
       const bool ok = rok && col < p;
-      fa[t] = ok ? A[(size_t)row * ld + col] : 0.0;
-      fb[t] = ((kMask & (kPAB | kPBB)) && ok) ? B[(size_t)row * ld + col] : 0.0;
+      fa[t] = ok ? (double)A[(size_t)row * ld + col] : 0.0;
+      fb[t] = ((kMask & (kPAB | kPBB)) && ok) ? (double)B[(size_t)row * ld + col] : 0.0;
     }
     int a = 0;
     if (kMask & kPAA) {
@@ -194,8 +193,14 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
 //          and, with kGram2, the Gram tiles X^T D and D^T D: an FP64 MFMA result tile of
 //          a 4-row group (register r) is laid out exactly as an MFMA input fragment, so
 //          D goes from the accumulators straight back into the matrix cores.
-template <int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad, bool kGram2>
+template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad, bool kGram2>
 __global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
+  const T* aX = static_cast<const T*>(a.X);
+  const T* aY = static_cast<const T*>(a.Y);
+  const T* aC0 = static_cast<const T*>(a.C0);
+  const T* aXk = static_cast<const T*>(a.Xk);
+  const T* aDk = static_cast<const T*>(a.Dk);
+  T* aout = static_cast<T*>(a.out);
   constexpr int kPP = kT * 16;
   constexpr int kK = kHasY ? 2 * kPP : kPP;  // contraction length
   constexpr int kG2 = kGram2 ? (kT * kT + kT * (kT + 1) / 2) : 1;
@@ -228,17 +233,17 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
     // A-fragment rows: g0 + lc ; columns k0 + lr
     const int arow = g0 + lc;
     const bool arok = arow < a.n;
-    const double* xr = a.X + (size_t)arow * ld;
-    const double* yr = kHasY ? a.Y + (size_t)arow * ld : nullptr;
+    const T* xr = aX + (size_t)arow * ld;
+    const T* yr = kHasY ? aY + (size_t)arow * ld : nullptr;
 #pragma unroll 4
     for (int k0 = 0; k0 < kK; k0 += 4) {
       const int k = k0 + lr;
       double av;
       if (!kHasY || k < kPP) {
-        av = (arok && k < p) ? xr[k] : 0.0;
+        av = (arok && k < p) ? (double)xr[k] : 0.0;
       } else {
         const int ky = k - kPP;
-        av = (arok && ky < p) ? yr[ky] : 0.0;
+        av = (arok && ky < p) ? (double)yr[ky] : 0.0;
       }
 #pragma unroll
       for (int t = 0; t < kT; ++t) {
@@ -259,12 +264,14 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
         if (ok) {
           const size_t off = (size_t)row * ld + col;
           v = acc[t][r];
-          if (kHasC0) v += a.C0[off];
-          a.out[off] = v;
+          if (kHasC0) v += (double)aC0[off];
+          const T vs = (T)v;
+          aout[off] = vs;
+          v = (double)vs;  // the epilogues see the stored value
           if (kRho) sq[r] += v * v;
           if (kGrad) {
-            const double s = a.X[off] - a.Xk[off];
-            const double y = v - a.Dk[off];
+            const double s = (double)aX[off] - (double)aXk[off];
+            const double y = v - (double)aDk[off];
             dd += v * v;
             ss += s * s;
             sy += s * y;
@@ -282,7 +289,7 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
 #pragma unroll
         for (int t = 0; t < kT; ++t) {
           const int col = t * 16 + lc;
-          fx[t] = (row < a.n && col < p) ? a.X[(size_t)row * ld + col] : 0.0;
+          fx[t] = (row < a.n && col < p) ? (double)aX[(size_t)row * ld + col] : 0.0;
         }
         int q = 0;
 #pragma unroll
@@ -344,59 +351,90 @@ void set_lds_attr(const void* k, size_t bytes) {
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int kT, int kMask>
-void launch_gram_m(const double* A, const double* B, int ld, int n, int p, double* part,
-                   int nchunks, hipStream_t st) {
+template <typename T, int kT, int kMask>
+void launch_gram_m(const T* A, const T* B, int ld, int n, int p, double* part, int nchunks,
+                   hipStream_t st) {
   const size_t lds = (size_t)3 * 4 * 64 * sizeof(double);
-  hipLaunchKernelGGL((k_gram<kT, kMask>), dim3(nchunks), dim3(256), lds, st, A, B, ld, n, p,
+  hipLaunchKernelGGL((k_gram<T, kT, kMask>), dim3(nchunks), dim3(256), lds, st, A, B, ld, n, p,
                      part);
 }
 
 // Up to 32 columns all requested products run in one pass; wider blocks run one product
 // per pass to bound the accumulator registers.
-template <int kT>
-void launch_gram_t(const double* A, const double* B, int ld, int n, int p, int mask,
-                   double* part, int nchunks, hipStream_t st) {
+template <typename T, int kT>
+void launch_gram_t(const T* A, const T* B, int ld, int n, int p, int mask, double* part,
+                   int nchunks, hipStream_t st) {
   if constexpr (kT <= 2) {
-    if (mask == (kPAA | kPAB | kPBB)) return launch_gram_m<kT, 7>(A, B, ld, n, p, part, nchunks, st);
-    if (mask == (kPAA | kPAB)) return launch_gram_m<kT, 3>(A, B, ld, n, p, part, nchunks, st);
+    if (mask == (kPAA | kPAB | kPBB))
+      return launch_gram_m<T, kT, 7>(A, B, ld, n, p, part, nchunks, st);
+    if (mask == (kPAA | kPAB)) return launch_gram_m<T, kT, 3>(A, B, ld, n, p, part, nchunks, st);
   }
-  if (mask & kPAA) launch_gram_m<kT, 1>(A, B, ld, n, p, part, nchunks, st);
-  if (mask & kPAB) launch_gram_m<kT, 2>(A, B, ld, n, p, part, nchunks, st);
-  if (mask & kPBB) launch_gram_m<kT, 4>(A, B, ld, n, p, part, nchunks, st);
+  if (mask & kPAA) launch_gram_m<T, kT, 1>(A, B, ld, n, p, part, nchunks, st);
+  if (mask & kPAB) launch_gram_m<T, kT, 2>(A, B, ld, n, p, part, nchunks, st);
+  if (mask & kPBB) launch_gram_m<T, kT, 4>(A, B, ld, n, p, part, nchunks, st);
 }
 
-template <int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad, bool kGram2>
+template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad, bool kGram2>
 void launch_combine_t(const CombineArgs& a, hipStream_t st) {
   constexpr int kPP = kT * 16;
   const size_t lds = (size_t)(kHasY ? 2 : 1) * kPP * kPP * sizeof(double) +
                      (kGram2 ? (size_t)3 * 4 * 64 * sizeof(double) : 0);
   static bool attr = false;
   if (!attr) {
-    set_lds_attr(reinterpret_cast<const void*>(k_combine<kT, kHasY, kHasC0, kRho, kGrad, kGram2>),
-                 lds);
+    set_lds_attr(
+        reinterpret_cast<const void*>(k_combine<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2>), lds);
     attr = true;
   }
   const int nb = kGram2 ? combine_blocks_gram(a.n) : combine_blocks(a.n);
-  hipLaunchKernelGGL((k_combine<kT, kHasY, kHasC0, kRho, kGrad, kGram2>), dim3(nb), dim3(256),
+  hipLaunchKernelGGL((k_combine<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2>), dim3(nb), dim3(256),
                      lds, st, a);
 }
 
-template <int kT>
+template <typename T, int kT>
 void launch_combine_tt(const CombineArgs& a, hipStream_t st) {
   const bool y = a.Y != nullptr, c0 = a.C0 != nullptr, rho = a.rho != nullptr,
              gr = a.Xk != nullptr, g2 = a.gram_part != nullptr;
   // the combinations the library uses
-  if (y && !c0 && rho && !gr) return launch_combine_t<kT, true, false, true, false, false>(a, st);
-  if (y && !c0 && !rho && !gr) return launch_combine_t<kT, true, false, false, false, false>(a, st);
+  if (y && !c0 && rho && !gr)
+    return launch_combine_t<T, kT, true, false, true, false, false>(a, st);
+  if (y && !c0 && !rho && !gr)
+    return launch_combine_t<T, kT, true, false, false, false, false>(a, st);
   if constexpr (kT <= 2) {
     if (!y && c0 && !rho && gr && g2)
-      return launch_combine_t<kT, false, true, false, true, true>(a, st);
+      return launch_combine_t<T, kT, false, true, false, true, true>(a, st);
   }
-  if (!y && c0 && !rho && gr) return launch_combine_t<kT, false, true, false, true, false>(a, st);
-  if (!y && c0 && !rho && !gr) return launch_combine_t<kT, false, true, false, false, false>(a, st);
-  if (!y && !c0 && rho && !gr) return launch_combine_t<kT, false, false, true, false, false>(a, st);
-  launch_combine_t<kT, false, false, false, false, false>(a, st);
+  if (!y && c0 && !rho && gr)
+    return launch_combine_t<T, kT, false, true, false, true, false>(a, st);
+  if (!y && c0 && !rho && !gr)
+    return launch_combine_t<T, kT, false, true, false, false, false>(a, st);
+  if (!y && !c0 && rho && !gr)
+    return launch_combine_t<T, kT, false, false, true, false, false>(a, st);
+  launch_combine_t<T, kT, false, false, false, false, false>(a, st);
+}
+
+template <typename T>
+void launch_combine_p(const CombineArgs& a, hipStream_t st) {
+  const int pp = round_up(a.p, 16);
+  switch (pp / 16) {
+    case 1: launch_combine_tt<T, 1>(a, st); break;
+    case 2: launch_combine_tt<T, 2>(a, st); break;
+    case 3: launch_combine_tt<T, 3>(a, st); break;
+    case 4: launch_combine_tt<T, 4>(a, st); break;
+    default: break;
+  }
+}
+
+template <typename T>
+void launch_gram_p(const T* A, const T* B, int ld, int n, int p, int mask, double* partials,
+                   int nchunks, hipStream_t st) {
+  const int pp = round_up(p, 16);
+  switch (pp / 16) {
+    case 1: launch_gram_t<T, 1>(A, B, ld, n, p, mask, partials, nchunks, st); break;
+    case 2: launch_gram_t<T, 2>(A, B, ld, n, p, mask, partials, nchunks, st); break;
+    case 3: launch_gram_t<T, 3>(A, B, ld, n, p, mask, partials, nchunks, st); break;
+    case 4: launch_gram_t<T, 4>(A, B, ld, n, p, mask, partials, nchunks, st); break;
+    default: break;
+  }
 }
 
 }  // namespace
@@ -415,16 +453,14 @@ size_t gram_part_doubles(int n, int pp) {
 
 bool combine_fuses_gram(int p) { return round_up(p, 16) <= 32; }
 
-void launch_gram(const double* A, const double* B, int ld, int n, int p, int mask,
+void launch_gram(const void* A, const void* B, bool f32, int ld, int n, int p, int mask,
                  double* partials, int nchunks, hipStream_t st) {
-  const int pp = round_up(p, 16);
-  switch (pp / 16) {
-    case 1: launch_gram_t<1>(A, B, ld, n, p, mask, partials, nchunks, st); break;
-    case 2: launch_gram_t<2>(A, B, ld, n, p, mask, partials, nchunks, st); break;
-    case 3: launch_gram_t<3>(A, B, ld, n, p, mask, partials, nchunks, st); break;
-    case 4: launch_gram_t<4>(A, B, ld, n, p, mask, partials, nchunks, st); break;
-    default: break;
-  }
+  if (f32)
+    launch_gram_p<float>(static_cast<const float*>(A), static_cast<const float*>(B), ld, n, p,
+                         mask, partials, nchunks, st);
+  else
+    launch_gram_p<double>(static_cast<const double*>(A), static_cast<const double*>(B), ld, n, p,
+                          mask, partials, nchunks, st);
 }
 
 void launch_gram_reduce(const double* partials, int nchunks, int pp, int mask, double* out,
@@ -447,14 +483,8 @@ int combine_blocks_gram(int n) {
 }
 
 void launch_combine(const CombineArgs& a, hipStream_t st) {
-  const int pp = round_up(a.p, 16);
-  switch (pp / 16) {
-    case 1: launch_combine_tt<1>(a, st); break;
-    case 2: launch_combine_tt<2>(a, st); break;
-    case 3: launch_combine_tt<3>(a, st); break;
-    case 4: launch_combine_tt<4>(a, st); break;
-    default: break;
-  }
+  if (a.f32) launch_combine_p<float>(a, st);
+  else launch_combine_p<double>(a, st);
 }
 
 }  // namespace ks

@@ -229,10 +229,11 @@ constexpr int kFdTiles = 8;     // result tiles a wave can hold (covers 128 x 12
 // (row = y).  Step 1 T = P S_x (results held in registers), step 2 Y = S_y T.  The plane
 // lives in LDS (row stride nxp + 1 doubles: conflict-free column reads).  With part the
 // partial r.Y of the plane goes to slot 3.
+template <bool kStageS>
 __global__ __launch_bounds__(512) void k_fd_plane(const double* __restrict__ in,
                                                   double* __restrict__ out,
-                                                  const double* __restrict__ Sx,
-                                                  const double* __restrict__ Sy, int nx, int ny,
+                                                  const double* __restrict__ Sxg,
+                                                  const double* __restrict__ Syg, int nx, int ny,
                                                   const double* __restrict__ r,
                                                   double* __restrict__ part,
                                                   const CgState* cs) {
@@ -247,6 +248,17 @@ __global__ __launch_bounds__(512) void k_fd_plane(const double* __restrict__ in,
   for (int e = threadIdx.x; e < nyp * nxp; e += blockDim.x) {
     const int j = e / nxp, m = e % nxp;
     P[j * sp + m] = (j < ny && m < nx) ? in[base + (size_t)j * nx + m] : 0.0;
+  }
+  // the sine matrices follow the plane in LDS when they fit (dense nx x nx, ny x ny)
+  const double* Sx = Sxg;
+  const double* Sy = Syg;
+  if (kStageS) {
+    double* sx = P + nyp * sp;
+    double* sy = sx + nx * nx;
+    for (int e = threadIdx.x; e < nx * nx; e += blockDim.x) sx[e] = Sxg[e];
+    for (int e = threadIdx.x; e < ny * ny; e += blockDim.x) sy[e] = Syg[e];
+    Sx = sx;
+    Sy = sy;
   }
   __syncthreads();
   const int tx = nxp / 16, ntile = (nyp / 16) * tx;
@@ -302,13 +314,14 @@ __global__ __launch_bounds__(512) void k_fd_plane(const double* __restrict__ in,
 
 // z lines (block = 64 adjacent (i, j) columns x nz): forward transform, division by
 // lx[i] + ly[j] + lz[k], inverse transform (S_z is its own inverse), in place.
+template <bool kStageS>
 __global__ __launch_bounds__(512) void k_fd_z(double* __restrict__ u,
-                                              const double* __restrict__ Sz,
+                                              const double* __restrict__ Szg,
                                               const double* __restrict__ lx,
                                               const double* __restrict__ ly,
                                               const double* __restrict__ lz, int nx, int ny,
                                               int nz, const CgState* cs) {
-  extern __shared__ double A[];  // nzp x 64
+  extern __shared__ double A[];  // nzp x 64 (then S_z when it fits)
   if (cs->done) return;
   const int npl = nx * ny;
   const int nzp = (nz + 15) & ~15;
@@ -318,6 +331,12 @@ __global__ __launch_bounds__(512) void k_fd_z(double* __restrict__ u,
   for (int e = threadIdx.x; e < nzp * 64; e += blockDim.x) {
     const int m = e / 64, l = e % 64;
     A[e] = (m < nz && l0 + l < npl) ? u[(size_t)m * npl + l0 + l] : 0.0;
+  }
+  const double* Sz = Szg;
+  if (kStageS) {
+    double* sz = A + nzp * 64;
+    for (int e = threadIdx.x; e < nz * nz; e += blockDim.x) sz[e] = Szg[e];
+    Sz = sz;
   }
   __syncthreads();
   const int ntile = (nzp / 16) * 4;
@@ -408,16 +427,33 @@ void launch_fd_apply(const double* r, double* z, const FdOps& fd, Grid g, const 
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const size_t nxp = (nx + 15) & ~15, nyp = (ny + 15) & ~15, nzp = (nz + 15) & ~15;
   const size_t lp = nyp * (nxp + 1) * sizeof(double);
+  const size_t lps = lp + (size_t)(nx * nx + ny * ny) * sizeof(double);
   const size_t lzb = nzp * 64 * sizeof(double);
-  set_lds(reinterpret_cast<const void*>(k_fd_plane), lp);
-  set_lds(reinterpret_cast<const void*>(k_fd_z), lzb);
+  const size_t lzs = lzb + (size_t)nz * nz * sizeof(double);
+  const size_t cap = 150 * 1024;  // stay inside the 160 KiB of LDS of a CU
   const int threads = kFdWaves * kWave;
-  hipLaunchKernelGGL(k_fd_plane, dim3(nz), dim3(threads), lp, st, r, z, fd.Sx, fd.Sy, nx, ny,
-                     nullptr, nullptr, cs);
-  hipLaunchKernelGGL(k_fd_z, dim3((nx * ny + 63) / 64), dim3(threads), lzb, st, z, fd.Sz, fd.lx,
-                     fd.ly, fd.lz, nx, ny, nz, cs);
-  hipLaunchKernelGGL(k_fd_plane, dim3(nz), dim3(threads), lp, st, z, z, fd.Sx, fd.Sy, nx, ny, r,
-                     part, cs);
+  auto plane = [&](const double* in, double* out, const double* rr, double* pt) {
+    if (lps <= cap) {
+      set_lds(reinterpret_cast<const void*>(k_fd_plane<true>), lps);
+      hipLaunchKernelGGL(k_fd_plane<true>, dim3(nz), dim3(threads), lps, st, in, out, fd.Sx,
+                         fd.Sy, nx, ny, rr, pt, cs);
+    } else {
+      set_lds(reinterpret_cast<const void*>(k_fd_plane<false>), lp);
+      hipLaunchKernelGGL(k_fd_plane<false>, dim3(nz), dim3(threads), lp, st, in, out, fd.Sx,
+                         fd.Sy, nx, ny, rr, pt, cs);
+    }
+  };
+  plane(r, z, nullptr, nullptr);
+  if (lzs <= cap) {
+    set_lds(reinterpret_cast<const void*>(k_fd_z<true>), lzs);
+    hipLaunchKernelGGL(k_fd_z<true>, dim3((nx * ny + 63) / 64), dim3(threads), lzs, st, z, fd.Sz,
+                       fd.lx, fd.ly, fd.lz, nx, ny, nz, cs);
+  } else {
+    set_lds(reinterpret_cast<const void*>(k_fd_z<false>), lzb);
+    hipLaunchKernelGGL(k_fd_z<false>, dim3((nx * ny + 63) / 64), dim3(threads), lzb, st, z, fd.Sz,
+                       fd.lx, fd.ly, fd.lz, nx, ny, nz, cs);
+  }
+  plane(z, z, r, part);
   hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kBlock), 0, st, part, nz, const_cast<CgState*>(cs));
 }
 

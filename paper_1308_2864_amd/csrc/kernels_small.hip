@@ -197,73 +197,63 @@ __global__ void k_qr_factor(const double* __restrict__ xx, const double* __restr
   blk_store_padded(B, pp, W, p, p, -tau);
 }
 
-// Single-wavefront variant for p <= P (P = 16, 32, 64): lane j owns column j of
-// Y^T Y (padded with the identity beyond p) in registers.  The Cholesky factor and its
-// inverse are formed with cross-lane broadcasts (readlane), no LDS and no barriers.
-__device__ inline double bcast(double v, int lane) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffu), lane);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
+// Single-wavefront variant for p <= P (P = 16, 32, 64): lane j owns column j of Y^T Y.
+// The matrix, the broadcast row of R and R^{-1} live in separate LDS arrays with
+// compile-time strides, every step is a short runtime loop, and with one wavefront the
+// barriers are nearly free.
 template <int P>
 __global__ __launch_bounds__(64) void k_qr_factor_wave(const double* __restrict__ xx,
                                                        const double* __restrict__ gxd, int p,
                                                        int pp, const double* __restrict__ tau_p,
                                                        double* __restrict__ A,
                                                        double* __restrict__ B, int* status) {
-  const int j = threadIdx.x;  // column owned by this lane
+  __shared__ double M[P][P + 1];
+  __shared__ double W[P][P + 1];
+  __shared__ double rowk[P];
+  const int j = threadIdx.x;
   const double tau = *tau_p;
   const double* XD = gxd + pp * pp;
   const double* DD = gxd + 2 * pp * pp;
-  double a[P];
-#pragma unroll
-  for (int i = 0; i < P; ++i) {
-    double v = (i == j) ? 1.0 : 0.0;
-    if (i < p && j < p)
-      v = xx[i * pp + j] - tau * (XD[i * pp + j] + XD[j * pp + i]) + tau * tau * DD[i * pp + j];
-    a[i] = v;
+  for (int e = j; e < p * p; e += 64) {
+    const int i = e / p, c = e % p;
+    M[i][c] = xx[i * pp + c] - tau * (XD[i * pp + c] + XD[c * pp + i]) + tau * tau * DD[i * pp + c];
   }
-  // right-looking upper Cholesky: afterwards a[i] (lane j) = R[i][j] for i <= j
-  bool bad = false;
-#pragma unroll
-  for (int k = 0; k < P; ++k) {
-    const double d = bcast(a[k], k);
-    if (!(d > 0.0) || !isfinite(d)) bad = true;
+  __syncthreads();
+  int bad = 0;
+  for (int k = 0; k < p; ++k) {
+    const double d = M[k][k];
+    if (!(d > 0.0) || !isfinite(d)) bad = 1;
     const double rkk = sqrt(d);
-    const double rk = (j == k) ? rkk : a[k] / rkk;  // R[k][j] for j >= k
-    a[k] = (j >= k) ? rk : 0.0;
-#pragma unroll
-    for (int i = k + 1; i < P; ++i) {
-      const double rki = bcast(rk, i);  // R[k][i]
-      if (j >= i) a[i] -= rki * rk;
+    __syncthreads();
+    double rk = 0.0;
+    if (j >= k && j < p) {
+      rk = (j == k) ? rkk : M[k][j] / rkk;
+      M[k][j] = rk;
+      rowk[j] = rk;
     }
+    __syncthreads();
+    if (j > k && j < p)
+      for (int i = k + 1; i <= j; ++i) M[i][j] -= rowk[i] * rk;
+    __syncthreads();
   }
   if (bad) {
     if (j == 0) *status = KS_E_NOT_SPD;
     return;
   }
-  // W = R^{-1}: W[i][j] = (delta_ij - sum_{m > i} R[i][m] W[m][j]) / R[i][i], i = P-1..0
-  double w[P];
-#pragma unroll
-  for (int i = 0; i < P; ++i) w[i] = 0.0;
-#pragma unroll
-  for (int i = P - 1; i >= 0; --i) {
-    double acc = (i == j) ? 1.0 : 0.0;
-#pragma unroll
-    for (int m = i + 1; m < P; ++m) acc -= bcast(a[i], m) * w[m];  // R[i][m] from lane m
-    const double rii = bcast(a[i], i);
-    w[i] = (i <= j) ? acc / rii : 0.0;
+  // W = R^{-1}: W[i][j] = (delta_ij - sum_{i < m <= j} R[i][m] W[m][j]) / R[i][i]
+  if (j < p) {
+    for (int i = p - 1; i >= 0; --i) {
+      double acc = (i == j) ? 1.0 : 0.0;
+      for (int m = i + 1; m <= j; ++m) acc -= M[i][m] * W[m][j];
+      W[i][j] = (i <= j) ? acc / M[i][i] : 0.0;
+    }
   }
+  __syncthreads();
   if (j < pp) {
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-      if (i < pp) {
-        const double v = (i < p && j < p) ? w[i] : 0.0;
-        A[i * pp + j] = v;
-        B[i * pp + j] = -tau * v;
-      }
+    for (int i = 0; i < pp; ++i) {
+      const double v = (i < p && j < p) ? W[i][j] : 0.0;
+      A[i * pp + j] = v;
+      B[i * pp + j] = -tau * v;
     }
   }
 }

@@ -36,7 +36,9 @@ struct ks_system {
   double *fdS[3] = {}, *fdL[3] = {};
   int solver = KS_HARTREE_CG;
   double *Rd = nullptr, *Zd = nullptr, *enuc = nullptr, *tau_user = nullptr;
-  double *X[2] = {}, *G[2] = {}, *D[2] = {};
+  void *X[2] = {}, *G[2] = {}, *D[2] = {};  // float (FP32 modes) or double
+  bool f32 = false;
+  int es = 8;  // bytes per orbital element
   double *gxg[2] = {}, *gxd[2] = {}, *W = nullptr, *A = nullptr, *B = nullptr;
   double *work = nullptr, *gram_part = nullptr, *spart = nullptr, *cgpart = nullptr;
   double* sums[2] = {};
@@ -106,9 +108,9 @@ void layout(ks_system* s, char* base, size_t* total) {
   s->enuc = c.take<double>(1);
   s->tau_user = c.take<double>(1);
   for (int i = 0; i < 2; ++i) {
-    s->X[i] = c.take<double>(np);
-    s->G[i] = c.take<double>(np);
-    s->D[i] = c.take<double>(np);
+    s->X[i] = c.take<char>(np * s->es);
+    s->G[i] = c.take<char>(np * s->es);
+    s->D[i] = c.take<char>(np * s->es);
     s->gxg[i] = c.take<double>(3 * pp2);
     s->gxd[i] = c.take<double>(3 * pp2);
     s->sums[i] = c.take<double>(kMaxScalarSlots);
@@ -135,8 +137,8 @@ int validate(const ks_system_desc* d, std::string* why) {
     *why = "only the 7-point finite-difference discretisation is built into this library";
     return KS_E_UNSUPPORTED;
   }
-  if (d->precision != KS_PREC_FP64) {
-    *why = "only KS_PREC_FP64 is built into this library";
+  if (d->precision != KS_PREC_FP64 && d->precision != KS_PREC_FP32) {
+    *why = "precision must be KS_PREC_FP64 or KS_PREC_FP32";
     return KS_E_UNSUPPORTED;
   }
   if (d->hartree_solver != KS_HARTREE_CG && d->hartree_solver != KS_HARTREE_PCG_FD) {
@@ -182,6 +184,8 @@ void init_dims(ks_system* s, const ks_system_desc* d) {
   s->htol = d->hartree_tol > 0.0 ? d->hartree_tol : 1e-13;
   s->hmaxit = d->hartree_maxit > 0 ? d->hartree_maxit : 5000;
   s->solver = d->hartree_solver;
+  s->f32 = d->precision == KS_PREC_FP32;
+  s->es = s->f32 ? 4 : 8;
   s->R.assign(d->R ? d->R : nullptr, d->R ? d->R + 3 * d->n_nuclei : nullptr);
   s->Z.assign(d->Z ? d->Z : nullptr, d->Z ? d->Z + d->n_nuclei : nullptr);
   s->grid.nx = d->nx;
@@ -207,6 +211,39 @@ int hip_check(ks_system* s, hipError_t e, const char* what) {
 
 int launch_check(ks_system* s, const char* what) {
   return hip_check(s, hipGetLastError(), what);
+}
+
+// ---- orbital-block launches in the system's storage precision -----------------------
+
+void copy_block(ks_system* s, void* dst, int ldd, const void* src, int lds) {
+  if (s->f32)
+    launch_copy_block<float>(static_cast<float*>(dst), ldd, static_cast<const float*>(src), lds,
+                             s->n, s->p, s->st);
+  else
+    launch_copy_block<double>(static_cast<double*>(dst), ldd, static_cast<const double*>(src),
+                              lds, s->n, s->p, s->st);
+}
+
+void density(ks_system* s, const void* X, int ld, double* rho) {
+  const double scale = s->f / s->grid.dV;
+  if (s->f32)
+    launch_density<float>(static_cast<const float*>(X), ld, s->n, s->p, scale, rho, s->st);
+  else
+    launch_density<double>(static_cast<const double*>(X), ld, s->n, s->p, scale, rho, s->st);
+}
+
+void hamiltonian(ks_system* s, const void* X, int ldx, void* Y, int ldy, const double* veff,
+                 double scale, Partials* pt) {
+  if (s->f32)
+    launch_hx<float>(static_cast<const float*>(X), ldx, static_cast<float*>(Y), ldy, veff, s->vext,
+                     s->grid, s->p, scale, pt, s->st);
+  else
+    launch_hx<double>(static_cast<const double*>(X), ldx, static_cast<double*>(Y), ldy, veff,
+                      s->vext, s->grid, s->p, scale, pt, s->st);
+}
+
+void gram(ks_system* s, const void* A, const void* B, int mask) {
+  launch_gram(A, B, s->f32, s->p, s->n, s->p, mask, s->gram_part, s->gram_nchunks, s->st);
 }
 
 CgState* host_cg(ks_system* s) { return reinterpret_cast<CgState*>(s->host); }
@@ -363,10 +400,11 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
 int evaluate(ks_system* s, int idx, bool rho_ready, int bb_ref, int warm, bool want_gxd,
              bool want_gg, bool wait_hartree = true) {
   const double scale = s->f / s->grid.dV;
-  const double* Xs = s->X[idx];
+  (void)scale;
+  const void* Xs = s->X[idx];
   if (!rho_ready) {
     tbeg(s, KS_PH_DENSITY);
-    launch_density<double>(Xs, s->p, s->n, s->p, scale, s->rho, s->st);
+    density(s, Xs, s->p, s->rho);
     tend(s, KS_PH_DENSITY);
   }
   int rc = launch_check(s, "density");
@@ -381,20 +419,19 @@ int evaluate(ks_system* s, int idx, bool rho_ready, int bb_ref, int warm, bool w
 // Everything after the Hartree solve: exchange, Hamiltonian, Gram blocks, gradient,
 // reductions and the evaluation summary of slot idx.
 int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg) {
-  const double* Xs = s->X[idx];
+  const void* Xs = s->X[idx];
   Partials pt{s->spart, kPartStride};
   tbeg(s, KS_PH_XC);
   launch_xc(s->rho, s->vh[idx], s->vext, s->veff[idx], s->grid, s->use_h, s->use_x,
             s->use_h ? s->cg : nullptr, pt, s->st);
   tend(s, KS_PH_XC);
   tbeg(s, KS_PH_HAMILTONIAN);
-  launch_hx<double>(Xs, s->p, s->G[idx], s->p, s->veff[idx], s->vext, s->grid, s->p,
-                    2.0 * s->f, &pt, s->st);
+  hamiltonian(s, Xs, s->p, s->G[idx], s->p, s->veff[idx], 2.0 * s->f, &pt);
   tend(s, KS_PH_HAMILTONIAN);
   // Gram blocks of [X, G]: X^T X and X^T G (and G^T G for the Cayley system)
   const int mask1 = kGramAA | kGramAB | (want_gg ? kGramBB : 0);
   tbeg(s, KS_PH_GRAM);
-  launch_gram(Xs, s->G[idx], s->p, s->n, s->p, mask1, s->gram_part, s->gram_nchunks, s->st);
+  gram(s, Xs, s->G[idx], mask1);
   tend(s, KS_PH_GRAM);
   tbeg(s, KS_PH_SMALL);
   launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, mask1, s->gxg[idx], s->W, s->st);
@@ -410,6 +447,7 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
   ca.Dk = bb_ref >= 0 ? s->D[bb_ref] : s->D[idx];
   ca.pt = pt;
   ca.gram_part = fused ? s->gram_part : nullptr;
+  ca.f32 = s->f32;
   ca.ld = s->p;
   ca.n = s->n;
   ca.p = s->p;
@@ -419,7 +457,7 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
   const int mask2 = kGramAB | kGramBB;
   if (want_gxd && !fused) {
     tbeg(s, KS_PH_GRAM);
-    launch_gram(Xs, s->D[idx], s->p, s->n, s->p, mask2, s->gram_part, s->gram_nchunks, s->st);
+    gram(s, Xs, s->D[idx], mask2);
     tend(s, KS_PH_GRAM);
   }
   tbeg(s, KS_PH_SMALL);
@@ -635,8 +673,7 @@ int ks_read_timers(ks_system* s, ks_phase_times* out, int reset) {
 
 int ks_density(ks_system* s, const void* X, double* rho) {
   if (!s || !X || !rho) return fail(s, KS_E_INVAL, "null argument");
-  launch_density<double>(static_cast<const double*>(X), s->ld, s->n, s->p, s->f / s->grid.dV,
-                         rho, s->st);
+  density(s, X, s->ld, rho);
   int rc = launch_check(s, "density");
   return rc ? rc : hip_check(s, hipStreamSynchronize(s->st), "density sync");
 }
@@ -660,9 +697,7 @@ int ks_hartree_solve(ks_system* s, const double* rho, double* v_h, int warm, int
 int ks_apply_hamiltonian(ks_system* s, const void* X, void* Y, const double* v_eff) {
   if (!s || !X || !Y) return fail(s, KS_E_INVAL, "null argument");
   if (X == Y) return fail(s, KS_E_INVAL, "X and Y must differ");
-  launch_hx<double>(static_cast<const double*>(X), s->ld, static_cast<double*>(Y), s->ld,
-                    v_eff ? v_eff : s->veff[s->cur], s->vext, s->grid, s->p, 1.0, nullptr,
-                    s->st);
+  hamiltonian(s, X, s->ld, Y, s->ld, v_eff ? v_eff : s->veff[s->cur], 1.0, nullptr);
   int rc = launch_check(s, "hamiltonian");
   return rc ? rc : hip_check(s, hipStreamSynchronize(s->st), "hamiltonian sync");
 }
@@ -679,12 +714,10 @@ int ks_get_potentials(ks_system* s, double* v_ext, double* v_h, double* v_eff) {
 int ks_gram(ks_system* s, const void* Ain, const void* Bin, double* out) {
   if (!s || !Ain || !Bin || !out) return fail(s, KS_E_INVAL, "null argument");
   const int t = 1 - s->cur;
-  launch_copy_block<double>(s->X[t], s->p, static_cast<const double*>(Ain), s->ld, s->n, s->p,
-                            s->st);
-  launch_copy_block<double>(s->G[t], s->p, static_cast<const double*>(Bin), s->ld, s->n, s->p,
-                            s->st);
+  copy_block(s, s->X[t], s->p, Ain, s->ld);
+  copy_block(s, s->G[t], s->p, Bin, s->ld);
   const int all = kGramAA | kGramAB | kGramBB;
-  launch_gram(s->X[t], s->G[t], s->p, s->n, s->p, all, s->gram_part, s->gram_nchunks, s->st);
+  gram(s, s->X[t], s->G[t], all);
   launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, all, s->gxg[t], nullptr, s->st);
   launch_compact_gram(s->gxg[t], s->pp, s->p, out, s->st);
   int rc = launch_check(s, "gram");
@@ -694,15 +727,13 @@ int ks_gram(ks_system* s, const void* Ain, const void* Bin, double* out) {
 int ks_energy_grad(ks_system* s, const void* X, void* G, void* gradE, ks_energy* out) {
   if (!s || !X) return fail(s, KS_E_INVAL, "null argument");
   const int c = s->cur;
-  launch_copy_block<double>(s->X[c], s->p, static_cast<const double*>(X), s->ld, s->n, s->p,
-                            s->st);
+  copy_block(s, s->X[c], s->p, X, s->ld);
   int rc = evaluate(s, c, false, -1, c, false, false);
   if (rc) return rc;
   if (G)
-    launch_copy_block<double>(static_cast<double*>(G), s->ld, s->G[c], s->p, s->n, s->p, s->st);
+    copy_block(s, G, s->ld, s->G[c], s->p);
   if (gradE)
-    launch_copy_block<double>(static_cast<double*>(gradE), s->ld, s->D[c], s->p, s->n, s->p,
-                              s->st);
+    copy_block(s, gradE, s->ld, s->D[c], s->p);
   rc = launch_check(s, "energy_grad");
   if (rc) return rc;
   EvalOut* he = host_ev(s);
@@ -719,12 +750,10 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
   if (X_out == X || X_out == G) return fail(s, KS_E_INVAL, "X_out must not alias X or G");
   if (!std::isfinite(tau)) return fail(s, KS_E_INVAL, "tau must be finite");
   const int t = 1 - s->cur, c = s->cur;
-  launch_copy_block<double>(s->X[t], s->p, static_cast<const double*>(X), s->ld, s->n, s->p,
-                            s->st);
-  launch_copy_block<double>(s->G[t], s->p, static_cast<const double*>(G), s->ld, s->n, s->p,
-                            s->st);
+  copy_block(s, s->X[t], s->p, X, s->ld);
+  copy_block(s, s->G[t], s->p, G, s->ld);
   const int all = kGramAA | kGramAB | kGramBB;
-  launch_gram(s->X[t], s->G[t], s->p, s->n, s->p, all, s->gram_part, s->gram_nchunks, s->st);
+  gram(s, s->X[t], s->G[t], all);
   launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, all, s->gxg[t], s->W, s->st);
   launch_set_scalar(s->tau_user, tau, s->st);
   int* hstat = host_int(s);
@@ -736,8 +765,10 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
   ca.ld = s->p;
   ca.n = s->n;
   ca.p = s->p;
+  ca.f32 = s->f32;
   if (kind == KS_QR) {
     CombineArgs cd{};
+    cd.f32 = s->f32;
     cd.X = s->X[t];
     cd.A = s->W;
     cd.C0 = s->G[t];
@@ -747,7 +778,7 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
     cd.p = s->p;
     launch_combine(cd, s->st);
     const int m2 = kGramAB | kGramBB;
-    launch_gram(s->X[t], s->D[t], s->p, s->n, s->p, m2, s->gram_part, s->gram_nchunks, s->st);
+    gram(s, s->X[t], s->D[t], m2);
     launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, m2, s->gxd[t], nullptr, s->st);
     launch_qr_factor(s->gxg[t], s->gxd[t], s->p, s->pp, s->tau_user, s->A, s->B, s->work,
                      s->status, s->st);
@@ -762,7 +793,7 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
   ca.B = s->B;
   ca.out = s->D[c];
   launch_combine(ca, s->st);
-  launch_copy_block<double>(static_cast<double*>(X_out), s->ld, s->D[c], s->p, s->n, s->p, s->st);
+  copy_block(s, X_out, s->ld, s->D[c], s->p);
   int rc = launch_check(s, "retract");
   if (rc) return rc;
   rc = readback(s, hstat, s->status);
@@ -787,8 +818,7 @@ int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* 
   const bool qr = prm.retraction == KS_QR;
   s->cg_total = 0;
   int c = s->cur;
-  launch_copy_block<double>(s->X[c], s->p, static_cast<const double*>(X_inout), s->ld, s->n,
-                            s->p, s->st);
+  copy_block(s, s->X[c], s->p, X_inout, s->ld);
   launch_ls_reset(s->ls, s->st);
   int* hint = host_int(s);
   hint[1] = 0;
@@ -812,6 +842,7 @@ int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* 
     ca.out = s->X[t];
     ca.rho = s->rho;
     ca.rho_scale = s->f / s->grid.dV;
+    ca.f32 = s->f32;
     ca.ld = s->p;
     ca.n = s->n;
     ca.p = s->p;
@@ -862,8 +893,7 @@ int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* 
       s->cur = c;
     }
   }
-  launch_copy_block<double>(static_cast<double*>(X_inout), s->ld, s->X[c], s->p, s->n, s->p,
-                            s->st);
+  copy_block(s, X_inout, s->ld, s->X[c], s->p);
   rc = launch_check(s, "minimize");
   if (rc) return rc;
   EvalOut* he = host_ev(s);

@@ -160,22 +160,25 @@ constexpr int kGramAA = 1, kGramAB = 2, kGramBB = 4;  // product bits of a Gram 
 int gram_chunks(int n, int pp);
 size_t gram_part_doubles(int n, int pp);
 bool combine_fuses_gram(int p);
-void launch_gram(const double* A, const double* B, int ld, int n, int p, int mask,
+// A, B: n x ld blocks of float (f32) or double; products accumulate in FP64
+void launch_gram(const void* A, const void* B, bool f32, int ld, int n, int p, int mask,
                  double* partials, int nchunks, hipStream_t st);
 // out: [3][pp][pp]; products outside mask are zero; W (nullable) = -(A^T B)^T
 void launch_gram_reduce(const double* partials, int nchunks, int pp, int mask, double* out,
                         double* W, hipStream_t st);
 struct CombineArgs {
-  const double* X; const double* A;     // X (n x ld) times A (pp x pp)
-  const double* Y; const double* B;     // optional Y (n x ld) times B
-  const double* C0;                     // optional additive n x ld term
-  double* out;                          // n x ld
+  // orbital blocks are float when f32, else double; weights and sums are double
+  const void* X; const double* A;       // X (n x ld) times A (pp x pp)
+  const void* Y; const double* B;       // optional Y (n x ld) times B
+  const void* C0;                       // optional additive n x ld term
+  void* out;                            // n x ld
   double* rho; double rho_scale;        // optional density of out
   // optional BB/gradient epilogue: out is D_t; uses Xt (= X), Xk, Dk
-  const double* Xk; const double* Dk;
+  const void* Xk; const void* Dk;
   Partials pt;                          // slots SL_DD.. SL_YY (by value)
   double* gram_part;                    // optional partial Gram tiles X^T D, D^T D
   int ld, n, p;
+  bool f32;
 };
 void launch_combine(const CombineArgs& a, hipStream_t st);
 int combine_blocks(int n);

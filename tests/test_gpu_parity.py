@@ -460,3 +460,68 @@ def test_minimize_forced_line_search_exhaustion():
     r = sysg.ks_minimize(X, K.ks_default_params(rho1=0.999999, h_max=2, max_iter=6,
                                                 stagnation_tol=0.0))
     assert r.iters == 6 and r.backtracks >= 2
+
+
+# ------------------------------------------------------------------------------------------
+# FP32 storage mode: X, G, D stored in float, every product accumulated in FP64
+# ------------------------------------------------------------------------------------------
+
+def devf(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+
+
+def test_fp32_energy_grad_matches_oracle_on_rounded_input():
+    """Energies are computed in FP64 from the FP32 data, so they match the oracle applied to
+    the FP32-rounded X to FP64 accuracy; G and grad E are rounded to FP32 on store."""
+    K = ks()
+    spec = spec_small(p=6, seed=50)
+    X = synth.make_x0(spec, 4).astype(np.float32)
+    Xd = X.astype(np.float64)
+    sysg = K.system_from_spec(spec, precision=K.KS_PREC_FP32)
+    G = torch.zeros((spec.n, spec.p), dtype=torch.float32, device="cuda")
+    D = torch.zeros_like(G)
+    e = sysg.ks_energy_grad(devf(X), G, D)
+    orc = oracle_fd(spec)
+    en, Gr, _ = orc.energy_grad(Xd)
+    Dr = stiefel.manifold_grad(Xd, Gr)
+    for t in TERMS:
+        a, b = getattr(e, t), float(getattr(en, t))
+        assert abs(a - b) <= 1e-10 * max(abs(b), 1e-3), (t, a, b)
+    assert np.max(np.abs(host(G) - Gr)) <= 2e-7 * np.max(np.abs(Gr))
+    # D is formed in FP64 from the FP32 G (already rounded) and rounded once more
+    assert np.max(np.abs(host(D) - Dr)) <= 5e-7 * np.max(np.abs(Gr))
+    assert abs(e.orth_error - stiefel.orth_error(Xd)) < 1e-12
+
+
+@pytest.mark.parametrize("kind", ["qr", "wy"])
+def test_fp32_retract_matches_oracle_on_rounded_input(kind):
+    K = ks()
+    spec = spec_small(p=5, seed=51)
+    X = synth.make_x0(spec, 5).astype(np.float32)
+    orc = oracle_fd(spec)
+    _, G, _ = orc.energy_grad(X.astype(np.float64))
+    G = G.astype(np.float32)
+    sysg = K.system_from_spec(spec, precision=K.KS_PREC_FP32)
+    out = torch.zeros((spec.n, spec.p), dtype=torch.float32, device="cuda")
+    tau = 0.05
+    sysg.ks_retract(devf(X), devf(G), tau, K.KS_QR if kind == "qr" else K.KS_WY, out)
+    Xd, Gd = X.astype(np.float64), G.astype(np.float64)
+    ref = stiefel.retract_qr(Xd, Gd, tau) if kind == "qr" else stiefel.retract_wy(Xd, Gd, tau)
+    assert np.max(np.abs(host(out) - ref)) <= 2e-7 * np.max(np.abs(ref))
+
+
+def test_fp32_minimize_reaches_fp64_energy():
+    """The FP32-storage run ends within 1e-6 Ha of the FP64 oracle minimum."""
+    K = ks()
+    spec = synth.make_system(12, 12, 12, 0.6, 4, 2, seed=0, zrange=(2, 3), margin=2.0,
+                             min_spacing=1.0)
+    X0 = synth.make_x0(spec, 1)
+    sysg = K.system_from_spec(spec, precision=K.KS_PREC_FP32, hartree_solver=K.KS_HARTREE_PCG_FD)
+    X = devf(X0)
+    r = sysg.ks_minimize(X, K.ks_default_params(max_iter=4000))
+    orc = oracle_fd(spec)
+    ref = optm.minimize(orc.energy_grad, X0, optm.Params(eps_g=1e-8, stagnation_tol=0.0,
+                                                         max_iter=4000))
+    assert r.stop_reason in (K.KS_STOP_GRAD, K.KS_STOP_STAGNATION)
+    assert abs(r.energy - ref.E) <= 1e-6
+    assert r.terms.orth_error < 1e-5
