@@ -525,3 +525,19 @@ def test_fp32_minimize_reaches_fp64_energy():
     assert r.stop_reason in (K.KS_STOP_GRAD, K.KS_STOP_STAGNATION)
     assert abs(r.energy - ref.E) <= 1e-6
     assert r.terms.orth_error < 1e-5
+
+
+def test_minimize_c2_matches_oracle_reference():
+    """Config c2 (64^3, p = 32, 16 nuclei, FP64) with the Section 4.1 stopping rules: the
+    converged energy agrees with the stored oracle run to 1e-10 relative."""
+    K = ks()
+    gold = _golden("oracle_c2_s0_qr.txt")
+    if gold is None:
+        pytest.skip("oracle reference for c2 not generated")
+    spec = synth.make_config("c2", 0)
+    sysg = K.system_from_spec(spec, hartree_solver=K.KS_HARTREE_PCG_FD)
+    X = dev(synth.make_x0(spec, 0))
+    r = sysg.ks_minimize(X, K.ks_default_params())
+    assert r.stop_reason in (K.KS_STOP_GRAD, K.KS_STOP_STAGNATION)
+    assert abs(r.energy - gold["E"]) <= 1e-10 * abs(gold["E"])
+    assert r.terms.orth_error < 1e-12
