@@ -63,6 +63,79 @@ def cpu_baseline(spec, X0, gpu_iters, iters):
     }
 
 
+def serve_leg(ks, synth, n_req, slots, hbm_gib, fracs, precision, seed, check_n):
+    """Serving stream: n_req requests of mixed sizes through the library's server.
+
+    First all requests are submitted at t = 0 (saturated throughput), then the same
+    stream arrives as a Poisson process at each fraction of that throughput.  Latency is
+    completion minus arrival; service time is completion minus admission.
+    """
+    import numpy as np
+    prec = ks.KS_PREC_FP32 if precision == "fp32" else ks.KS_PREC_FP64
+    dt = np.float32 if precision == "fp32" else np.float64
+    prm = ks.ks_default_params()
+    base = synth.make_serving_stream(n_req=n_req, rate=0.0, seed=seed)
+    descs = [ks.desc_from_spec(r.spec, precision=prec, hartree_solver=ks.KS_HARTREE_PCG_FD)
+             for r in base]
+    x0s = [synth.make_x0(r.spec, r.seed).astype(dt) for r in base]
+    nbytes = int(hbm_gib * (1 << 30))
+
+    def pct(v, q):
+        v = sorted(v)
+        k = min(len(v) - 1, max(0, int(math.ceil(q / 100.0 * len(v))) - 1))
+        return v[k]
+
+    def run(arrivals):
+        sv = ks.KSServer(nbytes, slots)
+        t0 = time.perf_counter()
+        for i, d in enumerate(descs):
+            if arrivals is not None:
+                wait = arrivals[i] - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(wait)
+            sv.ks_server_submit(i, d, x0s[i], prm)
+        sv.ks_server_wait_idle()
+        el = time.perf_counter() - t0
+        done = sv.ks_server_poll(n_req + 1)
+        sv.close()
+        ok = [c for c in done if c["status"] == ks.KS_OK and
+              c["result"].stop_reason in (ks.KS_STOP_GRAD, ks.KS_STOP_STAGNATION)]
+        lat = [1e3 * (c["t_done"] - c["t_submit"]) for c in done]
+        svc = [1e3 * (c["t_done"] - c["t_admit"]) for c in done]
+        return {"solves_per_s": round(len(ok) / el, 3), "seconds": round(el, 3),
+                "converged": len(ok), "requests": len(done),
+                "p50_ms": round(pct(lat, 50), 2), "p99_ms": round(pct(lat, 99), 2),
+                "service_p50_ms": round(pct(svc, 50), 2), "service_p99_ms": round(pct(svc, 99), 2),
+                "iters_p50": int(pct([c["result"].iters for c in done], 50))}, done
+
+    sat, done_sat = run(None)
+    print(f"# serve saturated: {sat}", file=sys.stderr, flush=True)
+    out = {"requests": n_req, "slots": slots, "hbm_budget_GiB": hbm_gib,
+           "precision": precision, "saturated": sat}
+    rate_sat = sat["solves_per_s"]
+    for fr in fracs:
+        rate = fr * rate_sat
+        stream = synth.make_serving_stream(n_req=n_req, rate=rate, seed=seed)
+        res, _ = run([r.arrival for r in stream])
+        res["rate_per_s"] = round(rate, 3)
+        print(f"# serve at {fr} x saturated: {res}", file=sys.stderr, flush=True)
+        out[f"poisson_{fr}"] = res
+    if check_n > 0 and precision == "fp32":
+        # error of the FP32 results against FP64 runs of the same requests
+        e32 = {c["id"]: c["result"].energy for c in done_sat}
+        sv = ks.KSServer(nbytes, slots)
+        for i in range(min(check_n, n_req)):
+            d64 = ks.desc_from_spec(base[i].spec, hartree_solver=ks.KS_HARTREE_PCG_FD)
+            sv.ks_server_submit(i, d64, synth.make_x0(base[i].spec, base[i].seed), prm)
+        sv.ks_server_wait_idle()
+        d = [abs(e32[c["id"]] - c["result"].energy) for c in sv.ks_server_poll(n_req + 1)]
+        sv.close()
+        out["fp32_vs_fp64"] = {"requests": len(d), "max_abs_Ha": max(d),
+                               "median_abs_Ha": float(np.median(d)),
+                               "within_1e-6_Ha": sum(1 for v in d if v <= 1e-6)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +148,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-steps", type=int, default=3,
                     help="timed solves of the FP32-storage leg (0 = skip)")
+    ap.add_argument("--serve-requests", type=int, default=512,
+                    help="requests in the serving leg (0 = skip)")
+    ap.add_argument("--serve-slots", type=int, default=4,
+                    help="concurrent requests (the device has 4 hardware queues per process)")
+    ap.add_argument("--serve-hbm-gib", type=float, default=8.0)
+    ap.add_argument("--serve-precision", choices=["fp32", "fp64"], default="fp64",
+                    help="storage precision of the served requests (FP32 reaches the float "
+                         "floor of X before the FP64 stopping rules and then exhausts line "
+                         "searches; its error against FP64 is reported when selected)")
+    ap.add_argument("--serve-fracs", default="0.7,0.9")
+    ap.add_argument("--serve-check", type=int, default=32,
+                    help="requests re-run in FP64 to state the FP32 error")
     ap.add_argument("--max-iter", type=int, default=10000,
                     help="iteration cap (profiling runs only; the metric needs the default)")
     args = ap.parse_args()
@@ -205,6 +290,11 @@ def main():
                                     round(1.0 / (el32 / args.fp32_steps + tpol), 4)}}
         print(f"# fp32: {r32.iters} it, E={r32.energy:.12f}, |E-E64|={abs(r32.energy - e64):.2e}, "
               f"{1e3 * el32 / args.fp32_steps:.1f} ms/solve", file=sys.stderr, flush=True)
+    serve = None
+    if args.serve_requests > 0:
+        fr = [float(v) for v in args.serve_fracs.split(",") if v]
+        serve = serve_leg(ks, synth, args.serve_requests, args.serve_slots, args.serve_hbm_gib,
+                          fr, args.serve_precision, args.seed, args.serve_check)
     cpu = None
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
@@ -235,6 +325,7 @@ def main():
         "grad_norm": results[-1].grad_norm if results else None,
         "spmm_GBps": spmm,
         "fp32": fp32,
+        "serving": serve,
         "phases": phase_out,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -240,6 +240,57 @@ int ks_get_potentials(ks_system* s, double* v_ext, double* v_h, double* v_eff);
  * p x p each) = [A^T A, A^T B, B^T B].  The tall-skinny products of Section 3. */
 int ks_gram(ks_system* s, const void* A, const void* B, double* out);
 
+/* ---- serving ---------------------------------------------------------------------------
+ * A server solves independent minimisation requests concurrently on one GPU.  It owns no
+ * device memory: requests are admitted in arrival order into first-fit regions of the
+ * caller's workspace, each sized by ks_workspace_bytes() plus the request's orbital block
+ * (admission by HBM footprint).  n_slots worker threads each drive one request at a time
+ * on a stream of their own, so requests that arrive while others run are admitted as
+ * slots and memory free up and their kernels overlap on the device.  A request's result
+ * does not depend on its co-tenants (same kernels, same reduction order as running it
+ * alone with ks_minimize). */
+typedef struct ks_server ks_server;
+
+typedef struct ks_request {
+  int id;                   /* caller's tag, echoed in the completion                     */
+  ks_system_desc desc;      /* its host arrays (R, Z, v_ext_override) are copied at submit */
+  const void* X0;           /* host n x p start block in the desc's precision; the server
+                               keeps every orbital block dense (desc.ld is ignored)       */
+  void* X_out;              /* host n x p result block, or NULL                           */
+  ks_opt_params params;     /* Alg. 3 parameters                                          */
+} ks_request;
+
+typedef struct ks_completion {
+  int id;
+  int status;               /* ks_minimize's return code, or the admission error          */
+  ks_result result;
+  double t_submit, t_admit, t_done;  /* seconds since ks_server_create                    */
+  size_t bytes;             /* device bytes the request held while it ran                 */
+} ks_completion;
+
+/* Creates a server over the caller's device workspace (256-byte aligned) with n_slots
+ * (1..64) concurrent workers on the current device.  Errors: KS_E_INVAL, KS_E_HIP. */
+int ks_server_create(void* dev_workspace, size_t ws_bytes, int n_slots, ks_server** out);
+
+/* Queues a request (copies X0 and the descriptor's host arrays before returning; X_out
+ * must stay valid until the request's completion has been polled).  A request larger
+ * than the whole workspace completes at once with status KS_E_NOMEM.  Errors: KS_E_INVAL
+ * (null arguments, or a descriptor ks_workspace_bytes rejects: ks_last_error(NULL) on
+ * the calling thread says why). */
+int ks_server_submit(ks_server* sv, const ks_request* rq);
+
+/* Moves up to max finished requests into out (host); *n_out receives the count. */
+int ks_server_poll(ks_server* sv, ks_completion* out, int max, int* n_out);
+
+/* Blocks until every submitted request has completed. */
+int ks_server_wait_idle(ks_server* sv);
+
+/* Number of requests queued and running. */
+int ks_server_pending(ks_server* sv);
+
+/* Stops the workers after the running requests finish; queued requests are dropped. */
+void ks_server_destroy(ks_server* sv);
+
 /* ---- instrumentation ------------------------------------------------------------------ */
 
 /* Turns the phase timers on (on != 0) or off.  While on, the library records a pair of

@@ -379,12 +379,12 @@ void launch_combine_t(const CombineArgs& a, hipStream_t st) {
   constexpr int kPP = kT * 16;
   const size_t lds = (size_t)(kHasY ? 2 : 1) * kPP * kPP * sizeof(double) +
                      (kGram2 ? (size_t)3 * 4 * 64 * sizeof(double) : 0);
-  static bool attr = false;
-  if (!attr) {
-    set_lds_attr(
-        reinterpret_cast<const void*>(k_combine<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2>), lds);
-    attr = true;
-  }
+  // function-local static initialisation runs once even when several host threads launch
+  static const bool attr = (set_lds_attr(reinterpret_cast<const void*>(
+                                k_combine<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2>),
+                                lds),
+                            true);
+  (void)attr;
   const int nb = kGram2 ? combine_blocks_gram(a.n) : combine_blocks(a.n);
   hipLaunchKernelGGL((k_combine<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2>), dim3(nb), dim3(256),
                      lds, st, a);

@@ -405,9 +405,13 @@ void launch_hartree_init(const double* rho, const double* x0, double* x, double*
 }
 
 namespace {
+constexpr size_t kFdLdsCap = 150 * 1024;  // stay inside the 160 KiB of LDS of a CU
+
+// Raises the dynamic-LDS limit of a kernel to the cap.  The value does not depend on the
+// grid, so concurrent callers on several host threads all set the same value.
 void set_lds(const void* k, size_t bytes) {
   if (bytes > 32768)
-    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFdLdsCap);
 }
 }  // namespace
 
@@ -430,7 +434,7 @@ void launch_fd_apply(const double* r, double* z, const FdOps& fd, Grid g, const 
   const size_t lps = lp + (size_t)(nx * nx + ny * ny) * sizeof(double);
   const size_t lzb = nzp * 64 * sizeof(double);
   const size_t lzs = lzb + (size_t)nz * nz * sizeof(double);
-  const size_t cap = 150 * 1024;  // stay inside the 160 KiB of LDS of a CU
+  const size_t cap = kFdLdsCap;
   const int threads = kFdWaves * kWave;
   auto plane = [&](const double* in, double* out, const double* rr, double* pt) {
     if (lps <= cap) {

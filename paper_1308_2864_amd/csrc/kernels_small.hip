@@ -504,24 +504,28 @@ __global__ void k_ls_judge(const EvalOut* ev, LsState* ls, LsParams prm, const C
   *ls = s;
 }
 
+size_t query_lds_limit() {
+  int dev = 0, v = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    v = 65536;
+  return (size_t)v;
+}
+
 size_t dyn_lds_limit() {
-  static size_t lim = 0;
-  if (lim == 0) {
-    int dev = 0, v = 0;
-    (void)hipGetDevice(&dev);
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-      v = 65536;
-    lim = (size_t)v;
-  }
+  static const size_t lim = query_lds_limit();  // initialised once, thread-safe
   return lim;
 }
 
 template <typename K>
 bool prepare_lds(K kernel, size_t bytes) {
   // leave room for the kernel's static shared arrays
+  // the limit set is the same for every size, so concurrent host threads agree on it
   if (bytes + 8192 > dyn_lds_limit()) return false;
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (bytes > 32768)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(dyn_lds_limit() - 8192));
   return true;
 }
 

@@ -79,6 +79,17 @@ class ks_result(C.Structure):
     ]
 
 
+class ks_request(C.Structure):
+    _fields_ = [("id", C.c_int), ("desc", ks_system_desc), ("X0", C.c_void_p),
+                ("X_out", C.c_void_p), ("params", ks_opt_params)]
+
+
+class ks_completion(C.Structure):
+    _fields_ = [("id", C.c_int), ("status", C.c_int), ("result", ks_result),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
+                ("bytes", C.c_size_t)]
+
+
 class ks_phase_times(C.Structure):
     _fields_ = [("ms", C.c_double * 8), ("count", C.c_longlong * 8)]
 
@@ -108,6 +119,12 @@ def _load():
         "ks_gram": (ip, [vp, vp, vp, vp]),
         "ks_enable_timers": (ip, [vp, ip]),
         "ks_read_timers": (ip, [vp, C.POINTER(ks_phase_times), ip]),
+        "ks_server_create": (ip, [vp, C.c_size_t, ip, C.POINTER(vp)]),
+        "ks_server_submit": (ip, [vp, C.POINTER(ks_request)]),
+        "ks_server_poll": (ip, [vp, C.POINTER(ks_completion), ip, C.POINTER(ip)]),
+        "ks_server_wait_idle": (ip, [vp]),
+        "ks_server_pending": (ip, [vp]),
+        "ks_server_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -255,12 +272,96 @@ class KSSystem:
         return t.as_dict()
 
 
-def system_from_spec(spec, **kw) -> KSSystem:
-    """Creates a KSSystem for a ``synth.SystemSpec``."""
+def desc_from_spec(spec, **kw):
+    """A ks_system_desc for a ``synth.SystemSpec`` (keyword arguments go to make_desc)."""
     terms = (KS_TERM_EXT if spec.ext else 0) | (KS_TERM_HARTREE if spec.hartree else 0) | \
             (KS_TERM_XC if spec.xc else 0)
     dkw = dict(f=spec.f, rc=spec.rc, terms=terms)
-    device = kw.pop("device", "cuda")
     dkw.update(kw)
-    desc = make_desc(spec.nx, spec.ny, spec.nz, spec.h, spec.lo, spec.p, spec.R, spec.Z, **dkw)
-    return KSSystem(desc, device=device)
+    return make_desc(spec.nx, spec.ny, spec.nz, spec.h, spec.lo, spec.p, spec.R, spec.Z, **dkw)
+
+
+def system_from_spec(spec, **kw) -> KSSystem:
+    """Creates a KSSystem for a ``synth.SystemSpec``."""
+    device = kw.pop("device", "cuda")
+    return KSSystem(desc_from_spec(spec, **kw), device=device)
+
+
+def ks_request_bytes(desc) -> int:
+    """Device bytes a server request for desc holds while it runs (256-byte regions)."""
+    desc = ks_system_desc.from_buffer_copy(desc)
+    desc.ld = 0
+    ws = ks_workspace_bytes(desc)
+    if ws == 0:
+        raise KSError(KS_E_INVAL, lib.ks_last_error(None).decode())
+    es = 4 if desc.precision == KS_PREC_FP32 else 8
+    x = desc.nx * desc.ny * desc.nz * desc.p * es  # the server keeps blocks dense
+    return (ws + 255) // 256 * 256 + (x + 255) // 256 * 256
+
+
+class KSServer:
+    """ks_server_* over a torch-owned device workspace of ``nbytes``.
+
+    ``submit`` takes a descriptor, a host start block (n x p, float64 or float32 to match
+    the descriptor's precision) and optional parameters; the result block, when asked
+    for, is written into a host array this object keeps alive until its completion has
+    been polled.
+    """
+
+    def __init__(self, nbytes, n_slots, device="cuda"):
+        import torch
+        self.device = torch.device(device)
+        self.workspace = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize(self.device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        h = C.c_void_p()
+        _check(lib.ks_server_create(C.c_void_p(base + off), int(nbytes), int(n_slots),
+                                    C.byref(h)))
+        self.h = h
+        self._out = {}
+
+    def ks_server_submit(self, rid, desc, X0, params=None, want_X=False):
+        dt = np.float32 if desc.precision == KS_PREC_FP32 else np.float64
+        X0 = np.ascontiguousarray(X0, dtype=dt)
+        n = desc.nx * desc.ny * desc.nz
+        if X0.shape != (n, desc.p):
+            raise ValueError(f"X0 must be {n} x {desc.p}")
+        rq = ks_request()
+        rq.id = int(rid)
+        rq.desc = desc
+        rq.X0 = X0.ctypes.data
+        if want_X:
+            out = np.empty_like(X0)
+            self._out[int(rid)] = out
+            rq.X_out = out.ctypes.data
+        rq.params = params if params is not None else ks_default_params()
+        _check(lib.ks_server_submit(self.h, C.byref(rq)))
+
+    def ks_server_poll(self, max_n=1024):
+        buf = (ks_completion * max_n)()
+        k = C.c_int()
+        _check(lib.ks_server_poll(self.h, buf, int(max_n), C.byref(k)))
+        out = []
+        for c in buf[:k.value]:
+            out.append(dict(id=c.id, status=c.status, result=c.result, t_submit=c.t_submit,
+                            t_admit=c.t_admit, t_done=c.t_done, bytes=int(c.bytes),
+                            X=self._out.pop(c.id, None)))
+        return out
+
+    def ks_server_wait_idle(self):
+        _check(lib.ks_server_wait_idle(self.h))
+
+    def ks_server_pending(self) -> int:
+        return int(lib.ks_server_pending(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.ks_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -78,3 +78,28 @@ def test_create_rejects_small_or_misaligned_workspace_without_a_device():
     assert ks.lib.ks_create_system(C.byref(d), C.c_void_p((1 << 20) + 8), need, None,
                                    C.byref(h)) == ks.KS_E_INVAL
     assert ks.lib.ks_create_system(C.byref(d), None, need, None, C.byref(h)) == ks.KS_E_INVAL
+
+
+def test_server_rejects_bad_arguments_without_a_device():
+    from paper_1308_2864_amd import ks
+    h = C.c_void_p()
+    for ws, nb, slots in ((None, 1 << 20, 2), (1 << 20, 0, 2), (1 << 20, 1 << 20, 0),
+                          (1 << 20, 1 << 20, 65), ((1 << 20) + 8, 1 << 20, 2)):
+        assert ks.lib.ks_server_create(C.c_void_p(ws) if ws else None, nb, slots,
+                                       C.byref(h)) == ks.KS_E_INVAL
+    assert ks.lib.ks_server_submit(None, None) == ks.KS_E_INVAL
+    k = C.c_int()
+    assert ks.lib.ks_server_poll(None, None, 0, C.byref(k)) == ks.KS_E_INVAL
+    assert ks.lib.ks_server_wait_idle(None) == ks.KS_E_INVAL
+    assert ks.lib.ks_server_pending(None) == 0
+    ks.lib.ks_server_destroy(None)
+
+
+def test_request_footprint_covers_system_and_orbitals():
+    from paper_1308_2864_amd import ks
+    for prec, es in ((ks.KS_PREC_FP64, 8), (ks.KS_PREC_FP32, 4)):
+        d = ks.make_desc(16, 16, 16, 16 / 17, (-8, -8, -8), 6, [[0, 0, 0]], [2],
+                         precision=prec)
+        nb = ks.ks_request_bytes(d)
+        assert nb >= ks.ks_workspace_bytes(d) + 16 ** 3 * 6 * es
+        assert nb % 256 == 0

@@ -1,0 +1,122 @@
+"""Serving runtime (ks_server_*): admission by HBM footprint, overlap of concurrent
+requests, and results that do not depend on what else runs.
+
+Each request is an independent run of Alg. 3.  The server runs it with the same kernels
+and reduction order as a lone ks_minimize call, so the bar for "alone vs in the mix" is
+bitwise equality of the energy and of the returned orbital block.
+"""
+import numpy as np
+import pytest
+
+from paper_1308_2864_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def ks():
+    from paper_1308_2864_amd import ks as _ks
+    return _ks
+
+
+def _requests(n_req, seed=3, sides=(16, 24), p_range=(2, 12), m_range=(1, 6)):
+    return synth.make_serving_stream(n_req=n_req, rate=0.0, seed=seed, sides=sides,
+                                     p_range=p_range, m_range=m_range)
+
+
+def _alone(K, rq, precision, prm):
+    spec = rq.spec
+    sysg = K.system_from_spec(spec, precision=precision, hartree_solver=K.KS_HARTREE_PCG_FD)
+    dt = torch.float32 if precision == K.KS_PREC_FP32 else torch.float64
+    X = torch.tensor(synth.make_x0(spec, rq.seed), dtype=dt, device="cuda")
+    r = sysg.ks_minimize(X, prm)
+    torch.cuda.synchronize()
+    out = X.cpu().numpy()
+    sysg.close()
+    return r, out
+
+
+def _run_server(K, reqs, precision, prm, nbytes, slots):
+    sv = K.KSServer(nbytes, slots)
+    dt = np.float32 if precision == K.KS_PREC_FP32 else np.float64
+    for rq in reqs:
+        desc = K.desc_from_spec(rq.spec, precision=precision, hartree_solver=K.KS_HARTREE_PCG_FD)
+        sv.ks_server_submit(rq.rid, desc, synth.make_x0(rq.spec, rq.seed).astype(dt), prm,
+                            want_X=True)
+    sv.ks_server_wait_idle()
+    done = {c["id"]: c for c in sv.ks_server_poll()}
+    assert sv.ks_server_pending() == 0
+    sv.close()
+    return done
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_server_alone_vs_mix_bitwise(precision):
+    """Eight requests of mixed grid sizes and orbital counts run four at a time: every
+    energy, iteration count and orbital block equals the lone ks_minimize run bit for bit."""
+    K = ks()
+    prec = K.KS_PREC_FP32 if precision == "fp32" else K.KS_PREC_FP64
+    prm = K.ks_default_params(max_iter=150)
+    reqs = _requests(8)
+    total = sum(K.ks_request_bytes(K.desc_from_spec(r.spec, precision=prec,
+                                                    hartree_solver=K.KS_HARTREE_PCG_FD))
+                for r in reqs)
+    done = _run_server(K, reqs, prec, prm, total, 4)
+    assert sorted(done) == [r.rid for r in reqs]
+    for rq in reqs:
+        c = done[rq.rid]
+        assert c["status"] in (K.KS_OK, K.KS_E_NOT_CONVERGED), (rq.rid, c["status"])
+        r, X = _alone(K, rq, prec, prm)
+        assert c["result"].iters == r.iters, rq.spec.name
+        assert c["result"].energy == r.energy, rq.spec.name
+        assert np.array_equal(c["X"], X), rq.spec.name
+    # with four slots and room for every request, some requests ran at the same time
+    iv = sorted((c["t_admit"], c["t_done"]) for c in done.values())
+    overlap = any(iv[i + 1][0] < iv[i][1] for i in range(len(iv) - 1))
+    assert overlap
+
+
+def test_server_admission_by_footprint():
+    """A budget smaller than two systems runs them one after the other; a request larger
+    than the whole budget completes at once with KS_E_NOMEM; the rest are unaffected."""
+    K = ks()
+    prm = K.ks_default_params(max_iter=40)
+    reqs = _requests(3, seed=5, sides=(16,), p_range=(4, 4), m_range=(2, 2))
+    descs = [K.desc_from_spec(r.spec, hartree_solver=K.KS_HARTREE_PCG_FD) for r in reqs]
+    one = max(K.ks_request_bytes(d) for d in descs)
+    big = synth.make_system(40, 40, 40, 16.0 / 41, 8, 2, seed=1, cfg="c5", lo=(-8.0,) * 3,
+                            margin=3.0)
+    sv = K.KSServer(int(1.5 * one), 4)
+    for rq, d in zip(reqs, descs):
+        sv.ks_server_submit(rq.rid, d, synth.make_x0(rq.spec, rq.seed), prm)
+    sv.ks_server_submit(99, K.desc_from_spec(big, hartree_solver=K.KS_HARTREE_PCG_FD),
+                        synth.make_x0(big, 1), prm)
+    sv.ks_server_wait_idle()
+    done = {c["id"]: c for c in sv.ks_server_poll()}
+    sv.close()
+    assert done[99]["status"] == K.KS_E_NOMEM
+    iv = sorted((done[r.rid]["t_admit"], done[r.rid]["t_done"]) for r in reqs)
+    for rq in reqs:
+        assert done[rq.rid]["status"] in (K.KS_OK, K.KS_E_NOT_CONVERGED)
+        assert done[rq.rid]["result"].iters > 0
+    # strictly one at a time, in arrival order
+    for a, b in zip(iv, iv[1:]):
+        assert b[0] >= a[1]
+    assert [done[r.rid]["t_admit"] for r in reqs] == sorted(done[r.rid]["t_admit"] for r in reqs)
+
+
+def test_server_poll_empty_and_destroy_with_queue():
+    """Polling an idle server returns nothing; destroying a server with queued requests
+    returns once the running ones finish."""
+    K = ks()
+    prm = K.ks_default_params(max_iter=20)
+    reqs = _requests(4, seed=7, sides=(16,), p_range=(2, 4))
+    descs = [K.desc_from_spec(r.spec) for r in reqs]
+    one = max(K.ks_request_bytes(d) for d in descs)
+    sv = K.KSServer(one, 1)
+    assert sv.ks_server_poll() == []
+    for rq, d in zip(reqs, descs):
+        sv.ks_server_submit(rq.rid, d, synth.make_x0(rq.spec, rq.seed), prm)
+    sv.close()
+    torch.cuda.synchronize()
