@@ -22,3 +22,10 @@ def box_energy_closed_form(nx, ny, nz, h, p, f=2.0):
     lam = (ev[0][None, None, :] + ev[1][None, :, None] + ev[2][:, None, None]).ravel()
     lam.sort()
     return 0.5 * f * float(lam[:p].sum()), lam
+
+
+def oracle_q1(spec, **kw):
+    from oracle.fe import KSSystemQ1
+    args = dict(f=spec.f, rc=spec.rc, ext=spec.ext, hartree=spec.hartree, xc=spec.xc)
+    args.update(kw)
+    return KSSystemQ1(spec.nx, spec.ny, spec.nz, spec.h, spec.lo, spec.p, spec.R, spec.Z, **args)
