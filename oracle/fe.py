@@ -87,7 +87,7 @@ class KSSystemQ1:
         self.f = float(f)
         self.h3 = self.grid.h ** 3
         self.A, self.B = q1_matrices(nx, ny, nz, h)
-        self._Blu = spla.splu(self.B.tocsc())
+        self._Blu = None  # sparse LU of B, built on the first mass solve
         R = np.asarray(R, dtype=np.float64).reshape(-1, 3)
         Z = np.asarray(Z, dtype=np.float64).ravel()
         self.use_hartree, self.use_xc = bool(hartree), bool(xc)
@@ -109,6 +109,8 @@ class KSSystemQ1:
 
     def mass_solve(self, G):
         """B^{-1} G (sparse LU of B)."""
+        if self._Blu is None:
+            self._Blu = spla.splu(self.B.tocsc())
         return self._Blu.solve(np.asarray(G, dtype=np.float64))
 
     def hartree_cg(self, rho, v0=None):

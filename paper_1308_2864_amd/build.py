@@ -18,7 +18,8 @@ OUT_DIR = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libks.so")
 
 SOURCES = ["ks_api.hip", "kernels_grid.hip", "kernels_poisson.hip", "kernels_dense.hip",
-           "kernels_small.hip", "ks_server.hip"]
+           "kernels_small.hip", "kernels_fe.hip",
+           "ks_server.hip"]
 
 ARCH = os.environ.get("KS_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
@@ -50,7 +51,7 @@ def _compile(src, verbose):
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
-    with concurrent.futures.ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         results = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     for _, warn in results:
         if warn and verbose:

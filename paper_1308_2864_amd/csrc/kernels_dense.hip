@@ -176,10 +176,10 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
   }
   red[sl][cl] = s;
   __syncthreads();
-  if (cl == 0 && e < 3 * per) {
+  // products outside the mask are left untouched in out
+  if (cl == 0 && e < 3 * per && live) {
     double t = 0.0;
     for (int c = 0; c < 16; ++c) t += red[sl][c];
-    t = live ? t : 0.0;
     out[e] = t;
     if (W && prod == 1) W[j * pp + i] = -t;
   }

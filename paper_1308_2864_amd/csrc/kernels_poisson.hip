@@ -12,6 +12,11 @@
 //    a dense N x N contraction along one axis.  With it the conjugate-gradient
 //    iteration converges in one or two steps.
 //
+// The finite-element form runs the same two solvers on A v = 4 pi h^3 rho with the Q1
+// stiffness stencil: A = K x M x M + M x K x M + M x M x K, and K, M share the sine
+// eigenvectors, so the preconditioner is exact there too with the divisor
+// lx my mz + mx ly mz + mx my lz.
+//
 // Reductions are fixed order: each grid kernel writes one partial per block and a
 // one-block kernel finishes the sum and updates the scalars, so there are no grid-wide
 // fences and results are reproducible bit for bit.
@@ -39,17 +44,39 @@ __device__ inline void range_of(int n, int lb, int nb, int* beg, int* end) {
   *end = (int)(e < n ? e : n);
 }
 
-__device__ inline double lap7(const double* __restrict__ u, int g, int i, int j, int k,
-                              const Grid& gr) {
-  double nb = 0.0;
-  if (i > 0) nb += u[g - 1];
-  if (i < gr.nx - 1) nb += u[g + 1];
-  if (j > 0) nb += u[g - gr.nx];
-  if (j < gr.ny - 1) nb += u[g + gr.nx];
-  const int sz = gr.nx * gr.ny;
-  if (k > 0) nb += u[g - sz];
-  if (k < gr.nz - 1) nb += u[g + sz];
-  return (6.0 * u[g] - nb) * gr.inv_h2;
+// (Op u)_g for u = z + beta po (po may be null): the 7-point -Laplacian_h, or for finite
+// elements the Q1 stiffness stencil (centre 8h/3, edges -h/6, corners -h/12, faces 0).
+__device__ inline double op_apply(const double* __restrict__ z, const double* __restrict__ po,
+                                  double beta, int g, int i, int j, int k, const Grid& gr) {
+  const int sy = gr.nx, sz = gr.nx * gr.ny;
+  auto u = [&](int o) { return po ? z[g + o] + beta * po[g + o] : z[g + o]; };
+  if (!gr.q1) {
+    double nb = 0.0;
+    if (i > 0) nb += u(-1);
+    if (i < gr.nx - 1) nb += u(1);
+    if (j > 0) nb += u(-sy);
+    if (j < gr.ny - 1) nb += u(sy);
+    if (k > 0) nb += u(-sz);
+    if (k < gr.nz - 1) nb += u(sz);
+    return (6.0 * u(0) - nb) * gr.inv_h2;
+  }
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz) {
+    if (k + dz < 0 || k + dz >= gr.nz) continue;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      if (j + dy < 0 || j + dy >= gr.ny) continue;
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        if (i + dx < 0 || i + dx >= gr.nx) continue;
+        const int cls = (dx != 0) + (dy != 0) + (dz != 0);
+        if (cls == 1) continue;
+        s[cls] += u(dz * sz + dy * sy + dx);
+      }
+    }
+  }
+  return (8.0 * gr.h / 3.0) * s[0] - (gr.h / 6.0) * s[2] - (gr.h / 12.0) * s[3];
 }
 
 // part layout: [4][kCgBlocksMax]
@@ -80,8 +107,8 @@ __global__ void k_init(const double* __restrict__ rho, const double* __restrict_
   double rr = 0.0, bb = 0.0;
   for (int g = beg + threadIdx.x; g < end; g += blockDim.x) {
     const int i = g % gr.nx, j = (g / gr.nx) % gr.ny, k = g / (gr.nx * gr.ny);
-    const double b = 4.0 * kPi * rho[g];
-    const double ri = x0 ? b - lap7(x0, g, i, j, k, gr) : b;
+    const double b = 4.0 * kPi * gr.rhs_scale * rho[g];
+    const double ri = x0 ? b - op_apply(x0, nullptr, 0.0, g, i, j, k, gr) : b;
     x[g] = x0 ? x0[g] : 0.0;
     r[g] = ri;
     p0[g] = 0.0;
@@ -123,14 +150,7 @@ __global__ void k_dir(const double* __restrict__ z, const double* __restrict__ p
   for (int g = beg + threadIdx.x; g < end; g += blockDim.x) {
     const int i = g % gr.nx, j = (g / gr.nx) % gr.ny, k = g / sz;
     const double pc = z[g] + beta * po[g];
-    double nb = 0.0;
-    if (i > 0) nb += z[g - 1] + beta * po[g - 1];
-    if (i < gr.nx - 1) nb += z[g + 1] + beta * po[g + 1];
-    if (j > 0) nb += z[g - gr.nx] + beta * po[g - gr.nx];
-    if (j < gr.ny - 1) nb += z[g + gr.nx] + beta * po[g + gr.nx];
-    if (k > 0) nb += z[g - sz] + beta * po[g - sz];
-    if (k < gr.nz - 1) nb += z[g + sz] + beta * po[g + sz];
-    const double qq = (6.0 * pc - nb) * gr.inv_h2;
+    const double qq = op_apply(z, po, beta, g, i, j, k, gr);
     pn[g] = pc;
     q[g] = qq;
     pq += pc * qq;
@@ -197,14 +217,23 @@ __global__ void k_fin_rz(const double* __restrict__ part, int nb, CgState* cs) {
 
 // ---- fast-diagonalisation preconditioner --------------------------------------------
 
-// S (N x N) and lambda (N) for one axis.
-__global__ void k_fd_setup(double* __restrict__ S, double* __restrict__ lam, int N, double h) {
+// S (N x N), the operator eigenvalues lam (N) and the mass eigenvalues mu (N) of one
+// axis.  Differences: lam = (2 - 2 cos t)/h^2, mu = 1.  Q1 elements: the 1D stiffness
+// (1/h) tridiag(-1, 2, -1) and mass (h/6) tridiag(1, 4, 1) share the sine eigenvectors,
+// lam = (2/h)(1 - cos t), mu = (h/3)(2 + cos t); then A = S3 diag(lx my mz + mx ly mz +
+// mx my lz) S3.
+__global__ void k_fd_setup(double* __restrict__ S, double* __restrict__ lam,
+                           double* __restrict__ mu, int N, double h, int q1) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e < N * N) {
     const int j = e / N, m = e % N;
     S[e] = sqrt(2.0 / (N + 1)) * sin(kPi * (double)((j + 1) * (m + 1)) / (double)(N + 1));
   }
-  if (e < N) lam[e] = (2.0 - 2.0 * cos(kPi * (double)(e + 1) / (double)(N + 1))) / (h * h);
+  if (e < N) {
+    const double c = cos(kPi * (double)(e + 1) / (double)(N + 1));
+    lam[e] = q1 ? (2.0 / h) * (1.0 - c) : (2.0 - 2.0 * c) / (h * h);
+    mu[e] = q1 ? (h / 3.0) * (2.0 + c) : 1.0;
+  }
 }
 
 // The sine-transform contractions run on the FP64 matrix cores (v_mfma_f64_16x16x4f64):
@@ -319,7 +348,10 @@ __global__ __launch_bounds__(512) void k_fd_z(double* __restrict__ u,
                                               const double* __restrict__ Szg,
                                               const double* __restrict__ lx,
                                               const double* __restrict__ ly,
-                                              const double* __restrict__ lz, int nx, int ny,
+                                              const double* __restrict__ lz,
+                                              const double* __restrict__ mx,
+                                              const double* __restrict__ my,
+                                              const double* __restrict__ mz, int nx, int ny,
                                               int nz, const CgState* cs) {
   extern __shared__ double A[];  // nzp x 64 (then S_z when it fits)
   if (cs->done) return;
@@ -349,13 +381,23 @@ __global__ __launch_bounds__(512) void k_fd_z(double* __restrict__ u,
       const int k0t = (t / 4) * 16, c0 = (t % 4) * 16;
       for (int k0 = 0; k0 < nzp; k0 += 4)
         acc[s] = mma(sget(Sz, nz, k0 + lr, k0t + lc), A[(k0 + lr) * 64 + c0 + lc], acc[s]);
-      // divide by the eigenvalue of L at (i, j, k)
+      // divide by the eigenvalue at (i, j, k): lx my mz + mx ly mz + mx my lz (with unit
+      // mass eigenvalues this is exactly lx + ly + lz)
       const int line = l0 + c0 + lc;
-      const double lij = (line < npl) ? lx[line % nx] + ly[line / nx] : 1.0;
+      const int ii = line % nx, jj = line / nx;
+      const bool live = line < npl;
+      const double lxi = live ? lx[ii] : 1.0, mxi = live ? mx[ii] : 1.0;
+      const double lyj = live ? ly[jj] : 1.0, myj = live ? my[jj] : 1.0;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int kk = k0t + lr + 4 * q;
-        acc[s][q] = (kk < nz) ? acc[s][q] / (lij + lz[kk]) : 0.0;
+        if (kk < nz) {
+          const double mzk = mz[kk];
+          const double den = (lxi * myj * mzk + mxi * lyj * mzk) + mxi * myj * lz[kk];
+          acc[s][q] = acc[s][q] / den;
+        } else {
+          acc[s][q] = 0.0;
+        }
       }
     }
   }
@@ -392,8 +434,10 @@ __global__ __launch_bounds__(512) void k_fd_z(double* __restrict__ u,
 size_t hartree_part_doubles() { return (size_t)4 * kCgBlocksMax; }
 
 
-void launch_fd_setup(double* S, double* lam, int N, double h, hipStream_t st) {
-  hipLaunchKernelGGL(k_fd_setup, dim3((N * N + 255) / 256), dim3(256), 0, st, S, lam, N, h);
+void launch_fd_setup(double* S, double* lam, double* mu, int N, double h, int q1,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_fd_setup, dim3((N * N + 255) / 256), dim3(256), 0, st, S, lam, mu, N, h,
+                     q1);
 }
 
 void launch_hartree_init(const double* rho, const double* x0, double* x, double* r, double* p0,
@@ -451,11 +495,11 @@ void launch_fd_apply(const double* r, double* z, const FdOps& fd, Grid g, const 
   if (lzs <= cap) {
     set_lds(reinterpret_cast<const void*>(k_fd_z<true>), lzs);
     hipLaunchKernelGGL(k_fd_z<true>, dim3((nx * ny + 63) / 64), dim3(threads), lzs, st, z, fd.Sz,
-                       fd.lx, fd.ly, fd.lz, nx, ny, nz, cs);
+                       fd.lx, fd.ly, fd.lz, fd.mx, fd.my, fd.mz, nx, ny, nz, cs);
   } else {
     set_lds(reinterpret_cast<const void*>(k_fd_z<false>), lzb);
     hipLaunchKernelGGL(k_fd_z<false>, dim3((nx * ny + 63) / 64), dim3(threads), lzb, st, z, fd.Sz,
-                       fd.lx, fd.ly, fd.lz, nx, ny, nz, cs);
+                       fd.lx, fd.ly, fd.lz, fd.mx, fd.my, fd.mz, nx, ny, nz, cs);
   }
   plane(z, z, r, part);
   hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kBlock), 0, st, part, nz, const_cast<CgState*>(cs));

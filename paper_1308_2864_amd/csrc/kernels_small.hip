@@ -22,8 +22,13 @@ namespace {
 
 // ---- block-cooperative helpers (all threads of the block call them) -----------------
 
+// A pivot is taken as a breakdown when it is not positive, not finite, or below
+// kPivotTol times the original diagonal entry: the matrix is then singular to working
+// precision (its condition number exceeds ~1/kPivotTol) and R^{-1} would be meaningless.
+constexpr double kPivotTol = 1e-13;
+
 // In-place upper Cholesky: on return M[i][j], j >= i, holds R with R^T R = M (input);
-// the strict lower part is zeroed.  Returns nonzero on a non-positive or non-finite pivot.
+// the strict lower part is zeroed.  Returns nonzero on a breakdown pivot (see kPivotTol).
 __device__ int blk_cholesky_upper(double* M, int ld, int p) {
   __shared__ int bad;
   if (threadIdx.x == 0) bad = 0;
@@ -31,7 +36,10 @@ __device__ int blk_cholesky_upper(double* M, int ld, int p) {
   for (int k = 0; k < p; ++k) {
     if (threadIdx.x == 0) {
       const double d = M[k * ld + k];
-      if (!(d > 0.0) || !isfinite(d)) bad = 1;
+      // the original diagonal entry is the pivot plus the squares above it in column k
+      double d0 = d;
+      for (int m = 0; m < k; ++m) d0 += M[m * ld + k] * M[m * ld + k];
+      if (!(d > kPivotTol * d0) || !isfinite(d)) bad = 1;
       else M[k * ld + k] = sqrt(d);
     }
     __syncthreads();
@@ -210,6 +218,7 @@ __global__ __launch_bounds__(64) void k_qr_factor_wave(const double* __restrict_
   __shared__ double M[P][P + 1];
   __shared__ double W[P][P + 1];
   __shared__ double rowk[P];
+  __shared__ double dg[P];
   const int j = threadIdx.x;
   const double tau = *tau_p;
   const double* XD = gxd + pp * pp;
@@ -219,10 +228,12 @@ __global__ __launch_bounds__(64) void k_qr_factor_wave(const double* __restrict_
     M[i][c] = xx[i * pp + c] - tau * (XD[i * pp + c] + XD[c * pp + i]) + tau * tau * DD[i * pp + c];
   }
   __syncthreads();
+  if (j < p) dg[j] = M[j][j];
+  __syncthreads();
   int bad = 0;
   for (int k = 0; k < p; ++k) {
     const double d = M[k][k];
-    if (!(d > 0.0) || !isfinite(d)) bad = 1;
+    if (!(d > kPivotTol * dg[k]) || !isfinite(d)) bad = 1;
     const double rkk = sqrt(d);
     __syncthreads();
     double rk = 0.0;

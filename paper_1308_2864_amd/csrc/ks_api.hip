@@ -33,7 +33,13 @@ struct ks_system {
   double *vext = nullptr, *rho = nullptr, *vh[2] = {}, *veff[2] = {};
   double *cg_r = nullptr, *cg_p[2] = {}, *cg_q = nullptr, *cg_z = nullptr;
   int cg_par = 0;
-  double *fdS[3] = {}, *fdL[3] = {};
+  double *fdS[3] = {}, *fdL[3] = {}, *fdM[3] = {};
+  // trilinear finite elements: B^{-1} tables and, per slot, B^{-1} G, B X, B grad E and the
+  // Gram block X^T B X (slot 1 of a [3][pp][pp] buffer)
+  bool q1 = false;
+  double* mtab[3] = {};
+  void *Gt[2] = {}, *BX[2] = {}, *BD[2] = {};
+  double* feg[2] = {};
   int solver = KS_HARTREE_CG;
   double *Rd = nullptr, *Zd = nullptr, *enuc = nullptr, *tau_user = nullptr;
   void *X[2] = {}, *G[2] = {}, *D[2] = {};  // float (FP32 modes) or double
@@ -102,6 +108,8 @@ void layout(ks_system* s, char* base, size_t* total) {
   for (int a = 0; a < 3; ++a) {
     s->fdS[a] = c.take<double>((size_t)dims[a] * dims[a]);
     s->fdL[a] = c.take<double>((size_t)dims[a]);
+    s->fdM[a] = c.take<double>((size_t)dims[a]);
+    if (s->q1) s->mtab[a] = c.take<double>(2 * (size_t)dims[a]);
   }
   s->Rd = c.take<double>(3 * (size_t)(M > 0 ? M : 1));
   s->Zd = c.take<double>((size_t)(M > 0 ? M : 1));
@@ -115,6 +123,12 @@ void layout(ks_system* s, char* base, size_t* total) {
     s->gxd[i] = c.take<double>(3 * pp2);
     s->sums[i] = c.take<double>(kMaxScalarSlots);
     s->ev[i] = c.take<EvalOut>(1);
+    if (s->q1) {
+      s->Gt[i] = c.take<char>(np * s->es);
+      s->BX[i] = c.take<char>(np * s->es);
+      s->BD[i] = c.take<char>(np * s->es);
+      s->feg[i] = c.take<double>(3 * pp2);
+    }
   }
   s->W = c.take<double>(pp2);
   s->A = c.take<double>(pp2);
@@ -133,8 +147,12 @@ void layout(ks_system* s, char* base, size_t* total) {
 
 int validate(const ks_system_desc* d, std::string* why) {
   if (!d) { *why = "null descriptor"; return KS_E_INVAL; }
-  if (d->disc != KS_DISC_FD7) {
-    *why = "only the 7-point finite-difference discretisation is built into this library";
+  if (d->disc != KS_DISC_FD7 && d->disc != KS_DISC_Q1) {
+    *why = "unknown discretisation";
+    return KS_E_UNSUPPORTED;
+  }
+  if (d->disc == KS_DISC_Q1 && (d->nx > 128 || d->ny > 128 || d->nz > 128)) {
+    *why = "the finite-element mass solve supports at most 128 nodes per axis";
     return KS_E_UNSUPPORTED;
   }
   if (d->precision != KS_PREC_FP64 && d->precision != KS_PREC_FP32) {
@@ -196,7 +214,15 @@ void init_dims(ks_system* s, const ks_system_desc* d) {
   s->grid.inv_h2 = 1.0 / (d->h * d->h);
   s->grid.dV = d->h * d->h * d->h;
   for (int i = 0; i < 3; ++i) s->grid.lo[i] = d->box_lo[i];
+  s->q1 = d->disc == KS_DISC_Q1;
+  s->grid.q1 = s->q1 ? 1 : 0;
+  // the finite-element Poisson problem is A V_H = 4 pi h^3 rho (nodal quadrature)
+  s->grid.rhs_scale = s->q1 ? s->grid.dV : 1.0;
 }
+
+// Density scale: rho_g = (f/h^3) sum X^2 on the grid (X^T X = I); rho_k = f sum X^2 at the
+// finite-element nodes (X^T B X = I).
+double rho_scale(const ks_system* s) { return s->q1 ? s->f : s->f / s->grid.dV; }
 
 int fail(ks_system* s, int code, const std::string& msg) {
   if (s) s->err = msg;
@@ -225,7 +251,7 @@ void copy_block(ks_system* s, void* dst, int ldd, const void* src, int lds) {
 }
 
 void density(ks_system* s, const void* X, int ld, double* rho) {
-  const double scale = s->f / s->grid.dV;
+  const double scale = rho_scale(s);
   if (s->f32)
     launch_density<float>(static_cast<const float*>(X), ld, s->n, s->p, scale, rho, s->st);
   else
@@ -240,6 +266,28 @@ void hamiltonian(ks_system* s, const void* X, int ldx, void* Y, int ldy, const d
   else
     launch_hx<double>(static_cast<const double*>(X), ldx, static_cast<double*>(Y), ldy, veff,
                       s->vext, s->grid, s->p, scale, pt, s->st);
+}
+
+void q1_apply(ks_system* s, const void* X, void* G, void* BX, const double* veff, double scale,
+              Partials* pt) {
+  if (s->f32)
+    launch_q1_apply<float>(static_cast<const float*>(X), static_cast<float*>(G),
+                           static_cast<float*>(BX), veff, s->vext, s->grid, s->p, scale, pt,
+                           s->st);
+  else
+    launch_q1_apply<double>(static_cast<const double*>(X), static_cast<double*>(G),
+                            static_cast<double*>(BX), veff, s->vext, s->grid, s->p, scale, pt,
+                            s->st);
+}
+
+void mass_solve(ks_system* s, const void* in, void* out) {
+  const double* const tab[3] = {s->mtab[0], s->mtab[1], s->mtab[2]};
+  if (s->f32)
+    launch_mass_solve<float>(static_cast<const float*>(in), static_cast<float*>(out), s->p,
+                             s->grid, tab, s->st);
+  else
+    launch_mass_solve<double>(static_cast<const double*>(in), static_cast<double*>(out), s->p,
+                              s->grid, tab, s->st);
 }
 
 void gram(ks_system* s, const void* A, const void* B, int mask) {
@@ -343,7 +391,8 @@ void harvest(ks_system* s) {
 int hartree_iterate(ks_system* s, double* x, int first_chunk, bool wait, int* iters,
                     double* relres) {
   const bool pcg = s->solver == KS_HARTREE_PCG_FD;
-  FdOps fd{s->fdS[0], s->fdS[1], s->fdS[2], s->fdL[0], s->fdL[1], s->fdL[2]};
+  FdOps fd{s->fdS[0], s->fdS[1], s->fdS[2], s->fdL[0], s->fdL[1], s->fdL[2],
+           s->fdM[0], s->fdM[1], s->fdM[2]};
   int launched = 0;
   int chunk = first_chunk;
   CgState* hc = host_cg(s);
@@ -396,6 +445,7 @@ int hartree(ks_system* s, const double* rho, const double* x0, double* x, bool w
 // bb_ref >= 0 the gradient epilogue also forms the BB sums against slot bb_ref.
 // warm: slot whose V_H starts the CG.  Writes G, D, gram blocks, sums, ev of the slot.
 int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg);
+int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd);
 
 int evaluate(ks_system* s, int idx, bool rho_ready, int bb_ref, int warm, bool want_gxd,
              bool want_gg, bool wait_hartree = true) {
@@ -419,6 +469,7 @@ int evaluate(ks_system* s, int idx, bool rho_ready, int bb_ref, int warm, bool w
 // Everything after the Hartree solve: exchange, Hamiltonian, Gram blocks, gradient,
 // reductions and the evaluation summary of slot idx.
 int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg) {
+  if (s->q1) return evaluate_tail_q1(s, idx, bb_ref, want_gxd);
   const void* Xs = s->X[idx];
   Partials pt{s->spart, kPartStride};
   tbeg(s, KS_PH_XC);
@@ -475,6 +526,110 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
                      s->use_h ? s->cg : nullptr, s->ev[idx], s->st);
   tend(s, KS_PH_SMALL);
   return launch_check(s, "evaluate");
+}
+
+// The finite-element evaluation in the B metric: G = E_X, BX = B X, Gt = B^{-1} G,
+// M = G^T X, D = grad E = Gt - X M and BD = B D = G - BX M (same weights), the Gram blocks
+// X^T B X (orthonormality and the Cholesky of the retraction), X^T BD and D^T BD (with
+// want_gxd), ||D||_B^2 and the BB sums of the B metric against slot bb_ref.
+int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd) {
+  const void* Xs = s->X[idx];
+  const int pp2 = s->pp * s->pp;
+  Partials pt{s->spart, kPartStride};
+  tbeg(s, KS_PH_XC);
+  launch_xc(s->rho, s->vh[idx], s->vext, s->veff[idx], s->grid, s->use_h, s->use_x,
+            s->use_h ? s->cg : nullptr, pt, s->st);
+  tend(s, KS_PH_XC);
+  tbeg(s, KS_PH_HAMILTONIAN);
+  q1_apply(s, Xs, s->G[idx], s->BX[idx], s->veff[idx], 2.0 * s->f, &pt);
+  mass_solve(s, s->G[idx], s->Gt[idx]);
+  tend(s, KS_PH_HAMILTONIAN);
+  tbeg(s, KS_PH_GRAM);
+  gram(s, Xs, s->G[idx], kGramAB);
+  launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, kGramAB, s->gxg[idx], s->W, s->st);
+  gram(s, Xs, s->BX[idx], kGramAB);
+  launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, kGramAB, s->feg[idx], nullptr,
+                     s->st);
+  tend(s, KS_PH_GRAM);
+  Q1GradArgs ga{};
+  ga.Gt = s->Gt[idx];
+  ga.X = Xs;
+  ga.G = s->G[idx];
+  ga.BX = s->BX[idx];
+  ga.W = s->W;
+  ga.D = s->D[idx];
+  ga.BD = s->BD[idx];
+  if (bb_ref >= 0) {
+    ga.Xc = s->X[bb_ref];
+    ga.BXc = s->BX[bb_ref];
+    ga.Dc = s->D[bb_ref];
+    ga.BDc = s->BD[bb_ref];
+  }
+  ga.pt = pt;
+  ga.n = s->n;
+  ga.p = s->p;
+  ga.pp = s->pp;
+  ga.f32 = s->f32;
+  tbeg(s, KS_PH_GRADIENT);
+  launch_q1_grad(ga, s->st);
+  tend(s, KS_PH_GRADIENT);
+  if (want_gxd) {
+    tbeg(s, KS_PH_GRAM);
+    gram(s, Xs, s->BD[idx], kGramAB);
+    launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, kGramAB, s->gxd[idx], nullptr,
+                       s->st);
+    // D^T BD lands in product slot 2 of gxd
+    gram(s, s->D[idx], s->BD[idx], kGramAB);
+    launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, kGramAB, s->gxd[idx] + pp2,
+                       nullptr, s->st);
+    tend(s, KS_PH_GRAM);
+  }
+  tbeg(s, KS_PH_SMALL);
+  int nblk[kMaxScalarSlots] = {};
+  nblk[SL_KIN] = nblk[SL_EXT] = q1_apply_blocks(s->n, s->p);
+  nblk[SL_EH] = nblk[SL_EX] = scalar_blocks(s->n);
+  nblk[SL_DD] = nblk[SL_SS] = nblk[SL_SY] = nblk[SL_YY] = q1_grad_blocks(s->n, s->p);
+  launch_reduce_scalars(s->spart, kPartStride, nblk, SL_COUNT, s->sums[idx], s->st);
+  launch_finish_eval(s->sums[idx], s->feg[idx] + pp2, s->p, s->pp, s->f, s->grid.dV, s->enuc,
+                     s->use_h ? s->cg : nullptr, s->ev[idx], s->st);
+  tend(s, KS_PH_SMALL);
+  return launch_check(s, "evaluate");
+}
+
+// X <- X R^{-1} with X^T B X = R^T R, in place on slot idx (uses slot 1 - idx as scratch).
+int b_orthonormalize(ks_system* s, int idx) {
+  const int o = 1 - idx;
+  const int pp2 = s->pp * s->pp;
+  q1_apply(s, s->X[idx], nullptr, s->BX[idx], nullptr, 1.0, nullptr);
+  gram(s, s->X[idx], s->BX[idx], kGramAB);
+  launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, kGramAB, s->feg[idx], nullptr,
+                     s->st);
+  // tau = 0: the factor reduces to the Cholesky of X^T B X; X^T D and D^T D are not used
+  launch_fill(s->gxd[idx], 0.0, 3 * (size_t)pp2, s->st);
+  launch_set_scalar(s->tau_user, 0.0, s->st);
+  int* hstat = host_int(s);
+  hstat[0] = 0;
+  int rc = hip_check(s, hipMemcpyAsync(s->status, hstat, sizeof(int), hipMemcpyHostToDevice,
+                                       s->st), "status upload");
+  if (rc) return rc;
+  launch_qr_factor(s->feg[idx] + pp2, s->gxd[idx], s->p, s->pp, s->tau_user, s->A, s->B,
+                   s->work, s->status, s->st);
+  CombineArgs ca{};
+  ca.X = s->X[idx];
+  ca.A = s->A;
+  ca.ld = s->p;
+  ca.n = s->n;
+  ca.p = s->p;
+  ca.f32 = s->f32;
+  ca.out = s->X[o];
+  launch_combine(ca, s->st);
+  copy_block(s, s->X[idx], s->p, s->X[o], s->p);
+  rc = launch_check(s, "B-orthonormalisation");
+  if (rc) return rc;
+  rc = readback(s, hstat, s->status);
+  if (rc) return rc;
+  if (hstat[0] != 0) return fail(s, KS_E_NOT_SPD, "start block is rank deficient in the B metric");
+  return KS_OK;
 }
 
 void to_energy(const EvalOut& e, ks_energy* out) {
@@ -612,7 +767,10 @@ int ks_create_system(const ks_system_desc* d, void* dev_workspace, size_t ws_byt
     launch_copy_vec(s->veff[i], s->vext, s->n, s->st);
   }
   const int dims[3] = {s->grid.nx, s->grid.ny, s->grid.nz};
-  for (int a = 0; a < 3; ++a) launch_fd_setup(s->fdS[a], s->fdL[a], dims[a], s->grid.h, s->st);
+  for (int a = 0; a < 3; ++a) {
+    launch_fd_setup(s->fdS[a], s->fdL[a], s->fdM[a], dims[a], s->grid.h, s->q1 ? 1 : 0, s->st);
+    if (s->q1) launch_mass_setup(s->mtab[a], dims[a], s->grid.h, s->st);
+  }
   launch_ls_reset(s->ls, s->st);
   // the CG arrival counter must start at zero
   launch_fill(reinterpret_cast<double*>(s->cg), 0.0, sizeof(CgState) / sizeof(double), s->st);
@@ -697,7 +855,15 @@ int ks_hartree_solve(ks_system* s, const double* rho, double* v_h, int warm, int
 int ks_apply_hamiltonian(ks_system* s, const void* X, void* Y, const double* v_eff) {
   if (!s || !X || !Y) return fail(s, KS_E_INVAL, "null argument");
   if (X == Y) return fail(s, KS_E_INVAL, "X and Y must differ");
-  hamiltonian(s, X, s->ld, Y, s->ld, v_eff ? v_eff : s->veff[s->cur], 1.0, nullptr);
+  if (s->q1) {
+    // Y = (1/2) A X + h^3 Diag(v_eff) X on dense internal copies
+    const int t = 1 - s->cur;
+    copy_block(s, s->X[t], s->p, X, s->ld);
+    q1_apply(s, s->X[t], s->G[t], s->BX[t], v_eff ? v_eff : s->veff[s->cur], 1.0, nullptr);
+    copy_block(s, Y, s->ld, s->G[t], s->p);
+  } else {
+    hamiltonian(s, X, s->ld, Y, s->ld, v_eff ? v_eff : s->veff[s->cur], 1.0, nullptr);
+  }
   int rc = launch_check(s, "hamiltonian");
   return rc ? rc : hip_check(s, hipStreamSynchronize(s->st), "hamiltonian sync");
 }
@@ -750,11 +916,44 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
   if (X_out == X || X_out == G) return fail(s, KS_E_INVAL, "X_out must not alias X or G");
   if (!std::isfinite(tau)) return fail(s, KS_E_INVAL, "tau must be finite");
   const int t = 1 - s->cur, c = s->cur;
+  if (s->q1 && kind != KS_QR)
+    return fail(s, KS_E_UNSUPPORTED, "finite elements use the QR retraction");
   copy_block(s, s->X[t], s->p, X, s->ld);
   copy_block(s, s->G[t], s->p, G, s->ld);
   const int all = kGramAA | kGramAB | kGramBB;
-  gram(s, s->X[t], s->G[t], all);
-  launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, all, s->gxg[t], s->W, s->st);
+  if (s->q1) {
+    // grad E = B^{-1} G - X (G^T X) and the B-metric Gram blocks, as in an evaluation
+    const int pp2 = s->pp * s->pp;
+    q1_apply(s, s->X[t], nullptr, s->BX[t], nullptr, 1.0, nullptr);
+    mass_solve(s, s->G[t], s->Gt[t]);
+    gram(s, s->X[t], s->G[t], kGramAB);
+    launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, kGramAB, s->gxg[t], s->W, s->st);
+    gram(s, s->X[t], s->BX[t], kGramAB);
+    launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, kGramAB, s->feg[t], nullptr,
+                       s->st);
+    Q1GradArgs ga{};
+    ga.Gt = s->Gt[t];
+    ga.X = s->X[t];
+    ga.G = s->G[t];
+    ga.BX = s->BX[t];
+    ga.W = s->W;
+    ga.D = s->D[t];
+    ga.BD = s->BD[t];
+    ga.pt = Partials{s->spart, kPartStride};
+    ga.n = s->n;
+    ga.p = s->p;
+    ga.pp = s->pp;
+    ga.f32 = s->f32;
+    launch_q1_grad(ga, s->st);
+    gram(s, s->X[t], s->BD[t], kGramAB);
+    launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, kGramAB, s->gxd[t], nullptr, s->st);
+    gram(s, s->D[t], s->BD[t], kGramAB);
+    launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, kGramAB, s->gxd[t] + pp2, nullptr,
+                       s->st);
+  } else {
+    gram(s, s->X[t], s->G[t], all);
+    launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, all, s->gxg[t], s->W, s->st);
+  }
   launch_set_scalar(s->tau_user, tau, s->st);
   int* hstat = host_int(s);
   hstat[0] = 0;
@@ -766,7 +965,11 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
   ca.n = s->n;
   ca.p = s->p;
   ca.f32 = s->f32;
-  if (kind == KS_QR) {
+  if (kind == KS_QR && s->q1) {
+    launch_qr_factor(s->feg[t] + s->pp * s->pp, s->gxd[t], s->p, s->pp, s->tau_user, s->A, s->B,
+                     s->work, s->status, s->st);
+    ca.Y = s->D[t];
+  } else if (kind == KS_QR) {
     CombineArgs cd{};
     cd.f32 = s->f32;
     cd.X = s->X[t];
@@ -814,11 +1017,18 @@ int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* 
     return fail(s, KS_E_INVAL, "unknown retraction");
   if (!(prm.delta > 0.0 && prm.delta < 1.0) || !(prm.tau0 > 0.0) || prm.h_max < 0)
     return fail(s, KS_E_INVAL, "bad line-search parameters");
+  if (s->q1 && prm.retraction != KS_QR)
+    return fail(s, KS_E_UNSUPPORTED, "finite elements use the QR retraction");
   const LsParams lp = to_params(prm);
   const bool qr = prm.retraction == KS_QR;
   s->cg_total = 0;
   int c = s->cur;
   copy_block(s, s->X[c], s->p, X_inout, s->ld);
+  if (s->q1) {
+    // the start block needs full column rank only: make it B-orthonormal first
+    int rb = b_orthonormalize(s, c);
+    if (rb) return rb;
+  }
   launch_ls_reset(s->ls, s->st);
   int* hint = host_int(s);
   hint[1] = 0;
@@ -841,15 +1051,15 @@ int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* 
     ca.B = s->B;
     ca.out = s->X[t];
     ca.rho = s->rho;
-    ca.rho_scale = s->f / s->grid.dV;
+    ca.rho_scale = rho_scale(s);
     ca.f32 = s->f32;
     ca.ld = s->p;
     ca.n = s->n;
     ca.p = s->p;
     tbeg(s, KS_PH_SMALL);
     if (qr) {
-      launch_qr_factor(s->gxg[c], s->gxd[c], s->p, s->pp, &s->ls->tau, s->A, s->B, s->work,
-                       &s->ls->error, s->st);
+      launch_qr_factor(s->q1 ? s->feg[c] + s->pp * s->pp : s->gxg[c], s->gxd[c], s->p, s->pp,
+                       &s->ls->tau, s->A, s->B, s->work, &s->ls->error, s->st);
       ca.Y = s->D[c];
     } else {
       launch_wy_factor(s->gxg[c], s->p, s->pp, &s->ls->tau, prm.reorth_tol, s->A, s->B, s->work,

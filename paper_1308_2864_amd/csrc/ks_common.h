@@ -81,6 +81,8 @@ struct Grid {
   int n;
   double h, inv_h2, dV;
   double lo[3];
+  int q1;            // 0: 7-point finite differences; 1: trilinear finite elements
+  double rhs_scale;  // Poisson right-hand side 4 pi * rhs_scale * rho (FE: h^3)
 };
 
 __host__ __device__ inline int round_up(int a, int b) { return (a + b - 1) / b * b; }
@@ -140,12 +142,14 @@ void launch_reduce_scalars(const double* part, int stride, const int* nblk, int 
 // Hartree solver (kernels_poisson.hip)
 struct FdOps {
   const double *Sx, *Sy, *Sz;   // sine-transform matrices per axis
-  const double *lx, *ly, *lz;   // their eigenvalues of -d^2/dx^2 (already / h^2)
+  const double *lx, *ly, *lz;   // eigenvalues of the 1D operator per axis
+  const double *mx, *my, *mz;   // eigenvalues of the 1D mass matrix (1 for differences)
 };
 size_t hartree_part_doubles();
 size_t fd_lds_bytes(int nx, int ny, int nz);
 int fd_max_plane();
-void launch_fd_setup(double* S, double* lam, int N, double h, hipStream_t st);
+void launch_fd_setup(double* S, double* lam, double* mu, int N, double h, int q1,
+                     hipStream_t st);
 void launch_hartree_init(const double* rho, const double* x0, double* x, double* r, double* p0,
                          CgState* cs, double tol, int maxit, Grid g, double* part,
                          hipStream_t st);
@@ -155,6 +159,33 @@ void launch_hartree_iter(double* x, double* r, const double* z, double* pa, doub
                          double* q, CgState* cs, Grid g, double* part, int pcg,
                          hipStream_t st);
 
+// trilinear finite elements (kernels_fe.hip)
+// G = scale ((1/2) A X + h^3 Diag(veff) X) (with kG) and BX = B X; with pt the partials
+// sum X.(AX) and h^3 sum vext X^2.  Blocks are n x p.
+template <typename T>
+void launch_q1_apply(const T* X, T* G, T* BX, const double* veff, const double* vext, Grid g,
+                     int p, double scale, Partials* pt, hipStream_t st);
+// Tables of the constant-coefficient tridiagonal solve with the 1D mass matrix (2N doubles)
+void launch_mass_setup(double* tab, int N, double h, hipStream_t st);
+// out = B^{-1} in (in and out may be the same block)
+template <typename T>
+void launch_mass_solve(const T* in, T* out, int p, Grid g, const double* const tab[3],
+                       hipStream_t st);
+// D = Gt + X W and BD = G + BX W (W: pp x pp), partials ||D||_B^2 and the B-metric BB
+// sums against (Xc, BXc, Dc, BDc) when those are given.
+struct Q1GradArgs {
+  const void *Gt, *X, *G, *BX;
+  const double* W;
+  void *D, *BD;
+  const void *Xc, *BXc, *Dc, *BDc;
+  Partials pt;
+  int n, p, pp;
+  bool f32;
+};
+void launch_q1_grad(const Q1GradArgs& a, hipStream_t st);
+int q1_grad_blocks(int n, int p);
+int q1_apply_blocks(int n, int p);
+
 // dense kernels (kernels_dense.hip)
 constexpr int kGramAA = 1, kGramAB = 2, kGramBB = 4;  // product bits of a Gram launch
 int gram_chunks(int n, int pp);
@@ -163,7 +194,7 @@ bool combine_fuses_gram(int p);
 // A, B: n x ld blocks of float (f32) or double; products accumulate in FP64
 void launch_gram(const void* A, const void* B, bool f32, int ld, int n, int p, int mask,
                  double* partials, int nchunks, hipStream_t st);
-// out: [3][pp][pp]; products outside mask are zero; W (nullable) = -(A^T B)^T
+// out: [3][pp][pp]; products outside mask are not written; W (nullable) = -(A^T B)^T
 void launch_gram_reduce(const double* partials, int nchunks, int pp, int mask, double* out,
                         double* W, hipStream_t st);
 struct CombineArgs {

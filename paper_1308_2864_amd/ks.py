@@ -276,7 +276,8 @@ def desc_from_spec(spec, **kw):
     """A ks_system_desc for a ``synth.SystemSpec`` (keyword arguments go to make_desc)."""
     terms = (KS_TERM_EXT if spec.ext else 0) | (KS_TERM_HARTREE if spec.hartree else 0) | \
             (KS_TERM_XC if spec.xc else 0)
-    dkw = dict(f=spec.f, rc=spec.rc, terms=terms)
+    dkw = dict(f=spec.f, rc=spec.rc, terms=terms,
+               disc=KS_DISC_Q1 if spec.disc == "q1" else KS_DISC_FD7)
     dkw.update(kw)
     return make_desc(spec.nx, spec.ny, spec.nz, spec.h, spec.lo, spec.p, spec.R, spec.Z, **dkw)
 
