@@ -63,6 +63,52 @@ def cpu_baseline(spec, X0, gpu_iters, iters):
     }
 
 
+def fe_leg(ks, synth, p, iters, seed):
+    """Finite-element (Q1, B metric) workload on the 96^3 mesh: per-evaluation time,
+    stencil (A X and B X) bandwidth and the FP32-storage error at a fixed X, for FP64 and
+    FP32 storage of the orbital blocks.  Runs a fixed number of Alg. 3 iterations from
+    the seeded start (a converged solve of this size takes thousands)."""
+    import numpy as np
+    import torch
+    spec = synth.make_config("c3", seed).copy(p=p)
+    X0h = synth.make_x0(spec, seed)
+    out = {"workload": f"{spec.name.replace('p128', f'p{p}')} (Q1 elements, B metric)",
+           "mesh": [spec.nx, spec.ny, spec.nz], "p": p, "iterations": iters}
+    energies = {}
+    for name, prec, dt, w in (("fp64", ks.KS_PREC_FP64, torch.float64, 8),
+                              ("fp32", ks.KS_PREC_FP32, torch.float32, 4)):
+        sysg = ks.system_from_spec(spec, hartree_solver=ks.KS_HARTREE_PCG_FD, precision=prec)
+        X0 = torch.tensor(X0h, dtype=dt, device="cuda")
+        X = X0.clone()
+        sysg.ks_minimize(X, ks.ks_default_params(max_iter=3), check=False)  # warm-up
+        # energy at the B-orthonormalised start (same X for both precisions up to rounding)
+        energies[name] = sysg.ks_energy_grad(X).total
+        X.copy_(X0)
+        torch.cuda.synchronize()
+        sysg.ks_enable_timers(True)
+        sysg.ks_read_timers(reset=True)
+        t0 = time.perf_counter()
+        r = sysg.ks_minimize(X, ks.ks_default_params(max_iter=iters), check=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ph = sysg.ks_read_timers(reset=True)
+        sysg.close()
+        n = spec.n
+        blk = n * p * w
+        ms, cnt = ph["hamiltonian"]
+        spmm_bytes = 3 * blk + 16 * n  # read X, write G and B X, read V_eff and V_ext
+        ent = {"ms_per_iteration": round(1e3 * el / max(r.iters, 1), 3),
+               "ms_per_evaluation": round(1e3 * el / max(r.nfe, 1), 3),
+               "evaluations": r.nfe, "energy": r.energy, "grad_norm_B": r.grad_norm,
+               "stencil_avg_us": round(1e3 * ms / max(cnt, 1), 1),
+               "stencil_GBps": round(spmm_bytes * cnt / (ms * 1e-3) / 1e9, 1) if cnt else None,
+               "phases_ms": {k: round(v[0], 2) for k, v in ph.items() if v[1]}}
+        print(f"# fe {name}: {ent}", file=sys.stderr, flush=True)
+        out[name] = ent
+    out["fp32_energy_error_at_start_Ha"] = abs(energies["fp32"] - energies["fp64"])
+    return out
+
+
 def serve_leg(ks, synth, n_req, slots, hbm_gib, fracs, precision, seed, check_n):
     """Serving stream: n_req requests of mixed sizes through the library's server.
 
@@ -160,6 +206,9 @@ def main():
     ap.add_argument("--serve-fracs", default="0.7,0.9")
     ap.add_argument("--serve-check", type=int, default=32,
                     help="requests re-run in FP64 to state the FP32 error")
+    ap.add_argument("--fe-p", type=int, default=64,
+                    help="orbitals of the finite-element leg (0 = skip; at most 64)")
+    ap.add_argument("--fe-iters", type=int, default=100)
     ap.add_argument("--max-iter", type=int, default=10000,
                     help="iteration cap (profiling runs only; the metric needs the default)")
     args = ap.parse_args()
@@ -290,6 +339,9 @@ def main():
                                     round(1.0 / (el32 / args.fp32_steps + tpol), 4)}}
         print(f"# fp32: {r32.iters} it, E={r32.energy:.12f}, |E-E64|={abs(r32.energy - e64):.2e}, "
               f"{1e3 * el32 / args.fp32_steps:.1f} ms/solve", file=sys.stderr, flush=True)
+    fe = None
+    if args.fe_p > 0:
+        fe = fe_leg(ks, synth, args.fe_p, args.fe_iters, args.seed)
     serve = None
     if args.serve_requests > 0:
         fr = [float(v) for v in args.serve_fracs.split(",") if v]
@@ -325,6 +377,7 @@ def main():
         "grad_norm": results[-1].grad_norm if results else None,
         "spmm_GBps": spmm,
         "fp32": fp32,
+        "finite_elements": fe,
         "serving": serve,
         "phases": phase_out,
         "roofline": roofline,

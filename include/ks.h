@@ -19,6 +19,17 @@
  * - Energy units are Hartree, lengths bohr.  Orbitals are normalised by
  *   X^T X = I, i.e. phi_i(r_g) = X_gi h^{-3/2}; the density is
  *   rho_g = (f/h^3) sum_i X_gi^2 with occupation f per orbital.
+ * - Finite elements (KS_DISC_Q1).  The grid points are the nodes of trilinear elements
+ *   on cubes of side h (Section 2.3, the finite-element form with the mass matrix B).
+ *   Orbitals are nodal coefficients with X^T B X = I, B = M x M x M and stiffness
+ *   A = K x M x M + M x K x M + M x M x K from the 1D linear-element matrices
+ *   K = (1/h) tridiag(-1, 2, -1), M = (h/6) tridiag(1, 4, 1).  Potential terms use nodal
+ *   quadrature: rho_k = f sum_i X_ki^2, A V_H = 4 pi h^3 rho, and
+ *   E_X = 2f [ (1/2) A X + h^3 Diag(V_ext + V_H + v_x) X ].  The manifold is handled in
+ *   the B metric (Section 3 with Y = B^{1/2} X, as eq. (OFDFT-y) does for p = 1):
+ *   gradE = B^{-1} G - X G^T X, ||gradE||^2 = tr(gradE^T B gradE), the QR retraction
+ *   factors Y^T B Y, and ks_energy reports ||X^T B X - I||_F.  Only the QR retraction is
+ *   built for this form, and each axis holds at most 128 nodes.
  * - Memory.  The caller owns every device buffer, including the workspace handed
  *   to ks_create_system; the library never allocates or frees device memory.
  *   The library allocates a small pinned host buffer per system for scalar
@@ -147,9 +158,11 @@ typedef struct ks_result {
  * The single-kernel phases bracket exactly one kernel per occurrence. */
 #define KS_PH_HARTREE 0          /* one Hartree solve (all CG kernels of it)              */
 #define KS_PH_XC 1               /* exchange and effective potential (one kernel)         */
-#define KS_PH_HAMILTONIAN 2      /* G = 2f H X with energy partials (one kernel)          */
+#define KS_PH_HAMILTONIAN 2      /* G = 2f H X with energy partials (one kernel; Q1: and
+                                    B X in the same kernel)                               */
 #define KS_PH_GRAM 3             /* Gram blocks of [X, G] or [X, D] (one kernel)          */
-#define KS_PH_GRADIENT 4         /* grad E = G - X G^T X with BB sums (one kernel)        */
+#define KS_PH_GRADIENT 4         /* grad E = G - X G^T X with BB sums (one kernel; Q1: the
+                                    B^{-1} G sweeps, then grad E and B grad E)            */
 #define KS_PH_RETRACT 5          /* X+ = X A + Y B with fused density (one kernel)        */
 #define KS_PH_SMALL 6            /* reductions, small dense factors, line-search logic    */
 #define KS_PH_DENSITY 7          /* stand-alone density (first evaluation)                */
@@ -207,7 +220,8 @@ int ks_energy_grad(ks_system* s, const void* X, void* G, void* gradE, ks_energy*
 int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
                void* X_out);
 
-/* Alg. 3 from X_inout (orthonormal columns expected) with BB steps (eq. (bb-1)) and the
+/* Alg. 3 from X_inout (orthonormal columns expected; for KS_DISC_Q1 any full-rank block,
+ * which is first B-orthonormalised by Cholesky QR in the B metric) with BB steps (eq. (bb-1)) and the
  * nonmonotone Armijo search (eq. (NMLS-Armijo)); on return X_inout holds the last
  * accepted iterate and *r (host) the statistics.  The first Hartree solve of a run
  * starts from V_H = 0, so the result depends only on X_inout and the parameters.  o may be NULL for defaults.  Returns

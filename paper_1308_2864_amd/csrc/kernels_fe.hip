@@ -7,8 +7,8 @@
 // Both are 27-point stencils with one coefficient per neighbour class (centre, face,
 // edge, corner): A = (8h/3, 0, -h/6, -h/12) (the face couplings cancel exactly) and
 // B = (8h^3/27, 2h^3/27, h^3/54, h^3/216).  The kernels apply them as stencils over the
-// grid-major orbital block instead of as CSR matrices: no index arrays to stream, and the
-// 27 loads of a node hit the same cache lines as its neighbours' loads.
+// grid-major orbital block instead of as CSR matrices: no index arrays to stream, and
+// both products come out of one pass over X.
 //
 // B^{-1} is exact through the tensor structure: three sweeps of the constant-coefficient
 // tridiagonal solve with M, one per axis.  A thread owns one (line, orbital) pair and
@@ -51,7 +51,33 @@ Q1Coef q1_coef(double h) {
                 8.0 * h3 / 27.0, 2.0 * h3 / 27.0, h3 / 54.0, h3 / 216.0};
 }
 
-// Y = scale ((1/2) A X + h3 veff X) and BX = B X for every (node, orbital) pair.
+// Y = scale ((1/2) A X + h3 veff X) and BX = B X.  A thread owns one (i, j, orbital) column
+// and marches along z over kQ1Chunk planes.  Per plane it loads the 3 x 3 in-plane
+// neighbourhood once and reduces it to three partial sums (centre P0, in-plane faces P1,
+// in-plane corners P2); the 3-D neighbour classes of plane k are then
+//   centre P0(k), faces P1(k) + P0(k-1) + P0(k+1), edges P2(k) + P1(k-1) + P1(k+1),
+//   corners P2(k-1) + P2(k+1),
+// so each output costs 9 loads instead of 27.  Consecutive threads take consecutive
+// orbitals of one node: every load of a wavefront is one contiguous segment.
+constexpr int kQ1Chunk = 16;
+
+template <typename T>
+__device__ inline void q1_plane(const T* __restrict__ X, int i, int j, int k, int nx, int ny,
+                                int nz, ptrdiff_t sx, ptrdiff_t sy, ptrdiff_t sz, double* P) {
+  P[0] = P[1] = P[2] = 0.0;
+  if (k < 0 || k >= nz) return;
+  const T* xp = X + k * sz;
+#pragma unroll
+  for (int dy = -1; dy <= 1; ++dy) {
+    if (j + dy < 0 || j + dy >= ny) continue;
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      if (i + dx < 0 || i + dx >= nx) continue;
+      P[(dx != 0) + (dy != 0)] += (double)xp[dy * sy + dx * sx];
+    }
+  }
+}
+
 template <typename T, bool kG, bool kEnergy>
 __global__ __launch_bounds__(256) void k_q1_apply(const T* __restrict__ X, T* __restrict__ Y,
                                                   T* __restrict__ BX,
@@ -60,43 +86,49 @@ __global__ __launch_bounds__(256) void k_q1_apply(const T* __restrict__ X, T* __
                                                   int p, double scale, Q1Coef cf,
                                                   Partials pt) {
   __shared__ double sh[kBlock / kWave];
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const size_t work = (size_t)gr.n * p;
-  size_t beg, end;
-  block_range(work, lb, gridDim.x, &beg, &end);
   const int nx = gr.nx, ny = gr.ny, nz = gr.nz;
+  const int nzc = (nz + kQ1Chunk - 1) / kQ1Chunk;
+  const size_t work = (size_t)nx * ny * p * nzc;
   const ptrdiff_t sx = p, sy = (ptrdiff_t)nx * p, sz = (ptrdiff_t)nx * ny * p;
   const double h3 = gr.dV;
   double kin = 0.0, ext = 0.0;
-  for (size_t t = beg + threadIdx.x; t < end; t += blockDim.x) {
-    const size_t g = t / (unsigned)p;
-    const int i = (int)(g % nx);
-    const size_t gy = g / nx;
-    const int j = (int)(gy % ny), k = (int)(gy / ny);
-    const T* xp = X + t;
-    double s[4] = {0.0, 0.0, 0.0, 0.0};  // sums per neighbour class
-#pragma unroll
-    for (int dz = -1; dz <= 1; ++dz) {
-      if (k + dz < 0 || k + dz >= nz) continue;
-#pragma unroll
-      for (int dy = -1; dy <= 1; ++dy) {
-        if (j + dy < 0 || j + dy >= ny) continue;
-#pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-          if (i + dx < 0 || i + dx >= nx) continue;
-          const int cls = (dx != 0) + (dy != 0) + (dz != 0);
-          s[cls] += (double)xp[dz * sz + dy * sy + dx * sx];
-        }
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  for (size_t t = (size_t)lb * blockDim.x + threadIdx.x; t < work;
+       t += (size_t)gridDim.x * blockDim.x) {
+    // t -> (z chunk, j, i, orbital), orbital fastest
+    const int c = (int)(t % (unsigned)p);
+    size_t r = t / (unsigned)p;
+    const int i = (int)(r % nx);
+    r /= nx;
+    const int j = (int)(r % ny);
+    const int kc = (int)(r / ny);
+    const int k0 = kc * kQ1Chunk;
+    const int k1 = min(k0 + kQ1Chunk, nz);
+    const T* col = X + (ptrdiff_t)(i + (size_t)nx * j) * p + c;
+    double Pm[3], Pc[3], Pn[3];
+    q1_plane(col, i, j, k0 - 1, nx, ny, nz, sx, sy, sz, Pm);
+    q1_plane(col, i, j, k0, nx, ny, nz, sx, sy, sz, Pc);
+    for (int k = k0; k < k1; ++k) {
+      q1_plane(col, i, j, k + 1, nx, ny, nz, sx, sy, sz, Pn);
+      const double s0 = Pc[0];
+      const double s1 = Pc[1] + Pm[0] + Pn[0];
+      const double s2 = Pc[2] + Pm[1] + Pn[1];
+      const double s3 = Pm[2] + Pn[2];
+      const double ax = cf.a0 * s0 + cf.a2 * s2 + cf.a3 * s3;
+      const double bx = cf.b0 * s0 + cf.b1 * s1 + cf.b2 * s2 + cf.b3 * s3;
+      const size_t g = i + (size_t)nx * (j + (size_t)ny * k);
+      const size_t o = g * p + c;
+      if (kG) Y[o] = (T)(scale * (0.5 * ax + h3 * veff[g] * s0));
+      BX[o] = (T)bx;
+      if (kEnergy) {
+        kin += s0 * ax;
+        ext += h3 * vext[g] * s0 * s0;
       }
-    }
-    const double x0 = s[0];
-    const double ax = cf.a0 * s[0] + cf.a2 * s[2] + cf.a3 * s[3];
-    const double bx = cf.b0 * s[0] + cf.b1 * s[1] + cf.b2 * s[2] + cf.b3 * s[3];
-    if (kG) Y[t] = (T)(scale * (0.5 * ax + h3 * veff[g] * x0));
-    BX[t] = (T)bx;
-    if (kEnergy) {
-      kin += x0 * ax;
-      ext += h3 * vext[g] * x0 * x0;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        Pm[q] = Pc[q];
+        Pc[q] = Pn[q];
+      }
     }
   }
   if (kEnergy) {
@@ -177,17 +209,25 @@ __global__ __launch_bounds__(256) void k_mass_axis(const T* in, T* out, int p, G
 
 // D = Gt + X W, BD = G + BX W with the p x p weights staged in LDS; ||D||_B^2 = sum D.BD and
 // the BB sums of the B metric: ss = S.BS, sy = S.BYd, yy = Yd.BYd with S = X - Xc,
-// BS = BX - BXc, Yd = D - Dc, BYd = BD - BDc.
+// BS = BX - BXc, Yd = D - Dc, BYd = BD - BDc.  A block takes kQ1Rows rows at a time: their
+// X and BX rows are staged in LDS with coalesced loads (each entry read from memory
+// once), then a thread computes kQ1Cols adjacent columns of one row from LDS.
+constexpr int kQ1Cols = 4;
+constexpr int kQ1Rows = 16;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_q1_grad(Q1GradArgs a) {
-  extern __shared__ double Ws[];
+  extern __shared__ double lds[];
   __shared__ double sh[kBlock / kWave];
   const int p = a.p, pp = a.pp;
-  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
-    const int k = e / p, j = e % p;
-    Ws[e] = a.W[k * pp + j];
+  const int pc = (p + kQ1Cols - 1) / kQ1Cols * kQ1Cols;  // padded row of Ws
+  double* Ws = lds;                                     // p x pc
+  double* Xs = Ws + (size_t)p * pc;                     // kQ1Rows x p
+  double* Bs = Xs + (size_t)kQ1Rows * p;                // kQ1Rows x p
+  for (int e = threadIdx.x; e < p * pc; e += blockDim.x) {
+    const int k = e / pc, j = e % pc;
+    Ws[e] = j < p ? a.W[k * pp + j] : 0.0;
   }
-  __syncthreads();
   const T* Gt = static_cast<const T*>(a.Gt);
   const T* X = static_cast<const T*>(a.X);
   const T* G = static_cast<const T*>(a.G);
@@ -200,35 +240,63 @@ __global__ __launch_bounds__(256) void k_q1_grad(Q1GradArgs a) {
   const T* BDc = static_cast<const T*>(a.BDc);
   const bool ref = Xc != nullptr;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const size_t work = (size_t)a.n * p;
-  size_t beg, end;
-  block_range(work, lb, gridDim.x, &beg, &end);
+  const int groups = pc / kQ1Cols;
+  const int tiles = (a.n + kQ1Rows - 1) / kQ1Rows;
+  size_t tb, te;
+  // contiguous range of row tiles for this block
+  {
+    const int per = (tiles + gridDim.x - 1) / gridDim.x;
+    const long b0 = (long)lb * per;
+    tb = (size_t)(b0 < tiles ? b0 : tiles);
+    const long e0 = b0 + per;
+    te = (size_t)(e0 < tiles ? e0 : tiles);
+  }
   double dd = 0.0, ss = 0.0, sy = 0.0, yy = 0.0;
-  for (size_t t = beg + threadIdx.x; t < end; t += blockDim.x) {
-    const size_t g = t / (unsigned)p;
-    const int j = (int)(t - g * p);
-    const T* xr = X + g * p;
-    const T* br = BX + g * p;
-    double u = 0.0, v = 0.0;
-    for (int k = 0; k < p; ++k) {
-      const double w = Ws[k * p + j];
-      u += (double)xr[k] * w;
-      v += (double)br[k] * w;
+  for (size_t tile = tb; tile < te; ++tile) {
+    const size_t r0 = tile * kQ1Rows;
+    const int rows = (int)((size_t)a.n - r0 < (size_t)kQ1Rows ? (size_t)a.n - r0 : kQ1Rows);
+    __syncthreads();  // previous tile's readers are done (and Ws is complete)
+    for (int e = threadIdx.x; e < rows * p; e += blockDim.x) {
+      Xs[e] = (double)X[r0 * p + e];
+      Bs[e] = (double)BX[r0 * p + e];
     }
-    const T dT = (T)((double)Gt[t] + u);
-    const T bT = (T)((double)G[t] + v);
-    D[t] = dT;
-    BD[t] = bT;
-    const double d = (double)dT, bd = (double)bT;
-    dd += d * bd;
-    if (ref) {
-      const double s = (double)X[t] - (double)Xc[t];
-      const double bs = (double)BX[t] - (double)BXc[t];
-      const double y = d - (double)Dc[t];
-      const double by = bd - (double)BDc[t];
-      ss += s * bs;
-      sy += s * by;
-      yy += y * by;
+    __syncthreads();
+    for (int q0 = threadIdx.x; q0 < rows * groups; q0 += blockDim.x) {
+      const int r = q0 / groups;
+      const int j0 = (q0 - r * groups) * kQ1Cols;
+      const double* xr = Xs + r * p;
+      const double* br = Bs + r * p;
+      double u[kQ1Cols] = {}, v[kQ1Cols] = {};
+      for (int k = 0; k < p; ++k) {
+        const double xk = xr[k], bk = br[k];
+        const double* w = Ws + k * pc + j0;
+#pragma unroll
+        for (int q = 0; q < kQ1Cols; ++q) {
+          u[q] += xk * w[q];
+          v[q] += bk * w[q];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kQ1Cols; ++q) {
+        const int j = j0 + q;
+        if (j >= p) break;
+        const size_t o = (r0 + r) * p + j;
+        const T dT = (T)((double)Gt[o] + u[q]);
+        const T bT = (T)((double)G[o] + v[q]);
+        D[o] = dT;
+        BD[o] = bT;
+        const double d = (double)dT, bd = (double)bT;
+        dd += d * bd;
+        if (ref) {
+          const double sdx = xr[j] - (double)Xc[o];
+          const double bs = br[j] - (double)BXc[o];
+          const double y = d - (double)Dc[o];
+          const double by = bd - (double)BDc[o];
+          ss += sdx * bs;
+          sy += sdx * by;
+          yy += y * by;
+        }
+      }
     }
   }
   dd = block_sum(dd, sh);
@@ -257,8 +325,15 @@ void mass_axes(const T* in, T* out, int p, Grid g, const double* const tab[3], h
 
 }  // namespace
 
-int q1_apply_blocks(int n, int p) { return stream_blocks((size_t)n * p); }
-int q1_grad_blocks(int n, int p) { return stream_blocks((size_t)n * p); }
+int q1_apply_blocks(int n, int p) { return stream_blocks((size_t)n * p / kQ1Chunk + 1); }
+int q1_grad_blocks(int n, int p) {
+  // a few row tiles per block; at most the streaming cap
+  const int tiles = (n + kQ1Rows - 1) / kQ1Rows;
+  int b = (tiles + 3) / 4;
+  if (b > kMaxStreamBlocks) b = kMaxStreamBlocks;
+  (void)p;
+  return b < 1 ? 1 : b;
+}
 
 template <typename T>
 void launch_q1_apply(const T* X, T* G, T* BX, const double* veff, const double* vext, Grid g,
@@ -292,7 +367,8 @@ void launch_mass_solve(const T* in, T* out, int p, Grid g, const double* const t
 
 void launch_q1_grad(const Q1GradArgs& a, hipStream_t st) {
   const int nb = q1_grad_blocks(a.n, a.p);
-  const size_t lds = (size_t)a.p * a.p * sizeof(double);
+  const size_t lds = ((size_t)a.p * ((a.p + kQ1Cols - 1) / kQ1Cols * kQ1Cols) +
+                      2 * (size_t)kQ1Rows * a.p) * sizeof(double);
   if (a.f32)
     hipLaunchKernelGGL(k_q1_grad<float>, dim3(nb), dim3(kBlock), lds, st, a);
   else

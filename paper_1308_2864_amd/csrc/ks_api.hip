@@ -542,8 +542,11 @@ int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd) {
   tend(s, KS_PH_XC);
   tbeg(s, KS_PH_HAMILTONIAN);
   q1_apply(s, Xs, s->G[idx], s->BX[idx], s->veff[idx], 2.0 * s->f, &pt);
-  mass_solve(s, s->G[idx], s->Gt[idx]);
   tend(s, KS_PH_HAMILTONIAN);
+  // B^{-1} G is part of the B-metric gradient
+  tbeg(s, KS_PH_GRADIENT);
+  mass_solve(s, s->G[idx], s->Gt[idx]);
+  tend(s, KS_PH_GRADIENT);
   tbeg(s, KS_PH_GRAM);
   gram(s, Xs, s->G[idx], kGramAB);
   launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, kGramAB, s->gxg[idx], s->W, s->st);
