@@ -305,6 +305,16 @@ int ks_server_pending(ks_server* sv);
 /* Stops the workers after the running requests finish; queued requests are dropped. */
 void ks_server_destroy(ks_server* sv);
 
+/* ---- launch replay ---------------------------------------------------------------------
+ * With graphs on, ks_minimize records its trial step (retraction factor and combine,
+ * energy/gradient evaluation, line-search judgement) once per slot parity into a HIP
+ * graph on a capture stream of the system's own, and replays it with one launch per
+ * trial instead of about thirty.  The kernels and their arguments are the same, so the
+ * results are bitwise those of the eager run.  Replay needs the KS_HARTREE_PCG_FD solver
+ * (or no Hartree term) and timers off; otherwise the run is eager.  The instantiated
+ * graphs live for one ks_minimize call.  Errors: KS_E_INVAL, KS_E_HIP. */
+int ks_enable_graphs(ks_system* s, int on);
+
 /* ---- instrumentation ------------------------------------------------------------------ */
 
 /* Turns the phase timers on (on != 0) or off.  While on, the library records a pair of

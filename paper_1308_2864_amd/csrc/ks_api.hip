@@ -66,6 +66,10 @@ struct ks_system {
     int ph;
   };
   bool timers = false;
+  // optional graph replay of the trial step of ks_minimize (one graph per slot parity)
+  bool graphs = false;
+  hipStream_t cap_st = nullptr;
+  hipGraphExec_t gx[2] = {};
   std::vector<hipEvent_t> ev_free;
   std::vector<Pending> ev_pend;
   Pending ev_open[KS_NPHASES] = {};
@@ -435,8 +439,9 @@ int hartree(ks_system* s, const double* rho, const double* x0, double* x, bool w
   launch_hartree_init(rho, x0, x, s->cg_r, s->cg_p[0], s->cg, s->htol, s->hmaxit, s->grid,
                       s->cgpart, s->st);
   // first chunk sized by the previous solve (warm starts need similar counts); with the
-  // exact preconditioner one or two iterations suffice
-  const int chunk = pcg ? 2 : (s->last_cg_iters > 0 ? s->last_cg_iters + 2 : 32);
+  // exact preconditioner one iteration reaches the tolerance (alpha = 1 up to rounding),
+  // and a trial whose solve needs more is finished by the caller (hartree_pending)
+  const int chunk = pcg ? 1 : (s->last_cg_iters > 0 ? s->last_cg_iters + 2 : 32);
   return hartree_iterate(s, x, chunk, wait, iters, relres);
 }
 
@@ -668,6 +673,80 @@ LsParams to_params(const ks_opt_params& o) {
 
 }  // namespace
 
+namespace {
+
+// One trial step of Alg. 3 from slot c into slot t = 1 - c: the retraction factor and
+// combine (with the density of the trial point), the evaluation and the line-search
+// judgement, all on the device.  Nothing in it waits for the host, so it can be captured
+// into a graph; with the plain CG Hartree solver the evaluation waits for convergence.
+int enqueue_trial(ks_system* s, int c, bool qr, const LsParams& lp, const ks_opt_params& prm) {
+  const int t = 1 - c;
+  CombineArgs ca{};
+  ca.X = s->X[c];
+  ca.A = s->A;
+  ca.B = s->B;
+  ca.out = s->X[t];
+  ca.rho = s->rho;
+  ca.rho_scale = rho_scale(s);
+  ca.f32 = s->f32;
+  ca.ld = s->p;
+  ca.n = s->n;
+  ca.p = s->p;
+  tbeg(s, KS_PH_SMALL);
+  if (qr) {
+    launch_qr_factor(s->q1 ? s->feg[c] + s->pp * s->pp : s->gxg[c], s->gxd[c], s->p, s->pp,
+                     &s->ls->tau, s->A, s->B, s->work, &s->ls->error, s->st);
+    ca.Y = s->D[c];
+  } else {
+    launch_wy_factor(s->gxg[c], s->p, s->pp, &s->ls->tau, prm.reorth_tol, s->A, s->B, s->work,
+                     &s->ls->error, s->reorth_count, s->st);
+    ca.Y = s->G[c];
+  }
+  tend(s, KS_PH_SMALL);
+  tbeg(s, KS_PH_RETRACT);
+  launch_combine(ca, s->st);
+  tend(s, KS_PH_RETRACT);
+  const bool pcg = s->solver == KS_HARTREE_PCG_FD;
+  int rc = evaluate(s, t, true, c, c, qr, !qr, !pcg);
+  if (rc) return rc;
+  tbeg(s, KS_PH_SMALL);
+  launch_ls_judge(s->ev[t], s->ls, lp, s->use_h ? s->cg : nullptr, s->st);
+  tend(s, KS_PH_SMALL);
+  return launch_check(s, "line search");
+}
+
+void drop_graphs(ks_system* s) {
+  for (auto& g : s->gx) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
+}
+
+// Records enqueue_trial(c) on the capture stream into s->gx[c].  A failed capture leaves
+// gx[c] empty and the trial runs eagerly.
+int capture_trial(ks_system* s, int c, bool qr, const LsParams& lp, const ks_opt_params& prm) {
+  hipStream_t orig = s->st;
+  s->st = s->cap_st;
+  hipError_t e = hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal);
+  int rc = KS_OK;
+  if (e == hipSuccess) rc = enqueue_trial(s, c, qr, lp, prm);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(s->st, &g) : e;
+  s->st = orig;
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e2 == hipSuccess && g) {
+    if (hipGraphInstantiate(&s->gx[c], g, nullptr, nullptr, 0) != hipSuccess) s->gx[c] = nullptr;
+  }
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipGetLastError();  // a refused capture is not an error of the run
+  return KS_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void ks_default_params(ks_opt_params* o) {
@@ -803,7 +882,21 @@ void ks_destroy_system(ks_system* s) {
     if (p.b) s->ev_free.push_back(p.b);
   }
   for (hipEvent_t e : s->ev_free) (void)hipEventDestroy(e);
+  drop_graphs(s);
+  if (s->cap_st) (void)hipStreamDestroy(s->cap_st);
   delete s;
+}
+
+int ks_enable_graphs(ks_system* s, int on) {
+  if (!s) return fail(s, KS_E_INVAL, "null system");
+  if (on && !s->cap_st) {
+    int rc = hip_check(s, hipStreamCreateWithFlags(&s->cap_st, hipStreamNonBlocking),
+                       "capture stream");
+    if (rc) return rc;
+  }
+  s->graphs = on != 0;
+  drop_graphs(s);
+  return KS_OK;
 }
 
 int ks_enable_timers(ks_system* s, int on) {
@@ -1025,6 +1118,7 @@ int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* 
   const LsParams lp = to_params(prm);
   const bool qr = prm.retraction == KS_QR;
   s->cg_total = 0;
+  drop_graphs(s);  // graphs hold the parameters of the run that captured them
   int c = s->cur;
   copy_block(s, s->X[c], s->p, X_inout, s->ld);
   if (s->q1) {
@@ -1048,38 +1142,20 @@ int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* 
   if (rc) return rc;
   while (hl->stop == KS_STOP_NONE) {
     const int t = 1 - c;
-    CombineArgs ca{};
-    ca.X = s->X[c];
-    ca.A = s->A;
-    ca.B = s->B;
-    ca.out = s->X[t];
-    ca.rho = s->rho;
-    ca.rho_scale = rho_scale(s);
-    ca.f32 = s->f32;
-    ca.ld = s->p;
-    ca.n = s->n;
-    ca.p = s->p;
-    tbeg(s, KS_PH_SMALL);
-    if (qr) {
-      launch_qr_factor(s->q1 ? s->feg[c] + s->pp * s->pp : s->gxg[c], s->gxd[c], s->p, s->pp,
-                       &s->ls->tau, s->A, s->B, s->work, &s->ls->error, s->st);
-      ca.Y = s->D[c];
-    } else {
-      launch_wy_factor(s->gxg[c], s->p, s->pp, &s->ls->tau, prm.reorth_tol, s->A, s->B, s->work,
-                       &s->ls->error, s->reorth_count, s->st);
-      ca.Y = s->G[c];
-    }
-    tend(s, KS_PH_SMALL);
-    tbeg(s, KS_PH_RETRACT);
-    launch_combine(ca, s->st);
-    tend(s, KS_PH_RETRACT);
     const bool pcg = s->solver == KS_HARTREE_PCG_FD;
-    rc = evaluate(s, t, true, c, c, qr, !qr, !pcg);
-    if (rc) return rc;
-    tbeg(s, KS_PH_SMALL);
-    launch_ls_judge(s->ev[t], s->ls, lp, s->use_h ? s->cg : nullptr, s->st);
-    tend(s, KS_PH_SMALL);
-    rc = launch_check(s, "line search");
+    // graph replay from the second trial on (the first runs eagerly and initialises the
+    // launch attributes); the CG solver's host-side convergence checks cannot be captured
+    const bool replay = s->graphs && s->cap_st && (pcg || !s->use_h) && !s->timers &&
+                        hl->nfe > 1;
+    if (replay && !s->gx[c]) {
+      rc = capture_trial(s, c, qr, lp, prm);
+      if (rc) return rc;
+    }
+    if (replay && s->gx[c]) {
+      rc = hip_check(s, hipGraphLaunch(s->gx[c], s->st), "graph launch");
+    } else {
+      rc = enqueue_trial(s, c, qr, lp, prm);
+    }
     if (rc) return rc;
     if (pcg && s->use_h) {
       rc = readback2(s, hl, s->ls, host_cg(s), s->cg);
@@ -1106,6 +1182,7 @@ int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* 
       s->cur = c;
     }
   }
+  drop_graphs(s);
   copy_block(s, X_inout, s->ld, s->X[c], s->p);
   rc = launch_check(s, "minimize");
   if (rc) return rc;

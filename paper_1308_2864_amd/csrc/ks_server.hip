@@ -114,6 +114,8 @@ void run_job(ks_server* sv, Job* jb, size_t off, hipStream_t st, ks_completion* 
   }
   ks_system* sys = nullptr;
   int rc = ks_create_system(&d, ws, jb->ws_bytes, st, &sys);
+  // replayed trial graphs cut the launch overhead that dominates small systems
+  if (rc == KS_OK) (void)ks_enable_graphs(sys, 1);
   if (rc == KS_OK) rc = ks_minimize(sys, X, &jb->rq.params, &c->result);
   // a run stopped by the iteration cap still returns its last iterate
   if ((rc == KS_OK || rc == KS_E_NOT_CONVERGED) && jb->rq.X_out) {

@@ -119,6 +119,7 @@ def _load():
         "ks_gram": (ip, [vp, vp, vp, vp]),
         "ks_enable_timers": (ip, [vp, ip]),
         "ks_read_timers": (ip, [vp, C.POINTER(ks_phase_times), ip]),
+        "ks_enable_graphs": (ip, [vp, ip]),
         "ks_server_create": (ip, [vp, C.c_size_t, ip, C.POINTER(vp)]),
         "ks_server_submit": (ip, [vp, C.POINTER(ks_request)]),
         "ks_server_poll": (ip, [vp, C.POINTER(ks_completion), ip, C.POINTER(ip)]),
@@ -262,6 +263,9 @@ class KSSystem:
 
     def ks_gram(self, A, B, out):
         _check(lib.ks_gram(self.h, _ptr(A), _ptr(B), _ptr(out)), self.h)
+
+    def ks_enable_graphs(self, on=True):
+        _check(lib.ks_enable_graphs(self.h, int(bool(on))), self.h)
 
     def ks_enable_timers(self, on=True):
         _check(lib.ks_enable_timers(self.h, int(bool(on))), self.h)
