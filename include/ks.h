@@ -323,6 +323,11 @@ int ks_enable_graphs(ks_system* s, int on);
  * the timers add two event records per phase. */
 int ks_enable_timers(ks_system* s, int on);
 
+/* Restricts the timers to the phases whose bit (1u << KS_PH_*) is set in mask, so that a
+ * measurement of one kernel costs two event records per launch of that kernel only.
+ * ks_enable_timers resets the mask to all phases.  Errors: KS_E_INVAL. */
+int ks_timer_phases(ks_system* s, unsigned mask);
+
 /* Copies the accumulated phase times into *out (host); reset != 0 clears them. */
 int ks_read_timers(ks_system* s, ks_phase_times* out, int reset);
 

@@ -66,6 +66,7 @@ struct ks_system {
     int ph;
   };
   bool timers = false;
+  unsigned timer_mask = ~0u;  // phases timed while timers are on
   // optional graph replay of the trial step of ks_minimize (one graph per slot parity)
   bool graphs = false;
   hipStream_t cap_st = nullptr;
@@ -341,7 +342,7 @@ hipEvent_t take_event(ks_system* s) {
 }
 
 void tbeg(ks_system* s, int ph) {
-  if (!s->timers) return;
+  if (!s->timers || !((s->timer_mask >> ph) & 1u)) return;
   ks_system::Pending p{take_event(s), take_event(s), ph};
   if (p.a) (void)hipEventRecord(p.a, s->st);
   s->ev_open[ph] = p;
@@ -887,6 +888,12 @@ void ks_destroy_system(ks_system* s) {
   delete s;
 }
 
+int ks_timer_phases(ks_system* s, unsigned mask) {
+  if (!s) return fail(s, KS_E_INVAL, "null system");
+  s->timer_mask = mask;
+  return KS_OK;
+}
+
 int ks_enable_graphs(ks_system* s, int on) {
   if (!s) return fail(s, KS_E_INVAL, "null system");
   if (on && !s->cap_st) {
@@ -902,6 +909,7 @@ int ks_enable_graphs(ks_system* s, int on) {
 int ks_enable_timers(ks_system* s, int on) {
   if (!s) return fail(s, KS_E_INVAL, "null system");
   s->timers = on != 0;
+  s->timer_mask = ~0u;
   return KS_OK;
 }
 

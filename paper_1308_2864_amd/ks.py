@@ -120,6 +120,7 @@ def _load():
         "ks_enable_timers": (ip, [vp, ip]),
         "ks_read_timers": (ip, [vp, C.POINTER(ks_phase_times), ip]),
         "ks_enable_graphs": (ip, [vp, ip]),
+        "ks_timer_phases": (ip, [vp, C.c_uint]),
         "ks_server_create": (ip, [vp, C.c_size_t, ip, C.POINTER(vp)]),
         "ks_server_submit": (ip, [vp, C.POINTER(ks_request)]),
         "ks_server_poll": (ip, [vp, C.POINTER(ks_completion), ip, C.POINTER(ip)]),
@@ -266,6 +267,12 @@ class KSSystem:
 
     def ks_enable_graphs(self, on=True):
         _check(lib.ks_enable_graphs(self.h, int(bool(on))), self.h)
+
+    def ks_timer_phases(self, names):
+        mask = 0
+        for nm in names:
+            mask |= 1 << PHASES.index(nm)
+        _check(lib.ks_timer_phases(self.h, mask), self.h)
 
     def ks_enable_timers(self, on=True):
         _check(lib.ks_enable_timers(self.h, int(bool(on))), self.h)
