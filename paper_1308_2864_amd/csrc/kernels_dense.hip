@@ -34,6 +34,7 @@ __device__ inline d4 mfma16(double a, double b, d4 c) {
 
 constexpr int kGramMaxChunks = 512;
 constexpr int kGradMaxBlocks = 512;
+constexpr bool kFuseGram = false;
 
 // Product bits of a Gram launch: A^T A, A^T B, B^T B.  Symmetric products store only the
 // tiles ti <= tj; the reduction mirrors them.
@@ -368,6 +369,7 @@ void launch_gram_t(const T* A, const T* B, int ld, int n, int p, int mask, doubl
     if (mask == (kPAA | kPAB | kPBB))
       return launch_gram_m<T, kT, 7>(A, B, ld, n, p, part, nchunks, st);
     if (mask == (kPAA | kPAB)) return launch_gram_m<T, kT, 3>(A, B, ld, n, p, part, nchunks, st);
+    if (mask == (kPAB | kPBB)) return launch_gram_m<T, kT, 6>(A, B, ld, n, p, part, nchunks, st);
   }
   if (mask & kPAA) launch_gram_m<T, kT, 1>(A, B, ld, n, p, part, nchunks, st);
   if (mask & kPAB) launch_gram_m<T, kT, 2>(A, B, ld, n, p, part, nchunks, st);
@@ -451,7 +453,7 @@ size_t gram_part_doubles(int n, int pp) {
   return (size_t)c * 3 * pp * pp;
 }
 
-bool combine_fuses_gram(int p) { return round_up(p, 16) <= 32; }
+bool combine_fuses_gram(int p) { return round_up(p, 16) <= 32 && kFuseGram; }
 
 void launch_gram(const void* A, const void* B, bool f32, int ld, int n, int p, int mask,
                  double* partials, int nchunks, hipStream_t st) {

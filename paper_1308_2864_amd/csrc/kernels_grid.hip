@@ -144,39 +144,57 @@ __global__ void k_xc(const double* __restrict__ rho, const double* __restrict__ 
 // Y = scale * ((1/2) L X + Diag(veff) X), L = -Laplacian_h (7 points, zero Dirichlet).
 // With pt: per-block partials of sum X.(LX) and sum vext X^2 (kinetic/external energy).
 
+// A thread owns one (i, j, orbital) column and marches along z over kHxChunk planes: the
+// z neighbours of plane k are the centres of planes k-1 and k+1, which it already holds,
+// so each output costs five loads (centre and four in-plane neighbours) and the block is
+// streamed plane by plane.  Consecutive threads take consecutive orbitals of one point.
+constexpr int kHxChunk = 16;
+
 template <typename T, bool kEnergy>
-__global__ void k_hx(const T* __restrict__ X, int ldx, T* __restrict__ Y, int ldy,
-                     const double* __restrict__ veff, const double* __restrict__ vext, Grid gr,
-                     int p, double scale, Partials pt) {
+__global__ __launch_bounds__(256) void k_hx(const T* __restrict__ X, int ldx, T* __restrict__ Y,
+                                            int ldy, const double* __restrict__ veff,
+                                            const double* __restrict__ vext, Grid gr, int p,
+                                            double scale, Partials pt) {
   __shared__ double sh[kBlock / kWave];
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const size_t work = (size_t)gr.n * p;
-  size_t beg, end;
-  block_range(work, lb, gridDim.x, &beg, &end);
   const int nx = gr.nx, ny = gr.ny, nz = gr.nz;
-  const size_t sy = (size_t)nx * ldx, sz = (size_t)nx * ny * ldx;
+  const int nzc = (nz + kHxChunk - 1) / kHxChunk;
+  const size_t work = (size_t)nx * ny * p * nzc;
+  const ptrdiff_t sy = (ptrdiff_t)nx * ldx, sz = (ptrdiff_t)nx * ny * ldx;
   const double ih2 = gr.inv_h2;
   double kin = 0.0, ext = 0.0;
-  for (size_t t = beg + threadIdx.x; t < end; t += blockDim.x) {
-    const size_t g = t / (unsigned)p;
-    const int c = (int)(t - g * p);
-    const int i = (int)(g % nx);
-    const size_t gy = g / nx;
-    const int j = (int)(gy % ny), k = (int)(gy / ny);
-    const T* xp = X + g * ldx + c;
-    const double x0 = (double)xp[0];
-    double nb = 0.0;
-    if (i > 0) nb += (double)xp[-ldx];
-    if (i < nx - 1) nb += (double)xp[ldx];
-    if (j > 0) nb += (double)xp[-(ptrdiff_t)sy];
-    if (j < ny - 1) nb += (double)xp[sy];
-    if (k > 0) nb += (double)xp[-(ptrdiff_t)sz];
-    if (k < nz - 1) nb += (double)xp[sz];
-    const double lx = (6.0 * x0 - nb) * ih2;
-    Y[g * ldy + c] = (T)(scale * (0.5 * lx + veff[g] * x0));
-    if (kEnergy) {
-      kin += x0 * lx;
-      ext += vext[g] * x0 * x0;
+  for (size_t t = (size_t)lb * blockDim.x + threadIdx.x; t < work;
+       t += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(t % (unsigned)p);
+    size_t r = t / (unsigned)p;
+    const int i = (int)(r % nx);
+    r /= nx;
+    const int j = (int)(r % ny);
+    const int kc = (int)(r / ny);
+    const int k0 = kc * kHxChunk;
+    const int k1 = min(k0 + kHxChunk, nz);
+    const T* col = X + (ptrdiff_t)(i + (size_t)nx * j) * ldx + c;
+    double below = k0 > 0 ? (double)col[(k0 - 1) * sz] : 0.0;
+    double cur = (double)col[k0 * sz];
+    for (int k = k0; k < k1; ++k) {
+      const T* xp = col + k * sz;
+      const double above = k + 1 < nz ? (double)xp[sz] : 0.0;
+      double nb = 0.0;
+      if (i > 0) nb += (double)xp[-ldx];
+      if (i < nx - 1) nb += (double)xp[ldx];
+      if (j > 0) nb += (double)xp[-sy];
+      if (j < ny - 1) nb += (double)xp[sy];
+      nb += below;
+      nb += above;
+      const double lx = (6.0 * cur - nb) * ih2;
+      const size_t g = i + (size_t)nx * (j + (size_t)ny * k);
+      Y[g * ldy + c] = (T)(scale * (0.5 * lx + veff[g] * cur));
+      if (kEnergy) {
+        kin += cur * lx;
+        ext += vext[g] * cur * cur;
+      }
+      below = cur;
+      cur = above;
     }
   }
   if (kEnergy) {
@@ -188,21 +206,6 @@ __global__ void k_hx(const T* __restrict__ X, int ldx, T* __restrict__ Y, int ld
 }
 
 // ---- fixed-order reduction of per-block partials: one block per slot ---------------
-
-struct NBlk {
-  int v[kMaxScalarSlots];
-};
-
-__global__ void k_reduce_scalars(const double* __restrict__ part, int stride, NBlk nb,
-                                 double* __restrict__ out) {
-  __shared__ double sh[kBlock / kWave];
-  const int s = blockIdx.x;
-  const int m = nb.v[s];
-  double v = 0.0;
-  for (int i = threadIdx.x; i < m; i += blockDim.x) v += part[(size_t)s * stride + i];
-  v = block_sum(v, sh);
-  if (threadIdx.x == 0) out[s] = v;
-}
 
 }  // namespace
 
@@ -256,7 +259,7 @@ void launch_xc(const double* rho, const double* vh, const double* vext, double* 
 template <typename T>
 void launch_hx(const T* X, int ldx, T* Y, int ldy, const double* veff, const double* vext,
                Grid g, int p, double scale, Partials* pt, hipStream_t st) {
-  const int nb = stream_blocks((size_t)g.n * p);
+  const int nb = hx_blocks(g.n, p);
   if (pt) {
     hipLaunchKernelGGL((k_hx<T, true>), dim3(nb), dim3(kBlock), 0, st, X, ldx, Y, ldy, veff,
                        vext, g, p, scale, *pt);
@@ -271,14 +274,7 @@ template void launch_hx<double>(const double*, int, double*, int, const double*,
 template void launch_hx<float>(const float*, int, float*, int, const double*, const double*,
                                Grid, int, double, Partials*, hipStream_t);
 
-int hx_blocks(size_t work) { return stream_blocks(work); }
+int hx_blocks(int n, int p) { return stream_blocks((size_t)n * p / kHxChunk + 1); }
 
-void launch_reduce_scalars(const double* part, int stride, const int* nblk, int nslots,
-                           double* out, hipStream_t st) {
-  NBlk nb{};
-  for (int i = 0; i < nslots && i < kMaxScalarSlots; ++i) nb.v[i] = nblk[i];
-  hipLaunchKernelGGL(k_reduce_scalars, dim3(nslots), dim3(kBlock), 0, st, part, stride, nb,
-                     out);
-}
 
 }  // namespace ks

@@ -205,64 +205,100 @@ __global__ void k_qr_factor(const double* __restrict__ xx, const double* __restr
   blk_store_padded(B, pp, W, p, p, -tau);
 }
 
-// Single-wavefront variant for p <= P (P = 16, 32, 64): lane j owns column j of Y^T Y.
-// The matrix, the broadcast row of R and R^{-1} live in separate LDS arrays with
-// compile-time strides, every step is a short runtime loop, and with one wavefront the
-// barriers are nearly free.
+// Element-parallel variant for p <= P (P = 16, 32, 64): the P x P matrix Y^T Y lives in
+// registers, one element per thread (four per thread for P = 64), and both the
+// right-looking Cholesky and the back substitution for R^{-1} run as p rank-1 steps in
+// which every thread updates its own elements; a step costs two barriers instead of a
+// serial loop over a column.  Rows/columns k are broadcast through LDS, double-buffered
+// by step parity.
 template <int P>
-__global__ __launch_bounds__(64) void k_qr_factor_wave(const double* __restrict__ xx,
+__global__ __launch_bounds__(1024) void k_qr_factor_2d(const double* __restrict__ xx,
                                                        const double* __restrict__ gxd, int p,
                                                        int pp, const double* __restrict__ tau_p,
                                                        double* __restrict__ A,
                                                        double* __restrict__ B, int* status) {
-  __shared__ double M[P][P + 1];
-  __shared__ double W[P][P + 1];
-  __shared__ double rowk[P];
+  constexpr int kT = P * P < 1024 ? P * P : 1024;  // threads
+  constexpr int kE = P * P / kT;                   // elements per thread
+  __shared__ double row[2][P];
   __shared__ double dg[P];
-  const int j = threadIdx.x;
+  __shared__ double Rs[P][P + 1];
+  __shared__ int bad;
+  const int t = threadIdx.x;
   const double tau = *tau_p;
   const double* XD = gxd + pp * pp;
   const double* DD = gxd + 2 * pp * pp;
-  for (int e = j; e < p * p; e += 64) {
-    const int i = e / p, c = e % p;
-    M[i][c] = xx[i * pp + c] - tau * (XD[i * pp + c] + XD[c * pp + i]) + tau * tau * DD[i * pp + c];
+  int ei[kE], ej[kE];
+  double a[kE];
+#pragma unroll
+  for (int q = 0; q < kE; ++q) {
+    const int e = t + q * kT;
+    ei[q] = e / P;
+    ej[q] = e % P;
+    const int i = ei[q], j = ej[q];
+    a[q] = (i < p && j < p) ? xx[i * pp + j] - tau * (XD[i * pp + j] + XD[j * pp + i]) +
+                                  tau * tau * DD[i * pp + j]
+                            : 0.0;
+    if (i == j && i < p) dg[i] = a[q];
   }
+  if (t == 0) bad = 0;
   __syncthreads();
-  if (j < p) dg[j] = M[j][j];
-  __syncthreads();
-  int bad = 0;
+  // Cholesky M = R^T R (upper R): step k takes the pivot, scales row k, updates the rest
   for (int k = 0; k < p; ++k) {
-    const double d = M[k][k];
-    if (!(d > kPivotTol * dg[k]) || !isfinite(d)) bad = 1;
-    const double rkk = sqrt(d);
+    double* rk = row[k & 1];
+#pragma unroll
+    for (int q = 0; q < kE; ++q)
+      if (ei[q] == k && ej[q] == k) {
+        const double d = a[q];
+        if (!(d > kPivotTol * dg[k]) || !isfinite(d)) bad = 1;
+        a[q] = sqrt(d);
+        rk[k] = a[q];
+      }
     __syncthreads();
-    double rk = 0.0;
-    if (j >= k && j < p) {
-      rk = (j == k) ? rkk : M[k][j] / rkk;
-      M[k][j] = rk;
-      rowk[j] = rk;
-    }
+    const double rkk = rk[k];
+#pragma unroll
+    for (int q = 0; q < kE; ++q)
+      if (ei[q] == k && ej[q] > k && ej[q] < p) {
+        a[q] /= rkk;
+        rk[ej[q]] = a[q];
+      }
     __syncthreads();
-    if (j > k && j < p)
-      for (int i = k + 1; i <= j; ++i) M[i][j] -= rowk[i] * rk;
-    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kE; ++q)
+      if (ei[q] > k && ej[q] >= ei[q] && ej[q] < p) a[q] -= rk[ei[q]] * rk[ej[q]];
   }
+  __syncthreads();
   if (bad) {
-    if (j == 0) *status = KS_E_NOT_SPD;
+    if (t == 0) *status = KS_E_NOT_SPD;
     return;
   }
-  // W = R^{-1}: W[i][j] = (delta_ij - sum_{i < m <= j} R[i][m] W[m][j]) / R[i][i]
-  if (j < p) {
-    for (int i = p - 1; i >= 0; --i) {
-      double acc = (i == j) ? 1.0 : 0.0;
-      for (int m = i + 1; m <= j; ++m) acc -= M[i][m] * W[m][j];
-      W[i][j] = (i <= j) ? acc / M[i][i] : 0.0;
-    }
-  }
+  // R to LDS (upper part), then R W = I by back substitution over rows m = p-1 .. 0:
+  // S_ij starts at delta_ij; row m of W is S_mj / R_mm, and every row above subtracts
+  // R_im W_mj.
+#pragma unroll
+  for (int q = 0; q < kE; ++q) Rs[ei[q]][ej[q]] = (ej[q] >= ei[q]) ? a[q] : 0.0;
+  double w[kE];
+#pragma unroll
+  for (int q = 0; q < kE; ++q) w[q] = (ei[q] == ej[q]) ? 1.0 : 0.0;
   __syncthreads();
-  if (j < pp) {
-    for (int i = 0; i < pp; ++i) {
-      const double v = (i < p && j < p) ? W[i][j] : 0.0;
+  for (int m = p - 1; m >= 0; --m) {
+    double* wm = row[m & 1];
+    const double rmm = Rs[m][m];
+#pragma unroll
+    for (int q = 0; q < kE; ++q)
+      if (ei[q] == m) {
+        w[q] = (ej[q] >= m && ej[q] < p) ? w[q] / rmm : 0.0;
+        wm[ej[q]] = w[q];
+      }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kE; ++q)
+      if (ei[q] < m && ej[q] >= m && ej[q] < p) w[q] -= Rs[ei[q]][m] * wm[ej[q]];
+  }
+#pragma unroll
+  for (int q = 0; q < kE; ++q) {
+    const int i = ei[q], j = ej[q];
+    if (i < pp && j < pp) {
+      const double v = (i < p && j < p && j >= i) ? w[q] : 0.0;
       A[i * pp + j] = v;
       B[i * pp + j] = -tau * v;
     }
@@ -371,29 +407,81 @@ __global__ void k_grad_weights(const double* __restrict__ gram, int pp, double* 
 }
 
 // ---- evaluation summary ----------------------------------------------------------------
-__global__ void k_finish_eval(const double* __restrict__ sums, const double* __restrict__ xx,
-                              int p, int pp, double f, double dV, const double* enuc,
-                              const CgState* cg, EvalOut* out) {
-  __shared__ double sh[kBlock / kWave];
+__device__ void ls_judge(const EvalOut* ev, LsState* ls, const LsParams& prm, const CgState* cg);
+
+// The evaluation summary: sums the per-block partials of every scalar slot (fixed
+// order), forms the energy terms, ||X^T X - I||_F (or X^T B X) from the Gram block and,
+// with ls, runs the line-search judgement on the result (one launch for all three).
+// Deterministic sum over a block of kFinishThreads threads (fixed tree order); valid in
+// thread 0.  sh holds kFinishThreads / kWave doubles.
+constexpr int kFinishThreads = 1024;
+
+__device__ inline double block_sum_wide(double v, double* sh) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < kFinishThreads / kWave; ++i) s += sh[i];
+  __syncthreads();
+  return s;
+}
+
+__global__ __launch_bounds__(1024) void k_finish_eval(const double* __restrict__ part,
+                                                     int stride, ScalarCounts nb,
+                                                     double* __restrict__ sums,
+                                                     const double* __restrict__ xx, int p,
+                                                     int pp, double f, double dV,
+                                                     const double* enuc, const CgState* cg,
+                                                     EvalOut* out, LsState* ls, LsParams prm) {
+  __shared__ double sh[kFinishThreads / kWave];
+  __shared__ double red[SL_COUNT];
+  // all slots in one sweep: each thread keeps SL_COUNT running sums, so its loads of the
+  // different slots are independent and overlap
+  int mx = 0;
+#pragma unroll
+  for (int sl = 0; sl < SL_COUNT; ++sl) mx = nb.v[sl] > mx ? nb.v[sl] : mx;
+  double v[SL_COUNT];
+#pragma unroll
+  for (int sl = 0; sl < SL_COUNT; ++sl) v[sl] = 0.0;
+  for (int i = threadIdx.x; i < mx; i += blockDim.x) {
+    // clamped, unconditional loads: no branch separates them, so they issue together
+    double x[SL_COUNT];
+#pragma unroll
+    for (int sl = 0; sl < SL_COUNT; ++sl) {
+      const int n = nb.v[sl];
+      x[sl] = n > 0 ? part[(size_t)sl * stride + (i < n ? i : n - 1)] : 0.0;
+    }
+#pragma unroll
+    for (int sl = 0; sl < SL_COUNT; ++sl) v[sl] += (i < nb.v[sl]) ? x[sl] : 0.0;
+  }
+#pragma unroll
+  for (int sl = 0; sl < SL_COUNT; ++sl) {
+    const double t = block_sum_wide(v[sl], sh);
+    if (threadIdx.x == 0) red[sl] = t;
+  }
   double acc = 0.0;
   for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
     const int i = e / p, j = e % p;
     const double d = xx[i * pp + j] - (i == j ? 1.0 : 0.0);
     acc += d * d;
   }
-  acc = block_sum(acc, sh);
+  acc = block_sum_wide(acc, sh);
   if (threadIdx.x != 0) return;
+  for (int sl = 0; sl < SL_COUNT; ++sl) sums[sl] = red[sl];
   EvalOut o;
-  o.kinetic = 0.5 * f * sums[SL_KIN];
-  o.external = f * sums[SL_EXT];
-  o.hartree = 0.5 * dV * sums[SL_EH];
-  o.xc = dV * sums[SL_EX];
+  o.kinetic = 0.5 * f * red[SL_KIN];
+  o.external = f * red[SL_EXT];
+  o.hartree = 0.5 * dV * red[SL_EH];
+  o.xc = dV * red[SL_EX];
   o.nuclear = *enuc;
   o.total = o.kinetic + o.external + o.hartree + o.xc + o.nuclear;
-  o.g2 = sums[SL_DD];
-  o.ss = sums[SL_SS];
-  o.sy = sums[SL_SY];
-  o.yy = sums[SL_YY];
+  o.g2 = red[SL_DD];
+  o.ss = red[SL_SS];
+  o.sy = red[SL_SY];
+  o.yy = red[SL_YY];
   o.orth2 = acc;
   if (cg) {
     o.cg_iters = cg->it;
@@ -404,6 +492,7 @@ __global__ void k_finish_eval(const double* __restrict__ sums, const double* __r
   }
   o.nonfinite = (!isfinite(o.total) || !isfinite(o.g2)) ? 1 : 0;
   *out = o;
+  if (ls) ls_judge(&o, ls, prm, cg);
 }
 
 __global__ void k_set_scalar(double* d, double v) { *d = v; }
@@ -457,7 +546,8 @@ __global__ void k_ls_init(const EvalOut* ev, LsState* ls, LsParams prm) {
   *ls = s;
 }
 
-__global__ void k_ls_judge(const EvalOut* ev, LsState* ls, LsParams prm, const CgState* cg) {
+__device__ void ls_judge(const EvalOut* ev, LsState* ls, const LsParams& prm,
+                         const CgState* cg) {
   LsState s = *ls;
   if (cg && !cg->done) {
     // the Hartree potential of this trial is not converged yet: the host finishes the
@@ -515,6 +605,7 @@ __global__ void k_ls_judge(const EvalOut* ev, LsState* ls, LsParams prm, const C
   *ls = s;
 }
 
+
 size_t query_lds_limit() {
   int dev = 0, v = 0;
   (void)hipGetDevice(&dev);
@@ -564,17 +655,17 @@ void launch_grad_weights(const double* gram, int pp, double* W, hipStream_t st) 
 void launch_qr_factor(const double* xx, const double* gxd, int p, int pp, const double* tau,
                       double* A, double* B, double* work, int* status, hipStream_t st) {
   if (p <= 16) {
-    hipLaunchKernelGGL(k_qr_factor_wave<16>, dim3(1), dim3(64), 0, st, xx, gxd, p, pp, tau, A,
-                       B, status);
+    hipLaunchKernelGGL(k_qr_factor_2d<16>, dim3(1), dim3(256), 0, st, xx, gxd, p, pp, tau, A, B,
+                       status);
     return;
   }
   if (p <= 32) {
-    hipLaunchKernelGGL(k_qr_factor_wave<32>, dim3(1), dim3(64), 0, st, xx, gxd, p, pp, tau, A,
+    hipLaunchKernelGGL(k_qr_factor_2d<32>, dim3(1), dim3(1024), 0, st, xx, gxd, p, pp, tau, A,
                        B, status);
     return;
   }
   if (p <= 64) {
-    hipLaunchKernelGGL(k_qr_factor_wave<64>, dim3(1), dim3(64), 0, st, xx, gxd, p, pp, tau, A,
+    hipLaunchKernelGGL(k_qr_factor_2d<64>, dim3(1), dim3(1024), 0, st, xx, gxd, p, pp, tau, A,
                        B, status);
     return;
   }
@@ -593,11 +684,14 @@ void launch_wy_factor(const double* gram_xg, int p, int pp, const double* tau,
                      tau, reorth_tol, A, B, lds ? nullptr : work, status, reorth_flag);
 }
 
-void launch_finish_eval(const double* sums, const double* gram_xx, int p, int pp, double f,
-                        double dV, const double* enuc, const CgState* cg, EvalOut* out,
-                        hipStream_t st) {
-  hipLaunchKernelGGL(k_finish_eval, dim3(1), dim3(kBlock), 0, st, sums, gram_xx, p, pp, f, dV,
-                     enuc, cg, out);
+void launch_finish_eval(const double* part, int stride, const int* nblk, double* sums,
+                        const double* gram_xx, int p, int pp, double f, double dV,
+                        const double* enuc, const CgState* cg, EvalOut* out, LsState* ls,
+                        const LsParams* prm, hipStream_t st) {
+  ScalarCounts nb{};
+  for (int i = 0; i < SL_COUNT; ++i) nb.v[i] = nblk[i];
+  hipLaunchKernelGGL(k_finish_eval, dim3(1), dim3(kFinishThreads), 0, st, part, stride, nb, sums,
+                     gram_xx, p, pp, f, dV, enuc, cg, out, ls, prm ? *prm : LsParams{});
 }
 
 void launch_set_scalar(double* dst, double v, hipStream_t st) {
@@ -608,9 +702,5 @@ void launch_ls_init(const EvalOut* ev, LsState* ls, LsParams prm, hipStream_t st
   hipLaunchKernelGGL(k_ls_init, dim3(1), dim3(1), 0, st, ev, ls, prm);
 }
 
-void launch_ls_judge(const EvalOut* ev, LsState* ls, LsParams prm, const CgState* cg,
-                     hipStream_t st) {
-  hipLaunchKernelGGL(k_ls_judge, dim3(1), dim3(1), 0, st, ev, ls, prm, cg);
-}
 
 }  // namespace ks

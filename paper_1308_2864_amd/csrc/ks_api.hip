@@ -144,7 +144,7 @@ void layout(ks_system* s, char* base, size_t* total) {
   s->spart = c.take<double>((size_t)SL_COUNT * kPartStride);
   s->cgpart = c.take<double>(hartree_part_doubles());
   s->cg = c.take<CgState>(1);
-  s->ls = c.take<LsState>(1);
+  s->ls = c.take<LsState>(1);  // 256 bytes after cg, mirrored on the host the same way
   s->status = c.take<int>(1);
   s->reorth_count = c.take<int>(1);
   *total = c.off + 256;
@@ -299,22 +299,24 @@ void gram(ks_system* s, const void* A, const void* B, int mask) {
   launch_gram(A, B, s->f32, s->p, s->n, s->p, mask, s->gram_part, s->gram_nchunks, s->st);
 }
 
+// Pinned host mirror: CgState at 0 and LsState at 256 (the same offsets as on the device,
+// so one copy brings both back), EvalOut at 512, ints at 768.
 CgState* host_cg(ks_system* s) { return reinterpret_cast<CgState*>(s->host); }
-EvalOut* host_ev(ks_system* s) {
-  return reinterpret_cast<EvalOut*>(static_cast<char*>(s->host) + 256);
-}
 LsState* host_ls(ks_system* s) {
-  return reinterpret_cast<LsState*>(static_cast<char*>(s->host) + 512);
+  return reinterpret_cast<LsState*>(static_cast<char*>(s->host) + 256);
+}
+EvalOut* host_ev(ks_system* s) {
+  return reinterpret_cast<EvalOut*>(static_cast<char*>(s->host) + 512);
 }
 int* host_int(ks_system* s) { return reinterpret_cast<int*>(static_cast<char*>(s->host) + 768); }
 
 void harvest(ks_system* s);
 
-// Two records with one synchronisation.
-template <typename T, typename U>
-int readback2(ks_system* s, T* h1, const T* d1, U* h2, const U* d2) {
-  hipError_t e = hipMemcpyAsync(h1, d1, sizeof(T), hipMemcpyDeviceToHost, s->st);
-  if (e == hipSuccess) e = hipMemcpyAsync(h2, d2, sizeof(U), hipMemcpyDeviceToHost, s->st);
+// The CG and line-search records with one copy and one synchronisation (they are
+// adjacent on the device, see layout()).
+int readback_cg_ls(ks_system* s) {
+  const size_t bytes = reinterpret_cast<char*>(s->ls + 1) - reinterpret_cast<char*>(s->cg);
+  hipError_t e = hipMemcpyAsync(s->host, s->cg, bytes, hipMemcpyDeviceToHost, s->st);
   if (e == hipSuccess) e = hipStreamSynchronize(s->st);
   if (e == hipSuccess && s->timers) harvest(s);
   return hip_check(s, e, "read-back");
@@ -450,11 +452,13 @@ int hartree(ks_system* s, const double* rho, const double* x0, double* x, bool w
 // rho of X[idx] is either ready (fused into the retraction) or computed here.  With
 // bb_ref >= 0 the gradient epilogue also forms the BB sums against slot bb_ref.
 // warm: slot whose V_H starts the CG.  Writes G, D, gram blocks, sums, ev of the slot.
-int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg);
-int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd);
+int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg,
+                  const LsParams* judge = nullptr);
+int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd, const LsParams* judge);
 
+// With judge, the summary kernel also runs the line-search judgement of the trial.
 int evaluate(ks_system* s, int idx, bool rho_ready, int bb_ref, int warm, bool want_gxd,
-             bool want_gg, bool wait_hartree = true) {
+             bool want_gg, bool wait_hartree = true, const LsParams* judge = nullptr) {
   const double scale = s->f / s->grid.dV;
   (void)scale;
   const void* Xs = s->X[idx];
@@ -469,13 +473,14 @@ int evaluate(ks_system* s, int idx, bool rho_ready, int bb_ref, int warm, bool w
     rc = hartree(s, s->rho, s->vh[warm], s->vh[idx], wait_hartree, nullptr, nullptr);
     if (rc) return rc;
   }
-  return evaluate_tail(s, idx, bb_ref, want_gxd, want_gg);
+  return evaluate_tail(s, idx, bb_ref, want_gxd, want_gg, judge);
 }
 
 // Everything after the Hartree solve: exchange, Hamiltonian, Gram blocks, gradient,
 // reductions and the evaluation summary of slot idx.
-int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg) {
-  if (s->q1) return evaluate_tail_q1(s, idx, bb_ref, want_gxd);
+int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg,
+                  const LsParams* judge) {
+  if (s->q1) return evaluate_tail_q1(s, idx, bb_ref, want_gxd, judge);
   const void* Xs = s->X[idx];
   Partials pt{s->spart, kPartStride};
   tbeg(s, KS_PH_XC);
@@ -522,14 +527,13 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
     launch_gram_reduce(s->gram_part, fused ? combine_blocks_gram(s->n) : s->gram_nchunks, s->pp,
                        mask2, s->gxd[idx], nullptr, s->st);
   int nblk[kMaxScalarSlots] = {};
-  const int hb = std::min((s->n * s->p + kBlock - 1) / kBlock, kPartStride);
-  nblk[SL_KIN] = nblk[SL_EXT] = std::max(hb, 1);
+  nblk[SL_KIN] = nblk[SL_EXT] = hx_blocks(s->n, s->p);
   nblk[SL_EH] = nblk[SL_EX] = scalar_blocks(s->n);
   nblk[SL_DD] = nblk[SL_SS] = nblk[SL_SY] = nblk[SL_YY] =
       fused ? combine_blocks_gram(s->n) : combine_blocks(s->n);
-  launch_reduce_scalars(s->spart, kPartStride, nblk, SL_COUNT, s->sums[idx], s->st);
-  launch_finish_eval(s->sums[idx], s->gxg[idx], s->p, s->pp, s->f, s->grid.dV, s->enuc,
-                     s->use_h ? s->cg : nullptr, s->ev[idx], s->st);
+  launch_finish_eval(s->spart, kPartStride, nblk, s->sums[idx], s->gxg[idx], s->p, s->pp, s->f,
+                     s->grid.dV, s->enuc, s->use_h ? s->cg : nullptr, s->ev[idx],
+                     judge ? s->ls : nullptr, judge, s->st);
   tend(s, KS_PH_SMALL);
   return launch_check(s, "evaluate");
 }
@@ -538,7 +542,7 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
 // M = G^T X, D = grad E = Gt - X M and BD = B D = G - BX M (same weights), the Gram blocks
 // X^T B X (orthonormality and the Cholesky of the retraction), X^T BD and D^T BD (with
 // want_gxd), ||D||_B^2 and the BB sums of the B metric against slot bb_ref.
-int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd) {
+int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd, const LsParams* judge) {
   const void* Xs = s->X[idx];
   const int pp2 = s->pp * s->pp;
   Partials pt{s->spart, kPartStride};
@@ -598,9 +602,9 @@ int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd) {
   nblk[SL_KIN] = nblk[SL_EXT] = q1_apply_blocks(s->n, s->p);
   nblk[SL_EH] = nblk[SL_EX] = scalar_blocks(s->n);
   nblk[SL_DD] = nblk[SL_SS] = nblk[SL_SY] = nblk[SL_YY] = q1_grad_blocks(s->n, s->p);
-  launch_reduce_scalars(s->spart, kPartStride, nblk, SL_COUNT, s->sums[idx], s->st);
-  launch_finish_eval(s->sums[idx], s->feg[idx] + pp2, s->p, s->pp, s->f, s->grid.dV, s->enuc,
-                     s->use_h ? s->cg : nullptr, s->ev[idx], s->st);
+  launch_finish_eval(s->spart, kPartStride, nblk, s->sums[idx], s->feg[idx] + pp2, s->p, s->pp,
+                     s->f, s->grid.dV, s->enuc, s->use_h ? s->cg : nullptr, s->ev[idx],
+                     judge ? s->ls : nullptr, judge, s->st);
   tend(s, KS_PH_SMALL);
   return launch_check(s, "evaluate");
 }
@@ -708,11 +712,8 @@ int enqueue_trial(ks_system* s, int c, bool qr, const LsParams& lp, const ks_opt
   launch_combine(ca, s->st);
   tend(s, KS_PH_RETRACT);
   const bool pcg = s->solver == KS_HARTREE_PCG_FD;
-  int rc = evaluate(s, t, true, c, c, qr, !qr, !pcg);
+  int rc = evaluate(s, t, true, c, c, qr, !qr, !pcg, &lp);
   if (rc) return rc;
-  tbeg(s, KS_PH_SMALL);
-  launch_ls_judge(s->ev[t], s->ls, lp, s->use_h ? s->cg : nullptr, s->st);
-  tend(s, KS_PH_SMALL);
   return launch_check(s, "line search");
 }
 
@@ -1166,7 +1167,7 @@ int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* 
     }
     if (rc) return rc;
     if (pcg && s->use_h) {
-      rc = readback2(s, hl, s->ls, host_cg(s), s->cg);
+      rc = readback_cg_ls(s);
       if (rc == KS_OK && !hl->hartree_pending) s->cg_total += host_cg(s)->it;
     } else {
       rc = readback(s, hl, s->ls);
@@ -1177,9 +1178,8 @@ int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* 
       // and evaluate the trial again
       rc = hartree_iterate(s, s->vh[t], 2, true, nullptr, nullptr);
       if (rc) return rc;
-      rc = evaluate_tail(s, t, c, qr, !qr);
+      rc = evaluate_tail(s, t, c, qr, !qr, &lp);
       if (rc) return rc;
-      launch_ls_judge(s->ev[t], s->ls, lp, s->use_h ? s->cg : nullptr, s->st);
       rc = readback(s, hl, s->ls);
       if (rc) return rc;
       if (hl->hartree_pending) return fail(s, KS_E_NOT_CONVERGED, "Hartree solve did not converge");

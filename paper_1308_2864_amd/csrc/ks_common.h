@@ -60,6 +60,10 @@ struct LsParams {
   int max_iter, bb_rule, h_max, retraction;
 };
 
+struct ScalarCounts {
+  int v[SL_COUNT];  // partial blocks per scalar slot
+};
+
 struct LsState {
   double E, g2;        // at the current iterate X_k
   double C, Q;         // nonmonotone reference value and weight
@@ -74,6 +78,11 @@ struct LsState {
   int error;           // KS_E_* raised by a device step
   int hartree_pending; // the trial's Hartree solve had not converged: nothing was judged
 };
+
+// The device records are carved at 256-byte boundaries and mirrored at fixed offsets in a
+// 1 KiB pinned host buffer.
+static_assert(sizeof(CgState) <= 256 && sizeof(LsState) <= 256 && sizeof(EvalOut) <= 256,
+              "scalar records must fit their 256-byte slots");
 
 // Constants of the discretisation, passed by value to kernels.
 struct Grid {
@@ -135,10 +144,8 @@ void launch_xc(const double* rho, const double* vh, const double* vext, double* 
 template <typename T>
 void launch_hx(const T* X, int ldx, T* Y, int ldy, const double* veff, const double* vext,
                Grid g, int p, double scale, Partials* pt, hipStream_t st);
+int hx_blocks(int n, int p);  // blocks (and energy partials) of launch_hx
 int scalar_blocks(int n);
-void launch_reduce_scalars(const double* part, int stride, const int* nblk, int nslots,
-                           double* out, hipStream_t st);
-
 // Hartree solver (kernels_poisson.hip)
 struct FdOps {
   const double *Sx, *Sy, *Sz;   // sine-transform matrices per axis
@@ -225,12 +232,12 @@ void launch_wy_factor(const double* gram_xg, int p, int pp, const double* tau,
 size_t small_work_doubles(int p);
 void launch_ls_reset(LsState* ls, hipStream_t st);
 void launch_compact_gram(const double* gram, int pp, int p, double* out, hipStream_t st);
-void launch_finish_eval(const double* sums, const double* gram_xx, int p, int pp, double f,
-                        double dV, const double* enuc, const CgState* cg, EvalOut* out,
-                        hipStream_t st);
+// Sums the scalar partials (nblk[slot] blocks per slot, slot stride `stride`) into sums,
+// writes the evaluation summary and, with ls, judges the trial (Alg. 3 line search).
+void launch_finish_eval(const double* part, int stride, const int* nblk, double* sums,
+                        const double* gram_xx, int p, int pp, double f, double dV,
+                        const double* enuc, const CgState* cg, EvalOut* out, LsState* ls,
+                        const LsParams* prm, hipStream_t st);
 void launch_set_scalar(double* dst, double v, hipStream_t st);
 void launch_ls_init(const EvalOut* ev, LsState* ls, LsParams prm, hipStream_t st);
-void launch_ls_judge(const EvalOut* ev, LsState* ls, LsParams prm, const CgState* cg,
-                     hipStream_t st);
-
 }  // namespace ks

@@ -33,7 +33,7 @@ def box():
         fh.write(f"E_box = {repr(float(lam[:4].sum()))}\n")
 
 
-def oracle_run(cfg, seed=0, kind="qr", eps_g=1e-8, stagnation_tol=0.0):
+def oracle_run(cfg, seed=0, kind="qr", eps_g=1e-8, stagnation_tol=0.0, tag=""):
     from oracle import optm
     from oracle.ks import KSSystemFD
     from paper_1308_2864_amd import synth
@@ -52,7 +52,7 @@ def oracle_run(cfg, seed=0, kind="qr", eps_g=1e-8, stagnation_tol=0.0):
                                                           max_iter=20000),
                         callback=progress)
     el = time.time() - t
-    fn = os.path.join(HERE, f"oracle_{cfg}_s{seed}_{kind}.txt")
+    fn = os.path.join(HERE, f"oracle_{cfg}_s{seed}_{kind}{tag}.txt")
     with open(fn, "w") as fh:
         fh.write(f"# FP64 oracle, Alg. 3 with the {kind.upper()} retraction, config {cfg} seed {seed},\n")
         fh.write(f"# eps_g = {eps_g}, stagnation tol = {stagnation_tol}; stopped by {res.stop} "
@@ -104,4 +104,5 @@ if __name__ == "__main__":
         oracle_run(what, int(sys.argv[2]) if len(sys.argv) > 2 else 0,
                    sys.argv[3] if len(sys.argv) > 3 else "qr",
                    float(sys.argv[4]) if len(sys.argv) > 4 else 1e-8,
-                   float(sys.argv[5]) if len(sys.argv) > 5 else 0.0)
+                   float(sys.argv[5]) if len(sys.argv) > 5 else 0.0,
+                   sys.argv[6] if len(sys.argv) > 6 else "")
