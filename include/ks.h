@@ -32,7 +32,7 @@
  *   built for this form, and each axis holds at most 128 nodes.
  * - Memory.  The caller owns every device buffer, including the workspace handed
  *   to ks_create_system; the library never allocates or frees device memory.
- *   The library allocates a small pinned host buffer per system for scalar
+ *   The library allocates a 9 KiB pinned host buffer per system for scalar
  *   read-back (freed by ks_destroy_system).
  * - Streams.  Work of a system is issued on the HIP stream given at creation.  All
  *   calls below return after that stream has finished the call's work
@@ -228,6 +228,18 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
  * KS_OK when the gradient or stagnation test stopped the run, KS_E_NOT_CONVERGED at
  * max_iter (r filled), or an error code. */
 int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* r);
+
+/* Runs ks_minimize on count (1..16) systems in lockstep: each kernel of a trial step is one
+ * launch for all of them (every system reads its own argument record and keeps the block
+ * partition of its lone run), so each result equals that system's lone ks_minimize bit for
+ * bit while small systems share the launch cost.  Requires the finite-difference form,
+ * the KS_HARTREE_PCG_FD solver with the Hartree term, the QR retraction, p <= 32 and
+ * timers off; systems of either storage precision may be mixed.  The launches go to the
+ * first system's stream.  r[i] and codes[i] (host, either may be NULL) receive each
+ * system's statistics and ks_minimize return code (KS_E_UNSUPPORTED for a system outside
+ * these limits).  Returns KS_OK, or the first error other than KS_E_NOT_CONVERGED. */
+int ks_minimize_batch(ks_system* const* sys, int count, void* const* X_inout,
+                      const ks_opt_params* o, ks_result* r, int* codes);
 
 /* ---- step-level calls (each is one step of ks_energy_grad) -------------------------- */
 

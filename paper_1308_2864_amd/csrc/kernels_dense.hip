@@ -76,14 +76,22 @@ __device__ inline void put_tile(double* part, int blk, int prod, int ti, int tj,
 
 // ---- Gram: per-chunk partials -------------------------------------------------------
 template <typename T, int kT, int kMask>
-__global__ __launch_bounds__(256) void k_gram(const T* __restrict__ A, const T* __restrict__ B,
-                                              int ld, int n, int p, double* __restrict__ part) {
+__device__ inline void k_gram_body(const GramArgs<T>& ka, int ks_bid, int ks_nb) {
+  const T* __restrict__ A = ka.A;
+  const T* __restrict__ B = ka.B;
+  int ld = ka.ld;
+  int n = ka.n;
+  int p = ka.p;
+  double* __restrict__ part = ka.part;
+  (void)ks_bid;
+  (void)ks_nb;
+
   constexpr int kPP = kT * 16;
   constexpr int kAcc = GramTiles<kT, kMask>::kN;
   extern __shared__ double lds[];
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int lr = lane / 16, lc = lane % 16;
-  const int chunk = blockIdx.x, nchunks = gridDim.x;
+  const int chunk = ks_bid, nchunks = ks_nb;
   const int ngroups = (n + 3) / 4;
   const int per = (ngroups + nchunks - 1) / nchunks;
   const int g_beg = chunk * per, g_end = min(ngroups, g_beg + per);
@@ -148,18 +156,36 @@ __global__ __launch_bounds__(256) void k_gram(const T* __restrict__ A, const T* 
   }
 }
 
+template <typename T, int kT, int kMask>
+__global__ __launch_bounds__(256) void k_gram(GramArgs<T> ka) {
+  k_gram_body<T, kT, kMask>(ka, blockIdx.x, gridDim.x);
+}
+
+template <typename T, int kT, int kMask>
+__global__ __launch_bounds__(256) void k_gram_batch(BatchPtrs<GramArgs<T>> b) {
+  const int s = batch_system(b.off, b.S, blockIdx.x);
+  k_gram_body<T, kT, kMask>(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+}
+
+
 // out[prod][i][j] = sum over chunks in increasing order, for the products in mask; the
 // other products are zero.  Block = 16 output slots x 16 chunk lanes; chunk lane c sums
 // chunks c, c+16, ... and the 16 lane sums are added in lane order.  Symmetric products
 // read the mirrored upper tile.  With W != nullptr also W = -(product 1)^T.
-__global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ part,
-                                                     int nchunks, int pp, int mask,
-                                                     double* __restrict__ out,
-                                                     double* __restrict__ W) {
+__device__ inline void k_gram_reduce_body(const GramReduceArgs& ka, int ks_bid, int ks_nb) {
+  const double* __restrict__ part = ka.part;
+  int nchunks = ka.nchunks;
+  int pp = ka.pp;
+  int mask = ka.mask;
+  double* __restrict__ out = ka.out;
+  double* __restrict__ W = ka.W;
+  (void)ks_bid;
+  (void)ks_nb;
+
   __shared__ double red[16][17];
   const int sl = threadIdx.x % 16, cl = threadIdx.x / 16;
   const int per = pp * pp;
-  const int e = blockIdx.x * 16 + sl;
+  const int e = ks_bid * 16 + sl;
   double s = 0.0;
   int prod = 0, i = 0, j = 0;
   bool live = false;
@@ -186,6 +212,16 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
   }
 }
 
+__global__ __launch_bounds__(256) void k_gram_reduce(GramReduceArgs ka) {
+  k_gram_reduce_body(ka, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_gram_reduce_batch(BatchPtrs<GramReduceArgs> b) {
+  const int s = batch_system(b.off, b.S, blockIdx.x);
+  k_gram_reduce_body(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+}
+
+
 // ---- combine ------------------------------------------------------------------------
 // out[g][:] = C0[g][:] + X[g][:] A + Y[g][:] B  (A, B: pp x pp, staged in LDS).
 // Each wavefront owns a 16-row tile and all column tiles of it.  Epilogues:
@@ -195,7 +231,10 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
 //          a 4-row group (register r) is laid out exactly as an MFMA input fragment, so
 //          D goes from the accumulators straight back into the matrix cores.
 template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad, bool kGram2>
-__global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
+__device__ inline void k_combine_body(const CombineArgs& a, int ks_bid, int ks_nb) {
+  (void)ks_bid;
+  (void)ks_nb;
+
   const T* aX = static_cast<const T*>(a.X);
   const T* aY = static_cast<const T*>(a.Y);
   const T* aC0 = static_cast<const T*>(a.C0);
@@ -217,8 +256,8 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int lr = lane / 16, lc = lane % 16;
   const int ntiles = (a.n + 15) / 16;
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int per = (ntiles + gridDim.x - 1) / gridDim.x;
+  const int lb = xcd_remap(ks_bid, ks_nb);
+  const int per = (ntiles + ks_nb - 1) / ks_nb;
   const int t_beg = lb * per, t_end = min(ntiles, t_beg + per);
   const int ld = a.ld, p = a.p;
   double dd = 0.0, ss = 0.0, sy = 0.0, yy = 0.0;
@@ -347,6 +386,18 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
   }
 }
 
+template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad, bool kGram2>
+__global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
+  k_combine_body<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2>(a, blockIdx.x, gridDim.x);
+}
+
+template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad, bool kGram2>
+__global__ __launch_bounds__(256) void k_combine_batch(BatchPtrs<CombineArgs> b) {
+  const int s = batch_system(b.off, b.S, blockIdx.x);
+  k_combine_body<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2>(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+}
+
+
 void set_lds_attr(const void* k, size_t bytes) {
   if (bytes > 32768)
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
@@ -356,8 +407,7 @@ template <typename T, int kT, int kMask>
 void launch_gram_m(const T* A, const T* B, int ld, int n, int p, double* part, int nchunks,
                    hipStream_t st) {
   const size_t lds = (size_t)3 * 4 * 64 * sizeof(double);
-  hipLaunchKernelGGL((k_gram<T, kT, kMask>), dim3(nchunks), dim3(256), lds, st, A, B, ld, n, p,
-                     part);
+  hipLaunchKernelGGL((k_gram<T, kT, kMask>), dim3(nchunks), dim3(256), lds, st, GramArgs<T>{A, B, ld, n, p, part});
 }
 
 // Up to 32 columns all requested products run in one pass; wider blocks run one product
@@ -468,8 +518,7 @@ void launch_gram(const void* A, const void* B, bool f32, int ld, int n, int p, i
 void launch_gram_reduce(const double* partials, int nchunks, int pp, int mask, double* out,
                         double* W, hipStream_t st) {
   const int total = 3 * pp * pp;
-  hipLaunchKernelGGL(k_gram_reduce, dim3((total + 15) / 16), dim3(256), 0, st, partials, nchunks,
-                     pp, mask, out, W);
+  hipLaunchKernelGGL(k_gram_reduce, dim3((total + 15) / 16), dim3(256), 0, st, GramReduceArgs{partials, nchunks, pp, mask, out, W});
 }
 
 int combine_blocks(int n) {
@@ -488,5 +537,69 @@ void launch_combine(const CombineArgs& a, hipStream_t st) {
   if (a.f32) launch_combine_p<float>(a, st);
   else launch_combine_p<double>(a, st);
 }
+
+// ---- batched launches ------------------------------------------------------------------
+
+template <typename T>
+void launch_gram_batch(const BatchPtrs<GramArgs<T>>& b, int pp, int mask, int blocks,
+                       hipStream_t st) {
+  const size_t lds = (size_t)3 * 4 * 64 * sizeof(double);
+  const bool t1 = pp <= 16;
+  if (mask == (kPAA | kPAB)) {
+    if (t1) hipLaunchKernelGGL((k_gram_batch<T, 1, 3>), dim3(blocks), dim3(256), lds, st, b);
+    else hipLaunchKernelGGL((k_gram_batch<T, 2, 3>), dim3(blocks), dim3(256), lds, st, b);
+  } else {
+    if (t1) hipLaunchKernelGGL((k_gram_batch<T, 1, 6>), dim3(blocks), dim3(256), lds, st, b);
+    else hipLaunchKernelGGL((k_gram_batch<T, 2, 6>), dim3(blocks), dim3(256), lds, st, b);
+  }
+}
+template void launch_gram_batch<double>(const BatchPtrs<GramArgs<double>>&, int, int, int,
+                                        hipStream_t);
+template void launch_gram_batch<float>(const BatchPtrs<GramArgs<float>>&, int, int, int,
+                                       hipStream_t);
+
+int gram_reduce_blocks(int pp) { return (3 * pp * pp + 15) / 16; }
+
+void launch_gram_reduce_batch(const BatchPtrs<GramReduceArgs>& b, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_gram_reduce_batch, dim3(blocks), dim3(256), 0, st, b);
+}
+
+template <typename T, int kT>
+void combine_batch_retract_t(const BatchPtrs<CombineArgs>& b, int blocks, hipStream_t st) {
+  constexpr int kPP = kT * 16;
+  const size_t lds = (size_t)2 * kPP * kPP * sizeof(double);
+  hipLaunchKernelGGL((k_combine_batch<T, kT, true, false, true, false, false>), dim3(blocks),
+                     dim3(256), lds, st, b);
+}
+
+template <typename T, int kT>
+void combine_batch_grad_t(const BatchPtrs<CombineArgs>& b, int blocks, hipStream_t st) {
+  constexpr int kPP = kT * 16;
+  const size_t lds = (size_t)kPP * kPP * sizeof(double);
+  hipLaunchKernelGGL((k_combine_batch<T, kT, false, true, false, true, false>), dim3(blocks),
+                     dim3(256), lds, st, b);
+}
+
+template <typename T>
+void launch_combine_retract_batch(const BatchPtrs<CombineArgs>& b, int pp, int blocks,
+                                  hipStream_t st) {
+  if (pp <= 16) combine_batch_retract_t<T, 1>(b, blocks, st);
+  else combine_batch_retract_t<T, 2>(b, blocks, st);
+}
+
+template <typename T>
+void launch_combine_grad_batch(const BatchPtrs<CombineArgs>& b, int pp, int blocks,
+                               hipStream_t st) {
+  if (pp <= 16) combine_batch_grad_t<T, 1>(b, blocks, st);
+  else combine_batch_grad_t<T, 2>(b, blocks, st);
+}
+template void launch_combine_retract_batch<double>(const BatchPtrs<CombineArgs>&, int, int,
+                                                   hipStream_t);
+template void launch_combine_retract_batch<float>(const BatchPtrs<CombineArgs>&, int, int,
+                                                  hipStream_t);
+template void launch_combine_grad_batch<double>(const BatchPtrs<CombineArgs>&, int, int,
+                                                hipStream_t);
+template void launch_combine_grad_batch<float>(const BatchPtrs<CombineArgs>&, int, int,
+                                               hipStream_t);
 
 }  // namespace ks

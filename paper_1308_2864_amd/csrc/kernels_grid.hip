@@ -110,13 +110,23 @@ __global__ void k_density(const T* __restrict__ X, int ld, int n, int p, double 
 
 // ---- Slater exchange, effective potential, Hartree/exchange energy partials ------------
 
-__global__ void k_xc(const double* __restrict__ rho, const double* __restrict__ vh,
-                     const double* __restrict__ vext, double* __restrict__ veff, Grid gr,
-                     int use_h, int use_x, const CgState* __restrict__ cg, Partials pt) {
+__device__ inline void k_xc_body(const XcArgs& ka, int ks_bid, int ks_nb) {
+  const double* __restrict__ rho = ka.rho;
+  const double* __restrict__ vh = ka.vh;
+  const double* __restrict__ vext = ka.vext;
+  double* __restrict__ veff = ka.veff;
+  Grid gr = ka.gr;
+  int use_h = ka.use_h;
+  int use_x = ka.use_x;
+  const CgState* __restrict__ cg = ka.cg;
+  Partials pt = ka.pt;
+  (void)ks_bid;
+  (void)ks_nb;
+
   __shared__ double sh[kBlock / kWave];
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int lb = xcd_remap(ks_bid, ks_nb);
   size_t beg, end;
-  block_range((size_t)gr.n, lb, gridDim.x, &beg, &end);
+  block_range((size_t)gr.n, lb, ks_nb, &beg, &end);
   // (3/4)(3/pi)^{1/3} and (3/pi)^{1/3}
   const double cv = cbrt(3.0 / kPi), cx = 0.75 * cv;
   const bool trivial = use_h && cg != nullptr && cg->bb == 0.0;  // rho == 0: V_H = 0
@@ -140,6 +150,16 @@ __global__ void k_xc(const double* __restrict__ rho, const double* __restrict__ 
   write_partial(pt, SL_EX, lb, ex);
 }
 
+__global__ void k_xc(XcArgs ka) {
+  k_xc_body(ka, blockIdx.x, gridDim.x);
+}
+
+__global__ void k_xc_batch(BatchPtrs<XcArgs> b) {
+  const int s = batch_system(b.off, b.S, blockIdx.x);
+  k_xc_body(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+}
+
+
 // ---- Hamiltonian on the orbital block -----------------------------------------------
 // Y = scale * ((1/2) L X + Diag(veff) X), L = -Laplacian_h (7 points, zero Dirichlet).
 // With pt: per-block partials of sum X.(LX) and sum vext X^2 (kinetic/external energy).
@@ -151,12 +171,22 @@ __global__ void k_xc(const double* __restrict__ rho, const double* __restrict__ 
 constexpr int kHxChunk = 16;
 
 template <typename T, bool kEnergy>
-__global__ __launch_bounds__(256) void k_hx(const T* __restrict__ X, int ldx, T* __restrict__ Y,
-                                            int ldy, const double* __restrict__ veff,
-                                            const double* __restrict__ vext, Grid gr, int p,
-                                            double scale, Partials pt) {
+__device__ inline void k_hx_body(const HxArgs<T>& ka, int ks_bid, int ks_nb) {
+  const T* __restrict__ X = ka.X;
+  int ldx = ka.ldx;
+  T* __restrict__ Y = ka.Y;
+  int ldy = ka.ldy;
+  const double* __restrict__ veff = ka.veff;
+  const double* __restrict__ vext = ka.vext;
+  Grid gr = ka.gr;
+  int p = ka.p;
+  double scale = ka.scale;
+  Partials pt = ka.pt;
+  (void)ks_bid;
+  (void)ks_nb;
+
   __shared__ double sh[kBlock / kWave];
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int lb = xcd_remap(ks_bid, ks_nb);
   const int nx = gr.nx, ny = gr.ny, nz = gr.nz;
   const int nzc = (nz + kHxChunk - 1) / kHxChunk;
   const size_t work = (size_t)nx * ny * p * nzc;
@@ -164,7 +194,7 @@ __global__ __launch_bounds__(256) void k_hx(const T* __restrict__ X, int ldx, T*
   const double ih2 = gr.inv_h2;
   double kin = 0.0, ext = 0.0;
   for (size_t t = (size_t)lb * blockDim.x + threadIdx.x; t < work;
-       t += (size_t)gridDim.x * blockDim.x) {
+       t += (size_t)ks_nb * blockDim.x) {
     const int c = (int)(t % (unsigned)p);
     size_t r = t / (unsigned)p;
     const int i = (int)(r % nx);
@@ -204,6 +234,18 @@ __global__ __launch_bounds__(256) void k_hx(const T* __restrict__ X, int ldx, T*
     write_partial(pt, SL_EXT, lb, ext);
   }
 }
+
+template <typename T, bool kEnergy>
+__global__ __launch_bounds__(256) void k_hx(HxArgs<T> ka) {
+  k_hx_body<T, kEnergy>(ka, blockIdx.x, gridDim.x);
+}
+
+template <typename T, bool kEnergy>
+__global__ __launch_bounds__(256) void k_hx_batch(BatchPtrs<HxArgs<T>> b) {
+  const int s = batch_system(b.off, b.S, blockIdx.x);
+  k_hx_body<T, kEnergy>(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+}
+
 
 // ---- fixed-order reduction of per-block partials: one block per slot ---------------
 
@@ -252,8 +294,7 @@ int scalar_blocks(int n) { return stream_blocks((size_t)n); }
 
 void launch_xc(const double* rho, const double* vh, const double* vext, double* veff, Grid g,
                int use_h, int use_x, const CgState* cg, Partials pt, hipStream_t st) {
-  hipLaunchKernelGGL(k_xc, dim3(scalar_blocks(g.n)), dim3(kBlock), 0, st, rho, vh, vext, veff,
-                     g, use_h, use_x, cg, pt);
+  hipLaunchKernelGGL(k_xc, dim3(scalar_blocks(g.n)), dim3(kBlock), 0, st, XcArgs{rho, vh, vext, veff, g, use_h, use_x, cg, pt});
 }
 
 template <typename T>
@@ -261,12 +302,10 @@ void launch_hx(const T* X, int ldx, T* Y, int ldy, const double* veff, const dou
                Grid g, int p, double scale, Partials* pt, hipStream_t st) {
   const int nb = hx_blocks(g.n, p);
   if (pt) {
-    hipLaunchKernelGGL((k_hx<T, true>), dim3(nb), dim3(kBlock), 0, st, X, ldx, Y, ldy, veff,
-                       vext, g, p, scale, *pt);
+    hipLaunchKernelGGL((k_hx<T, true>), dim3(nb), dim3(kBlock), 0, st, HxArgs<T>{X, ldx, Y, ldy, veff, vext, g, p, scale, *pt});
   } else {
     Partials none{nullptr, 0};
-    hipLaunchKernelGGL((k_hx<T, false>), dim3(nb), dim3(kBlock), 0, st, X, ldx, Y, ldy, veff,
-                       vext, g, p, scale, none);
+    hipLaunchKernelGGL((k_hx<T, false>), dim3(nb), dim3(kBlock), 0, st, HxArgs<T>{X, ldx, Y, ldy, veff, vext, g, p, scale, none});
   }
 }
 template void launch_hx<double>(const double*, int, double*, int, const double*,
@@ -276,5 +315,16 @@ template void launch_hx<float>(const float*, int, float*, int, const double*, co
 
 int hx_blocks(int n, int p) { return stream_blocks((size_t)n * p / kHxChunk + 1); }
 
+
+void launch_xc_batch(const BatchPtrs<XcArgs>& b, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_xc_batch, dim3(blocks), dim3(kBlock), 0, st, b);
+}
+
+template <typename T>
+void launch_hx_batch(const BatchPtrs<HxArgs<T>>& b, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL((k_hx_batch<T, true>), dim3(blocks), dim3(kBlock), 0, st, b);
+}
+template void launch_hx_batch<double>(const BatchPtrs<HxArgs<double>>&, int, hipStream_t);
+template void launch_hx_batch<float>(const BatchPtrs<HxArgs<float>>&, int, hipStream_t);
 
 }  // namespace ks

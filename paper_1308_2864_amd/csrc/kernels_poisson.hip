@@ -97,13 +97,21 @@ __device__ inline double fin_sum(const double* part, int slot, int nb, double* s
 }
 
 // r = 4 pi rho - L x0 ; x = x0 (or 0) ; p = 0 ; partials r.r (slot 0), b.b (slot 1)
-__global__ void k_init(const double* __restrict__ rho, const double* __restrict__ x0,
-                       double* __restrict__ x, double* __restrict__ r, double* __restrict__ p0,
-                       Grid gr, double* __restrict__ part) {
+__device__ inline void k_init_body(const InitArgs& ka, int ks_bid, int ks_nb) {
+  const double* __restrict__ rho = ka.rho;
+  const double* __restrict__ x0 = ka.x0;
+  double* __restrict__ x = ka.x;
+  double* __restrict__ r = ka.r;
+  double* __restrict__ p0 = ka.p0;
+  Grid gr = ka.gr;
+  double* __restrict__ part = ka.part;
+  (void)ks_bid;
+  (void)ks_nb;
+
   __shared__ double sh[kBlock / kWave];
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int lb = xcd_remap(ks_bid, ks_nb);
   int beg, end;
-  range_of(gr.n, lb, gridDim.x, &beg, &end);
+  range_of(gr.n, lb, ks_nb, &beg, &end);
   double rr = 0.0, bb = 0.0;
   for (int g = beg + threadIdx.x; g < end; g += blockDim.x) {
     const int i = g % gr.nx, j = (g / gr.nx) % gr.ny, k = g / (gr.nx * gr.ny);
@@ -118,8 +126,25 @@ __global__ void k_init(const double* __restrict__ rho, const double* __restrict_
   put2(part, lb, rr, bb, sh, 0, 1);
 }
 
-__global__ void k_fin_init(const double* __restrict__ part, int nb, CgState* cs, double tol,
-                           int maxit) {
+__global__ void k_init(InitArgs ka) {
+  k_init_body(ka, blockIdx.x, gridDim.x);
+}
+
+__global__ void k_init_batch(BatchPtrs<InitArgs> b) {
+  const int s = batch_system(b.off, b.S, blockIdx.x);
+  k_init_body(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+}
+
+
+__device__ inline void k_fin_init_body(const FinInitArgs& ka, int ks_bid, int ks_nb) {
+  const double* __restrict__ part = ka.part;
+  int nb = ka.nb;
+  CgState* cs = ka.cs;
+  double tol = ka.tol;
+  int maxit = ka.maxit;
+  (void)ks_bid;
+  (void)ks_nb;
+
   __shared__ double sh[kBlock / kWave];
   const double rr = fin_sum(part, 0, nb, sh);
   const double bb = fin_sum(part, 1, nb, sh);
@@ -135,16 +160,34 @@ __global__ void k_fin_init(const double* __restrict__ part, int nb, CgState* cs,
   }
 }
 
+__global__ void k_fin_init(FinInitArgs ka) {
+  k_fin_init_body(ka, blockIdx.x, gridDim.x);
+}
+
+__global__ void k_fin_init_batch(BatchPtrs<FinInitArgs> b) {
+  const int s = batch_system(b.off, b.S, blockIdx.x);
+  k_fin_init_body(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+}
+
+
 // pn = z + beta po ; q = L pn ; partial pn.q (slot 2).  z = r for plain CG.
-__global__ void k_dir(const double* __restrict__ z, const double* __restrict__ po,
-                      double* __restrict__ pn, double* __restrict__ q, const CgState* cs, Grid gr,
-                      double* __restrict__ part) {
+__device__ inline void k_dir_body(const DirArgs& ka, int ks_bid, int ks_nb) {
+  const double* __restrict__ z = ka.z;
+  const double* __restrict__ po = ka.po;
+  double* __restrict__ pn = ka.pn;
+  double* __restrict__ q = ka.q;
+  const CgState* cs = ka.cs;
+  Grid gr = ka.gr;
+  double* __restrict__ part = ka.part;
+  (void)ks_bid;
+  (void)ks_nb;
+
   __shared__ double sh[kBlock / kWave];
   if (cs->done) return;
   const double beta = cs->beta;
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int lb = xcd_remap(ks_bid, ks_nb);
   int beg, end;
-  range_of(gr.n, lb, gridDim.x, &beg, &end);
+  range_of(gr.n, lb, ks_nb, &beg, &end);
   const int sz = gr.nx * gr.ny;
   double pq = 0.0;
   for (int g = beg + threadIdx.x; g < end; g += blockDim.x) {
@@ -159,8 +202,25 @@ __global__ void k_dir(const double* __restrict__ z, const double* __restrict__ p
   if (threadIdx.x == 0) part[2 * kCgBlocksMax + lb] = pq;
 }
 
+__global__ void k_dir(DirArgs ka) {
+  k_dir_body(ka, blockIdx.x, gridDim.x);
+}
+
+__global__ void k_dir_batch(BatchPtrs<DirArgs> b) {
+  const int s = batch_system(b.off, b.S, blockIdx.x);
+  k_dir_body(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+}
+
+
 // alpha = (r.z)/(p.q)   (r.z = r.r for plain CG)
-__global__ void k_fin_dir(const double* __restrict__ part, int nb, CgState* cs, int pcg) {
+__device__ inline void k_fin_dir_body(const FinDirArgs& ka, int ks_bid, int ks_nb) {
+  const double* __restrict__ part = ka.part;
+  int nb = ka.nb;
+  CgState* cs = ka.cs;
+  int pcg = ka.pcg;
+  (void)ks_bid;
+  (void)ks_nb;
+
   __shared__ double sh[kBlock / kWave];
   if (cs->done) return;
   const double pq = fin_sum(part, 2, nb, sh);
@@ -170,16 +230,34 @@ __global__ void k_fin_dir(const double* __restrict__ part, int nb, CgState* cs, 
   }
 }
 
+__global__ void k_fin_dir(FinDirArgs ka) {
+  k_fin_dir_body(ka, blockIdx.x, gridDim.x);
+}
+
+__global__ void k_fin_dir_batch(BatchPtrs<FinDirArgs> b) {
+  const int s = batch_system(b.off, b.S, blockIdx.x);
+  k_fin_dir_body(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+}
+
+
 // x += alpha p ; r -= alpha q ; partial r.r (slot 0)
-__global__ void k_upd(double* __restrict__ x, double* __restrict__ r,
-                      const double* __restrict__ pn, const double* __restrict__ q,
-                      const CgState* cs, Grid gr, double* __restrict__ part) {
+__device__ inline void k_upd_body(const UpdArgs& ka, int ks_bid, int ks_nb) {
+  double* __restrict__ x = ka.x;
+  double* __restrict__ r = ka.r;
+  const double* __restrict__ pn = ka.pn;
+  const double* __restrict__ q = ka.q;
+  const CgState* cs = ka.cs;
+  Grid gr = ka.gr;
+  double* __restrict__ part = ka.part;
+  (void)ks_bid;
+  (void)ks_nb;
+
   __shared__ double sh[kBlock / kWave];
   if (cs->done) return;
   const double alpha = cs->alpha;
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int lb = xcd_remap(ks_bid, ks_nb);
   int beg, end;
-  range_of(gr.n, lb, gridDim.x, &beg, &end);
+  range_of(gr.n, lb, ks_nb, &beg, &end);
   double rr = 0.0;
   for (int g = beg + threadIdx.x; g < end; g += blockDim.x) {
     x[g] += alpha * pn[g];
@@ -191,8 +269,25 @@ __global__ void k_upd(double* __restrict__ x, double* __restrict__ r,
   if (threadIdx.x == 0) part[0 * kCgBlocksMax + lb] = rr;
 }
 
+__global__ void k_upd(UpdArgs ka) {
+  k_upd_body(ka, blockIdx.x, gridDim.x);
+}
+
+__global__ void k_upd_batch(BatchPtrs<UpdArgs> b) {
+  const int s = batch_system(b.off, b.S, blockIdx.x);
+  k_upd_body(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+}
+
+
 // plain CG: beta = rr_new/rr ; convergence
-__global__ void k_fin_upd(const double* __restrict__ part, int nb, CgState* cs, int pcg) {
+__device__ inline void k_fin_upd_body(const FinUpdArgs& ka, int ks_bid, int ks_nb) {
+  const double* __restrict__ part = ka.part;
+  int nb = ka.nb;
+  CgState* cs = ka.cs;
+  int pcg = ka.pcg;
+  (void)ks_bid;
+  (void)ks_nb;
+
   __shared__ double sh[kBlock / kWave];
   if (cs->done) return;
   const double rr = fin_sum(part, 0, nb, sh);
@@ -204,8 +299,24 @@ __global__ void k_fin_upd(const double* __restrict__ part, int nb, CgState* cs, 
   }
 }
 
+__global__ void k_fin_upd(FinUpdArgs ka) {
+  k_fin_upd_body(ka, blockIdx.x, gridDim.x);
+}
+
+__global__ void k_fin_upd_batch(BatchPtrs<FinUpdArgs> b) {
+  const int s = batch_system(b.off, b.S, blockIdx.x);
+  k_fin_upd_body(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+}
+
+
 // PCG: rz_new = r.z (slot 3, written by the last transform) ; beta = rz_new/rz
-__global__ void k_fin_rz(const double* __restrict__ part, int nb, CgState* cs) {
+__device__ inline void k_fin_rz_body(const FinRzArgs& ka, int ks_bid, int ks_nb) {
+  const double* __restrict__ part = ka.part;
+  int nb = ka.nb;
+  CgState* cs = ka.cs;
+  (void)ks_bid;
+  (void)ks_nb;
+
   __shared__ double sh[kBlock / kWave];
   if (cs->done) return;
   const double rz = fin_sum(part, 3, nb, sh);
@@ -214,6 +325,16 @@ __global__ void k_fin_rz(const double* __restrict__ part, int nb, CgState* cs) {
     cs->rz = rz;
   }
 }
+
+__global__ void k_fin_rz(FinRzArgs ka) {
+  k_fin_rz_body(ka, blockIdx.x, gridDim.x);
+}
+
+__global__ void k_fin_rz_batch(BatchPtrs<FinRzArgs> b) {
+  const int s = batch_system(b.off, b.S, blockIdx.x);
+  k_fin_rz_body(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+}
+
 
 // ---- fast-diagonalisation preconditioner --------------------------------------------
 
@@ -259,17 +380,23 @@ constexpr int kFdTiles = 8;     // result tiles a wave can hold (covers 128 x 12
 // lives in LDS (row stride nxp + 1 doubles: conflict-free column reads).  With part the
 // partial r.Y of the plane goes to slot 3.
 template <bool kStageS>
-__global__ __launch_bounds__(512) void k_fd_plane(const double* __restrict__ in,
-                                                  double* __restrict__ out,
-                                                  const double* __restrict__ Sxg,
-                                                  const double* __restrict__ Syg, int nx, int ny,
-                                                  const double* __restrict__ r,
-                                                  double* __restrict__ part,
-                                                  const CgState* cs) {
+__device__ inline void k_fd_plane_body(const FdPlaneArgs& ka, int ks_bid, int ks_nb) {
+  const double* __restrict__ in = ka.in;
+  double* __restrict__ out = ka.out;
+  const double* __restrict__ Sxg = ka.Sxg;
+  const double* __restrict__ Syg = ka.Syg;
+  int nx = ka.nx;
+  int ny = ka.ny;
+  const double* __restrict__ r = ka.r;
+  double* __restrict__ part = ka.part;
+  const CgState* cs = ka.cs;
+  (void)ks_bid;
+  (void)ks_nb;
+
   extern __shared__ double P[];
   __shared__ double sh[512 / kWave];
   if (cs->done) return;
-  const int k = blockIdx.x;
+  const int k = ks_bid;
   const int nxp = (nx + 15) & ~15, nyp = (ny + 15) & ~15, sp = nxp + 1;
   const size_t base = (size_t)k * nx * ny;
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
@@ -341,23 +468,42 @@ __global__ __launch_bounds__(512) void k_fd_plane(const double* __restrict__ in,
   }
 }
 
+template <bool kStageS>
+__global__ __launch_bounds__(512) void k_fd_plane(FdPlaneArgs ka) {
+  k_fd_plane_body<kStageS>(ka, blockIdx.x, gridDim.x);
+}
+
+template <bool kStageS>
+__global__ __launch_bounds__(512) void k_fd_plane_batch(BatchPtrs<FdPlaneArgs> b) {
+  const int s = batch_system(b.off, b.S, blockIdx.x);
+  k_fd_plane_body<kStageS>(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+}
+
+
 // z lines (block = 64 adjacent (i, j) columns x nz): forward transform, division by
 // lx[i] + ly[j] + lz[k], inverse transform (S_z is its own inverse), in place.
 template <bool kStageS>
-__global__ __launch_bounds__(512) void k_fd_z(double* __restrict__ u,
-                                              const double* __restrict__ Szg,
-                                              const double* __restrict__ lx,
-                                              const double* __restrict__ ly,
-                                              const double* __restrict__ lz,
-                                              const double* __restrict__ mx,
-                                              const double* __restrict__ my,
-                                              const double* __restrict__ mz, int nx, int ny,
-                                              int nz, const CgState* cs) {
+__device__ inline void k_fd_z_body(const FdZArgs& ka, int ks_bid, int ks_nb) {
+  double* __restrict__ u = ka.u;
+  const double* __restrict__ Szg = ka.Szg;
+  const double* __restrict__ lx = ka.lx;
+  const double* __restrict__ ly = ka.ly;
+  const double* __restrict__ lz = ka.lz;
+  const double* __restrict__ mx = ka.mx;
+  const double* __restrict__ my = ka.my;
+  const double* __restrict__ mz = ka.mz;
+  int nx = ka.nx;
+  int ny = ka.ny;
+  int nz = ka.nz;
+  const CgState* cs = ka.cs;
+  (void)ks_bid;
+  (void)ks_nb;
+
   extern __shared__ double A[];  // nzp x 64 (then S_z when it fits)
   if (cs->done) return;
   const int npl = nx * ny;
   const int nzp = (nz + 15) & ~15;
-  const int l0 = blockIdx.x * 64;
+  const int l0 = ks_bid * 64;
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int lr = lane / 16, lc = lane % 16;
   for (int e = threadIdx.x; e < nzp * 64; e += blockDim.x) {
@@ -429,6 +575,18 @@ __global__ __launch_bounds__(512) void k_fd_z(double* __restrict__ u,
   }
 }
 
+template <bool kStageS>
+__global__ __launch_bounds__(512) void k_fd_z(FdZArgs ka) {
+  k_fd_z_body<kStageS>(ka, blockIdx.x, gridDim.x);
+}
+
+template <bool kStageS>
+__global__ __launch_bounds__(512) void k_fd_z_batch(BatchPtrs<FdZArgs> b) {
+  const int s = batch_system(b.off, b.S, blockIdx.x);
+  k_fd_z_body<kStageS>(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+}
+
+
 }  // namespace
 
 size_t hartree_part_doubles() { return (size_t)4 * kCgBlocksMax; }
@@ -444,8 +602,8 @@ void launch_hartree_init(const double* rho, const double* x0, double* x, double*
                          CgState* cs, double tol, int maxit, Grid g, double* part,
                          hipStream_t st) {
   const int nb = cg_nblocks(g.n);
-  hipLaunchKernelGGL(k_init, dim3(nb), dim3(kBlock), 0, st, rho, x0, x, r, p0, g, part);
-  hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kBlock), 0, st, part, nb, cs, tol, maxit);
+  hipLaunchKernelGGL(k_init, dim3(nb), dim3(kBlock), 0, st, InitArgs{rho, x0, x, r, p0, g, part});
+  hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kBlock), 0, st, FinInitArgs{part, nb, cs, tol, maxit});
 }
 
 namespace {
@@ -483,36 +641,93 @@ void launch_fd_apply(const double* r, double* z, const FdOps& fd, Grid g, const 
   auto plane = [&](const double* in, double* out, const double* rr, double* pt) {
     if (lps <= cap) {
       set_lds(reinterpret_cast<const void*>(k_fd_plane<true>), lps);
-      hipLaunchKernelGGL(k_fd_plane<true>, dim3(nz), dim3(threads), lps, st, in, out, fd.Sx,
-                         fd.Sy, nx, ny, rr, pt, cs);
+      hipLaunchKernelGGL(k_fd_plane<true>, dim3(nz), dim3(threads), lps, st, FdPlaneArgs{in, out, fd.Sx, fd.Sy, nx, ny, rr, pt, cs});
     } else {
       set_lds(reinterpret_cast<const void*>(k_fd_plane<false>), lp);
-      hipLaunchKernelGGL(k_fd_plane<false>, dim3(nz), dim3(threads), lp, st, in, out, fd.Sx,
-                         fd.Sy, nx, ny, rr, pt, cs);
+      hipLaunchKernelGGL(k_fd_plane<false>, dim3(nz), dim3(threads), lp, st, FdPlaneArgs{in, out, fd.Sx, fd.Sy, nx, ny, rr, pt, cs});
     }
   };
   plane(r, z, nullptr, nullptr);
   if (lzs <= cap) {
     set_lds(reinterpret_cast<const void*>(k_fd_z<true>), lzs);
-    hipLaunchKernelGGL(k_fd_z<true>, dim3((nx * ny + 63) / 64), dim3(threads), lzs, st, z, fd.Sz,
-                       fd.lx, fd.ly, fd.lz, fd.mx, fd.my, fd.mz, nx, ny, nz, cs);
+    hipLaunchKernelGGL(k_fd_z<true>, dim3((nx * ny + 63) / 64), dim3(threads), lzs, st, FdZArgs{z, fd.Sz, fd.lx, fd.ly, fd.lz, fd.mx, fd.my, fd.mz, nx, ny, nz, cs});
   } else {
     set_lds(reinterpret_cast<const void*>(k_fd_z<false>), lzb);
-    hipLaunchKernelGGL(k_fd_z<false>, dim3((nx * ny + 63) / 64), dim3(threads), lzb, st, z, fd.Sz,
-                       fd.lx, fd.ly, fd.lz, fd.mx, fd.my, fd.mz, nx, ny, nz, cs);
+    hipLaunchKernelGGL(k_fd_z<false>, dim3((nx * ny + 63) / 64), dim3(threads), lzb, st, FdZArgs{z, fd.Sz, fd.lx, fd.ly, fd.lz, fd.mx, fd.my, fd.mz, nx, ny, nz, cs});
   }
   plane(z, z, r, part);
-  hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kBlock), 0, st, part, nz, const_cast<CgState*>(cs));
+  hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kBlock), 0, st, FinRzArgs{part, nz, const_cast<CgState*>(cs)});
 }
 
 void launch_hartree_iter(double* x, double* r, const double* z, double* pa, double* pb,
                          double* q, CgState* cs, Grid g, double* part, int pcg,
                          hipStream_t st) {
   const int nb = cg_nblocks(g.n);
-  hipLaunchKernelGGL(k_dir, dim3(nb), dim3(kBlock), 0, st, pcg ? z : r, pa, pb, q, cs, g, part);
-  hipLaunchKernelGGL(k_fin_dir, dim3(1), dim3(kBlock), 0, st, part, nb, cs, pcg);
-  hipLaunchKernelGGL(k_upd, dim3(nb), dim3(kBlock), 0, st, x, r, pb, q, cs, g, part);
-  hipLaunchKernelGGL(k_fin_upd, dim3(1), dim3(kBlock), 0, st, part, nb, cs, pcg);
+  hipLaunchKernelGGL(k_dir, dim3(nb), dim3(kBlock), 0, st, DirArgs{pcg ? z : r, pa, pb, q, cs, g, part});
+  hipLaunchKernelGGL(k_fin_dir, dim3(1), dim3(kBlock), 0, st, FinDirArgs{part, nb, cs, pcg});
+  hipLaunchKernelGGL(k_upd, dim3(nb), dim3(kBlock), 0, st, UpdArgs{x, r, pb, q, cs, g, part});
+  hipLaunchKernelGGL(k_fin_upd, dim3(1), dim3(kBlock), 0, st, FinUpdArgs{part, nb, cs, pcg});
+}
+
+// ---- batched launches (one launch for the systems of a BatchPtrs table) ---------------
+
+int hartree_blocks(int n) { return cg_nblocks(n); }
+
+FdLaunch fd_launch(int nx, int ny, int nz) {
+  const size_t nxp = (nx + 15) & ~15, nyp = (ny + 15) & ~15, nzp = (nz + 15) & ~15;
+  FdLaunch l;
+  l.plane_bytes = nyp * (nxp + 1) * sizeof(double);
+  l.plane_bytes_staged = l.plane_bytes + (size_t)(nx * nx + ny * ny) * sizeof(double);
+  l.z_bytes = nzp * 64 * sizeof(double);
+  l.z_bytes_staged = l.z_bytes + (size_t)nz * nz * sizeof(double);
+  l.cap = kFdLdsCap;
+  l.plane_blocks = nz;
+  l.z_blocks = (nx * ny + 63) / 64;
+  return l;
+}
+
+void launch_init_batch(const BatchPtrs<InitArgs>& b, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_batch, dim3(blocks), dim3(kBlock), 0, st, b);
+}
+void launch_fin_init_batch(const BatchPtrs<FinInitArgs>& b, hipStream_t st) {
+  hipLaunchKernelGGL(k_fin_init_batch, dim3(b.S), dim3(kBlock), 0, st, b);
+}
+void launch_dir_batch(const BatchPtrs<DirArgs>& b, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_dir_batch, dim3(blocks), dim3(kBlock), 0, st, b);
+}
+void launch_fin_dir_batch(const BatchPtrs<FinDirArgs>& b, hipStream_t st) {
+  hipLaunchKernelGGL(k_fin_dir_batch, dim3(b.S), dim3(kBlock), 0, st, b);
+}
+void launch_upd_batch(const BatchPtrs<UpdArgs>& b, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_upd_batch, dim3(blocks), dim3(kBlock), 0, st, b);
+}
+void launch_fin_upd_batch(const BatchPtrs<FinUpdArgs>& b, hipStream_t st) {
+  hipLaunchKernelGGL(k_fin_upd_batch, dim3(b.S), dim3(kBlock), 0, st, b);
+}
+void launch_fin_rz_batch(const BatchPtrs<FinRzArgs>& b, hipStream_t st) {
+  hipLaunchKernelGGL(k_fin_rz_batch, dim3(b.S), dim3(kBlock), 0, st, b);
+}
+void launch_fd_plane_batch(const BatchPtrs<FdPlaneArgs>& b, int blocks, bool staged, size_t lds,
+                           hipStream_t st) {
+  const int threads = kFdWaves * kWave;
+  if (staged) {
+    set_lds(reinterpret_cast<const void*>(k_fd_plane_batch<true>), lds);
+    hipLaunchKernelGGL(k_fd_plane_batch<true>, dim3(blocks), dim3(threads), lds, st, b);
+  } else {
+    set_lds(reinterpret_cast<const void*>(k_fd_plane_batch<false>), lds);
+    hipLaunchKernelGGL(k_fd_plane_batch<false>, dim3(blocks), dim3(threads), lds, st, b);
+  }
+}
+void launch_fd_z_batch(const BatchPtrs<FdZArgs>& b, int blocks, bool staged, size_t lds,
+                       hipStream_t st) {
+  const int threads = kFdWaves * kWave;
+  if (staged) {
+    set_lds(reinterpret_cast<const void*>(k_fd_z_batch<true>), lds);
+    hipLaunchKernelGGL(k_fd_z_batch<true>, dim3(blocks), dim3(threads), lds, st, b);
+  } else {
+    set_lds(reinterpret_cast<const void*>(k_fd_z_batch<false>), lds);
+    hipLaunchKernelGGL(k_fd_z_batch<false>, dim3(blocks), dim3(threads), lds, st, b);
+  }
 }
 
 }  // namespace ks

@@ -212,11 +212,18 @@ __global__ void k_qr_factor(const double* __restrict__ xx, const double* __restr
 // serial loop over a column.  Rows/columns k are broadcast through LDS, double-buffered
 // by step parity.
 template <int P>
-__global__ __launch_bounds__(1024) void k_qr_factor_2d(const double* __restrict__ xx,
-                                                       const double* __restrict__ gxd, int p,
-                                                       int pp, const double* __restrict__ tau_p,
-                                                       double* __restrict__ A,
-                                                       double* __restrict__ B, int* status) {
+__device__ inline void k_qr_factor_2d_body(const QrFactor2dArgs& ka, int ks_bid, int ks_nb) {
+  const double* __restrict__ xx = ka.xx;
+  const double* __restrict__ gxd = ka.gxd;
+  int p = ka.p;
+  int pp = ka.pp;
+  const double* __restrict__ tau_p = ka.tau_p;
+  double* __restrict__ A = ka.A;
+  double* __restrict__ B = ka.B;
+  int* status = ka.status;
+  (void)ks_bid;
+  (void)ks_nb;
+
   constexpr int kT = P * P < 1024 ? P * P : 1024;  // threads
   constexpr int kE = P * P / kT;                   // elements per thread
   __shared__ double row[2][P];
@@ -304,6 +311,18 @@ __global__ __launch_bounds__(1024) void k_qr_factor_2d(const double* __restrict_
     }
   }
 }
+
+template <int P>
+__global__ __launch_bounds__(1024) void k_qr_factor_2d(QrFactor2dArgs ka) {
+  k_qr_factor_2d_body<P>(ka, blockIdx.x, gridDim.x);
+}
+
+template <int P>
+__global__ __launch_bounds__(1024) void k_qr_factor_2d_batch(BatchPtrs<QrFactor2dArgs> b) {
+  const int s = batch_system(b.off, b.S, blockIdx.x);
+  k_qr_factor_2d_body<P>(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+}
+
 
 // ---- Cayley / SMW retraction weights -------------------------------------------------
 // gram: [X^T X, X^T G, G^T G] (pp x pp each).
@@ -429,13 +448,24 @@ __device__ inline double block_sum_wide(double v, double* sh) {
   return s;
 }
 
-__global__ __launch_bounds__(1024) void k_finish_eval(const double* __restrict__ part,
-                                                     int stride, ScalarCounts nb,
-                                                     double* __restrict__ sums,
-                                                     const double* __restrict__ xx, int p,
-                                                     int pp, double f, double dV,
-                                                     const double* enuc, const CgState* cg,
-                                                     EvalOut* out, LsState* ls, LsParams prm) {
+__device__ inline void k_finish_eval_body(const FinishEvalArgs& ka, int ks_bid, int ks_nb) {
+  const double* __restrict__ part = ka.part;
+  int stride = ka.stride;
+  ScalarCounts nb = ka.nb;
+  double* __restrict__ sums = ka.sums;
+  const double* __restrict__ xx = ka.xx;
+  int p = ka.p;
+  int pp = ka.pp;
+  double f = ka.f;
+  double dV = ka.dV;
+  const double* enuc = ka.enuc;
+  const CgState* cg = ka.cg;
+  EvalOut* out = ka.out;
+  LsState* ls = ka.ls;
+  LsParams prm = ka.prm;
+  (void)ks_bid;
+  (void)ks_nb;
+
   __shared__ double sh[kFinishThreads / kWave];
   __shared__ double red[SL_COUNT];
   // all slots in one sweep: each thread keeps SL_COUNT running sums, so its loads of the
@@ -494,6 +524,16 @@ __global__ __launch_bounds__(1024) void k_finish_eval(const double* __restrict__
   *out = o;
   if (ls) ls_judge(&o, ls, prm, cg);
 }
+
+__global__ __launch_bounds__(1024) void k_finish_eval(FinishEvalArgs ka) {
+  k_finish_eval_body(ka, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(1024) void k_finish_eval_batch(BatchPtrs<FinishEvalArgs> b) {
+  const int s = batch_system(b.off, b.S, blockIdx.x);
+  k_finish_eval_body(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+}
+
 
 __global__ void k_set_scalar(double* d, double v) { *d = v; }
 
@@ -655,18 +695,15 @@ void launch_grad_weights(const double* gram, int pp, double* W, hipStream_t st) 
 void launch_qr_factor(const double* xx, const double* gxd, int p, int pp, const double* tau,
                       double* A, double* B, double* work, int* status, hipStream_t st) {
   if (p <= 16) {
-    hipLaunchKernelGGL(k_qr_factor_2d<16>, dim3(1), dim3(256), 0, st, xx, gxd, p, pp, tau, A, B,
-                       status);
+    hipLaunchKernelGGL(k_qr_factor_2d<16>, dim3(1), dim3(256), 0, st, QrFactor2dArgs{xx, gxd, p, pp, tau, A, B, status});
     return;
   }
   if (p <= 32) {
-    hipLaunchKernelGGL(k_qr_factor_2d<32>, dim3(1), dim3(1024), 0, st, xx, gxd, p, pp, tau, A,
-                       B, status);
+    hipLaunchKernelGGL(k_qr_factor_2d<32>, dim3(1), dim3(1024), 0, st, QrFactor2dArgs{xx, gxd, p, pp, tau, A, B, status});
     return;
   }
   if (p <= 64) {
-    hipLaunchKernelGGL(k_qr_factor_2d<64>, dim3(1), dim3(1024), 0, st, xx, gxd, p, pp, tau, A,
-                       B, status);
+    hipLaunchKernelGGL(k_qr_factor_2d<64>, dim3(1), dim3(1024), 0, st, QrFactor2dArgs{xx, gxd, p, pp, tau, A, B, status});
     return;
   }
   const size_t bytes = (size_t)2 * p * p * sizeof(double);
@@ -690,8 +727,7 @@ void launch_finish_eval(const double* part, int stride, const int* nblk, double*
                         const LsParams* prm, hipStream_t st) {
   ScalarCounts nb{};
   for (int i = 0; i < SL_COUNT; ++i) nb.v[i] = nblk[i];
-  hipLaunchKernelGGL(k_finish_eval, dim3(1), dim3(kFinishThreads), 0, st, part, stride, nb, sums,
-                     gram_xx, p, pp, f, dV, enuc, cg, out, ls, prm ? *prm : LsParams{});
+  hipLaunchKernelGGL(k_finish_eval, dim3(1), dim3(kFinishThreads), 0, st, FinishEvalArgs{part, stride, nb, sums, gram_xx, p, pp, f, dV, enuc, cg, out, ls, prm ? *prm : LsParams{}});
 }
 
 void launch_set_scalar(double* dst, double v, hipStream_t st) {
@@ -702,5 +738,33 @@ void launch_ls_init(const EvalOut* ev, LsState* ls, LsParams prm, hipStream_t st
   hipLaunchKernelGGL(k_ls_init, dim3(1), dim3(1), 0, st, ev, ls, prm);
 }
 
+
+// ---- batched launches ------------------------------------------------------------------
+
+void launch_qr_factor_batch(const BatchPtrs<QrFactor2dArgs>& b, int p_max, hipStream_t st) {
+  if (p_max <= 16)
+    hipLaunchKernelGGL(k_qr_factor_2d_batch<16>, dim3(b.S), dim3(256), 0, st, b);
+  else if (p_max <= 32)
+    hipLaunchKernelGGL(k_qr_factor_2d_batch<32>, dim3(b.S), dim3(1024), 0, st, b);
+  else
+    hipLaunchKernelGGL(k_qr_factor_2d_batch<64>, dim3(b.S), dim3(1024), 0, st, b);
+}
+
+void launch_finish_eval_batch(const BatchPtrs<FinishEvalArgs>& b, hipStream_t st) {
+  hipLaunchKernelGGL(k_finish_eval_batch, dim3(b.S), dim3(kFinishThreads), 0, st, b);
+}
+
+namespace {
+__global__ void k_gather(GatherArgs g) {
+  const int s = blockIdx.x;
+  const double* src = reinterpret_cast<const double*>(g.src[s]);
+  double* dst = reinterpret_cast<double*>(g.dst + (size_t)s * g.bytes);
+  for (int i = threadIdx.x; i < g.bytes / 8; i += blockDim.x) dst[i] = src[i];
+}
+}  // namespace
+
+void launch_gather(const GatherArgs& g, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather, dim3(g.S), dim3(64), 0, st, g);
+}
 
 }  // namespace ks

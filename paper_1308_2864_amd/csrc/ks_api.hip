@@ -17,6 +17,15 @@ using namespace ks;
 namespace {
 thread_local std::string g_err;
 constexpr int kPartStride = 4096;  // >= blocks of every streaming kernel
+// argument records of the batched trial kernels: one 256-byte slot per kernel and parity
+enum Rec {
+  R_QR, R_RETRACT, R_INIT, R_FIN_INIT, R_PLANE1, R_FDZ, R_PLANE2, R_FIN_RZ, R_DIR, R_FIN_DIR,
+  R_UPD, R_FIN_UPD, R_XC, R_HX, R_GRAM1, R_RED1, R_GRAD, R_GRAM2, R_RED2, R_FINISH, R_COUNT
+};
+constexpr size_t kRecSlot = 256;
+constexpr size_t kRecBytes = 2 * R_COUNT * kRecSlot;
+constexpr int kGatherBytes = 512;  // CgState and LsState of one system (adjacent)
+constexpr size_t kHostBytes = 1024 + (size_t)kMaxBatch * kGatherBytes;
 }  // namespace
 
 struct ks_system {
@@ -38,6 +47,10 @@ struct ks_system {
   // Gram block X^T B X (slot 1 of a [3][pp][pp] buffer)
   bool q1 = false;
   double* mtab[3] = {};
+  // batched runs: argument records of the trial kernels for both slot parities, and a
+  // staging area for the scalar records of a whole batch (used when this system leads)
+  char* rec = nullptr;
+  char* gstage = nullptr;
   void *Gt[2] = {}, *BX[2] = {}, *BD[2] = {};
   double* feg[2] = {};
   int solver = KS_HARTREE_CG;
@@ -147,6 +160,8 @@ void layout(ks_system* s, char* base, size_t* total) {
   s->ls = c.take<LsState>(1);  // 256 bytes after cg, mirrored on the host the same way
   s->status = c.take<int>(1);
   s->reorth_count = c.take<int>(1);
+  s->rec = c.take<char>(kRecBytes);
+  s->gstage = c.take<char>((size_t)kMaxBatch * kGatherBytes);
   *total = c.off + 256;
 }
 
@@ -749,6 +764,455 @@ int capture_trial(ks_system* s, int c, bool qr, const LsParams& lp, const ks_opt
 
 }  // namespace
 
+namespace {
+
+// State of one Alg. 3 run between its steps (shared by ks_minimize and the batched runner,
+// so both take the same decisions from the same device records).
+struct MinRun {
+  ks_opt_params prm;
+  LsParams lp;
+  bool qr = true;
+  int c = 0;
+  void* X_inout = nullptr;
+  std::chrono::steady_clock::time_point t0;
+};
+
+// Validation, start block, first evaluation and line-search initialisation.
+int run_begin(ks_system* s, void* X_inout, const ks_opt_params* o, MinRun* m) {
+  if (!s || !X_inout) return fail(s, KS_E_INVAL, "null argument");
+  m->t0 = std::chrono::steady_clock::now();
+  if (o) m->prm = *o;
+  else ks_default_params(&m->prm);
+  const ks_opt_params& prm = m->prm;
+  if (prm.retraction != KS_QR && prm.retraction != KS_WY)
+    return fail(s, KS_E_INVAL, "unknown retraction");
+  if (!(prm.delta > 0.0 && prm.delta < 1.0) || !(prm.tau0 > 0.0) || prm.h_max < 0)
+    return fail(s, KS_E_INVAL, "bad line-search parameters");
+  if (s->q1 && prm.retraction != KS_QR)
+    return fail(s, KS_E_UNSUPPORTED, "finite elements use the QR retraction");
+  m->lp = to_params(prm);
+  m->qr = prm.retraction == KS_QR;
+  m->X_inout = X_inout;
+  s->cg_total = 0;
+  drop_graphs(s);  // graphs hold the parameters of the run that captured them
+  int c = s->cur;
+  m->c = c;
+  copy_block(s, s->X[c], s->p, X_inout, s->ld);
+  if (s->q1) {
+    // the start block needs full column rank only: make it B-orthonormal first
+    int rb = b_orthonormalize(s, c);
+    if (rb) return rb;
+  }
+  launch_ls_reset(s->ls, s->st);
+  int* hint = host_int(s);
+  hint[1] = 0;
+  int rc = hip_check(s, hipMemcpyAsync(s->reorth_count, &hint[1], sizeof(int),
+                                       hipMemcpyHostToDevice, s->st), "counter upload");
+  if (rc) return rc;
+  // the first Hartree solve starts from V_H = 0, so a run depends only on X_inout
+  launch_fill(s->vh[c], 0.0, s->n, s->st);
+  rc = evaluate(s, c, false, -1, c, m->qr, !m->qr);
+  if (rc) return rc;
+  launch_ls_init(s->ev[c], s->ls, m->lp, s->st);
+  return readback(s, host_ls(s), s->ls);
+}
+
+// After a trial's CG and line-search records are in the host mirror: finish a Hartree
+// solve that had not converged (rare), then accept or keep the slot.
+int run_after_trial(ks_system* s, MinRun* m, bool cg_read) {
+  LsState* hl = host_ls(s);
+  const int c = m->c, t = 1 - c;
+  if (cg_read && !hl->hartree_pending) s->cg_total += host_cg(s)->it;
+  if (hl->hartree_pending) {
+    // the queued PCG iteration did not reach the tolerance; finish the solve and evaluate
+    // the trial again
+    int rc = hartree_iterate(s, s->vh[t], 2, true, nullptr, nullptr);
+    if (rc) return rc;
+    rc = evaluate_tail(s, t, c, m->qr, !m->qr, &m->lp);
+    if (rc) return rc;
+    rc = readback(s, hl, s->ls);
+    if (rc) return rc;
+    if (hl->hartree_pending) return fail(s, KS_E_NOT_CONVERGED, "Hartree solve did not converge");
+  }
+  if (hl->error) return KS_OK;
+  if (hl->accepted) {
+    m->c = t;
+    s->cur = t;
+  }
+  return KS_OK;
+}
+
+// Copies the result out and fills the statistics.
+int run_end(ks_system* s, MinRun* m, ks_result* r) {
+  LsState* hl = host_ls(s);
+  int* hint = host_int(s);
+  drop_graphs(s);
+  copy_block(s, m->X_inout, s->ld, s->X[m->c], s->p);
+  int rc = launch_check(s, "minimize");
+  if (rc) return rc;
+  EvalOut* he = host_ev(s);
+  rc = readback(s, he, s->ev[m->c]);
+  if (rc) return rc;
+  rc = readback(s, &hint[1], s->reorth_count);
+  if (rc) return rc;
+  if (r) {
+    std::memset(r, 0, sizeof(*r));
+    r->iters = hl->k;
+    r->nfe = hl->nfe;
+    r->backtracks = hl->backtracks;
+    r->ls_fail = hl->ls_fail;
+    r->reorths = hint[1];
+    r->stop_reason = hl->stop;
+    r->energy = he->total;
+    r->grad_norm = std::sqrt(std::max(he->g2, 0.0));
+    to_energy(*he, &r->terms);
+    r->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - m->t0).count();
+    r->hartree_iters_total = s->cg_total;
+  }
+  if (hl->error) return fail(s, hl->error, ks_status_string(hl->error));
+  if (hl->stop == KS_STOP_MAXIT) return fail(s, KS_E_NOT_CONVERGED, "max_iter reached");
+  return KS_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// ---- batched runs ----------------------------------------------------------------------
+// Systems that share the trial's launch shapes (finite differences, PCG with the exact
+// preconditioner, QR retraction, p_p <= 32, one storage precision) run their trials in
+// lockstep: each kernel of a trial is one launch for all of them, every system reading
+// its own argument record.  The records hold exactly the arguments the lone trial passes,
+// and each system keeps its lone block counts, so every result equals its lone run.
+
+static_assert(sizeof(QrFactor2dArgs) <= kRecSlot && sizeof(CombineArgs) <= kRecSlot &&
+                  sizeof(InitArgs) <= kRecSlot && sizeof(FinInitArgs) <= kRecSlot &&
+                  sizeof(FdPlaneArgs) <= kRecSlot && sizeof(FdZArgs) <= kRecSlot &&
+                  sizeof(FinRzArgs) <= kRecSlot && sizeof(DirArgs) <= kRecSlot &&
+                  sizeof(FinDirArgs) <= kRecSlot && sizeof(UpdArgs) <= kRecSlot &&
+                  sizeof(FinUpdArgs) <= kRecSlot && sizeof(XcArgs) <= kRecSlot &&
+                  sizeof(HxArgs<double>) <= kRecSlot && sizeof(GramArgs<double>) <= kRecSlot &&
+                  sizeof(GramReduceArgs) <= kRecSlot && sizeof(FinishEvalArgs) <= kRecSlot,
+              "argument records must fit their slots");
+
+bool batchable(const ks_system* s, const MinRun& m) {
+  return !s->q1 && s->solver == KS_HARTREE_PCG_FD && s->use_h && m.qr && s->pp <= 32 &&
+         !s->timers;
+}
+
+template <typename A>
+const A* rec_at(const ks_system* s, int c, int r) {
+  return reinterpret_cast<const A*>(s->rec + ((size_t)c * R_COUNT + r) * kRecSlot);
+}
+
+template <typename A>
+void put_rec(std::vector<char>& buf, int c, int r, const A& a) {
+  std::memcpy(buf.data() + ((size_t)c * R_COUNT + r) * kRecSlot, &a, sizeof(A));
+}
+
+template <typename T>
+void fill_typed(ks_system* s, std::vector<char>& buf, int c) {
+  const int t = 1 - c;
+  Partials pt{s->spart, kPartStride};
+  const int hb = hartree_blocks(s->n);
+  // retraction: X_t = X_c A + D_c B with the density (QR weights)
+  put_rec(buf, c, R_QR, QrFactor2dArgs{s->gxg[c], s->gxd[c], s->p, s->pp, &s->ls->tau, s->A,
+                                        s->B, &s->ls->error});
+  CombineArgs rt{};
+  rt.X = s->X[c];
+  rt.A = s->A;
+  rt.Y = s->D[c];
+  rt.B = s->B;
+  rt.out = s->X[t];
+  rt.rho = s->rho;
+  rt.rho_scale = rho_scale(s);
+  rt.ld = s->p;
+  rt.n = s->n;
+  rt.p = s->p;
+  rt.f32 = s->f32;
+  put_rec(buf, c, R_RETRACT, rt);
+  // Hartree: one PCG iteration warm-started from V_H of slot c (parity of p arrays is 0)
+  put_rec(buf, c, R_INIT, InitArgs{s->rho, s->vh[c], s->vh[t], s->cg_r, s->cg_p[0], s->grid,
+                                   s->cgpart});
+  put_rec(buf, c, R_FIN_INIT, FinInitArgs{s->cgpart, hb, s->cg, s->htol, s->hmaxit});
+  put_rec(buf, c, R_PLANE1, FdPlaneArgs{s->cg_r, s->cg_z, s->fdS[0], s->fdS[1], s->grid.nx,
+                                        s->grid.ny, nullptr, nullptr, s->cg});
+  put_rec(buf, c, R_FDZ, FdZArgs{s->cg_z, s->fdS[2], s->fdL[0], s->fdL[1], s->fdL[2], s->fdM[0],
+                                 s->fdM[1], s->fdM[2], s->grid.nx, s->grid.ny, s->grid.nz,
+                                 s->cg});
+  put_rec(buf, c, R_PLANE2, FdPlaneArgs{s->cg_z, s->cg_z, s->fdS[0], s->fdS[1], s->grid.nx,
+                                        s->grid.ny, s->cg_r, s->cgpart, s->cg});
+  put_rec(buf, c, R_FIN_RZ, FinRzArgs{s->cgpart, s->grid.nz, s->cg});
+  put_rec(buf, c, R_DIR, DirArgs{s->cg_z, s->cg_p[0], s->cg_p[1], s->cg_q, s->cg, s->grid,
+                                 s->cgpart});
+  put_rec(buf, c, R_FIN_DIR, FinDirArgs{s->cgpart, hb, s->cg, 1});
+  put_rec(buf, c, R_UPD, UpdArgs{s->vh[t], s->cg_r, s->cg_p[1], s->cg_q, s->cg, s->grid,
+                                 s->cgpart});
+  put_rec(buf, c, R_FIN_UPD, FinUpdArgs{s->cgpart, hb, s->cg, 1});
+  // evaluation of slot t
+  put_rec(buf, c, R_XC, XcArgs{s->rho, s->vh[t], s->vext, s->veff[t], s->grid, s->use_h,
+                               s->use_x, s->cg, pt});
+  put_rec(buf, c, R_HX, HxArgs<T>{static_cast<const T*>(s->X[t]), s->p,
+                                  static_cast<T*>(s->G[t]), s->p, s->veff[t], s->vext, s->grid,
+                                  s->p, 2.0 * s->f, pt});
+  put_rec(buf, c, R_GRAM1, GramArgs<T>{static_cast<const T*>(s->X[t]),
+                                       static_cast<const T*>(s->G[t]), s->p, s->n, s->p,
+                                       s->gram_part});
+  put_rec(buf, c, R_RED1, GramReduceArgs{s->gram_part, s->gram_nchunks, s->pp,
+                                         kGramAA | kGramAB, s->gxg[t], s->W});
+  CombineArgs gd{};
+  gd.X = s->X[t];
+  gd.A = s->W;
+  gd.C0 = s->G[t];
+  gd.out = s->D[t];
+  gd.Xk = s->X[c];
+  gd.Dk = s->D[c];
+  gd.pt = pt;
+  gd.ld = s->p;
+  gd.n = s->n;
+  gd.p = s->p;
+  gd.f32 = s->f32;
+  put_rec(buf, c, R_GRAD, gd);
+  put_rec(buf, c, R_GRAM2, GramArgs<T>{static_cast<const T*>(s->X[t]),
+                                       static_cast<const T*>(s->D[t]), s->p, s->n, s->p,
+                                       s->gram_part});
+  put_rec(buf, c, R_RED2, GramReduceArgs{s->gram_part, s->gram_nchunks, s->pp,
+                                         kGramAB | kGramBB, s->gxd[t], nullptr});
+}
+
+int upload_records(ks_system* s, const MinRun& m) {
+  std::vector<char> buf(kRecBytes, 0);
+  for (int c = 0; c < 2; ++c) {
+    if (s->f32) fill_typed<float>(s, buf, c);
+    else fill_typed<double>(s, buf, c);
+    const int t = 1 - c;
+    int nblk[kMaxScalarSlots] = {};
+    nblk[SL_KIN] = nblk[SL_EXT] = hx_blocks(s->n, s->p);
+    nblk[SL_EH] = nblk[SL_EX] = scalar_blocks(s->n);
+    nblk[SL_DD] = nblk[SL_SS] = nblk[SL_SY] = nblk[SL_YY] = combine_blocks(s->n);
+    ScalarCounts sc{};
+    for (int i = 0; i < SL_COUNT; ++i) sc.v[i] = nblk[i];
+    put_rec(buf, c, R_FINISH, FinishEvalArgs{s->spart, kPartStride, sc, s->sums[t], s->gxg[t],
+                                             s->p, s->pp, s->f, s->grid.dV, s->enuc, s->cg,
+                                             s->ev[t], s->ls, m.lp});
+  }
+  int rc = hip_check(s, hipMemcpyAsync(s->rec, buf.data(), kRecBytes, hipMemcpyHostToDevice,
+                                       s->st), "record upload");
+  if (rc) return rc;
+  return hip_check(s, hipStreamSynchronize(s->st), "record upload sync");
+}
+
+}  // namespace
+
+namespace ks {
+
+struct BatchMember {
+  ks_system* s = nullptr;
+  MinRun m;
+  void* tag = nullptr;
+  int code = KS_OK;
+  ks_result r{};
+};
+
+struct BatchEngine {
+  hipStream_t st = nullptr;
+  std::vector<BatchMember*> act;
+  std::vector<BatchMember*> fin;
+};
+
+namespace {
+
+template <typename A, typename F>
+BatchPtrs<A> table(const std::vector<BatchMember*>& g, int r, F blocks, int* total) {
+  BatchPtrs<A> b{};
+  b.S = (int)g.size();
+  int off = 0;
+  for (int i = 0; i < b.S; ++i) {
+    b.off[i] = off;
+    b.a[i] = rec_at<A>(g[i]->s, g[i]->m.c, r);
+    off += blocks(g[i]->s);
+  }
+  b.off[b.S] = off;
+  *total = off;
+  return b;
+}
+
+int one(const ks_system*) { return 1; }
+
+// One trial of every member of g (same precision and p_p), then their records back.
+template <typename T>
+void launch_trial_batch(const std::vector<BatchMember*>& g, hipStream_t st) {
+  int tot = 0;
+  const int pp = g[0]->s->pp;
+  int pmax = 0;
+  for (auto* m : g) pmax = std::max(pmax, m->s->p);
+  auto qr = table<QrFactor2dArgs>(g, R_QR, one, &tot);
+  launch_qr_factor_batch(qr, pmax <= 16 ? 16 : 32, st);
+  auto cb = [](const ks_system* s) { return combine_blocks(s->n); };
+  auto rt = table<CombineArgs>(g, R_RETRACT, cb, &tot);
+  launch_combine_retract_batch<T>(rt, pp, tot, st);
+  auto hb = [](const ks_system* s) { return hartree_blocks(s->n); };
+  auto in = table<InitArgs>(g, R_INIT, hb, &tot);
+  launch_init_batch(in, tot, st);
+  launch_fin_init_batch(table<FinInitArgs>(g, R_FIN_INIT, one, &tot), st);
+  bool stage_p = true, stage_z = true;
+  for (auto* m : g) {
+    const FdLaunch l = fd_launch(m->s->grid.nx, m->s->grid.ny, m->s->grid.nz);
+    stage_p = stage_p && l.plane_bytes_staged <= l.cap;
+    stage_z = stage_z && l.z_bytes_staged <= l.cap;
+  }
+  size_t lds_p = 0, lds_z = 0;
+  for (auto* m : g) {
+    const FdLaunch l = fd_launch(m->s->grid.nx, m->s->grid.ny, m->s->grid.nz);
+    lds_p = std::max(lds_p, stage_p ? l.plane_bytes_staged : l.plane_bytes);
+    lds_z = std::max(lds_z, stage_z ? l.z_bytes_staged : l.z_bytes);
+  }
+  auto pb = [](const ks_system* s) { return s->grid.nz; };
+  auto zb = [](const ks_system* s) { return (s->grid.nx * s->grid.ny + 63) / 64; };
+  auto p1 = table<FdPlaneArgs>(g, R_PLANE1, pb, &tot);
+  launch_fd_plane_batch(p1, tot, stage_p, lds_p, st);
+  auto fz = table<FdZArgs>(g, R_FDZ, zb, &tot);
+  launch_fd_z_batch(fz, tot, stage_z, lds_z, st);
+  auto p2 = table<FdPlaneArgs>(g, R_PLANE2, pb, &tot);
+  launch_fd_plane_batch(p2, tot, stage_p, lds_p, st);
+  launch_fin_rz_batch(table<FinRzArgs>(g, R_FIN_RZ, one, &tot), st);
+  auto di = table<DirArgs>(g, R_DIR, hb, &tot);
+  launch_dir_batch(di, tot, st);
+  launch_fin_dir_batch(table<FinDirArgs>(g, R_FIN_DIR, one, &tot), st);
+  auto up = table<UpdArgs>(g, R_UPD, hb, &tot);
+  launch_upd_batch(up, tot, st);
+  launch_fin_upd_batch(table<FinUpdArgs>(g, R_FIN_UPD, one, &tot), st);
+  auto sb = [](const ks_system* s) { return scalar_blocks(s->n); };
+  auto xc = table<XcArgs>(g, R_XC, sb, &tot);
+  launch_xc_batch(xc, tot, st);
+  auto hxb = [](const ks_system* s) { return hx_blocks(s->n, s->p); };
+  auto hx = table<HxArgs<T>>(g, R_HX, hxb, &tot);
+  launch_hx_batch<T>(hx, tot, st);
+  auto gb = [](const ks_system* s) { return s->gram_nchunks; };
+  auto rb = [](const ks_system* s) { return gram_reduce_blocks(s->pp); };
+  auto g1 = table<GramArgs<T>>(g, R_GRAM1, gb, &tot);
+  launch_gram_batch<T>(g1, pp, kGramAA | kGramAB, tot, st);
+  auto r1 = table<GramReduceArgs>(g, R_RED1, rb, &tot);
+  launch_gram_reduce_batch(r1, tot, st);
+  auto gd = table<CombineArgs>(g, R_GRAD, cb, &tot);
+  launch_combine_grad_batch<T>(gd, pp, tot, st);
+  auto g2 = table<GramArgs<T>>(g, R_GRAM2, gb, &tot);
+  launch_gram_batch<T>(g2, pp, kGramAB | kGramBB, tot, st);
+  auto r2 = table<GramReduceArgs>(g, R_RED2, rb, &tot);
+  launch_gram_reduce_batch(r2, tot, st);
+  launch_finish_eval_batch(table<FinishEvalArgs>(g, R_FINISH, one, &tot), st);
+}
+
+}  // namespace
+
+BatchEngine* batch_create(hipStream_t st) {
+  BatchEngine* e = new BatchEngine();
+  e->st = st;
+  return e;
+}
+
+void batch_destroy(BatchEngine* e) {
+  if (!e) return;
+  for (auto* m : e->act) delete m;
+  for (auto* m : e->fin) delete m;
+  delete e;
+}
+
+int batch_size(const BatchEngine* e) { return (int)e->act.size(); }
+
+// Starts a run (first evaluation on the system's own stream).  A run that cannot start,
+// or that stops at once, goes straight to the finished list.
+int batch_add(BatchEngine* e, ks_system* s, void* X, const ks_opt_params* o, void* tag) {
+  if ((int)e->act.size() >= kMaxBatch) return KS_E_INVAL;
+  BatchMember* m = new BatchMember();
+  m->s = s;
+  m->tag = tag;
+  int rc = run_begin(s, X, o, &m->m);
+  if (rc == KS_OK && !batchable(s, m->m)) rc = fail(s, KS_E_UNSUPPORTED, "not batchable");
+  if (rc == KS_OK) rc = upload_records(s, m->m);
+  if (rc != KS_OK) {
+    m->code = rc;
+    e->fin.push_back(m);
+    return rc;
+  }
+  const LsState* hl = host_ls(s);
+  if (hl->stop != KS_STOP_NONE || hl->error) {
+    m->code = run_end(s, &m->m, &m->r);
+    e->fin.push_back(m);
+    return KS_OK;
+  }
+  e->act.push_back(m);
+  return KS_OK;
+}
+
+// One trial for every active member; members that stop move to the finished list.
+int batch_tick(BatchEngine* e) {
+  if (e->act.empty()) return KS_OK;
+  // groups of equal storage precision and p_p
+  std::vector<std::vector<BatchMember*>> groups;
+  for (auto* m : e->act) {
+    bool placed = false;
+    for (auto& g : groups)
+      if (g[0]->s->f32 == m->s->f32 && g[0]->s->pp == m->s->pp) {
+        g.push_back(m);
+        placed = true;
+        break;
+      }
+    if (!placed) groups.push_back({m});
+  }
+  for (auto& g : groups) {
+    if (g[0]->s->f32) launch_trial_batch<float>(g, e->st);
+    else launch_trial_batch<double>(g, e->st);
+  }
+  // the CG and line-search records of all members in one copy
+  ks_system* lead = e->act[0]->s;
+  GatherArgs ga{};
+  ga.S = (int)e->act.size();
+  ga.bytes = kGatherBytes;
+  for (int i = 0; i < ga.S; ++i) ga.src[i] = reinterpret_cast<const char*>(e->act[i]->s->cg);
+  ga.dst = lead->gstage;
+  launch_gather(ga, e->st);
+  char* hstage = static_cast<char*>(lead->host) + 1024;
+  hipError_t he = hipMemcpyAsync(hstage, lead->gstage, (size_t)ga.S * kGatherBytes,
+                                 hipMemcpyDeviceToHost, e->st);
+  if (he == hipSuccess) he = hipStreamSynchronize(e->st);
+  int rc = hip_check(lead, he, "batch read-back");
+  if (rc) return rc;
+  std::vector<BatchMember*> keep;
+  for (int i = 0; i < ga.S; ++i) {
+    BatchMember* m = e->act[i];
+    std::memcpy(m->s->host, hstage + (size_t)i * kGatherBytes, kGatherBytes);
+    m->s->cg_par = 1;  // the host state a lone trial leaves after its one PCG iteration
+    int code = run_after_trial(m->s, &m->m, true);
+    const LsState* hl = host_ls(m->s);
+    if (code != KS_OK) {
+      m->code = code;
+      e->fin.push_back(m);
+    } else if (hl->stop != KS_STOP_NONE || hl->error) {
+      m->code = run_end(m->s, &m->m, &m->r);
+      e->fin.push_back(m);
+    } else {
+      keep.push_back(m);
+    }
+  }
+  e->act.swap(keep);
+  return KS_OK;
+}
+
+// Pops one finished run: its tag, result and return code.
+bool batch_take(BatchEngine* e, void** tag, ks_result* r, int* code) {
+  if (e->fin.empty()) return false;
+  BatchMember* m = e->fin.front();
+  e->fin.erase(e->fin.begin());
+  if (tag) *tag = m->tag;
+  if (r) *r = m->r;
+  if (code) *code = m->code;
+  delete m;
+  return true;
+}
+
+}  // namespace ks
+
 extern "C" {
 
 void ks_default_params(ks_opt_params* o) {
@@ -820,11 +1284,11 @@ int ks_create_system(const ks_system_desc* d, void* dev_workspace, size_t ws_byt
   }
   layout(s, static_cast<char*>(dev_workspace), &need);
   s->st = static_cast<hipStream_t>(hip_stream);
-  if (hipHostMalloc(&s->host, 1024, hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc(&s->host, kHostBytes, hipHostMallocDefault) != hipSuccess) {
     delete s;
     return fail(nullptr, KS_E_HIP, "pinned host buffer");
   }
-  std::memset(s->host, 0, 1024);
+  std::memset(s->host, 0, kHostBytes);
   const int M = d->n_nuclei;
   hipError_t e = hipSuccess;
   if (M > 0) {
@@ -1113,109 +1577,64 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
 }
 
 int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* r) {
-  if (!s || !X_inout) return fail(s, KS_E_INVAL, "null argument");
-  const auto t0 = std::chrono::steady_clock::now();
-  ks_opt_params prm;
-  if (o) prm = *o;
-  else ks_default_params(&prm);
-  if (prm.retraction != KS_QR && prm.retraction != KS_WY)
-    return fail(s, KS_E_INVAL, "unknown retraction");
-  if (!(prm.delta > 0.0 && prm.delta < 1.0) || !(prm.tau0 > 0.0) || prm.h_max < 0)
-    return fail(s, KS_E_INVAL, "bad line-search parameters");
-  if (s->q1 && prm.retraction != KS_QR)
-    return fail(s, KS_E_UNSUPPORTED, "finite elements use the QR retraction");
-  const LsParams lp = to_params(prm);
-  const bool qr = prm.retraction == KS_QR;
-  s->cg_total = 0;
-  drop_graphs(s);  // graphs hold the parameters of the run that captured them
-  int c = s->cur;
-  copy_block(s, s->X[c], s->p, X_inout, s->ld);
-  if (s->q1) {
-    // the start block needs full column rank only: make it B-orthonormal first
-    int rb = b_orthonormalize(s, c);
-    if (rb) return rb;
-  }
-  launch_ls_reset(s->ls, s->st);
-  int* hint = host_int(s);
-  hint[1] = 0;
-  int rc = hip_check(s, hipMemcpyAsync(s->reorth_count, &hint[1], sizeof(int),
-                                       hipMemcpyHostToDevice, s->st), "counter upload");
+  MinRun m;
+  int rc = run_begin(s, X_inout, o, &m);
   if (rc) return rc;
-  // the first Hartree solve starts from V_H = 0, so a run depends only on X_inout
-  launch_fill(s->vh[c], 0.0, s->n, s->st);
-  rc = evaluate(s, c, false, -1, c, qr, !qr);
-  if (rc) return rc;
-  launch_ls_init(s->ev[c], s->ls, lp, s->st);
   LsState* hl = host_ls(s);
-  rc = readback(s, hl, s->ls);
-  if (rc) return rc;
-  while (hl->stop == KS_STOP_NONE) {
-    const int t = 1 - c;
+  while (hl->stop == KS_STOP_NONE && !hl->error) {
+    const int c = m.c;
     const bool pcg = s->solver == KS_HARTREE_PCG_FD;
     // graph replay from the second trial on (the first runs eagerly and initialises the
     // launch attributes); the CG solver's host-side convergence checks cannot be captured
     const bool replay = s->graphs && s->cap_st && (pcg || !s->use_h) && !s->timers &&
                         hl->nfe > 1;
     if (replay && !s->gx[c]) {
-      rc = capture_trial(s, c, qr, lp, prm);
+      rc = capture_trial(s, c, m.qr, m.lp, m.prm);
       if (rc) return rc;
     }
     if (replay && s->gx[c]) {
       rc = hip_check(s, hipGraphLaunch(s->gx[c], s->st), "graph launch");
     } else {
-      rc = enqueue_trial(s, c, qr, lp, prm);
+      rc = enqueue_trial(s, c, m.qr, m.lp, m.prm);
     }
     if (rc) return rc;
-    if (pcg && s->use_h) {
-      rc = readback_cg_ls(s);
-      if (rc == KS_OK && !hl->hartree_pending) s->cg_total += host_cg(s)->it;
-    } else {
-      rc = readback(s, hl, s->ls);
-    }
+    const bool cg_read = pcg && s->use_h;
+    rc = cg_read ? readback_cg_ls(s) : readback(s, hl, s->ls);
     if (rc) return rc;
-    if (hl->hartree_pending) {
-      // rare: the queued PCG iterations did not reach the tolerance; finish the solve
-      // and evaluate the trial again
-      rc = hartree_iterate(s, s->vh[t], 2, true, nullptr, nullptr);
-      if (rc) return rc;
-      rc = evaluate_tail(s, t, c, qr, !qr, &lp);
-      if (rc) return rc;
-      rc = readback(s, hl, s->ls);
-      if (rc) return rc;
-      if (hl->hartree_pending) return fail(s, KS_E_NOT_CONVERGED, "Hartree solve did not converge");
-    }
-    if (hl->error) break;
-    if (hl->accepted) {
-      c = t;
-      s->cur = c;
-    }
+    rc = run_after_trial(s, &m, cg_read);
+    if (rc) return rc;
   }
-  drop_graphs(s);
-  copy_block(s, X_inout, s->ld, s->X[c], s->p);
-  rc = launch_check(s, "minimize");
-  if (rc) return rc;
-  EvalOut* he = host_ev(s);
-  rc = readback(s, he, s->ev[c]);
-  if (rc) return rc;
-  rc = readback(s, &hint[1], s->reorth_count);
-  if (rc) return rc;
-  if (r) {
-    std::memset(r, 0, sizeof(*r));
-    r->iters = hl->k;
-    r->nfe = hl->nfe;
-    r->backtracks = hl->backtracks;
-    r->ls_fail = hl->ls_fail;
-    r->reorths = hint[1];
-    r->stop_reason = hl->stop;
-    r->energy = he->total;
-    r->grad_norm = std::sqrt(std::max(he->g2, 0.0));
-    to_energy(*he, &r->terms);
-    r->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    r->hartree_iters_total = s->cg_total;
+  return run_end(s, &m, r);
+}
+
+int ks_minimize_batch(ks_system* const* sys, int count, void* const* X_inout,
+                      const ks_opt_params* o, ks_result* r, int* codes) {
+  if (!sys || !X_inout || count < 1 || count > kMaxBatch) return fail(nullptr, KS_E_INVAL, "bad batch");
+  for (int i = 0; i < count; ++i)
+    if (!sys[i] || !X_inout[i]) return fail(nullptr, KS_E_INVAL, "null system or block");
+  BatchEngine* e = batch_create(sys[0]->st);
+  for (int i = 0; i < count; ++i) {
+    hipError_t he = hipStreamSynchronize(sys[i]->st);
+    if (he != hipSuccess) {
+      batch_destroy(e);
+      return hip_check(sys[i], he, "batch start");
+    }
+    (void)batch_add(e, sys[i], X_inout[i], o, reinterpret_cast<void*>((intptr_t)i));
   }
-  if (hl->error) return fail(s, hl->error, ks_status_string(hl->error));
-  if (hl->stop == KS_STOP_MAXIT) return fail(s, KS_E_NOT_CONVERGED, "max_iter reached");
-  return KS_OK;
+  int rc = KS_OK;
+  while (batch_size(e) > 0 && rc == KS_OK) rc = batch_tick(e);
+  void* tag = nullptr;
+  ks_result res{};
+  int code = KS_OK;
+  int worst = rc;
+  while (batch_take(e, &tag, &res, &code)) {
+    const int i = (int)(intptr_t)tag;
+    if (r) r[i] = res;
+    if (codes) codes[i] = code;
+    if (worst == KS_OK && code != KS_OK && code != KS_E_NOT_CONVERGED) worst = code;
+  }
+  batch_destroy(e);
+  return worst;
 }
 
 }  // extern "C"

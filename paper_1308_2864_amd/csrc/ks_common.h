@@ -121,12 +121,62 @@ __device__ inline double block_sum(double v, double* sh) {
 }
 
 // ------------------------------------------------------------------------------------
+// Batched launches.  A batched kernel runs the body of a single-system kernel for up to
+// kMaxBatch systems in one launch: system s owns blocks [off[s], off[s+1]) and its
+// argument record lives in device memory at a[s].  The body receives the block index and
+// block count of its own system, so each system keeps the block partition (and the
+// fixed-order reductions) of its lone launch and the results are bitwise the same.
+// ------------------------------------------------------------------------------------
+constexpr int kMaxBatch = 16;
+
+template <typename A>
+struct BatchPtrs {
+  int S;
+  int off[kMaxBatch + 1];
+  const A* a[kMaxBatch];
+};
+
+__device__ inline int batch_system(const int* off, int S, int b) {
+  int s = 0;
+  while (s + 1 < S && b >= off[s + 1]) ++s;
+  return s;
+}
+
+// ------------------------------------------------------------------------------------
 // Launch wrappers (defined in the .hip files).  All take the stream last.
 // ------------------------------------------------------------------------------------
 struct Partials {
   double* buf;      // [slot][block]
   int stride;       // max blocks per slot
 };
+
+// Argument records of the grid kernels (see BatchPtrs).
+struct XcArgs {
+  const double* rho;
+  const double* vh;
+  const double* vext;
+  double* veff;
+  Grid gr;
+  int use_h;
+  int use_x;
+  const CgState* cg;
+  Partials pt;
+};
+
+template <typename T>
+struct HxArgs {
+  const T* X;
+  int ldx;
+  T* Y;
+  int ldy;
+  const double* veff;
+  const double* vext;
+  Grid gr;
+  int p;
+  double scale;
+  Partials pt;
+};
+
 
 // grid kernels (kernels_grid.hip)
 void launch_vext(double* v, const double* R, const double* Z, int M, Grid g, double rc,
@@ -145,6 +195,9 @@ template <typename T>
 void launch_hx(const T* X, int ldx, T* Y, int ldy, const double* veff, const double* vext,
                Grid g, int p, double scale, Partials* pt, hipStream_t st);
 int hx_blocks(int n, int p);  // blocks (and energy partials) of launch_hx
+void launch_xc_batch(const BatchPtrs<XcArgs>& b, int blocks, hipStream_t st);
+template <typename T>
+void launch_hx_batch(const BatchPtrs<HxArgs<T>>& b, int blocks, hipStream_t st);
 int scalar_blocks(int n);
 // Hartree solver (kernels_poisson.hip)
 struct FdOps {
@@ -152,7 +205,111 @@ struct FdOps {
   const double *lx, *ly, *lz;   // eigenvalues of the 1D operator per axis
   const double *mx, *my, *mz;   // eigenvalues of the 1D mass matrix (1 for differences)
 };
+// Argument records of the Hartree kernels (one per launch; see BatchPtrs).
+struct InitArgs {
+  const double* rho;
+  const double* x0;
+  double* x;
+  double* r;
+  double* p0;
+  Grid gr;
+  double* part;
+};
+
+struct FinInitArgs {
+  const double* part;
+  int nb;
+  CgState* cs;
+  double tol;
+  int maxit;
+};
+
+struct DirArgs {
+  const double* z;
+  const double* po;
+  double* pn;
+  double* q;
+  const CgState* cs;
+  Grid gr;
+  double* part;
+};
+
+struct FinDirArgs {
+  const double* part;
+  int nb;
+  CgState* cs;
+  int pcg;
+};
+
+struct UpdArgs {
+  double* x;
+  double* r;
+  const double* pn;
+  const double* q;
+  const CgState* cs;
+  Grid gr;
+  double* part;
+};
+
+struct FinUpdArgs {
+  const double* part;
+  int nb;
+  CgState* cs;
+  int pcg;
+};
+
+struct FinRzArgs {
+  const double* part;
+  int nb;
+  CgState* cs;
+};
+
+struct FdPlaneArgs {
+  const double* in;
+  double* out;
+  const double* Sxg;
+  const double* Syg;
+  int nx;
+  int ny;
+  const double* r;
+  double* part;
+  const CgState* cs;
+};
+
+struct FdZArgs {
+  double* u;
+  const double* Szg;
+  const double* lx;
+  const double* ly;
+  const double* lz;
+  const double* mx;
+  const double* my;
+  const double* mz;
+  int nx;
+  int ny;
+  int nz;
+  const CgState* cs;
+};
+
 size_t hartree_part_doubles();
+// Launch shapes of the Hartree kernels for one system (blocks and dynamic LDS).
+int hartree_blocks(int n);
+struct FdLaunch {
+  size_t plane_bytes, plane_bytes_staged, z_bytes, z_bytes_staged, cap;
+  int plane_blocks, z_blocks;
+};
+FdLaunch fd_launch(int nx, int ny, int nz);
+void launch_init_batch(const BatchPtrs<InitArgs>& b, int blocks, hipStream_t st);
+void launch_fin_init_batch(const BatchPtrs<FinInitArgs>& b, hipStream_t st);
+void launch_dir_batch(const BatchPtrs<DirArgs>& b, int blocks, hipStream_t st);
+void launch_fin_dir_batch(const BatchPtrs<FinDirArgs>& b, hipStream_t st);
+void launch_upd_batch(const BatchPtrs<UpdArgs>& b, int blocks, hipStream_t st);
+void launch_fin_upd_batch(const BatchPtrs<FinUpdArgs>& b, hipStream_t st);
+void launch_fin_rz_batch(const BatchPtrs<FinRzArgs>& b, hipStream_t st);
+void launch_fd_plane_batch(const BatchPtrs<FdPlaneArgs>& b, int blocks, bool staged, size_t lds,
+                           hipStream_t st);
+void launch_fd_z_batch(const BatchPtrs<FdZArgs>& b, int blocks, bool staged, size_t lds,
+                       hipStream_t st);
 size_t fd_lds_bytes(int nx, int ny, int nz);
 int fd_max_plane();
 void launch_fd_setup(double* S, double* lam, double* mu, int N, double h, int q1,
@@ -194,6 +351,27 @@ int q1_grad_blocks(int n, int p);
 int q1_apply_blocks(int n, int p);
 
 // dense kernels (kernels_dense.hip)
+// Argument records of the Gram kernels (see BatchPtrs).
+template <typename T>
+struct GramArgs {
+  const T* A;
+  const T* B;
+  int ld;
+  int n;
+  int p;
+  double* part;
+};
+
+struct GramReduceArgs {
+  const double* part;
+  int nchunks;
+  int pp;
+  int mask;
+  double* out;
+  double* W;
+};
+
+
 constexpr int kGramAA = 1, kGramAB = 2, kGramBB = 4;  // product bits of a Gram launch
 int gram_chunks(int n, int pp);
 size_t gram_part_doubles(int n, int pp);
@@ -219,10 +397,54 @@ struct CombineArgs {
   bool f32;
 };
 void launch_combine(const CombineArgs& a, hipStream_t st);
+// Batched Gram (products kMask of [A, B], p_p <= 32), its reduction, and the two combine
+// forms of a trial: the retraction (X A + Y B with the density) and the gradient
+// (C0 + X A with the BB sums).
+template <typename T>
+void launch_gram_batch(const BatchPtrs<GramArgs<T>>& b, int pp, int mask, int blocks,
+                       hipStream_t st);
+void launch_gram_reduce_batch(const BatchPtrs<GramReduceArgs>& b, int blocks, hipStream_t st);
+int gram_reduce_blocks(int pp);
+template <typename T>
+void launch_combine_retract_batch(const BatchPtrs<CombineArgs>& b, int pp, int blocks,
+                                  hipStream_t st);
+template <typename T>
+void launch_combine_grad_batch(const BatchPtrs<CombineArgs>& b, int pp, int blocks,
+                               hipStream_t st);
 int combine_blocks(int n);
 int combine_blocks_gram(int n);
 
 // small dense kernels (kernels_small.hip)
+// Argument records of the per-system small kernels (see BatchPtrs).
+struct QrFactor2dArgs {
+  const double* xx;
+  const double* gxd;
+  int p;
+  int pp;
+  const double* tau_p;
+  double* A;
+  double* B;
+  int* status;
+};
+
+struct FinishEvalArgs {
+  const double* part;
+  int stride;
+  ScalarCounts nb;
+  double* sums;
+  const double* xx;
+  int p;
+  int pp;
+  double f;
+  double dV;
+  const double* enuc;
+  const CgState* cg;
+  EvalOut* out;
+  LsState* ls;
+  LsParams prm;
+};
+
+
 void launch_grad_weights(const double* gram, int pp, double* W, hipStream_t st);
 void launch_qr_factor(const double* xx, const double* gxd, int p, int pp, const double* tau,
                       double* A, double* B, double* work, int* status, hipStream_t st);
@@ -239,5 +461,14 @@ void launch_finish_eval(const double* part, int stride, const int* nblk, double*
                         const double* enuc, const CgState* cg, EvalOut* out, LsState* ls,
                         const LsParams* prm, hipStream_t st);
 void launch_set_scalar(double* dst, double v, hipStream_t st);
+void launch_qr_factor_batch(const BatchPtrs<QrFactor2dArgs>& b, int p_max, hipStream_t st);
+void launch_finish_eval_batch(const BatchPtrs<FinishEvalArgs>& b, hipStream_t st);
+// Copies `bytes` from each src[s] to dst + s * bytes (one block per system).
+struct GatherArgs {
+  int S, bytes;
+  const char* src[kMaxBatch];
+  char* dst;
+};
+void launch_gather(const GatherArgs& g, hipStream_t st);
 void launch_ls_init(const EvalOut* ev, LsState* ls, LsParams prm, hipStream_t st);
 }  // namespace ks

@@ -120,6 +120,8 @@ def _load():
         "ks_enable_timers": (ip, [vp, ip]),
         "ks_read_timers": (ip, [vp, C.POINTER(ks_phase_times), ip]),
         "ks_enable_graphs": (ip, [vp, ip]),
+        "ks_minimize_batch": (ip, [C.POINTER(vp), ip, C.POINTER(vp), C.POINTER(ks_opt_params),
+                                   C.POINTER(ks_result), C.POINTER(ip)]),
         "ks_timer_phases": (ip, [vp, C.c_uint]),
         "ks_server_create": (ip, [vp, C.c_size_t, ip, C.POINTER(vp)]),
         "ks_server_submit": (ip, [vp, C.POINTER(ks_request)]),
@@ -297,6 +299,21 @@ def system_from_spec(spec, **kw) -> KSSystem:
     """Creates a KSSystem for a ``synth.SystemSpec``."""
     device = kw.pop("device", "cuda")
     return KSSystem(desc_from_spec(spec, **kw), device=device)
+
+
+def ks_minimize_batch(systems, blocks, params=None):
+    """ks_minimize on several KSSystem objects in lockstep (see include/ks.h).  Returns
+    (list of ks_result, list of return codes)."""
+    n = len(systems)
+    hs = (C.c_void_p * n)(*[s.h for s in systems])
+    xs = (C.c_void_p * n)(*[X.data_ptr() for X in blocks])
+    rs = (ks_result * n)()
+    codes = (C.c_int * n)()
+    rc = lib.ks_minimize_batch(hs, n, xs, C.byref(params) if params is not None else None, rs,
+                               codes)
+    if rc in (KS_E_INVAL, KS_E_HIP):  # the batch itself failed; per-system codes otherwise
+        _check(rc)
+    return list(rs), list(codes)
 
 
 def ks_request_bytes(desc) -> int:
