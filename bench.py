@@ -122,7 +122,8 @@ def fe_leg(ks, synth, p, iters, seed):
     return out
 
 
-def serve_leg(ks, synth, n_req, slots, hbm_gib, fracs, precision, seed, check_n):
+def serve_leg(ks, synth, n_req, slots, hbm_gib, fracs, precision, seed, check_n, batched,
+              small=False):
     """Serving stream: n_req requests of mixed sizes through the library's server.
 
     First all requests are submitted at t = 0 (saturated throughput), then the same
@@ -133,7 +134,8 @@ def serve_leg(ks, synth, n_req, slots, hbm_gib, fracs, precision, seed, check_n)
     prec = ks.KS_PREC_FP32 if precision == "fp32" else ks.KS_PREC_FP64
     dt = np.float32 if precision == "fp32" else np.float64
     prm = ks.ks_default_params()
-    base = synth.make_serving_stream(n_req=n_req, rate=0.0, seed=seed)
+    mix = dict(sides=(16,), p_range=(2, 8), m_range=(1, 4)) if small else {}
+    base = synth.make_serving_stream(n_req=n_req, rate=0.0, seed=seed, **mix)
     descs = [ks.desc_from_spec(r.spec, precision=prec, hartree_solver=ks.KS_HARTREE_PCG_FD)
              for r in base]
     x0s = [synth.make_x0(r.spec, r.seed).astype(dt) for r in base]
@@ -145,7 +147,7 @@ def serve_leg(ks, synth, n_req, slots, hbm_gib, fracs, precision, seed, check_n)
         return v[k]
 
     def run(arrivals):
-        sv = ks.KSServer(nbytes, slots)
+        sv = ks.KSServer(nbytes, slots, batched=batched)
         t0 = time.perf_counter()
         for i, d in enumerate(descs):
             if arrivals is not None:
@@ -169,12 +171,14 @@ def serve_leg(ks, synth, n_req, slots, hbm_gib, fracs, precision, seed, check_n)
 
     sat, done_sat = run(None)
     print(f"# serve saturated: {sat}", file=sys.stderr, flush=True)
-    out = {"requests": n_req, "slots": slots, "hbm_budget_GiB": hbm_gib,
-           "precision": precision, "saturated": sat}
+    out = {"requests": n_req, "mode": "continuous batching" if batched else "worker streams",
+           "resident_max" if batched else "slots": slots, "hbm_budget_GiB": hbm_gib,
+           "precision": precision, "request_mix": "16^3, p 2-8" if small else "c5",
+           "saturated": sat}
     rate_sat = sat["solves_per_s"]
     for fr in fracs:
         rate = fr * rate_sat
-        stream = synth.make_serving_stream(n_req=n_req, rate=rate, seed=seed)
+        stream = synth.make_serving_stream(n_req=n_req, rate=rate, seed=seed, **mix)
         res, _ = run([r.arrival for r in stream])
         res["rate_per_s"] = round(rate, 3)
         print(f"# serve at {fr} x saturated: {res}", file=sys.stderr, flush=True)
@@ -182,7 +186,7 @@ def serve_leg(ks, synth, n_req, slots, hbm_gib, fracs, precision, seed, check_n)
     if check_n > 0 and precision == "fp32":
         # error of the FP32 results against FP64 runs of the same requests
         e32 = {c["id"]: c["result"].energy for c in done_sat}
-        sv = ks.KSServer(nbytes, slots)
+        sv = ks.KSServer(nbytes, slots, batched=batched)
         for i in range(min(check_n, n_req)):
             d64 = ks.desc_from_spec(base[i].spec, hartree_solver=ks.KS_HARTREE_PCG_FD)
             sv.ks_server_submit(i, d64, synth.make_x0(base[i].spec, base[i].seed), prm)
@@ -209,8 +213,14 @@ def main():
                     help="timed solves of the FP32-storage leg (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests in the serving leg (0 = skip)")
-    ap.add_argument("--serve-slots", type=int, default=4,
-                    help="concurrent requests (the device has 4 hardware queues per process)")
+    ap.add_argument("--serve-mode", choices=["batched", "streams"], default="batched",
+                    help="continuous batching (one launch per kernel for all resident "
+                         "requests) or one worker stream per slot")
+    ap.add_argument("--serve-slots", type=int, default=0,
+                    help="resident requests (batched, default 16) or worker streams "
+                         "(default 4: the device has 4 hardware queues per process)")
+    ap.add_argument("--serve-small", action="store_true",
+                    help="a mix of small requests (16^3 grids, p 2-8) instead of the c5 mix")
     ap.add_argument("--serve-hbm-gib", type=float, default=8.0)
     ap.add_argument("--serve-precision", choices=["fp32", "fp64"], default="fp64",
                     help="storage precision of the served requests (FP32 reaches the float "
@@ -372,8 +382,11 @@ def main():
     serve = None
     if args.serve_requests > 0:
         fr = [float(v) for v in args.serve_fracs.split(",") if v]
-        serve = serve_leg(ks, synth, args.serve_requests, args.serve_slots, args.serve_hbm_gib,
-                          fr, args.serve_precision, args.seed, args.serve_check)
+        batched = args.serve_mode == "batched"
+        slots = args.serve_slots or (16 if batched else 4)
+        serve = serve_leg(ks, synth, args.serve_requests, slots, args.serve_hbm_gib,
+                          fr, args.serve_precision, args.seed, args.serve_check, batched,
+                          args.serve_small)
     cpu = None
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)

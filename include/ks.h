@@ -298,6 +298,15 @@ typedef struct ks_completion {
  * (1..64) concurrent workers on the current device.  Errors: KS_E_INVAL, KS_E_HIP. */
 int ks_server_create(void* dev_workspace, size_t ws_bytes, int n_slots, ks_server** out);
 
+/* Creates a server in continuous-batching mode: one engine thread keeps up to max_batch
+ * (1..16) requests resident and advances them together, one trial step at a time, with
+ * one launch per kernel for all of them (ks_minimize_batch's lockstep runner); between
+ * steps it admits queued requests into free regions and places, and retires the ones
+ * that stopped.  Requests outside the runner's limits run alone on the engine thread.
+ * Results equal lone ks_minimize runs bit for bit.  Errors: KS_E_INVAL, KS_E_HIP. */
+int ks_server_create_batched(void* dev_workspace, size_t ws_bytes, int max_batch,
+                             ks_server** out);
+
 /* Queues a request (copies X0 and the descriptor's host arrays before returning; X_out
  * must stay valid until the request's completion has been polled).  A request larger
  * than the whole workspace completes at once with status KS_E_NOMEM.  Errors: KS_E_INVAL

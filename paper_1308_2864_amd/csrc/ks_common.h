@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/ks.h"
+
 namespace ks {
 
 constexpr int kBlock = 256;          // threads per block of the streaming kernels
@@ -141,6 +143,18 @@ __device__ inline int batch_system(const int* off, int S, int b) {
   while (s + 1 < S && b >= off[s + 1]) ++s;
   return s;
 }
+
+// Lockstep runner (ks_api.hip): members run Alg. 3 with one launch per trial kernel for
+// all of them.  batch_add starts a run on the system's stream (which must be the engine's
+// stream); batch_tick advances every active member by one trial; batch_take pops a
+// finished run.
+struct BatchEngine;
+BatchEngine* batch_create(hipStream_t st);
+void batch_destroy(BatchEngine* e);
+int batch_size(const BatchEngine* e);
+int batch_add(BatchEngine* e, ks_system* s, void* X, const ks_opt_params* o, void* tag);
+int batch_tick(BatchEngine* e);
+bool batch_take(BatchEngine* e, void** tag, ks_result* r, int* code);
 
 // ------------------------------------------------------------------------------------
 // Launch wrappers (defined in the .hip files).  All take the stream last.

@@ -11,6 +11,12 @@
 // large requests from starving.  Every request runs the same kernels with the same
 // reduction order as a lone ks_minimize call, so its result does not depend on what else
 // is resident.
+//
+// In batched mode (ks_server_create_batched) one engine thread does continuous batching:
+// between trial steps it admits queued requests while regions and batch places are free,
+// advances every resident request by one trial with one launch per kernel for all of
+// them, and retires the ones that stopped.  Requests the lockstep runner cannot take run
+// alone on the engine thread.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -23,7 +29,7 @@
 
 #include <hip/hip_runtime.h>
 
-#include "../../include/ks.h"
+#include "ks_common.h"
 
 namespace {
 
@@ -59,6 +65,7 @@ struct ks_server {
   std::vector<std::thread> workers;
   int running = 0;
   bool stop = false;
+  int max_batch = 0;  // > 0: batched mode
 
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -171,6 +178,120 @@ void worker(ks_server* sv) {
   if (st) (void)hipStreamDestroy(st);
 }
 
+// Whether the lockstep runner takes the request (its limits are in include/ks.h).
+bool batch_ok(const ks_request& rq) {
+  const ks_system_desc& d = rq.desc;
+  return d.disc == KS_DISC_FD7 && d.hartree_solver == KS_HARTREE_PCG_FD &&
+         (d.terms & KS_TERM_HARTREE) && d.p <= 32 && rq.params.retraction == KS_QR &&
+         (d.precision == KS_PREC_FP64 || d.precision == KS_PREC_FP32);
+}
+
+struct Resident {
+  Job* jb;
+  size_t off;
+  ks_system* sys;
+  char* X;
+  ks_completion c;
+};
+
+void finish_resident(ks_server* sv, Resident* rs, int code, const ks_result& r,
+                     hipStream_t st) {
+  rs->c.status = code;
+  rs->c.result = r;
+  if ((code == KS_OK || code == KS_E_NOT_CONVERGED) && rs->jb->rq.X_out) {
+    hipError_t e = hipMemcpyAsync(rs->jb->rq.X_out, rs->X, rs->jb->x_bytes,
+                                  hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) rs->c.status = KS_E_HIP;
+  }
+  ks_destroy_system(rs->sys);
+  rs->c.t_done = sv->now();
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->give(rs->off, rs->c.bytes);
+    sv->done.push_back(rs->c);
+    --sv->running;
+  }
+  delete rs->jb;
+  delete rs;
+  sv->cv_idle.notify_all();
+}
+
+void batch_worker(ks_server* sv) {
+  hipStream_t st = nullptr;
+  const bool ok = hipSetDevice(sv->device) == hipSuccess &&
+                  hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+  ks::BatchEngine* eng = ok ? ks::batch_create(st) : nullptr;
+  for (;;) {
+    std::vector<std::pair<Job*, size_t>> admit;
+    {
+      std::unique_lock<std::mutex> lk(sv->mu);
+      auto fill = [&] {
+        size_t off = 0;
+        while (!sv->queue.empty() &&
+               (eng ? ks::batch_size(eng) : 0) + (int)admit.size() < sv->max_batch) {
+          Job* h = sv->queue.front();
+          if (!sv->take(align_up(h->ws_bytes) + align_up(h->x_bytes), &off)) break;
+          sv->queue.pop_front();
+          ++sv->running;
+          admit.emplace_back(h, off);
+        }
+      };
+      fill();
+      if (admit.empty() && (!eng || ks::batch_size(eng) == 0)) {
+        sv->cv_work.wait(lk, [&] {
+          if (sv->stop) return true;
+          fill();
+          return !admit.empty();
+        });
+        if (sv->stop && admit.empty()) break;
+      }
+    }
+    for (auto& a : admit) {
+      Resident* rs = new Resident{a.first, a.second, nullptr, nullptr, ks_completion{}};
+      Job* jb = a.first;
+      rs->c.id = jb->rq.id;
+      rs->c.t_submit = jb->t_submit;
+      rs->c.t_admit = sv->now();
+      rs->c.bytes = align_up(jb->ws_bytes) + align_up(jb->x_bytes);
+      char* ws = sv->base + a.second;
+      rs->X = ws + align_up(jb->ws_bytes);
+      ks_result r{};
+      int rc = ok ? KS_OK : KS_E_HIP;
+      if (rc == KS_OK &&
+          hipMemcpyAsync(rs->X, jb->X0.data(), jb->x_bytes, hipMemcpyHostToDevice, st) !=
+              hipSuccess)
+        rc = KS_E_HIP;
+      if (rc == KS_OK) rc = ks_create_system(&jb->rq.desc, ws, jb->ws_bytes, st, &rs->sys);
+      if (rc == KS_OK && batch_ok(jb->rq)) {
+        ks::batch_add(eng, rs->sys, rs->X, &jb->rq.params, rs);
+        continue;  // batch_add parks failures and instant stops in the finished list
+      }
+      // not for the lockstep runner: run it alone here
+      if (rc == KS_OK) rc = ks_minimize(rs->sys, rs->X, &jb->rq.params, &r);
+      finish_resident(sv, rs, rc, r, st);
+    }
+    if (eng && ks::batch_size(eng) > 0) ks::batch_tick(eng);
+    void* tag = nullptr;
+    ks_result r{};
+    int code = KS_OK;
+    while (eng && ks::batch_take(eng, &tag, &r, &code))
+      finish_resident(sv, static_cast<Resident*>(tag), code, r, st);
+    sv->cv_work.notify_all();
+  }
+  // stop: finish what is resident so every admitted request completes
+  while (eng && ks::batch_size(eng) > 0) {
+    ks::batch_tick(eng);
+    void* tag = nullptr;
+    ks_result r{};
+    int code = KS_OK;
+    while (ks::batch_take(eng, &tag, &r, &code))
+      finish_resident(sv, static_cast<Resident*>(tag), code, r, st);
+  }
+  ks::batch_destroy(eng);
+  if (st) (void)hipStreamDestroy(st);
+}
+
 }  // namespace
 
 extern "C" {
@@ -190,6 +311,28 @@ int ks_server_create(void* dev_workspace, size_t ws_bytes, int n_slots, ks_serve
   sv->free_list.push_back(Region{0, sv->bytes});
   sv->t0 = std::chrono::steady_clock::now();
   for (int i = 0; i < n_slots; ++i) sv->workers.emplace_back(worker, sv);
+  *out = sv;
+  return KS_OK;
+}
+
+int ks_server_create_batched(void* dev_workspace, size_t ws_bytes, int max_batch,
+                             ks_server** out) {
+  if (!out) return KS_E_INVAL;
+  *out = nullptr;
+  if (!dev_workspace || ws_bytes == 0 || max_batch < 1 || max_batch > ks::kMaxBatch)
+    return KS_E_INVAL;
+  if (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign != 0) return KS_E_INVAL;
+  ks_server* sv = new ks_server();
+  if (hipGetDevice(&sv->device) != hipSuccess) {
+    delete sv;
+    return KS_E_HIP;
+  }
+  sv->base = static_cast<char*>(dev_workspace);
+  sv->bytes = ws_bytes / kAlign * kAlign;
+  sv->free_list.push_back(Region{0, sv->bytes});
+  sv->t0 = std::chrono::steady_clock::now();
+  sv->max_batch = max_batch;
+  sv->workers.emplace_back(batch_worker, sv);
   *out = sv;
   return KS_OK;
 }

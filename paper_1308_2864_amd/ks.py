@@ -124,6 +124,7 @@ def _load():
                                    C.POINTER(ks_result), C.POINTER(ip)]),
         "ks_timer_phases": (ip, [vp, C.c_uint]),
         "ks_server_create": (ip, [vp, C.c_size_t, ip, C.POINTER(vp)]),
+        "ks_server_create_batched": (ip, [vp, C.c_size_t, ip, C.POINTER(vp)]),
         "ks_server_submit": (ip, [vp, C.POINTER(ks_request)]),
         "ks_server_poll": (ip, [vp, C.POINTER(ks_completion), ip, C.POINTER(ip)]),
         "ks_server_wait_idle": (ip, [vp]),
@@ -329,7 +330,8 @@ def ks_request_bytes(desc) -> int:
 
 
 class KSServer:
-    """ks_server_* over a torch-owned device workspace of ``nbytes``.
+    """ks_server_* over a torch-owned device workspace of ``nbytes``.  With batched=True,
+    n_slots is the number of requests the continuous-batching engine keeps resident.
 
     ``submit`` takes a descriptor, a host start block (n x p, float64 or float32 to match
     the descriptor's precision) and optional parameters; the result block, when asked
@@ -337,7 +339,7 @@ class KSServer:
     been polled.
     """
 
-    def __init__(self, nbytes, n_slots, device="cuda"):
+    def __init__(self, nbytes, n_slots, device="cuda", batched=False):
         import torch
         self.device = torch.device(device)
         self.workspace = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=self.device)
@@ -345,8 +347,8 @@ class KSServer:
         base = self.workspace.data_ptr()
         off = (-base) % 256
         h = C.c_void_p()
-        _check(lib.ks_server_create(C.c_void_p(base + off), int(nbytes), int(n_slots),
-                                    C.byref(h)))
+        create = lib.ks_server_create_batched if batched else lib.ks_server_create
+        _check(create(C.c_void_p(base + off), int(nbytes), int(n_slots), C.byref(h)))
         self.h = h
         self._out = {}
 

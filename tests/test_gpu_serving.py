@@ -37,8 +37,8 @@ def _alone(K, rq, precision, prm):
     return r, out
 
 
-def _run_server(K, reqs, precision, prm, nbytes, slots):
-    sv = K.KSServer(nbytes, slots)
+def _run_server(K, reqs, precision, prm, nbytes, slots, batched=False):
+    sv = K.KSServer(nbytes, slots, batched=batched)
     dt = np.float32 if precision == K.KS_PREC_FP32 else np.float64
     for rq in reqs:
         desc = K.desc_from_spec(rq.spec, precision=precision, hartree_solver=K.KS_HARTREE_PCG_FD)
@@ -51,10 +51,12 @@ def _run_server(K, reqs, precision, prm, nbytes, slots):
     return done
 
 
+@pytest.mark.parametrize("batched", [False, True])
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_server_alone_vs_mix_bitwise(precision):
-    """Eight requests of mixed grid sizes and orbital counts run four at a time: every
-    energy, iteration count and orbital block equals the lone ks_minimize run bit for bit."""
+def test_server_alone_vs_mix_bitwise(precision, batched):
+    """Eight requests of mixed grid sizes and orbital counts run four at a time (on worker
+    streams, or resident together in the continuous-batching engine): every energy,
+    iteration count and orbital block equals the lone ks_minimize run bit for bit."""
     K = ks()
     prec = K.KS_PREC_FP32 if precision == "fp32" else K.KS_PREC_FP64
     prm = K.ks_default_params(max_iter=150)
@@ -62,7 +64,7 @@ def test_server_alone_vs_mix_bitwise(precision):
     total = sum(K.ks_request_bytes(K.desc_from_spec(r.spec, precision=prec,
                                                     hartree_solver=K.KS_HARTREE_PCG_FD))
                 for r in reqs)
-    done = _run_server(K, reqs, prec, prm, total, 4)
+    done = _run_server(K, reqs, prec, prm, total, 4, batched)
     assert sorted(done) == [r.rid for r in reqs]
     for rq in reqs:
         c = done[rq.rid]
@@ -120,3 +122,30 @@ def test_server_poll_empty_and_destroy_with_queue():
         sv.ks_server_submit(rq.rid, d, synth.make_x0(rq.spec, rq.seed), prm)
     sv.close()
     torch.cuda.synchronize()
+
+
+def test_batched_server_admits_by_footprint_and_runs_odd_requests_alone():
+    """Continuous batching under a budget that holds two requests at a time, with one
+    request the lockstep runner does not take (plain CG Hartree): all complete, and the
+    resident set never needs more memory than the budget."""
+    K = ks()
+    prm = K.ks_default_params(max_iter=60)
+    reqs = _requests(5, seed=11, sides=(16,), p_range=(4, 4), m_range=(2, 2))
+    descs = [K.desc_from_spec(r.spec, hartree_solver=K.KS_HARTREE_PCG_FD) for r in reqs]
+    descs[2] = K.desc_from_spec(reqs[2].spec, hartree_solver=K.KS_HARTREE_CG)
+    one = max(K.ks_request_bytes(d) for d in descs)
+    sv = K.KSServer(int(2.5 * one), 8, batched=True)
+    for rq, d in zip(reqs, descs):
+        sv.ks_server_submit(rq.rid, d, synth.make_x0(rq.spec, rq.seed), prm)
+    sv.ks_server_wait_idle()
+    done = {c["id"]: c for c in sv.ks_server_poll()}
+    sv.close()
+    assert sorted(done) == [r.rid for r in reqs]
+    for rq in reqs:
+        assert done[rq.rid]["status"] in (K.KS_OK, K.KS_E_NOT_CONVERGED)
+    # at most two resident at any time
+    ev = sorted([(c["t_admit"], 1) for c in done.values()] + [(c["t_done"], -1) for c in done.values()])
+    live = 0
+    for _, d in ev:
+        live += d
+        assert live <= 2
