@@ -168,7 +168,7 @@ __global__ void k_xc_batch(BatchPtrs<XcArgs> b) {
 // z neighbours of plane k are the centres of planes k-1 and k+1, which it already holds,
 // so each output costs five loads (centre and four in-plane neighbours) and the block is
 // streamed plane by plane.  Consecutive threads take consecutive orbitals of one point.
-constexpr int kHxChunk = 16;
+constexpr int kHxChunk = 8;
 
 template <typename T, bool kEnergy>
 __device__ inline void k_hx_body(const HxArgs<T>& ka, int ks_bid, int ks_nb) {
@@ -206,6 +206,7 @@ __device__ inline void k_hx_body(const HxArgs<T>& ka, int ks_bid, int ks_nb) {
     const T* col = X + (ptrdiff_t)(i + (size_t)nx * j) * ldx + c;
     double below = k0 > 0 ? (double)col[(k0 - 1) * sz] : 0.0;
     double cur = (double)col[k0 * sz];
+#pragma unroll 2
     for (int k = k0; k < k1; ++k) {
       const T* xp = col + k * sz;
       const double above = k + 1 < nz ? (double)xp[sz] : 0.0;

@@ -374,30 +374,34 @@ __device__ inline double sget(const double* S, int N, int row, int col) {
 
 constexpr int kFdWaves = 8;     // waves per block of the transform kernels
 constexpr int kFdTiles = 8;     // result tiles a wave can hold (covers 128 x 128)
+constexpr int kZCols = 32;      // (i, j) lines per block of the z transform
 
-// 2-D transform of one z-plane (block = plane k): Y = S_y P S_x with P the ny x nx plane
-// (row = y).  Step 1 T = P S_x (results held in registers), step 2 Y = S_y T.  The plane
-// lives in LDS (row stride nxp + 1 doubles: conflict-free column reads).  With part the
-// partial r.Y of the plane goes to slot 3.
-template <bool kStageS>
+// 2-D transform of one z-plane, split by 16-column strips of the output: block
+// (plane k, strip c) computes T[:, strip] = P S_x[:, strip] and then
+// Y[:, strip] = S_y T[:, strip] (row = y), which needs only that strip of T, so the strips
+// of a plane are independent blocks.  The plane lives in LDS (row stride nxp + 1 doubles:
+// conflict-free column reads), then the T strip, the S_x strip and (kStageSy, when it
+// fits) S_y, so the MFMA operands of both steps come from LDS.  With part the partial r.Y
+// of the block goes to slot 3 at the block's index.
+constexpr int kPlaneWaves = 4;
+
+template <bool kStageSy>
 __device__ inline void k_fd_plane_body(const FdPlaneArgs& ka, int ks_bid, int ks_nb) {
   const double* __restrict__ in = ka.in;
   double* __restrict__ out = ka.out;
-  const double* __restrict__ Sxg = ka.Sxg;
-  const double* __restrict__ Syg = ka.Syg;
-  int nx = ka.nx;
-  int ny = ka.ny;
+  const double* __restrict__ Sx = ka.Sxg;
+  const double* __restrict__ Sy = ka.Syg;
+  const int nx = ka.nx, ny = ka.ny;
   const double* __restrict__ r = ka.r;
   double* __restrict__ part = ka.part;
   const CgState* cs = ka.cs;
-  (void)ks_bid;
   (void)ks_nb;
-
   extern __shared__ double P[];
-  __shared__ double sh[512 / kWave];
+  __shared__ double sh[kBlock / kWave];
   if (cs->done) return;
-  const int k = ks_bid;
   const int nxp = (nx + 15) & ~15, nyp = (ny + 15) & ~15, sp = nxp + 1;
+  const int ncs = nxp / 16;
+  const int k = ks_bid / ncs, i0 = (ks_bid % ncs) * 16;
   const size_t base = (size_t)k * nx * ny;
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int lr = lane / 16, lc = lane % 16;
@@ -405,78 +409,62 @@ __device__ inline void k_fd_plane_body(const FdPlaneArgs& ka, int ks_bid, int ks
     const int j = e / nxp, m = e % nxp;
     P[j * sp + m] = (j < ny && m < nx) ? in[base + (size_t)j * nx + m] : 0.0;
   }
-  // the sine matrices follow the plane in LDS when they fit (dense nx x nx, ny x ny)
-  const double* Sx = Sxg;
-  const double* Sy = Syg;
-  if (kStageS) {
-    double* sx = P + nyp * sp;
-    double* sy = sx + nx * nx;
-    for (int e = threadIdx.x; e < nx * nx; e += blockDim.x) sx[e] = Sxg[e];
-    for (int e = threadIdx.x; e < ny * ny; e += blockDim.x) sy[e] = Syg[e];
-    Sx = sx;
-    Sy = sy;
+  double* Tt = P + nyp * sp;     // nyp x 17
+  double* Sxs = Tt + nyp * 17;   // nxp x 16: S_x[:, i0 .. i0 + 15]
+  for (int e = threadIdx.x; e < nxp * 16; e += blockDim.x) {
+    const int m = e / 16, c = e % 16;
+    Sxs[e] = (m < nx && i0 + c < nx) ? Sx[m * nx + i0 + c] : 0.0;
+  }
+  const double* SyL = Sy;
+  if (kStageSy) {
+    double* sy = Sxs + nxp * 16;
+    for (int e = threadIdx.x; e < ny * ny; e += blockDim.x) sy[e] = Sy[e];
+    SyL = sy;
   }
   __syncthreads();
-  const int tx = nxp / 16, ntile = (nyp / 16) * tx;
-  d4 acc[kFdTiles];
-  // step 1: T[j][i] = sum_m P[j][m] S_x[m][i]
+  const int ntile = nyp / 16;
+  // step 1: T[j][i0 + c] = sum_m P[j][m] S_x[m][i0 + c]
+  for (int t = w; t < ntile; t += kPlaneWaves) {
+    const int j0 = t * 16;
+    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < nxp; k0 += 4)
+      acc = mma(P[(j0 + lc) * sp + k0 + lr], Sxs[(k0 + lr) * 16 + lc], acc);
 #pragma unroll
-  for (int s = 0; s < kFdTiles; ++s) {
-    acc[s] = d4{0.0, 0.0, 0.0, 0.0};
-    const int t = w + s * kFdWaves;
-    if (t < ntile) {
-      const int j0 = (t / tx) * 16, i0 = (t % tx) * 16;
-      for (int k0 = 0; k0 < nxp; k0 += 4)
-        acc[s] = mma(P[(j0 + lc) * sp + k0 + lr], sget(Sx, nx, k0 + lr, i0 + lc), acc[s]);
-    }
+    for (int q = 0; q < 4; ++q) Tt[(j0 + lr + 4 * q) * 17 + lc] = acc[q];
   }
   __syncthreads();
-#pragma unroll
-  for (int s = 0; s < kFdTiles; ++s) {
-    const int t = w + s * kFdWaves;
-    if (t < ntile) {
-      const int j0 = (t / tx) * 16, i0 = (t % tx) * 16;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) P[(j0 + lr + 4 * q) * sp + i0 + lc] = acc[s][q];
-    }
-  }
-  __syncthreads();
-  // step 2: Y[j][i] = sum_m S_y[j][m] T[m][i]
+  // step 2: Y[j][i0 + c] = sum_m S_y[j][m] T[m][i0 + c]
   double rz = 0.0;
+  for (int t = w; t < ntile; t += kPlaneWaves) {
+    const int j0 = t * 16;
+    d4 y = d4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < nyp; k0 += 4)
+      y = mma(sget(SyL, ny, k0 + lr, j0 + lc), Tt[(k0 + lr) * 17 + lc], y);
 #pragma unroll
-  for (int s = 0; s < kFdTiles; ++s) {
-    const int t = w + s * kFdWaves;
-    if (t < ntile) {
-      const int j0 = (t / tx) * 16, i0 = (t % tx) * 16;
-      d4 y = d4{0.0, 0.0, 0.0, 0.0};
-      for (int k0 = 0; k0 < nyp; k0 += 4)
-        y = mma(sget(Sy, ny, k0 + lr, j0 + lc), P[(k0 + lr) * sp + i0 + lc], y);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int j = j0 + lr + 4 * q, i = i0 + lc;
-        if (j < ny && i < nx) {
-          const size_t o = base + (size_t)j * nx + i;
-          out[o] = y[q];
-          if (part) rz += y[q] * r[o];
-        }
+    for (int q = 0; q < 4; ++q) {
+      const int j = j0 + lr + 4 * q, i = i0 + lc;
+      if (j < ny && i < nx) {
+        const size_t o = base + (size_t)j * nx + i;
+        out[o] = y[q];
+        if (part) rz += y[q] * r[o];
       }
     }
   }
   if (part) {
     rz = block_sum(rz, sh);
-    if (threadIdx.x == 0) part[3 * kCgBlocksMax + k] = rz;
+    if (threadIdx.x == 0) part[3 * kCgBlocksMax + ks_bid] = rz;
   }
 }
 
-template <bool kStageS>
-__global__ __launch_bounds__(512) void k_fd_plane(FdPlaneArgs ka) {
-  k_fd_plane_body<kStageS>(ka, blockIdx.x, gridDim.x);
+template <bool kStageSy>
+__global__ __launch_bounds__(256) void k_fd_plane(FdPlaneArgs ka) {
+  k_fd_plane_body<kStageSy>(ka, blockIdx.x, gridDim.x);
 }
 
-template <bool kStageS>
-__global__ __launch_bounds__(512) void k_fd_plane_batch(BatchPtrs<FdPlaneArgs> b) {
+template <bool kStageSy>
+__global__ __launch_bounds__(256) void k_fd_plane_batch(BatchPtrs<FdPlaneArgs> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_fd_plane_body<kStageS>(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+  k_fd_plane_body<kStageSy>(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
 }
 
 
@@ -499,34 +487,35 @@ __device__ inline void k_fd_z_body(const FdZArgs& ka, int ks_bid, int ks_nb) {
   (void)ks_bid;
   (void)ks_nb;
 
-  extern __shared__ double A[];  // nzp x 64 (then S_z when it fits)
+  extern __shared__ double A[];  // nzp x kZCols (then S_z when it fits)
   if (cs->done) return;
   const int npl = nx * ny;
   const int nzp = (nz + 15) & ~15;
-  const int l0 = ks_bid * 64;
+  const int l0 = ks_bid * kZCols;
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int lr = lane / 16, lc = lane % 16;
-  for (int e = threadIdx.x; e < nzp * 64; e += blockDim.x) {
-    const int m = e / 64, l = e % 64;
+  for (int e = threadIdx.x; e < nzp * kZCols; e += blockDim.x) {
+    const int m = e / kZCols, l = e % kZCols;
     A[e] = (m < nz && l0 + l < npl) ? u[(size_t)m * npl + l0 + l] : 0.0;
   }
   const double* Sz = Szg;
   if (kStageS) {
-    double* sz = A + nzp * 64;
+    double* sz = A + nzp * kZCols;
     for (int e = threadIdx.x; e < nz * nz; e += blockDim.x) sz[e] = Szg[e];
     Sz = sz;
   }
   __syncthreads();
-  const int ntile = (nzp / 16) * 4;
+  constexpr int kCT = kZCols / 16;  // column tiles per block
+  const int ntile = (nzp / 16) * kCT;
   d4 acc[kFdTiles];
 #pragma unroll
   for (int s = 0; s < kFdTiles; ++s) {
     acc[s] = d4{0.0, 0.0, 0.0, 0.0};
     const int t = w + s * kFdWaves;
     if (t < ntile) {
-      const int k0t = (t / 4) * 16, c0 = (t % 4) * 16;
+      const int k0t = (t / kCT) * 16, c0 = (t % kCT) * 16;
       for (int k0 = 0; k0 < nzp; k0 += 4)
-        acc[s] = mma(sget(Sz, nz, k0 + lr, k0t + lc), A[(k0 + lr) * 64 + c0 + lc], acc[s]);
+        acc[s] = mma(sget(Sz, nz, k0 + lr, k0t + lc), A[(k0 + lr) * kZCols + c0 + lc], acc[s]);
       // divide by the eigenvalue at (i, j, k): lx my mz + mx ly mz + mx my lz (with unit
       // mass eigenvalues this is exactly lx + ly + lz)
       const int line = l0 + c0 + lc;
@@ -552,9 +541,9 @@ __device__ inline void k_fd_z_body(const FdZArgs& ka, int ks_bid, int ks_nb) {
   for (int s = 0; s < kFdTiles; ++s) {
     const int t = w + s * kFdWaves;
     if (t < ntile) {
-      const int k0t = (t / 4) * 16, c0 = (t % 4) * 16;
+      const int k0t = (t / kCT) * 16, c0 = (t % kCT) * 16;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) A[(k0t + lr + 4 * q) * 64 + c0 + lc] = acc[s][q];
+      for (int q = 0; q < 4; ++q) A[(k0t + lr + 4 * q) * kZCols + c0 + lc] = acc[s][q];
     }
   }
   __syncthreads();
@@ -562,10 +551,10 @@ __device__ inline void k_fd_z_body(const FdZArgs& ka, int ks_bid, int ks_nb) {
   for (int s = 0; s < kFdTiles; ++s) {
     const int t = w + s * kFdWaves;
     if (t < ntile) {
-      const int k0t = (t / 4) * 16, c0 = (t % 4) * 16;
+      const int k0t = (t / kCT) * 16, c0 = (t % kCT) * 16;
       d4 y = d4{0.0, 0.0, 0.0, 0.0};
       for (int k0 = 0; k0 < nzp; k0 += 4)
-        y = mma(sget(Sz, nz, k0 + lr, k0t + lc), A[(k0 + lr) * 64 + c0 + lc], y);
+        y = mma(sget(Sz, nz, k0 + lr, k0t + lc), A[(k0 + lr) * kZCols + c0 + lc], y);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int kk = k0t + lr + 4 * q, line = l0 + c0 + lc;
@@ -620,7 +609,7 @@ void set_lds(const void* k, size_t bytes) {
 // LDS the preconditioner needs for an nx x ny x nz grid.
 size_t fd_lds_bytes(int nx, int ny, int nz) {
   const size_t nxp = (nx + 15) & ~15, nyp = (ny + 15) & ~15, nzp = (nz + 15) & ~15;
-  return std::max(nyp * (nxp + 1), nzp * 64) * sizeof(double);
+  return std::max(nyp * (nxp + 1), nzp * (size_t)kZCols) * sizeof(double);
 }
 
 // Largest plane the register tiles of k_fd_plane cover (kFdWaves * kFdTiles tiles).
@@ -628,35 +617,45 @@ int fd_max_plane() { return kFdWaves * kFdTiles * 256; }
 
 // z = L^{-1} r by the fast diagonalisation (plane transform, z pass with the eigenvalue
 // division, inverse plane transform with the partial r.z), then beta from r.z.
-void launch_fd_apply(const double* r, double* z, const FdOps& fd, Grid g, const CgState* cs,
-                     double* part, hipStream_t st) {
+void launch_fd_apply(const double* r, double* z, double* tmp, const FdOps& fd, Grid g,
+                     const CgState* cs, double* part, hipStream_t st) {
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const size_t nxp = (nx + 15) & ~15, nyp = (ny + 15) & ~15, nzp = (nz + 15) & ~15;
-  const size_t lp = nyp * (nxp + 1) * sizeof(double);
-  const size_t lps = lp + (size_t)(nx * nx + ny * ny) * sizeof(double);
-  const size_t lzb = nzp * 64 * sizeof(double);
+  const size_t lzb = nzp * kZCols * sizeof(double);
   const size_t lzs = lzb + (size_t)nz * nz * sizeof(double);
   const size_t cap = kFdLdsCap;
   const int threads = kFdWaves * kWave;
+  const int ncs = (int)(nxp / 16);
+  const size_t lpl = (nyp * (nxp + 1) + nyp * 17 + nxp * 16) * sizeof(double);
+  const size_t lpls = lpl + (size_t)ny * ny * sizeof(double);
   auto plane = [&](const double* in, double* out, const double* rr, double* pt) {
-    if (lps <= cap) {
-      set_lds(reinterpret_cast<const void*>(k_fd_plane<true>), lps);
-      hipLaunchKernelGGL(k_fd_plane<true>, dim3(nz), dim3(threads), lps, st, FdPlaneArgs{in, out, fd.Sx, fd.Sy, nx, ny, rr, pt, cs});
+    const FdPlaneArgs pa{in, out, fd.Sx, fd.Sy, nx, ny, rr, pt, cs};
+    if (lpls <= cap) {
+      set_lds(reinterpret_cast<const void*>(k_fd_plane<true>), lpls);
+      hipLaunchKernelGGL(k_fd_plane<true>, dim3(nz * ncs), dim3(kPlaneWaves * kWave), lpls,
+                         st, pa);
     } else {
-      set_lds(reinterpret_cast<const void*>(k_fd_plane<false>), lp);
-      hipLaunchKernelGGL(k_fd_plane<false>, dim3(nz), dim3(threads), lp, st, FdPlaneArgs{in, out, fd.Sx, fd.Sy, nx, ny, rr, pt, cs});
+      set_lds(reinterpret_cast<const void*>(k_fd_plane<false>), lpl);
+      hipLaunchKernelGGL(k_fd_plane<false>, dim3(nz * ncs), dim3(kPlaneWaves * kWave), lpl,
+                         st, pa);
     }
   };
-  plane(r, z, nullptr, nullptr);
+
+  // the strips of a plane are separate blocks, so a plane pass never works in place:
+  // r -> tmp, z pass in place on tmp, tmp -> z
+  const int zblocks = (nx * ny + kZCols - 1) / kZCols;
+  const FdZArgs za{tmp, fd.Sz, fd.lx, fd.ly, fd.lz, fd.mx, fd.my, fd.mz, nx, ny, nz, cs};
+  plane(r, tmp, nullptr, nullptr);
   if (lzs <= cap) {
     set_lds(reinterpret_cast<const void*>(k_fd_z<true>), lzs);
-    hipLaunchKernelGGL(k_fd_z<true>, dim3((nx * ny + 63) / 64), dim3(threads), lzs, st, FdZArgs{z, fd.Sz, fd.lx, fd.ly, fd.lz, fd.mx, fd.my, fd.mz, nx, ny, nz, cs});
+    hipLaunchKernelGGL(k_fd_z<true>, dim3(zblocks), dim3(threads), lzs, st, za);
   } else {
     set_lds(reinterpret_cast<const void*>(k_fd_z<false>), lzb);
-    hipLaunchKernelGGL(k_fd_z<false>, dim3((nx * ny + 63) / 64), dim3(threads), lzb, st, FdZArgs{z, fd.Sz, fd.lx, fd.ly, fd.lz, fd.mx, fd.my, fd.mz, nx, ny, nz, cs});
+    hipLaunchKernelGGL(k_fd_z<false>, dim3(zblocks), dim3(threads), lzb, st, za);
   }
-  plane(z, z, r, part);
-  hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kBlock), 0, st, FinRzArgs{part, nz, const_cast<CgState*>(cs)});
+  plane(tmp, z, r, part);
+  hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kBlock), 0, st,
+                     FinRzArgs{part, nz * ncs, const_cast<CgState*>(cs)});
 }
 
 void launch_hartree_iter(double* x, double* r, const double* z, double* pa, double* pb,
@@ -676,13 +675,13 @@ int hartree_blocks(int n) { return cg_nblocks(n); }
 FdLaunch fd_launch(int nx, int ny, int nz) {
   const size_t nxp = (nx + 15) & ~15, nyp = (ny + 15) & ~15, nzp = (nz + 15) & ~15;
   FdLaunch l;
-  l.plane_bytes = nyp * (nxp + 1) * sizeof(double);
-  l.plane_bytes_staged = l.plane_bytes + (size_t)(nx * nx + ny * ny) * sizeof(double);
-  l.z_bytes = nzp * 64 * sizeof(double);
+  l.plane_bytes = (nyp * (nxp + 1) + nyp * 17 + nxp * 16) * sizeof(double);
+  l.plane_bytes_staged = l.plane_bytes + (size_t)ny * ny * sizeof(double);
+  l.z_bytes = nzp * kZCols * sizeof(double);
   l.z_bytes_staged = l.z_bytes + (size_t)nz * nz * sizeof(double);
   l.cap = kFdLdsCap;
-  l.plane_blocks = nz;
-  l.z_blocks = (nx * ny + 63) / 64;
+  l.plane_blocks = nz * (int)(nxp / 16);
+  l.z_blocks = (nx * ny + kZCols - 1) / kZCols;
   return l;
 }
 
@@ -709,13 +708,14 @@ void launch_fin_rz_batch(const BatchPtrs<FinRzArgs>& b, hipStream_t st) {
 }
 void launch_fd_plane_batch(const BatchPtrs<FdPlaneArgs>& b, int blocks, bool staged, size_t lds,
                            hipStream_t st) {
-  const int threads = kFdWaves * kWave;
   if (staged) {
     set_lds(reinterpret_cast<const void*>(k_fd_plane_batch<true>), lds);
-    hipLaunchKernelGGL(k_fd_plane_batch<true>, dim3(blocks), dim3(threads), lds, st, b);
+    hipLaunchKernelGGL(k_fd_plane_batch<true>, dim3(blocks), dim3(kPlaneWaves * kWave), lds, st,
+                       b);
   } else {
     set_lds(reinterpret_cast<const void*>(k_fd_plane_batch<false>), lds);
-    hipLaunchKernelGGL(k_fd_plane_batch<false>, dim3(blocks), dim3(threads), lds, st, b);
+    hipLaunchKernelGGL(k_fd_plane_batch<false>, dim3(blocks), dim3(kPlaneWaves * kWave), lds,
+                       st, b);
   }
 }
 void launch_fd_z_batch(const BatchPtrs<FdZArgs>& b, int blocks, bool staged, size_t lds,

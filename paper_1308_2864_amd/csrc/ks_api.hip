@@ -421,7 +421,7 @@ int hartree_iterate(ks_system* s, double* x, int first_chunk, bool wait, int* it
   for (;;) {
     const int c = std::min(chunk, s->hmaxit - launched);
     for (int i = 0; i < c; ++i) {
-      if (pcg) launch_fd_apply(s->cg_r, s->cg_z, fd, s->grid, s->cg, s->cgpart, s->st);
+      if (pcg) launch_fd_apply(s->cg_r, s->cg_z, s->cg_q, fd, s->grid, s->cg, s->cgpart, s->st);
       launch_hartree_iter(x, s->cg_r, s->cg_z, s->cg_p[s->cg_par], s->cg_p[1 - s->cg_par],
                           s->cg_q, s->cg, s->grid, s->cgpart, pcg ? 1 : 0, s->st);
       s->cg_par = 1 - s->cg_par;
@@ -935,14 +935,16 @@ void fill_typed(ks_system* s, std::vector<char>& buf, int c) {
   put_rec(buf, c, R_INIT, InitArgs{s->rho, s->vh[c], s->vh[t], s->cg_r, s->cg_p[0], s->grid,
                                    s->cgpart});
   put_rec(buf, c, R_FIN_INIT, FinInitArgs{s->cgpart, hb, s->cg, s->htol, s->hmaxit});
-  put_rec(buf, c, R_PLANE1, FdPlaneArgs{s->cg_r, s->cg_z, s->fdS[0], s->fdS[1], s->grid.nx,
+  put_rec(buf, c, R_PLANE1, FdPlaneArgs{s->cg_r, s->cg_q, s->fdS[0], s->fdS[1], s->grid.nx,
                                         s->grid.ny, nullptr, nullptr, s->cg});
-  put_rec(buf, c, R_FDZ, FdZArgs{s->cg_z, s->fdS[2], s->fdL[0], s->fdL[1], s->fdL[2], s->fdM[0],
+  put_rec(buf, c, R_FDZ, FdZArgs{s->cg_q, s->fdS[2], s->fdL[0], s->fdL[1], s->fdL[2], s->fdM[0],
                                  s->fdM[1], s->fdM[2], s->grid.nx, s->grid.ny, s->grid.nz,
                                  s->cg});
-  put_rec(buf, c, R_PLANE2, FdPlaneArgs{s->cg_z, s->cg_z, s->fdS[0], s->fdS[1], s->grid.nx,
+  put_rec(buf, c, R_PLANE2, FdPlaneArgs{s->cg_q, s->cg_z, s->fdS[0], s->fdS[1], s->grid.nx,
                                         s->grid.ny, s->cg_r, s->cgpart, s->cg});
-  put_rec(buf, c, R_FIN_RZ, FinRzArgs{s->cgpart, s->grid.nz, s->cg});
+  put_rec(buf, c, R_FIN_RZ, FinRzArgs{s->cgpart,
+                                      fd_launch(s->grid.nx, s->grid.ny, s->grid.nz).plane_blocks,
+                                      s->cg});
   put_rec(buf, c, R_DIR, DirArgs{s->cg_z, s->cg_p[0], s->cg_p[1], s->cg_q, s->cg, s->grid,
                                  s->cgpart});
   put_rec(buf, c, R_FIN_DIR, FinDirArgs{s->cgpart, hb, s->cg, 1});
@@ -1067,8 +1069,12 @@ void launch_trial_batch(const std::vector<BatchMember*>& g, hipStream_t st) {
     lds_p = std::max(lds_p, stage_p ? l.plane_bytes_staged : l.plane_bytes);
     lds_z = std::max(lds_z, stage_z ? l.z_bytes_staged : l.z_bytes);
   }
-  auto pb = [](const ks_system* s) { return s->grid.nz; };
-  auto zb = [](const ks_system* s) { return (s->grid.nx * s->grid.ny + 63) / 64; };
+  auto pb = [](const ks_system* s) {
+    return fd_launch(s->grid.nx, s->grid.ny, s->grid.nz).plane_blocks;
+  };
+  auto zb = [](const ks_system* s) {
+    return fd_launch(s->grid.nx, s->grid.ny, s->grid.nz).z_blocks;
+  };
   auto p1 = table<FdPlaneArgs>(g, R_PLANE1, pb, &tot);
   launch_fd_plane_batch(p1, tot, stage_p, lds_p, st);
   auto fz = table<FdZArgs>(g, R_FDZ, zb, &tot);

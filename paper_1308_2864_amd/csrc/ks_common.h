@@ -331,8 +331,9 @@ void launch_fd_setup(double* S, double* lam, double* mu, int N, double h, int q1
 void launch_hartree_init(const double* rho, const double* x0, double* x, double* r, double* p0,
                          CgState* cs, double tol, int maxit, Grid g, double* part,
                          hipStream_t st);
-void launch_fd_apply(const double* r, double* z, const FdOps& fd, Grid g, const CgState* cs,
-                     double* part, hipStream_t st);
+// z = L^{-1} r (or A^{-1} r) by the fast diagonalisation; tmp is an n-vector of scratch.
+void launch_fd_apply(const double* r, double* z, double* tmp, const FdOps& fd, Grid g,
+                     const CgState* cs, double* part, hipStream_t st);
 void launch_hartree_iter(double* x, double* r, const double* z, double* pa, double* pb,
                          double* q, CgState* cs, Grid g, double* part, int pcg,
                          hipStream_t st);
