@@ -405,7 +405,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{spec.name} FP64 {args.retraction.upper()} (configs[1])",
+        "config": {"workload": f"{spec.name} FP64 {args.retraction.upper()}",
                    "grid": [spec.nx, spec.ny, spec.nz], "h": spec.h, "p": spec.p,
                    "nuclei": spec.M, "eps_g": prm.eps_g, "retraction": args.retraction,
                    "hartree": args.hartree,

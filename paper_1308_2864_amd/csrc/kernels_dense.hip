@@ -394,7 +394,8 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
 template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad, bool kGram2>
 __global__ __launch_bounds__(256) void k_combine_batch(BatchPtrs<CombineArgs> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_combine_body<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2>(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+  k_combine_body<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2>(*b.a[s], blockIdx.x - b.off[s],
+                                                             b.off[s + 1] - b.off[s]);
 }
 
 
@@ -407,7 +408,8 @@ template <typename T, int kT, int kMask>
 void launch_gram_m(const T* A, const T* B, int ld, int n, int p, double* part, int nchunks,
                    hipStream_t st) {
   const size_t lds = (size_t)3 * 4 * 64 * sizeof(double);
-  hipLaunchKernelGGL((k_gram<T, kT, kMask>), dim3(nchunks), dim3(256), lds, st, GramArgs<T>{A, B, ld, n, p, part});
+  hipLaunchKernelGGL((k_gram<T, kT, kMask>), dim3(nchunks), dim3(256), lds, st,
+                     GramArgs<T>{A, B, ld, n, p, part});
 }
 
 // Up to 32 columns all requested products run in one pass; wider blocks run one product
@@ -518,7 +520,8 @@ void launch_gram(const void* A, const void* B, bool f32, int ld, int n, int p, i
 void launch_gram_reduce(const double* partials, int nchunks, int pp, int mask, double* out,
                         double* W, hipStream_t st) {
   const int total = 3 * pp * pp;
-  hipLaunchKernelGGL(k_gram_reduce, dim3((total + 15) / 16), dim3(256), 0, st, GramReduceArgs{partials, nchunks, pp, mask, out, W});
+  hipLaunchKernelGGL(k_gram_reduce, dim3((total + 15) / 16), dim3(256), 0, st,
+                     GramReduceArgs{partials, nchunks, pp, mask, out, W});
 }
 
 int combine_blocks(int n) {

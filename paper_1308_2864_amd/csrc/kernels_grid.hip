@@ -295,7 +295,8 @@ int scalar_blocks(int n) { return stream_blocks((size_t)n); }
 
 void launch_xc(const double* rho, const double* vh, const double* vext, double* veff, Grid g,
                int use_h, int use_x, const CgState* cg, Partials pt, hipStream_t st) {
-  hipLaunchKernelGGL(k_xc, dim3(scalar_blocks(g.n)), dim3(kBlock), 0, st, XcArgs{rho, vh, vext, veff, g, use_h, use_x, cg, pt});
+  hipLaunchKernelGGL(k_xc, dim3(scalar_blocks(g.n)), dim3(kBlock), 0, st,
+                     XcArgs{rho, vh, vext, veff, g, use_h, use_x, cg, pt});
 }
 
 template <typename T>
@@ -303,10 +304,12 @@ void launch_hx(const T* X, int ldx, T* Y, int ldy, const double* veff, const dou
                Grid g, int p, double scale, Partials* pt, hipStream_t st) {
   const int nb = hx_blocks(g.n, p);
   if (pt) {
-    hipLaunchKernelGGL((k_hx<T, true>), dim3(nb), dim3(kBlock), 0, st, HxArgs<T>{X, ldx, Y, ldy, veff, vext, g, p, scale, *pt});
+    hipLaunchKernelGGL((k_hx<T, true>), dim3(nb), dim3(kBlock), 0, st,
+                       HxArgs<T>{X, ldx, Y, ldy, veff, vext, g, p, scale, *pt});
   } else {
     Partials none{nullptr, 0};
-    hipLaunchKernelGGL((k_hx<T, false>), dim3(nb), dim3(kBlock), 0, st, HxArgs<T>{X, ldx, Y, ldy, veff, vext, g, p, scale, none});
+    hipLaunchKernelGGL((k_hx<T, false>), dim3(nb), dim3(kBlock), 0, st,
+                       HxArgs<T>{X, ldx, Y, ldy, veff, vext, g, p, scale, none});
   }
 }
 template void launch_hx<double>(const double*, int, double*, int, const double*,

@@ -592,7 +592,8 @@ void launch_hartree_init(const double* rho, const double* x0, double* x, double*
                          hipStream_t st) {
   const int nb = cg_nblocks(g.n);
   hipLaunchKernelGGL(k_init, dim3(nb), dim3(kBlock), 0, st, InitArgs{rho, x0, x, r, p0, g, part});
-  hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kBlock), 0, st, FinInitArgs{part, nb, cs, tol, maxit});
+  hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kBlock), 0, st,
+                     FinInitArgs{part, nb, cs, tol, maxit});
 }
 
 namespace {
@@ -662,7 +663,8 @@ void launch_hartree_iter(double* x, double* r, const double* z, double* pa, doub
                          double* q, CgState* cs, Grid g, double* part, int pcg,
                          hipStream_t st) {
   const int nb = cg_nblocks(g.n);
-  hipLaunchKernelGGL(k_dir, dim3(nb), dim3(kBlock), 0, st, DirArgs{pcg ? z : r, pa, pb, q, cs, g, part});
+  hipLaunchKernelGGL(k_dir, dim3(nb), dim3(kBlock), 0, st,
+                     DirArgs{pcg ? z : r, pa, pb, q, cs, g, part});
   hipLaunchKernelGGL(k_fin_dir, dim3(1), dim3(kBlock), 0, st, FinDirArgs{part, nb, cs, pcg});
   hipLaunchKernelGGL(k_upd, dim3(nb), dim3(kBlock), 0, st, UpdArgs{x, r, pb, q, cs, g, part});
   hipLaunchKernelGGL(k_fin_upd, dim3(1), dim3(kBlock), 0, st, FinUpdArgs{part, nb, cs, pcg});

@@ -695,15 +695,18 @@ void launch_grad_weights(const double* gram, int pp, double* W, hipStream_t st) 
 void launch_qr_factor(const double* xx, const double* gxd, int p, int pp, const double* tau,
                       double* A, double* B, double* work, int* status, hipStream_t st) {
   if (p <= 16) {
-    hipLaunchKernelGGL(k_qr_factor_2d<16>, dim3(1), dim3(256), 0, st, QrFactor2dArgs{xx, gxd, p, pp, tau, A, B, status});
+    hipLaunchKernelGGL(k_qr_factor_2d<16>, dim3(1), dim3(256), 0, st,
+                       QrFactor2dArgs{xx, gxd, p, pp, tau, A, B, status});
     return;
   }
   if (p <= 32) {
-    hipLaunchKernelGGL(k_qr_factor_2d<32>, dim3(1), dim3(1024), 0, st, QrFactor2dArgs{xx, gxd, p, pp, tau, A, B, status});
+    hipLaunchKernelGGL(k_qr_factor_2d<32>, dim3(1), dim3(1024), 0, st,
+                       QrFactor2dArgs{xx, gxd, p, pp, tau, A, B, status});
     return;
   }
   if (p <= 64) {
-    hipLaunchKernelGGL(k_qr_factor_2d<64>, dim3(1), dim3(1024), 0, st, QrFactor2dArgs{xx, gxd, p, pp, tau, A, B, status});
+    hipLaunchKernelGGL(k_qr_factor_2d<64>, dim3(1), dim3(1024), 0, st,
+                       QrFactor2dArgs{xx, gxd, p, pp, tau, A, B, status});
     return;
   }
   const size_t bytes = (size_t)2 * p * p * sizeof(double);
@@ -727,7 +730,9 @@ void launch_finish_eval(const double* part, int stride, const int* nblk, double*
                         const LsParams* prm, hipStream_t st) {
   ScalarCounts nb{};
   for (int i = 0; i < SL_COUNT; ++i) nb.v[i] = nblk[i];
-  hipLaunchKernelGGL(k_finish_eval, dim3(1), dim3(kFinishThreads), 0, st, FinishEvalArgs{part, stride, nb, sums, gram_xx, p, pp, f, dV, enuc, cg, out, ls, prm ? *prm : LsParams{}});
+  hipLaunchKernelGGL(k_finish_eval, dim3(1), dim3(kFinishThreads), 0, st,
+                     FinishEvalArgs{part, stride, nb, sums, gram_xx, p, pp, f, dV, enuc, cg, out,
+                         ls, prm ? *prm : LsParams{}});
 }
 
 void launch_set_scalar(double* dst, double v, hipStream_t st) {

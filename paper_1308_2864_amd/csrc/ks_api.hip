@@ -1615,7 +1615,8 @@ int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* 
 
 int ks_minimize_batch(ks_system* const* sys, int count, void* const* X_inout,
                       const ks_opt_params* o, ks_result* r, int* codes) {
-  if (!sys || !X_inout || count < 1 || count > kMaxBatch) return fail(nullptr, KS_E_INVAL, "bad batch");
+  if (!sys || !X_inout || count < 1 || count > kMaxBatch)
+    return fail(nullptr, KS_E_INVAL, "bad batch");
   for (int i = 0; i < count; ++i)
     if (!sys[i] || !X_inout[i]) return fail(nullptr, KS_E_INVAL, "null system or block");
   BatchEngine* e = batch_create(sys[0]->st);
