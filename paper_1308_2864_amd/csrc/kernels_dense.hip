@@ -33,8 +33,6 @@ __device__ inline d4 mfma16(double a, double b, d4 c) {
 }
 
 constexpr int kGramMaxChunks = 512;
-constexpr int kGradMaxBlocks = 512;
-constexpr bool kFuseGram = false;
 
 // Product bits of a Gram launch: A^T A, A^T B, B^T B.  Symmetric products store only the
 // tiles ti <= tj; the reduction mirrors them.
@@ -100,35 +98,49 @@ __device__ inline void k_gram_body(const GramArgs<T>& ka, int ks_bid, int ks_nb)
 #pragma unroll
   for (int t = 0; t < kAcc; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
 
-  for (int grp = g_beg + w; grp < g_end; grp += 4) {
-    const int row = grp * 4 + lr;
-    const bool rok = row < n;
-    double fa[kT], fb[kT];
+  // kU row groups are loaded (branch-free, clamped addresses) before their products, so
+  // each wavefront keeps kU times more bytes in flight; the accumulation order per
+  // wavefront (groups g_beg + w, + 4, + 8, ...) is that of one group at a time.
+  constexpr int kU = 4;
+  for (int grp0 = g_beg + w; grp0 < g_end; grp0 += 4 * kU) {
+    double fa[kU][kT], fb[kU][kT];
 #pragma unroll
-    for (int t = 0; t < kT; ++t) {
-      const int col = t * 16 + lc;
-      const bool ok = rok && col < p;
-      fa[t] = ok ? (double)A[(size_t)row * ld + col] : 0.0;
-      fb[t] = ((kMask & (kPAB | kPBB)) && ok) ? (double)B[(size_t)row * ld + col] : 0.0;
+    for (int u = 0; u < kU; ++u) {
+      const int row = (grp0 + 4 * u) * 4 + lr;
+      const bool rok = grp0 + 4 * u < g_end && row < n;
+      const size_t roff = (size_t)(rok ? row : 0) * ld;
+#pragma unroll
+      for (int t = 0; t < kT; ++t) {
+        const int col = t * 16 + lc;
+        const bool ok = rok && col < p;
+        const size_t idx = ok ? roff + col : 0;
+        fa[u][t] = ok ? (double)A[idx] : 0.0;
+        fb[u][t] = 0.0;
+        if (kMask & (kPAB | kPBB)) fb[u][t] = ok ? (double)B[idx] : 0.0;
+      }
     }
-    int a = 0;
-    if (kMask & kPAA) {
 #pragma unroll
-      for (int ti = 0; ti < kT; ++ti)
+    for (int u = 0; u < kU; ++u) {
+      if (grp0 + 4 * u >= g_end) break;
+      int a = 0;
+      if (kMask & kPAA) {
 #pragma unroll
-        for (int tj = ti; tj < kT; ++tj, ++a) acc[a] = mfma16(fa[ti], fa[tj], acc[a]);
-    }
-    if (kMask & kPAB) {
+        for (int ti = 0; ti < kT; ++ti)
 #pragma unroll
-      for (int ti = 0; ti < kT; ++ti)
+          for (int tj = ti; tj < kT; ++tj, ++a) acc[a] = mfma16(fa[u][ti], fa[u][tj], acc[a]);
+      }
+      if (kMask & kPAB) {
 #pragma unroll
-        for (int tj = 0; tj < kT; ++tj, ++a) acc[a] = mfma16(fa[ti], fb[tj], acc[a]);
-    }
-    if (kMask & kPBB) {
+        for (int ti = 0; ti < kT; ++ti)
 #pragma unroll
-      for (int ti = 0; ti < kT; ++ti)
+          for (int tj = 0; tj < kT; ++tj, ++a) acc[a] = mfma16(fa[u][ti], fb[u][tj], acc[a]);
+      }
+      if (kMask & kPBB) {
 #pragma unroll
-        for (int tj = ti; tj < kT; ++tj, ++a) acc[a] = mfma16(fb[ti], fb[tj], acc[a]);
+        for (int ti = 0; ti < kT; ++ti)
+#pragma unroll
+          for (int tj = ti; tj < kT; ++tj, ++a) acc[a] = mfma16(fb[u][ti], fb[u][tj], acc[a]);
+      }
     }
   }
 #pragma unroll
@@ -169,9 +181,13 @@ __global__ __launch_bounds__(256) void k_gram_batch(BatchPtrs<GramArgs<T>> b) {
 
 
 // out[prod][i][j] = sum over chunks in increasing order, for the products in mask; the
-// other products are zero.  Block = 16 output slots x 16 chunk lanes; chunk lane c sums
-// chunks c, c+16, ... and the 16 lane sums are added in lane order.  Symmetric products
-// read the mirrored upper tile.  With W != nullptr also W = -(product 1)^T.
+// other products are left untouched.  Block = 4 output slots x 16 chunk lanes (one
+// wavefront); chunk lane c sums chunks c, c+16, ... (loaded kRedU at a time) and the 16
+// lane sums are added in lane order.  Symmetric products read the mirrored upper tile.
+// With W != nullptr also W = -(product 1)^T.
+constexpr int kRedSlots = 4;
+constexpr int kRedU = 8;
+
 __device__ inline void k_gram_reduce_body(const GramReduceArgs& ka, int ks_bid, int ks_nb) {
   const double* __restrict__ part = ka.part;
   int nchunks = ka.nchunks;
@@ -179,13 +195,12 @@ __device__ inline void k_gram_reduce_body(const GramReduceArgs& ka, int ks_bid, 
   int mask = ka.mask;
   double* __restrict__ out = ka.out;
   double* __restrict__ W = ka.W;
-  (void)ks_bid;
   (void)ks_nb;
 
-  __shared__ double red[16][17];
-  const int sl = threadIdx.x % 16, cl = threadIdx.x / 16;
+  __shared__ double red[kRedSlots][17];
+  const int sl = threadIdx.x % kRedSlots, cl = threadIdx.x / kRedSlots;
   const int per = pp * pp;
-  const int e = ks_bid * 16 + sl;
+  const int e = ks_bid * kRedSlots + sl;
   double s = 0.0;
   int prod = 0, i = 0, j = 0;
   bool live = false;
@@ -198,12 +213,23 @@ __device__ inline void k_gram_reduce_body(const GramReduceArgs& ka, int ks_bid, 
     if (live) {
       const int src = (prod != 1 && (i / 16) > (j / 16)) ? j * pp + i : ij;
       const double* q = part + (size_t)prod * per + src;
-      for (int c = cl; c < nchunks; c += 16) s += q[(size_t)c * 3 * per];
+      const size_t cs = (size_t)3 * per;
+      for (int c0 = cl; c0 < nchunks; c0 += 16 * kRedU) {
+        double v[kRedU];
+#pragma unroll
+        for (int u = 0; u < kRedU; ++u) {
+          const int c = c0 + 16 * u;
+          const double x = q[(size_t)(c < nchunks ? c : 0) * cs];
+          v[u] = c < nchunks ? x : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kRedU; ++u)
+          if (c0 + 16 * u < nchunks) s += v[u];
+      }
     }
   }
   red[sl][cl] = s;
   __syncthreads();
-  // products outside the mask are left untouched in out
   if (cl == 0 && e < 3 * per && live) {
     double t = 0.0;
     for (int c = 0; c < 16; ++c) t += red[sl][c];
@@ -212,11 +238,11 @@ __device__ inline void k_gram_reduce_body(const GramReduceArgs& ka, int ks_bid, 
   }
 }
 
-__global__ __launch_bounds__(256) void k_gram_reduce(GramReduceArgs ka) {
+__global__ __launch_bounds__(64) void k_gram_reduce(GramReduceArgs ka) {
   k_gram_reduce_body(ka, blockIdx.x, gridDim.x);
 }
 
-__global__ __launch_bounds__(256) void k_gram_reduce_batch(BatchPtrs<GramReduceArgs> b) {
+__global__ __launch_bounds__(64) void k_gram_reduce_batch(BatchPtrs<GramReduceArgs> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
   k_gram_reduce_body(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
 }
@@ -224,17 +250,61 @@ __global__ __launch_bounds__(256) void k_gram_reduce_batch(BatchPtrs<GramReduceA
 
 // ---- combine ------------------------------------------------------------------------
 // out[g][:] = C0[g][:] + X[g][:] A + Y[g][:] B  (A, B: pp x pp, staged in LDS).
-// Each wavefront owns a 16-row tile and all column tiles of it.  Epilogues:
-//   kRho   density of out,
-//   kGrad  out is D = grad E; Frobenius sums ||D||^2 and the BB sums against (Xk, Dk),
-//          and, with kGram2, the Gram tiles X^T D and D^T D: an FP64 MFMA result tile of
-//          a 4-row group (register r) is laid out exactly as an MFMA input fragment, so
-//          D goes from the accumulators straight back into the matrix cores.
-template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad, bool kGram2>
-__device__ inline void k_combine_body(const CombineArgs& a, int ks_bid, int ks_nb) {
-  (void)ks_bid;
-  (void)ks_nb;
+//
+// The product is formed transposed, out^T = A^T X^T, so that the rows of X enter the
+// matrix cores as B fragments (lane l holds X[row l % 16][k]) and the result tile comes
+// back one grid row per lane as well.  The contraction index k and the output column
+// are both free to be permuted (the weights in LDS are permuted to match), which is used
+// to give every operand and the result one common register layout:
+//   lane (q = l / 16, c = l % 16) of a wavefront owning rows g0 .. g0 + 15 holds row
+//   g0 + c, columns 8 j + 2 q + e (j < 2 kT, e < 2): element s = 2 j + e.
+// Each lane therefore reads and writes column pairs (one 16-byte load or store for FP64
+// when p and ld are even), four lanes cover 64 contiguous bytes of a row, and X, C0, Xk
+// and Dk are each read exactly once.  For MFMA step s (contraction indices
+// k(s, q) = 8 (s >> 1) + 2 q + (s & 1)) the B fragment is element s of X; the A fragment
+// of output tile t is Wp[4 s + q][16 t + c] with Wp[4 s + q][16 t + m] = A[k(s, q)][16 t +
+// pi(m)], pi(m) = 8 (m >> 3) + 2 (m & 3) + ((m >> 2) & 1); register r of output tile t is
+// then element 4 t + r.  Each wavefront owns 16-row tiles.  Epilogues:
+//   kRho   density of out (row sums across the four lanes of a row),
+//   kGrad  out is D = grad E; Frobenius sums ||D||^2 and the BB sums against (Xk, Dk).
+template <int kT>
+struct CombineFrag {
+  static constexpr int kE = 4 * kT;  // elements per lane
+  double v[kE];
+};
 
+__device__ inline int comb_col(int s, int q) { return 8 * (s >> 1) + 2 * q + (s & 1); }
+
+// Loads the lane's elements of rows g0 + c (zero outside n x p).  kVec: column pairs as
+// one load (p, ld even, 2-element aligned base).
+template <typename T, int kT, bool kVec>
+__device__ inline void comb_load(const T* __restrict__ base, int ld, int n, int p, int row,
+                                 int q, CombineFrag<kT>& f) {
+  const bool rok = row < n;
+  const size_t roff = (size_t)(rok ? row : 0) * ld;
+#pragma unroll
+  for (int j = 0; j < 2 * kT; ++j) {
+    const int c0 = 8 * j + 2 * q;
+    if constexpr (kVec) {
+      const bool ok = rok && c0 < p;
+      typedef T t2 __attribute__((ext_vector_type(2)));
+      const t2 w = *reinterpret_cast<const t2*>(base + (ok ? roff + c0 : 0));
+      f.v[2 * j] = ok ? (double)w[0] : 0.0;
+      f.v[2 * j + 1] = ok ? (double)w[1] : 0.0;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const bool ok = rok && c0 + e < p;
+        const T w = base[ok ? roff + c0 + e : 0];
+        f.v[2 * j + e] = ok ? (double)w : 0.0;
+      }
+    }
+  }
+}
+
+template <typename T, int kT, bool kVec, bool kHasY, bool kHasC0, bool kRho, bool kGrad>
+__device__ inline void combine_tiles(const CombineArgs& a, const double* lds, int t_beg,
+                                     int t_end, d4& sums) {
   const T* aX = static_cast<const T*>(a.X);
   const T* aY = static_cast<const T*>(a.Y);
   const T* aC0 = static_cast<const T*>(a.C0);
@@ -242,124 +312,122 @@ __device__ inline void k_combine_body(const CombineArgs& a, int ks_bid, int ks_n
   const T* aDk = static_cast<const T*>(a.Dk);
   T* aout = static_cast<T*>(a.out);
   constexpr int kPP = kT * 16;
+  constexpr int kS = 4 * kT;  // MFMA steps per operand (= elements per lane)
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int q = lane / 16, c = lane % 16;
+  const int ld = a.ld, p = a.p, n = a.n;
+
+  for (int tile = t_beg + w; tile < t_end; tile += 4) {
+    const int row = tile * 16 + c;
+    CombineFrag<kT> fx, fy, fc, fxk, fdk;
+    comb_load<T, kT, kVec>(aX, ld, n, p, row, q, fx);
+    if constexpr (kHasY) comb_load<T, kT, kVec>(aY, ld, n, p, row, q, fy);
+    if constexpr (kHasC0) comb_load<T, kT, kVec>(aC0, ld, n, p, row, q, fc);
+    if constexpr (kGrad) {
+      comb_load<T, kT, kVec>(aXk, ld, n, p, row, q, fxk);
+      comb_load<T, kT, kVec>(aDk, ld, n, p, row, q, fdk);
+    }
+    d4 acc[kT];
+#pragma unroll
+    for (int t = 0; t < kT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < kS; ++s) {
+#pragma unroll
+      for (int t = 0; t < kT; ++t)
+        acc[t] = mfma16(lds[(4 * s + q) * kPP + t * 16 + c], fx.v[s], acc[t]);
+    }
+    if constexpr (kHasY) {
+#pragma unroll
+      for (int s = 0; s < kS; ++s) {
+#pragma unroll
+        for (int t = 0; t < kT; ++t)
+          acc[t] = mfma16(lds[kPP * kPP + (4 * s + q) * kPP + t * 16 + c], fy.v[s], acc[t]);
+      }
+    }
+    const bool rok = row < n;
+    const size_t roff = (size_t)(rok ? row : 0) * ld;
+    double sq = 0.0;
+#pragma unroll
+    for (int j = 0; j < 2 * kT; ++j) {
+      double v[2];
+      bool ok[2];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int s = 2 * j + e;
+        ok[e] = rok && comb_col(s, q) < p;
+        double x = acc[s / 4][s % 4];
+        if constexpr (kHasC0) x += fc.v[s];
+        x = ok[e] ? (double)(T)x : 0.0;  // the epilogues see the stored value
+        v[e] = x;
+        if constexpr (kRho) sq += x * x;
+        if constexpr (kGrad) {
+          const double sd = fx.v[s] - fxk.v[s];
+          const double yd = x - fdk.v[s];
+          sums[0] += x * x;
+          sums[1] += sd * sd;
+          sums[2] += sd * yd;
+          sums[3] += yd * yd;
+        }
+      }
+      const int c0 = 8 * j + 2 * q;
+      if constexpr (kVec) {
+        typedef T t2 __attribute__((ext_vector_type(2)));
+        if (ok[0]) {
+          t2 o;
+          o[0] = (T)v[0];
+          o[1] = (T)v[1];
+          *reinterpret_cast<t2*>(aout + roff + c0) = o;
+        }
+      } else {
+        if (ok[0]) aout[roff + c0] = (T)v[0];
+        if (ok[1]) aout[roff + c0 + 1] = (T)v[1];
+      }
+    }
+    if constexpr (kRho) {
+      sq += __shfl_xor(sq, 16, kWave);
+      sq += __shfl_xor(sq, 32, kWave);
+      if (q == 0 && rok) a.rho[row] = a.rho_scale * sq;
+    }
+  }
+}
+
+template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad>
+__device__ inline void k_combine_body(const CombineArgs& a, int ks_bid, int ks_nb) {
+  constexpr int kPP = kT * 16;
   constexpr int kK = kHasY ? 2 * kPP : kPP;  // contraction length
-  constexpr int kG2 = kGram2 ? (kT * kT + kT * (kT + 1) / 2) : 1;
-  extern __shared__ double lds[];            // W = [A; B] : kK x kPP (+ 6 KiB reduction)
+  extern __shared__ double lds[];            // permuted weights Wp = [A; B]: kK x kPP
   __shared__ double sh[kBlock / kWave];
 
-  for (int e = threadIdx.x; e < kPP * kPP; e += blockDim.x) {
-    lds[e] = a.A[e];
-    if (kHasY) lds[kPP * kPP + e] = a.B[e];
+  for (int e = threadIdx.x; e < kK * kPP; e += blockDim.x) {
+    const int r = e / kPP, col = e % kPP;
+    const int rr = r % kPP, s = rr >> 2, qq = rr & 3;
+    const int t = col >> 4, m = col & 15;
+    const int src = comb_col(s, qq) * kPP + 16 * t + 8 * (m >> 3) + 2 * (m & 3) + ((m >> 2) & 1);
+    lds[e] = (kHasY && r >= kPP) ? a.B[src] : a.A[src];
   }
   __syncthreads();
 
-  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-  const int lr = lane / 16, lc = lane % 16;
   const int ntiles = (a.n + 15) / 16;
   const int lb = xcd_remap(ks_bid, ks_nb);
   const int per = (ntiles + ks_nb - 1) / ks_nb;
   const int t_beg = lb * per, t_end = min(ntiles, t_beg + per);
-  const int ld = a.ld, p = a.p;
-  double dd = 0.0, ss = 0.0, sy = 0.0, yy = 0.0;
-  d4 g2[kG2];
-#pragma unroll
-  for (int t = 0; t < kG2; ++t) g2[t] = d4{0.0, 0.0, 0.0, 0.0};
-
-  for (int tile = t_beg + w; tile < t_end; tile += 4) {
-    const int g0 = tile * 16;
-    d4 acc[kT];
-#pragma unroll
-    for (int t = 0; t < kT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-    // A-fragment rows: g0 + lc ; columns k0 + lr
-    const int arow = g0 + lc;
-    const bool arok = arow < a.n;
-    const T* xr = aX + (size_t)arow * ld;
-    const T* yr = kHasY ? aY + (size_t)arow * ld : nullptr;
-#pragma unroll 4
-    for (int k0 = 0; k0 < kK; k0 += 4) {
-      const int k = k0 + lr;
-      double av;
-      if (!kHasY || k < kPP) {
-        av = (arok && k < p) ? (double)xr[k] : 0.0;
-      } else {
-        const int ky = k - kPP;
-        av = (arok && ky < p) ? (double)yr[ky] : 0.0;
-      }
-#pragma unroll
-      for (int t = 0; t < kT; ++t) {
-        const double bv = lds[k * kPP + t * 16 + lc];
-        acc[t] = mfma16(av, bv, acc[t]);
-      }
-    }
-    // epilogue: lane holds rows g0 + lr + 4 r, column t*16 + lc
-    double sq[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int t = 0; t < kT; ++t) {
-      const int col = t * 16 + lc;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = g0 + lr + 4 * r;
-        const bool ok = row < a.n && col < p;
-        double v = 0.0;
-        if (ok) {
-          const size_t off = (size_t)row * ld + col;
-          v = acc[t][r];
-          if (kHasC0) v += (double)aC0[off];
-          const T vs = (T)v;
-          aout[off] = vs;
-          v = (double)vs;  // the epilogues see the stored value
-          if (kRho) sq[r] += v * v;
-          if (kGrad) {
-            const double s = (double)aX[off] - (double)aXk[off];
-            const double y = v - (double)aDk[off];
-            dd += v * v;
-            ss += s * s;
-            sy += s * y;
-            yy += y * y;
-          }
-        }
-        acc[t][r] = v;  // masked D, reused as an MFMA fragment below
-      }
-    }
-    if (kGram2) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = g0 + 4 * r + lr;
-        double fx[kT];
-#pragma unroll
-        for (int t = 0; t < kT; ++t) {
-          const int col = t * 16 + lc;
-          fx[t] = (row < a.n && col < p) ? (double)aX[(size_t)row * ld + col] : 0.0;
-        }
-        int q = 0;
-#pragma unroll
-        for (int ti = 0; ti < kT; ++ti)
-#pragma unroll
-          for (int tj = 0; tj < kT; ++tj, ++q) g2[q] = mfma16(fx[ti], acc[tj][r], g2[q]);
-#pragma unroll
-        for (int ti = 0; ti < kT; ++ti)
-#pragma unroll
-          for (int tj = ti; tj < kT; ++tj, ++q) g2[q] = mfma16(acc[ti][r], acc[tj][r], g2[q]);
-      }
-    }
-    if (kRho) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        double v = sq[r];
-        v += __shfl_xor(v, 8, 16);
-        v += __shfl_xor(v, 4, 16);
-        v += __shfl_xor(v, 2, 16);
-        v += __shfl_xor(v, 1, 16);
-        const int row = g0 + lr + 4 * r;
-        if (lc == 0 && row < a.n) a.rho[row] = a.rho_scale * v;
-      }
-    }
-  }
+  // column pairs can be moved as one load or store when every block is pair-aligned
+  constexpr uintptr_t kAl = 2 * sizeof(T) - 1;
+  const bool vec = ((a.ld | a.p) & 1) == 0 &&
+                   ((reinterpret_cast<uintptr_t>(a.X) | reinterpret_cast<uintptr_t>(a.Y) |
+                     reinterpret_cast<uintptr_t>(a.C0) | reinterpret_cast<uintptr_t>(a.out) |
+                     reinterpret_cast<uintptr_t>(a.Xk) | reinterpret_cast<uintptr_t>(a.Dk)) &
+                    kAl) == 0;
+  d4 sums = {0.0, 0.0, 0.0, 0.0};
+  if (vec)
+    combine_tiles<T, kT, true, kHasY, kHasC0, kRho, kGrad>(a, lds, t_beg, t_end, sums);
+  else
+    combine_tiles<T, kT, false, kHasY, kHasC0, kRho, kGrad>(a, lds, t_beg, t_end, sums);
   if (kGrad) {
-    dd = block_sum(dd, sh);
-    ss = block_sum(ss, sh);
-    sy = block_sum(sy, sh);
-    yy = block_sum(yy, sh);
+    const double dd = block_sum(sums[0], sh);
+    const double ss = block_sum(sums[1], sh);
+    const double sy = block_sum(sums[2], sh);
+    const double yy = block_sum(sums[3], sh);
     if (threadIdx.x == 0) {
       const int st = a.pt.stride;
       a.pt.buf[(size_t)SL_DD * st + lb] = dd;
@@ -368,36 +436,19 @@ __device__ inline void k_combine_body(const CombineArgs& a, int ks_bid, int ks_n
       a.pt.buf[(size_t)SL_YY * st + lb] = yy;
     }
   }
-  if (kGram2) {
-    double* red = lds + kK * kPP;
-#pragma unroll
-    for (int t = 0; t < kG2; ++t) wave_reduce_tile(g2[t], red, w, lane);
-    if (w == 0) {
-      int q = 0;
-#pragma unroll
-      for (int ti = 0; ti < kT; ++ti)
-#pragma unroll
-        for (int tj = 0; tj < kT; ++tj) put_tile<kPP>(a.gram_part, lb, 1, ti, tj, g2[q++], lr, lc);
-#pragma unroll
-      for (int ti = 0; ti < kT; ++ti)
-#pragma unroll
-        for (int tj = ti; tj < kT; ++tj) put_tile<kPP>(a.gram_part, lb, 2, ti, tj, g2[q++], lr, lc);
-    }
-  }
 }
 
-template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad, bool kGram2>
+template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad>
 __global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
-  k_combine_body<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2>(a, blockIdx.x, gridDim.x);
+  k_combine_body<T, kT, kHasY, kHasC0, kRho, kGrad>(a, blockIdx.x, gridDim.x);
 }
 
-template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad, bool kGram2>
+template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad>
 __global__ __launch_bounds__(256) void k_combine_batch(BatchPtrs<CombineArgs> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_combine_body<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2>(*b.a[s], blockIdx.x - b.off[s],
-                                                             b.off[s + 1] - b.off[s]);
+  k_combine_body<T, kT, kHasY, kHasC0, kRho, kGrad>(*b.a[s], blockIdx.x - b.off[s],
+                                                    b.off[s + 1] - b.off[s]);
 }
-
 
 void set_lds_attr(const void* k, size_t bytes) {
   if (bytes > 32768)
@@ -428,42 +479,31 @@ void launch_gram_t(const T* A, const T* B, int ld, int n, int p, int mask, doubl
   if (mask & kPBB) launch_gram_m<T, kT, 4>(A, B, ld, n, p, part, nchunks, st);
 }
 
-template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad, bool kGram2>
+template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad>
 void launch_combine_t(const CombineArgs& a, hipStream_t st) {
   constexpr int kPP = kT * 16;
-  const size_t lds = (size_t)(kHasY ? 2 : 1) * kPP * kPP * sizeof(double) +
-                     (kGram2 ? (size_t)3 * 4 * 64 * sizeof(double) : 0);
+  const size_t lds = (size_t)(kHasY ? 2 : 1) * kPP * kPP * sizeof(double);
   // function-local static initialisation runs once even when several host threads launch
   static const bool attr = (set_lds_attr(reinterpret_cast<const void*>(
-                                k_combine<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2>),
+                                k_combine<T, kT, kHasY, kHasC0, kRho, kGrad>),
                                 lds),
                             true);
   (void)attr;
-  const int nb = kGram2 ? combine_blocks_gram(a.n) : combine_blocks(a.n);
-  hipLaunchKernelGGL((k_combine<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2>), dim3(nb), dim3(256),
-                     lds, st, a);
+  hipLaunchKernelGGL((k_combine<T, kT, kHasY, kHasC0, kRho, kGrad>), dim3(combine_blocks(a.n)),
+                     dim3(256), lds, st, a);
 }
 
 template <typename T, int kT>
 void launch_combine_tt(const CombineArgs& a, hipStream_t st) {
   const bool y = a.Y != nullptr, c0 = a.C0 != nullptr, rho = a.rho != nullptr,
-             gr = a.Xk != nullptr, g2 = a.gram_part != nullptr;
+             gr = a.Xk != nullptr;
   // the combinations the library uses
-  if (y && !c0 && rho && !gr)
-    return launch_combine_t<T, kT, true, false, true, false, false>(a, st);
-  if (y && !c0 && !rho && !gr)
-    return launch_combine_t<T, kT, true, false, false, false, false>(a, st);
-  if constexpr (kT <= 2) {
-    if (!y && c0 && !rho && gr && g2)
-      return launch_combine_t<T, kT, false, true, false, true, true>(a, st);
-  }
-  if (!y && c0 && !rho && gr)
-    return launch_combine_t<T, kT, false, true, false, true, false>(a, st);
-  if (!y && c0 && !rho && !gr)
-    return launch_combine_t<T, kT, false, true, false, false, false>(a, st);
-  if (!y && !c0 && rho && !gr)
-    return launch_combine_t<T, kT, false, false, true, false, false>(a, st);
-  launch_combine_t<T, kT, false, false, false, false, false>(a, st);
+  if (y && !c0 && rho && !gr) return launch_combine_t<T, kT, true, false, true, false>(a, st);
+  if (y && !c0 && !rho && !gr) return launch_combine_t<T, kT, true, false, false, false>(a, st);
+  if (!y && c0 && !rho && gr) return launch_combine_t<T, kT, false, true, false, true>(a, st);
+  if (!y && c0 && !rho && !gr) return launch_combine_t<T, kT, false, true, false, false>(a, st);
+  if (!y && !c0 && rho && !gr) return launch_combine_t<T, kT, false, false, true, false>(a, st);
+  launch_combine_t<T, kT, false, false, false, false>(a, st);
 }
 
 template <typename T>
@@ -500,12 +540,7 @@ int gram_chunks(int n, int pp) {
   return c < 1 ? 1 : c;
 }
 
-size_t gram_part_doubles(int n, int pp) {
-  const int c = std::max(gram_chunks(n, pp), combine_blocks_gram(n));
-  return (size_t)c * 3 * pp * pp;
-}
-
-bool combine_fuses_gram(int p) { return round_up(p, 16) <= 32 && kFuseGram; }
+size_t gram_part_doubles(int n, int pp) { return (size_t)gram_chunks(n, pp) * 3 * pp * pp; }
 
 void launch_gram(const void* A, const void* B, bool f32, int ld, int n, int p, int mask,
                  double* partials, int nchunks, hipStream_t st) {
@@ -519,8 +554,7 @@ void launch_gram(const void* A, const void* B, bool f32, int ld, int n, int p, i
 
 void launch_gram_reduce(const double* partials, int nchunks, int pp, int mask, double* out,
                         double* W, hipStream_t st) {
-  const int total = 3 * pp * pp;
-  hipLaunchKernelGGL(k_gram_reduce, dim3((total + 15) / 16), dim3(256), 0, st,
+  hipLaunchKernelGGL(k_gram_reduce, dim3(gram_reduce_blocks(pp)), dim3(16 * kRedSlots), 0, st,
                      GramReduceArgs{partials, nchunks, pp, mask, out, W});
 }
 
@@ -531,10 +565,6 @@ int combine_blocks(int n) {
   return b < 1 ? 1 : b;
 }
 
-int combine_blocks_gram(int n) {
-  int b = combine_blocks(n);
-  return b > kGradMaxBlocks ? kGradMaxBlocks : b;
-}
 
 void launch_combine(const CombineArgs& a, hipStream_t st) {
   if (a.f32) launch_combine_p<float>(a, st);
@@ -561,17 +591,17 @@ template void launch_gram_batch<double>(const BatchPtrs<GramArgs<double>>&, int,
 template void launch_gram_batch<float>(const BatchPtrs<GramArgs<float>>&, int, int, int,
                                        hipStream_t);
 
-int gram_reduce_blocks(int pp) { return (3 * pp * pp + 15) / 16; }
+int gram_reduce_blocks(int pp) { return (3 * pp * pp + kRedSlots - 1) / kRedSlots; }
 
 void launch_gram_reduce_batch(const BatchPtrs<GramReduceArgs>& b, int blocks, hipStream_t st) {
-  hipLaunchKernelGGL(k_gram_reduce_batch, dim3(blocks), dim3(256), 0, st, b);
+  hipLaunchKernelGGL(k_gram_reduce_batch, dim3(blocks), dim3(16 * kRedSlots), 0, st, b);
 }
 
 template <typename T, int kT>
 void combine_batch_retract_t(const BatchPtrs<CombineArgs>& b, int blocks, hipStream_t st) {
   constexpr int kPP = kT * 16;
   const size_t lds = (size_t)2 * kPP * kPP * sizeof(double);
-  hipLaunchKernelGGL((k_combine_batch<T, kT, true, false, true, false, false>), dim3(blocks),
+  hipLaunchKernelGGL((k_combine_batch<T, kT, true, false, true, false>), dim3(blocks),
                      dim3(256), lds, st, b);
 }
 
@@ -579,7 +609,7 @@ template <typename T, int kT>
 void combine_batch_grad_t(const BatchPtrs<CombineArgs>& b, int blocks, hipStream_t st) {
   constexpr int kPP = kT * 16;
   const size_t lds = (size_t)kPP * kPP * sizeof(double);
-  hipLaunchKernelGGL((k_combine_batch<T, kT, false, true, false, true, false>), dim3(blocks),
+  hipLaunchKernelGGL((k_combine_batch<T, kT, false, true, false, true>), dim3(blocks),
                      dim3(256), lds, st, b);
 }
 

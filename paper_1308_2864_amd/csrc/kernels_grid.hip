@@ -164,75 +164,122 @@ __global__ void k_xc_batch(BatchPtrs<XcArgs> b) {
 // Y = scale * ((1/2) L X + Diag(veff) X), L = -Laplacian_h (7 points, zero Dirichlet).
 // With pt: per-block partials of sum X.(LX) and sum vext X^2 (kinetic/external energy).
 
-// A thread owns one (i, j, orbital) column and marches along z over kHxChunk planes: the
-// z neighbours of plane k are the centres of planes k-1 and k+1, which it already holds,
-// so each output costs five loads (centre and four in-plane neighbours) and the block is
-// streamed plane by plane.  Consecutive threads take consecutive orbitals of one point.
+// A thread owns kW orbitals (a column pair when p, ld are even and the blocks are
+// pair-aligned) of one grid column (i, j) over kHxChunk consecutive planes.  The centre
+// values of those planes and of the two planes around them are loaded first, so the z
+// neighbours come from registers and each output needs only its four in-plane
+// neighbours; all loads are branch-free (clamped addresses, zero outside the grid).
+// Consecutive threads take consecutive orbitals of one point.
 constexpr int kHxChunk = 8;
 
-template <typename T, bool kEnergy>
-__device__ inline void k_hx_body(const HxArgs<T>& ka, int ks_bid, int ks_nb) {
+template <typename T, int kW>
+struct HxVec {
+  typedef T type __attribute__((ext_vector_type(kW)));
+};
+template <typename T>
+struct HxVec<T, 1> {
+  typedef T type;
+};
+
+template <typename T, int kW>
+__device__ inline void hx_load(const T* ptr, bool ok, double (&v)[kW]) {
+  const typename HxVec<T, kW>::type w = *reinterpret_cast<const typename HxVec<T, kW>::type*>(ptr);
+  if constexpr (kW == 1) {
+    v[0] = ok ? (double)w : 0.0;
+  } else {
+#pragma unroll
+    for (int e = 0; e < kW; ++e) v[e] = ok ? (double)w[e] : 0.0;
+  }
+}
+
+template <typename T, bool kEnergy, int kW>
+__device__ inline void hx_items(const HxArgs<T>& ka, int lb, int nblk, double& kin,
+                                double& ext) {
   const T* __restrict__ X = ka.X;
-  int ldx = ka.ldx;
+  const int ldx = ka.ldx, ldy = ka.ldy;
   T* __restrict__ Y = ka.Y;
-  int ldy = ka.ldy;
   const double* __restrict__ veff = ka.veff;
   const double* __restrict__ vext = ka.vext;
-  Grid gr = ka.gr;
-  int p = ka.p;
-  double scale = ka.scale;
-  Partials pt = ka.pt;
-  (void)ks_bid;
-  (void)ks_nb;
-
-  __shared__ double sh[kBlock / kWave];
-  const int lb = xcd_remap(ks_bid, ks_nb);
+  const Grid gr = ka.gr;
   const int nx = gr.nx, ny = gr.ny, nz = gr.nz;
+  const int pw = ka.p / kW;
   const int nzc = (nz + kHxChunk - 1) / kHxChunk;
-  const size_t work = (size_t)nx * ny * p * nzc;
+  const size_t work = (size_t)nx * ny * pw * nzc;
   const ptrdiff_t sy = (ptrdiff_t)nx * ldx, sz = (ptrdiff_t)nx * ny * ldx;
-  const double ih2 = gr.inv_h2;
-  double kin = 0.0, ext = 0.0;
+  const double ih2 = gr.inv_h2, scale = ka.scale;
   for (size_t t = (size_t)lb * blockDim.x + threadIdx.x; t < work;
-       t += (size_t)ks_nb * blockDim.x) {
-    const int c = (int)(t % (unsigned)p);
-    size_t r = t / (unsigned)p;
+       t += (size_t)nblk * blockDim.x) {
+    const int c = (int)(t % (unsigned)pw) * kW;
+    size_t r = t / (unsigned)pw;
     const int i = (int)(r % nx);
     r /= nx;
     const int j = (int)(r % ny);
-    const int kc = (int)(r / ny);
-    const int k0 = kc * kHxChunk;
+    const int k0 = (int)(r / ny) * kHxChunk;
     const int k1 = min(k0 + kHxChunk, nz);
     const T* col = X + (ptrdiff_t)(i + (size_t)nx * j) * ldx + c;
-    double below = k0 > 0 ? (double)col[(k0 - 1) * sz] : 0.0;
-    double cur = (double)col[k0 * sz];
-#pragma unroll 2
-    for (int k = k0; k < k1; ++k) {
+    double zc[kHxChunk + 2][kW];
+#pragma unroll
+    for (int u = 0; u < kHxChunk + 2; ++u) {
+      const int k = k0 - 1 + u;
+      const bool ok = k >= 0 && k < nz;
+      hx_load<T, kW>(col + (ok ? k * sz : 0), ok, zc[u]);
+    }
+    const bool hxm = i > 0, hxp = i < nx - 1, hym = j > 0, hyp = j < ny - 1;
+#pragma unroll
+    for (int u = 0; u < kHxChunk; ++u) {
+      const int k = k0 + u;
+      if (k >= k1) break;
       const T* xp = col + k * sz;
-      const double above = k + 1 < nz ? (double)xp[sz] : 0.0;
-      double nb = 0.0;
-      if (i > 0) nb += (double)xp[-ldx];
-      if (i < nx - 1) nb += (double)xp[ldx];
-      if (j > 0) nb += (double)xp[-sy];
-      if (j < ny - 1) nb += (double)xp[sy];
-      nb += below;
-      nb += above;
-      const double lx = (6.0 * cur - nb) * ih2;
+      double a[kW], b[kW], cc[kW], d[kW];
+      hx_load<T, kW>(xp - (hxm ? ldx : 0), hxm, a);
+      hx_load<T, kW>(xp + (hxp ? ldx : 0), hxp, b);
+      hx_load<T, kW>(xp - (hym ? sy : 0), hym, cc);
+      hx_load<T, kW>(xp + (hyp ? sy : 0), hyp, d);
       const size_t g = i + (size_t)nx * (j + (size_t)ny * k);
-      Y[g * ldy + c] = (T)(scale * (0.5 * lx + veff[g] * cur));
-      if (kEnergy) {
-        kin += cur * lx;
-        ext += vext[g] * cur * cur;
+      const double ve = veff[g];
+      double o[kW];
+#pragma unroll
+      for (int e = 0; e < kW; ++e) {
+        const double cur = zc[u + 1][e];
+        const double nb = a[e] + b[e] + cc[e] + d[e] + zc[u][e] + zc[u + 2][e];
+        const double lx = (6.0 * cur - nb) * ih2;
+        o[e] = scale * (0.5 * lx + ve * cur);
+        if (kEnergy) {
+          kin += cur * lx;
+          ext += vext[g] * cur * cur;
+        }
       }
-      below = cur;
-      cur = above;
+      T* yp = Y + g * ldy + c;
+      if constexpr (kW == 1) {
+        *yp = (T)o[0];
+      } else {
+        typename HxVec<T, kW>::type w;
+#pragma unroll
+        for (int e = 0; e < kW; ++e) w[e] = (T)o[e];
+        *reinterpret_cast<typename HxVec<T, kW>::type*>(yp) = w;
+      }
     }
   }
+}
+
+template <typename T, bool kEnergy>
+__device__ inline void k_hx_body(const HxArgs<T>& ka, int ks_bid, int ks_nb) {
+  __shared__ double sh[kBlock / kWave];
+  const int lb = xcd_remap(ks_bid, ks_nb);
+  double kin = 0.0, ext = 0.0;
+  constexpr uintptr_t kAl = 2 * sizeof(T) - 1;
+  const bool vec = ((ka.p | ka.ldx | ka.ldy) & 1) == 0 &&
+                   ((reinterpret_cast<uintptr_t>(ka.X) | reinterpret_cast<uintptr_t>(ka.Y)) &
+                    kAl) == 0;
+  if (vec)
+    hx_items<T, kEnergy, 2>(ka, lb, ks_nb, kin, ext);
+  else
+    hx_items<T, kEnergy, 1>(ka, lb, ks_nb, kin, ext);
   if (kEnergy) {
     kin = block_sum(kin, sh);
     ext = block_sum(ext, sh);
-    write_partial(pt, SL_KIN, lb, kin);
-    write_partial(pt, SL_EXT, lb, ext);
+    write_partial(ka.pt, SL_KIN, lb, kin);
+    write_partial(ka.pt, SL_EXT, lb, ext);
   }
 }
 
@@ -317,7 +364,7 @@ template void launch_hx<double>(const double*, int, double*, int, const double*,
 template void launch_hx<float>(const float*, int, float*, int, const double*, const double*,
                                Grid, int, double, Partials*, hipStream_t);
 
-int hx_blocks(int n, int p) { return stream_blocks((size_t)n * p / kHxChunk + 1); }
+int hx_blocks(int n, int p) { return stream_blocks((size_t)n * p / (2 * kHxChunk) + 1); }
 
 
 void launch_xc_batch(const BatchPtrs<XcArgs>& b, int blocks, hipStream_t st) {

@@ -513,8 +513,7 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
   tbeg(s, KS_PH_SMALL);
   launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, mask1, s->gxg[idx], s->W, s->st);
   tend(s, KS_PH_SMALL);
-  // D = G - X (G^T X) with ||D||^2, the BB sums and (QR) the Gram blocks X^T D, D^T D
-  const bool fused = want_gxd && combine_fuses_gram(s->p);
+  // D = G - X (G^T X) with ||D||^2 and the BB sums; then (QR) the Gram blocks X^T D, D^T D
   CombineArgs ca{};
   ca.X = Xs;
   ca.A = s->W;
@@ -523,7 +522,6 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
   ca.Xk = bb_ref >= 0 ? s->X[bb_ref] : Xs;
   ca.Dk = bb_ref >= 0 ? s->D[bb_ref] : s->D[idx];
   ca.pt = pt;
-  ca.gram_part = fused ? s->gram_part : nullptr;
   ca.f32 = s->f32;
   ca.ld = s->p;
   ca.n = s->n;
@@ -532,20 +530,19 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
   launch_combine(ca, s->st);
   tend(s, KS_PH_GRADIENT);
   const int mask2 = kGramAB | kGramBB;
-  if (want_gxd && !fused) {
+  if (want_gxd) {
     tbeg(s, KS_PH_GRAM);
     gram(s, Xs, s->D[idx], mask2);
     tend(s, KS_PH_GRAM);
   }
   tbeg(s, KS_PH_SMALL);
   if (want_gxd)
-    launch_gram_reduce(s->gram_part, fused ? combine_blocks_gram(s->n) : s->gram_nchunks, s->pp,
-                       mask2, s->gxd[idx], nullptr, s->st);
+    launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, mask2, s->gxd[idx], nullptr,
+                       s->st);
   int nblk[kMaxScalarSlots] = {};
   nblk[SL_KIN] = nblk[SL_EXT] = hx_blocks(s->n, s->p);
   nblk[SL_EH] = nblk[SL_EX] = scalar_blocks(s->n);
-  nblk[SL_DD] = nblk[SL_SS] = nblk[SL_SY] = nblk[SL_YY] =
-      fused ? combine_blocks_gram(s->n) : combine_blocks(s->n);
+  nblk[SL_DD] = nblk[SL_SS] = nblk[SL_SY] = nblk[SL_YY] = combine_blocks(s->n);
   launch_finish_eval(s->spart, kPartStride, nblk, s->sums[idx], s->gxg[idx], s->p, s->pp, s->f,
                      s->grid.dV, s->enuc, s->use_h ? s->cg : nullptr, s->ev[idx],
                      judge ? s->ls : nullptr, judge, s->st);

@@ -390,7 +390,6 @@ struct GramReduceArgs {
 constexpr int kGramAA = 1, kGramAB = 2, kGramBB = 4;  // product bits of a Gram launch
 int gram_chunks(int n, int pp);
 size_t gram_part_doubles(int n, int pp);
-bool combine_fuses_gram(int p);
 // A, B: n x ld blocks of float (f32) or double; products accumulate in FP64
 void launch_gram(const void* A, const void* B, bool f32, int ld, int n, int p, int mask,
                  double* partials, int nchunks, hipStream_t st);
@@ -407,7 +406,6 @@ struct CombineArgs {
   // optional BB/gradient epilogue: out is D_t; uses Xt (= X), Xk, Dk
   const void* Xk; const void* Dk;
   Partials pt;                          // slots SL_DD.. SL_YY (by value)
-  double* gram_part;                    // optional partial Gram tiles X^T D, D^T D
   int ld, n, p;
   bool f32;
 };
@@ -427,7 +425,6 @@ template <typename T>
 void launch_combine_grad_batch(const BatchPtrs<CombineArgs>& b, int pp, int blocks,
                                hipStream_t st);
 int combine_blocks(int n);
-int combine_blocks_gram(int n);
 
 // small dense kernels (kernels_small.hip)
 // Argument records of the per-system small kernels (see BatchPtrs).
