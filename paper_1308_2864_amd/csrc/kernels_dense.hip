@@ -33,6 +33,9 @@ __device__ inline d4 mfma16(double a, double b, d4 c) {
 }
 
 constexpr int kGramMaxChunks = 512;
+// One resident wave of blocks on 256 CUs at three blocks per CU keeps every wavefront
+// streaming several 16-row tiles (measured against 256 - 4096 blocks on a 64^3 grid).
+constexpr int kCombineMaxBlocks = 512;
 
 // Product bits of a Gram launch: A^T A, A^T B, B^T B.  Symmetric products store only the
 // tiles ti <= tj; the reduction mirrors them.
@@ -98,12 +101,15 @@ __device__ inline void k_gram_body(const GramArgs<T>& ka, int ks_bid, int ks_nb)
 #pragma unroll
   for (int t = 0; t < kAcc; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
 
-  // kU row groups are loaded (branch-free, clamped addresses) before their products, so
-  // each wavefront keeps kU times more bytes in flight; the accumulation order per
-  // wavefront (groups g_beg + w, + 4, + 8, ...) is that of one group at a time.
-  constexpr int kU = 4;
-  for (int grp0 = g_beg + w; grp0 < g_end; grp0 += 4 * kU) {
-    double fa[kU][kT], fb[kU][kT];
+  // Software pipeline over batches of kU row groups: the loads of the next batch
+  // (branch-free, clamped addresses) are issued before the products of the current one,
+  // so memory and matrix cores overlap.  The accumulation order per wavefront (groups
+  // g_beg + w, + 4, + 8, ...) is that of one group at a time.
+  constexpr int kU = kT <= 2 ? 4 : 2;
+  struct Batch {
+    double a[kU][kT], b[kU][kT];
+  };
+  auto load = [&](Batch& f, int grp0) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int row = (grp0 + 4 * u) * 4 + lr;
@@ -114,11 +120,13 @@ __device__ inline void k_gram_body(const GramArgs<T>& ka, int ks_bid, int ks_nb)
         const int col = t * 16 + lc;
         const bool ok = rok && col < p;
         const size_t idx = ok ? roff + col : 0;
-        fa[u][t] = ok ? (double)A[idx] : 0.0;
-        fb[u][t] = 0.0;
-        if (kMask & (kPAB | kPBB)) fb[u][t] = ok ? (double)B[idx] : 0.0;
+        f.a[u][t] = ok ? (double)A[idx] : 0.0;
+        f.b[u][t] = 0.0;
+        if (kMask & (kPAB | kPBB)) f.b[u][t] = ok ? (double)B[idx] : 0.0;
       }
     }
+  };
+  auto products = [&](const Batch& f, int grp0) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       if (grp0 + 4 * u >= g_end) break;
@@ -127,21 +135,34 @@ __device__ inline void k_gram_body(const GramArgs<T>& ka, int ks_bid, int ks_nb)
 #pragma unroll
         for (int ti = 0; ti < kT; ++ti)
 #pragma unroll
-          for (int tj = ti; tj < kT; ++tj, ++a) acc[a] = mfma16(fa[u][ti], fa[u][tj], acc[a]);
+          for (int tj = ti; tj < kT; ++tj, ++a) acc[a] = mfma16(f.a[u][ti], f.a[u][tj], acc[a]);
       }
       if (kMask & kPAB) {
 #pragma unroll
         for (int ti = 0; ti < kT; ++ti)
 #pragma unroll
-          for (int tj = 0; tj < kT; ++tj, ++a) acc[a] = mfma16(fa[u][ti], fb[u][tj], acc[a]);
+          for (int tj = 0; tj < kT; ++tj, ++a) acc[a] = mfma16(f.a[u][ti], f.b[u][tj], acc[a]);
       }
       if (kMask & kPBB) {
 #pragma unroll
         for (int ti = 0; ti < kT; ++ti)
 #pragma unroll
-          for (int tj = ti; tj < kT; ++tj, ++a) acc[a] = mfma16(fb[u][ti], fb[u][tj], acc[a]);
+          for (int tj = ti; tj < kT; ++tj, ++a) acc[a] = mfma16(f.b[u][ti], f.b[u][tj], acc[a]);
       }
     }
+  };
+  constexpr int kStep = 4 * kU;  // groups per batch of one wavefront
+  int grp0 = g_beg + w;
+  Batch f0, f1;
+  if (grp0 < g_end) load(f0, grp0);
+  while (grp0 < g_end) {
+    if (grp0 + kStep < g_end) load(f1, grp0 + kStep);
+    products(f0, grp0);
+    grp0 += kStep;
+    if (grp0 >= g_end) break;
+    if (grp0 + kStep < g_end) load(f0, grp0 + kStep);
+    products(f1, grp0);
+    grp0 += kStep;
   }
 #pragma unroll
   for (int t = 0; t < kAcc; ++t) wave_reduce_tile(acc[t], lds, w, lane);
@@ -302,9 +323,25 @@ __device__ inline void comb_load(const T* __restrict__ base, int ld, int n, int 
   }
 }
 
+// Permuted weights Wp = [A; B] (kK x kPP) into LDS.
+template <int kT, bool kHasY>
+__device__ inline void comb_stage(const CombineArgs& a, double* lds) {
+  constexpr int kPP = kT * 16;
+  constexpr int kK = kHasY ? 2 * kPP : kPP;
+  for (int e = threadIdx.x; e < kK * kPP; e += blockDim.x) {
+    const int r = e / kPP, col = e % kPP;
+    const int rr = r % kPP, s = rr >> 2, qq = rr & 3;
+    const int t = col >> 4, m = col & 15;
+    const int src = comb_col(s, qq) * kPP + 16 * t + 8 * (m >> 3) + 2 * (m & 3) + ((m >> 2) & 1);
+    lds[e] = (kHasY && r >= kPP) ? a.B[src] : a.A[src];
+  }
+}
+
+// The first tile's loads are issued before the weights are staged, so they overlap the
+// staging and the barrier.
 template <typename T, int kT, bool kVec, bool kHasY, bool kHasC0, bool kRho, bool kGrad>
-__device__ inline void combine_tiles(const CombineArgs& a, const double* lds, int t_beg,
-                                     int t_end, d4& sums) {
+__device__ inline void combine_tiles(const CombineArgs& a, double* lds, int t_beg, int t_end,
+                                     d4& sums) {
   const T* aX = static_cast<const T*>(a.X);
   const T* aY = static_cast<const T*>(a.Y);
   const T* aC0 = static_cast<const T*>(a.C0);
@@ -317,16 +354,22 @@ __device__ inline void combine_tiles(const CombineArgs& a, const double* lds, in
   const int q = lane / 16, c = lane % 16;
   const int ld = a.ld, p = a.p, n = a.n;
 
-  for (int tile = t_beg + w; tile < t_end; tile += 4) {
+  // operands of one tile
+  struct Tile {
+    CombineFrag<kT> x, y, c0, xk, dk;
+  };
+  auto load = [&](Tile& f, int tile) {
     const int row = tile * 16 + c;
-    CombineFrag<kT> fx, fy, fc, fxk, fdk;
-    comb_load<T, kT, kVec>(aX, ld, n, p, row, q, fx);
-    if constexpr (kHasY) comb_load<T, kT, kVec>(aY, ld, n, p, row, q, fy);
-    if constexpr (kHasC0) comb_load<T, kT, kVec>(aC0, ld, n, p, row, q, fc);
+    comb_load<T, kT, kVec>(aX, ld, n, p, row, q, f.x);
+    if constexpr (kHasY) comb_load<T, kT, kVec>(aY, ld, n, p, row, q, f.y);
+    if constexpr (kHasC0) comb_load<T, kT, kVec>(aC0, ld, n, p, row, q, f.c0);
     if constexpr (kGrad) {
-      comb_load<T, kT, kVec>(aXk, ld, n, p, row, q, fxk);
-      comb_load<T, kT, kVec>(aDk, ld, n, p, row, q, fdk);
+      comb_load<T, kT, kVec>(aXk, ld, n, p, row, q, f.xk);
+      comb_load<T, kT, kVec>(aDk, ld, n, p, row, q, f.dk);
     }
+  };
+  auto compute = [&](const Tile& f, int tile) {
+    const int row = tile * 16 + c;
     d4 acc[kT];
 #pragma unroll
     for (int t = 0; t < kT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
@@ -334,14 +377,14 @@ __device__ inline void combine_tiles(const CombineArgs& a, const double* lds, in
     for (int s = 0; s < kS; ++s) {
 #pragma unroll
       for (int t = 0; t < kT; ++t)
-        acc[t] = mfma16(lds[(4 * s + q) * kPP + t * 16 + c], fx.v[s], acc[t]);
+        acc[t] = mfma16(lds[(4 * s + q) * kPP + t * 16 + c], f.x.v[s], acc[t]);
     }
     if constexpr (kHasY) {
 #pragma unroll
       for (int s = 0; s < kS; ++s) {
 #pragma unroll
         for (int t = 0; t < kT; ++t)
-          acc[t] = mfma16(lds[kPP * kPP + (4 * s + q) * kPP + t * 16 + c], fy.v[s], acc[t]);
+          acc[t] = mfma16(lds[kPP * kPP + (4 * s + q) * kPP + t * 16 + c], f.y.v[s], acc[t]);
       }
     }
     const bool rok = row < n;
@@ -356,13 +399,13 @@ __device__ inline void combine_tiles(const CombineArgs& a, const double* lds, in
         const int s = 2 * j + e;
         ok[e] = rok && comb_col(s, q) < p;
         double x = acc[s / 4][s % 4];
-        if constexpr (kHasC0) x += fc.v[s];
+        if constexpr (kHasC0) x += f.c0.v[s];
         x = ok[e] ? (double)(T)x : 0.0;  // the epilogues see the stored value
         v[e] = x;
         if constexpr (kRho) sq += x * x;
         if constexpr (kGrad) {
-          const double sd = fx.v[s] - fxk.v[s];
-          const double yd = x - fdk.v[s];
+          const double sd = f.x.v[s] - f.xk.v[s];
+          const double yd = x - f.dk.v[s];
           sums[0] += x * x;
           sums[1] += sd * sd;
           sums[2] += sd * yd;
@@ -388,24 +431,23 @@ __device__ inline void combine_tiles(const CombineArgs& a, const double* lds, in
       sq += __shfl_xor(sq, 32, kWave);
       if (q == 0 && rok) a.rho[row] = a.rho_scale * sq;
     }
+  };
+
+  int tile = t_beg + w;
+  Tile f0;
+  if (tile < t_end) load(f0, tile);
+  comb_stage<kT, kHasY>(a, lds);
+  __syncthreads();
+  for (; tile < t_end; tile += 4) {
+    if (tile > t_beg + w) load(f0, tile);
+    compute(f0, tile);
   }
 }
 
 template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad>
 __device__ inline void k_combine_body(const CombineArgs& a, int ks_bid, int ks_nb) {
-  constexpr int kPP = kT * 16;
-  constexpr int kK = kHasY ? 2 * kPP : kPP;  // contraction length
   extern __shared__ double lds[];            // permuted weights Wp = [A; B]: kK x kPP
   __shared__ double sh[kBlock / kWave];
-
-  for (int e = threadIdx.x; e < kK * kPP; e += blockDim.x) {
-    const int r = e / kPP, col = e % kPP;
-    const int rr = r % kPP, s = rr >> 2, qq = rr & 3;
-    const int t = col >> 4, m = col & 15;
-    const int src = comb_col(s, qq) * kPP + 16 * t + 8 * (m >> 3) + 2 * (m & 3) + ((m >> 2) & 1);
-    lds[e] = (kHasY && r >= kPP) ? a.B[src] : a.A[src];
-  }
-  __syncthreads();
 
   const int ntiles = (a.n + 15) / 16;
   const int lb = xcd_remap(ks_bid, ks_nb);
@@ -561,7 +603,7 @@ void launch_gram_reduce(const double* partials, int nchunks, int pp, int mask, d
 int combine_blocks(int n) {
   int tiles = (n + 15) / 16;
   int b = (tiles + 3) / 4;
-  if (b > 4096) b = 4096;
+  if (b > kCombineMaxBlocks) b = kCombineMaxBlocks;
   return b < 1 ? 1 : b;
 }
 
