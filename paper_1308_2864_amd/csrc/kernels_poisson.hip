@@ -100,7 +100,7 @@ __device__ inline double fin_sum(const double* part, int slot, int nb, double* s
 __device__ inline void k_init_body(const InitArgs& ka, int ks_bid, int ks_nb) {
   const double* __restrict__ rho = ka.rho;
   const double* __restrict__ x0 = ka.x0;
-  double* __restrict__ x = ka.x;
+  double* x = ka.x;  // may be nullptr (x0 is the iterate)
   double* __restrict__ r = ka.r;
   double* __restrict__ p0 = ka.p0;
   Grid gr = ka.gr;
@@ -117,7 +117,7 @@ __device__ inline void k_init_body(const InitArgs& ka, int ks_bid, int ks_nb) {
     const int i = g % gr.nx, j = (g / gr.nx) % gr.ny, k = g / (gr.nx * gr.ny);
     const double b = 4.0 * kPi * gr.rhs_scale * rho[g];
     const double ri = x0 ? b - op_apply(x0, nullptr, 0.0, g, i, j, k, gr) : b;
-    x[g] = x0 ? x0[g] : 0.0;
+    if (x) x[g] = x0 ? x0[g] : 0.0;
     r[g] = ri;
     p0[g] = 0.0;
     rr += ri * ri;
@@ -154,7 +154,7 @@ __device__ inline void k_fin_init_body(const FinInitArgs& ka, int ks_bid, int ks
     cs->tol2 = tol * tol;
     cs->alpha = cs->beta = cs->pq = 0.0;
     cs->rz = 0.0;
-    cs->it = 0;
+    cs->it = bb == 0.0 ? 0 : ka.it0;  // rho == 0: nothing was solved
     cs->maxit = maxit;
     cs->done = (bb == 0.0 || !isfinite(rr) || !isfinite(bb) || rr <= tol * tol * bb) ? 1 : 0;
   }
@@ -321,7 +321,7 @@ __device__ inline void k_fin_rz_body(const FinRzArgs& ka, int ks_bid, int ks_nb)
   if (cs->done) return;
   const double rz = fin_sum(part, 3, nb, sh);
   if (threadIdx.x == 0) {
-    cs->beta = (cs->it == 0) ? 0.0 : rz / cs->rz;
+    cs->beta = (cs->rz == 0.0) ? 0.0 : rz / cs->rz;  // rz is 0 right after a (re)start
     cs->rz = rz;
   }
 }
@@ -398,7 +398,7 @@ __device__ inline void k_fd_plane_body(const FdPlaneArgs& ka, int ks_bid, int ks
   (void)ks_nb;
   extern __shared__ double P[];
   __shared__ double sh[kBlock / kWave];
-  if (cs->done) return;
+  if (cs && cs->done) return;
   const int nxp = (nx + 15) & ~15, nyp = (ny + 15) & ~15, sp = nxp + 1;
   const int ncs = nxp / 16;
   const int k = ks_bid / ncs, i0 = (ks_bid % ncs) * 16;
@@ -445,6 +445,7 @@ __device__ inline void k_fd_plane_body(const FdPlaneArgs& ka, int ks_bid, int ks
       const int j = j0 + lr + 4 * q, i = i0 + lc;
       if (j < ny && i < nx) {
         const size_t o = base + (size_t)j * nx + i;
+        if (ka.add) y[q] += ka.add[o];
         out[o] = y[q];
         if (part) rz += y[q] * r[o];
       }
@@ -488,7 +489,7 @@ __device__ inline void k_fd_z_body(const FdZArgs& ka, int ks_bid, int ks_nb) {
   (void)ks_nb;
 
   extern __shared__ double A[];  // nzp x kZCols (then S_z when it fits)
-  if (cs->done) return;
+  if (cs && cs->done) return;
   const int npl = nx * ny;
   const int nzp = (nz + 15) & ~15;
   const int l0 = ks_bid * kZCols;
@@ -588,12 +589,12 @@ void launch_fd_setup(double* S, double* lam, double* mu, int N, double h, int q1
 }
 
 void launch_hartree_init(const double* rho, const double* x0, double* x, double* r, double* p0,
-                         CgState* cs, double tol, int maxit, Grid g, double* part,
+                         CgState* cs, double tol, int maxit, int it0, Grid g, double* part,
                          hipStream_t st) {
   const int nb = cg_nblocks(g.n);
   hipLaunchKernelGGL(k_init, dim3(nb), dim3(kBlock), 0, st, InitArgs{rho, x0, x, r, p0, g, part});
   hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kBlock), 0, st,
-                     FinInitArgs{part, nb, cs, tol, maxit});
+                     FinInitArgs{part, nb, cs, tol, maxit, it0});
 }
 
 namespace {
@@ -616,10 +617,14 @@ size_t fd_lds_bytes(int nx, int ny, int nz) {
 // Largest plane the register tiles of k_fd_plane cover (kFdWaves * kFdTiles tiles).
 int fd_max_plane() { return kFdWaves * kFdTiles * 256; }
 
-// z = L^{-1} r by the fast diagonalisation (plane transform, z pass with the eigenvalue
-// division, inverse plane transform with the partial r.z), then beta from r.z.
-void launch_fd_apply(const double* r, double* z, double* tmp, const FdOps& fd, Grid g,
-                     const CgState* cs, double* part, hipStream_t st) {
+namespace {
+// The three fast-diagonalisation passes: in -> tmp (plane transform), the z pass
+// with the eigenvalue division in place on tmp, tmp -> out (inverse plane transform, plus
+// add when given; with part also the partials of out . rr).  The strips of a plane are separate blocks, so a
+// plane pass never works in place.
+void fd_passes(const double* in, double* out, const double* add, double* tmp,
+               const FdOps& fd, Grid g, const CgState* cs, const double* rr, double* part,
+               hipStream_t st) {
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const size_t nxp = (nx + 15) & ~15, nyp = (ny + 15) & ~15, nzp = (nz + 15) & ~15;
   const size_t lzb = nzp * kZCols * sizeof(double);
@@ -629,8 +634,9 @@ void launch_fd_apply(const double* r, double* z, double* tmp, const FdOps& fd, G
   const int ncs = (int)(nxp / 16);
   const size_t lpl = (nyp * (nxp + 1) + nyp * 17 + nxp * 16) * sizeof(double);
   const size_t lpls = lpl + (size_t)ny * ny * sizeof(double);
-  auto plane = [&](const double* in, double* out, const double* rr, double* pt) {
-    const FdPlaneArgs pa{in, out, fd.Sx, fd.Sy, nx, ny, rr, pt, cs};
+  auto plane = [&](const double* src, double* dst, const double* ad, const double* r,
+                   double* pt) {
+    const FdPlaneArgs pa{src, dst, fd.Sx, fd.Sy, nx, ny, r, pt, cs, ad};
     if (lpls <= cap) {
       set_lds(reinterpret_cast<const void*>(k_fd_plane<true>), lpls);
       hipLaunchKernelGGL(k_fd_plane<true>, dim3(nz * ncs), dim3(kPlaneWaves * kWave), lpls,
@@ -641,12 +647,9 @@ void launch_fd_apply(const double* r, double* z, double* tmp, const FdOps& fd, G
                          st, pa);
     }
   };
-
-  // the strips of a plane are separate blocks, so a plane pass never works in place:
-  // r -> tmp, z pass in place on tmp, tmp -> z
   const int zblocks = (nx * ny + kZCols - 1) / kZCols;
   const FdZArgs za{tmp, fd.Sz, fd.lx, fd.ly, fd.lz, fd.mx, fd.my, fd.mz, nx, ny, nz, cs};
-  plane(r, tmp, nullptr, nullptr);
+  plane(in, tmp, nullptr, nullptr, nullptr);
   if (lzs <= cap) {
     set_lds(reinterpret_cast<const void*>(k_fd_z<true>), lzs);
     hipLaunchKernelGGL(k_fd_z<true>, dim3(zblocks), dim3(threads), lzs, st, za);
@@ -654,9 +657,30 @@ void launch_fd_apply(const double* r, double* z, double* tmp, const FdOps& fd, G
     set_lds(reinterpret_cast<const void*>(k_fd_z<false>), lzb);
     hipLaunchKernelGGL(k_fd_z<false>, dim3(zblocks), dim3(threads), lzb, st, za);
   }
-  plane(tmp, z, r, part);
+  plane(tmp, out, add, rr, part);
+}
+}  // namespace
+
+// z = L^{-1} r by the fast diagonalisation, then beta from r.z.
+void launch_fd_apply(const double* r, double* z, double* tmp, const FdOps& fd, Grid g,
+                     const CgState* cs, double* part, hipStream_t st) {
+  fd_passes(r, z, nullptr, tmp, fd, g, cs, r, part, st);
+  const int ncs = (g.nx + 15) / 16;
   hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kBlock), 0, st,
-                     FinRzArgs{part, nz * ncs, const_cast<CgState*>(cs)});
+                     FinRzArgs{part, g.nz * ncs, const_cast<CgState*>(cs)});
+}
+
+// x = x0 + L^{-1} r: with r = b - L x0 this is the first iterate of the preconditioned CG
+// from x0 with the step length the exact preconditioner gives (exactly 1).
+void launch_fd_correct(const double* r, const double* x0, double* x, double* tmp,
+                       const FdOps& fd, Grid g, hipStream_t st) {
+  fd_passes(r, x, x0, tmp, fd, g, nullptr, nullptr, nullptr, st);
+}
+
+void launch_cg_residual(const double* rho, const double* x0, double* r, double* p0, Grid g,
+                        double* part, hipStream_t st) {
+  hipLaunchKernelGGL(k_init, dim3(cg_nblocks(g.n)), dim3(kBlock), 0, st,
+                     InitArgs{rho, x0, nullptr, r, p0, g, part});
 }
 
 void launch_hartree_iter(double* x, double* r, const double* z, double* pa, double* pb,

@@ -19,8 +19,8 @@ thread_local std::string g_err;
 constexpr int kPartStride = 4096;  // >= blocks of every streaming kernel
 // argument records of the batched trial kernels: one 256-byte slot per kernel and parity
 enum Rec {
-  R_QR, R_RETRACT, R_INIT, R_FIN_INIT, R_PLANE1, R_FDZ, R_PLANE2, R_FIN_RZ, R_DIR, R_FIN_DIR,
-  R_UPD, R_FIN_UPD, R_XC, R_HX, R_GRAM1, R_RED1, R_GRAD, R_GRAM2, R_RED2, R_FINISH, R_COUNT
+  R_QR, R_RETRACT, R_RESID, R_PLANE1, R_FDZ, R_PLANE2, R_INIT, R_FIN_INIT, R_XC, R_HX, R_GRAM1,
+  R_RED1, R_GRAD, R_GRAM2, R_RED2, R_FINISH, R_COUNT
 };
 constexpr size_t kRecSlot = 256;
 constexpr size_t kRecBytes = 2 * R_COUNT * kRecSlot;
@@ -410,11 +410,15 @@ void harvest(ks_system* s) {
 // Queues Hartree iterations on the current CG state until the device flag says done
 // (checked between chunks).  With wait == false a PCG solve only queues its usual two
 // iterations; whoever reads the CG state later must check the flag.
+FdOps fd_ops(const ks_system* s) {
+  return FdOps{s->fdS[0], s->fdS[1], s->fdS[2], s->fdL[0], s->fdL[1], s->fdL[2],
+               s->fdM[0], s->fdM[1], s->fdM[2]};
+}
+
 int hartree_iterate(ks_system* s, double* x, int first_chunk, bool wait, int* iters,
                     double* relres) {
   const bool pcg = s->solver == KS_HARTREE_PCG_FD;
-  FdOps fd{s->fdS[0], s->fdS[1], s->fdS[2], s->fdL[0], s->fdL[1], s->fdL[2],
-           s->fdM[0], s->fdM[1], s->fdM[2]};
+  const FdOps fd = fd_ops(s);
   int launched = 0;
   int chunk = first_chunk;
   CgState* hc = host_cg(s);
@@ -452,14 +456,22 @@ int hartree_iterate(ks_system* s, double* x, int first_chunk, bool wait, int* it
 int hartree(ks_system* s, const double* rho, const double* x0, double* x, bool wait,
             int* iters, double* relres) {
   tbeg(s, KS_PH_HARTREE);
-  const bool pcg = s->solver == KS_HARTREE_PCG_FD;
   s->cg_par = 0;
-  launch_hartree_init(rho, x0, x, s->cg_r, s->cg_p[0], s->cg, s->htol, s->hmaxit, s->grid,
+  if (s->solver == KS_HARTREE_PCG_FD) {
+    // One preconditioned CG iteration from x0 with the exact step length of the exact
+    // preconditioner: x = x0 + L^{-1}(b - L x0).  The CG start then measures the residual
+    // of x and counts the iteration; only a solve that misses the tolerance continues with
+    // PCG iterations (for a queued trial the caller does that: hartree_pending).
+    launch_cg_residual(rho, x0, s->cg_r, s->cg_p[0], s->grid, s->cgpart, s->st);
+    launch_fd_correct(s->cg_r, x0, x, s->cg_q, fd_ops(s), s->grid, s->st);
+    launch_hartree_init(rho, x, nullptr, s->cg_r, s->cg_p[0], s->cg, s->htol, s->hmaxit, 1,
+                        s->grid, s->cgpart, s->st);
+    return hartree_iterate(s, x, 0, wait, iters, relres);
+  }
+  launch_hartree_init(rho, x0, x, s->cg_r, s->cg_p[0], s->cg, s->htol, s->hmaxit, 0, s->grid,
                       s->cgpart, s->st);
-  // first chunk sized by the previous solve (warm starts need similar counts); with the
-  // exact preconditioner one iteration reaches the tolerance (alpha = 1 up to rounding),
-  // and a trial whose solve needs more is finished by the caller (hartree_pending)
-  const int chunk = pcg ? 1 : (s->last_cg_iters > 0 ? s->last_cg_iters + 2 : 32);
+  // first chunk sized by the previous solve (warm starts need similar counts)
+  const int chunk = s->last_cg_iters > 0 ? s->last_cg_iters + 2 : 32;
   return hartree_iterate(s, x, chunk, wait, iters, relres);
 }
 
@@ -928,26 +940,21 @@ void fill_typed(ks_system* s, std::vector<char>& buf, int c) {
   rt.p = s->p;
   rt.f32 = s->f32;
   put_rec(buf, c, R_RETRACT, rt);
-  // Hartree: one PCG iteration warm-started from V_H of slot c (parity of p arrays is 0)
-  put_rec(buf, c, R_INIT, InitArgs{s->rho, s->vh[c], s->vh[t], s->cg_r, s->cg_p[0], s->grid,
+  // Hartree: V_H of slot t = V_H(c) + L^{-1}(b - L V_H(c)) by the fast diagonalisation,
+  // then the CG start that measures its residual (a solve that misses the tolerance is
+  // finished by the host)
+  const FdOps fd = fd_ops(s);
+  put_rec(buf, c, R_RESID, InitArgs{s->rho, s->vh[c], nullptr, s->cg_r, s->cg_p[0], s->grid,
+                                    s->cgpart});
+  put_rec(buf, c, R_PLANE1, FdPlaneArgs{s->cg_r, s->cg_q, fd.Sx, fd.Sy, s->grid.nx, s->grid.ny,
+                                        nullptr, nullptr, nullptr, nullptr});
+  put_rec(buf, c, R_FDZ, FdZArgs{s->cg_q, fd.Sz, fd.lx, fd.ly, fd.lz, fd.mx, fd.my, fd.mz,
+                                 s->grid.nx, s->grid.ny, s->grid.nz, nullptr});
+  put_rec(buf, c, R_PLANE2, FdPlaneArgs{s->cg_q, s->vh[t], fd.Sx, fd.Sy, s->grid.nx, s->grid.ny,
+                                        nullptr, nullptr, nullptr, s->vh[c]});
+  put_rec(buf, c, R_INIT, InitArgs{s->rho, s->vh[t], nullptr, s->cg_r, s->cg_p[0], s->grid,
                                    s->cgpart});
-  put_rec(buf, c, R_FIN_INIT, FinInitArgs{s->cgpart, hb, s->cg, s->htol, s->hmaxit});
-  put_rec(buf, c, R_PLANE1, FdPlaneArgs{s->cg_r, s->cg_q, s->fdS[0], s->fdS[1], s->grid.nx,
-                                        s->grid.ny, nullptr, nullptr, s->cg});
-  put_rec(buf, c, R_FDZ, FdZArgs{s->cg_q, s->fdS[2], s->fdL[0], s->fdL[1], s->fdL[2], s->fdM[0],
-                                 s->fdM[1], s->fdM[2], s->grid.nx, s->grid.ny, s->grid.nz,
-                                 s->cg});
-  put_rec(buf, c, R_PLANE2, FdPlaneArgs{s->cg_q, s->cg_z, s->fdS[0], s->fdS[1], s->grid.nx,
-                                        s->grid.ny, s->cg_r, s->cgpart, s->cg});
-  put_rec(buf, c, R_FIN_RZ, FinRzArgs{s->cgpart,
-                                      fd_launch(s->grid.nx, s->grid.ny, s->grid.nz).plane_blocks,
-                                      s->cg});
-  put_rec(buf, c, R_DIR, DirArgs{s->cg_z, s->cg_p[0], s->cg_p[1], s->cg_q, s->cg, s->grid,
-                                 s->cgpart});
-  put_rec(buf, c, R_FIN_DIR, FinDirArgs{s->cgpart, hb, s->cg, 1});
-  put_rec(buf, c, R_UPD, UpdArgs{s->vh[t], s->cg_r, s->cg_p[1], s->cg_q, s->cg, s->grid,
-                                 s->cgpart});
-  put_rec(buf, c, R_FIN_UPD, FinUpdArgs{s->cgpart, hb, s->cg, 1});
+  put_rec(buf, c, R_FIN_INIT, FinInitArgs{s->cgpart, hb, s->cg, s->htol, s->hmaxit, 1});
   // evaluation of slot t
   put_rec(buf, c, R_XC, XcArgs{s->rho, s->vh[t], s->vext, s->veff[t], s->grid, s->use_h,
                                s->use_x, s->cg, pt});
@@ -1051,9 +1058,6 @@ void launch_trial_batch(const std::vector<BatchMember*>& g, hipStream_t st) {
   auto rt = table<CombineArgs>(g, R_RETRACT, cb, &tot);
   launch_combine_retract_batch<T>(rt, pp, tot, st);
   auto hb = [](const ks_system* s) { return hartree_blocks(s->n); };
-  auto in = table<InitArgs>(g, R_INIT, hb, &tot);
-  launch_init_batch(in, tot, st);
-  launch_fin_init_batch(table<FinInitArgs>(g, R_FIN_INIT, one, &tot), st);
   bool stage_p = true, stage_z = true;
   for (auto* m : g) {
     const FdLaunch l = fd_launch(m->s->grid.nx, m->s->grid.ny, m->s->grid.nz);
@@ -1072,19 +1076,17 @@ void launch_trial_batch(const std::vector<BatchMember*>& g, hipStream_t st) {
   auto zb = [](const ks_system* s) {
     return fd_launch(s->grid.nx, s->grid.ny, s->grid.nz).z_blocks;
   };
+  auto r0 = table<InitArgs>(g, R_RESID, hb, &tot);
+  launch_init_batch(r0, tot, st);
   auto p1 = table<FdPlaneArgs>(g, R_PLANE1, pb, &tot);
   launch_fd_plane_batch(p1, tot, stage_p, lds_p, st);
   auto fz = table<FdZArgs>(g, R_FDZ, zb, &tot);
   launch_fd_z_batch(fz, tot, stage_z, lds_z, st);
   auto p2 = table<FdPlaneArgs>(g, R_PLANE2, pb, &tot);
   launch_fd_plane_batch(p2, tot, stage_p, lds_p, st);
-  launch_fin_rz_batch(table<FinRzArgs>(g, R_FIN_RZ, one, &tot), st);
-  auto di = table<DirArgs>(g, R_DIR, hb, &tot);
-  launch_dir_batch(di, tot, st);
-  launch_fin_dir_batch(table<FinDirArgs>(g, R_FIN_DIR, one, &tot), st);
-  auto up = table<UpdArgs>(g, R_UPD, hb, &tot);
-  launch_upd_batch(up, tot, st);
-  launch_fin_upd_batch(table<FinUpdArgs>(g, R_FIN_UPD, one, &tot), st);
+  auto in = table<InitArgs>(g, R_INIT, hb, &tot);
+  launch_init_batch(in, tot, st);
+  launch_fin_init_batch(table<FinInitArgs>(g, R_FIN_INIT, one, &tot), st);
   auto sb = [](const ks_system* s) { return scalar_blocks(s->n); };
   auto xc = table<XcArgs>(g, R_XC, sb, &tot);
   launch_xc_batch(xc, tot, st);
@@ -1185,7 +1187,7 @@ int batch_tick(BatchEngine* e) {
   for (int i = 0; i < ga.S; ++i) {
     BatchMember* m = e->act[i];
     std::memcpy(m->s->host, hstage + (size_t)i * kGatherBytes, kGatherBytes);
-    m->s->cg_par = 1;  // the host state a lone trial leaves after its one PCG iteration
+    m->s->cg_par = 0;  // the host state a lone trial leaves (no PCG iteration queued)
     int code = run_after_trial(m->s, &m->m, true);
     const LsState* hl = host_ls(m->s);
     if (code != KS_OK) {

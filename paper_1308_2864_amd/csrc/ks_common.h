@@ -223,7 +223,7 @@ struct FdOps {
 struct InitArgs {
   const double* rho;
   const double* x0;
-  double* x;
+  double* x;        // nullptr: x0 is the iterate (no copy)
   double* r;
   double* p0;
   Grid gr;
@@ -236,6 +236,7 @@ struct FinInitArgs {
   CgState* cs;
   double tol;
   int maxit;
+  int it0;          // iterations the start already stands for (1 after a direct solve)
 };
 
 struct DirArgs {
@@ -287,7 +288,8 @@ struct FdPlaneArgs {
   int ny;
   const double* r;
   double* part;
-  const CgState* cs;
+  const CgState* cs;  // nullptr: no early exit
+  const double* add;  // optional: out = add + transform
 };
 
 struct FdZArgs {
@@ -329,8 +331,15 @@ int fd_max_plane();
 void launch_fd_setup(double* S, double* lam, double* mu, int N, double h, int q1,
                      hipStream_t st);
 void launch_hartree_init(const double* rho, const double* x0, double* x, double* r, double* p0,
-                         CgState* cs, double tol, int maxit, Grid g, double* part,
+                         CgState* cs, double tol, int maxit, int it0, Grid g, double* part,
                          hipStream_t st);
+// r = 4 pi rhs_scale rho - L x0 (x0 may be nullptr: r = b) with the partials r.r, b.b
+void launch_cg_residual(const double* rho, const double* x0, double* r, double* p0, Grid g,
+                        double* part, hipStream_t st);
+// x = x0 + L^{-1} r (or A^{-1} r; x0 may be nullptr) in three fast-diagonalisation passes
+// (plane, z with the eigenvalue division, plane); tmp is an n-vector of scratch.
+void launch_fd_correct(const double* r, const double* x0, double* x, double* tmp,
+                       const FdOps& fd, Grid g, hipStream_t st);
 // z = L^{-1} r (or A^{-1} r) by the fast diagonalisation; tmp is an n-vector of scratch.
 void launch_fd_apply(const double* r, double* z, double* tmp, const FdOps& fd, Grid g,
                      const CgState* cs, double* part, hipStream_t st);
