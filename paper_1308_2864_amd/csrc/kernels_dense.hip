@@ -328,13 +328,17 @@ template <int kT, bool kHasY>
 __device__ inline void comb_stage(const CombineArgs& a, double* lds) {
   constexpr int kPP = kT * 16;
   constexpr int kK = kHasY ? 2 * kPP : kPP;
-  for (int e = threadIdx.x; e < kK * kPP; e += blockDim.x) {
-    const int r = e / kPP, col = e % kPP;
-    const int rr = r % kPP, s = rr >> 2, qq = rr & 3;
-    const int t = col >> 4, m = col & 15;
-    const int src = comb_col(s, qq) * kPP + 16 * t + 8 * (m >> 3) + 2 * (m & 3) + ((m >> 2) & 1);
-    lds[e] = (kHasY && r >= kPP) ? a.B[src] : a.A[src];
-  }
+  lds_stage<kK * kPP / kBlock>(
+      kK * kPP,
+      [&](int e) {
+        const int r = e / kPP, col = e % kPP;
+        const int rr = r % kPP, s = rr >> 2, qq = rr & 3;
+        const int t = col >> 4, m = col & 15;
+        const int src =
+            comb_col(s, qq) * kPP + 16 * t + 8 * (m >> 3) + 2 * (m & 3) + ((m >> 2) & 1);
+        return (kHasY && r >= kPP) ? a.B[src] : a.A[src];
+      },
+      [&](int e, double v) { lds[e] = v; });
 }
 
 // The first tile's loads are issued before the weights are staged, so they overlap the

@@ -405,20 +405,30 @@ __device__ inline void k_fd_plane_body(const FdPlaneArgs& ka, int ks_bid, int ks
   const size_t base = (size_t)k * nx * ny;
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int lr = lane / 16, lc = lane % 16;
-  for (int e = threadIdx.x; e < nyp * nxp; e += blockDim.x) {
-    const int j = e / nxp, m = e % nxp;
-    P[j * sp + m] = (j < ny && m < nx) ? in[base + (size_t)j * nx + m] : 0.0;
-  }
+  lds_stage<16>(
+      nyp * nxp,
+      [&](int e) {
+        const int j = e / nxp, m = e % nxp;
+        const bool ok = j < ny && m < nx;
+        const double v = in[ok ? base + (size_t)j * nx + m : base];
+        return ok ? v : 0.0;
+      },
+      [&](int e, double v) { P[(e / nxp) * sp + e % nxp] = v; });
   double* Tt = P + nyp * sp;     // nyp x 17
   double* Sxs = Tt + nyp * 17;   // nxp x 16: S_x[:, i0 .. i0 + 15]
-  for (int e = threadIdx.x; e < nxp * 16; e += blockDim.x) {
-    const int m = e / 16, c = e % 16;
-    Sxs[e] = (m < nx && i0 + c < nx) ? Sx[m * nx + i0 + c] : 0.0;
-  }
+  lds_stage<8>(
+      nxp * 16,
+      [&](int e) {
+        const int m = e / 16, c = e % 16;
+        const bool ok = m < nx && i0 + c < nx;
+        const double v = Sx[ok ? m * nx + i0 + c : 0];
+        return ok ? v : 0.0;
+      },
+      [&](int e, double v) { Sxs[e] = v; });
   const double* SyL = Sy;
   if (kStageSy) {
     double* sy = Sxs + nxp * 16;
-    for (int e = threadIdx.x; e < ny * ny; e += blockDim.x) sy[e] = Sy[e];
+    lds_stage<16>(ny * ny, [&](int e) { return Sy[e]; }, [&](int e, double v) { sy[e] = v; });
     SyL = sy;
   }
   __syncthreads();
@@ -469,6 +479,114 @@ __global__ __launch_bounds__(256) void k_fd_plane_batch(BatchPtrs<FdPlaneArgs> b
 }
 
 
+// The same 2-D transform with one whole z-plane per block of kFullWaves waves, used when
+// the plane, T, S_x and S_y all fit in LDS (planes up to 64 x 64): every operand is staged
+// once per plane instead of once per strip, and each wave computes one 16 x 16 tile of T
+// and then one of Y.
+constexpr int kFullWaves = 16;
+
+__device__ inline void k_fd_plane_full_body(const FdPlaneArgs& ka, int ks_bid, int ks_nb) {
+  const double* __restrict__ in = ka.in;
+  double* __restrict__ out = ka.out;
+  const double* __restrict__ Sx = ka.Sxg;
+  const double* __restrict__ Sy = ka.Syg;
+  const int nx = ka.nx, ny = ka.ny;
+  const double* __restrict__ r = ka.r;
+  double* __restrict__ part = ka.part;
+  const CgState* cs = ka.cs;
+  (void)ks_nb;
+  extern __shared__ double P[];
+  __shared__ double sh[kFullWaves];
+  if (cs && cs->done) return;
+  const int nxp = (nx + 15) & ~15, nyp = (ny + 15) & ~15, sp = nxp + 1;
+  const size_t base = (size_t)ks_bid * nx * ny;
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int lr = lane / 16, lc = lane % 16;
+  double* T = P + nyp * sp;      // nyp x sp
+  double* Sxs = T + nyp * sp;    // nxp x nxp (zero padded)
+  double* Sys = Sxs + nxp * nxp; // nyp x nyp (zero padded)
+  lds_stage<4>(
+      nyp * nxp,
+      [&](int e) {
+        const int j = e / nxp, m = e % nxp;
+        const bool ok = j < ny && m < nx;
+        const double v = in[ok ? base + (size_t)j * nx + m : base];
+        return ok ? v : 0.0;
+      },
+      [&](int e, double v) { P[(e / nxp) * sp + e % nxp] = v; });
+  lds_stage<4>(
+      nxp * nxp,
+      [&](int e) {
+        const int m = e / nxp, c = e % nxp;
+        const bool ok = m < nx && c < nx;
+        const double v = Sx[ok ? m * nx + c : 0];
+        return ok ? v : 0.0;
+      },
+      [&](int e, double v) { Sxs[e] = v; });
+  lds_stage<4>(
+      nyp * nyp,
+      [&](int e) {
+        const int m = e / nyp, c = e % nyp;
+        const bool ok = m < ny && c < ny;
+        const double v = Sy[ok ? m * ny + c : 0];
+        return ok ? v : 0.0;
+      },
+      [&](int e, double v) { Sys[e] = v; });
+  __syncthreads();
+  const int nti = nxp / 16, ntile = (nyp / 16) * nti;
+  // T[j][i] = sum_m P[j][m] S_x[m][i]
+  for (int t = w; t < ntile; t += kFullWaves) {
+    const int j0 = (t / nti) * 16, i0 = (t % nti) * 16;
+    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < nxp; k0 += 4)
+      acc = mma(P[(j0 + lc) * sp + k0 + lr], Sxs[(k0 + lr) * nxp + i0 + lc], acc);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) T[(j0 + lr + 4 * q) * sp + i0 + lc] = acc[q];
+  }
+  __syncthreads();
+  // Y[j][i] = sum_m S_y[j][m] T[m][i]  (S_y symmetric: its fragments are read along rows)
+  double rz = 0.0;
+  for (int t = w; t < ntile; t += kFullWaves) {
+    const int j0 = (t / nti) * 16, i0 = (t % nti) * 16;
+    d4 y = d4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < nyp; k0 += 4)
+      y = mma(Sys[(k0 + lr) * nyp + j0 + lc], T[(k0 + lr) * sp + i0 + lc], y);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = j0 + lr + 4 * q, i = i0 + lc;
+      if (j < ny && i < nx) {
+        const size_t o = base + (size_t)j * nx + i;
+        if (ka.add) y[q] += ka.add[o];
+        out[o] = y[q];
+        if (part) rz += y[q] * r[o];
+      }
+    }
+  }
+  if (part) {
+    // fixed-order sum over the block's waves
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) rz += __shfl_down(rz, o, kWave);
+    if (lane == 0) sh[w] = rz;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int i = 0; i < kFullWaves; ++i) t += sh[i];
+      part[3 * kCgBlocksMax + ks_bid] = t;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kFullWaves * kWave) void k_fd_plane_full(FdPlaneArgs ka) {
+  k_fd_plane_full_body(ka, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(kFullWaves * kWave) void k_fd_plane_full_batch(
+    BatchPtrs<FdPlaneArgs> b) {
+  const int s = batch_system(b.off, b.S, blockIdx.x);
+  k_fd_plane_full_body(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+}
+
+
 // z lines (block = 64 adjacent (i, j) columns x nz): forward transform, division by
 // lx[i] + ly[j] + lz[k], inverse transform (S_z is its own inverse), in place.
 template <bool kStageS>
@@ -495,14 +613,19 @@ __device__ inline void k_fd_z_body(const FdZArgs& ka, int ks_bid, int ks_nb) {
   const int l0 = ks_bid * kZCols;
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int lr = lane / 16, lc = lane % 16;
-  for (int e = threadIdx.x; e < nzp * kZCols; e += blockDim.x) {
-    const int m = e / kZCols, l = e % kZCols;
-    A[e] = (m < nz && l0 + l < npl) ? u[(size_t)m * npl + l0 + l] : 0.0;
-  }
+  lds_stage<8>(
+      nzp * kZCols,
+      [&](int e) {
+        const int m = e / kZCols, l = e % kZCols;
+        const bool ok = m < nz && l0 + l < npl;
+        const double v = u[ok ? (size_t)m * npl + l0 + l : 0];
+        return ok ? v : 0.0;
+      },
+      [&](int e, double v) { A[e] = v; });
   const double* Sz = Szg;
   if (kStageS) {
     double* sz = A + nzp * kZCols;
-    for (int e = threadIdx.x; e < nz * nz; e += blockDim.x) sz[e] = Szg[e];
+    lds_stage<8>(nz * nz, [&](int e) { return Szg[e]; }, [&](int e, double v) { sz[e] = v; });
     Sz = sz;
   }
   __syncthreads();
@@ -608,16 +731,49 @@ void set_lds(const void* k, size_t bytes) {
 }
 }  // namespace
 
-// LDS the preconditioner needs for an nx x ny x nz grid.
+// LDS of one plane-transform block in each mode (strips with S_y read from L2, strips
+// with S_y staged, whole plane).
+size_t fd_plane_bytes(int nx, int ny, int mode) {
+  const size_t nxp = (nx + 15) & ~15, nyp = (ny + 15) & ~15;
+  if (mode == kPlaneFull) return (2 * nyp * (nxp + 1) + nxp * nxp + nyp * nyp) * sizeof(double);
+  const size_t strip = (nyp * (nxp + 1) + nyp * 17 + nxp * 16) * sizeof(double);
+  return mode == kPlaneStripSy ? strip + (size_t)ny * ny * sizeof(double) : strip;
+}
+
+int fd_plane_mode(int nx, int ny) {
+  if (fd_plane_bytes(nx, ny, kPlaneFull) <= kFdLdsCap) return kPlaneFull;
+  return fd_plane_bytes(nx, ny, kPlaneStripSy) <= kFdLdsCap ? kPlaneStripSy : kPlaneStrip;
+}
+
+int fd_plane_blocks(int nx, int nz, int mode) {
+  return mode == kPlaneFull ? nz : nz * ((nx + 15) / 16);
+}
+
+// LDS the preconditioner needs for an nx x ny x nz grid (the plane strips at least).
 size_t fd_lds_bytes(int nx, int ny, int nz) {
-  const size_t nxp = (nx + 15) & ~15, nyp = (ny + 15) & ~15, nzp = (nz + 15) & ~15;
-  return std::max(nyp * (nxp + 1), nzp * (size_t)kZCols) * sizeof(double);
+  const size_t nzp = (nz + 15) & ~15;
+  return std::max(fd_plane_bytes(nx, ny, kPlaneStrip), nzp * (size_t)kZCols * sizeof(double));
 }
 
 // Largest plane the register tiles of k_fd_plane cover (kFdWaves * kFdTiles tiles).
 int fd_max_plane() { return kFdWaves * kFdTiles * 256; }
 
 namespace {
+void launch_fd_plane(const FdPlaneArgs& pa, int nz, int mode, hipStream_t st) {
+  const size_t lds = fd_plane_bytes(pa.nx, pa.ny, mode);
+  const int nb = fd_plane_blocks(pa.nx, nz, mode);
+  if (mode == kPlaneFull) {
+    set_lds(reinterpret_cast<const void*>(k_fd_plane_full), lds);
+    hipLaunchKernelGGL(k_fd_plane_full, dim3(nb), dim3(kFullWaves * kWave), lds, st, pa);
+  } else if (mode == kPlaneStripSy) {
+    set_lds(reinterpret_cast<const void*>(k_fd_plane<true>), lds);
+    hipLaunchKernelGGL(k_fd_plane<true>, dim3(nb), dim3(kPlaneWaves * kWave), lds, st, pa);
+  } else {
+    set_lds(reinterpret_cast<const void*>(k_fd_plane<false>), lds);
+    hipLaunchKernelGGL(k_fd_plane<false>, dim3(nb), dim3(kPlaneWaves * kWave), lds, st, pa);
+  }
+}
+
 // The three fast-diagonalisation passes: in -> tmp (plane transform), the z pass
 // with the eigenvalue division in place on tmp, tmp -> out (inverse plane transform, plus
 // add when given; with part also the partials of out . rr).  The strips of a plane are separate blocks, so a
@@ -626,26 +782,15 @@ void fd_passes(const double* in, double* out, const double* add, double* tmp,
                const FdOps& fd, Grid g, const CgState* cs, const double* rr, double* part,
                hipStream_t st) {
   const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const size_t nxp = (nx + 15) & ~15, nyp = (ny + 15) & ~15, nzp = (nz + 15) & ~15;
+  const size_t nzp = (nz + 15) & ~15;
   const size_t lzb = nzp * kZCols * sizeof(double);
   const size_t lzs = lzb + (size_t)nz * nz * sizeof(double);
   const size_t cap = kFdLdsCap;
   const int threads = kFdWaves * kWave;
-  const int ncs = (int)(nxp / 16);
-  const size_t lpl = (nyp * (nxp + 1) + nyp * 17 + nxp * 16) * sizeof(double);
-  const size_t lpls = lpl + (size_t)ny * ny * sizeof(double);
+  const int mode = fd_plane_mode(nx, ny);
   auto plane = [&](const double* src, double* dst, const double* ad, const double* r,
                    double* pt) {
-    const FdPlaneArgs pa{src, dst, fd.Sx, fd.Sy, nx, ny, r, pt, cs, ad};
-    if (lpls <= cap) {
-      set_lds(reinterpret_cast<const void*>(k_fd_plane<true>), lpls);
-      hipLaunchKernelGGL(k_fd_plane<true>, dim3(nz * ncs), dim3(kPlaneWaves * kWave), lpls,
-                         st, pa);
-    } else {
-      set_lds(reinterpret_cast<const void*>(k_fd_plane<false>), lpl);
-      hipLaunchKernelGGL(k_fd_plane<false>, dim3(nz * ncs), dim3(kPlaneWaves * kWave), lpl,
-                         st, pa);
-    }
+    launch_fd_plane(FdPlaneArgs{src, dst, fd.Sx, fd.Sy, nx, ny, r, pt, cs, ad}, nz, mode, st);
   };
   const int zblocks = (nx * ny + kZCols - 1) / kZCols;
   const FdZArgs za{tmp, fd.Sz, fd.lx, fd.ly, fd.lz, fd.mx, fd.my, fd.mz, nx, ny, nz, cs};
@@ -665,9 +810,9 @@ void fd_passes(const double* in, double* out, const double* add, double* tmp,
 void launch_fd_apply(const double* r, double* z, double* tmp, const FdOps& fd, Grid g,
                      const CgState* cs, double* part, hipStream_t st) {
   fd_passes(r, z, nullptr, tmp, fd, g, cs, r, part, st);
-  const int ncs = (g.nx + 15) / 16;
+  const int nb = fd_plane_blocks(g.nx, g.nz, fd_plane_mode(g.nx, g.ny));
   hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kBlock), 0, st,
-                     FinRzArgs{part, g.nz * ncs, const_cast<CgState*>(cs)});
+                     FinRzArgs{part, nb, const_cast<CgState*>(cs)});
 }
 
 // x = x0 + L^{-1} r: with r = b - L x0 this is the first iterate of the preconditioned CG
@@ -699,14 +844,12 @@ void launch_hartree_iter(double* x, double* r, const double* z, double* pa, doub
 int hartree_blocks(int n) { return cg_nblocks(n); }
 
 FdLaunch fd_launch(int nx, int ny, int nz) {
-  const size_t nxp = (nx + 15) & ~15, nyp = (ny + 15) & ~15, nzp = (nz + 15) & ~15;
+  const size_t nzp = (nz + 15) & ~15;
   FdLaunch l;
-  l.plane_bytes = (nyp * (nxp + 1) + nyp * 17 + nxp * 16) * sizeof(double);
-  l.plane_bytes_staged = l.plane_bytes + (size_t)ny * ny * sizeof(double);
+  l.plane_mode = fd_plane_mode(nx, ny);
   l.z_bytes = nzp * kZCols * sizeof(double);
   l.z_bytes_staged = l.z_bytes + (size_t)nz * nz * sizeof(double);
   l.cap = kFdLdsCap;
-  l.plane_blocks = nz * (int)(nxp / 16);
   l.z_blocks = (nx * ny + kZCols - 1) / kZCols;
   return l;
 }
@@ -732,9 +875,13 @@ void launch_fin_upd_batch(const BatchPtrs<FinUpdArgs>& b, hipStream_t st) {
 void launch_fin_rz_batch(const BatchPtrs<FinRzArgs>& b, hipStream_t st) {
   hipLaunchKernelGGL(k_fin_rz_batch, dim3(b.S), dim3(kBlock), 0, st, b);
 }
-void launch_fd_plane_batch(const BatchPtrs<FdPlaneArgs>& b, int blocks, bool staged, size_t lds,
+void launch_fd_plane_batch(const BatchPtrs<FdPlaneArgs>& b, int blocks, int mode, size_t lds,
                            hipStream_t st) {
-  if (staged) {
+  if (mode == kPlaneFull) {
+    set_lds(reinterpret_cast<const void*>(k_fd_plane_full_batch), lds);
+    hipLaunchKernelGGL(k_fd_plane_full_batch, dim3(blocks), dim3(kFullWaves * kWave), lds, st,
+                       b);
+  } else if (mode == kPlaneStripSy) {
     set_lds(reinterpret_cast<const void*>(k_fd_plane_batch<true>), lds);
     hipLaunchKernelGGL(k_fd_plane_batch<true>, dim3(blocks), dim3(kPlaneWaves * kWave), lds, st,
                        b);

@@ -1058,32 +1058,32 @@ void launch_trial_batch(const std::vector<BatchMember*>& g, hipStream_t st) {
   auto rt = table<CombineArgs>(g, R_RETRACT, cb, &tot);
   launch_combine_retract_batch<T>(rt, pp, tot, st);
   auto hb = [](const ks_system* s) { return hartree_blocks(s->n); };
-  bool stage_p = true, stage_z = true;
+  // one plane mode for the group (the slowest any member needs), LDS for the largest
+  int mode = kPlaneFull;
+  bool stage_z = true;
   for (auto* m : g) {
     const FdLaunch l = fd_launch(m->s->grid.nx, m->s->grid.ny, m->s->grid.nz);
-    stage_p = stage_p && l.plane_bytes_staged <= l.cap;
+    mode = std::min(mode, l.plane_mode);
     stage_z = stage_z && l.z_bytes_staged <= l.cap;
   }
   size_t lds_p = 0, lds_z = 0;
   for (auto* m : g) {
     const FdLaunch l = fd_launch(m->s->grid.nx, m->s->grid.ny, m->s->grid.nz);
-    lds_p = std::max(lds_p, stage_p ? l.plane_bytes_staged : l.plane_bytes);
+    lds_p = std::max(lds_p, fd_plane_bytes(m->s->grid.nx, m->s->grid.ny, mode));
     lds_z = std::max(lds_z, stage_z ? l.z_bytes_staged : l.z_bytes);
   }
-  auto pb = [](const ks_system* s) {
-    return fd_launch(s->grid.nx, s->grid.ny, s->grid.nz).plane_blocks;
-  };
+  auto pb = [mode](const ks_system* s) { return fd_plane_blocks(s->grid.nx, s->grid.nz, mode); };
   auto zb = [](const ks_system* s) {
     return fd_launch(s->grid.nx, s->grid.ny, s->grid.nz).z_blocks;
   };
   auto r0 = table<InitArgs>(g, R_RESID, hb, &tot);
   launch_init_batch(r0, tot, st);
   auto p1 = table<FdPlaneArgs>(g, R_PLANE1, pb, &tot);
-  launch_fd_plane_batch(p1, tot, stage_p, lds_p, st);
+  launch_fd_plane_batch(p1, tot, mode, lds_p, st);
   auto fz = table<FdZArgs>(g, R_FDZ, zb, &tot);
   launch_fd_z_batch(fz, tot, stage_z, lds_z, st);
   auto p2 = table<FdPlaneArgs>(g, R_PLANE2, pb, &tot);
-  launch_fd_plane_batch(p2, tot, stage_p, lds_p, st);
+  launch_fd_plane_batch(p2, tot, mode, lds_p, st);
   auto in = table<InitArgs>(g, R_INIT, hb, &tot);
   launch_init_batch(in, tot, st);
   launch_fin_init_batch(table<FinInitArgs>(g, R_FIN_INIT, one, &tot), st);

@@ -106,6 +106,27 @@ __device__ inline int xcd_remap(int b, int nb) {
   return x * q + (x < r ? x : r) + idx;
 }
 
+// Copies n values into LDS: value e (e < n) is load(e), stored by store(e, v).  Each
+// thread issues kB global loads before it stores any of them, so a block keeps kB loads
+// per thread in flight instead of waiting on each one.  load must be safe to call for
+// every e < n (clamp its address and select zero for padding).
+template <int kB, typename Load, typename Store>
+__device__ inline void lds_stage(int n, Load load, Store store) {
+  for (int e0 = threadIdx.x; e0 < n; e0 += kB * blockDim.x) {
+    double v[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const int e = e0 + u * blockDim.x;
+      v[u] = load(e < n ? e : e0);
+    }
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const int e = e0 + u * blockDim.x;
+      if (e < n) store(e, v[u]);
+    }
+  }
+}
+
 // Deterministic sum over a block of kBlock threads (fixed shuffle/LDS tree order).
 // sh must hold kBlock/kWave doubles.  Result valid in thread 0.
 __device__ inline double block_sum(double v, double* sh) {
@@ -310,9 +331,16 @@ struct FdZArgs {
 size_t hartree_part_doubles();
 // Launch shapes of the Hartree kernels for one system (blocks and dynamic LDS).
 int hartree_blocks(int n);
+// Plane-transform modes: 16-column strips (S_y read from L2), strips with S_y staged in
+// LDS, one whole plane per block.
+enum { kPlaneStrip = 0, kPlaneStripSy = 1, kPlaneFull = 2 };
+size_t fd_plane_bytes(int nx, int ny, int mode);
+int fd_plane_mode(int nx, int ny);  // the fastest mode whose LDS fits
+int fd_plane_blocks(int nx, int nz, int mode);
 struct FdLaunch {
-  size_t plane_bytes, plane_bytes_staged, z_bytes, z_bytes_staged, cap;
-  int plane_blocks, z_blocks;
+  int plane_mode;
+  size_t z_bytes, z_bytes_staged, cap;
+  int z_blocks;
 };
 FdLaunch fd_launch(int nx, int ny, int nz);
 void launch_init_batch(const BatchPtrs<InitArgs>& b, int blocks, hipStream_t st);
@@ -322,7 +350,7 @@ void launch_fin_dir_batch(const BatchPtrs<FinDirArgs>& b, hipStream_t st);
 void launch_upd_batch(const BatchPtrs<UpdArgs>& b, int blocks, hipStream_t st);
 void launch_fin_upd_batch(const BatchPtrs<FinUpdArgs>& b, hipStream_t st);
 void launch_fin_rz_batch(const BatchPtrs<FinRzArgs>& b, hipStream_t st);
-void launch_fd_plane_batch(const BatchPtrs<FdPlaneArgs>& b, int blocks, bool staged, size_t lds,
+void launch_fd_plane_batch(const BatchPtrs<FdPlaneArgs>& b, int blocks, int mode, size_t lds,
                            hipStream_t st);
 void launch_fd_z_batch(const BatchPtrs<FdZArgs>& b, int blocks, bool staged, size_t lds,
                        hipStream_t st);
