@@ -343,9 +343,18 @@ __device__ inline void comb_stage(const CombineArgs& a, double* lds) {
 
 // The first tile's loads are issued before the weights are staged, so they overlap the
 // staging and the barrier.
-template <typename T, int kT, bool kVec, bool kHasY, bool kHasC0, bool kRho, bool kGrad>
+// Gram tiles accumulated by the gradient combine with kGram2: X^T D (kT^2 tiles) and the
+// upper tiles of D^T D.
+template <int kT>
+struct Gram2Acc {
+  static constexpr int kN = kT * kT + kT * (kT + 1) / 2;
+  d4 t[kN];
+};
+
+template <typename T, int kT, bool kVec, bool kHasY, bool kHasC0, bool kRho, bool kGrad,
+          bool kGram2>
 __device__ inline void combine_tiles(const CombineArgs& a, double* lds, int t_beg, int t_end,
-                                     d4& sums) {
+                                     d4& sums, Gram2Acc<kT>& g2) {
   const T* aX = static_cast<const T*>(a.X);
   const T* aY = static_cast<const T*>(a.Y);
   const T* aC0 = static_cast<const T*>(a.C0);
@@ -394,6 +403,7 @@ __device__ inline void combine_tiles(const CombineArgs& a, double* lds, int t_be
     const bool rok = row < n;
     const size_t roff = (size_t)(rok ? row : 0) * ld;
     double sq = 0.0;
+    double dv[kS];  // the stored values (kGram2)
 #pragma unroll
     for (int j = 0; j < 2 * kT; ++j) {
       double v[2];
@@ -406,6 +416,7 @@ __device__ inline void combine_tiles(const CombineArgs& a, double* lds, int t_be
         if constexpr (kHasC0) x += f.c0.v[s];
         x = ok[e] ? (double)(T)x : 0.0;  // the epilogues see the stored value
         v[e] = x;
+        dv[s] = x;
         if constexpr (kRho) sq += x * x;
         if constexpr (kGrad) {
           const double sd = f.x.v[s] - f.xk.v[s];
@@ -435,6 +446,37 @@ __device__ inline void combine_tiles(const CombineArgs& a, double* lds, int t_be
       sq += __shfl_xor(sq, 32, kWave);
       if (q == 0 && rok) a.rho[row] = a.rho_scale * sq;
     }
+    if constexpr (kGram2) {
+      // X^T D and D^T D of the tile: the grid rows must be the contraction index, so the
+      // X and D tiles go through a wavefront-private LDS patch (row stride kPP + 1) and come
+      // back as Gram fragments (lane l: row 4 kk + l / 16, column 16 t + l % 16).
+      constexpr int kGS = kPP + 1;
+      double* xs = lds + (kHasY ? 2 : 1) * kPP * kPP + w * 2 * 16 * kGS;
+      double* ds = xs + 16 * kGS;
+#pragma unroll
+      for (int s2 = 0; s2 < kS; ++s2) {
+        xs[c * kGS + comb_col(s2, q)] = f.x.v[s2];
+        ds[c * kGS + comb_col(s2, q)] = dv[s2];
+      }
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        double fa[kT], fd[kT];
+#pragma unroll
+        for (int t = 0; t < kT; ++t) {
+          fa[t] = xs[(4 * kk + q) * kGS + 16 * t + c];
+          fd[t] = ds[(4 * kk + q) * kGS + 16 * t + c];
+        }
+        int g = 0;
+#pragma unroll
+        for (int ti = 0; ti < kT; ++ti)
+#pragma unroll
+          for (int tj = 0; tj < kT; ++tj, ++g) g2.t[g] = mfma16(fa[ti], fd[tj], g2.t[g]);
+#pragma unroll
+        for (int ti = 0; ti < kT; ++ti)
+#pragma unroll
+          for (int tj = ti; tj < kT; ++tj, ++g) g2.t[g] = mfma16(fd[ti], fd[tj], g2.t[g]);
+      }
+    }
   };
 
   int tile = t_beg + w;
@@ -448,7 +490,8 @@ __device__ inline void combine_tiles(const CombineArgs& a, double* lds, int t_be
   }
 }
 
-template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad>
+template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad,
+          bool kGram2 = false>
 __device__ inline void k_combine_body(const CombineArgs& a, int ks_bid, int ks_nb) {
   extern __shared__ double lds[];            // permuted weights Wp = [A; B]: kK x kPP
   __shared__ double sh[kBlock / kWave];
@@ -465,10 +508,36 @@ __device__ inline void k_combine_body(const CombineArgs& a, int ks_bid, int ks_n
                      reinterpret_cast<uintptr_t>(a.Xk) | reinterpret_cast<uintptr_t>(a.Dk)) &
                     kAl) == 0;
   d4 sums = {0.0, 0.0, 0.0, 0.0};
+  Gram2Acc<kT> g2;
+#pragma unroll
+  for (int t = 0; t < Gram2Acc<kT>::kN; ++t) g2.t[t] = d4{0.0, 0.0, 0.0, 0.0};
   if (vec)
-    combine_tiles<T, kT, true, kHasY, kHasC0, kRho, kGrad>(a, lds, t_beg, t_end, sums);
+    combine_tiles<T, kT, true, kHasY, kHasC0, kRho, kGrad, kGram2>(a, lds, t_beg, t_end, sums,
+                                                                   g2);
   else
-    combine_tiles<T, kT, false, kHasY, kHasC0, kRho, kGrad>(a, lds, t_beg, t_end, sums);
+    combine_tiles<T, kT, false, kHasY, kHasC0, kRho, kGrad, kGram2>(a, lds, t_beg, t_end, sums,
+                                                                    g2);
+  if constexpr (kGram2) {
+    // fixed-order sum over the block's waves, then this block's partial tiles (chunk lb)
+    constexpr int kPP = kT * 16;
+    double* red = lds + (kHasY ? 2 : 1) * kPP * kPP;
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    __syncthreads();  // every wave is done with its LDS patch
+#pragma unroll
+    for (int t = 0; t < Gram2Acc<kT>::kN; ++t) wave_reduce_tile(g2.t[t], red, w, lane);
+    if (w == 0) {
+      const int lr = lane / 16, lc = lane % 16;
+      int g = 0;
+#pragma unroll
+      for (int ti = 0; ti < kT; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < kT; ++tj) put_tile<kPP>(a.gram_part, lb, 1, ti, tj, g2.t[g++], lr, lc);
+#pragma unroll
+      for (int ti = 0; ti < kT; ++ti)
+#pragma unroll
+        for (int tj = ti; tj < kT; ++tj) put_tile<kPP>(a.gram_part, lb, 2, ti, tj, g2.t[g++], lr, lc);
+    }
+  }
   if (kGrad) {
     const double dd = block_sum(sums[0], sh);
     const double ss = block_sum(sums[1], sh);
@@ -484,16 +553,26 @@ __device__ inline void k_combine_body(const CombineArgs& a, int ks_bid, int ks_n
   }
 }
 
-template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad>
+template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad,
+          bool kGram2 = false>
 __global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
-  k_combine_body<T, kT, kHasY, kHasC0, kRho, kGrad>(a, blockIdx.x, gridDim.x);
+  k_combine_body<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2>(a, blockIdx.x, gridDim.x);
 }
 
-template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad>
+template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad,
+          bool kGram2 = false>
 __global__ __launch_bounds__(256) void k_combine_batch(BatchPtrs<CombineArgs> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_combine_body<T, kT, kHasY, kHasC0, kRho, kGrad>(*b.a[s], blockIdx.x - b.off[s],
-                                                    b.off[s + 1] - b.off[s]);
+  k_combine_body<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2>(*b.a[s], blockIdx.x - b.off[s],
+                                                            b.off[s + 1] - b.off[s]);
+}
+
+// LDS of a combine block: the weights, and with kGram2 the wavefronts' X and D patches (the
+// Gram reduction reuses them).
+template <int kT, bool kHasY, bool kGram2>
+constexpr size_t combine_lds_bytes() {
+  constexpr size_t kPP = kT * 16;
+  return ((kHasY ? 2 : 1) * kPP * kPP + (kGram2 ? 4 * 2 * 16 * (kPP + 1) : 0)) * sizeof(double);
 }
 
 void set_lds_attr(const void* k, size_t bytes) {
@@ -525,18 +604,18 @@ void launch_gram_t(const T* A, const T* B, int ld, int n, int p, int mask, doubl
   if (mask & kPBB) launch_gram_m<T, kT, 4>(A, B, ld, n, p, part, nchunks, st);
 }
 
-template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad>
+template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad,
+          bool kGram2 = false>
 void launch_combine_t(const CombineArgs& a, hipStream_t st) {
-  constexpr int kPP = kT * 16;
-  const size_t lds = (size_t)(kHasY ? 2 : 1) * kPP * kPP * sizeof(double);
+  constexpr size_t lds = combine_lds_bytes<kT, kHasY, kGram2>();
   // function-local static initialisation runs once even when several host threads launch
   static const bool attr = (set_lds_attr(reinterpret_cast<const void*>(
-                                k_combine<T, kT, kHasY, kHasC0, kRho, kGrad>),
+                                k_combine<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2>),
                                 lds),
                             true);
   (void)attr;
-  hipLaunchKernelGGL((k_combine<T, kT, kHasY, kHasC0, kRho, kGrad>), dim3(combine_blocks(a.n)),
-                     dim3(256), lds, st, a);
+  hipLaunchKernelGGL((k_combine<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2>),
+                     dim3(combine_blocks(a.n)), dim3(256), lds, st, a);
 }
 
 template <typename T, int kT>
@@ -546,6 +625,10 @@ void launch_combine_tt(const CombineArgs& a, hipStream_t st) {
   // the combinations the library uses
   if (y && !c0 && rho && !gr) return launch_combine_t<T, kT, true, false, true, false>(a, st);
   if (y && !c0 && !rho && !gr) return launch_combine_t<T, kT, true, false, false, false>(a, st);
+  if constexpr (kT <= 2) {
+    if (!y && c0 && !rho && gr && a.gram_part)
+      return launch_combine_t<T, kT, false, true, false, true, true>(a, st);
+  }
   if (!y && c0 && !rho && gr) return launch_combine_t<T, kT, false, true, false, true>(a, st);
   if (!y && c0 && !rho && !gr) return launch_combine_t<T, kT, false, true, false, false>(a, st);
   if (!y && !c0 && rho && !gr) return launch_combine_t<T, kT, false, false, true, false>(a, st);
@@ -586,7 +669,10 @@ int gram_chunks(int n, int pp) {
   return c < 1 ? 1 : c;
 }
 
-size_t gram_part_doubles(int n, int pp) { return (size_t)gram_chunks(n, pp) * 3 * pp * pp; }
+// partial tiles of the Gram launches and of the gradient combine's fused Gram tiles
+size_t gram_part_doubles(int n, int pp) {
+  return (size_t)std::max(gram_chunks(n, pp), combine_blocks(n)) * 3 * pp * pp;
+}
 
 void launch_gram(const void* A, const void* B, bool f32, int ld, int n, int p, int mask,
                  double* partials, int nchunks, hipStream_t st) {
@@ -653,9 +739,13 @@ void combine_batch_retract_t(const BatchPtrs<CombineArgs>& b, int blocks, hipStr
 
 template <typename T, int kT>
 void combine_batch_grad_t(const BatchPtrs<CombineArgs>& b, int blocks, hipStream_t st) {
-  constexpr int kPP = kT * 16;
-  const size_t lds = (size_t)kPP * kPP * sizeof(double);
-  hipLaunchKernelGGL((k_combine_batch<T, kT, false, true, false, true>), dim3(blocks),
+  constexpr size_t lds = combine_lds_bytes<kT, false, true>();
+  static const bool attr = (set_lds_attr(reinterpret_cast<const void*>(
+                                k_combine_batch<T, kT, false, true, false, true, true>),
+                                lds),
+                            true);
+  (void)attr;
+  hipLaunchKernelGGL((k_combine_batch<T, kT, false, true, false, true, true>), dim3(blocks),
                      dim3(256), lds, st, b);
 }
 

@@ -20,7 +20,7 @@ constexpr int kPartStride = 4096;  // >= blocks of every streaming kernel
 // argument records of the batched trial kernels: one 256-byte slot per kernel and parity
 enum Rec {
   R_QR, R_RETRACT, R_RESID, R_PLANE1, R_FDZ, R_PLANE2, R_INIT, R_FIN_INIT, R_XC, R_HX, R_GRAM1,
-  R_RED1, R_GRAD, R_GRAM2, R_RED2, R_FINISH, R_COUNT
+  R_RED1, R_GRAD, R_RED2, R_FINISH, R_COUNT
 };
 constexpr size_t kRecSlot = 256;
 constexpr size_t kRecBytes = 2 * R_COUNT * kRecSlot;
@@ -525,7 +525,9 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
   tbeg(s, KS_PH_SMALL);
   launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, mask1, s->gxg[idx], s->W, s->st);
   tend(s, KS_PH_SMALL);
-  // D = G - X (G^T X) with ||D||^2 and the BB sums; then (QR) the Gram blocks X^T D, D^T D
+  // D = G - X (G^T X) with ||D||^2, the BB sums and (QR) the Gram blocks X^T D, D^T D:
+  // up to 32 columns they come out of the same kernel, wider blocks take a Gram launch
+  const bool fused = want_gxd && s->pp <= 32;
   CombineArgs ca{};
   ca.X = Xs;
   ca.A = s->W;
@@ -534,6 +536,7 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
   ca.Xk = bb_ref >= 0 ? s->X[bb_ref] : Xs;
   ca.Dk = bb_ref >= 0 ? s->D[bb_ref] : s->D[idx];
   ca.pt = pt;
+  ca.gram_part = fused ? s->gram_part : nullptr;
   ca.f32 = s->f32;
   ca.ld = s->p;
   ca.n = s->n;
@@ -542,15 +545,15 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
   launch_combine(ca, s->st);
   tend(s, KS_PH_GRADIENT);
   const int mask2 = kGramAB | kGramBB;
-  if (want_gxd) {
+  if (want_gxd && !fused) {
     tbeg(s, KS_PH_GRAM);
     gram(s, Xs, s->D[idx], mask2);
     tend(s, KS_PH_GRAM);
   }
   tbeg(s, KS_PH_SMALL);
   if (want_gxd)
-    launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, mask2, s->gxd[idx], nullptr,
-                       s->st);
+    launch_gram_reduce(s->gram_part, fused ? combine_blocks(s->n) : s->gram_nchunks, s->pp,
+                       mask2, s->gxd[idx], nullptr, s->st);
   int nblk[kMaxScalarSlots] = {};
   nblk[SL_KIN] = nblk[SL_EXT] = hx_blocks(s->n, s->p);
   nblk[SL_EH] = nblk[SL_EX] = scalar_blocks(s->n);
@@ -974,15 +977,13 @@ void fill_typed(ks_system* s, std::vector<char>& buf, int c) {
   gd.Xk = s->X[c];
   gd.Dk = s->D[c];
   gd.pt = pt;
+  gd.gram_part = s->gram_part;  // X^T D, D^T D from the same kernel
   gd.ld = s->p;
   gd.n = s->n;
   gd.p = s->p;
   gd.f32 = s->f32;
   put_rec(buf, c, R_GRAD, gd);
-  put_rec(buf, c, R_GRAM2, GramArgs<T>{static_cast<const T*>(s->X[t]),
-                                       static_cast<const T*>(s->D[t]), s->p, s->n, s->p,
-                                       s->gram_part});
-  put_rec(buf, c, R_RED2, GramReduceArgs{s->gram_part, s->gram_nchunks, s->pp,
+  put_rec(buf, c, R_RED2, GramReduceArgs{s->gram_part, combine_blocks(s->n), s->pp,
                                          kGramAB | kGramBB, s->gxd[t], nullptr});
 }
 
@@ -1101,8 +1102,6 @@ void launch_trial_batch(const std::vector<BatchMember*>& g, hipStream_t st) {
   launch_gram_reduce_batch(r1, tot, st);
   auto gd = table<CombineArgs>(g, R_GRAD, cb, &tot);
   launch_combine_grad_batch<T>(gd, pp, tot, st);
-  auto g2 = table<GramArgs<T>>(g, R_GRAM2, gb, &tot);
-  launch_gram_batch<T>(g2, pp, kGramAB | kGramBB, tot, st);
   auto r2 = table<GramReduceArgs>(g, R_RED2, rb, &tot);
   launch_gram_reduce_batch(r2, tot, st);
   launch_finish_eval_batch(table<FinishEvalArgs>(g, R_FINISH, one, &tot), st);

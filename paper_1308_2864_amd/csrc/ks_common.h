@@ -443,6 +443,7 @@ struct CombineArgs {
   // optional BB/gradient epilogue: out is D_t; uses Xt (= X), Xk, Dk
   const void* Xk; const void* Dk;
   Partials pt;                          // slots SL_DD.. SL_YY (by value)
+  double* gram_part;                    // optional (p_p <= 32): partial X^T D, D^T D tiles
   int ld, n, p;
   bool f32;
 };
@@ -458,6 +459,7 @@ int gram_reduce_blocks(int pp);
 template <typename T>
 void launch_combine_retract_batch(const BatchPtrs<CombineArgs>& b, int pp, int blocks,
                                   hipStream_t st);
+// (the gradient form also accumulates the Gram tiles X^T D, D^T D into gram_part)
 template <typename T>
 void launch_combine_grad_batch(const BatchPtrs<CombineArgs>& b, int pp, int blocks,
                                hipStream_t st);
