@@ -273,9 +273,9 @@ def main():
     phases = sysg.ks_read_timers(reset=True)
     pb = phase_bytes(spec.n, spec.p)
     single = [k for k in pb if phases[k][1] > 0]
-    # a phase may launch its kernel more than once per evaluation (the Gram phase forms
-    # [X, G] and [X, D] products with two launches of different kernels): rank phases by
-    # the time of one launch sequence per evaluation
+    # a phase may launch its kernel more than once per evaluation (beyond 32 columns the
+    # Gram phase forms [X, G] and [X, D] products with two launches): rank phases by the
+    # time of one launch sequence per evaluation
     evals = max(phases["xc"][1], 1)
     dom = max(single, key=lambda k: phases[k][0] / max(phases[k][1] / evals, 1.0))
     # the timed region times only that kernel (two events per launch of it)
@@ -323,7 +323,7 @@ def main():
     avg_s = ms * 1e-3 / cnt
     achieved = pb[dom] / avg_s / 1e9
     kernel_names = {"hamiltonian": "k_hx<double,true>", "gram": "k_gram<double,2,3>",
-                    "gradient": "k_combine<double,2,false,true,false,true,false>",
+                    "gradient": "k_combine<double,2,false,true,false,true,true>",
                     "retract": "k_combine<double,2,true,false,true,false,false>"}
     traffic = pmc_traffic(kernel_names[dom]) if args.hartree == "pcg_fd" else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
