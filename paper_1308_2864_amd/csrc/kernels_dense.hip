@@ -201,12 +201,13 @@ __global__ __launch_bounds__(256) void k_gram_batch(BatchPtrs<GramArgs<T>> b) {
 }
 
 
-// out[prod][i][j] = sum over chunks in increasing order, for the products in mask; the
-// other products are left untouched.  Block = 4 output slots x 16 chunk lanes (one
-// wavefront); chunk lane c sums chunks c, c+16, ... (loaded kRedU at a time) and the 16
-// lane sums are added in lane order.  Symmetric products read the mirrored upper tile.
-// With W != nullptr also W = -(product 1)^T.
+// out[prod][i][j] = sum over the chunk partials, for the products in mask; the other
+// products are left untouched.  Block = 4 output slots x kRedLanes chunk lanes; chunk lane c
+// sums chunks c, c + kRedLanes, ... (loaded kRedU at a time, all in flight together) and the
+// lane sums are added in lane order, so the result is the same on every run.  Symmetric
+// products read the mirrored upper tile.  With W != nullptr also W = -(product 1)^T.
 constexpr int kRedSlots = 4;
+constexpr int kRedLanes = 64;
 constexpr int kRedU = 8;
 
 __device__ inline void k_gram_reduce_body(const GramReduceArgs& ka, int ks_bid, int ks_nb) {
@@ -218,7 +219,7 @@ __device__ inline void k_gram_reduce_body(const GramReduceArgs& ka, int ks_bid, 
   double* __restrict__ W = ka.W;
   (void)ks_nb;
 
-  __shared__ double red[kRedSlots][17];
+  __shared__ double red[kRedSlots][kRedLanes + 1];
   const int sl = threadIdx.x % kRedSlots, cl = threadIdx.x / kRedSlots;
   const int per = pp * pp;
   const int e = ks_bid * kRedSlots + sl;
@@ -235,17 +236,17 @@ __device__ inline void k_gram_reduce_body(const GramReduceArgs& ka, int ks_bid, 
       const int src = (prod != 1 && (i / 16) > (j / 16)) ? j * pp + i : ij;
       const double* q = part + (size_t)prod * per + src;
       const size_t cs = (size_t)3 * per;
-      for (int c0 = cl; c0 < nchunks; c0 += 16 * kRedU) {
+      for (int c0 = cl; c0 < nchunks; c0 += kRedLanes * kRedU) {
         double v[kRedU];
 #pragma unroll
         for (int u = 0; u < kRedU; ++u) {
-          const int c = c0 + 16 * u;
+          const int c = c0 + kRedLanes * u;
           const double x = q[(size_t)(c < nchunks ? c : 0) * cs];
           v[u] = c < nchunks ? x : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < kRedU; ++u)
-          if (c0 + 16 * u < nchunks) s += v[u];
+          if (c0 + kRedLanes * u < nchunks) s += v[u];
       }
     }
   }
@@ -253,17 +254,18 @@ __device__ inline void k_gram_reduce_body(const GramReduceArgs& ka, int ks_bid, 
   __syncthreads();
   if (cl == 0 && e < 3 * per && live) {
     double t = 0.0;
-    for (int c = 0; c < 16; ++c) t += red[sl][c];
+    for (int c = 0; c < kRedLanes; ++c) t += red[sl][c];
     out[e] = t;
     if (W && prod == 1) W[j * pp + i] = -t;
   }
 }
 
-__global__ __launch_bounds__(64) void k_gram_reduce(GramReduceArgs ka) {
+__global__ __launch_bounds__(kRedSlots * kRedLanes) void k_gram_reduce(GramReduceArgs ka) {
   k_gram_reduce_body(ka, blockIdx.x, gridDim.x);
 }
 
-__global__ __launch_bounds__(64) void k_gram_reduce_batch(BatchPtrs<GramReduceArgs> b) {
+__global__ __launch_bounds__(kRedSlots * kRedLanes) void k_gram_reduce_batch(
+    BatchPtrs<GramReduceArgs> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
   k_gram_reduce_body(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
 }
@@ -352,7 +354,7 @@ struct Gram2Acc {
 };
 
 template <typename T, int kT, bool kVec, bool kHasY, bool kHasC0, bool kRho, bool kGrad,
-          bool kGram2>
+          bool kGram2, bool kUpper>
 __device__ inline void combine_tiles(const CombineArgs& a, double* lds, int t_beg, int t_end,
                                      d4& sums, Gram2Acc<kT>& g2) {
   const T* aX = static_cast<const T*>(a.X);
@@ -386,18 +388,23 @@ __device__ inline void combine_tiles(const CombineArgs& a, double* lds, int t_be
     d4 acc[kT];
 #pragma unroll
     for (int t = 0; t < kT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+    // kUpper: A and B are upper triangular (the QR weights R^{-1}, -tau R^{-1}), so output
+    // tile t only needs the steps whose rows 8 (s >> 1) .. + 7 reach its columns
+    // 16 t .. 16 t + 15, i.e. s < 4 (t + 1); the skipped products are exact zeros.
 #pragma unroll
     for (int s = 0; s < kS; ++s) {
 #pragma unroll
       for (int t = 0; t < kT; ++t)
-        acc[t] = mfma16(lds[(4 * s + q) * kPP + t * 16 + c], f.x.v[s], acc[t]);
+        if (!kUpper || s < 4 * (t + 1))
+          acc[t] = mfma16(lds[(4 * s + q) * kPP + t * 16 + c], f.x.v[s], acc[t]);
     }
     if constexpr (kHasY) {
 #pragma unroll
       for (int s = 0; s < kS; ++s) {
 #pragma unroll
         for (int t = 0; t < kT; ++t)
-          acc[t] = mfma16(lds[kPP * kPP + (4 * s + q) * kPP + t * 16 + c], f.y.v[s], acc[t]);
+          if (!kUpper || s < 4 * (t + 1))
+            acc[t] = mfma16(lds[kPP * kPP + (4 * s + q) * kPP + t * 16 + c], f.y.v[s], acc[t]);
       }
     }
     const bool rok = row < n;
@@ -491,7 +498,7 @@ __device__ inline void combine_tiles(const CombineArgs& a, double* lds, int t_be
 }
 
 template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad,
-          bool kGram2 = false>
+          bool kGram2 = false, bool kUpper = false>
 __device__ inline void k_combine_body(const CombineArgs& a, int ks_bid, int ks_nb) {
   extern __shared__ double lds[];            // permuted weights Wp = [A; B]: kK x kPP
   __shared__ double sh[kBlock / kWave];
@@ -512,10 +519,10 @@ __device__ inline void k_combine_body(const CombineArgs& a, int ks_bid, int ks_n
 #pragma unroll
   for (int t = 0; t < Gram2Acc<kT>::kN; ++t) g2.t[t] = d4{0.0, 0.0, 0.0, 0.0};
   if (vec)
-    combine_tiles<T, kT, true, kHasY, kHasC0, kRho, kGrad, kGram2>(a, lds, t_beg, t_end, sums,
+    combine_tiles<T, kT, true, kHasY, kHasC0, kRho, kGrad, kGram2, kUpper>(a, lds, t_beg, t_end, sums,
                                                                    g2);
   else
-    combine_tiles<T, kT, false, kHasY, kHasC0, kRho, kGrad, kGram2>(a, lds, t_beg, t_end, sums,
+    combine_tiles<T, kT, false, kHasY, kHasC0, kRho, kGrad, kGram2, kUpper>(a, lds, t_beg, t_end, sums,
                                                                     g2);
   if constexpr (kGram2) {
     // fixed-order sum over the block's waves, then this block's partial tiles (chunk lb)
@@ -554,16 +561,16 @@ __device__ inline void k_combine_body(const CombineArgs& a, int ks_bid, int ks_n
 }
 
 template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad,
-          bool kGram2 = false>
+          bool kGram2 = false, bool kUpper = false>
 __global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
-  k_combine_body<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2>(a, blockIdx.x, gridDim.x);
+  k_combine_body<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2, kUpper>(a, blockIdx.x, gridDim.x);
 }
 
 template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad,
-          bool kGram2 = false>
+          bool kGram2 = false, bool kUpper = false>
 __global__ __launch_bounds__(256) void k_combine_batch(BatchPtrs<CombineArgs> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_combine_body<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2>(*b.a[s], blockIdx.x - b.off[s],
+  k_combine_body<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2, kUpper>(*b.a[s], blockIdx.x - b.off[s],
                                                             b.off[s + 1] - b.off[s]);
 }
 
@@ -605,16 +612,16 @@ void launch_gram_t(const T* A, const T* B, int ld, int n, int p, int mask, doubl
 }
 
 template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad,
-          bool kGram2 = false>
+          bool kGram2 = false, bool kUpper = false>
 void launch_combine_t(const CombineArgs& a, hipStream_t st) {
   constexpr size_t lds = combine_lds_bytes<kT, kHasY, kGram2>();
   // function-local static initialisation runs once even when several host threads launch
   static const bool attr = (set_lds_attr(reinterpret_cast<const void*>(
-                                k_combine<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2>),
+                                k_combine<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2, kUpper>),
                                 lds),
                             true);
   (void)attr;
-  hipLaunchKernelGGL((k_combine<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2>),
+  hipLaunchKernelGGL((k_combine<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2, kUpper>),
                      dim3(combine_blocks(a.n)), dim3(256), lds, st, a);
 }
 
@@ -623,6 +630,8 @@ void launch_combine_tt(const CombineArgs& a, hipStream_t st) {
   const bool y = a.Y != nullptr, c0 = a.C0 != nullptr, rho = a.rho != nullptr,
              gr = a.Xk != nullptr;
   // the combinations the library uses
+  if (y && !c0 && rho && !gr && a.upper)
+    return launch_combine_t<T, kT, true, false, true, false, false, true>(a, st);
   if (y && !c0 && rho && !gr) return launch_combine_t<T, kT, true, false, true, false>(a, st);
   if (y && !c0 && !rho && !gr) return launch_combine_t<T, kT, true, false, false, false>(a, st);
   if constexpr (kT <= 2) {
@@ -686,7 +695,8 @@ void launch_gram(const void* A, const void* B, bool f32, int ld, int n, int p, i
 
 void launch_gram_reduce(const double* partials, int nchunks, int pp, int mask, double* out,
                         double* W, hipStream_t st) {
-  hipLaunchKernelGGL(k_gram_reduce, dim3(gram_reduce_blocks(pp)), dim3(16 * kRedSlots), 0, st,
+  hipLaunchKernelGGL(k_gram_reduce, dim3(gram_reduce_blocks(pp)), dim3(kRedSlots * kRedLanes), 0,
+                     st,
                      GramReduceArgs{partials, nchunks, pp, mask, out, W});
 }
 
@@ -726,15 +736,16 @@ template void launch_gram_batch<float>(const BatchPtrs<GramArgs<float>>&, int, i
 int gram_reduce_blocks(int pp) { return (3 * pp * pp + kRedSlots - 1) / kRedSlots; }
 
 void launch_gram_reduce_batch(const BatchPtrs<GramReduceArgs>& b, int blocks, hipStream_t st) {
-  hipLaunchKernelGGL(k_gram_reduce_batch, dim3(blocks), dim3(16 * kRedSlots), 0, st, b);
+  hipLaunchKernelGGL(k_gram_reduce_batch, dim3(blocks), dim3(kRedSlots * kRedLanes), 0, st,
+                     b);
 }
 
 template <typename T, int kT>
 void combine_batch_retract_t(const BatchPtrs<CombineArgs>& b, int blocks, hipStream_t st) {
-  constexpr int kPP = kT * 16;
-  const size_t lds = (size_t)2 * kPP * kPP * sizeof(double);
-  hipLaunchKernelGGL((k_combine_batch<T, kT, true, false, true, false>), dim3(blocks),
-                     dim3(256), lds, st, b);
+  constexpr size_t lds = combine_lds_bytes<kT, true, false>();
+  // batches run the QR retraction: upper triangular weights
+  hipLaunchKernelGGL((k_combine_batch<T, kT, true, false, true, false, false, true>),
+                     dim3(blocks), dim3(256), lds, st, b);
 }
 
 template <typename T, int kT>

@@ -12,6 +12,8 @@ namespace ks {
 
 namespace {
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
 constexpr int kMaxStreamBlocks = 4096;  // blocks of the grid-stride streaming kernels
 
 inline int stream_blocks(size_t work) {
@@ -262,19 +264,160 @@ __device__ inline void hx_items(const HxArgs<T>& ka, int lb, int nblk, double& k
   }
 }
 
-template <typename T, bool kEnergy>
+// The Hamiltonian with the Gram blocks X^T X and X^T G of the same pass (p = 32, column
+// pairs, ld = 32).  A wavefront takes 4 grid columns x 16 column pairs, so on every plane
+// its lanes hold a 4-point slice of X and of G exactly as FP64 MFMA fragments with the grid
+// points as the contraction index: lane l holds point l / 16, columns 2 (l % 16) + e.  The
+// even and odd columns form two 16-column tiles each, so X^T G and X^T X are 4 + 4 tiles per
+// plane step (entry (m, n) of tile (a, b) is column pair (2 m + a, 2 n + b)).  The loop is
+// uniform over the wavefront (MFMAs need every lane); lanes past the grid or the z chunk
+// contribute zeros.
+struct HxGramAcc {
+  d4 xg[4], xx[4];  // tiles (a, b) at index 2 a + b
+};
+
+template <typename T>
+__device__ inline void hx_gram_items(const HxArgs<T>& ka, int lb, int nblk, double& kin,
+                                     double& ext, HxGramAcc& g) {
+  constexpr int kW = 2, pw = 16;
+  const T* __restrict__ X = ka.X;
+  constexpr int ld = 2 * pw;
+  T* __restrict__ Y = ka.Y;
+  const double* __restrict__ veff = ka.veff;
+  const double* __restrict__ vext = ka.vext;
+  const Grid gr = ka.gr;
+  const int nx = gr.nx, ny = gr.ny, nz = gr.nz;
+  const int nzc = (nz + kHxChunk - 1) / kHxChunk;
+  const size_t work = (size_t)nx * ny * pw * nzc;
+  const ptrdiff_t sy = (ptrdiff_t)nx * ld, sz = (ptrdiff_t)nx * ny * ld;
+  const double ih2 = gr.inv_h2, scale = ka.scale;
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  for (size_t tw = ((size_t)lb * (kBlock / kWave) + w) * kWave; tw < work;
+       tw += (size_t)nblk * kBlock) {
+    const size_t t0 = tw + lane;
+    const bool live = t0 < work;
+    const size_t t = live ? t0 : tw;
+    const int c = (int)(t % (unsigned)pw) * kW;
+    size_t r = t / (unsigned)pw;
+    const int i = (int)(r % nx);
+    r /= nx;
+    const int j = (int)(r % ny);
+    const int k0 = (int)(r / ny) * kHxChunk;
+    const int k1 = min(k0 + kHxChunk, nz);
+    const T* col = X + (ptrdiff_t)(i + (size_t)nx * j) * ld + c;
+    double zc[kHxChunk + 2][kW];
+#pragma unroll
+    for (int u = 0; u < kHxChunk + 2; ++u) {
+      const int k = k0 - 1 + u;
+      const bool ok = k >= 0 && k < nz;
+      hx_load<T, kW>(col + (ok ? k * sz : 0), ok, zc[u]);
+    }
+    const bool hxm = i > 0, hxp = i < nx - 1, hym = j > 0, hyp = j < ny - 1;
+#pragma unroll
+    for (int u = 0; u < kHxChunk; ++u) {
+      const int k = k0 + u;
+      const bool ok = live && k < k1;
+      const int kk = ok ? k : k0;
+      const T* xp = col + kk * sz;
+      double a[kW], b[kW], cc[kW], d[kW];
+      hx_load<T, kW>(xp - (hxm ? ld : 0), hxm, a);
+      hx_load<T, kW>(xp + (hxp ? ld : 0), hxp, b);
+      hx_load<T, kW>(xp - (hym ? sy : 0), hym, cc);
+      hx_load<T, kW>(xp + (hyp ? sy : 0), hyp, d);
+      const size_t gp = i + (size_t)nx * (j + (size_t)ny * kk);
+      const double ve = veff[gp];
+      const double vx = vext[gp];
+      double xo[kW], go[kW];
+      typename HxVec<T, kW>::type wv;
+#pragma unroll
+      for (int e = 0; e < kW; ++e) {
+        const double cur = zc[u + 1][e];
+        const double nb = a[e] + b[e] + cc[e] + d[e] + zc[u][e] + zc[u + 2][e];
+        const double lx = (6.0 * cur - nb) * ih2;
+        const T o = (T)(scale * (0.5 * lx + ve * cur));
+        wv[e] = o;
+        if (ok) {
+          kin += cur * lx;
+          ext += vx * cur * cur;
+        }
+        xo[e] = ok ? cur : 0.0;
+        go[e] = ok ? (double)o : 0.0;
+      }
+      if (ok) *reinterpret_cast<typename HxVec<T, kW>::type*>(Y + gp * ld + c) = wv;
+#pragma unroll
+      for (int ea = 0; ea < kW; ++ea)
+#pragma unroll
+        for (int eb = 0; eb < kW; ++eb) {
+          g.xg[2 * ea + eb] = __builtin_amdgcn_mfma_f64_16x16x4f64(xo[ea], go[eb],
+                                                                    g.xg[2 * ea + eb], 0, 0, 0);
+          g.xx[2 * ea + eb] = __builtin_amdgcn_mfma_f64_16x16x4f64(xo[ea], xo[eb],
+                                                                    g.xx[2 * ea + eb], 0, 0, 0);
+        }
+    }
+  }
+}
+
+// Fixed-order sum of one 16 x 16 tile over the four wavefronts of a block (waves 1..3 park
+// it in LDS, wave 0 adds them in order).
+__device__ inline void hx_reduce_tile(d4& v, double* red, int w, int lane) {
+  if (w > 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) red[((w - 1) * 4 + r) * kWave + lane] = v[r];
+  }
+  __syncthreads();
+  if (w == 0) {
+#pragma unroll
+    for (int ww = 0; ww < 3; ++ww)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[r] += red[(ww * 4 + r) * kWave + lane];
+  }
+  __syncthreads();
+}
+
+template <typename T, bool kEnergy, bool kGram>
 __device__ inline void k_hx_body(const HxArgs<T>& ka, int ks_bid, int ks_nb) {
   __shared__ double sh[kBlock / kWave];
   const int lb = xcd_remap(ks_bid, ks_nb);
   double kin = 0.0, ext = 0.0;
-  constexpr uintptr_t kAl = 2 * sizeof(T) - 1;
-  const bool vec = ((ka.p | ka.ldx | ka.ldy) & 1) == 0 &&
-                   ((reinterpret_cast<uintptr_t>(ka.X) | reinterpret_cast<uintptr_t>(ka.Y)) &
-                    kAl) == 0;
-  if (vec)
-    hx_items<T, kEnergy, 2>(ka, lb, ks_nb, kin, ext);
-  else
-    hx_items<T, kEnergy, 1>(ka, lb, ks_nb, kin, ext);
+  if constexpr (kGram) {
+    __shared__ double red[3 * 4 * kWave];
+    HxGramAcc g;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) g.xg[q] = g.xx[q] = d4{0.0, 0.0, 0.0, 0.0};
+    hx_gram_items<T>(ka, lb, ks_nb, kin, ext, g);
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      hx_reduce_tile(g.xg[q], red, w, lane);
+      hx_reduce_tile(g.xx[q], red, w, lane);
+    }
+    if (w == 0) {
+      // tile (a, b), lane (lr, lc), register r: entry (2 (lr + 4 r) + a, 2 lc + b)
+      constexpr int pp = 32;
+      double* o0 = ka.gram_part + ((size_t)lb * 3 + 0) * pp * pp;  // X^T X
+      double* o1 = ka.gram_part + ((size_t)lb * 3 + 1) * pp * pp;  // X^T G
+      const int lr = lane / 16, lc = lane % 16;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ea = q / 2, eb = q % 2;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 2 * (lr + 4 * r) + ea, col = 2 * lc + eb;
+          o0[row * pp + col] = g.xx[q][r];
+          o1[row * pp + col] = g.xg[q][r];
+        }
+      }
+    }
+  } else {
+    constexpr uintptr_t kAl = 2 * sizeof(T) - 1;
+    const bool vec = ((ka.p | ka.ldx | ka.ldy) & 1) == 0 &&
+                     ((reinterpret_cast<uintptr_t>(ka.X) | reinterpret_cast<uintptr_t>(ka.Y)) &
+                      kAl) == 0;
+    if (vec)
+      hx_items<T, kEnergy, 2>(ka, lb, ks_nb, kin, ext);
+    else
+      hx_items<T, kEnergy, 1>(ka, lb, ks_nb, kin, ext);
+  }
   if (kEnergy) {
     kin = block_sum(kin, sh);
     ext = block_sum(ext, sh);
@@ -283,15 +426,15 @@ __device__ inline void k_hx_body(const HxArgs<T>& ka, int ks_bid, int ks_nb) {
   }
 }
 
-template <typename T, bool kEnergy>
+template <typename T, bool kEnergy, bool kGram = false>
 __global__ __launch_bounds__(256) void k_hx(HxArgs<T> ka) {
-  k_hx_body<T, kEnergy>(ka, blockIdx.x, gridDim.x);
+  k_hx_body<T, kEnergy, kGram>(ka, blockIdx.x, gridDim.x);
 }
 
-template <typename T, bool kEnergy>
+template <typename T, bool kEnergy, bool kGram = false>
 __global__ __launch_bounds__(256) void k_hx_batch(BatchPtrs<HxArgs<T>> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_hx_body<T, kEnergy>(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+  k_hx_body<T, kEnergy, kGram>(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
 }
 
 
@@ -348,23 +491,38 @@ void launch_xc(const double* rho, const double* vh, const double* vext, double* 
 
 template <typename T>
 void launch_hx(const T* X, int ldx, T* Y, int ldy, const double* veff, const double* vext,
-               Grid g, int p, double scale, Partials* pt, hipStream_t st) {
+               Grid g, int p, double scale, Partials* pt, double* gram_part, hipStream_t st) {
+  if (gram_part) {
+    hipLaunchKernelGGL((k_hx<T, true, true>), dim3(hx_gram_blocks(g.n)), dim3(kBlock), 0, st,
+                       HxArgs<T>{X, ldx, Y, ldy, veff, vext, g, p, scale, *pt, gram_part});
+    return;
+  }
   const int nb = hx_blocks(g.n, p);
   if (pt) {
     hipLaunchKernelGGL((k_hx<T, true>), dim3(nb), dim3(kBlock), 0, st,
-                       HxArgs<T>{X, ldx, Y, ldy, veff, vext, g, p, scale, *pt});
+                       HxArgs<T>{X, ldx, Y, ldy, veff, vext, g, p, scale, *pt, nullptr});
   } else {
     Partials none{nullptr, 0};
     hipLaunchKernelGGL((k_hx<T, false>), dim3(nb), dim3(kBlock), 0, st,
-                       HxArgs<T>{X, ldx, Y, ldy, veff, vext, g, p, scale, none});
+                       HxArgs<T>{X, ldx, Y, ldy, veff, vext, g, p, scale, none, nullptr});
   }
 }
 template void launch_hx<double>(const double*, int, double*, int, const double*,
-                                const double*, Grid, int, double, Partials*, hipStream_t);
+                                const double*, Grid, int, double, Partials*, double*,
+                                hipStream_t);
 template void launch_hx<float>(const float*, int, float*, int, const double*, const double*,
-                               Grid, int, double, Partials*, hipStream_t);
+                               Grid, int, double, Partials*, double*, hipStream_t);
 
 int hx_blocks(int n, int p) { return stream_blocks((size_t)n * p / (2 * kHxChunk) + 1); }
+
+// Blocks of the Hamiltonian that also forms the Gram blocks of [X, G]: as many as the Gram
+// launch would use (each block writes one partial tile set).
+int hx_gram_blocks(int n) {
+  const int c = (n + 63) / 64;
+  return c < 1 ? 1 : (c > 512 ? 512 : c);
+}
+
+bool hx_fuses_gram(int p) { return p == 32; }
 
 
 void launch_xc_batch(const BatchPtrs<XcArgs>& b, int blocks, hipStream_t st) {
@@ -372,10 +530,14 @@ void launch_xc_batch(const BatchPtrs<XcArgs>& b, int blocks, hipStream_t st) {
 }
 
 template <typename T>
-void launch_hx_batch(const BatchPtrs<HxArgs<T>>& b, int blocks, hipStream_t st) {
-  hipLaunchKernelGGL((k_hx_batch<T, true>), dim3(blocks), dim3(kBlock), 0, st, b);
+void launch_hx_batch(const BatchPtrs<HxArgs<T>>& b, int blocks, bool gram, hipStream_t st) {
+  if (gram)
+    hipLaunchKernelGGL((k_hx_batch<T, true, true>), dim3(blocks), dim3(kBlock), 0, st, b);
+  else
+    hipLaunchKernelGGL((k_hx_batch<T, true>), dim3(blocks), dim3(kBlock), 0, st, b);
 }
-template void launch_hx_batch<double>(const BatchPtrs<HxArgs<double>>&, int, hipStream_t);
-template void launch_hx_batch<float>(const BatchPtrs<HxArgs<float>>&, int, hipStream_t);
+template void launch_hx_batch<double>(const BatchPtrs<HxArgs<double>>&, int, bool,
+                                      hipStream_t);
+template void launch_hx_batch<float>(const BatchPtrs<HxArgs<float>>&, int, bool, hipStream_t);
 
 }  // namespace ks

@@ -206,12 +206,12 @@ __global__ void k_qr_factor(const double* __restrict__ xx, const double* __restr
 }
 
 // Element-parallel variant for p <= P (P = 16, 32, 64): the P x P matrix Y^T Y lives in
-// registers, one element per thread (four per thread for P = 64), and both the
+// registers, a few elements per thread (qr_threads threads), and both the
 // right-looking Cholesky and the back substitution for R^{-1} run as p rank-1 steps in
 // which every thread updates its own elements; a step costs two barriers instead of a
 // serial loop over a column.  Rows/columns k are broadcast through LDS, double-buffered
 // by step parity.
-template <int P>
+template <int P, int kThreads>
 __device__ inline void k_qr_factor_2d_body(const QrFactor2dArgs& ka, int ks_bid, int ks_nb) {
   const double* __restrict__ xx = ka.xx;
   const double* __restrict__ gxd = ka.gxd;
@@ -224,8 +224,8 @@ __device__ inline void k_qr_factor_2d_body(const QrFactor2dArgs& ka, int ks_bid,
   (void)ks_bid;
   (void)ks_nb;
 
-  constexpr int kT = P * P < 1024 ? P * P : 1024;  // threads
-  constexpr int kE = P * P / kT;                   // elements per thread
+  constexpr int kT = kThreads;       // threads
+  constexpr int kE = P * P / kT;     // elements per thread
   __shared__ double row[2][P];
   __shared__ double dg[P];
   __shared__ double Rs[P][P + 1];
@@ -312,15 +312,25 @@ __device__ inline void k_qr_factor_2d_body(const QrFactor2dArgs& ka, int ks_bid,
   }
 }
 
+// Threads of the factor block for P: one element per thread up to 32 x 32 (measured on
+// P = 32: 1024 threads of one element, 19.5 us, beat 256 threads of four, 31 us), four
+// per thread at P = 64.
 template <int P>
-__global__ __launch_bounds__(1024) void k_qr_factor_2d(QrFactor2dArgs ka) {
-  k_qr_factor_2d_body<P>(ka, blockIdx.x, gridDim.x);
+constexpr int qr_threads() {
+  return P * P < 1024 ? P * P : 1024;
 }
 
 template <int P>
-__global__ __launch_bounds__(1024) void k_qr_factor_2d_batch(BatchPtrs<QrFactor2dArgs> b) {
+__global__ __launch_bounds__(qr_threads<P>()) void k_qr_factor_2d(QrFactor2dArgs ka) {
+  k_qr_factor_2d_body<P, qr_threads<P>()>(ka, blockIdx.x, gridDim.x);
+}
+
+template <int P>
+__global__ __launch_bounds__(qr_threads<P>()) void k_qr_factor_2d_batch(
+    BatchPtrs<QrFactor2dArgs> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_qr_factor_2d_body<P>(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+  k_qr_factor_2d_body<P, qr_threads<P>()>(*b.a[s], blockIdx.x - b.off[s],
+                                          b.off[s + 1] - b.off[s]);
 }
 
 
@@ -487,19 +497,40 @@ __device__ inline void k_finish_eval_body(const FinishEvalArgs& ka, int ks_bid, 
 #pragma unroll
     for (int sl = 0; sl < SL_COUNT; ++sl) v[sl] += (i < nb.v[sl]) ? x[sl] : 0.0;
   }
-#pragma unroll
-  for (int sl = 0; sl < SL_COUNT; ++sl) {
-    const double t = block_sum_wide(v[sl], sh);
-    if (threadIdx.x == 0) red[sl] = t;
-  }
   double acc = 0.0;
   for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
     const int i = e / p, j = e % p;
     const double d = xx[i * pp + j] - (i == j ? 1.0 : 0.0);
     acc += d * d;
   }
-  acc = block_sum_wide(acc, sh);
+  // all SL_COUNT + 1 block sums at once: independent shuffle trees per wavefront, one
+  // barrier, then one thread per value adds the wavefront sums in wavefront order
+  constexpr int kNW = kFinishThreads / kWave;
+  __shared__ double wsum[SL_COUNT + 1][kNW];
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+#pragma unroll
+    for (int sl = 0; sl < SL_COUNT; ++sl) v[sl] += __shfl_down(v[sl], o, kWave);
+    acc += __shfl_down(acc, o, kWave);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int sl = 0; sl < SL_COUNT; ++sl) wsum[sl][wv] = v[sl];
+    wsum[SL_COUNT][wv] = acc;
+  }
+  __syncthreads();
+  __shared__ double orth;
+  if (threadIdx.x <= SL_COUNT) {
+    double t = 0.0;
+    for (int i = 0; i < kNW; ++i) t += wsum[threadIdx.x][i];
+    if (threadIdx.x < SL_COUNT) red[threadIdx.x] = t;
+    else orth = t;
+  }
+  __syncthreads();
+  (void)sh;
   if (threadIdx.x != 0) return;
+  acc = orth;
   for (int sl = 0; sl < SL_COUNT; ++sl) sums[sl] = red[sl];
   EvalOut o;
   o.kinetic = 0.5 * f * red[SL_KIN];
@@ -695,17 +726,17 @@ void launch_grad_weights(const double* gram, int pp, double* W, hipStream_t st) 
 void launch_qr_factor(const double* xx, const double* gxd, int p, int pp, const double* tau,
                       double* A, double* B, double* work, int* status, hipStream_t st) {
   if (p <= 16) {
-    hipLaunchKernelGGL(k_qr_factor_2d<16>, dim3(1), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_qr_factor_2d<16>, dim3(1), dim3(qr_threads<16>()), 0, st,
                        QrFactor2dArgs{xx, gxd, p, pp, tau, A, B, status});
     return;
   }
   if (p <= 32) {
-    hipLaunchKernelGGL(k_qr_factor_2d<32>, dim3(1), dim3(1024), 0, st,
+    hipLaunchKernelGGL(k_qr_factor_2d<32>, dim3(1), dim3(qr_threads<32>()), 0, st,
                        QrFactor2dArgs{xx, gxd, p, pp, tau, A, B, status});
     return;
   }
   if (p <= 64) {
-    hipLaunchKernelGGL(k_qr_factor_2d<64>, dim3(1), dim3(1024), 0, st,
+    hipLaunchKernelGGL(k_qr_factor_2d<64>, dim3(1), dim3(qr_threads<64>()), 0, st,
                        QrFactor2dArgs{xx, gxd, p, pp, tau, A, B, status});
     return;
   }
@@ -748,11 +779,11 @@ void launch_ls_init(const EvalOut* ev, LsState* ls, LsParams prm, hipStream_t st
 
 void launch_qr_factor_batch(const BatchPtrs<QrFactor2dArgs>& b, int p_max, hipStream_t st) {
   if (p_max <= 16)
-    hipLaunchKernelGGL(k_qr_factor_2d_batch<16>, dim3(b.S), dim3(256), 0, st, b);
+    hipLaunchKernelGGL(k_qr_factor_2d_batch<16>, dim3(b.S), dim3(qr_threads<16>()), 0, st, b);
   else if (p_max <= 32)
-    hipLaunchKernelGGL(k_qr_factor_2d_batch<32>, dim3(b.S), dim3(1024), 0, st, b);
+    hipLaunchKernelGGL(k_qr_factor_2d_batch<32>, dim3(b.S), dim3(qr_threads<32>()), 0, st, b);
   else
-    hipLaunchKernelGGL(k_qr_factor_2d_batch<64>, dim3(b.S), dim3(1024), 0, st, b);
+    hipLaunchKernelGGL(k_qr_factor_2d_batch<64>, dim3(b.S), dim3(qr_threads<64>()), 0, st, b);
 }
 
 void launch_finish_eval_batch(const BatchPtrs<FinishEvalArgs>& b, hipStream_t st) {

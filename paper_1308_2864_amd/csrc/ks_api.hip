@@ -279,13 +279,13 @@ void density(ks_system* s, const void* X, int ld, double* rho) {
 }
 
 void hamiltonian(ks_system* s, const void* X, int ldx, void* Y, int ldy, const double* veff,
-                 double scale, Partials* pt) {
+                 double scale, Partials* pt, double* gram_part = nullptr) {
   if (s->f32)
     launch_hx<float>(static_cast<const float*>(X), ldx, static_cast<float*>(Y), ldy, veff, s->vext,
-                     s->grid, s->p, scale, pt, s->st);
+                     s->grid, s->p, scale, pt, gram_part, s->st);
   else
     launch_hx<double>(static_cast<const double*>(X), ldx, static_cast<double*>(Y), ldy, veff,
-                      s->vext, s->grid, s->p, scale, pt, s->st);
+                      s->vext, s->grid, s->p, scale, pt, gram_part, s->st);
 }
 
 void q1_apply(ks_system* s, const void* X, void* G, void* BX, const double* veff, double scale,
@@ -514,16 +514,22 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
   launch_xc(s->rho, s->vh[idx], s->vext, s->veff[idx], s->grid, s->use_h, s->use_x,
             s->use_h ? s->cg : nullptr, pt, s->st);
   tend(s, KS_PH_XC);
+  // Gram blocks of [X, G]: X^T X and X^T G (and G^T G for the Cayley system); at p = 32
+  // without G^T G the Hamiltonian pass forms them itself
+  const bool hxg = !want_gg && hx_fuses_gram(s->p);
   tbeg(s, KS_PH_HAMILTONIAN);
-  hamiltonian(s, Xs, s->p, s->G[idx], s->p, s->veff[idx], 2.0 * s->f, &pt);
+  hamiltonian(s, Xs, s->p, s->G[idx], s->p, s->veff[idx], 2.0 * s->f, &pt,
+              hxg ? s->gram_part : nullptr);
   tend(s, KS_PH_HAMILTONIAN);
-  // Gram blocks of [X, G]: X^T X and X^T G (and G^T G for the Cayley system)
   const int mask1 = kGramAA | kGramAB | (want_gg ? kGramBB : 0);
-  tbeg(s, KS_PH_GRAM);
-  gram(s, Xs, s->G[idx], mask1);
-  tend(s, KS_PH_GRAM);
+  if (!hxg) {
+    tbeg(s, KS_PH_GRAM);
+    gram(s, Xs, s->G[idx], mask1);
+    tend(s, KS_PH_GRAM);
+  }
   tbeg(s, KS_PH_SMALL);
-  launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, mask1, s->gxg[idx], s->W, s->st);
+  launch_gram_reduce(s->gram_part, hxg ? hx_gram_blocks(s->n) : s->gram_nchunks, s->pp, mask1,
+                     s->gxg[idx], s->W, s->st);
   tend(s, KS_PH_SMALL);
   // D = G - X (G^T X) with ||D||^2, the BB sums and (QR) the Gram blocks X^T D, D^T D:
   // up to 32 columns they come out of the same kernel, wider blocks take a Gram launch
@@ -555,7 +561,7 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
     launch_gram_reduce(s->gram_part, fused ? combine_blocks(s->n) : s->gram_nchunks, s->pp,
                        mask2, s->gxd[idx], nullptr, s->st);
   int nblk[kMaxScalarSlots] = {};
-  nblk[SL_KIN] = nblk[SL_EXT] = hx_blocks(s->n, s->p);
+  nblk[SL_KIN] = nblk[SL_EXT] = hxg ? hx_gram_blocks(s->n) : hx_blocks(s->n, s->p);
   nblk[SL_EH] = nblk[SL_EX] = scalar_blocks(s->n);
   nblk[SL_DD] = nblk[SL_SS] = nblk[SL_SY] = nblk[SL_YY] = combine_blocks(s->n);
   launch_finish_eval(s->spart, kPartStride, nblk, s->sums[idx], s->gxg[idx], s->p, s->pp, s->f,
@@ -729,6 +735,7 @@ int enqueue_trial(ks_system* s, int c, bool qr, const LsParams& lp, const ks_opt
     launch_qr_factor(s->q1 ? s->feg[c] + s->pp * s->pp : s->gxg[c], s->gxd[c], s->p, s->pp,
                      &s->ls->tau, s->A, s->B, s->work, &s->ls->error, s->st);
     ca.Y = s->D[c];
+    ca.upper = true;
   } else {
     launch_wy_factor(s->gxg[c], s->p, s->pp, &s->ls->tau, prm.reorth_tol, s->A, s->B, s->work,
                      &s->ls->error, s->reorth_count, s->st);
@@ -934,6 +941,7 @@ void fill_typed(ks_system* s, std::vector<char>& buf, int c) {
   rt.X = s->X[c];
   rt.A = s->A;
   rt.Y = s->D[c];
+  rt.upper = true;
   rt.B = s->B;
   rt.out = s->X[t];
   rt.rho = s->rho;
@@ -961,13 +969,15 @@ void fill_typed(ks_system* s, std::vector<char>& buf, int c) {
   // evaluation of slot t
   put_rec(buf, c, R_XC, XcArgs{s->rho, s->vh[t], s->vext, s->veff[t], s->grid, s->use_h,
                                s->use_x, s->cg, pt});
+  const bool hxg = hx_fuses_gram(s->p);
   put_rec(buf, c, R_HX, HxArgs<T>{static_cast<const T*>(s->X[t]), s->p,
                                   static_cast<T*>(s->G[t]), s->p, s->veff[t], s->vext, s->grid,
-                                  s->p, 2.0 * s->f, pt});
+                                  s->p, 2.0 * s->f, pt, hxg ? s->gram_part : nullptr});
   put_rec(buf, c, R_GRAM1, GramArgs<T>{static_cast<const T*>(s->X[t]),
                                        static_cast<const T*>(s->G[t]), s->p, s->n, s->p,
                                        s->gram_part});
-  put_rec(buf, c, R_RED1, GramReduceArgs{s->gram_part, s->gram_nchunks, s->pp,
+  put_rec(buf, c, R_RED1, GramReduceArgs{s->gram_part,
+                                         hxg ? hx_gram_blocks(s->n) : s->gram_nchunks, s->pp,
                                          kGramAA | kGramAB, s->gxg[t], s->W});
   CombineArgs gd{};
   gd.X = s->X[t];
@@ -994,7 +1004,8 @@ int upload_records(ks_system* s, const MinRun& m) {
     else fill_typed<double>(s, buf, c);
     const int t = 1 - c;
     int nblk[kMaxScalarSlots] = {};
-    nblk[SL_KIN] = nblk[SL_EXT] = hx_blocks(s->n, s->p);
+    nblk[SL_KIN] = nblk[SL_EXT] =
+        hx_fuses_gram(s->p) ? hx_gram_blocks(s->n) : hx_blocks(s->n, s->p);
     nblk[SL_EH] = nblk[SL_EX] = scalar_blocks(s->n);
     nblk[SL_DD] = nblk[SL_SS] = nblk[SL_SY] = nblk[SL_YY] = combine_blocks(s->n);
     ScalarCounts sc{};
@@ -1091,13 +1102,19 @@ void launch_trial_batch(const std::vector<BatchMember*>& g, hipStream_t st) {
   auto sb = [](const ks_system* s) { return scalar_blocks(s->n); };
   auto xc = table<XcArgs>(g, R_XC, sb, &tot);
   launch_xc_batch(xc, tot, st);
-  auto hxb = [](const ks_system* s) { return hx_blocks(s->n, s->p); };
+  // the members of a group agree on whether the Hamiltonian forms the [X, G] Gram blocks
+  const bool hxg = hx_fuses_gram(g[0]->s->p);
+  auto hxb = [hxg](const ks_system* s) {
+    return hxg ? hx_gram_blocks(s->n) : hx_blocks(s->n, s->p);
+  };
   auto hx = table<HxArgs<T>>(g, R_HX, hxb, &tot);
-  launch_hx_batch<T>(hx, tot, st);
+  launch_hx_batch<T>(hx, tot, hxg, st);
   auto gb = [](const ks_system* s) { return s->gram_nchunks; };
   auto rb = [](const ks_system* s) { return gram_reduce_blocks(s->pp); };
-  auto g1 = table<GramArgs<T>>(g, R_GRAM1, gb, &tot);
-  launch_gram_batch<T>(g1, pp, kGramAA | kGramAB, tot, st);
+  if (!hxg) {
+    auto g1 = table<GramArgs<T>>(g, R_GRAM1, gb, &tot);
+    launch_gram_batch<T>(g1, pp, kGramAA | kGramAB, tot, st);
+  }
   auto r1 = table<GramReduceArgs>(g, R_RED1, rb, &tot);
   launch_gram_reduce_batch(r1, tot, st);
   auto gd = table<CombineArgs>(g, R_GRAD, cb, &tot);
@@ -1152,12 +1169,13 @@ int batch_add(BatchEngine* e, ks_system* s, void* X, const ks_opt_params* o, voi
 // One trial for every active member; members that stop move to the finished list.
 int batch_tick(BatchEngine* e) {
   if (e->act.empty()) return KS_OK;
-  // groups of equal storage precision and p_p
+  // groups of equal storage precision, p_p and Hamiltonian form (with or without the Gram)
   std::vector<std::vector<BatchMember*>> groups;
   for (auto* m : e->act) {
     bool placed = false;
     for (auto& g : groups)
-      if (g[0]->s->f32 == m->s->f32 && g[0]->s->pp == m->s->pp) {
+      if (g[0]->s->f32 == m->s->f32 && g[0]->s->pp == m->s->pp &&
+          hx_fuses_gram(g[0]->s->p) == hx_fuses_gram(m->s->p)) {
         g.push_back(m);
         placed = true;
         break;
@@ -1542,6 +1560,7 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
     launch_qr_factor(s->feg[t] + s->pp * s->pp, s->gxd[t], s->p, s->pp, s->tau_user, s->A, s->B,
                      s->work, s->status, s->st);
     ca.Y = s->D[t];
+    ca.upper = true;
   } else if (kind == KS_QR) {
     CombineArgs cd{};
     cd.f32 = s->f32;
@@ -1559,6 +1578,7 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
     launch_qr_factor(s->gxg[t], s->gxd[t], s->p, s->pp, s->tau_user, s->A, s->B, s->work,
                      s->status, s->st);
     ca.Y = s->D[t];
+    ca.upper = true;
   } else {
     launch_wy_factor(s->gxg[t], s->p, s->pp, s->tau_user, INFINITY, s->A, s->B, s->work,
                      s->status, nullptr, s->st);

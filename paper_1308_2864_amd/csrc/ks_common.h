@@ -210,6 +210,7 @@ struct HxArgs {
   int p;
   double scale;
   Partials pt;
+  double* gram_part;  // optional (p = 32, ld = 32): partial X^T X, X^T G tiles
 };
 
 
@@ -228,11 +229,15 @@ void launch_xc(const double* rho, const double* vh, const double* vext, double* 
                Grid g, int use_h, int use_x, const CgState* cg, Partials pt, hipStream_t st);
 template <typename T>
 void launch_hx(const T* X, int ldx, T* Y, int ldy, const double* veff, const double* vext,
-               Grid g, int p, double scale, Partials* pt, hipStream_t st);
+               Grid g, int p, double scale, Partials* pt, double* gram_part, hipStream_t st);
 int hx_blocks(int n, int p);  // blocks (and energy partials) of launch_hx
+// With gram_part (p = 32, ld = 32, pt given) launch_hx also forms the partial Gram tiles
+// X^T X and X^T G (products 0 and 1) with hx_gram_blocks(n) blocks.
+int hx_gram_blocks(int n);
+bool hx_fuses_gram(int p);
 void launch_xc_batch(const BatchPtrs<XcArgs>& b, int blocks, hipStream_t st);
 template <typename T>
-void launch_hx_batch(const BatchPtrs<HxArgs<T>>& b, int blocks, hipStream_t st);
+void launch_hx_batch(const BatchPtrs<HxArgs<T>>& b, int blocks, bool gram, hipStream_t st);
 int scalar_blocks(int n);
 // Hartree solver (kernels_poisson.hip)
 struct FdOps {
@@ -446,6 +451,7 @@ struct CombineArgs {
   double* gram_part;                    // optional (p_p <= 32): partial X^T D, D^T D tiles
   int ld, n, p;
   bool f32;
+  bool upper;                           // A and B are upper triangular (QR retraction)
 };
 void launch_combine(const CombineArgs& a, hipStream_t st);
 // Batched Gram (products kMask of [A, B], p_p <= 32), its reduction, and the two combine
