@@ -322,9 +322,9 @@ def main():
     ms, cnt = live[dom]
     avg_s = ms * 1e-3 / cnt
     achieved = pb[dom] / avg_s / 1e9
-    kernel_names = {"hamiltonian": "k_hx<double,true>", "gram": "k_gram<double,2,3>",
-                    "gradient": "k_combine<double,2,false,true,false,true,true>",
-                    "retract": "k_combine<double,2,true,false,true,false,false>"}
+    kernel_names = {"hamiltonian": "k_hx<double,true,true>", "gram": "k_gram<double,2,3>",
+                    "gradient": "k_combine<double,2,false,true,false,true,true,false>",
+                    "retract": "k_combine<double,2,true,false,true,false,false,true>"}
     traffic = pmc_traffic(kernel_names[dom]) if args.hartree == "pcg_fd" else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
