@@ -207,6 +207,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--retraction", choices=["qr", "wy"], default="qr")
     ap.add_argument("--hartree", choices=["cg", "pcg_fd"], default="pcg_fd")
+    ap.add_argument("--graphs", type=int, default=0,
+                    help="replay each trial step from a captured HIP graph (1) or launch eagerly")
     ap.add_argument("--cpu-iters", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-steps", type=int, default=3,
@@ -251,6 +253,8 @@ def main():
           f"warmup={args.warmup}", file=sys.stderr, flush=True)
     solver = ks.KS_HARTREE_CG if args.hartree == "cg" else ks.KS_HARTREE_PCG_FD
     sysg = ks.system_from_spec(spec, hartree_solver=solver)
+    if args.graphs:
+        sysg.ks_enable_graphs(True)
     X0 = torch.tensor(X0h, dtype=torch.float64, device="cuda")
     X = torch.empty_like(X0)
     prm = ks.ks_default_params(retraction=ks.KS_QR if args.retraction == "qr" else ks.KS_WY,

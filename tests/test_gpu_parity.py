@@ -354,6 +354,29 @@ def test_minimize_matches_oracle_pcg_fd(kind):
     assert np.linalg.norm(X @ X.T - ref.X @ ref.X.T) <= 1e-6
 
 
+@pytest.mark.parametrize("kind", ["qr", "wy"])
+def test_minimize_p32_first_steps_match_oracle(kind):
+    """p = 32 (c2's width): the Hamiltonian pass forms X^T X and X^T G itself (QR) and the
+    gradient combine forms X^T D and D^T D; eight steps of Alg. 3 from the same start follow
+    the oracle's eight steps (the trajectories agree to rounding this early)."""
+    K = ks()
+    spec = synth.make_system(16, 14, 12, 0.6, 32, 6, seed=4, zrange=(2, 4), margin=1.5,
+                             min_spacing=1.0)
+    X0 = synth.make_x0(spec, 5)
+    sysg = K.system_from_spec(spec, hartree_solver=K.KS_HARTREE_PCG_FD)
+    X = dev(X0)
+    r = sysg.ks_minimize(X, K.ks_default_params(eps_g=1e-12, stagnation_tol=0.0, max_iter=8,
+                                                retraction=K.KS_QR if kind == "qr" else K.KS_WY))
+    orc = oracle_fd(spec)
+    ref = optm.minimize(orc.energy_grad, X0, optm.Params(eps_g=1e-12, stagnation_tol=0.0,
+                                                         max_iter=8, retraction=kind))
+    assert r.iters == ref.iters == 8 and r.nfe == ref.nfe
+    assert abs(r.energy - ref.E) <= 1e-12 * abs(ref.E)
+    assert abs(r.grad_norm - ref.gnorm) <= 1e-8 * ref.gnorm
+    assert np.max(np.abs(host(X) - ref.X)) <= 1e-9
+    assert r.terms.orth_error < 1e-12
+
+
 def test_minimize_ragged_p5():
     K = ks()
     spec = spec_small(15, 12, 10, p=5, M=2, seed=31, h=0.6)
