@@ -83,6 +83,7 @@ __device__ inline void k_gram_body(const GramArgs<T>& ka, int ks_bid, int ks_nb)
   int ld = ka.ld;
   int n = ka.n;
   int p = ka.p;
+  const int pb = ka.pb ? ka.pb : ka.p;  // columns of B (a sub-block of a wider block)
   double* __restrict__ part = ka.part;
   (void)ks_bid;
   (void)ks_nb;
@@ -118,11 +119,11 @@ __device__ inline void k_gram_body(const GramArgs<T>& ka, int ks_bid, int ks_nb)
 #pragma unroll
       for (int t = 0; t < kT; ++t) {
         const int col = t * 16 + lc;
-        const bool ok = rok && col < p;
-        const size_t idx = ok ? roff + col : 0;
+        const bool ok = rok && col < p, okb = rok && col < pb;
+        const size_t idx = ok ? roff + col : 0, idxb = okb ? roff + col : 0;
         f.a[u][t] = ok ? (double)A[idx] : 0.0;
         f.b[u][t] = 0.0;
-        if (kMask & (kPAB | kPBB)) f.b[u][t] = ok ? (double)B[idx] : 0.0;
+        if (kMask & (kPAB | kPBB)) f.b[u][t] = okb ? (double)B[idxb] : 0.0;
       }
     }
   };
@@ -330,15 +331,21 @@ template <int kT, bool kHasY>
 __device__ inline void comb_stage(const CombineArgs& a, double* lds) {
   constexpr int kPP = kT * 16;
   constexpr int kK = kHasY ? 2 * kPP : kPP;
+  const int lda = a.lda ? a.lda : kPP;  // row stride of A and B (a sub-block of larger weights)
+  const int pk = a.pk ? a.pk : a.p;
   lds_stage<kK * kPP / kBlock>(
       kK * kPP,
       [&](int e) {
         const int r = e / kPP, col = e % kPP;
         const int rr = r % kPP, s = rr >> 2, qq = rr & 3;
         const int t = col >> 4, m = col & 15;
-        const int src =
-            comb_col(s, qq) * kPP + 16 * t + 8 * (m >> 3) + 2 * (m & 3) + ((m >> 2) & 1);
-        return (kHasY && r >= kPP) ? a.B[src] : a.A[src];
+        const int kr = comb_col(s, qq), kc = 16 * t + 8 * (m >> 3) + 2 * (m & 3) + ((m >> 2) & 1);
+        // rows past the contraction width and columns past the output width are zero
+        // (a sub-block of wider weights may end inside the tile)
+        const bool ok = kr < pk && kc < a.p;
+        const int src = ok ? kr * lda + kc : 0;
+        const double v = (kHasY && r >= kPP) ? a.B[src] : a.A[src];
+        return ok ? v : 0.0;
       },
       [&](int e, double v) { lds[e] = v; });
 }
@@ -368,6 +375,7 @@ __device__ inline void combine_tiles(const CombineArgs& a, double* lds, int t_be
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int q = lane / 16, c = lane % 16;
   const int ld = a.ld, p = a.p, n = a.n;
+  const int pk = a.pk ? a.pk : a.p;  // columns of X and Y (the contraction) to read
 
   // operands of one tile
   struct Tile {
@@ -375,8 +383,8 @@ __device__ inline void combine_tiles(const CombineArgs& a, double* lds, int t_be
   };
   auto load = [&](Tile& f, int tile) {
     const int row = tile * 16 + c;
-    comb_load<T, kT, kVec>(aX, ld, n, p, row, q, f.x);
-    if constexpr (kHasY) comb_load<T, kT, kVec>(aY, ld, n, p, row, q, f.y);
+    comb_load<T, kT, kVec>(aX, ld, n, pk, row, q, f.x);
+    if constexpr (kHasY) comb_load<T, kT, kVec>(aY, ld, n, pk, row, q, f.y);
     if constexpr (kHasC0) comb_load<T, kT, kVec>(aC0, ld, n, p, row, q, f.c0);
     if constexpr (kGrad) {
       comb_load<T, kT, kVec>(aXk, ld, n, p, row, q, f.xk);
@@ -509,7 +517,7 @@ __device__ inline void k_combine_body(const CombineArgs& a, int ks_bid, int ks_n
   const int t_beg = lb * per, t_end = min(ntiles, t_beg + per);
   // column pairs can be moved as one load or store when every block is pair-aligned
   constexpr uintptr_t kAl = 2 * sizeof(T) - 1;
-  const bool vec = ((a.ld | a.p) & 1) == 0 &&
+  const bool vec = ((a.ld | a.p | a.pk) & 1) == 0 &&
                    ((reinterpret_cast<uintptr_t>(a.X) | reinterpret_cast<uintptr_t>(a.Y) |
                      reinterpret_cast<uintptr_t>(a.C0) | reinterpret_cast<uintptr_t>(a.out) |
                      reinterpret_cast<uintptr_t>(a.Xk) | reinterpret_cast<uintptr_t>(a.Dk)) &
@@ -641,6 +649,7 @@ void launch_combine_tt(const CombineArgs& a, hipStream_t st) {
   if (!y && c0 && !rho && gr) return launch_combine_t<T, kT, false, true, false, true>(a, st);
   if (!y && c0 && !rho && !gr) return launch_combine_t<T, kT, false, true, false, false>(a, st);
   if (!y && !c0 && rho && !gr) return launch_combine_t<T, kT, false, false, true, false>(a, st);
+  if (y && c0 && !rho && !gr) return launch_combine_t<T, kT, true, true, false, false>(a, st);
   launch_combine_t<T, kT, false, false, false, false>(a, st);
 }
 
@@ -678,9 +687,11 @@ int gram_chunks(int n, int pp) {
   return c < 1 ? 1 : c;
 }
 
-// partial tiles of the Gram launches and of the gradient combine's fused Gram tiles
+// partial tiles of the Gram launches and of the gradient combine's fused Gram tiles (blocks
+// wider than 64 columns reduce 64-column sub-products one at a time)
 size_t gram_part_doubles(int n, int pp) {
-  return (size_t)std::max(gram_chunks(n, pp), combine_blocks(n)) * 3 * pp * pp;
+  const size_t w = std::min(pp, 64);
+  return (size_t)std::max(gram_chunks(n, pp), combine_blocks(n)) * 3 * w * w;
 }
 
 void launch_gram(const void* A, const void* B, bool f32, int ld, int n, int p, int mask,
@@ -708,9 +719,114 @@ int combine_blocks(int n) {
 }
 
 
+// ---- blocks wider than 64 columns ------------------------------------------------------
+// The products run as 64-column sub-blocks of the kernels above.  A Gram product is formed
+// per pair of column blocks (X[:, I]^T Y[:, J], reduced, then placed into the p_p x p_p
+// result), and the combine runs per output column block J, accumulating its contraction
+// blocks I in place (the diagonal block last, so that the gradient epilogue sees X, X_k
+// and D_k at the output columns).  The density of a retraction is formed afterwards.
+constexpr int kSubCols = 64;
+
+__global__ void k_gram_place(const double* __restrict__ sub, double* __restrict__ out, int pp,
+                             int i0, int j0, int mirror, double* __restrict__ W) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= kSubCols * kSubCols) return;
+  const int i = e / kSubCols, j = e % kSubCols;
+  if (i0 + i >= pp || j0 + j >= pp) return;
+  const double v = sub[e];
+  out[(size_t)(i0 + i) * pp + j0 + j] = v;
+  if (mirror) out[(size_t)(j0 + j) * pp + i0 + i] = v;
+  if (W) W[(size_t)(j0 + j) * pp + i0 + i] = -v;
+}
+
+int sub_blocks(int p) { return (p + kSubCols - 1) / kSubCols; }
+
+template <typename T>
+void launch_combine_tiled(const CombineArgs& a, hipStream_t st) {
+  const int p = a.p, pp = round_up(p, 16), nb = sub_blocks(p), nbk = combine_blocks(a.n);
+  auto off = [](const void* ptr, int col) -> const void* {
+    return ptr ? static_cast<const T*>(ptr) + col : nullptr;
+  };
+  for (int J = 0; J < nb; ++J) {
+    int order[16], no = 0;
+    for (int I = 0; I < nb; ++I)
+      if (I != J && (!a.upper || I < J)) order[no++] = I;
+    order[no++] = J;
+    for (int k = 0; k < no; ++k) {
+      const int I = order[k];
+      CombineArgs c{};
+      c.X = off(a.X, kSubCols * I);
+      c.Y = off(a.Y, kSubCols * I);
+      c.A = a.A + (size_t)kSubCols * I * pp + kSubCols * J;
+      c.B = a.B ? a.B + (size_t)kSubCols * I * pp + kSubCols * J : nullptr;
+      c.C0 = k == 0 ? off(a.C0, kSubCols * J) : off(a.out, kSubCols * J);
+      c.out = const_cast<void*>(off(a.out, kSubCols * J));
+      c.ld = a.ld;
+      c.n = a.n;
+      c.p = std::min(kSubCols, p - kSubCols * J);
+      c.pk = std::min(kSubCols, p - kSubCols * I);
+      c.lda = pp;
+      c.f32 = a.f32;
+      if (k == no - 1 && a.Xk) {
+        c.Xk = off(a.Xk, kSubCols * J);
+        c.Dk = off(a.Dk, kSubCols * J);
+        c.pt = Partials{a.pt.buf + (size_t)J * nbk, a.pt.stride};
+      }
+      launch_combine_tt<T, 4>(c, st);
+    }
+  }
+  if (a.rho)
+    launch_density<T>(static_cast<const T*>(a.out), a.ld, a.n, p, a.rho_scale, a.rho, st);
+}
+
 void launch_combine(const CombineArgs& a, hipStream_t st) {
+  if (round_up(a.p, 16) > kSubCols) {
+    if (a.f32) launch_combine_tiled<float>(a, st);
+    else launch_combine_tiled<double>(a, st);
+    return;
+  }
   if (a.f32) launch_combine_p<float>(a, st);
   else launch_combine_p<double>(a, st);
+}
+
+int combine_partial_blocks(int n, int p) {
+  return combine_blocks(n) * (round_up(p, 16) > kSubCols ? sub_blocks(p) : 1);
+}
+
+template <typename T>
+void launch_gram_full_t(const T* A, const T* B, int ld, int n, int p, int mask,
+                        double* partials, double* sub, double* out, double* W, hipStream_t st) {
+  const int pp = round_up(p, 16), nb = sub_blocks(p), nch = gram_chunks(n, kSubCols);
+  const size_t lds = (size_t)3 * 4 * 64 * sizeof(double);
+  for (int prod = 0; prod < 3; ++prod) {
+    if (!((mask >> prod) & 1)) continue;
+    const T* L = prod == 2 ? B : A;
+    const T* R = prod == 0 ? A : B;
+    const bool sym = prod != 1;
+    for (int I = 0; I < nb; ++I)
+      for (int J = sym ? I : 0; J < nb; ++J) {
+        const int pa = std::min(kSubCols, p - kSubCols * I);
+        const int pb = std::min(kSubCols, p - kSubCols * J);
+        hipLaunchKernelGGL((k_gram<T, 4, kPAB>), dim3(nch), dim3(256), lds, st,
+                           GramArgs<T>{L + kSubCols * I, R + kSubCols * J, ld, n, pa, partials,
+                                       pb});
+        launch_gram_reduce(partials, nch, kSubCols, kPAB, sub, nullptr, st);
+        hipLaunchKernelGGL(k_gram_place, dim3(kSubCols * kSubCols / 256), dim3(256), 0, st,
+                           sub + kSubCols * kSubCols, out + (size_t)prod * pp * pp, pp,
+                           kSubCols * I, kSubCols * J, sym && I != J ? 1 : 0,
+                           prod == 1 ? W : nullptr);
+      }
+  }
+}
+
+void launch_gram_full(const void* A, const void* B, bool f32, int ld, int n, int p, int mask,
+                      double* partials, double* sub, double* out, double* W, hipStream_t st) {
+  if (f32)
+    launch_gram_full_t<float>(static_cast<const float*>(A), static_cast<const float*>(B), ld, n,
+                              p, mask, partials, sub, out, W, st);
+  else
+    launch_gram_full_t<double>(static_cast<const double*>(A), static_cast<const double*>(B), ld,
+                               n, p, mask, partials, sub, out, W, st);
 }
 
 // ---- batched launches ------------------------------------------------------------------

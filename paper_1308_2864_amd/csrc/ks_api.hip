@@ -60,6 +60,7 @@ struct ks_system {
   int es = 8;  // bytes per orbital element
   double *gxg[2] = {}, *gxd[2] = {}, *W = nullptr, *A = nullptr, *B = nullptr;
   double *work = nullptr, *gram_part = nullptr, *spart = nullptr, *cgpart = nullptr;
+  double* gsub = nullptr;
   double* sums[2] = {};
   CgState* cg = nullptr;
   EvalOut* ev[2] = {};
@@ -154,6 +155,7 @@ void layout(ks_system* s, char* base, size_t* total) {
   s->work = c.take<double>(small_work_doubles(s->p));
   s->gram_nchunks = gram_chunks(s->n, s->pp);
   s->gram_part = c.take<double>(gram_part_doubles(s->n, s->pp));
+  s->gsub = c.take<double>(3 * 64 * 64);  // one reduced 64-column sub-product (p > 64)
   s->spart = c.take<double>((size_t)SL_COUNT * kPartStride);
   s->cgpart = c.take<double>(hartree_part_doubles());
   s->cg = c.take<CgState>(1);
@@ -191,7 +193,11 @@ int validate(const ks_system_desc* d, std::string* why) {
   }
   if (d->nx < 1 || d->ny < 1 || d->nz < 1) { *why = "grid sizes must be >= 1"; return KS_E_INVAL; }
   if (!(d->h > 0.0) || !std::isfinite(d->h)) { *why = "h must be > 0"; return KS_E_INVAL; }
-  if (d->p < 1 || d->p > 64) { *why = "p must be in [1, 64]"; return KS_E_INVAL; }
+  if (d->p < 1 || d->p > 512) { *why = "p must be in [1, 512]"; return KS_E_INVAL; }
+  if (d->disc == KS_DISC_Q1 && d->p > 64) {
+    *why = "the finite-element gradient kernel supports p <= 64";
+    return KS_E_UNSUPPORTED;
+  }
   const int ld = d->ld ? d->ld : d->p;
   if (ld < d->p) { *why = "ld must be >= p"; return KS_E_INVAL; }
   const double cells = (double)d->nx * d->ny * d->nz;
@@ -312,6 +318,19 @@ void mass_solve(ks_system* s, const void* in, void* out) {
 
 void gram(ks_system* s, const void* A, const void* B, int mask) {
   launch_gram(A, B, s->f32, s->p, s->n, s->p, mask, s->gram_part, s->gram_nchunks, s->st);
+}
+
+// Gram products of [A, B] (mask) reduced into out (and W = -(A^T B)^T with W); blocks wider
+// than 64 columns run as 64-column sub-products.
+void gram_reduced(ks_system* s, const void* A, const void* B, int mask, double* out,
+                  double* W) {
+  if (s->pp > 64) {
+    launch_gram_full(A, B, s->f32, s->p, s->n, s->p, mask, s->gram_part, s->gsub, out, W,
+                     s->st);
+    return;
+  }
+  gram(s, A, B, mask);
+  launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, mask, out, W, s->st);
 }
 
 // Pinned host mirror: CgState at 0 and LsState at 256 (the same offsets as on the device,
@@ -522,15 +541,16 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
               hxg ? s->gram_part : nullptr);
   tend(s, KS_PH_HAMILTONIAN);
   const int mask1 = kGramAA | kGramAB | (want_gg ? kGramBB : 0);
-  if (!hxg) {
+  if (hxg) {
+    tbeg(s, KS_PH_SMALL);
+    launch_gram_reduce(s->gram_part, hx_gram_blocks(s->n), s->pp, mask1, s->gxg[idx], s->W,
+                       s->st);
+    tend(s, KS_PH_SMALL);
+  } else {
     tbeg(s, KS_PH_GRAM);
-    gram(s, Xs, s->G[idx], mask1);
+    gram_reduced(s, Xs, s->G[idx], mask1, s->gxg[idx], s->W);
     tend(s, KS_PH_GRAM);
   }
-  tbeg(s, KS_PH_SMALL);
-  launch_gram_reduce(s->gram_part, hxg ? hx_gram_blocks(s->n) : s->gram_nchunks, s->pp, mask1,
-                     s->gxg[idx], s->W, s->st);
-  tend(s, KS_PH_SMALL);
   // D = G - X (G^T X) with ||D||^2, the BB sums and (QR) the Gram blocks X^T D, D^T D:
   // up to 32 columns they come out of the same kernel, wider blocks take a Gram launch
   const bool fused = want_gxd && s->pp <= 32;
@@ -553,17 +573,17 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
   const int mask2 = kGramAB | kGramBB;
   if (want_gxd && !fused) {
     tbeg(s, KS_PH_GRAM);
-    gram(s, Xs, s->D[idx], mask2);
+    gram_reduced(s, Xs, s->D[idx], mask2, s->gxd[idx], nullptr);
     tend(s, KS_PH_GRAM);
   }
   tbeg(s, KS_PH_SMALL);
-  if (want_gxd)
-    launch_gram_reduce(s->gram_part, fused ? combine_blocks(s->n) : s->gram_nchunks, s->pp,
-                       mask2, s->gxd[idx], nullptr, s->st);
+  if (fused)
+    launch_gram_reduce(s->gram_part, combine_blocks(s->n), s->pp, mask2, s->gxd[idx], nullptr,
+                       s->st);
   int nblk[kMaxScalarSlots] = {};
   nblk[SL_KIN] = nblk[SL_EXT] = hxg ? hx_gram_blocks(s->n) : hx_blocks(s->n, s->p);
   nblk[SL_EH] = nblk[SL_EX] = scalar_blocks(s->n);
-  nblk[SL_DD] = nblk[SL_SS] = nblk[SL_SY] = nblk[SL_YY] = combine_blocks(s->n);
+  nblk[SL_DD] = nblk[SL_SS] = nblk[SL_SY] = nblk[SL_YY] = combine_partial_blocks(s->n, s->p);
   launch_finish_eval(s->spart, kPartStride, nblk, s->sums[idx], s->gxg[idx], s->p, s->pp, s->f,
                      s->grid.dV, s->enuc, s->use_h ? s->cg : nullptr, s->ev[idx],
                      judge ? s->ls : nullptr, judge, s->st);
@@ -591,11 +611,8 @@ int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd, const LsP
   mass_solve(s, s->G[idx], s->Gt[idx]);
   tend(s, KS_PH_GRADIENT);
   tbeg(s, KS_PH_GRAM);
-  gram(s, Xs, s->G[idx], kGramAB);
-  launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, kGramAB, s->gxg[idx], s->W, s->st);
-  gram(s, Xs, s->BX[idx], kGramAB);
-  launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, kGramAB, s->feg[idx], nullptr,
-                     s->st);
+  gram_reduced(s, Xs, s->G[idx], kGramAB, s->gxg[idx], s->W);
+  gram_reduced(s, Xs, s->BX[idx], kGramAB, s->feg[idx], nullptr);
   tend(s, KS_PH_GRAM);
   Q1GradArgs ga{};
   ga.Gt = s->Gt[idx];
@@ -621,9 +638,7 @@ int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd, const LsP
   tend(s, KS_PH_GRADIENT);
   if (want_gxd) {
     tbeg(s, KS_PH_GRAM);
-    gram(s, Xs, s->BD[idx], kGramAB);
-    launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, kGramAB, s->gxd[idx], nullptr,
-                       s->st);
+    gram_reduced(s, Xs, s->BD[idx], kGramAB, s->gxd[idx], nullptr);
     // D^T BD lands in product slot 2 of gxd
     gram(s, s->D[idx], s->BD[idx], kGramAB);
     launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, kGramAB, s->gxd[idx] + pp2,
@@ -647,9 +662,7 @@ int b_orthonormalize(ks_system* s, int idx) {
   const int o = 1 - idx;
   const int pp2 = s->pp * s->pp;
   q1_apply(s, s->X[idx], nullptr, s->BX[idx], nullptr, 1.0, nullptr);
-  gram(s, s->X[idx], s->BX[idx], kGramAB);
-  launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, kGramAB, s->feg[idx], nullptr,
-                     s->st);
+  gram_reduced(s, s->X[idx], s->BX[idx], kGramAB, s->feg[idx], nullptr);
   // tau = 0: the factor reduces to the Cholesky of X^T B X; X^T D and D^T D are not used
   launch_fill(s->gxd[idx], 0.0, 3 * (size_t)pp2, s->st);
   launch_set_scalar(s->tau_user, 0.0, s->st);
@@ -1474,8 +1487,7 @@ int ks_gram(ks_system* s, const void* Ain, const void* Bin, double* out) {
   copy_block(s, s->X[t], s->p, Ain, s->ld);
   copy_block(s, s->G[t], s->p, Bin, s->ld);
   const int all = kGramAA | kGramAB | kGramBB;
-  gram(s, s->X[t], s->G[t], all);
-  launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, all, s->gxg[t], nullptr, s->st);
+  gram_reduced(s, s->X[t], s->G[t], all, s->gxg[t], nullptr);
   launch_compact_gram(s->gxg[t], s->pp, s->p, out, s->st);
   int rc = launch_check(s, "gram");
   return rc ? rc : hip_check(s, hipStreamSynchronize(s->st), "gram sync");
@@ -1517,11 +1529,8 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
     const int pp2 = s->pp * s->pp;
     q1_apply(s, s->X[t], nullptr, s->BX[t], nullptr, 1.0, nullptr);
     mass_solve(s, s->G[t], s->Gt[t]);
-    gram(s, s->X[t], s->G[t], kGramAB);
-    launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, kGramAB, s->gxg[t], s->W, s->st);
-    gram(s, s->X[t], s->BX[t], kGramAB);
-    launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, kGramAB, s->feg[t], nullptr,
-                       s->st);
+    gram_reduced(s, s->X[t], s->G[t], kGramAB, s->gxg[t], s->W);
+    gram_reduced(s, s->X[t], s->BX[t], kGramAB, s->feg[t], nullptr);
     Q1GradArgs ga{};
     ga.Gt = s->Gt[t];
     ga.X = s->X[t];
@@ -1536,14 +1545,10 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
     ga.pp = s->pp;
     ga.f32 = s->f32;
     launch_q1_grad(ga, s->st);
-    gram(s, s->X[t], s->BD[t], kGramAB);
-    launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, kGramAB, s->gxd[t], nullptr, s->st);
-    gram(s, s->D[t], s->BD[t], kGramAB);
-    launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, kGramAB, s->gxd[t] + pp2, nullptr,
-                       s->st);
+    gram_reduced(s, s->X[t], s->BD[t], kGramAB, s->gxd[t], nullptr);
+    gram_reduced(s, s->D[t], s->BD[t], kGramAB, s->gxd[t] + pp2, nullptr);
   } else {
-    gram(s, s->X[t], s->G[t], all);
-    launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, all, s->gxg[t], s->W, s->st);
+    gram_reduced(s, s->X[t], s->G[t], all, s->gxg[t], s->W);
   }
   launch_set_scalar(s->tau_user, tau, s->st);
   int* hstat = host_int(s);
@@ -1573,8 +1578,7 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
     cd.p = s->p;
     launch_combine(cd, s->st);
     const int m2 = kGramAB | kGramBB;
-    gram(s, s->X[t], s->D[t], m2);
-    launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, m2, s->gxd[t], nullptr, s->st);
+    gram_reduced(s, s->X[t], s->D[t], m2, s->gxd[t], nullptr);
     launch_qr_factor(s->gxg[t], s->gxd[t], s->p, s->pp, s->tau_user, s->A, s->B, s->work,
                      s->status, s->st);
     ca.Y = s->D[t];

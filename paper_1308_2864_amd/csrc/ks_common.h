@@ -417,6 +417,7 @@ struct GramArgs {
   int n;
   int p;
   double* part;
+  int pb;  // columns of B when they differ from p (0: p)
 };
 
 struct GramReduceArgs {
@@ -452,8 +453,18 @@ struct CombineArgs {
   int ld, n, p;
   bool f32;
   bool upper;                           // A and B are upper triangular (QR retraction)
+  int lda;                              // row stride of A and B (0: p_p of the launch)
+  int pk;                               // columns of X and Y to contract over (0: p)
 };
 void launch_combine(const CombineArgs& a, hipStream_t st);
+// Blocks of scalar partials a combine launch sequence writes per slot (more than one set
+// of blocks when p > 64: one per 64-column output block).
+int combine_partial_blocks(int n, int p);
+// Reduced Gram products (mask over A^T A, A^T B, B^T B) of blocks wider than 64 columns,
+// written into out (3 x p_p x p_p, products outside the mask untouched) and, with W,
+// W = -(A^T B)^T; sub is 3 x 64 x 64 doubles of scratch.
+void launch_gram_full(const void* A, const void* B, bool f32, int ld, int n, int p, int mask,
+                      double* partials, double* sub, double* out, double* W, hipStream_t st);
 // Batched Gram (products kMask of [A, B], p_p <= 32), its reduction, and the two combine
 // forms of a trial: the retraction (X A + Y B with the density) and the gradient
 // (C0 + X A with the BB sums).

@@ -71,6 +71,21 @@ def test_gram_blocks(p):
         assert np.max(np.abs(g - ref)) <= 1e-13 * np.max(np.abs(ref)) * math.sqrt(spec.n)
 
 
+@pytest.mark.parametrize("p", [80, 130])
+def test_gram_blocks_wide(p):
+    """More than 64 columns: the products run as 64-column sub-products (ragged last block)."""
+    spec = spec_small(12, 11, 10, p=p, seed=p)
+    sysg = ks().system_from_spec(spec)
+    rng = np.random.default_rng(p)
+    A = rng.standard_normal((spec.n, p))
+    B = rng.standard_normal((spec.n, p))
+    out = torch.zeros(3 * p * p, dtype=torch.float64, device="cuda")
+    sysg.ks_gram(dev(A), dev(B), out)
+    got = host(out).reshape(3, p, p)
+    for g, ref in zip(got, (A.T @ A, A.T @ B, B.T @ B)):
+        assert np.max(np.abs(g - ref)) <= 1e-13 * np.max(np.abs(ref)) * math.sqrt(spec.n)
+
+
 def test_gram_blocks_large_n_ragged():
     spec = spec_small(64, 33, 31, p=32, seed=3)
     sysg = ks().system_from_spec(spec)
@@ -275,6 +290,24 @@ def test_retract(kind, p):
         assert np.max(np.abs(host(out) - ref)) <= 1e-11, (kind, p, tau)
 
 
+@pytest.mark.parametrize("kind", ["qr", "wy"])
+@pytest.mark.parametrize("p", [80, 130])
+def test_retract_wide(kind, p):
+    """More than 64 columns: the combine accumulates 64-column contraction blocks per output
+    block; the density follows from the finished block."""
+    K = ks()
+    spec = spec_small(12, 11, 10, p=p, seed=40 + p)
+    sysg = K.system_from_spec(spec)
+    X = synth.make_x0(spec, 5)
+    orc = oracle_fd(spec)
+    _, G, _ = orc.energy_grad(X)
+    for tau in (1e-3, 0.05):
+        out = torch.zeros((spec.n, p), dtype=torch.float64, device="cuda")
+        sysg.ks_retract(dev(X), dev(G), tau, K.KS_QR if kind == "qr" else K.KS_WY, out)
+        ref = stiefel.retract_qr(X, G, tau) if kind == "qr" else stiefel.retract_wy(X, G, tau)
+        assert np.max(np.abs(host(out) - ref)) <= 1e-11, (kind, p, tau)
+
+
 def test_retract_rank_deficient_reports_cholesky_breakdown():
     K = ks()
     spec = spec_small(p=3)
@@ -371,6 +404,29 @@ def test_minimize_p32_first_steps_match_oracle(kind):
     ref = optm.minimize(orc.energy_grad, X0, optm.Params(eps_g=1e-12, stagnation_tol=0.0,
                                                          max_iter=8, retraction=kind))
     assert r.iters == ref.iters == 8 and r.nfe == ref.nfe
+    assert abs(r.energy - ref.E) <= 1e-12 * abs(ref.E)
+    assert abs(r.grad_norm - ref.gnorm) <= 1e-8 * ref.gnorm
+    assert np.max(np.abs(host(X) - ref.X)) <= 1e-9
+    assert r.terms.orth_error < 1e-12
+
+
+@pytest.mark.parametrize("kind", ["qr", "wy"])
+def test_minimize_wide_p_first_steps_match_oracle(kind):
+    """p = 100 (two 64-column blocks, the second ragged): six steps of Alg. 3 against the
+    oracle's six steps (Gram sub-products, tiled combines, the one-workgroup factorisations
+    for p > 64)."""
+    K = ks()
+    spec = synth.make_system(14, 13, 12, 0.6, 100, 8, seed=6, zrange=(2, 4), margin=1.5,
+                             min_spacing=1.0)
+    X0 = synth.make_x0(spec, 7)
+    sysg = K.system_from_spec(spec, hartree_solver=K.KS_HARTREE_PCG_FD)
+    X = dev(X0)
+    r = sysg.ks_minimize(X, K.ks_default_params(eps_g=1e-12, stagnation_tol=0.0, max_iter=6,
+                                                retraction=K.KS_QR if kind == "qr" else K.KS_WY))
+    orc = oracle_fd(spec)
+    ref = optm.minimize(orc.energy_grad, X0, optm.Params(eps_g=1e-12, stagnation_tol=0.0,
+                                                         max_iter=6, retraction=kind))
+    assert r.iters == ref.iters == 6 and r.nfe == ref.nfe
     assert abs(r.energy - ref.E) <= 1e-12 * abs(ref.E)
     assert abs(r.grad_norm - ref.gnorm) <= 1e-8 * ref.gnorm
     assert np.max(np.abs(host(X) - ref.X)) <= 1e-9
