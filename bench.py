@@ -76,6 +76,55 @@ def cpu_baseline(spec, X0, gpu_iters, iters):
     }
 
 
+def c4_leg(ks, synth, iters, seed):
+    """The largest single-system workload (128^3 grid, n = 2097152, p = 512): seconds per
+    iteration of Alg. 3 for FP64 and FP32 storage of the orbital blocks (blocks wider than 64
+    columns run as 64-column sub-blocks), and the FP32 energy error against FP64 after the
+    same iterations.  The start block is the seeded N(0,1) block orthonormalised on the
+    device by two Cholesky-QR passes (the QR retraction at tau = 0 with G = 0); a host
+    Householder QR of 2097152 x 512 takes minutes.  The Hartree potential uses the plain
+    CG solver (the 128 x 128 planes of the fast diagonalisation do not fit in LDS)."""
+    import torch
+    spec = synth.make_config("c4", seed)
+    n, p = spec.n, spec.p
+    out = {"workload": f"{spec.name} (FP64 and FP32 storage, CG Hartree)",
+           "grid": [spec.nx, spec.ny, spec.nz], "n": n, "p": p, "iterations": iters}
+    t0 = time.perf_counter()
+    X0 = torch.tensor(synth.make_random_block(n, p, seed=seed, cfg="c4"), dtype=torch.float64,
+                      device="cuda")
+    energies = {}
+    for name, prec, dt in (("fp64", ks.KS_PREC_FP64, torch.float64),
+                           ("fp32", ks.KS_PREC_FP32, torch.float32)):
+        sysg = ks.system_from_spec(spec, hartree_solver=ks.KS_HARTREE_CG, precision=prec)
+        if name == "fp64":
+            zero = torch.zeros_like(X0)
+            tmp = torch.empty_like(X0)
+            for _ in range(2):
+                sysg.ks_retract(X0, zero, 0.0, ks.KS_QR, tmp)
+                X0.copy_(tmp)
+            del zero, tmp
+            out["setup_s"] = round(time.perf_counter() - t0, 2)
+        X = X0.to(dt).clone()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r = sysg.ks_minimize(X, ks.ks_default_params(max_iter=iters), check=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        sysg.close()
+        del X
+        energies[name] = r.energy
+        ent = {"s_per_iteration": round(el / max(r.iters, 1), 4),
+               "s_per_evaluation": round(el / max(r.nfe, 1), 4), "iterations": r.iters,
+               "evaluations": r.nfe, "energy": r.energy, "grad_norm": r.grad_norm,
+               "hartree_iters": r.hartree_iters_total}
+        print(f"# c4 {name}: {ent}", file=sys.stderr, flush=True)
+        out[name] = ent
+    out["fp32_energy_error_vs_fp64_Ha"] = abs(energies["fp32"] - energies["fp64"])
+    del X0
+    torch.cuda.empty_cache()
+    return out
+
+
 def fe_leg(ks, synth, p, iters, seed):
     """Finite-element (Q1, B metric) workload on the 96^3 mesh: per-evaluation time,
     stencil (A X and B X) bandwidth and the FP32-storage error at a fixed X, for FP64 and
@@ -234,6 +283,8 @@ def main():
     ap.add_argument("--fe-p", type=int, default=64,
                     help="orbitals of the finite-element leg (0 = skip; at most 64)")
     ap.add_argument("--fe-iters", type=int, default=100)
+    ap.add_argument("--c4-iters", type=int, default=5,
+                    help="iterations of the 128^3, p = 512 leg (0: skip it)")
     ap.add_argument("--max-iter", type=int, default=10000,
                     help="iteration cap (profiling runs only; the metric needs the default)")
     args = ap.parse_args()
@@ -383,6 +434,9 @@ def main():
     fe = None
     if args.fe_p > 0:
         fe = fe_leg(ks, synth, args.fe_p, args.fe_iters, args.seed)
+    c4 = None
+    if args.c4_iters > 0:
+        c4 = c4_leg(ks, synth, args.c4_iters, args.seed)
     serve = None
     if args.serve_requests > 0:
         fr = [float(v) for v in args.serve_fracs.split(",") if v]
@@ -422,6 +476,7 @@ def main():
         "spmm_GBps": spmm,
         "fp32": fp32,
         "finite_elements": fe,
+        "large_block": c4,
         "serving": serve,
         "phases": phase_out,
         "roofline": roofline,

@@ -745,6 +745,12 @@ int fd_plane_mode(int nx, int ny) {
   return fd_plane_bytes(nx, ny, kPlaneStripSy) <= kFdLdsCap ? kPlaneStripSy : kPlaneStrip;
 }
 
+bool fd_fits(int nx, int ny, int nz) {
+  const size_t nzp = (nz + 15) & ~15;
+  return fd_plane_bytes(nx, ny, kPlaneStrip) <= kFdLdsCap &&
+         nzp * (size_t)kZCols * sizeof(double) <= kFdLdsCap;
+}
+
 int fd_plane_blocks(int nx, int nz, int mode) {
   return mode == kPlaneFull ? nz : nz * ((nx + 15) / 16);
 }

@@ -342,6 +342,7 @@ enum { kPlaneStrip = 0, kPlaneStripSy = 1, kPlaneFull = 2 };
 size_t fd_plane_bytes(int nx, int ny, int mode);
 int fd_plane_mode(int nx, int ny);  // the fastest mode whose LDS fits
 int fd_plane_blocks(int nx, int nz, int mode);
+bool fd_fits(int nx, int ny, int nz);  // the transforms' LDS fits for this grid
 struct FdLaunch {
   int plane_mode;
   size_t z_bytes, z_bytes_staged, cap;

@@ -46,7 +46,10 @@ def test_workspace_sizing_and_descriptor_validation():
     # bigger p, bigger workspace
     d2 = ks.make_desc(24, 24, 24, 0.64, (-8, -8, -8), 32, [[0, 0, 0]], [2])
     assert ks.ks_workspace_bytes(d2) > nb
-    for bad in (dict(p=0), dict(p=65), dict(nx=0), dict(h=0.0), dict(f=0.0)):
+    # blocks of up to 512 orbitals (wider than 64 run as 64-column sub-blocks)
+    assert ks.ks_workspace_bytes(ks.make_desc(8, 8, 8, 0.5, (0, 0, 0), 65)) > 0
+    assert ks.ks_workspace_bytes(ks.make_desc(16, 16, 16, 0.5, (0, 0, 0), 512)) > 0
+    for bad in (dict(p=0), dict(p=513), dict(nx=0), dict(h=0.0), dict(f=0.0)):
         kw = dict(nx=8, ny=8, nz=8, h=0.5, lo=(0, 0, 0), p=2)
         f = bad.pop("f", 2.0)
         kw.update(bad)
@@ -55,6 +58,12 @@ def test_workspace_sizing_and_descriptor_validation():
         h = C.c_void_p()
         assert ks.lib.ks_create_system(C.byref(db), C.c_void_p(1 << 20), 1 << 30, None,
                                        C.byref(h)) == ks.KS_E_INVAL
+    # the fast-diagonalisation Hartree solver needs its plane strip in LDS: 112^2 planes fit,
+    # 128^2 planes do not (such grids use the plain CG solver)
+    kw = dict(hartree_solver=ks.KS_HARTREE_PCG_FD)
+    assert ks.ks_workspace_bytes(ks.make_desc(112, 112, 16, 0.3, (0, 0, 0), 4, **kw)) > 0
+    assert ks.ks_workspace_bytes(ks.make_desc(128, 128, 16, 0.3, (0, 0, 0), 4, **kw)) == 0
+    assert ks.ks_workspace_bytes(ks.make_desc(128, 128, 128, 0.3, (0, 0, 0), 512)) > 0
     # ld < p
     db = ks.make_desc(8, 8, 8, 0.5, (0, 0, 0), 4, ld=3)
     assert ks.ks_workspace_bytes(db) == 0
