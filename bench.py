@@ -280,8 +280,8 @@ def main():
     ap.add_argument("--serve-fracs", default="0.7,0.9")
     ap.add_argument("--serve-check", type=int, default=32,
                     help="requests re-run in FP64 to state the FP32 error")
-    ap.add_argument("--fe-p", type=int, default=64,
-                    help="orbitals of the finite-element leg (0 = skip; at most 64)")
+    ap.add_argument("--fe-p", type=int, default=128,
+                    help="orbitals of the finite-element leg (0 = skip; at most 128)")
     ap.add_argument("--fe-iters", type=int, default=100)
     ap.add_argument("--c4-iters", type=int, default=5,
                     help="iterations of the 128^3, p = 512 leg (0: skip it)")

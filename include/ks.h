@@ -185,8 +185,10 @@ size_t ks_workspace_bytes(const ks_system_desc* d);
 /* Creates a system: validates d, carves the caller's device workspace (ws_bytes >=
  * ks_workspace_bytes(d), 256-byte aligned), copies nuclei to the device, and computes
  * V_ext and E_II there (setup of Section 2.1 eq. (EKS)).  hip_stream is a hipStream_t
- * (NULL = default stream).  On success *out receives the handle.  Errors: KS_E_INVAL,
- * KS_E_NOMEM, KS_E_HIP, KS_E_UNSUPPORTED. */
+ * (NULL = default stream).  On success *out receives the handle.  Errors: KS_E_INVAL
+ * (also when the first or last byte of the needed workspace is not memory the HIP runtime
+ * reports as device or managed memory; nothing is launched then), KS_E_NOMEM, KS_E_HIP,
+ * KS_E_UNSUPPORTED. */
 int ks_create_system(const ks_system_desc* d, void* dev_workspace, size_t ws_bytes,
                      void* hip_stream, ks_system** out);
 
@@ -295,7 +297,8 @@ typedef struct ks_completion {
 } ks_completion;
 
 /* Creates a server over the caller's device workspace (256-byte aligned) with n_slots
- * (1..64) concurrent workers on the current device.  Errors: KS_E_INVAL, KS_E_HIP. */
+ * (1..64) concurrent workers on the current device.  Errors: KS_E_INVAL (including a
+ * workspace that is not device memory of ws_bytes bytes), KS_E_HIP. */
 int ks_server_create(void* dev_workspace, size_t ws_bytes, int n_slots, ks_server** out);
 
 /* Creates a server in continuous-batching mode: one engine thread keeps up to max_batch
@@ -303,7 +306,8 @@ int ks_server_create(void* dev_workspace, size_t ws_bytes, int n_slots, ks_serve
  * one launch per kernel for all of them (ks_minimize_batch's lockstep runner); between
  * steps it admits queued requests into free regions and places, and retires the ones
  * that stopped.  Requests outside the runner's limits run alone on the engine thread.
- * Results equal lone ks_minimize runs bit for bit.  Errors: KS_E_INVAL, KS_E_HIP. */
+ * Results equal lone ks_minimize runs bit for bit.  Errors: KS_E_INVAL (as for
+ * ks_server_create), KS_E_HIP. */
 int ks_server_create_batched(void* dev_workspace, size_t ws_bytes, int max_batch,
                              ks_server** out);
 

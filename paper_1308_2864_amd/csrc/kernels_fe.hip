@@ -209,11 +209,14 @@ __global__ __launch_bounds__(256) void k_mass_axis(const T* in, T* out, int p, G
 
 // D = Gt + X W, BD = G + BX W with the p x p weights staged in LDS; ||D||_B^2 = sum D.BD and
 // the BB sums of the B metric: ss = S.BS, sy = S.BYd, yy = Yd.BYd with S = X - Xc,
-// BS = BX - BXc, Yd = D - Dc, BYd = BD - BDc.  A block takes kQ1Rows rows at a time: their
+// BS = BX - BXc, Yd = D - Dc, BYd = BD - BDc.  A block takes q1_rows(p) rows at a time: their
 // X and BX rows are staged in LDS with coalesced loads (each entry read from memory
 // once), then a thread computes kQ1Cols adjacent columns of one row from LDS.
 constexpr int kQ1Cols = 4;
-constexpr int kQ1Rows = 16;
+constexpr int kQ1Rows = 16;  // rows per tile up to p = 64; 8 above, so the weights fit LDS
+constexpr size_t kQ1LdsCap = 150 * 1024;
+
+__host__ __device__ inline int q1_rows(int p) { return p > 64 ? kQ1Rows / 2 : kQ1Rows; }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_q1_grad(Q1GradArgs a) {
@@ -221,9 +224,10 @@ __global__ __launch_bounds__(256) void k_q1_grad(Q1GradArgs a) {
   __shared__ double sh[kBlock / kWave];
   const int p = a.p, pp = a.pp;
   const int pc = (p + kQ1Cols - 1) / kQ1Cols * kQ1Cols;  // padded row of Ws
+  const int nrow = q1_rows(p);
   double* Ws = lds;                                     // p x pc
-  double* Xs = Ws + (size_t)p * pc;                     // kQ1Rows x p
-  double* Bs = Xs + (size_t)kQ1Rows * p;                // kQ1Rows x p
+  double* Xs = Ws + (size_t)p * pc;                     // nrow x p
+  double* Bs = Xs + (size_t)nrow * p;                   // nrow x p
   for (int e = threadIdx.x; e < p * pc; e += blockDim.x) {
     const int k = e / pc, j = e % pc;
     Ws[e] = j < p ? a.W[k * pp + j] : 0.0;
@@ -241,7 +245,7 @@ __global__ __launch_bounds__(256) void k_q1_grad(Q1GradArgs a) {
   const bool ref = Xc != nullptr;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int groups = pc / kQ1Cols;
-  const int tiles = (a.n + kQ1Rows - 1) / kQ1Rows;
+  const int tiles = (a.n + nrow - 1) / nrow;
   size_t tb, te;
   // contiguous range of row tiles for this block
   {
@@ -253,8 +257,8 @@ __global__ __launch_bounds__(256) void k_q1_grad(Q1GradArgs a) {
   }
   double dd = 0.0, ss = 0.0, sy = 0.0, yy = 0.0;
   for (size_t tile = tb; tile < te; ++tile) {
-    const size_t r0 = tile * kQ1Rows;
-    const int rows = (int)((size_t)a.n - r0 < (size_t)kQ1Rows ? (size_t)a.n - r0 : kQ1Rows);
+    const size_t r0 = tile * nrow;
+    const int rows = (int)((size_t)a.n - r0 < (size_t)nrow ? (size_t)a.n - r0 : nrow);
     __syncthreads();  // previous tile's readers are done (and Ws is complete)
     for (int e = threadIdx.x; e < rows * p; e += blockDim.x) {
       Xs[e] = (double)X[r0 * p + e];
@@ -328,11 +332,15 @@ void mass_axes(const T* in, T* out, int p, Grid g, const double* const tab[3], h
 int q1_apply_blocks(int n, int p) { return stream_blocks((size_t)n * p / kQ1Chunk + 1); }
 int q1_grad_blocks(int n, int p) {
   // a few row tiles per block; at most the streaming cap
-  const int tiles = (n + kQ1Rows - 1) / kQ1Rows;
+  const int tiles = (n + q1_rows(p) - 1) / q1_rows(p);
   int b = (tiles + 3) / 4;
   if (b > kMaxStreamBlocks) b = kMaxStreamBlocks;
-  (void)p;
   return b < 1 ? 1 : b;
+}
+
+size_t q1_grad_lds(int p) {
+  return ((size_t)p * ((p + kQ1Cols - 1) / kQ1Cols * kQ1Cols) + 2 * (size_t)q1_rows(p) * p) *
+         sizeof(double);
 }
 
 template <typename T>
@@ -367,8 +375,12 @@ void launch_mass_solve(const T* in, T* out, int p, Grid g, const double* const t
 
 void launch_q1_grad(const Q1GradArgs& a, hipStream_t st) {
   const int nb = q1_grad_blocks(a.n, a.p);
-  const size_t lds = ((size_t)a.p * ((a.p + kQ1Cols - 1) / kQ1Cols * kQ1Cols) +
-                      2 * (size_t)kQ1Rows * a.p) * sizeof(double);
+  const size_t lds = q1_grad_lds(a.p);
+  // the limit set does not depend on p, so concurrent callers agree on it
+  const void* k = a.f32 ? reinterpret_cast<const void*>(k_q1_grad<float>)
+                        : reinterpret_cast<const void*>(k_q1_grad<double>);
+  if (lds > 65536)
+    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kQ1LdsCap);
   if (a.f32)
     hipLaunchKernelGGL(k_q1_grad<float>, dim3(nb), dim3(kBlock), lds, st, a);
   else

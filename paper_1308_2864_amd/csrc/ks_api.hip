@@ -14,6 +14,26 @@
 
 using namespace ks;
 
+namespace ks {
+
+bool device_range(const void* ptr, size_t bytes) {
+  if (!ptr || bytes == 0) return false;
+  const char* ends[2] = {static_cast<const char*>(ptr), static_cast<const char*>(ptr) + bytes - 1};
+  for (const char* q : ends) {
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, q) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged &&
+        at.type != hipMemoryTypeUnified)
+      return false;
+  }
+  return true;
+}
+
+}  // namespace ks
+
 namespace {
 thread_local std::string g_err;
 constexpr int kPartStride = 4096;  // >= blocks of every streaming kernel
@@ -195,8 +215,8 @@ int validate(const ks_system_desc* d, std::string* why) {
   if (d->nx < 1 || d->ny < 1 || d->nz < 1) { *why = "grid sizes must be >= 1"; return KS_E_INVAL; }
   if (!(d->h > 0.0) || !std::isfinite(d->h)) { *why = "h must be > 0"; return KS_E_INVAL; }
   if (d->p < 1 || d->p > 512) { *why = "p must be in [1, 512]"; return KS_E_INVAL; }
-  if (d->disc == KS_DISC_Q1 && d->p > 64) {
-    *why = "the finite-element gradient kernel supports p <= 64";
+  if (d->disc == KS_DISC_Q1 && d->p > 128) {
+    *why = "the finite-element gradient kernel supports p <= 128 (its weights live in LDS)";
     return KS_E_UNSUPPORTED;
   }
   const int ld = d->ld ? d->ld : d->p;
@@ -641,9 +661,7 @@ int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd, const LsP
     tbeg(s, KS_PH_GRAM);
     gram_reduced(s, Xs, s->BD[idx], kGramAB, s->gxd[idx], nullptr);
     // D^T BD lands in product slot 2 of gxd
-    gram(s, s->D[idx], s->BD[idx], kGramAB);
-    launch_gram_reduce(s->gram_part, s->gram_nchunks, s->pp, kGramAB, s->gxd[idx] + pp2,
-                       nullptr, s->st);
+    gram_reduced(s, s->D[idx], s->BD[idx], kGramAB, s->gxd[idx] + pp2, nullptr);
     tend(s, KS_PH_GRAM);
   }
   tbeg(s, KS_PH_SMALL);
@@ -1317,6 +1335,12 @@ int ks_create_system(const ks_system_desc* d, void* dev_workspace, size_t ws_byt
   if (ws_bytes < need) {
     delete s;
     return fail(nullptr, KS_E_NOMEM, "workspace smaller than ks_workspace_bytes()");
+  }
+  // every later step writes into the workspace from kernels: an address the runtime does
+  // not know as device memory is refused here, before any launch
+  if (!device_range(dev_workspace, need)) {
+    delete s;
+    return fail(nullptr, KS_E_INVAL, "workspace is not device memory of ws_bytes bytes");
   }
   layout(s, static_cast<char*>(dev_workspace), &need);
   s->st = static_cast<hipStream_t>(hip_stream);

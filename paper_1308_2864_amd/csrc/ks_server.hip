@@ -301,6 +301,7 @@ int ks_server_create(void* dev_workspace, size_t ws_bytes, int n_slots, ks_serve
   *out = nullptr;
   if (!dev_workspace || ws_bytes == 0 || n_slots < 1 || n_slots > 64) return KS_E_INVAL;
   if (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign != 0) return KS_E_INVAL;
+  if (!ks::device_range(dev_workspace, ws_bytes)) return KS_E_INVAL;
   ks_server* sv = new ks_server();
   if (hipGetDevice(&sv->device) != hipSuccess) {
     delete sv;
@@ -322,6 +323,7 @@ int ks_server_create_batched(void* dev_workspace, size_t ws_bytes, int max_batch
   if (!dev_workspace || ws_bytes == 0 || max_batch < 1 || max_batch > ks::kMaxBatch)
     return KS_E_INVAL;
   if (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign != 0) return KS_E_INVAL;
+  if (!ks::device_range(dev_workspace, ws_bytes)) return KS_E_INVAL;
   ks_server* sv = new ks_server();
   if (hipGetDevice(&sv->device) != hipSuccess) {
     delete sv;

@@ -64,14 +64,22 @@ def test_workspace_sizing_and_descriptor_validation():
     assert ks.ks_workspace_bytes(ks.make_desc(112, 112, 16, 0.3, (0, 0, 0), 4, **kw)) > 0
     assert ks.ks_workspace_bytes(ks.make_desc(128, 128, 16, 0.3, (0, 0, 0), 4, **kw)) == 0
     assert ks.ks_workspace_bytes(ks.make_desc(128, 128, 128, 0.3, (0, 0, 0), 512)) > 0
+    # the finite-element gradient kernel keeps its p x p weights in LDS: p <= 128
+    q = dict(disc=ks.KS_DISC_Q1)
+    assert ks.ks_workspace_bytes(ks.make_desc(16, 16, 16, 0.5, (0, 0, 0), 128, **q)) > 0
+    assert ks.ks_workspace_bytes(ks.make_desc(16, 16, 16, 0.5, (0, 0, 0), 129, **q)) == 0
     # ld < p
     db = ks.make_desc(8, 8, 8, 0.5, (0, 0, 0), 4, ld=3)
     assert ks.ks_workspace_bytes(db) == 0
-    # unsupported discretisation / precision in this build are reported, not ignored
+    # a valid descriptor with an address that is not device memory is refused before any
+    # launch (the library's kernels would otherwise write through it)
     dq = ks.make_desc(8, 8, 8, 0.5, (0, 0, 0), 4, disc=ks.KS_DISC_Q1)
+    assert ks.ks_workspace_bytes(dq) > 0
     h = C.c_void_p()
-    rc = ks.lib.ks_create_system(C.byref(dq), C.c_void_p(1 << 20), 1 << 30, None, C.byref(h))
-    assert rc in (ks.KS_E_UNSUPPORTED, ks.KS_OK) or rc < 0
+    assert ks.lib.ks_create_system(C.byref(dq), C.c_void_p(1 << 20), 1 << 30, None,
+                                   C.byref(h)) == ks.KS_E_INVAL
+    assert b"device memory" in ks.lib.ks_last_error(None)
+    assert ks.lib.ks_server_create(C.c_void_p(1 << 20), 1 << 30, 2, C.byref(h)) == ks.KS_E_INVAL
 
 
 def test_create_rejects_small_or_misaligned_workspace_without_a_device():

@@ -116,7 +116,7 @@ def _compare(spec, X, solver="cg", precision=None):
 
 
 @pytest.mark.parametrize("solver", ["cg", "pcg_fd"])
-@pytest.mark.parametrize("p", [1, 5, 20])
+@pytest.mark.parametrize("p", [1, 5, 20, 80])
 def test_q1_energy_grad_matches_oracle(p, solver):
     spec = fe_spec(p=p, seed=10 + p)
     orc = oracle_q1(spec)
@@ -147,7 +147,7 @@ def test_q1_energy_grad_fp32_storage():
     assert np.max(np.abs(D - Dr)) <= 1e-5 * np.max(np.abs(Gr))
 
 
-@pytest.mark.parametrize("p", [1, 5, 32])
+@pytest.mark.parametrize("p", [1, 5, 32, 80])
 def test_q1_retract_qr_matches_oracle(p):
     K = ks()
     spec = fe_spec(p=p, seed=40 + p)
@@ -220,6 +220,26 @@ def test_q1_minimize_matches_oracle(solver):
     assert np.min(cos) > 1 - 1e-8
 
 
+def test_q1_minimize_wide_p_first_steps_match_oracle():
+    """p = 80 (a full 64-column block and a ragged one; the gradient kernel takes 8-row
+    tiles): five steps of Alg. 3 in the B metric against the oracle's five."""
+    K = ks()
+    spec = fe_spec(16, 14, 13, p=80, M=6, seed=12, h=0.6)
+    orc = oracle_q1(spec)
+    mf = BStiefel(orc.B, orc.mass_solve)
+    X0 = synth.make_x0(spec, 4)
+    ref = optm.minimize(orc.energy_grad, b_orthonormalize(orc.B, X0),
+                        optm.Params(eps_g=1e-12, stagnation_tol=0.0, max_iter=5), manifold=mf)
+    sysg = K.system_from_spec(spec, hartree_solver=K.KS_HARTREE_PCG_FD)
+    X = dev(X0)
+    r = sysg.ks_minimize(X, K.ks_default_params(eps_g=1e-12, stagnation_tol=0.0, max_iter=5))
+    assert r.iters == ref.iters == 5 and r.nfe == ref.nfe
+    assert abs(r.energy - ref.E) <= 1e-12 * abs(ref.E)
+    assert abs(r.grad_norm - ref.gnorm) <= 1e-8 * ref.gnorm
+    assert np.max(np.abs(host(X) - ref.X)) <= 1e-9
+    assert mf.orth_error(host(X)) < 1e-12
+
+
 def test_q1_minimize_rejects_rank_deficient_start():
     K = ks()
     spec = fe_spec(p=3)
@@ -232,12 +252,12 @@ def test_q1_minimize_rejects_rank_deficient_start():
 
 
 def test_q1_c3_mesh_sampled():
-    """The 96^3 finite-element mesh of the large workload with p = 64 (the widest orbital
-    block of the kernels), FP64: energy terms at the B-orthonormalised seeded start agree
+    """The 96^3 finite-element mesh of the large workload at its p = 128, FP64: energy terms at the B-orthonormalised seeded start agree
     with the oracle to 1e-10, sampled rows of G to 1e-9, and B grad E = G - B X (G^T X)
     holds for the GPU's grad E (checked with the oracle's sparse B)."""
     K = ks()
-    spec = synth.make_config("c3", 0).copy(p=64)
+    spec = synth.make_config("c3", 0)
+    assert spec.p == 128
     orc = oracle_q1(spec)
     X = b_orthonormalize(orc.B, synth.make_x0(spec, 0))
     sysg = K.system_from_spec(spec, hartree_solver=K.KS_HARTREE_PCG_FD)
