@@ -107,8 +107,10 @@ __device__ inline void k_gram_body(const GramArgs<T>& ka, int ks_bid, int ks_nb)
   // so memory and matrix cores overlap.  The accumulation order per wavefront (groups
   // g_beg + w, + 4, + 8, ...) is that of one group at a time.
   constexpr int kU = kT <= 2 ? 4 : 2;
+  // raw storage values: converting at load time would wait for the loads of the next
+  // batch before the products of the current one
   struct Batch {
-    double a[kU][kT], b[kU][kT];
+    T a[kU][kT], b[kU][kT];
   };
   auto load = [&](Batch& f, int grp0) {
 #pragma unroll
@@ -121,9 +123,9 @@ __device__ inline void k_gram_body(const GramArgs<T>& ka, int ks_bid, int ks_nb)
         const int col = t * 16 + lc;
         const bool ok = rok && col < p, okb = rok && col < pb;
         const size_t idx = ok ? roff + col : 0, idxb = okb ? roff + col : 0;
-        f.a[u][t] = ok ? (double)A[idx] : 0.0;
-        f.b[u][t] = 0.0;
-        if (kMask & (kPAB | kPBB)) f.b[u][t] = okb ? (double)B[idxb] : 0.0;
+        f.a[u][t] = ok ? A[idx] : T(0);
+        f.b[u][t] = T(0);
+        if (kMask & (kPAB | kPBB)) f.b[u][t] = okb ? B[idxb] : T(0);
       }
     }
   };
@@ -131,24 +133,30 @@ __device__ inline void k_gram_body(const GramArgs<T>& ka, int ks_bid, int ks_nb)
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       if (grp0 + 4 * u >= g_end) break;
+      double fa[kT], fb[kT];
+#pragma unroll
+      for (int t = 0; t < kT; ++t) {
+        fa[t] = (double)f.a[u][t];
+        fb[t] = (double)f.b[u][t];
+      }
       int a = 0;
       if (kMask & kPAA) {
 #pragma unroll
         for (int ti = 0; ti < kT; ++ti)
 #pragma unroll
-          for (int tj = ti; tj < kT; ++tj, ++a) acc[a] = mfma16(f.a[u][ti], f.a[u][tj], acc[a]);
+          for (int tj = ti; tj < kT; ++tj, ++a) acc[a] = mfma16(fa[ti], fa[tj], acc[a]);
       }
       if (kMask & kPAB) {
 #pragma unroll
         for (int ti = 0; ti < kT; ++ti)
 #pragma unroll
-          for (int tj = 0; tj < kT; ++tj, ++a) acc[a] = mfma16(f.a[u][ti], f.b[u][tj], acc[a]);
+          for (int tj = 0; tj < kT; ++tj, ++a) acc[a] = mfma16(fa[ti], fb[tj], acc[a]);
       }
       if (kMask & kPBB) {
 #pragma unroll
         for (int ti = 0; ti < kT; ++ti)
 #pragma unroll
-          for (int tj = ti; tj < kT; ++tj, ++a) acc[a] = mfma16(f.b[u][ti], f.b[u][tj], acc[a]);
+          for (int tj = ti; tj < kT; ++tj, ++a) acc[a] = mfma16(fb[ti], fb[tj], acc[a]);
       }
     }
   };

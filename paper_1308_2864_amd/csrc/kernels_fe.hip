@@ -207,93 +207,140 @@ __global__ __launch_bounds__(256) void k_mass_axis(const T* in, T* out, int p, G
   }
 }
 
-// D = Gt + X W, BD = G + BX W with the p x p weights staged in LDS; ||D||_B^2 = sum D.BD and
-// the BB sums of the B metric: ss = S.BS, sy = S.BYd, yy = Yd.BYd with S = X - Xc,
-// BS = BX - BXc, Yd = D - Dc, BYd = BD - BDc.  A block takes q1_rows(p) rows at a time: their
-// X and BX rows are staged in LDS with coalesced loads (each entry read from memory
-// once), then a thread computes kQ1Cols adjacent columns of one row from LDS.
-constexpr int kQ1Cols = 4;
-constexpr int kQ1Rows = 16;  // rows per tile up to p = 64; 8 above, so the weights fit LDS
+// D = Gt + X W, BD = G + BX W on the matrix cores; ||D||_B^2 = sum D.BD and the BB sums
+// of the B metric: ss = S.BS, sy = S.BYd, yy = Yd.BYd with S = X - Xc, BS = BX - BXc,
+// Yd = D - Dc, BYd = BD - BDc.  The p_p x p_p weights (zero-padded) sit in LDS, shared by
+// the block's wavefronts.  A wavefront owns a 16-row tile and a group of up to 64 output
+// columns (four 16 x 16 FP64 MFMA tiles per product); per 16-wide slice of the
+// contraction each lane loads four consecutive entries of its row of X and of BX (lane
+// l: row l % 16, entries 4 (l / 16) .. + 3, so 16 lanes read one full cache line), which
+// feed four MFMA steps against the matching weight rows.  The next slice's entries are
+// loaded before the current slice's products.
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ inline d4 mfma16(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int kQ1Threads = 512;
+constexpr int kQ1Waves = kQ1Threads / kWave;
+constexpr int kQ1MaxBlocks = 1024;
 constexpr size_t kQ1LdsCap = 150 * 1024;
 
-__host__ __device__ inline int q1_rows(int p) { return p > 64 ? kQ1Rows / 2 : kQ1Rows; }
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_q1_grad(Q1GradArgs a) {
-  extern __shared__ double lds[];
-  __shared__ double sh[kBlock / kWave];
-  const int p = a.p, pp = a.pp;
-  const int pc = (p + kQ1Cols - 1) / kQ1Cols * kQ1Cols;  // padded row of Ws
-  const int nrow = q1_rows(p);
-  double* Ws = lds;                                     // p x pc
-  double* Xs = Ws + (size_t)p * pc;                     // nrow x p
-  double* Bs = Xs + (size_t)nrow * p;                   // nrow x p
-  for (int e = threadIdx.x; e < p * pc; e += blockDim.x) {
-    const int k = e / pc, j = e % pc;
-    Ws[e] = j < p ? a.W[k * pp + j] : 0.0;
+// v[e] = A[row][k + e] for e < 4, zero beyond n rows or p columns (k is a multiple of 4;
+// with kVec, p is one too and the four entries are in or out together)
+template <typename T, bool kVec>
+__device__ inline void q1_load4(const T* __restrict__ A, size_t row, int n, int p, int k,
+                                double v[4]) {
+  if (kVec) {
+    if (row < (size_t)n && k < p) {
+      const T* q = A + row * p + k;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] = (double)q[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] = 0.0;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      v[e] = (row < (size_t)n && k + e < p) ? (double)A[row * p + k + e] : 0.0;
   }
-  const T* Gt = static_cast<const T*>(a.Gt);
-  const T* X = static_cast<const T*>(a.X);
-  const T* G = static_cast<const T*>(a.G);
-  const T* BX = static_cast<const T*>(a.BX);
-  T* D = static_cast<T*>(a.D);
-  T* BD = static_cast<T*>(a.BD);
-  const T* Xc = static_cast<const T*>(a.Xc);
-  const T* BXc = static_cast<const T*>(a.BXc);
-  const T* Dc = static_cast<const T*>(a.Dc);
-  const T* BDc = static_cast<const T*>(a.BDc);
+}
+
+template <typename T, bool kVec>
+__global__ __launch_bounds__(kQ1Threads) void k_q1_grad(Q1GradArgs a) {
+  extern __shared__ double Ws[];
+  __shared__ double sh[4][kQ1Waves];
+  const int p = a.p, pp = a.pp, n = a.n;
+  const int ncg = (pp + 63) / 64;  // column groups of four 16-wide tiles
+  const int wc = 64 * ncg;         // LDS row: every group full width, zero beyond p
+  for (int e = threadIdx.x; e < pp * wc; e += blockDim.x) {
+    const int k = e / wc, j = e % wc;
+    Ws[e] = (k < p && j < p) ? a.W[(size_t)k * pp + j] : 0.0;
+  }
+  __syncthreads();
+  const T* __restrict__ Gt = static_cast<const T*>(a.Gt);
+  const T* __restrict__ X = static_cast<const T*>(a.X);
+  const T* __restrict__ G = static_cast<const T*>(a.G);
+  const T* __restrict__ BX = static_cast<const T*>(a.BX);
+  T* __restrict__ D = static_cast<T*>(a.D);
+  T* __restrict__ BD = static_cast<T*>(a.BD);
+  const T* __restrict__ Xc = static_cast<const T*>(a.Xc);
+  const T* __restrict__ BXc = static_cast<const T*>(a.BXc);
+  const T* __restrict__ Dc = static_cast<const T*>(a.Dc);
+  const T* __restrict__ BDc = static_cast<const T*>(a.BDc);
   const bool ref = Xc != nullptr;
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int lr = lane % 16, lq = lane / 16;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int groups = pc / kQ1Cols;
-  const int tiles = (a.n + nrow - 1) / nrow;
+  const size_t tiles = ((size_t)n + 15) / 16;
   size_t tb, te;
   // contiguous range of row tiles for this block
   {
-    const int per = (tiles + gridDim.x - 1) / gridDim.x;
-    const long b0 = (long)lb * per;
-    tb = (size_t)(b0 < tiles ? b0 : tiles);
-    const long e0 = b0 + per;
-    te = (size_t)(e0 < tiles ? e0 : tiles);
+    const size_t per = (tiles + gridDim.x - 1) / gridDim.x;
+    const size_t b0 = (size_t)lb * per;
+    tb = b0 < tiles ? b0 : tiles;
+    te = b0 + per < tiles ? b0 + per : tiles;
   }
+  const size_t items = (te - tb) * ncg;
   double dd = 0.0, ss = 0.0, sy = 0.0, yy = 0.0;
-  for (size_t tile = tb; tile < te; ++tile) {
-    const size_t r0 = tile * nrow;
-    const int rows = (int)((size_t)a.n - r0 < (size_t)nrow ? (size_t)a.n - r0 : nrow);
-    __syncthreads();  // previous tile's readers are done (and Ws is complete)
-    for (int e = threadIdx.x; e < rows * p; e += blockDim.x) {
-      Xs[e] = (double)X[r0 * p + e];
-      Bs[e] = (double)BX[r0 * p + e];
-    }
-    __syncthreads();
-    for (int q0 = threadIdx.x; q0 < rows * groups; q0 += blockDim.x) {
-      const int r = q0 / groups;
-      const int j0 = (q0 - r * groups) * kQ1Cols;
-      const double* xr = Xs + r * p;
-      const double* br = Bs + r * p;
-      double u[kQ1Cols] = {}, v[kQ1Cols] = {};
-      for (int k = 0; k < p; ++k) {
-        const double xk = xr[k], bk = br[k];
-        const double* w = Ws + k * pc + j0;
+  for (size_t it = wave; it < items; it += kQ1Waves) {
+    const size_t g0 = (tb + it / ncg) * 16;
+    const int c0 = (int)(it % ncg) * 64;
+    d4 ax[4], ab[4];
 #pragma unroll
-        for (int q = 0; q < kQ1Cols; ++q) {
-          u[q] += xk * w[q];
-          v[q] += bk * w[q];
-        }
+    for (int t = 0; t < 4; ++t) ax[t] = ab[t] = d4{0.0, 0.0, 0.0, 0.0};
+    const size_t row = g0 + lr;
+    double xa[4], ba[4];
+    q1_load4<T, kVec>(X, row, n, p, 4 * lq, xa);
+    q1_load4<T, kVec>(BX, row, n, p, 4 * lq, ba);
+    for (int k0 = 0; k0 < pp; k0 += 16) {
+      const bool more = k0 + 16 < pp;
+      double xn[4], bn[4];
+      if (more) {
+        q1_load4<T, kVec>(X, row, n, p, k0 + 16 + 4 * lq, xn);
+        q1_load4<T, kVec>(BX, row, n, p, k0 + 16 + 4 * lq, bn);
       }
 #pragma unroll
-      for (int q = 0; q < kQ1Cols; ++q) {
-        const int j = j0 + q;
-        if (j >= p) break;
-        const size_t o = (r0 + r) * p + j;
-        const T dT = (T)((double)Gt[o] + u[q]);
-        const T bT = (T)((double)G[o] + v[q]);
+      for (int e = 0; e < 4; ++e) {
+        const double* wr = Ws + (size_t)(k0 + 4 * lq + e) * wc + c0 + lr;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const double w = wr[16 * t];
+          ax[t] = mfma16(xa[e], w, ax[t]);
+          ab[t] = mfma16(ba[e], w, ab[t]);
+        }
+      }
+      if (more) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          xa[e] = xn[e];
+          ba[e] = bn[e];
+        }
+      }
+    }
+    // one column tile at a time keeps the epilogue's loads few in flight
+    const int ntv = min(4, (p - c0 + 15) / 16);  // tiles holding columns below p
+#pragma unroll 1
+    for (int t = 0; t < ntv; ++t) {
+      const d4 vx = t == 0 ? ax[0] : t == 1 ? ax[1] : t == 2 ? ax[2] : ax[3];
+      const d4 vb = t == 0 ? ab[0] : t == 1 ? ab[1] : t == 2 ? ab[2] : ab[3];
+      const int j = c0 + 16 * t + lr;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const size_t g = g0 + lq + 4 * r;
+        if (g >= (size_t)n || j >= p) continue;
+        const size_t o = g * p + j;
+        const T dT = (T)((double)Gt[o] + vx[r]);
+        const T bT = (T)((double)G[o] + vb[r]);
         D[o] = dT;
         BD[o] = bT;
         const double d = (double)dT, bd = (double)bT;
         dd += d * bd;
         if (ref) {
-          const double sdx = xr[j] - (double)Xc[o];
-          const double bs = br[j] - (double)BXc[o];
+          const double sdx = (double)X[o] - (double)Xc[o];
+          const double bs = (double)BX[o] - (double)BXc[o];
           const double y = d - (double)Dc[o];
           const double by = bd - (double)BDc[o];
           ss += sdx * bs;
@@ -303,14 +350,20 @@ __global__ __launch_bounds__(256) void k_q1_grad(Q1GradArgs a) {
       }
     }
   }
-  dd = block_sum(dd, sh);
-  ss = block_sum(ss, sh);
-  sy = block_sum(sy, sh);
-  yy = block_sum(yy, sh);
-  write_partial(a.pt, SL_DD, lb, dd);
-  write_partial(a.pt, SL_SS, lb, ss);
-  write_partial(a.pt, SL_SY, lb, sy);
-  write_partial(a.pt, SL_YY, lb, yy);
+  // fixed-order block reduction of the four sums
+  double v[4] = {dd, ss, sy, yy};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v[q] += __shfl_down(v[q], o, kWave);
+    if (lane == 0) sh[q][wave] = v[q];
+  }
+  __syncthreads();
+  // slots SL_DD .. SL_YY are consecutive
+  for (int q = 0; q < 4; ++q) {
+    double acc = 0.0;
+    for (int w = 0; w < kQ1Waves; ++w) acc += sh[q][w];
+    write_partial(a.pt, SL_DD + q, lb, acc);
+  }
 }
 
 template <typename T, int kN>
@@ -331,16 +384,16 @@ void mass_axes(const T* in, T* out, int p, Grid g, const double* const tab[3], h
 
 int q1_apply_blocks(int n, int p) { return stream_blocks((size_t)n * p / kQ1Chunk + 1); }
 int q1_grad_blocks(int n, int p) {
-  // a few row tiles per block; at most the streaming cap
-  const int tiles = (n + q1_rows(p) - 1) / q1_rows(p);
-  int b = (tiles + 3) / 4;
-  if (b > kMaxStreamBlocks) b = kMaxStreamBlocks;
-  return b < 1 ? 1 : b;
+  // a few rounds of (row tile, column group) items per wavefront
+  const size_t items = ((size_t)n + 15) / 16 * ((round_up(p, 16) + 63) / 64);
+  size_t b = (items + 4 * kQ1Waves - 1) / (4 * kQ1Waves);
+  if (b > (size_t)kQ1MaxBlocks) b = kQ1MaxBlocks;
+  return b < 1 ? 1 : (int)b;
 }
 
 size_t q1_grad_lds(int p) {
-  return ((size_t)p * ((p + kQ1Cols - 1) / kQ1Cols * kQ1Cols) + 2 * (size_t)q1_rows(p) * p) *
-         sizeof(double);
+  const size_t pp = round_up(p, 16), wc = (pp + 63) / 64 * 64;
+  return pp * wc * sizeof(double);
 }
 
 template <typename T>
@@ -377,14 +430,21 @@ void launch_q1_grad(const Q1GradArgs& a, hipStream_t st) {
   const int nb = q1_grad_blocks(a.n, a.p);
   const size_t lds = q1_grad_lds(a.p);
   // the limit set does not depend on p, so concurrent callers agree on it
-  const void* k = a.f32 ? reinterpret_cast<const void*>(k_q1_grad<float>)
-                        : reinterpret_cast<const void*>(k_q1_grad<double>);
+  const bool vec = a.p % 4 == 0;
+  const void* k = a.f32 ? (vec ? reinterpret_cast<const void*>(k_q1_grad<float, true>)
+                               : reinterpret_cast<const void*>(k_q1_grad<float, false>))
+                        : (vec ? reinterpret_cast<const void*>(k_q1_grad<double, true>)
+                               : reinterpret_cast<const void*>(k_q1_grad<double, false>));
   if (lds > 65536)
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kQ1LdsCap);
-  if (a.f32)
-    hipLaunchKernelGGL(k_q1_grad<float>, dim3(nb), dim3(kBlock), lds, st, a);
+  if (a.f32 && vec)
+    hipLaunchKernelGGL((k_q1_grad<float, true>), dim3(nb), dim3(kQ1Threads), lds, st, a);
+  else if (a.f32)
+    hipLaunchKernelGGL((k_q1_grad<float, false>), dim3(nb), dim3(kQ1Threads), lds, st, a);
+  else if (vec)
+    hipLaunchKernelGGL((k_q1_grad<double, true>), dim3(nb), dim3(kQ1Threads), lds, st, a);
   else
-    hipLaunchKernelGGL(k_q1_grad<double>, dim3(nb), dim3(kBlock), lds, st, a);
+    hipLaunchKernelGGL((k_q1_grad<double, false>), dim3(nb), dim3(kQ1Threads), lds, st, a);
 }
 
 template void launch_q1_apply<double>(const double*, double*, double*, const double*,

@@ -96,9 +96,11 @@ __global__ void k_copy_block(T* __restrict__ d, int ldd, const T* __restrict__ s
 
 // ---- density rho_g = scale * sum_i X_gi^2 ----------------------------------------------
 
+// Up to 64 columns a thread sums its row in column order (the density of a start block;
+// wide retractions use the grouped form below).
 template <typename T>
-__global__ void k_density(const T* __restrict__ X, int ld, int n, int p, double scale,
-                          double* __restrict__ rho) {
+__global__ void k_density_row(const T* __restrict__ X, int ld, int n, int p, double scale,
+                              double* __restrict__ rho) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   const T* row = X + (size_t)g * ld;
@@ -108,6 +110,29 @@ __global__ void k_density(const T* __restrict__ X, int ld, int n, int p, double 
     s += x * x;
   }
   rho[g] = scale * s;
+}
+
+// Wider blocks: kG = 64 lanes share a row, each summing the squares of columns lane,
+// lane + 64, ... (a wave reads one row of contiguous memory), then the lanes fold in a
+// fixed order.
+template <typename T, int kG>
+__global__ __launch_bounds__(256) void k_density(const T* __restrict__ X, int ld, int n, int p,
+                                                 double scale, double* __restrict__ rho) {
+  constexpr int kRows = kWave / kG;
+  const int lane = threadIdx.x % kWave, sub = lane % kG;
+  const size_t g = ((size_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * kRows +
+                   lane / kG;
+  double s = 0.0;
+  if (g < (size_t)n) {
+    const T* row = X + g * ld;
+    for (int c = sub; c < p; c += kG) {
+      const double x = (double)row[c];
+      s += x * x;
+    }
+  }
+#pragma unroll
+  for (int m = kG / 2; m >= 1; m /= 2) s += __shfl_xor(s, m, kG);
+  if (g < (size_t)n && sub == 0) rho[g] = scale * s;
 }
 
 // ---- Slater exchange, effective potential, Hartree/exchange energy partials ------------
@@ -471,11 +496,24 @@ template void launch_copy_block<double>(double*, int, const double*, int, int, i
                                         hipStream_t);
 template void launch_copy_block<float>(float*, int, const float*, int, int, int, hipStream_t);
 
+template <typename T, int kG>
+void launch_density_g(const T* X, int ld, int n, int p, double scale, double* rho,
+                      hipStream_t st) {
+  const size_t rows_per_block = (size_t)(kBlock / kWave) * (kWave / kG);
+  const size_t nb = ((size_t)n + rows_per_block - 1) / rows_per_block;
+  hipLaunchKernelGGL((k_density<T, kG>), dim3((unsigned)(nb < 1 ? 1 : nb)), dim3(kBlock), 0, st,
+                     X, ld, n, p, scale, rho);
+}
+
 template <typename T>
 void launch_density(const T* X, int ld, int n, int p, double scale, double* rho,
                     hipStream_t st) {
-  hipLaunchKernelGGL(k_density<T>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, X, ld,
-                     n, p, scale, rho);
+  if (p > 64) {
+    launch_density_g<T, 64>(X, ld, n, p, scale, rho, st);
+    return;
+  }
+  hipLaunchKernelGGL(k_density_row<T>, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, X,
+                     ld, n, p, scale, rho);
 }
 template void launch_density<double>(const double*, int, int, int, double, double*,
                                      hipStream_t);

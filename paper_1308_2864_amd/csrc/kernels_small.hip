@@ -182,27 +182,82 @@ __device__ inline double* work_base(double* glob) {
 
 // ---- QR retraction weights -----------------------------------------------------------
 // xx: X^T X; gxd: [., X^T D, D^T D] (pp x pp blocks).
-__global__ void k_qr_factor(const double* __restrict__ xx, const double* __restrict__ gxd, int p,
-                            int pp, const double* __restrict__ tau_p, double* __restrict__ A,
-                            double* __restrict__ B, double* glob, int* status) {
+
+// Wide blocks (p > 64): a right-looking Cholesky of M = Y^T Y whose pivots are judged
+// against the saved diagonal, then R^{-1} in place: for k = p-1 .. 0, row k (already
+// reduced by the rows below it) is scaled by 1/R_kk and eliminated from the rows above,
+// whose column k still holds R and is read first.  Every step is one parallel update of
+// the block (1024 threads); M sits in LDS up to p = 128 and in the scratch area above.
+constexpr int kQrWideThreads = 1024;
+constexpr int kQrWideMaxP = 512;
+constexpr size_t kQrWideStatic = 3 * kQrWideMaxP * sizeof(double) + 1024;
+
+__global__ __launch_bounds__(kQrWideThreads) void k_qr_factor_wide(
+    const double* __restrict__ xx, const double* __restrict__ gxd, int p, int pp,
+    const double* __restrict__ tau_p, double* __restrict__ A, double* __restrict__ B,
+    double* glob, int* status) {
+  __shared__ double d0[kQrWideMaxP], rk[kQrWideMaxP], ck[kQrWideMaxP];
+  __shared__ int bad;
   double* M = work_base(glob);
-  double* W = M + p * p;
+  const int t = threadIdx.x, nt = blockDim.x;
   const double tau = *tau_p;
-  const double* XX = xx;
-  const double* XD = gxd + pp * pp;
-  const double* DD = gxd + 2 * pp * pp;
-  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+  const double* XD = gxd + (size_t)pp * pp;
+  const double* DD = gxd + 2 * (size_t)pp * pp;
+  for (int e = t; e < p * p; e += nt) {
     const int i = e / p, j = e % p;
-    M[e] = XX[i * pp + j] - tau * (XD[i * pp + j] + XD[j * pp + i]) + tau * tau * DD[i * pp + j];
+    M[e] = xx[i * pp + j] - tau * (XD[i * pp + j] + XD[j * pp + i]) + tau * tau * DD[i * pp + j];
   }
+  if (t == 0) bad = 0;
   __syncthreads();
-  if (blk_cholesky_upper(M, p, p)) {
-    if (threadIdx.x == 0) *status = KS_E_NOT_SPD;
-    return;
+  for (int i = t; i < p; i += nt) d0[i] = M[i * p + i];
+  __syncthreads();
+  for (int k = 0; k < p; ++k) {
+    if (t == 0) {
+      const double d = M[k * p + k];
+      if (!(d > kPivotTol * d0[k]) || !isfinite(d)) bad = 1;
+      else M[k * p + k] = sqrt(d);
+    }
+    __syncthreads();
+    if (bad) {
+      if (t == 0) *status = KS_E_NOT_SPD;
+      return;
+    }
+    const double rkk = M[k * p + k];
+    for (int j = k + 1 + t; j < p; j += nt) {
+      const double v = M[k * p + j] / rkk;
+      M[k * p + j] = v;
+      rk[j] = v;
+    }
+    __syncthreads();
+    const int m = p - k - 1;
+    for (int e = t; e < m * m; e += nt) {
+      const int i = k + 1 + e / m, j = k + 1 + e % m;
+      if (j >= i) M[i * p + j] -= rk[i] * rk[j];
+    }
+    __syncthreads();
   }
-  blk_upper_inverse(M, p, W, p, p);
-  blk_store_padded(A, pp, W, p, p, 1.0);
-  blk_store_padded(B, pp, W, p, p, -tau);
+  for (int k = p - 1; k >= 0; --k) {
+    const double inv = 1.0 / M[k * p + k];
+    for (int j = k + t; j < p; j += nt) {
+      const double w = j == k ? inv : M[k * p + j] * inv;
+      rk[j] = w;
+      M[k * p + j] = w;
+    }
+    for (int i = t; i < k; i += nt) ck[i] = M[i * p + k];
+    __syncthreads();
+    const int m = p - k;
+    for (int e = t; e < k * m; e += nt) {
+      const int i = e / m, j = k + e % m;
+      M[i * p + j] = (j == k ? 0.0 : M[i * p + j]) - ck[i] * rk[j];
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < pp * pp; e += nt) {
+    const int i = e / pp, j = e % pp;
+    const double w = (i < p && j < p && j >= i) ? M[i * p + j] : 0.0;
+    A[e] = w;
+    B[e] = -tau * w;
+  }
 }
 
 // Element-parallel variant for p <= P (P = 16, 32, 64): the P x P matrix Y^T Y lives in
@@ -740,10 +795,16 @@ void launch_qr_factor(const double* xx, const double* gxd, int p, int pp, const 
                        QrFactor2dArgs{xx, gxd, p, pp, tau, A, B, status});
     return;
   }
-  const size_t bytes = (size_t)2 * p * p * sizeof(double);
-  const bool lds = prepare_lds(k_qr_factor, bytes);
-  hipLaunchKernelGGL(k_qr_factor, dim3(1), dim3(kBlock), lds ? bytes : 0, st, xx, gxd, p, pp,
-                     tau, A, B, lds ? nullptr : work, status);
+  // M (p x p) in LDS when it fits beside the static arrays; the attribute value does not
+  // depend on p, so concurrent host threads agree on it
+  const size_t bytes = (size_t)p * p * sizeof(double);
+  const bool lds = bytes + kQrWideStatic <= dyn_lds_limit();
+  if (lds && bytes > 32768)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_qr_factor_wide),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(dyn_lds_limit() - kQrWideStatic));
+  hipLaunchKernelGGL(k_qr_factor_wide, dim3(1), dim3(kQrWideThreads), lds ? bytes : 0, st, xx,
+                     gxd, p, pp, tau, A, B, lds ? nullptr : work, status);
 }
 
 void launch_wy_factor(const double* gram_xg, int p, int pp, const double* tau,
