@@ -51,31 +51,90 @@ Q1Coef q1_coef(double h) {
                 8.0 * h3 / 27.0, 2.0 * h3 / 27.0, h3 / 54.0, h3 / 216.0};
 }
 
-// Y = scale ((1/2) A X + h3 veff X) and BX = B X.  A thread owns one (i, j, orbital) column
-// and marches along z over kQ1Chunk planes.  Per plane it loads the 3 x 3 in-plane
-// neighbourhood once and reduces it to three partial sums (centre P0, in-plane faces P1,
+// Y = scale ((1/2) A X + h3 veff X) and BX = B X.  Per plane the 3 x 3 in-plane
+// neighbourhood of a point reduces to three partial sums (centre P0, in-plane faces P1,
 // in-plane corners P2); the 3-D neighbour classes of plane k are then
 //   centre P0(k), faces P1(k) + P0(k-1) + P0(k+1), edges P2(k) + P1(k-1) + P1(k+1),
-//   corners P2(k-1) + P2(k+1),
-// so each output costs 9 loads instead of 27.  Consecutive threads take consecutive
-// orbitals of one node: every load of a wavefront is one contiguous segment.
+//   corners P2(k-1) + P2(k+1).
+// A block owns a tile of kQ1Tx x-points, kQ1Ty y-rows and kQ1Tc orbitals and marches
+// along z over kQ1Chunk planes: each plane of the tile, with its one-point x/y halo, is
+// staged once in LDS (double-buffered, one barrier per plane; each 16-orbital run is one
+// 128-byte segment; the next plane is fetched into registers meanwhile), and a thread
+// forms the partial sums of its point in its kQ1Ty rows from LDS, keeping P(k-1) and P(k)
+// in registers.  Global reads per plane are
+// (kQ1Tx + 2)(kQ1Ty + 2) / (kQ1Tx kQ1Ty) = 1.7 times the tile.  Blocks loop over tiles
+// (at most kQ1ApplyMaxBlocks blocks, so the energy partials fit their slots).
 constexpr int kQ1Chunk = 16;
+constexpr int kQ1Tx = 16, kQ1Ty = 4, kQ1Tc = 16;
+constexpr int kQ1ApplyMaxBlocks = 2048;
+static_assert(kQ1Tx * kQ1Tc == kBlock, "one thread per (x-point, orbital) of the tile");
+
+struct Q1Tiles {
+  int tx, ty, tc, tz;
+  __host__ __device__ size_t total() const { return (size_t)tx * ty * tc * tz; }
+};
+
+__host__ __device__ inline Q1Tiles q1_tiles(const Grid& g, int p) {
+  return Q1Tiles{(g.nx + kQ1Tx - 1) / kQ1Tx, (g.ny + kQ1Ty - 1) / kQ1Ty,
+                 (p + kQ1Tc - 1) / kQ1Tc, (g.nz + kQ1Chunk - 1) / kQ1Chunk};
+}
+
+typedef double Q1Plane[kQ1Ty + 2][kQ1Tx + 2][kQ1Tc];
+
+constexpr int kQ1Stage = (kQ1Ty + 2) * (kQ1Tx + 2) * kQ1Tc;  // values of one staged plane
+constexpr int kQ1StagePer = (kQ1Stage + kBlock - 1) / kBlock;  // per thread
+
+// The thread's share of a staged plane: offsets within plane 0 and the mask of entries
+// inside the grid (computed once per tile); q1_fetch then loads plane k into registers,
+// so the loads of the next plane fly while the current one is used.
+struct Q1Share {
+  size_t off[kQ1StagePer];
+  unsigned mask;
+};
+
+__device__ inline Q1Share q1_share(const Grid& gr, int p, int i0, int j0, int c0) {
+  Q1Share sh{};
+#pragma unroll
+  for (int q = 0; q < kQ1StagePer; ++q) {
+    const int e = threadIdx.x + q * kBlock;
+    const int cc = e % kQ1Tc, xx = (e / kQ1Tc) % (kQ1Tx + 2), yy = e / (kQ1Tc * (kQ1Tx + 2));
+    const int gi = i0 + xx - 1, gj = j0 + yy - 1, c = c0 + cc;
+    const bool ok = e < kQ1Stage && gi >= 0 && gi < gr.nx && gj >= 0 && gj < gr.ny && c < p;
+    sh.off[q] = ok ? ((size_t)gi + (size_t)gr.nx * gj) * p + c : 0;
+    sh.mask |= ok ? 1u << q : 0u;
+  }
+  return sh;
+}
+
+// (storage type: a conversion here would wait for the loads at once)
+template <typename T>
+__device__ inline void q1_fetch(T v[kQ1StagePer], const T* __restrict__ X, const Grid& gr,
+                                int p, const Q1Share& sh, int k) {
+  const bool kin = k >= 0 && k < gr.nz;
+  const T* plane = X + (kin ? (size_t)k * gr.nx * gr.ny * p : 0);
+#pragma unroll
+  for (int q = 0; q < kQ1StagePer; ++q)
+    v[q] = (kin && ((sh.mask >> q) & 1u)) ? plane[sh.off[q]] : T(0);
+}
 
 template <typename T>
-__device__ inline void q1_plane(const T* __restrict__ X, int i, int j, int k, int nx, int ny,
-                                int nz, ptrdiff_t sx, ptrdiff_t sy, ptrdiff_t sz, double* P) {
-  P[0] = P[1] = P[2] = 0.0;
-  if (k < 0 || k >= nz) return;
-  const T* xp = X + k * sz;
+__device__ inline void q1_put(Q1Plane& L, const T v[kQ1StagePer]) {
 #pragma unroll
-  for (int dy = -1; dy <= 1; ++dy) {
-    if (j + dy < 0 || j + dy >= ny) continue;
-#pragma unroll
-    for (int dx = -1; dx <= 1; ++dx) {
-      if (i + dx < 0 || i + dx >= nx) continue;
-      P[(dx != 0) + (dy != 0)] += (double)xp[dy * sy + dx * sx];
+  for (int q = 0; q < kQ1StagePer; ++q) {
+    const int e = threadIdx.x + q * kBlock;
+    if (e < kQ1Stage) {
+      const int cc = e % kQ1Tc, xx = (e / kQ1Tc) % (kQ1Tx + 2), yy = e / (kQ1Tc * (kQ1Tx + 2));
+      L[yy][xx][cc] = (double)v[q];
     }
   }
+}
+
+// partial sums of row r at x-point lx, orbital lc (the halo is zero outside the grid);
+// neighbours in the order dy = -1, 0, 1 and dx = -1, 0, 1
+__device__ inline void q1_sums(const Q1Plane& L, int r, int lx, int lc, double P[3]) {
+  P[0] = L[r + 1][lx + 1][lc];
+  P[1] = ((L[r][lx + 1][lc] + L[r + 1][lx][lc]) + L[r + 1][lx + 2][lc]) + L[r + 2][lx + 1][lc];
+  P[2] = ((L[r][lx][lc] + L[r][lx + 2][lc]) + L[r + 2][lx][lc]) + L[r + 2][lx + 2][lc];
 }
 
 template <typename T, bool kG, bool kEnergy>
@@ -85,50 +144,75 @@ __global__ __launch_bounds__(256) void k_q1_apply(const T* __restrict__ X, T* __
                                                   const double* __restrict__ vext, Grid gr,
                                                   int p, double scale, Q1Coef cf,
                                                   Partials pt) {
+  __shared__ Q1Plane L[2];
   __shared__ double sh[kBlock / kWave];
-  const int nx = gr.nx, ny = gr.ny, nz = gr.nz;
-  const int nzc = (nz + kQ1Chunk - 1) / kQ1Chunk;
-  const size_t work = (size_t)nx * ny * p * nzc;
-  const ptrdiff_t sx = p, sy = (ptrdiff_t)nx * p, sz = (ptrdiff_t)nx * ny * p;
+  const int lc = threadIdx.x % kQ1Tc, lx = threadIdx.x / kQ1Tc;
+  const Q1Tiles nt = q1_tiles(gr, p);
+  const size_t total = nt.total();
   const double h3 = gr.dV;
   double kin = 0.0, ext = 0.0;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  for (size_t t = (size_t)lb * blockDim.x + threadIdx.x; t < work;
-       t += (size_t)gridDim.x * blockDim.x) {
-    // t -> (z chunk, j, i, orbital), orbital fastest
-    const int c = (int)(t % (unsigned)p);
-    size_t r = t / (unsigned)p;
-    const int i = (int)(r % nx);
-    r /= nx;
-    const int j = (int)(r % ny);
-    const int kc = (int)(r / ny);
-    const int k0 = kc * kQ1Chunk;
-    const int k1 = min(k0 + kQ1Chunk, nz);
-    const T* col = X + (ptrdiff_t)(i + (size_t)nx * j) * p + c;
-    double Pm[3], Pc[3], Pn[3];
-    q1_plane(col, i, j, k0 - 1, nx, ny, nz, sx, sy, sz, Pm);
-    q1_plane(col, i, j, k0, nx, ny, nz, sx, sy, sz, Pc);
-    for (int k = k0; k < k1; ++k) {
-      q1_plane(col, i, j, k + 1, nx, ny, nz, sx, sy, sz, Pn);
-      const double s0 = Pc[0];
-      const double s1 = Pc[1] + Pm[0] + Pn[0];
-      const double s2 = Pc[2] + Pm[1] + Pn[1];
-      const double s3 = Pm[2] + Pn[2];
-      const double ax = cf.a0 * s0 + cf.a2 * s2 + cf.a3 * s3;
-      const double bx = cf.b0 * s0 + cf.b1 * s1 + cf.b2 * s2 + cf.b3 * s3;
-      const size_t g = i + (size_t)nx * (j + (size_t)ny * k);
-      const size_t o = g * p + c;
-      if (kG) Y[o] = (T)(scale * (0.5 * ax + h3 * veff[g] * s0));
-      BX[o] = (T)bx;
-      if (kEnergy) {
-        kin += s0 * ax;
-        ext += h3 * vext[g] * s0 * s0;
-      }
+  for (size_t tile = lb; tile < total; tile += gridDim.x) {
+    // tile -> (orbital tile, x tile, y tile, z chunk), orbital tile fastest
+    size_t r = tile;
+    const int tc = (int)(r % nt.tc);
+    r /= nt.tc;
+    const int tx = (int)(r % nt.tx);
+    r /= nt.tx;
+    const int ty = (int)(r % nt.ty);
+    const int tz = (int)(r / nt.ty);
+    const int i0 = tx * kQ1Tx, j0 = ty * kQ1Ty, c0 = tc * kQ1Tc;
+    const int k0 = tz * kQ1Chunk, k1 = min(k0 + kQ1Chunk, gr.nz);
+    const int i = i0 + lx, c = c0 + lc;
+    const Q1Share share = q1_share(gr, p, i0, j0, c0);
+    T v[kQ1StagePer];
+    __syncthreads();  // the previous tile's readers are done with both buffers
+    q1_fetch(v, X, gr, p, share, k0 - 1);
+    q1_put(L[0], v);
+    q1_fetch(v, X, gr, p, share, k0);
+    q1_put(L[1], v);
+    q1_fetch(v, X, gr, p, share, k0 + 1);
+    __syncthreads();
+    double Pm[kQ1Ty][3], Pc[kQ1Ty][3];
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        Pm[q] = Pc[q];
-        Pc[q] = Pn[q];
+    for (int rr = 0; rr < kQ1Ty; ++rr) {
+      q1_sums(L[0], rr, lx, lc, Pm[rr]);
+      q1_sums(L[1], rr, lx, lc, Pc[rr]);
+    }
+    __syncthreads();  // buffer 0 is refilled below
+    int b = 0;
+    for (int k = k0; k < k1; ++k) {
+      q1_put(L[b], v);  // plane k + 1
+      if (k + 1 < k1) q1_fetch(v, X, gr, p, share, k + 2);
+      __syncthreads();
+#pragma unroll
+      for (int rr = 0; rr < kQ1Ty; ++rr) {
+        double Pn[3];
+        q1_sums(L[b], rr, lx, lc, Pn);
+        const int j = j0 + rr;
+        if (i < gr.nx && j < gr.ny && c < p) {
+          const double s0 = Pc[rr][0];
+          const double s1 = Pc[rr][1] + Pm[rr][0] + Pn[0];
+          const double s2 = Pc[rr][2] + Pm[rr][1] + Pn[1];
+          const double s3 = Pm[rr][2] + Pn[2];
+          const double ax = cf.a0 * s0 + cf.a2 * s2 + cf.a3 * s3;
+          const double bx = cf.b0 * s0 + cf.b1 * s1 + cf.b2 * s2 + cf.b3 * s3;
+          const size_t g = (size_t)i + (size_t)gr.nx * ((size_t)j + (size_t)gr.ny * k);
+          const size_t o = g * p + c;
+          if (kG) Y[o] = (T)(scale * (0.5 * ax + h3 * veff[g] * s0));
+          BX[o] = (T)bx;
+          if (kEnergy) {
+            kin += s0 * ax;
+            ext += h3 * vext[g] * s0 * s0;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          Pm[rr][q] = Pc[rr][q];
+          Pc[rr][q] = Pn[q];
+        }
       }
+      b ^= 1;
     }
   }
   if (kEnergy) {
@@ -382,7 +466,10 @@ void mass_axes(const T* in, T* out, int p, Grid g, const double* const tab[3], h
 
 }  // namespace
 
-int q1_apply_blocks(int n, int p) { return stream_blocks((size_t)n * p / kQ1Chunk + 1); }
+int q1_apply_blocks(Grid g, int p) {
+  const size_t t = q1_tiles(g, p).total();
+  return (int)(t < (size_t)kQ1ApplyMaxBlocks ? (t < 1 ? 1 : t) : (size_t)kQ1ApplyMaxBlocks);
+}
 int q1_grad_blocks(int n, int p) {
   // a few rounds of (row tile, column group) items per wavefront
   const size_t items = ((size_t)n + 15) / 16 * ((round_up(p, 16) + 63) / 64);
@@ -399,7 +486,7 @@ size_t q1_grad_lds(int p) {
 template <typename T>
 void launch_q1_apply(const T* X, T* G, T* BX, const double* veff, const double* vext, Grid g,
                      int p, double scale, Partials* pt, hipStream_t st) {
-  const int nb = q1_apply_blocks(g.n, p);
+  const int nb = q1_apply_blocks(g, p);
   const Q1Coef cf = q1_coef(g.h);
   if (G && pt)
     hipLaunchKernelGGL((k_q1_apply<T, true, true>), dim3(nb), dim3(kBlock), 0, st, X, G, BX,

@@ -666,7 +666,7 @@ int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd, const LsP
   }
   tbeg(s, KS_PH_SMALL);
   int nblk[kMaxScalarSlots] = {};
-  nblk[SL_KIN] = nblk[SL_EXT] = q1_apply_blocks(s->n, s->p);
+  nblk[SL_KIN] = nblk[SL_EXT] = q1_apply_blocks(s->grid, s->p);
   nblk[SL_EH] = nblk[SL_EX] = scalar_blocks(s->n);
   nblk[SL_DD] = nblk[SL_SS] = nblk[SL_SY] = nblk[SL_YY] = q1_grad_blocks(s->n, s->p);
   launch_finish_eval(s->spart, kPartStride, nblk, s->sums[idx], s->feg[idx] + pp2, s->p, s->pp,

@@ -410,7 +410,7 @@ size_t q1_grad_lds(int p);  // dynamic LDS of the gradient kernel (its weights; 
 // True when [ptr, ptr + bytes) starts and ends inside memory the HIP runtime knows as
 // device (or managed) memory; a query the runtime refuses leaves no pending error.
 bool device_range(const void* ptr, size_t bytes);
-int q1_apply_blocks(int n, int p);
+int q1_apply_blocks(Grid g, int p);
 
 // dense kernels (kernels_dense.hip)
 // Argument records of the Gram kernels (see BatchPtrs).
