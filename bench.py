@@ -83,7 +83,8 @@ def c4_leg(ks, synth, iters, seed):
     same iterations.  The start block is the seeded N(0,1) block orthonormalised on the
     device by two Cholesky-QR passes (the QR retraction at tau = 0 with G = 0); a host
     Householder QR of 2097152 x 512 takes minutes.  The Hartree potential uses the plain
-    CG solver (the 128 x 128 planes of the fast diagonalisation do not fit in LDS)."""
+    CG solver: at 128 x 128 planes the fast diagonalisation runs in strips that re-stage the
+    plane and read S_x from L2, and measured slower than CG on this grid."""
     import torch
     spec = synth.make_config("c4", seed)
     n, p = spec.n, spec.p

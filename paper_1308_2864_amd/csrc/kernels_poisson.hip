@@ -385,7 +385,7 @@ constexpr int kZCols = 32;      // (i, j) lines per block of the z transform
 // of the block goes to slot 3 at the block's index.
 constexpr int kPlaneWaves = 4;
 
-template <bool kStageSy>
+template <bool kStageSy, bool kStageSx>
 __device__ inline void k_fd_plane_body(const FdPlaneArgs& ka, int ks_bid, int ks_nb) {
   const double* __restrict__ in = ka.in;
   double* __restrict__ out = ka.out;
@@ -415,16 +415,24 @@ __device__ inline void k_fd_plane_body(const FdPlaneArgs& ka, int ks_bid, int ks
       },
       [&](int e, double v) { P[(e / nxp) * sp + e % nxp] = v; });
   double* Tt = P + nyp * sp;     // nyp x 17
-  double* Sxs = Tt + nyp * 17;   // nxp x 16: S_x[:, i0 .. i0 + 15]
-  lds_stage<8>(
-      nxp * 16,
-      [&](int e) {
-        const int m = e / 16, c = e % 16;
-        const bool ok = m < nx && i0 + c < nx;
-        const double v = Sx[ok ? m * nx + i0 + c : 0];
-        return ok ? v : 0.0;
-      },
-      [&](int e, double v) { Sxs[e] = v; });
+  double* Sxs = Tt + nyp * 17;   // nxp x 16: S_x[:, i0 .. i0 + 15] (when staged)
+  if (kStageSx)
+    lds_stage<8>(
+        nxp * 16,
+        [&](int e) {
+          const int m = e / 16, c = e % 16;
+          const bool ok = m < nx && i0 + c < nx;
+          const double v = Sx[ok ? m * nx + i0 + c : 0];
+          return ok ? v : 0.0;
+        },
+        [&](int e, double v) { Sxs[e] = v; });
+  // the strip of S_x as a B fragment: from LDS, or from global memory (L2-resident) when
+  // the plane leaves no room for it
+  auto sx = [&](int m, int c) -> double {
+    if (kStageSx) return Sxs[m * 16 + c];
+    const bool ok = m < nx && i0 + c < nx;
+    return ok ? Sx[m * nx + i0 + c] : 0.0;
+  };
   const double* SyL = Sy;
   if (kStageSy) {
     double* sy = Sxs + nxp * 16;
@@ -438,7 +446,7 @@ __device__ inline void k_fd_plane_body(const FdPlaneArgs& ka, int ks_bid, int ks
     const int j0 = t * 16;
     d4 acc = d4{0.0, 0.0, 0.0, 0.0};
     for (int k0 = 0; k0 < nxp; k0 += 4)
-      acc = mma(P[(j0 + lc) * sp + k0 + lr], Sxs[(k0 + lr) * 16 + lc], acc);
+      acc = mma(P[(j0 + lc) * sp + k0 + lr], sx(k0 + lr, lc), acc);
 #pragma unroll
     for (int q = 0; q < 4; ++q) Tt[(j0 + lr + 4 * q) * 17 + lc] = acc[q];
   }
@@ -467,15 +475,15 @@ __device__ inline void k_fd_plane_body(const FdPlaneArgs& ka, int ks_bid, int ks
   }
 }
 
-template <bool kStageSy>
+template <bool kStageSy, bool kStageSx>
 __global__ __launch_bounds__(256) void k_fd_plane(FdPlaneArgs ka) {
-  k_fd_plane_body<kStageSy>(ka, blockIdx.x, gridDim.x);
+  k_fd_plane_body<kStageSy, kStageSx>(ka, blockIdx.x, gridDim.x);
 }
 
-template <bool kStageSy>
+template <bool kStageSy, bool kStageSx>
 __global__ __launch_bounds__(256) void k_fd_plane_batch(BatchPtrs<FdPlaneArgs> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_fd_plane_body<kStageSy>(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+  k_fd_plane_body<kStageSy, kStageSx>(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
 }
 
 
@@ -736,18 +744,20 @@ void set_lds(const void* k, size_t bytes) {
 size_t fd_plane_bytes(int nx, int ny, int mode) {
   const size_t nxp = (nx + 15) & ~15, nyp = (ny + 15) & ~15;
   if (mode == kPlaneFull) return (2 * nyp * (nxp + 1) + nxp * nxp + nyp * nyp) * sizeof(double);
+  if (mode == kPlaneStripG) return (nyp * (nxp + 1) + nyp * 17) * sizeof(double);
   const size_t strip = (nyp * (nxp + 1) + nyp * 17 + nxp * 16) * sizeof(double);
   return mode == kPlaneStripSy ? strip + (size_t)ny * ny * sizeof(double) : strip;
 }
 
 int fd_plane_mode(int nx, int ny) {
   if (fd_plane_bytes(nx, ny, kPlaneFull) <= kFdLdsCap) return kPlaneFull;
-  return fd_plane_bytes(nx, ny, kPlaneStripSy) <= kFdLdsCap ? kPlaneStripSy : kPlaneStrip;
+  if (fd_plane_bytes(nx, ny, kPlaneStripSy) <= kFdLdsCap) return kPlaneStripSy;
+  return fd_plane_bytes(nx, ny, kPlaneStrip) <= kFdLdsCap ? kPlaneStrip : kPlaneStripG;
 }
 
 bool fd_fits(int nx, int ny, int nz) {
   const size_t nzp = (nz + 15) & ~15;
-  return fd_plane_bytes(nx, ny, kPlaneStrip) <= kFdLdsCap &&
+  return fd_plane_bytes(nx, ny, kPlaneStripG) <= kFdLdsCap &&
          nzp * (size_t)kZCols * sizeof(double) <= kFdLdsCap;
 }
 
@@ -758,7 +768,7 @@ int fd_plane_blocks(int nx, int nz, int mode) {
 // LDS the preconditioner needs for an nx x ny x nz grid (the plane strips at least).
 size_t fd_lds_bytes(int nx, int ny, int nz) {
   const size_t nzp = (nz + 15) & ~15;
-  return std::max(fd_plane_bytes(nx, ny, kPlaneStrip), nzp * (size_t)kZCols * sizeof(double));
+  return std::max(fd_plane_bytes(nx, ny, kPlaneStripG), nzp * (size_t)kZCols * sizeof(double));
 }
 
 // Largest plane the register tiles of k_fd_plane cover (kFdWaves * kFdTiles tiles).
@@ -772,11 +782,17 @@ void launch_fd_plane(const FdPlaneArgs& pa, int nz, int mode, hipStream_t st) {
     set_lds(reinterpret_cast<const void*>(k_fd_plane_full), lds);
     hipLaunchKernelGGL(k_fd_plane_full, dim3(nb), dim3(kFullWaves * kWave), lds, st, pa);
   } else if (mode == kPlaneStripSy) {
-    set_lds(reinterpret_cast<const void*>(k_fd_plane<true>), lds);
-    hipLaunchKernelGGL(k_fd_plane<true>, dim3(nb), dim3(kPlaneWaves * kWave), lds, st, pa);
+    set_lds(reinterpret_cast<const void*>(k_fd_plane<true, true>), lds);
+    hipLaunchKernelGGL((k_fd_plane<true, true>), dim3(nb), dim3(kPlaneWaves * kWave), lds, st,
+                       pa);
+  } else if (mode == kPlaneStrip) {
+    set_lds(reinterpret_cast<const void*>(k_fd_plane<false, true>), lds);
+    hipLaunchKernelGGL((k_fd_plane<false, true>), dim3(nb), dim3(kPlaneWaves * kWave), lds, st,
+                       pa);
   } else {
-    set_lds(reinterpret_cast<const void*>(k_fd_plane<false>), lds);
-    hipLaunchKernelGGL(k_fd_plane<false>, dim3(nb), dim3(kPlaneWaves * kWave), lds, st, pa);
+    set_lds(reinterpret_cast<const void*>(k_fd_plane<false, false>), lds);
+    hipLaunchKernelGGL((k_fd_plane<false, false>), dim3(nb), dim3(kPlaneWaves * kWave), lds, st,
+                       pa);
   }
 }
 
@@ -888,13 +904,17 @@ void launch_fd_plane_batch(const BatchPtrs<FdPlaneArgs>& b, int blocks, int mode
     hipLaunchKernelGGL(k_fd_plane_full_batch, dim3(blocks), dim3(kFullWaves * kWave), lds, st,
                        b);
   } else if (mode == kPlaneStripSy) {
-    set_lds(reinterpret_cast<const void*>(k_fd_plane_batch<true>), lds);
-    hipLaunchKernelGGL(k_fd_plane_batch<true>, dim3(blocks), dim3(kPlaneWaves * kWave), lds, st,
-                       b);
+    set_lds(reinterpret_cast<const void*>(k_fd_plane_batch<true, true>), lds);
+    hipLaunchKernelGGL((k_fd_plane_batch<true, true>), dim3(blocks), dim3(kPlaneWaves * kWave),
+                       lds, st, b);
+  } else if (mode == kPlaneStrip) {
+    set_lds(reinterpret_cast<const void*>(k_fd_plane_batch<false, true>), lds);
+    hipLaunchKernelGGL((k_fd_plane_batch<false, true>), dim3(blocks), dim3(kPlaneWaves * kWave),
+                       lds, st, b);
   } else {
-    set_lds(reinterpret_cast<const void*>(k_fd_plane_batch<false>), lds);
-    hipLaunchKernelGGL(k_fd_plane_batch<false>, dim3(blocks), dim3(kPlaneWaves * kWave), lds,
-                       st, b);
+    set_lds(reinterpret_cast<const void*>(k_fd_plane_batch<false, false>), lds);
+    hipLaunchKernelGGL((k_fd_plane_batch<false, false>), dim3(blocks),
+                       dim3(kPlaneWaves * kWave), lds, st, b);
   }
 }
 void launch_fd_z_batch(const BatchPtrs<FdZArgs>& b, int blocks, bool staged, size_t lds,

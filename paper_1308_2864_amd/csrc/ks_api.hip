@@ -208,8 +208,8 @@ int validate(const ks_system_desc* d, std::string* why) {
   if (d->hartree_solver == KS_HARTREE_PCG_FD &&
       (((d->nx + 15) / 16) * ((d->ny + 15) / 16) * 256 > fd_max_plane() || d->nz > 128 ||
        !fd_fits(d->nx, d->ny, d->nz))) {
-    *why = "the fast-diagonalisation solver needs a plane strip of LDS (at most 112 x 112 "
-           "planes) and nz <= 128";
+    *why = "the fast-diagonalisation solver needs a plane in LDS (at most 128 x 128 planes) "
+           "and nz <= 128";
     return KS_E_UNSUPPORTED;
   }
   if (d->nx < 1 || d->ny < 1 || d->nz < 1) { *why = "grid sizes must be >= 1"; return KS_E_INVAL; }

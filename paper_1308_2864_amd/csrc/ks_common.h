@@ -338,7 +338,9 @@ size_t hartree_part_doubles();
 int hartree_blocks(int n);
 // Plane-transform modes: 16-column strips (S_y read from L2), strips with S_y staged in
 // LDS, one whole plane per block.
-enum { kPlaneStrip = 0, kPlaneStripSy = 1, kPlaneFull = 2 };
+// plane transform modes, slowest first: S_x strip read from global memory, S_x strip in
+// LDS, S_x strip and S_y in LDS, whole plane per block
+enum { kPlaneStripG = -1, kPlaneStrip = 0, kPlaneStripSy = 1, kPlaneFull = 2 };
 size_t fd_plane_bytes(int nx, int ny, int mode);
 int fd_plane_mode(int nx, int ny);  // the fastest mode whose LDS fits
 int fd_plane_blocks(int nx, int nz, int mode);

@@ -58,11 +58,12 @@ def test_workspace_sizing_and_descriptor_validation():
         h = C.c_void_p()
         assert ks.lib.ks_create_system(C.byref(db), C.c_void_p(1 << 20), 1 << 30, None,
                                        C.byref(h)) == ks.KS_E_INVAL
-    # the fast-diagonalisation Hartree solver needs its plane strip in LDS: 112^2 planes fit,
-    # 128^2 planes do not (such grids use the plain CG solver)
+    # the fast-diagonalisation Hartree solver needs a plane in LDS and its register tiles
+    # cover 128 x 128: 128^2 planes fit (S_x then comes from L2), wider ones do not
     kw = dict(hartree_solver=ks.KS_HARTREE_PCG_FD)
     assert ks.ks_workspace_bytes(ks.make_desc(112, 112, 16, 0.3, (0, 0, 0), 4, **kw)) > 0
-    assert ks.ks_workspace_bytes(ks.make_desc(128, 128, 16, 0.3, (0, 0, 0), 4, **kw)) == 0
+    assert ks.ks_workspace_bytes(ks.make_desc(128, 128, 128, 0.3, (0, 0, 0), 4, **kw)) > 0
+    assert ks.ks_workspace_bytes(ks.make_desc(144, 128, 16, 0.3, (0, 0, 0), 4, **kw)) == 0
     assert ks.ks_workspace_bytes(ks.make_desc(128, 128, 128, 0.3, (0, 0, 0), 512)) > 0
     # the finite-element gradient kernel keeps its p x p weights in LDS: p <= 128
     q = dict(disc=ks.KS_DISC_Q1)

@@ -110,7 +110,8 @@ def test_density():
 
 
 @pytest.mark.parametrize("solver", ["cg", "pcg_fd"])
-@pytest.mark.parametrize("shape", [(17, 13, 11), (32, 32, 32), (5, 40, 3), (70, 9, 66)])
+@pytest.mark.parametrize("shape", [(17, 13, 11), (32, 32, 32), (5, 40, 3), (70, 9, 66),
+                                   (128, 120, 20)])
 def test_hartree_solve(shape, solver):
     nx, ny, nz = shape
     K = ks()
