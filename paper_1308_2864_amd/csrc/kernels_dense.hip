@@ -803,14 +803,17 @@ int combine_partial_blocks(int n, int p) {
 
 template <typename T>
 void launch_gram_full_t(const T* A, const T* B, int ld, int n, int p, int mask,
-                        double* partials, double* sub, double* out, double* W, hipStream_t st) {
+                        double* partials, double* sub, double* out, double* W, hipStream_t st,
+                        bool sym_ab) {
   const int pp = round_up(p, 16), nb = sub_blocks(p), nch = gram_chunks(n, kSubCols);
   const size_t lds = (size_t)3 * 4 * 64 * sizeof(double);
   for (int prod = 0; prod < 3; ++prod) {
     if (!((mask >> prod) & 1)) continue;
     const T* L = prod == 2 ? B : A;
     const T* R = prod == 0 ? A : B;
-    const bool sym = prod != 1;
+    // A^T A and B^T B, and A^T B when the caller knows it is symmetric (X^T B X, D^T B D
+    // in the B metric): the blocks I <= J only, mirrored
+    const bool sym = prod != 1 || sym_ab;
     for (int I = 0; I < nb; ++I)
       for (int J = sym ? I : 0; J < nb; ++J) {
         const int pa = std::min(kSubCols, p - kSubCols * I);
@@ -828,13 +831,14 @@ void launch_gram_full_t(const T* A, const T* B, int ld, int n, int p, int mask,
 }
 
 void launch_gram_full(const void* A, const void* B, bool f32, int ld, int n, int p, int mask,
-                      double* partials, double* sub, double* out, double* W, hipStream_t st) {
+                      double* partials, double* sub, double* out, double* W, hipStream_t st,
+                      bool sym_ab) {
   if (f32)
     launch_gram_full_t<float>(static_cast<const float*>(A), static_cast<const float*>(B), ld, n,
-                              p, mask, partials, sub, out, W, st);
+                              p, mask, partials, sub, out, W, st, sym_ab);
   else
     launch_gram_full_t<double>(static_cast<const double*>(A), static_cast<const double*>(B), ld,
-                               n, p, mask, partials, sub, out, W, st);
+                               n, p, mask, partials, sub, out, W, st, sym_ab);
 }
 
 // ---- batched launches ------------------------------------------------------------------

@@ -343,11 +343,13 @@ void gram(ks_system* s, const void* A, const void* B, int mask) {
 
 // Gram products of [A, B] (mask) reduced into out (and W = -(A^T B)^T with W); blocks wider
 // than 64 columns run as 64-column sub-products.
+// sym_ab: A^T B is symmetric (X^T B X, D^T B D); beyond 64 columns only its blocks I <= J
+// are formed and mirrored
 void gram_reduced(ks_system* s, const void* A, const void* B, int mask, double* out,
-                  double* W) {
+                  double* W, bool sym_ab = false) {
   if (s->pp > 64) {
     launch_gram_full(A, B, s->f32, s->p, s->n, s->p, mask, s->gram_part, s->gsub, out, W,
-                     s->st);
+                     s->st, sym_ab);
     return;
   }
   gram(s, A, B, mask);
@@ -633,7 +635,7 @@ int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd, const LsP
   tend(s, KS_PH_GRADIENT);
   tbeg(s, KS_PH_GRAM);
   gram_reduced(s, Xs, s->G[idx], kGramAB, s->gxg[idx], s->W);
-  gram_reduced(s, Xs, s->BX[idx], kGramAB, s->feg[idx], nullptr);
+  gram_reduced(s, Xs, s->BX[idx], kGramAB, s->feg[idx], nullptr, true);
   tend(s, KS_PH_GRAM);
   Q1GradArgs ga{};
   ga.Gt = s->Gt[idx];
@@ -661,7 +663,7 @@ int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd, const LsP
     tbeg(s, KS_PH_GRAM);
     gram_reduced(s, Xs, s->BD[idx], kGramAB, s->gxd[idx], nullptr);
     // D^T BD lands in product slot 2 of gxd
-    gram_reduced(s, s->D[idx], s->BD[idx], kGramAB, s->gxd[idx] + pp2, nullptr);
+    gram_reduced(s, s->D[idx], s->BD[idx], kGramAB, s->gxd[idx] + pp2, nullptr, true);
     tend(s, KS_PH_GRAM);
   }
   tbeg(s, KS_PH_SMALL);
@@ -681,7 +683,7 @@ int b_orthonormalize(ks_system* s, int idx) {
   const int o = 1 - idx;
   const int pp2 = s->pp * s->pp;
   q1_apply(s, s->X[idx], nullptr, s->BX[idx], nullptr, 1.0, nullptr);
-  gram_reduced(s, s->X[idx], s->BX[idx], kGramAB, s->feg[idx], nullptr);
+  gram_reduced(s, s->X[idx], s->BX[idx], kGramAB, s->feg[idx], nullptr, true);
   // tau = 0: the factor reduces to the Cholesky of X^T B X; X^T D and D^T D are not used
   launch_fill(s->gxd[idx], 0.0, 3 * (size_t)pp2, s->st);
   launch_set_scalar(s->tau_user, 0.0, s->st);
@@ -1555,7 +1557,7 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
     q1_apply(s, s->X[t], nullptr, s->BX[t], nullptr, 1.0, nullptr);
     mass_solve(s, s->G[t], s->Gt[t]);
     gram_reduced(s, s->X[t], s->G[t], kGramAB, s->gxg[t], s->W);
-    gram_reduced(s, s->X[t], s->BX[t], kGramAB, s->feg[t], nullptr);
+    gram_reduced(s, s->X[t], s->BX[t], kGramAB, s->feg[t], nullptr, true);
     Q1GradArgs ga{};
     ga.Gt = s->Gt[t];
     ga.X = s->X[t];
@@ -1571,7 +1573,7 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
     ga.f32 = s->f32;
     launch_q1_grad(ga, s->st);
     gram_reduced(s, s->X[t], s->BD[t], kGramAB, s->gxd[t], nullptr);
-    gram_reduced(s, s->D[t], s->BD[t], kGramAB, s->gxd[t] + pp2, nullptr);
+    gram_reduced(s, s->D[t], s->BD[t], kGramAB, s->gxd[t] + pp2, nullptr, true);
   } else {
     gram_reduced(s, s->X[t], s->G[t], all, s->gxg[t], s->W);
   }

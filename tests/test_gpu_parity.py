@@ -309,6 +309,26 @@ def test_retract_wide(kind, p):
         assert np.max(np.abs(host(out) - ref)) <= 1e-11, (kind, p, tau)
 
 
+@pytest.mark.parametrize("kind,p,shape", [("qr", 200, (12, 11, 10)), ("wy", 200, (12, 11, 10)),
+                                          ("qr", 512, (16, 16, 16))])
+def test_retract_wide_factor_in_global_memory(kind, p, shape):
+    """Factors too large for LDS (the p x p Cholesky above p = 138, the 2p x 2p LU above
+    p = 64) work in the global scratch area; p = 512 is the widest block the library takes."""
+    K = ks()
+    spec = spec_small(*shape, p=p, seed=7 + p)
+    sysg = K.system_from_spec(spec)
+    X = synth.make_x0(spec, 6)
+    orc = oracle_fd(spec)
+    _, G, _ = orc.energy_grad(X)
+    tau = 1e-3
+    out = torch.zeros((spec.n, p), dtype=torch.float64, device="cuda")
+    sysg.ks_retract(dev(X), dev(G), tau, K.KS_QR if kind == "qr" else K.KS_WY, out)
+    ref = stiefel.retract_qr(X, G, tau) if kind == "qr" else stiefel.retract_wy(X, G, tau)
+    assert np.max(np.abs(host(out) - ref)) <= 1e-10 * np.max(np.abs(ref)), (kind, p)
+    Y = host(out)
+    assert np.max(np.abs(Y.T @ Y - np.eye(p))) < 1e-11
+
+
 def test_retract_rank_deficient_reports_cholesky_breakdown():
     K = ks()
     spec = spec_small(p=3)
