@@ -268,8 +268,18 @@ __global__ __launch_bounds__(kQrWideThreads) void k_qr_factor_wide(
 // by step parity.
 template <int P, int kThreads>
 __device__ inline void k_qr_factor_2d_body(const QrFactor2dArgs& ka, int ks_bid, int ks_nb) {
-  const double* __restrict__ xx = ka.xx;
-  const double* __restrict__ gxd = ka.gxd;
+  const double* xx = ka.xx;
+  const double* gxd = ka.gxd;
+  if (ka.sel) {
+    // launched ahead of the host's read of the line-search record: the same decisions the
+    // host is about to take, from the same record
+    const LsState* ls = ka.sel;
+    if (ls->hartree_pending || ls->stop != KS_STOP_NONE || ls->error) return;
+    if (!ls->accepted) {
+      xx = ka.xx_rej;
+      gxd = ka.gxd_rej;
+    }
+  }
   int p = ka.p;
   int pp = ka.pp;
   const double* __restrict__ tau_p = ka.tau_p;
@@ -805,6 +815,15 @@ void launch_qr_factor(const double* xx, const double* gxd, int p, int pp, const 
                               (int)(dyn_lds_limit() - kQrWideStatic));
   hipLaunchKernelGGL(k_qr_factor_wide, dim3(1), dim3(kQrWideThreads), lds ? bytes : 0, st, xx,
                      gxd, p, pp, tau, A, B, lds ? nullptr : work, status);
+}
+
+void launch_qr_factor_next(const QrFactor2dArgs& a, hipStream_t st) {
+  if (a.p <= 16)
+    hipLaunchKernelGGL(k_qr_factor_2d<16>, dim3(1), dim3(qr_threads<16>()), 0, st, a);
+  else if (a.p <= 32)
+    hipLaunchKernelGGL(k_qr_factor_2d<32>, dim3(1), dim3(qr_threads<32>()), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_qr_factor_2d<64>, dim3(1), dim3(qr_threads<64>()), 0, st, a);
 }
 
 void launch_wy_factor(const double* gram_xg, int p, int pp, const double* tau,

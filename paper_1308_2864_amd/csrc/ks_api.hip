@@ -106,6 +106,7 @@ struct ks_system {
   hipStream_t cap_st = nullptr;
   hipGraphExec_t gx[2] = {};
   std::vector<hipEvent_t> ev_free;
+  hipEvent_t ev_rb = nullptr;  // marks the end of a trial's record copy (the wait ahead)
   std::vector<Pending> ev_pend;
   Pending ev_open[KS_NPHASES] = {};
   double ph_ms[KS_NPHASES] = {};
@@ -375,6 +376,43 @@ int readback_cg_ls(ks_system* s) {
   const size_t bytes = reinterpret_cast<char*>(s->ls + 1) - reinterpret_cast<char*>(s->cg);
   hipError_t e = hipMemcpyAsync(s->host, s->cg, bytes, hipMemcpyDeviceToHost, s->st);
   if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  if (e == hipSuccess && s->timers) harvest(s);
+  return hip_check(s, e, "read-back");
+}
+
+void tbeg(ks_system* s, int ph);
+void tend(ks_system* s, int ph);
+
+// As readback_cg_ls for a trial from slot c, with the QR factor of the next trial queued
+// behind the record copy before the host waits (for the copy only): the factor picks slot
+// 1 - c or c on the device from the same record (QrFactor2dArgs::sel), so the GPU works
+// while the host wakes up and decides.  (Queuing the retraction as well measured slower:
+// it then starts with a dependent load of the record.)
+int readback_cg_ls_ahead(ks_system* s, int c) {
+  const int t = 1 - c;
+  const int pp2 = s->pp * s->pp;
+  const size_t bytes = reinterpret_cast<char*>(s->ls + 1) - reinterpret_cast<char*>(s->cg);
+  hipError_t e = hipMemcpyAsync(s->host, s->cg, bytes, hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess && !s->ev_rb) e = hipEventCreateWithFlags(&s->ev_rb, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(s->ev_rb, s->st);
+  if (e == hipSuccess) {
+    QrFactor2dArgs a{};
+    a.xx = s->q1 ? s->feg[t] + pp2 : s->gxg[t];
+    a.gxd = s->gxd[t];
+    a.p = s->p;
+    a.pp = s->pp;
+    a.tau_p = &s->ls->tau;
+    a.A = s->A;
+    a.B = s->B;
+    a.status = &s->ls->error;
+    a.sel = s->ls;
+    a.xx_rej = s->q1 ? s->feg[c] + pp2 : s->gxg[c];
+    a.gxd_rej = s->gxd[c];
+    tbeg(s, KS_PH_SMALL);
+    launch_qr_factor_next(a, s->st);
+    tend(s, KS_PH_SMALL);
+    e = hipEventSynchronize(s->ev_rb);
+  }
   if (e == hipSuccess && s->timers) harvest(s);
   return hip_check(s, e, "read-back");
 }
@@ -751,7 +789,9 @@ namespace {
 // combine (with the density of the trial point), the evaluation and the line-search
 // judgement, all on the device.  Nothing in it waits for the host, so it can be captured
 // into a graph; with the plain CG Hartree solver the evaluation waits for convergence.
-int enqueue_trial(ks_system* s, int c, bool qr, const LsParams& lp, const ks_opt_params& prm) {
+// queued: the QR factor of this trial was already queued by readback_cg_ls_ahead.
+int enqueue_trial(ks_system* s, int c, bool qr, const LsParams& lp, const ks_opt_params& prm,
+                  bool queued = false) {
   const int t = 1 - c;
   CombineArgs ca{};
   ca.X = s->X[c];
@@ -764,18 +804,22 @@ int enqueue_trial(ks_system* s, int c, bool qr, const LsParams& lp, const ks_opt
   ca.ld = s->p;
   ca.n = s->n;
   ca.p = s->p;
-  tbeg(s, KS_PH_SMALL);
   if (qr) {
-    launch_qr_factor(s->q1 ? s->feg[c] + s->pp * s->pp : s->gxg[c], s->gxd[c], s->p, s->pp,
-                     &s->ls->tau, s->A, s->B, s->work, &s->ls->error, s->st);
+    if (!queued) {
+      tbeg(s, KS_PH_SMALL);
+      launch_qr_factor(s->q1 ? s->feg[c] + s->pp * s->pp : s->gxg[c], s->gxd[c], s->p, s->pp,
+                       &s->ls->tau, s->A, s->B, s->work, &s->ls->error, s->st);
+      tend(s, KS_PH_SMALL);
+    }
     ca.Y = s->D[c];
     ca.upper = true;
   } else {
+    tbeg(s, KS_PH_SMALL);
     launch_wy_factor(s->gxg[c], s->p, s->pp, &s->ls->tau, prm.reorth_tol, s->A, s->B, s->work,
                      &s->ls->error, s->reorth_count, s->st);
+    tend(s, KS_PH_SMALL);
     ca.Y = s->G[c];
   }
-  tend(s, KS_PH_SMALL);
   tbeg(s, KS_PH_RETRACT);
   launch_combine(ca, s->st);
   tend(s, KS_PH_RETRACT);
@@ -1410,6 +1454,7 @@ void ks_destroy_system(ks_system* s) {
     if (p.b) s->ev_free.push_back(p.b);
   }
   for (hipEvent_t e : s->ev_free) (void)hipEventDestroy(e);
+  if (s->ev_rb) (void)hipEventDestroy(s->ev_rb);
   drop_graphs(s);
   if (s->cap_st) (void)hipStreamDestroy(s->cap_st);
   delete s;
@@ -1636,6 +1681,7 @@ int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* 
   int rc = run_begin(s, X_inout, o, &m);
   if (rc) return rc;
   LsState* hl = host_ls(s);
+  bool queued = false;  // the next trial's QR factor is already on the stream
   while (hl->stop == KS_STOP_NONE && !hl->error) {
     const int c = m.c;
     const bool pcg = s->solver == KS_HARTREE_PCG_FD;
@@ -1650,12 +1696,19 @@ int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* 
     if (replay && s->gx[c]) {
       rc = hip_check(s, hipGraphLaunch(s->gx[c], s->st), "graph launch");
     } else {
-      rc = enqueue_trial(s, c, m.qr, m.lp, m.prm);
+      rc = enqueue_trial(s, c, m.qr, m.lp, m.prm, queued);
     }
+    queued = false;
     if (rc) return rc;
     const bool cg_read = pcg && s->use_h;
-    rc = cg_read ? readback_cg_ls(s) : readback(s, hl, s->ls);
+    // eager QR runs queue the next trial's factor behind the record copy
+    const bool ahead = cg_read && m.qr && s->p <= 64 && !s->graphs;
+    if (ahead) rc = readback_cg_ls_ahead(s, c);
+    else rc = cg_read ? readback_cg_ls(s) : readback(s, hl, s->ls);
     if (rc) return rc;
+    // a pending Hartree solve re-evaluates the trial first; the queued factor then returned
+    // without writing, and the next trial queues its own
+    queued = ahead && !hl->hartree_pending;
     rc = run_after_trial(s, &m, cg_read);
     if (rc) return rc;
   }

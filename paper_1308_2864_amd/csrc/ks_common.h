@@ -502,6 +502,13 @@ struct QrFactor2dArgs {
   double* A;
   double* B;
   int* status;
+  // With sel, the factor of the next trial launched before the host has read the line-search
+  // record: it returns at once when that trial will not run (a stop, an error or a pending
+  // Hartree solve), and takes xx_rej, gxd_rej (the current point's blocks) when the last
+  // trial was rejected.
+  const LsState* sel;
+  const double* xx_rej;
+  const double* gxd_rej;
 };
 
 struct FinishEvalArgs {
@@ -525,6 +532,8 @@ struct FinishEvalArgs {
 void launch_grad_weights(const double* gram, int pp, double* W, hipStream_t st);
 void launch_qr_factor(const double* xx, const double* gxd, int p, int pp, const double* tau,
                       double* A, double* B, double* work, int* status, hipStream_t st);
+// The p <= 64 factor in its speculative form (see QrFactor2dArgs::sel).
+void launch_qr_factor_next(const QrFactor2dArgs& a, hipStream_t st);
 void launch_wy_factor(const double* gram_xg, int p, int pp, const double* tau,
                       double reorth_tol, double* A, double* B, double* work, int* status,
                       int* reorth_flag, hipStream_t st);
