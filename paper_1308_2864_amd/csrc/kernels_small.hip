@@ -687,7 +687,7 @@ __device__ void ls_judge(const EvalOut* ev, LsState* ls, const LsParams& prm,
   LsState s = *ls;
   if (cg && !cg->done) {
     // the Hartree potential of this trial is not converged yet: the host finishes the
-    // solve, re-evaluates the trial and calls the judge again
+    // solve, re-evaluates the trial and judges it again
     s.hartree_pending = 1;
     *ls = s;
     return;

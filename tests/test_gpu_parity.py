@@ -454,6 +454,26 @@ def test_minimize_wide_p_first_steps_match_oracle(kind):
     assert r.terms.orth_error < 1e-12
 
 
+def test_minimize_p512_first_steps_match_oracle():
+    """p = 512, the widest block (eight 64-column blocks; the factor in global memory):
+    three steps of Alg. 3 against the oracle's three on a 16^3 grid."""
+    K = ks()
+    spec = synth.make_system(16, 16, 16, 0.6, 512, 8, seed=9, zrange=(2, 4), margin=1.5,
+                             min_spacing=1.0)
+    X0 = synth.make_x0(spec, 8)
+    sysg = K.system_from_spec(spec, hartree_solver=K.KS_HARTREE_PCG_FD)
+    X = dev(X0)
+    r = sysg.ks_minimize(X, K.ks_default_params(eps_g=1e-12, stagnation_tol=0.0, max_iter=3))
+    orc = oracle_fd(spec)
+    ref = optm.minimize(orc.energy_grad, X0, optm.Params(eps_g=1e-12, stagnation_tol=0.0,
+                                                         max_iter=3))
+    assert r.iters == ref.iters == 3 and r.nfe == ref.nfe
+    assert abs(r.energy - ref.E) <= 1e-12 * abs(ref.E)
+    assert abs(r.grad_norm - ref.gnorm) <= 1e-8 * ref.gnorm
+    assert np.max(np.abs(host(X) - ref.X)) <= 1e-9
+    assert r.terms.orth_error < 1e-11
+
+
 def test_minimize_ragged_p5():
     K = ks()
     spec = spec_small(15, 12, 10, p=5, M=2, seed=31, h=0.6)
