@@ -19,23 +19,6 @@ namespace ks {
 
 namespace {
 
-constexpr int kMaxStreamBlocks = 4096;
-
-inline int stream_blocks(size_t work) {
-  size_t b = (work + kBlock - 1) / kBlock;
-  if (b < 1) b = 1;
-  return (int)(b < (size_t)kMaxStreamBlocks ? b : (size_t)kMaxStreamBlocks);
-}
-
-__device__ inline void block_range(size_t work, int lb, int nb, size_t* beg, size_t* end) {
-  size_t per = (work + nb - 1) / nb;
-  per = (per + kBlock - 1) / kBlock * kBlock;
-  size_t b0 = (size_t)lb * per;
-  *beg = b0 < work ? b0 : work;
-  size_t e = b0 + per;
-  *end = e < work ? e : work;
-}
-
 __device__ inline void write_partial(Partials pt, int slot, int b, double v) {
   if (threadIdx.x == 0) pt.buf[(size_t)slot * pt.stride + b] = v;
 }

@@ -506,22 +506,7 @@ __device__ void ls_judge(const EvalOut* ev, LsState* ls, const LsParams& prm, co
 // The evaluation summary: sums the per-block partials of every scalar slot (fixed
 // order), forms the energy terms, ||X^T X - I||_F (or X^T B X) from the Gram block and,
 // with ls, runs the line-search judgement on the result (one launch for all three).
-// Deterministic sum over a block of kFinishThreads threads (fixed tree order); valid in
-// thread 0.  sh holds kFinishThreads / kWave doubles.
 constexpr int kFinishThreads = 1024;
-
-__device__ inline double block_sum_wide(double v, double* sh) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
-  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-  if (lane == 0) sh[w] = v;
-  __syncthreads();
-  double s = 0.0;
-  if (threadIdx.x == 0)
-    for (int i = 0; i < kFinishThreads / kWave; ++i) s += sh[i];
-  __syncthreads();
-  return s;
-}
 
 __device__ inline void k_finish_eval_body(const FinishEvalArgs& ka, int ks_bid, int ks_nb) {
   const double* __restrict__ part = ka.part;
