@@ -133,12 +133,13 @@ def test_q1_energy_grad_matches_oracle(p, solver):
     assert e.orth_error < 1e-12
 
 
-def test_q1_energy_grad_fp32_storage():
+@pytest.mark.parametrize("p", [6, 80])
+def test_q1_energy_grad_fp32_storage(p):
     """X, G, grad E stored in float: energy at the rounded X matches the oracle evaluated at
     the same rounded X to 1e-10 (products accumulate in FP64); G and grad E to the float
-    rounding of their entries."""
+    rounding of their entries (p = 80: the wide FP32 kernels)."""
     K = ks()
-    spec = fe_spec(p=6, seed=31)
+    spec = fe_spec(p=p, seed=31)
     orc = oracle_q1(spec)
     X = b_orthonormalize(orc.B, synth.make_x0(spec, 2))
     e, en, G, Gr, D, Dr, mf, Xr = _compare(spec, X, "pcg_fd", K.KS_PREC_FP32)
@@ -220,11 +221,13 @@ def test_q1_minimize_matches_oracle(solver):
     assert np.min(cos) > 1 - 1e-8
 
 
-def test_q1_minimize_wide_p_first_steps_match_oracle():
-    """p = 80 (a full 64-column block and a ragged one; the gradient kernel takes 8-row
-    tiles): five steps of Alg. 3 in the B metric against the oracle's five."""
+@pytest.mark.parametrize("p", [80, 128])
+def test_q1_minimize_wide_p_first_steps_match_oracle(p):
+    """p = 80 (a full 64-column block and a ragged one) and p = 128 (two full column groups
+    of the MFMA gradient, the wide factor in LDS): five steps of Alg. 3 in the B metric
+    against the oracle's five."""
     K = ks()
-    spec = fe_spec(16, 14, 13, p=80, M=6, seed=12, h=0.6)
+    spec = fe_spec(16, 14, 13, p=p, M=6, seed=12, h=0.6)
     orc = oracle_q1(spec)
     mf = BStiefel(orc.B, orc.mass_solve)
     X0 = synth.make_x0(spec, 4)

@@ -595,11 +595,13 @@ def devf(a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
 
 
-def test_fp32_energy_grad_matches_oracle_on_rounded_input():
+@pytest.mark.parametrize("p", [6, 100])
+def test_fp32_energy_grad_matches_oracle_on_rounded_input(p):
     """Energies are computed in FP64 from the FP32 data, so they match the oracle applied to
-    the FP32-rounded X to FP64 accuracy; G and grad E are rounded to FP32 on store."""
+    the FP32-rounded X to FP64 accuracy; G and grad E are rounded to FP32 on store.  p = 100
+    takes the 64-column sub-block Gram and combine kernels in FP32 storage."""
     K = ks()
-    spec = spec_small(p=6, seed=50)
+    spec = spec_small(p=p, seed=50)
     X = synth.make_x0(spec, 4).astype(np.float32)
     Xd = X.astype(np.float64)
     sysg = K.system_from_spec(spec, precision=K.KS_PREC_FP32)
@@ -619,9 +621,10 @@ def test_fp32_energy_grad_matches_oracle_on_rounded_input():
 
 
 @pytest.mark.parametrize("kind", ["qr", "wy"])
-def test_fp32_retract_matches_oracle_on_rounded_input(kind):
+@pytest.mark.parametrize("p", [5, 100])
+def test_fp32_retract_matches_oracle_on_rounded_input(kind, p):
     K = ks()
-    spec = spec_small(p=5, seed=51)
+    spec = spec_small(p=p, seed=51)
     X = synth.make_x0(spec, 5).astype(np.float32)
     orc = oracle_fd(spec)
     _, G, _ = orc.energy_grad(X.astype(np.float64))
