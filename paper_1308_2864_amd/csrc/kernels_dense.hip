@@ -20,6 +20,8 @@
 // reproducible run to run.
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 #include "ks_common.h"
 
 namespace ks {
@@ -627,6 +629,9 @@ void launch_gram_t(const T* A, const T* B, int ld, int n, int p, int mask, doubl
   if (mask & kPBB) launch_gram_m<T, kT, 4>(A, B, ld, n, p, part, nchunks, st);
 }
 
+// set_launch_events: per host thread, consumed by the next single-kernel combine launch
+thread_local hipEvent_t g_launch_start = nullptr, g_launch_stop = nullptr;
+
 template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad,
           bool kGram2 = false, bool kUpper = false>
 void launch_combine_t(const CombineArgs& a, hipStream_t st) {
@@ -637,6 +642,15 @@ void launch_combine_t(const CombineArgs& a, hipStream_t st) {
                                 lds),
                             true);
   (void)attr;
+  if (g_launch_start) {
+    // the dispatch itself records the events: the kernel's own start and end
+    hipEvent_t e0 = g_launch_start, e1 = g_launch_stop;
+    g_launch_start = g_launch_stop = nullptr;
+    hipExtLaunchKernelGGL((k_combine<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2, kUpper>),
+                          dim3(combine_blocks(a.n)), dim3(256), (std::uint32_t)lds, st, e0, e1,
+                          0u, a);
+    return;
+  }
   hipLaunchKernelGGL((k_combine<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2, kUpper>),
                      dim3(combine_blocks(a.n)), dim3(256), lds, st, a);
 }
@@ -785,6 +799,11 @@ void launch_combine_tiled(const CombineArgs& a, hipStream_t st) {
   }
   if (a.rho)
     launch_density<T>(static_cast<const T*>(a.out), a.ld, a.n, p, a.rho_scale, a.rho, st);
+}
+
+void set_launch_events(hipEvent_t start, hipEvent_t stop) {
+  g_launch_start = start;
+  g_launch_stop = stop;
 }
 
 void launch_combine(const CombineArgs& a, hipStream_t st) {

@@ -465,6 +465,21 @@ void tend(ks_system* s, int ph) {
   tcommit(s, ph);
 }
 
+// Times a phase that is one combine launch by the launch's own dispatch (no event packets
+// around it); false when the phase is not timed.  Close it with tcommit.
+bool tbeg_launch(ks_system* s, int ph) {
+  if (!s->timers || !((s->timer_mask >> ph) & 1u)) return false;
+  ks_system::Pending p{take_event(s), take_event(s), ph};
+  if (!p.a || !p.b) {
+    if (p.a) s->ev_free.push_back(p.a);
+    if (p.b) s->ev_free.push_back(p.b);
+    return false;
+  }
+  set_launch_events(p.a, p.b);
+  s->ev_open[ph] = p;
+  return true;
+}
+
 // Accumulates every finished pair (called after stream synchronisations).
 void harvest(ks_system* s) {
   std::vector<ks_system::Pending> keep;
@@ -628,9 +643,16 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
   ca.ld = s->p;
   ca.n = s->n;
   ca.p = s->p;
-  tbeg(s, KS_PH_GRADIENT);
+  // one launch up to 64 columns: timed by its own dispatch
+  const bool exact = s->pp <= 64 && tbeg_launch(s, KS_PH_GRADIENT);
+  if (!exact) tbeg(s, KS_PH_GRADIENT);
   launch_combine(ca, s->st);
-  tend(s, KS_PH_GRADIENT);
+  if (exact) {
+    set_launch_events(nullptr, nullptr);
+    tcommit(s, KS_PH_GRADIENT);
+  } else {
+    tend(s, KS_PH_GRADIENT);
+  }
   const int mask2 = kGramAB | kGramBB;
   if (want_gxd && !fused) {
     tbeg(s, KS_PH_GRAM);

@@ -464,6 +464,9 @@ struct CombineArgs {
   int pk;                               // columns of X and Y to contract over (0: p)
 };
 void launch_combine(const CombineArgs& a, hipStream_t st);
+// Events for the next single-kernel combine launch of this host thread: that launch records
+// them from its own dispatch (its exact start and end), and clears them.
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
 // Blocks of scalar partials a combine launch sequence writes per slot (more than one set
 // of blocks when p > 64: one per 64-column output block).
 int combine_partial_blocks(int n, int p);
