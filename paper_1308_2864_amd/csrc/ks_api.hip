@@ -40,7 +40,7 @@ constexpr int kPartStride = 4096;  // >= blocks of every streaming kernel
 // argument records of the batched trial kernels: one 256-byte slot per kernel and parity
 enum Rec {
   R_QR, R_RETRACT, R_RESID, R_PLANE1, R_FDZ, R_PLANE2, R_INIT, R_FIN_INIT, R_XC, R_HX, R_GRAM1,
-  R_RED1, R_GRAD, R_RED2, R_FINISH, R_COUNT
+  R_RED1, R_GRAD, R_RED2, R_FINISH, R_QR_NEXT, R_COUNT
 };
 constexpr size_t kRecSlot = 256;
 constexpr size_t kRecBytes = 2 * R_COUNT * kRecSlot;
@@ -1037,6 +1037,11 @@ void fill_typed(ks_system* s, std::vector<char>& buf, int c) {
   // retraction: X_t = X_c A + D_c B with the density (QR weights)
   put_rec(buf, c, R_QR, QrFactor2dArgs{s->gxg[c], s->gxd[c], s->p, s->pp, &s->ls->tau, s->A,
                                         s->B, &s->ls->error});
+  // the factor of the trial after a trial from slot c, queued before the host reads the
+  // record: slot t when that trial is accepted, slot c otherwise (QrFactor2dArgs::sel)
+  put_rec(buf, c, R_QR_NEXT, QrFactor2dArgs{s->gxg[t], s->gxd[t], s->p, s->pp, &s->ls->tau,
+                                             s->A, s->B, &s->ls->error, s->ls, s->gxg[c],
+                                             s->gxd[c]});
   CombineArgs rt{};
   rt.X = s->X[c];
   rt.A = s->A;
@@ -1127,6 +1132,7 @@ namespace ks {
 struct BatchMember {
   ks_system* s = nullptr;
   MinRun m;
+  bool queued = false;  // the QR factor of its next trial is already on the engine stream
   void* tag = nullptr;
   int code = KS_OK;
   ks_result r{};
@@ -1134,6 +1140,7 @@ struct BatchMember {
 
 struct BatchEngine {
   hipStream_t st = nullptr;
+  hipEvent_t ev = nullptr;  // end of the record copy of a tick
   std::vector<BatchMember*> act;
   std::vector<BatchMember*> fin;
 };
@@ -1164,8 +1171,17 @@ void launch_trial_batch(const std::vector<BatchMember*>& g, hipStream_t st) {
   const int pp = g[0]->s->pp;
   int pmax = 0;
   for (auto* m : g) pmax = std::max(pmax, m->s->p);
-  auto qr = table<QrFactor2dArgs>(g, R_QR, one, &tot);
-  launch_qr_factor_batch(qr, pmax <= 16 ? 16 : 32, st);
+  // the factor of members whose factor was queued at the end of the last tick is in place
+  std::vector<BatchMember*> fresh;
+  for (auto* m : g)
+    if (!m->queued) fresh.push_back(m);
+  for (auto* m : g) m->queued = false;
+  if (!fresh.empty()) {
+    int pf = 0;
+    for (auto* m : fresh) pf = std::max(pf, m->s->p);
+    auto qr = table<QrFactor2dArgs>(fresh, R_QR, one, &tot);
+    launch_qr_factor_batch(qr, pf <= 16 ? 16 : 32, st);
+  }
   auto cb = [](const ks_system* s) { return combine_blocks(s->n); };
   auto rt = table<CombineArgs>(g, R_RETRACT, cb, &tot);
   launch_combine_retract_batch<T>(rt, pp, tot, st);
@@ -1234,6 +1250,7 @@ BatchEngine* batch_create(hipStream_t st) {
 
 void batch_destroy(BatchEngine* e) {
   if (!e) return;
+  if (e->ev) (void)hipEventDestroy(e->ev);
   for (auto* m : e->act) delete m;
   for (auto* m : e->fin) delete m;
   delete e;
@@ -1297,13 +1314,34 @@ int batch_tick(BatchEngine* e) {
   char* hstage = static_cast<char*>(lead->host) + 1024;
   hipError_t he = hipMemcpyAsync(hstage, lead->gstage, (size_t)ga.S * kGatherBytes,
                                  hipMemcpyDeviceToHost, e->st);
-  if (he == hipSuccess) he = hipStreamSynchronize(e->st);
+  // the QR factors of every member's next trial go behind the copy; each picks its slot
+  // from its own line-search record on the device, and the host waits for the copy only
+  if (he == hipSuccess && !e->ev) he = hipEventCreateWithFlags(&e->ev, hipEventDisableTiming);
+  if (he == hipSuccess) he = hipEventRecord(e->ev, e->st);
+  if (he == hipSuccess) {
+    int tot = 0, pm = 0;
+    for (auto* m : e->act) pm = std::max(pm, m->s->p);
+    launch_qr_factor_batch(table<QrFactor2dArgs>(e->act, R_QR_NEXT, one, &tot),
+                           pm <= 16 ? 16 : 32, e->st);
+    he = hipEventSynchronize(e->ev);
+  }
   int rc = hip_check(lead, he, "batch read-back");
   if (rc) return rc;
+  bool pending = false;
+  for (int i = 0; i < ga.S; ++i) {
+    std::memcpy(e->act[i]->s->host, hstage + (size_t)i * kGatherBytes, kGatherBytes);
+    pending = pending || host_ls(e->act[i]->s)->hartree_pending;
+  }
+  // a pending member is re-evaluated on its own stream: the queued factors (which return at
+  // once for it) finish first
+  if (pending) {
+    rc = hip_check(lead, hipStreamSynchronize(e->st), "batch factor wait");
+    if (rc) return rc;
+  }
   std::vector<BatchMember*> keep;
   for (int i = 0; i < ga.S; ++i) {
     BatchMember* m = e->act[i];
-    std::memcpy(m->s->host, hstage + (size_t)i * kGatherBytes, kGatherBytes);
+    m->queued = !host_ls(m->s)->hartree_pending;
     m->s->cg_par = 0;  // the host state a lone trial leaves (no PCG iteration queued)
     int code = run_after_trial(m->s, &m->m, true);
     const LsState* hl = host_ls(m->s);
