@@ -93,6 +93,7 @@ struct ks_system {
   void* host = nullptr;
   std::string err;
   int last_cg_iters = 0;
+  int pcg_extra = 0;  // PCG iterations queued after the exact step (1 once a trial went pending)
   long long cg_total = 0;
   // optional phase timers
   struct Pending {
@@ -561,7 +562,10 @@ int hartree(ks_system* s, const double* rho, const double* x0, double* x, bool w
     launch_fd_correct(s->cg_r, x0, x, s->cg_q, fd_ops(s), s->grid, s->st);
     launch_hartree_init(rho, x, nullptr, s->cg_r, s->cg_p[0], s->cg, s->htol, s->hmaxit, 1,
                         s->grid, s->cgpart, s->st);
-    return hartree_iterate(s, x, 0, wait, iters, relres);
+    // pcg_extra: a run whose exact steps miss the tolerance (large grids: eps cond(L) above
+    // it) queues one more PCG iteration with each solve, so that its trials do not come back
+    // pending (the iteration exits at once when the solve has converged)
+    return hartree_iterate(s, x, s->pcg_extra, wait, iters, relres);
   }
   launch_hartree_init(rho, x0, x, s->cg_r, s->cg_p[0], s->cg, s->htol, s->hmaxit, 0, s->grid,
                       s->cgpart, s->st);
@@ -913,6 +917,7 @@ int run_begin(ks_system* s, void* X_inout, const ks_opt_params* o, MinRun* m) {
   m->qr = prm.retraction == KS_QR;
   m->X_inout = X_inout;
   s->cg_total = 0;
+  s->pcg_extra = 0;  // each run starts from the same solver settings
   drop_graphs(s);  // graphs hold the parameters of the run that captured them
   int c = s->cur;
   m->c = c;
@@ -944,7 +949,11 @@ int run_after_trial(ks_system* s, MinRun* m, bool cg_read) {
   if (cg_read && !hl->hartree_pending) s->cg_total += host_cg(s)->it;
   if (hl->hartree_pending) {
     // the queued PCG iteration did not reach the tolerance; finish the solve and evaluate
-    // the trial again
+    // the trial again, and queue one more iteration with the solves of later trials
+    if (!s->pcg_extra) {
+      s->pcg_extra = 1;
+      drop_graphs(s);
+    }
     int rc = hartree_iterate(s, s->vh[t], 2, true, nullptr, nullptr);
     if (rc) return rc;
     rc = evaluate_tail(s, t, c, m->qr, !m->qr, &m->lp);
