@@ -474,6 +474,29 @@ def test_minimize_p512_first_steps_match_oracle():
     assert r.terms.orth_error < 1e-11
 
 
+@pytest.mark.parametrize("solver", ["cg", "pcg_fd"])
+def test_minimize_wide_planes_first_steps_match_oracle(solver):
+    """128 x 120 x 20 (planes of the widest transform, S_x read from L2): three steps of
+    Alg. 3 against the oracle's three, with the plain CG solver and with the fast
+    diagonalisation (whose exact steps meet the 1e-13 residual test on this grid)."""
+    K = ks()
+    spec = synth.make_system(128, 120, 20, 0.3, 4, 3, seed=4, zrange=(1, 3), margin=1.5,
+                             min_spacing=1.0)
+    X0 = synth.make_x0(spec, 2)
+    sysg = K.system_from_spec(spec, hartree_solver=K.KS_HARTREE_CG if solver == "cg"
+                              else K.KS_HARTREE_PCG_FD,
+                              **({"hartree_tol": 1e-14} if solver == "cg" else {}))
+    X = dev(X0)
+    r = sysg.ks_minimize(X, K.ks_default_params(eps_g=1e-12, stagnation_tol=0.0, max_iter=3))
+    orc = oracle_fd(spec)
+    ref = optm.minimize(orc.energy_grad, X0, optm.Params(eps_g=1e-12, stagnation_tol=0.0,
+                                                         max_iter=3))
+    assert r.iters == ref.iters == 3 and r.nfe == ref.nfe
+    assert abs(r.energy - ref.E) <= 1e-10 * abs(ref.E)
+    assert abs(r.grad_norm - ref.gnorm) <= 1e-7 * ref.gnorm
+    assert np.max(np.abs(host(X) - ref.X)) <= 1e-8
+
+
 def test_minimize_ragged_p5():
     K = ks()
     spec = spec_small(15, 12, 10, p=5, M=2, seed=31, h=0.6)
