@@ -93,7 +93,8 @@ struct ks_system {
   void* host = nullptr;
   std::string err;
   int last_cg_iters = 0;
-  int pcg_extra = 0;  // PCG iterations queued after the exact step (1 once a trial went pending)
+  int pcg_extra = 0;     // PCG iterations queued after the exact step of a trial's solve
+  bool pcg_probe = false;  // the first trial of a run queues one to see whether it is needed
   long long cg_total = 0;
   // optional phase timers
   struct Pending {
@@ -917,7 +918,10 @@ int run_begin(ks_system* s, void* X_inout, const ks_opt_params* o, MinRun* m) {
   m->qr = prm.retraction == KS_QR;
   m->X_inout = X_inout;
   s->cg_total = 0;
-  s->pcg_extra = 0;  // each run starts from the same solver settings
+  // each run starts from the same solver settings: its first trial queues one PCG
+  // iteration after the exact step, and whether that iteration ran decides the rest
+  s->pcg_extra = 1;
+  s->pcg_probe = true;
   drop_graphs(s);  // graphs hold the parameters of the run that captured them
   int c = s->cur;
   m->c = c;
@@ -950,6 +954,7 @@ int run_after_trial(ks_system* s, MinRun* m, bool cg_read) {
   if (hl->hartree_pending) {
     // the queued PCG iteration did not reach the tolerance; finish the solve and evaluate
     // the trial again, and queue one more iteration with the solves of later trials
+    s->pcg_probe = false;
     if (!s->pcg_extra) {
       s->pcg_extra = 1;
       drop_graphs(s);
@@ -961,6 +966,15 @@ int run_after_trial(ks_system* s, MinRun* m, bool cg_read) {
     rc = readback(s, hl, s->ls);
     if (rc) return rc;
     if (hl->hartree_pending) return fail(s, KS_E_NOT_CONVERGED, "Hartree solve did not converge");
+  } else if (cg_read && s->pcg_probe) {
+    // the first trial of the run: keep the queued iteration only if it had to run (the
+    // exact step counts as iteration 1; a converged solve skips the rest)
+    s->pcg_probe = false;
+    const int need = host_cg(s)->it > 1 ? 1 : 0;
+    if (need != s->pcg_extra) {
+      s->pcg_extra = need;
+      drop_graphs(s);
+    }
   }
   if (hl->error) return KS_OK;
   if (hl->accepted) {
