@@ -802,6 +802,34 @@ void launch_qr_factor(const double* xx, const double* gxd, int p, int pp, const 
                      gxd, p, pp, tau, A, B, lds ? nullptr : work, status);
 }
 
+// C = A + B W for p x p blocks (stride pp; FP64): 16 x 16 output tiles, the contraction in
+// 16-wide slices staged through LDS.  Used to form X^T D = X^T G + (X^T X) W (and
+// X^T B D = X^T G + (X^T B X) W) from blocks already reduced, instead of a Gram pass over D.
+__global__ __launch_bounds__(256) void k_small_gemm_add(const double* __restrict__ A,
+                                                        const double* __restrict__ B,
+                                                        const double* __restrict__ W,
+                                                        double* __restrict__ C, int p, int pp) {
+  __shared__ double Bs[16][17], Ws[16][17];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int i = blockIdx.y * 16 + ty, j = blockIdx.x * 16 + tx;
+  double acc = 0.0;
+  for (int k0 = 0; k0 < p; k0 += 16) {
+    Bs[ty][tx] = (i < p && k0 + tx < p) ? B[(size_t)i * pp + k0 + tx] : 0.0;
+    Ws[ty][tx] = (k0 + ty < p && j < p) ? W[(size_t)(k0 + ty) * pp + j] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc += Bs[ty][k] * Ws[k][tx];
+    __syncthreads();
+  }
+  if (i < p && j < p) C[(size_t)i * pp + j] = A[(size_t)i * pp + j] + acc;
+}
+
+void launch_small_gemm_add(const double* A, const double* B, const double* W, double* C, int p,
+                           int pp, hipStream_t st) {
+  const int t = (p + 15) / 16;
+  hipLaunchKernelGGL(k_small_gemm_add, dim3(t, t), dim3(256), 0, st, A, B, W, C, p, pp);
+}
+
 void launch_qr_factor_next(const QrFactor2dArgs& a, hipStream_t st) {
   if (a.p <= 16)
     hipLaunchKernelGGL(k_qr_factor_2d<16>, dim3(1), dim3(qr_threads<16>()), 0, st, a);

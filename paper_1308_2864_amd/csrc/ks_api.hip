@@ -661,7 +661,15 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
   const int mask2 = kGramAB | kGramBB;
   if (want_gxd && !fused) {
     tbeg(s, KS_PH_GRAM);
-    gram_reduced(s, Xs, s->D[idx], mask2, s->gxd[idx], nullptr);
+    if (s->pp > 64) {
+      // X^T D = X^T G + (X^T X) W from the blocks already reduced; only D^T D is a pass
+      const int pp2 = s->pp * s->pp;
+      gram_reduced(s, Xs, s->D[idx], kGramBB, s->gxd[idx], nullptr);
+      launch_small_gemm_add(s->gxg[idx] + pp2, s->gxg[idx], s->W, s->gxd[idx] + pp2, s->p,
+                            s->pp, s->st);
+    } else {
+      gram_reduced(s, Xs, s->D[idx], mask2, s->gxd[idx], nullptr);
+    }
     tend(s, KS_PH_GRAM);
   }
   tbeg(s, KS_PH_SMALL);
@@ -726,7 +734,13 @@ int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd, const LsP
   tend(s, KS_PH_GRADIENT);
   if (want_gxd) {
     tbeg(s, KS_PH_GRAM);
-    gram_reduced(s, Xs, s->BD[idx], kGramAB, s->gxd[idx], nullptr);
+    if (s->pp > 64) {
+      // X^T BD = X^T G + (X^T B X) W from the blocks already reduced
+      launch_small_gemm_add(s->gxg[idx] + pp2, s->feg[idx] + pp2, s->W, s->gxd[idx] + pp2,
+                            s->p, s->pp, s->st);
+    } else {
+      gram_reduced(s, Xs, s->BD[idx], kGramAB, s->gxd[idx], nullptr);
+    }
     // D^T BD lands in product slot 2 of gxd
     gram_reduced(s, s->D[idx], s->BD[idx], kGramAB, s->gxd[idx] + pp2, nullptr, true);
     tend(s, KS_PH_GRAM);

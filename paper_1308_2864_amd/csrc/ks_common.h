@@ -535,6 +535,9 @@ struct FinishEvalArgs {
 void launch_grad_weights(const double* gram, int pp, double* W, hipStream_t st);
 void launch_qr_factor(const double* xx, const double* gxd, int p, int pp, const double* tau,
                       double* A, double* B, double* work, int* status, hipStream_t st);
+// C = A + B W (p x p blocks of stride pp, FP64; C may not alias B or W).
+void launch_small_gemm_add(const double* A, const double* B, const double* W, double* C, int p,
+                           int pp, hipStream_t st);
 // The p <= 64 factor in its speculative form (see QrFactor2dArgs::sel).
 void launch_qr_factor_next(const QrFactor2dArgs& a, hipStream_t st);
 void launch_wy_factor(const double* gram_xg, int p, int pp, const double* tau,
