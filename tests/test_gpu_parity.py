@@ -661,6 +661,28 @@ def test_fp32_retract_matches_oracle_on_rounded_input(kind, p):
     assert np.max(np.abs(host(out) - ref)) <= 2e-7 * np.max(np.abs(ref))
 
 
+def test_fp32_wide_p_first_steps_track_oracle():
+    """FP32 storage at p = 100 (64-column sub-blocks, X^T D from the reduced blocks): four
+    steps of Alg. 3 from the float-rounded start stay within the float rounding of the FP64
+    oracle's four steps (each retraction rounds X to float: ~6e-8 relative)."""
+    K = ks()
+    spec = synth.make_system(14, 13, 12, 0.6, 100, 8, seed=6, zrange=(2, 4), margin=1.5,
+                             min_spacing=1.0)
+    X0 = synth.make_x0(spec, 7).astype(np.float32)
+    sysg = K.system_from_spec(spec, hartree_solver=K.KS_HARTREE_PCG_FD,
+                              precision=K.KS_PREC_FP32)
+    X = devf(X0)
+    r = sysg.ks_minimize(X, K.ks_default_params(eps_g=1e-12, stagnation_tol=0.0, max_iter=4))
+    orc = oracle_fd(spec)
+    ref = optm.minimize(orc.energy_grad, X0.astype(np.float64),
+                        optm.Params(eps_g=1e-12, stagnation_tol=0.0, max_iter=4))
+    assert r.iters == ref.iters == 4
+    assert abs(r.energy - ref.E) <= 1e-7 * abs(ref.E)
+    assert abs(r.grad_norm - ref.gnorm) <= 1e-6 * ref.gnorm
+    assert np.max(np.abs(host(X) - ref.X)) <= 1e-5
+    assert r.terms.orth_error < 1e-5
+
+
 def test_fp32_minimize_reaches_fp64_energy():
     """The FP32-storage run ends within 1e-6 Ha of the FP64 oracle minimum."""
     K = ks()
