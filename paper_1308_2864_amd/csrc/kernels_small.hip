@@ -200,6 +200,7 @@ __global__ __launch_bounds__(kQrWideThreads) void k_qr_factor_wide(
   __shared__ int bad;
   double* M = work_base(glob);
   const int t = threadIdx.x, nt = blockDim.x;
+  const int lane = t % kWave, wv = t / kWave, nw = nt / kWave;
   const double tau = *tau_p;
   const double* XD = gxd + (size_t)pp * pp;
   const double* DD = gxd + 2 * (size_t)pp * pp;
@@ -229,10 +230,10 @@ __global__ __launch_bounds__(kQrWideThreads) void k_qr_factor_wide(
       rk[j] = v;
     }
     __syncthreads();
-    const int m = p - k - 1;
-    for (int e = t; e < m * m; e += nt) {
-      const int i = k + 1 + e / m, j = k + 1 + e % m;
-      if (j >= i) M[i * p + j] -= rk[i] * rk[j];
+    // upper triangle of the trailing block: a wavefront per row, lanes along the row
+    for (int i = k + 1 + wv; i < p; i += nw) {
+      const double ri = rk[i];
+      for (int j = i + lane; j < p; j += kWave) M[i * p + j] -= ri * rk[j];
     }
     __syncthreads();
   }
@@ -245,10 +246,10 @@ __global__ __launch_bounds__(kQrWideThreads) void k_qr_factor_wide(
     }
     for (int i = t; i < k; i += nt) ck[i] = M[i * p + k];
     __syncthreads();
-    const int m = p - k;
-    for (int e = t; e < k * m; e += nt) {
-      const int i = e / m, j = k + e % m;
-      M[i * p + j] = (j == k ? 0.0 : M[i * p + j]) - ck[i] * rk[j];
+    for (int i = wv; i < k; i += nw) {
+      const double ci = ck[i];
+      for (int j = k + lane; j < p; j += kWave)
+        M[i * p + j] = (j == k ? 0.0 : M[i * p + j]) - ci * rk[j];
     }
     __syncthreads();
   }
