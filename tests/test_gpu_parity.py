@@ -497,6 +497,27 @@ def test_minimize_wide_planes_first_steps_match_oracle(solver):
     assert np.max(np.abs(host(X) - ref.X)) <= 1e-8
 
 
+def test_minimize_with_backtracking_matches_oracle():
+    """A first step far too long (tau0 = 20) is rejected and backtracked: the next trial's QR
+    factor, queued before the host has read the judgement, must then take the current
+    point's Gram blocks.  Eight steps against the oracle's eight, backtracks included."""
+    K = ks()
+    spec = synth.make_system(17, 13, 11, 0.55, 5, 3, seed=21, zrange=(1, 3), margin=1.5,
+                             min_spacing=1.0)
+    X0 = synth.make_x0(spec, 3)
+    sysg = K.system_from_spec(spec, hartree_solver=K.KS_HARTREE_PCG_FD)
+    X = dev(X0)
+    r = sysg.ks_minimize(X, K.ks_default_params(tau0=20.0, eps_g=1e-12, stagnation_tol=0.0,
+                                                max_iter=8))
+    orc = oracle_fd(spec)
+    ref = optm.minimize(orc.energy_grad, X0, optm.Params(tau0=20.0, eps_g=1e-12,
+                                                         stagnation_tol=0.0, max_iter=8))
+    assert ref.backtracks >= 1
+    assert (r.iters, r.nfe, r.backtracks) == (ref.iters, ref.nfe, ref.backtracks)
+    assert abs(r.energy - ref.E) <= 1e-12 * abs(ref.E)
+    assert np.max(np.abs(host(X) - ref.X)) <= 1e-9
+
+
 def test_minimize_ragged_p5():
     K = ks()
     spec = spec_small(15, 12, 10, p=5, M=2, seed=31, h=0.6)
