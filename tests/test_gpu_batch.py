@@ -36,9 +36,12 @@ def _lone(K, spec, prec, prm):
     return r, X.cpu().numpy()
 
 
-def test_batch_equals_lone_runs_bitwise():
+@pytest.mark.parametrize("tau0", [1e-3, 20.0])
+def test_batch_equals_lone_runs_bitwise(tau0):
+    """tau0 = 20: first steps far too long, rejected and backtracked (the QR factors queued
+    behind each tick's record copy then take the current points' blocks)."""
     K = ks()
-    prm = K.ks_default_params(max_iter=300)
+    prm = K.ks_default_params(max_iter=300, tau0=tau0)
     specs = _specs()
     precs = [K.KS_PREC_FP64 if i % 3 else K.KS_PREC_FP32 for i in range(len(specs))]
     systems, blocks = [], []
@@ -57,6 +60,9 @@ def test_batch_equals_lone_runs_bitwise():
         assert res[i].energy == r.energy, spec.name
         assert res[i].hartree_iters_total == r.hartree_iters_total, spec.name
         assert np.array_equal(blocks[i].cpu().numpy(), X), spec.name
+        assert res[i].backtracks == r.backtracks, spec.name
+    if tau0 > 1.0:
+        assert any(x.backtracks > 0 for x in res)
 
 
 def test_batch_rejects_what_it_cannot_run():
