@@ -261,6 +261,225 @@ __global__ __launch_bounds__(kQrWideThreads) void k_qr_factor_wide(
   }
 }
 
+// Blocked form for p > 128 (the matrix in global memory): 64-column blocks; one workgroup
+// factors and inverts each diagonal block in LDS (pivots judged against the saved
+// diagonal, as above), the panel R_KJ = R_KK^-T M_KJ and the trailing update
+// M_IJ -= R_KI^T R_KJ are multi-workgroup products, and W = R^-1 follows by row blocks from
+// the bottom, W_I = R_II^-1 (E_I - sum_{K > I} R_IK W_K).  A breakdown sets a flag that
+// every later step reads, and A, B are then left untouched.
+constexpr int kWB = 64;
+
+__global__ void k_wf_assemble(const double* __restrict__ xx, const double* __restrict__ gxd,
+                              int p, int pp, const double* __restrict__ tau_p,
+                              double* __restrict__ M, double* __restrict__ R,
+                              double* __restrict__ d0, double* __restrict__ flag) {
+  const double tau = *tau_p;
+  const double* XD = gxd + (size_t)pp * pp;
+  const double* DD = gxd + 2 * (size_t)pp * pp;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < (size_t)p * p;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / p), j = (int)(e % p);
+    const double v =
+        xx[i * pp + j] - tau * (XD[i * pp + j] + XD[j * pp + i]) + tau * tau * DD[i * pp + j];
+    M[e] = v;
+    R[e] = 0.0;
+    if (i == j) d0[i] = v;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 0.0;
+}
+
+// Cholesky and inverse of diagonal block K (b = min(64, p - 64 K) columns) in LDS.
+__global__ __launch_bounds__(1024) void k_wf_diag(const double* __restrict__ M, int p, int K,
+                                                  const double* __restrict__ d0,
+                                                  double* __restrict__ R, double* __restrict__ Ri,
+                                                  double* __restrict__ flag, int* status) {
+  __shared__ double S[kWB][kWB + 1];
+  __shared__ double rk[kWB], ck[kWB];
+  __shared__ int bad;
+  if (*flag != 0.0) return;
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int lane = t % kWave, wv = t / kWave, nw = nt / kWave;
+  const int k0 = K * kWB, b = min(kWB, p - k0);
+  for (int e = t; e < kWB * kWB; e += nt) {
+    const int i = e / kWB, j = e % kWB;
+    S[i][j] = (i < b && j < b) ? M[(size_t)(k0 + i) * p + k0 + j] : 0.0;
+  }
+  if (t == 0) bad = 0;
+  __syncthreads();
+  for (int k = 0; k < b; ++k) {
+    if (t == 0) {
+      const double d = S[k][k];
+      if (!(d > kPivotTol * d0[k0 + k]) || !isfinite(d)) bad = 1;
+      else S[k][k] = sqrt(d);
+    }
+    __syncthreads();
+    if (bad) {
+      if (t == 0) {
+        *flag = 1.0;
+        *status = KS_E_NOT_SPD;
+      }
+      return;
+    }
+    const double rkk = S[k][k];
+    for (int j = k + 1 + t; j < b; j += nt) {
+      const double v = S[k][j] / rkk;
+      S[k][j] = v;
+      rk[j] = v;
+    }
+    __syncthreads();
+    for (int i = k + 1 + wv; i < b; i += nw) {
+      const double ri = rk[i];
+      for (int j = i + lane; j < b; j += kWave) S[i][j] -= ri * rk[j];
+    }
+    __syncthreads();
+  }
+  // R_KK (upper, zero below) into R
+  for (int e = t; e < b * b; e += nt) {
+    const int i = e / b, j = e % b;
+    R[(size_t)(k0 + i) * p + k0 + j] = j >= i ? S[i][j] : 0.0;
+  }
+  __syncthreads();
+  // R_KK^-1 in place (right-looking elimination from the last row)
+  for (int k = b - 1; k >= 0; --k) {
+    const double inv = 1.0 / S[k][k];
+    for (int j = k + t; j < b; j += nt) {
+      const double w = j == k ? inv : S[k][j] * inv;
+      rk[j] = w;
+      S[k][j] = w;
+    }
+    for (int i = t; i < k; i += nt) ck[i] = S[i][k];
+    __syncthreads();
+    for (int i = wv; i < k; i += nw) {
+      const double ci = ck[i];
+      for (int j = k + lane; j < b; j += kWave) S[i][j] = (j == k ? 0.0 : S[i][j]) - ci * rk[j];
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < kWB * kWB; e += nt) {
+    const int i = e / kWB, j = e % kWB;
+    Ri[e] = (i < b && j < b && j >= i) ? S[i][j] : 0.0;
+  }
+}
+
+// C (m x n, ldc) = beta C + alpha op(A) B with op(A)[i][k] = A[k][i] (transA) or A[i][k];
+// 16 x 16 output tiles, 16-wide contraction slices through LDS.  Nothing when *flag is set.
+struct WfGemm {
+  const double* A;
+  int lda;
+  int transA;
+  const double* B;
+  int ldb;
+  double* C;
+  int ldc;
+  int m, n, k;
+  double alpha, beta;
+  const double* flag;
+};
+
+__global__ __launch_bounds__(256) void k_wf_gemm(WfGemm g) {
+  __shared__ double As[16][17], Bs[16][17];
+  if (*g.flag != 0.0) return;
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int i = blockIdx.y * 16 + ty, j = blockIdx.x * 16 + tx;
+  const int ia = blockIdx.y * 16 + tx;  // row of op(A) this thread stages (transposed load)
+  double acc = 0.0;
+  for (int k0 = 0; k0 < g.k; k0 += 16) {
+    if (g.transA) {
+      // op(A)[ia][k0 + ty] = A[k0 + ty][ia]: lanes along ia read contiguous memory
+      As[tx][ty] = (ia < g.m && k0 + ty < g.k) ? g.A[(size_t)(k0 + ty) * g.lda + ia] : 0.0;
+    } else {
+      As[ty][tx] = (i < g.m && k0 + tx < g.k) ? g.A[(size_t)i * g.lda + k0 + tx] : 0.0;
+    }
+    Bs[ty][tx] = (k0 + ty < g.k && j < g.n) ? g.B[(size_t)(k0 + ty) * g.ldb + j] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) acc += As[ty][kk] * Bs[kk][tx];
+    __syncthreads();
+  }
+  if (i < g.m && j < g.n) {
+    double* c = g.C + (size_t)i * g.ldc + j;
+    *c = (g.beta == 0.0 ? 0.0 : g.beta * *c) + g.alpha * acc;
+  }
+}
+
+// Rows 64 I .. of the identity (b x p): the right-hand side of a row block of R W = I.
+__global__ void k_wf_eye(double* __restrict__ T, int b, int p, int I,
+                         const double* __restrict__ flag) {
+  if (*flag != 0.0) return;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < (size_t)b * p;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e / p), c = (int)(e % p);
+    T[e] = c == kWB * I + r ? 1.0 : 0.0;
+  }
+}
+
+__global__ void k_wf_store(const double* __restrict__ W, int p, int pp,
+                           const double* __restrict__ tau_p, double* __restrict__ A,
+                           double* __restrict__ B, const double* __restrict__ flag) {
+  if (*flag != 0.0) return;
+  const double tau = *tau_p;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < (size_t)pp * pp;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / pp), j = (int)(e % pp);
+    const double w = (i < p && j < p && j >= i) ? W[(size_t)i * p + j] : 0.0;
+    A[e] = w;
+    B[e] = -tau * w;
+  }
+}
+
+void wf_gemm(const WfGemm& g, hipStream_t st) {
+  if (g.m <= 0 || g.n <= 0) return;
+  hipLaunchKernelGGL(k_wf_gemm, dim3((g.n + 15) / 16, (g.m + 15) / 16), dim3(256), 0, st, g);
+}
+
+// The blocked factor; work holds 3 p^2 + 129 p + 4096 doubles (within small_work_doubles).
+void launch_qr_factor_blocked(const double* xx, const double* gxd, int p, int pp,
+                              const double* tau, double* A, double* B, double* work,
+                              int* status, hipStream_t st) {
+  const int nb = (p + kWB - 1) / kWB;
+  const size_t p2 = (size_t)p * p;
+  double* M = work;
+  double* R = M + p2;
+  double* W = R + p2;
+  double* T = W + p2;                       // kWB x p
+  double* Ri = T + (size_t)kWB * p;         // nb blocks of kWB x kWB
+  double* d0 = Ri + (size_t)nb * kWB * kWB; // p
+  double* flag = d0 + p;
+  const int eb = (int)std::min<size_t>((p2 + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_wf_assemble, dim3(eb), dim3(256), 0, st, xx, gxd, p, pp, tau, M, R, d0,
+                     flag);
+  for (int K = 0; K < nb; ++K) {
+    const int k0 = K * kWB, b = std::min(kWB, p - k0), r0 = k0 + b, rest = p - r0;
+    double* RiK = Ri + (size_t)K * kWB * kWB;
+    hipLaunchKernelGGL(k_wf_diag, dim3(1), dim3(1024), 0, st, M, p, K, d0, R, RiK, flag,
+                       status);
+    if (rest <= 0) continue;
+    // panel: R[k0.., r0..] = R_KK^-T M[k0.., r0..]
+    wf_gemm(WfGemm{RiK, kWB, 1, M + (size_t)k0 * p + r0, p, R + (size_t)k0 * p + r0, p, b, rest,
+                   b, 1.0, 0.0, flag},
+            st);
+    // trailing: M[r0.., r0..] -= R[k0.., r0..]^T R[k0.., r0..]
+    wf_gemm(WfGemm{R + (size_t)k0 * p + r0, p, 1, R + (size_t)k0 * p + r0, p,
+                   M + (size_t)r0 * p + r0, p, rest, rest, b, -1.0, 1.0, flag},
+            st);
+  }
+  for (int I = nb - 1; I >= 0; --I) {
+    const int i0 = I * kWB, b = std::min(kWB, p - i0), r0 = i0 + b, rest = p - r0;
+    const int tb = (int)std::min<size_t>(((size_t)b * p + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_wf_eye, dim3(tb), dim3(256), 0, st, T, b, p, I, flag);
+    if (rest > 0)  // T -= R[i0.., r0..] W[r0.., :]
+      wf_gemm(WfGemm{R + (size_t)i0 * p + r0, p, 0, W + (size_t)r0 * p, p, T, p, b, p, rest,
+                     -1.0, 1.0, flag},
+              st);
+    // W[i0.., :] = R_II^-1 T
+    wf_gemm(WfGemm{Ri + (size_t)I * kWB * kWB, kWB, 0, T, p, W + (size_t)i0 * p, p, b, p, b, 1.0,
+                   0.0, flag},
+            st);
+  }
+  const int sb = (int)std::min<size_t>(((size_t)pp * pp + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_wf_store, dim3(sb), dim3(256), 0, st, W, p, pp, tau, A, B, flag);
+}
+
 // Element-parallel variant for p <= P (P = 16, 32, 64): the P x P matrix Y^T Y lives in
 // registers, a few elements per thread (qr_threads threads), and both the
 // right-looking Cholesky and the back substitution for R^{-1} run as p rank-1 steps in
@@ -789,6 +1008,10 @@ void launch_qr_factor(const double* xx, const double* gxd, int p, int pp, const 
   if (p <= 64) {
     hipLaunchKernelGGL(k_qr_factor_2d<64>, dim3(1), dim3(qr_threads<64>()), 0, st,
                        QrFactor2dArgs{xx, gxd, p, pp, tau, A, B, status});
+    return;
+  }
+  if (p > 128) {
+    launch_qr_factor_blocked(xx, gxd, p, pp, tau, A, B, work, status, st);
     return;
   }
   // M (p x p) in LDS when it fits beside the static arrays; the attribute value does not
