@@ -276,7 +276,7 @@ def test_energy_grad_nonfinite_input():
 # ------------------------------------------------------------------------------------------
 
 @pytest.mark.parametrize("kind", ["qr", "wy"])
-@pytest.mark.parametrize("p", [1, 5, 32])
+@pytest.mark.parametrize("p", [1, 5, 17, 29, 32])
 def test_retract(kind, p):
     K = ks()
     spec = spec_small(p=p, seed=20 + p)
@@ -329,12 +329,13 @@ def test_retract_wide_factor_in_global_memory(kind, p, shape):
     assert np.max(np.abs(Y.T @ Y - np.eye(p))) < 1e-11
 
 
-def test_retract_rank_deficient_reports_cholesky_breakdown():
+@pytest.mark.parametrize("p", [3, 24])
+def test_retract_rank_deficient_reports_cholesky_breakdown(p):
     K = ks()
-    spec = spec_small(p=3)
+    spec = spec_small(p=p)
     sysg = K.system_from_spec(spec)
     X = synth.make_x0(spec, 5)
-    X[:, 2] = X[:, 1]
+    X[:, p - 1] = X[:, 1]
     G = np.zeros_like(X)
     out = torch.zeros_like(dev(X))
     with pytest.raises(K.KSError) as ei:
