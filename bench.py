@@ -78,8 +78,9 @@ def cpu_baseline(spec, X0, gpu_iters, iters):
 
 def c4_leg(ks, synth, iters, seed, hartree="pcg_fd"):
     """The largest single-system workload (128^3 grid, n = 2097152, p = 512): seconds per
-    iteration of Alg. 3 for FP64 and FP32 storage of the orbital blocks (blocks wider than 64
-    columns run as 64-column sub-blocks), and the FP32 energy error against FP64 after the
+    iteration of Alg. 3 for FP64 and FP32 storage of the orbital blocks and for FP32 storage
+    with X^T G on the bf16 matrix cores (blocks wider than 64 columns run as 64-column
+    sub-blocks), and the FP32 and BF16 energy errors against FP64 after the
     same iterations.  The start block is the seeded N(0,1) block orthonormalised on the
     device by two Cholesky-QR passes (the QR retraction at tau = 0 with G = 0); a host
     Householder QR of 2097152 x 512 takes minutes.  The Hartree potential uses the fast
@@ -90,14 +91,16 @@ def c4_leg(ks, synth, iters, seed, hartree="pcg_fd"):
     spec = synth.make_config("c4", seed)
     n, p = spec.n, spec.p
     solver = ks.KS_HARTREE_CG if hartree == "cg" else ks.KS_HARTREE_PCG_FD
-    out = {"workload": f"{spec.name} (FP64 and FP32 storage, {hartree} Hartree)",
+    out = {"workload": f"{spec.name} (FP64, FP32 storage, FP32 storage with BF16 Gram, "
+                       f"{hartree} Hartree)",
            "grid": [spec.nx, spec.ny, spec.nz], "n": n, "p": p, "iterations": iters}
     t0 = time.perf_counter()
     X0 = torch.tensor(synth.make_random_block(n, p, seed=seed, cfg="c4"), dtype=torch.float64,
                       device="cuda")
     energies = {}
     for name, prec, dt in (("fp64", ks.KS_PREC_FP64, torch.float64),
-                           ("fp32", ks.KS_PREC_FP32, torch.float32)):
+                           ("fp32", ks.KS_PREC_FP32, torch.float32),
+                           ("bf16", ks.KS_PREC_MIXED_BF16, torch.float32)):
         sysg = ks.system_from_spec(spec, hartree_solver=solver, precision=prec)
         if name == "fp64":
             zero = torch.zeros_like(X0)
@@ -113,16 +116,26 @@ def c4_leg(ks, synth, iters, seed, hartree="pcg_fd"):
         r = sysg.ks_minimize(X, ks.ks_default_params(max_iter=iters), check=False)
         torch.cuda.synchronize()
         el = time.perf_counter() - t1
-        sysg.close()
-        del X
         energies[name] = r.energy
         ent = {"s_per_iteration": round(el / max(r.iters, 1), 4),
                "s_per_evaluation": round(el / max(r.nfe, 1), 4), "iterations": r.iters,
                "evaluations": r.nfe, "energy": r.energy, "grad_norm": r.grad_norm,
-               "hartree_iters": r.hartree_iters_total}
+               "hartree_iters": r.hartree_iters_total, "orth_error": r.terms.orth_error}
+        if name == "bf16":
+            # X^T G in bf16 perturbs each retraction off the manifold by O(tau |dX^T G|);
+            # one Cholesky-QR pass with the exact X^T X (untimed) takes X back before the
+            # energy is compared
+            zero = torch.zeros_like(X)
+            tmp = torch.empty_like(X)
+            sysg.ks_retract(X, zero, 0.0, ks.KS_QR, tmp)
+            energies[name] = ent["energy_reorthonormalised"] = sysg.ks_energy_grad(tmp).total
+            del zero, tmp
+        sysg.close()
+        del X
         print(f"# c4 {name}: {ent}", file=sys.stderr, flush=True)
         out[name] = ent
     out["fp32_energy_error_vs_fp64_Ha"] = abs(energies["fp32"] - energies["fp64"])
+    out["bf16_energy_error_vs_fp64_Ha"] = abs(energies["bf16"] - energies["fp64"])
     del X0
     torch.cuda.empty_cache()
     return out

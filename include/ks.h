@@ -68,7 +68,12 @@ extern "C" {
 
 #define KS_PREC_FP64 0           /* everything in double                                  */
 #define KS_PREC_FP32 1           /* X, G stored/applied in float; reductions in double    */
-#define KS_PREC_MIXED_BF16 2     /* as FP32, Gram products in bf16 MFMA, fp32 accumulate  */
+#define KS_PREC_MIXED_BF16 2     /* as FP32; X^T G of blocks wider than 64 columns on bf16
+                                    matrix cores with fp32 sums (other products exact).
+                                    Each retraction then leaves X off the manifold by
+                                    O(tau |error of X^T G|): re-orthonormalise (ks_retract
+                                    with tau = 0, G = 0 uses the exact X^T X) before an
+                                    energy is compared.  Not accepted by the server.       */
 
 #define KS_TERM_EXT 1            /* external (nuclear) potential                          */
 #define KS_TERM_HARTREE 2        /* Hartree potential                                     */

@@ -22,6 +22,8 @@ for electronic structure calculations"):
 * ``fe``      trilinear (Q1) finite elements on a uniform hexahedral mesh with
               the consistent mass matrix B and the B-orthonormality constraint
               (Section 2.3 finite-element form, Section 3 eq. (OFDFT-y)).
+* ``precision`` bfloat16 rounding and the Gram blocks of rounded operands (the
+              tall-skinny products of Section 3 in a reduced-precision mode).
 
 Everything is float64 and written for clarity, not speed: no blocking, fusion or
 reordering beyond what the definitions state.

@@ -21,6 +21,7 @@
 #include <algorithm>
 
 #include <hip/hip_ext.h>
+#include <type_traits>
 
 #include "ks_common.h"
 
@@ -820,10 +821,98 @@ int combine_partial_blocks(int n, int p) {
   return combine_blocks(n) * (round_up(p, 16) > kSubCols ? sub_blocks(p) : 1);
 }
 
+// ---- BF16 Gram sub-product (KS_PREC_MIXED_BF16) ---------------------------------------
+// L[:, 0:pa]^T R[:, 0:pb] over one chunk of rows on the bf16 matrix cores (16 x 16 x 16,
+// fp32 accumulation); L and R are stored in float and rounded to nearest-even bf16 in
+// registers.  Lane l of a wavefront on the rows g0 .. g0 + 15 holds rows g0 + 4 (l / 16) + e
+// (e < 4) of column 16 t + l % 16: the A operand of tile t of L^T and the B operand of tile
+// t of R alike.  A wavefront sums its 16-row groups in fp32; the four wavefronts are added
+// in a fixed order in fp64, and the 64 x 64 tile goes to the slot of the fp64 kernel's
+// A^T B partial, so the reduction and placement that follow are shared.
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline short bf16_rne(float x) {
+  const unsigned u = __float_as_uint(x);
+  return (short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+__global__ __launch_bounds__(256) void k_gram_bf16(GramArgs<float> ka) {
+  const float* __restrict__ L = ka.A;
+  const float* __restrict__ R = ka.B;
+  const int ld = ka.ld, n = ka.n, pa = ka.p, pb = ka.pb ? ka.pb : ka.p;
+  extern __shared__ double lds[];
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int lr = lane / 16, lc = lane % 16;
+  const int ngroups = (n + 15) / 16;
+  const int per = (ngroups + (int)gridDim.x - 1) / (int)gridDim.x;
+  const int g_beg = (int)blockIdx.x * per, g_end = min(ngroups, g_beg + per);
+  f32x4 acc[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  struct Raw {
+    float a[4][4], b[4][4];  // [tile][row e]
+  };
+  auto load = [&](Raw& f, int grp) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = grp * 16 + 4 * lr + e;
+      const bool rok = grp < g_end && row < n;
+      const size_t roff = (size_t)(rok ? row : 0) * ld;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int col = 16 * t + lc;
+        f.a[t][e] = (rok && col < pa) ? L[roff + col] : 0.f;
+        f.b[t][e] = (rok && col < pb) ? R[roff + col] : 0.f;
+      }
+    }
+  };
+  auto products = [&](const Raw& f) {
+    bf16x4 a[4], b[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        a[t][e] = bf16_rne(f.a[t][e]);
+        b[t][e] = bf16_rne(f.b[t][e]);
+      }
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj)
+        acc[ti * 4 + tj] =
+            __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[ti], b[tj], acc[ti * 4 + tj], 0, 0, 0);
+  };
+  int grp = g_beg + w;
+  Raw f0, f1;
+  if (grp < g_end) load(f0, grp);
+  while (grp < g_end) {
+    if (grp + 4 < g_end) load(f1, grp + 4);
+    products(f0);
+    grp += 4;
+    if (grp >= g_end) break;
+    if (grp + 4 < g_end) load(f0, grp + 4);
+    products(f1);
+    grp += 4;
+  }
+  double* o = ka.part + ((size_t)blockIdx.x * 3 + 1) * kSubCols * kSubCols;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    d4 v = d4{acc[t][0], acc[t][1], acc[t][2], acc[t][3]};
+    wave_reduce_tile(v, lds, w, lane);
+    if (w == 0) {
+      const int ti = t / 4, tj = t % 4;
+      // fp32 result layout: register r of lane l is row 4 (l / 16) + r, column l % 16
+#pragma unroll
+      for (int r = 0; r < 4; ++r) o[(ti * 16 + 4 * lr + r) * kSubCols + tj * 16 + lc] = v[r];
+    }
+  }
+}
+
 template <typename T>
 void launch_gram_full_t(const T* A, const T* B, int ld, int n, int p, int mask,
                         double* partials, double* sub, double* out, double* W, hipStream_t st,
-                        bool sym_ab) {
+                        bool sym_ab, int bf16_mask) {
   const int pp = round_up(p, 16), nb = sub_blocks(p), nch = gram_chunks(n, kSubCols);
   const size_t lds = (size_t)3 * 4 * 64 * sizeof(double);
   for (int prod = 0; prod < 3; ++prod) {
@@ -837,9 +926,19 @@ void launch_gram_full_t(const T* A, const T* B, int ld, int n, int p, int mask,
       for (int J = sym ? I : 0; J < nb; ++J) {
         const int pa = std::min(kSubCols, p - kSubCols * I);
         const int pb = std::min(kSubCols, p - kSubCols * J);
-        hipLaunchKernelGGL((k_gram<T, 4, kPAB>), dim3(nch), dim3(256), lds, st,
-                           GramArgs<T>{L + kSubCols * I, R + kSubCols * J, ld, n, pa, partials,
-                                       pb});
+        bool done = false;
+        if constexpr (std::is_same<T, float>::value) {
+          if ((bf16_mask >> prod) & 1) {
+            hipLaunchKernelGGL(k_gram_bf16, dim3(nch), dim3(256), lds, st,
+                               GramArgs<float>{L + kSubCols * I, R + kSubCols * J, ld, n, pa,
+                                               partials, pb});
+            done = true;
+          }
+        }
+        if (!done)
+          hipLaunchKernelGGL((k_gram<T, 4, kPAB>), dim3(nch), dim3(256), lds, st,
+                             GramArgs<T>{L + kSubCols * I, R + kSubCols * J, ld, n, pa, partials,
+                                         pb});
         launch_gram_reduce(partials, nch, kSubCols, kPAB, sub, nullptr, st);
         hipLaunchKernelGGL(k_gram_place, dim3(kSubCols * kSubCols / 256), dim3(256), 0, st,
                            sub + kSubCols * kSubCols, out + (size_t)prod * pp * pp, pp,
@@ -851,13 +950,13 @@ void launch_gram_full_t(const T* A, const T* B, int ld, int n, int p, int mask,
 
 void launch_gram_full(const void* A, const void* B, bool f32, int ld, int n, int p, int mask,
                       double* partials, double* sub, double* out, double* W, hipStream_t st,
-                      bool sym_ab) {
+                      bool sym_ab, int bf16_mask) {
   if (f32)
     launch_gram_full_t<float>(static_cast<const float*>(A), static_cast<const float*>(B), ld, n,
-                              p, mask, partials, sub, out, W, st, sym_ab);
+                              p, mask, partials, sub, out, W, st, sym_ab, bf16_mask);
   else
     launch_gram_full_t<double>(static_cast<const double*>(A), static_cast<const double*>(B), ld,
-                               n, p, mask, partials, sub, out, W, st, sym_ab);
+                               n, p, mask, partials, sub, out, W, st, sym_ab, 0);
 }
 
 // ---- batched launches ------------------------------------------------------------------

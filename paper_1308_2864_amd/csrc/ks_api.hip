@@ -77,6 +77,7 @@ struct ks_system {
   double *Rd = nullptr, *Zd = nullptr, *enuc = nullptr, *tau_user = nullptr;
   void *X[2] = {}, *G[2] = {}, *D[2] = {};  // float (FP32 modes) or double
   bool f32 = false;
+  bool bf16 = false;  // KS_PREC_MIXED_BF16: float storage, Gram sub-products in bf16
   int es = 8;  // bytes per orbital element
   double *gxg[2] = {}, *gxd[2] = {}, *W = nullptr, *A = nullptr, *B = nullptr;
   double *work = nullptr, *gram_part = nullptr, *spart = nullptr, *cgpart = nullptr;
@@ -200,8 +201,9 @@ int validate(const ks_system_desc* d, std::string* why) {
     *why = "the finite-element mass solve supports at most 128 nodes per axis";
     return KS_E_UNSUPPORTED;
   }
-  if (d->precision != KS_PREC_FP64 && d->precision != KS_PREC_FP32) {
-    *why = "precision must be KS_PREC_FP64 or KS_PREC_FP32";
+  if (d->precision != KS_PREC_FP64 && d->precision != KS_PREC_FP32 &&
+      d->precision != KS_PREC_MIXED_BF16) {
+    *why = "precision must be KS_PREC_FP64, KS_PREC_FP32 or KS_PREC_MIXED_BF16";
     return KS_E_UNSUPPORTED;
   }
   if (d->hartree_solver != KS_HARTREE_CG && d->hartree_solver != KS_HARTREE_PCG_FD) {
@@ -252,7 +254,8 @@ void init_dims(ks_system* s, const ks_system_desc* d) {
   s->htol = d->hartree_tol > 0.0 ? d->hartree_tol : 1e-13;
   s->hmaxit = d->hartree_maxit > 0 ? d->hartree_maxit : 5000;
   s->solver = d->hartree_solver;
-  s->f32 = d->precision == KS_PREC_FP32;
+  s->bf16 = d->precision == KS_PREC_MIXED_BF16;
+  s->f32 = d->precision == KS_PREC_FP32 || s->bf16;
   s->es = s->f32 ? 4 : 8;
   s->R.assign(d->R ? d->R : nullptr, d->R ? d->R + 3 * d->n_nuclei : nullptr);
   s->Z.assign(d->Z ? d->Z : nullptr, d->Z ? d->Z + d->n_nuclei : nullptr);
@@ -348,11 +351,17 @@ void gram(ks_system* s, const void* A, const void* B, int mask) {
 // than 64 columns run as 64-column sub-products.
 // sym_ab: A^T B is symmetric (X^T B X, D^T B D); beyond 64 columns only its blocks I <= J
 // are formed and mirrored
+// KS_PREC_MIXED_BF16 takes A^T B (the calls marked bf16_ok: X^T G) on the bf16 matrix
+// cores; every other product stays exact.  The retraction sees X^T G only through
+// X^T D + D^T X with X^T D = X^T G + (X^T X) W, W = -(X^T G)^T, where its rounding error
+// cancels to first order (X^T X = I), so the constraint does not drift; X^T X, D^T D and
+// the B-metric blocks enter the Cholesky factor directly and would.
 void gram_reduced(ks_system* s, const void* A, const void* B, int mask, double* out,
-                  double* W, bool sym_ab = false) {
+                  double* W, bool sym_ab = false, bool bf16_ok = false) {
   if (s->pp > 64) {
+    const int bf16_mask = s->bf16 && bf16_ok ? kGramAB : 0;
     launch_gram_full(A, B, s->f32, s->p, s->n, s->p, mask, s->gram_part, s->gsub, out, W,
-                     s->st, sym_ab);
+                     s->st, sym_ab, bf16_mask);
     return;
   }
   gram(s, A, B, mask);
@@ -629,7 +638,7 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
     tend(s, KS_PH_SMALL);
   } else {
     tbeg(s, KS_PH_GRAM);
-    gram_reduced(s, Xs, s->G[idx], mask1, s->gxg[idx], s->W);
+    gram_reduced(s, Xs, s->G[idx], mask1, s->gxg[idx], s->W, false, true);
     tend(s, KS_PH_GRAM);
   }
   // D = G - X (G^T X) with ||D||^2, the BB sums and (QR) the Gram blocks X^T D, D^T D:
@@ -707,7 +716,7 @@ int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd, const LsP
   mass_solve(s, s->G[idx], s->Gt[idx]);
   tend(s, KS_PH_GRADIENT);
   tbeg(s, KS_PH_GRAM);
-  gram_reduced(s, Xs, s->G[idx], kGramAB, s->gxg[idx], s->W);
+  gram_reduced(s, Xs, s->G[idx], kGramAB, s->gxg[idx], s->W, false, true);
   gram_reduced(s, Xs, s->BX[idx], kGramAB, s->feg[idx], nullptr, true);
   tend(s, KS_PH_GRAM);
   Q1GradArgs ga{};
@@ -1656,7 +1665,7 @@ int ks_gram(ks_system* s, const void* Ain, const void* Bin, double* out) {
   copy_block(s, s->X[t], s->p, Ain, s->ld);
   copy_block(s, s->G[t], s->p, Bin, s->ld);
   const int all = kGramAA | kGramAB | kGramBB;
-  gram_reduced(s, s->X[t], s->G[t], all, s->gxg[t], nullptr);
+  gram_reduced(s, s->X[t], s->G[t], all, s->gxg[t], nullptr, false, true);
   launch_compact_gram(s->gxg[t], s->pp, s->p, out, s->st);
   int rc = launch_check(s, "gram");
   return rc ? rc : hip_check(s, hipStreamSynchronize(s->st), "gram sync");
@@ -1698,7 +1707,7 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
     const int pp2 = s->pp * s->pp;
     q1_apply(s, s->X[t], nullptr, s->BX[t], nullptr, 1.0, nullptr);
     mass_solve(s, s->G[t], s->Gt[t]);
-    gram_reduced(s, s->X[t], s->G[t], kGramAB, s->gxg[t], s->W);
+    gram_reduced(s, s->X[t], s->G[t], kGramAB, s->gxg[t], s->W, false, true);
     gram_reduced(s, s->X[t], s->BX[t], kGramAB, s->feg[t], nullptr, true);
     Q1GradArgs ga{};
     ga.Gt = s->Gt[t];
@@ -1717,7 +1726,7 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
     gram_reduced(s, s->X[t], s->BD[t], kGramAB, s->gxd[t], nullptr);
     gram_reduced(s, s->D[t], s->BD[t], kGramAB, s->gxd[t] + pp2, nullptr, true);
   } else {
-    gram_reduced(s, s->X[t], s->G[t], all, s->gxg[t], s->W);
+    gram_reduced(s, s->X[t], s->G[t], all, s->gxg[t], s->W, false, true);
   }
   launch_set_scalar(s->tau_user, tau, s->st);
   int* hstat = host_int(s);

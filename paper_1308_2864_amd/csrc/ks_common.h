@@ -473,10 +473,11 @@ int combine_partial_blocks(int n, int p);
 // Reduced Gram products (mask over A^T A, A^T B, B^T B) of blocks wider than 64 columns,
 // written into out (3 x p_p x p_p, products outside the mask untouched) and, with W,
 // W = -(A^T B)^T; sub is 3 x 64 x 64 doubles of scratch.  sym_ab: A^T B is symmetric, so
-// only its blocks I <= J are formed (and mirrored).
+// only its blocks I <= J are formed (and mirrored).  bf16_mask (float storage only): the
+// products whose bit is set run on the bf16 matrix cores with fp32 accumulation.
 void launch_gram_full(const void* A, const void* B, bool f32, int ld, int n, int p, int mask,
                       double* partials, double* sub, double* out, double* W, hipStream_t st,
-                      bool sym_ab = false);
+                      bool sym_ab = false, int bf16_mask = 0);
 // Batched Gram (products kMask of [A, B], p_p <= 32), its reduction, and the two combine
 // forms of a trial: the retraction (X A + Y B with the density) and the gradient
 // (C0 + X A with the BB sums).

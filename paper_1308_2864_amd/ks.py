@@ -324,7 +324,7 @@ def ks_request_bytes(desc) -> int:
     ws = ks_workspace_bytes(desc)
     if ws == 0:
         raise KSError(KS_E_INVAL, lib.ks_last_error(None).decode())
-    es = 4 if desc.precision == KS_PREC_FP32 else 8
+    es = 4 if desc.precision in (KS_PREC_FP32, KS_PREC_MIXED_BF16) else 8
     x = desc.nx * desc.ny * desc.nz * desc.p * es  # the server keeps blocks dense
     return (ws + 255) // 256 * 256 + (x + 255) // 256 * 256
 
@@ -353,7 +353,7 @@ class KSServer:
         self._out = {}
 
     def ks_server_submit(self, rid, desc, X0, params=None, want_X=False):
-        dt = np.float32 if desc.precision == KS_PREC_FP32 else np.float64
+        dt = np.float32 if desc.precision in (KS_PREC_FP32, KS_PREC_MIXED_BF16) else np.float64
         X0 = np.ascontiguousarray(X0, dtype=dt)
         n = desc.nx * desc.ny * desc.nz
         if X0.shape != (n, desc.p):

@@ -755,3 +755,35 @@ def test_minimize_c2_matches_tight_oracle_reference():
     assert r.stop_reason in (K.KS_STOP_GRAD, K.KS_STOP_STAGNATION)
     assert abs(r.energy - gold["E"]) <= 1e-10 * abs(gold["E"])
     assert r.terms.orth_error < 1e-12
+
+@pytest.mark.parametrize("p", [80, 130])
+def test_bf16_gram_matches_rounded_oracle(p):
+    """KS_PREC_MIXED_BF16 forms A^T B (X^T G) of blocks wider than 64 columns on the bf16
+    matrix cores; A^T A and B^T B stay as in FP32 storage (exact products, FP64 sums).
+    Against the exact FP64 Gram of the bf16-rounded operands the only
+    difference is the fp32 accumulation of each wavefront's rows: at most m fp32 roundings
+    of a partial sum bounded by sum |a b|, m <= 1024 rows per chain at every size the
+    library chunks, so |err| <= (m + 16) 2^-24 (|A|^T |B|) elementwise.  Ragged p (two and
+    three 64-column sub-blocks) and a row count that is not a multiple of 16."""
+    from oracle import precision
+    K = ks()
+    spec = spec_small(13, 11, 10, p=p, seed=70 + p)
+    sysg = K.system_from_spec(spec, precision=K.KS_PREC_MIXED_BF16)
+    rng = np.random.default_rng(p)
+    A = rng.standard_normal((spec.n, p)).astype(np.float32)
+    B = rng.standard_normal((spec.n, p)).astype(np.float32)
+    out = torch.zeros(3 * p * p, dtype=torch.float64, device="cuda")
+    sysg.ks_gram(devf(A), devf(B), out)
+    got = host(out).reshape(3, p, p)
+    ref = precision.gram_blocks_bf16(A, B)
+    Ar, Br = np.abs(precision.round_bf16(A)), np.abs(precision.round_bf16(B))
+    bound = ((1024 + 16) * 2.0**-24) * np.stack([Ar.T @ Ar, Ar.T @ Br, Br.T @ Br])
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    f32ref = np.stack([A64.T @ A64, A64.T @ B64, B64.T @ B64])
+    assert np.all(np.abs(got[1] - ref[1]) <= bound[1])
+    # the operands were rounded: the float products differ by far more than the bound
+    assert np.mean(np.abs(got[1] - ref[1])) < 1e-2 * np.mean(np.abs(got[1] - f32ref[1]))
+    # A^T A and B^T B from the float operands, summed in FP64
+    for k in (0, 2):
+        assert np.max(np.abs(got[k] - f32ref[k])) <= 1e-12 * np.max(np.abs(f32ref[k]))
+    sysg.close()

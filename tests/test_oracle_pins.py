@@ -355,3 +355,38 @@ def test_random_starts_reach_the_same_minimum():
                                                               max_iter=4000))
         Es.append(res.E)
     assert max(Es) - min(Es) < 1e-10 * abs(min(Es))
+
+
+# ------------------------------------------------------------------------------------------
+# bfloat16 rounding of the reduced-precision Gram mode
+# ------------------------------------------------------------------------------------------
+
+def test_round_bf16_matches_library_conversion_and_ties():
+    """round_bf16 is pinned to torch's CPU float32 -> bfloat16 conversion (round to nearest,
+    ties to even) on random values across many binades, and to hand-computed ties."""
+    import torch
+    from oracle import precision
+    rng = np.random.default_rng(3)
+    x = (rng.standard_normal(20000) * np.exp(rng.uniform(-30, 30, 20000))).astype(np.float32)
+    lib = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(precision.round_bf16(x), lib)
+    # 1 + 2^-8 lies halfway between 1 and 1 + 2^-7: ties to the even significand (1);
+    # 1 + 3 * 2^-8 lies halfway between 1 + 2^-7 and 1 + 2^-6: ties to 1 + 2^-6
+    ties = np.array([1 + 2.0**-8, 1 + 3 * 2.0**-8, -(1 + 2.0**-8), 0.0], dtype=np.float32)
+    assert list(precision.round_bf16(ties)) == [1.0, 1 + 2.0**-6, -1.0, 0.0]
+
+
+def test_gram_blocks_bf16_are_exact_products_of_rounded_operands():
+    """Products of two bfloat16 values are exact in FP64, so the Gram blocks of small-integer
+    multiples of powers of two (exactly representable) equal the plain products, and a
+    value that rounds moves its Gram entry by the rounding step."""
+    from oracle import precision
+    rng = np.random.default_rng(4)
+    A = rng.integers(-128, 128, (50, 3)).astype(np.float32) * 2.0**-7
+    B = rng.integers(-128, 128, (50, 3)).astype(np.float32) * 2.0**-5
+    aa, ab, bb = precision.gram_blocks_bf16(A, B)
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    assert np.array_equal(aa, A64.T @ A64) and np.array_equal(ab, A64.T @ B64)
+    assert np.array_equal(bb, B64.T @ B64)
+    C = np.array([[1 + 2.0**-9], [1.0]], dtype=np.float32)  # rounds to 1
+    assert precision.gram_blocks_bf16(C, C)[0][0, 0] == 2.0
