@@ -93,26 +93,44 @@ class EuclideanStiefel:
         return stiefel.cholqr(X)[0]
 
 
+def bb_candidates(ss, sy, yy):
+    """The two Barzilai-Borwein values of eq. (bb-1) from the Frobenius sums
+    ss = tr(S^T S), sy = tr(S^T Y), yy = tr(Y^T Y):
+    tau_{k,1} = ss / |sy|  and  tau_{k,2} = |sy| / yy  (inf where the divisor is zero)."""
+    tau1 = ss / abs(sy) if sy != 0.0 else float("inf")
+    tau2 = abs(sy) / yy if yy != 0.0 else float("inf")
+    return tau1, tau2
+
+
 def bb_step(k, ss, sy, yy, p: Params):
+    """Step of iteration k: tau_0 at k = 0; otherwise tau_{k,1} (rule "bb1"), tau_{k,2}
+    ("bb2") or, by default, tau_{k,1} on odd and tau_{k,2} on even k.  A value that is not
+    finite and positive becomes tau_0; the result is clamped to [tau_min, tau_max]."""
     if k == 0:
         return p.tau0
     rule = p.bb
     if rule == "alt":
         rule = "bb1" if (k % 2 == 1) else "bb2"
-    if rule == "bb1":
-        tau = ss / abs(sy) if sy != 0.0 else float("inf")
-    else:
-        tau = abs(sy) / yy if yy != 0.0 else float("inf")
+    tau1, tau2 = bb_candidates(ss, sy, yy)
+    tau = tau1 if rule == "bb1" else tau2
     if not math.isfinite(tau) or tau <= 0.0:
         tau = p.tau0
     return min(max(tau, p.tau_min), p.tau_max)
 
 
+def reference_update(C, Q, E_new, eta):
+    """Alg. 3's nonmonotone reference: Q_{k+1} = eta Q_k + 1,
+    C_{k+1} = (eta Q_k C_k + E(X_{k+1})) / Q_{k+1}.  Returns (C_{k+1}, Q_{k+1})."""
+    Qn = eta * Q + 1.0
+    return (eta * Q * C + E_new) / Qn, Qn
+
+
 def minimize(energy_grad: Callable, X0, params: Params = Params(), manifold=None, vh0=None,
-             callback=None):
+             callback=None, keep_iterates=False):
     """Run Alg. 3 from X0.  energy_grad(X, vh_warm) -> (Energy, E_X, vh).
 
-    callback(k, E, gnorm), if given, is called after every accepted iteration.
+    callback(k, E, gnorm), if given, is called after every accepted iteration.  With
+    keep_iterates the history also holds every accepted X_k (small problems only).
     """
     mf = manifold or EuclideanStiefel()
     p = params
@@ -136,6 +154,7 @@ def minimize(energy_grad: Callable, X0, params: Params = Params(), manifold=None
             stop = "maxit"
             break
         tau_bb = bb_step(k, ss, sy, yy, p)
+        tau1, tau2 = bb_candidates(ss, sy, yy) if k > 0 else (p.tau0, p.tau0)
         h = 0
         while True:
             tau = tau_bb * p.delta ** h
@@ -158,11 +177,11 @@ def minimize(energy_grad: Callable, X0, params: Params = Params(), manifold=None
         ss, sy, yy = mf.inner(S, S), mf.inner(S, Yd), mf.inner(Yd, Yd)
         Et = ent.total
         df = abs(E - Et) / (abs(E) + 1.0)
-        hist.append(dict(k=k, E=E, E_new=Et, C=C, tau=tau, h=h, g2=g2,
-                         armijo_rhs=C - p.rho1 * tau * g2))
-        Qn = p.eta * Q + 1.0
-        C = (p.eta * Q * C + Et) / Qn
-        Q = Qn
+        hist.append(dict(k=k, E=E, E_new=Et, C=C, Q=Q, tau=tau, tau_bb=tau_bb, tau1=tau1,
+                         tau2=tau2, h=h, g2=g2, armijo_rhs=C - p.rho1 * tau * g2))
+        if keep_iterates:
+            hist[-1]["X"] = X.copy()
+        C, Q = reference_update(C, Q, Et, p.eta)
         X, G, D, E, en, vh = Xt, Gt, Dt, Et, ent, vht
         g2 = mf.inner(D, D)
         k += 1
