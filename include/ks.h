@@ -273,6 +273,23 @@ int ks_get_potentials(ks_system* s, double* v_ext, double* v_h, double* v_eff);
  * p x p each) = [A^T A, A^T B, B^T B].  The tall-skinny products of Section 3. */
 int ks_gram(ks_system* s, const void* A, const void* B, double* out);
 
+/* ---- no-allocation variant ------------------------------------------------------------ */
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the Gram blocks of ks_gram without a
+ * system handle or workspace.  A, B: device n x ld blocks (double for KS_PREC_FP64, float
+ * for KS_PREC_FP32 / KS_PREC_MIXED_BF16; products always in FP64); ld = 0 means p.
+ * out (device, 3*p*p doubles, row-major p x p each) = [A^T A, A^T B, B^T B].  The call only
+ * enqueues work on hip_stream (NULL = default stream) and returns; it calls no hipMalloc,
+ * hipFree or allocating routine.  Its partial products live in one static device array of
+ * 12.7 MB per GPU, held until the process ends: limits 1 <= p <= 64, n * ld < 2^31 (at most
+ * 128 row chunks).  Calls on one GPU share that array, so calls that can overlap on the
+ * device (different streams without ordering between them) race; calls on one stream are
+ * ordered.  Errors (the message via ks_last_error(NULL)): KS_E_INVAL for sizes beyond the
+ * limits or null pointers, KS_E_HIP. */
+int ks_gram_static(const void* A, const void* B, int n, int p, int ld, int precision,
+                   double* out, void* hip_stream);
+
 /* ---- serving ---------------------------------------------------------------------------
  * A server solves independent minimisation requests concurrently on one GPU.  It owns no
  * device memory: requests are admitted in arrival order into first-fit regions of the

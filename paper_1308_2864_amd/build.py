@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libks.so")
 
 SOURCES = ["ks_api.hip", "kernels_grid.hip", "kernels_poisson.hip", "kernels_dense.hip",
            "kernels_small.hip", "kernels_fe.hip",
-           "ks_server.hip"]
+           "ks_server.hip", "ks_static.hip"]
 
 ARCH = os.environ.get("KS_OFFLOAD_ARCH", "gfx950")
 FLAGS = [

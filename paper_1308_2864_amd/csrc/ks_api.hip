@@ -36,6 +36,13 @@ bool device_range(const void* ptr, size_t bytes) {
 
 namespace {
 thread_local std::string g_err;
+}  // namespace
+
+namespace ks {
+void set_thread_error(const char* msg) { g_err = msg ? msg : ""; }
+}  // namespace ks
+
+namespace {
 constexpr int kPartStride = 4096;  // >= blocks of every streaming kernel
 // argument records of the batched trial kernels: one 256-byte slot per kernel and parity
 enum Rec {

@@ -409,6 +409,8 @@ struct Q1GradArgs {
 void launch_q1_grad(const Q1GradArgs& a, hipStream_t st);
 int q1_grad_blocks(int n, int p);
 size_t q1_grad_lds(int p);  // dynamic LDS of the gradient kernel (its weights; p <= 128)
+// Sets the message ks_last_error(NULL) returns on the calling thread.
+void set_thread_error(const char* msg);
 // True when [ptr, ptr + bytes) starts and ends inside memory the HIP runtime knows as
 // device (or managed) memory; a query the runtime refuses leaves no pending error.
 bool device_range(const void* ptr, size_t bytes);

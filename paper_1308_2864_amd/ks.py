@@ -117,6 +117,7 @@ def _load():
         "ks_apply_hamiltonian": (ip, [vp, vp, vp, vp]),
         "ks_get_potentials": (ip, [vp, vp, vp, vp]),
         "ks_gram": (ip, [vp, vp, vp, vp]),
+        "ks_gram_static": (ip, [vp, vp, ip, ip, ip, ip, vp, vp]),
         "ks_enable_timers": (ip, [vp, ip]),
         "ks_read_timers": (ip, [vp, C.POINTER(ks_phase_times), ip]),
         "ks_enable_graphs": (ip, [vp, ip]),
@@ -315,6 +316,19 @@ def ks_minimize_batch(systems, blocks, params=None):
     if rc in (KS_E_INVAL, KS_E_HIP):  # the batch itself failed; per-system codes otherwise
         _check(rc)
     return list(rs), list(codes)
+
+
+def ks_gram_static(A, B, out, stream=None):
+    """[A^T A, A^T B, B^T B] of two device n x p blocks into out (3 x p x p doubles) with the
+    library's static scratch (no allocation; see include/ks.h).  Enqueues on the stream."""
+    import torch
+    if A.shape != B.shape or A.dim() != 2 or A.dtype != B.dtype:
+        raise ValueError("A and B must be n x p blocks of one dtype")
+    n, p = A.shape
+    prec = KS_PREC_FP64 if A.dtype == torch.float64 else KS_PREC_FP32
+    st = stream or torch.cuda.current_stream(A.device)
+    _check(lib.ks_gram_static(_ptr(A), _ptr(B), int(n), int(p), int(A.stride(0)), prec,
+                              _ptr(out), C.c_void_p(st.cuda_stream)))
 
 
 def ks_request_bytes(desc) -> int:
