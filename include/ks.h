@@ -69,11 +69,13 @@ extern "C" {
 #define KS_PREC_FP64 0           /* everything in double                                  */
 #define KS_PREC_FP32 1           /* X, G stored/applied in float; reductions in double    */
 #define KS_PREC_MIXED_BF16 2     /* as FP32; X^T G of blocks wider than 64 columns on bf16
-                                    matrix cores with fp32 sums (other products exact).
-                                    Each retraction then leaves X off the manifold by
-                                    O(tau |error of X^T G|): re-orthonormalise (ks_retract
-                                    with tau = 0, G = 0 uses the exact X^T X) before an
-                                    energy is compared.  Not accepted by the server.       */
+                                    matrix cores with fp32 sums.  X^T G only sets the
+                                    direction D = G - X (X^T G)^T; the Gram blocks the
+                                    retraction factors (X^T X, X^T D, D^T D) are products
+                                    of the stored blocks, so X stays orthonormal to the
+                                    float rounding of its entries.  The gradient norm then
+                                    carries the bf16 error of X^T G: stop on
+                                    energy_target.  Not accepted by the server.          */
 
 #define KS_TERM_EXT 1            /* external (nuclear) potential                          */
 #define KS_TERM_HARTREE 2        /* Hartree potential                                     */
@@ -95,6 +97,7 @@ extern "C" {
 #define KS_STOP_STAGNATION 2     /* mean of last three relative energy changes < tol      */
 #define KS_STOP_MAXIT 3
 #define KS_STOP_ERROR 4
+#define KS_STOP_ENERGY 5         /* an accepted energy reached energy_target               */
 
 /* ---- descriptors ------------------------------------------------------------------- */
 typedef struct ks_system_desc {
@@ -102,7 +105,7 @@ typedef struct ks_system_desc {
   int nx, ny, nz;          /* interior points per axis (>= 1)                             */
   double h;                /* grid spacing, bohr (> 0)                                    */
   double box_lo[3];        /* box corner: point (i,j,k) sits at box_lo + (i+1, j+1, k+1) h */
-  int p;                   /* orbitals (1 <= p <= 64 for FD7 in this version)             */
+  int p;                   /* orbitals: 1 <= p <= 512 (FD7), 1 <= p <= 128 (Q1)          */
   int ld;                  /* row stride of X/G/gradE in elements; 0 means p              */
   double occupation;       /* f, electrons per orbital (2 = closed shell)                 */
   int n_nuclei;            /* M >= 0                                                      */
@@ -143,6 +146,15 @@ typedef struct ks_opt_params {
   int h_max;               /* backtracks before a trial is accepted anyway (20)           */
   double reorth_tol;       /* WY: re-orthonormalise when ||X^T X - I||_F > tol (1e-12)    */
   double stagnation_tol;   /* stop when mean(df_k, df_k-1, df_k-2) < tol (1e-13); 0 = off */
+  int reorth_every;        /* > 0: every reorth_every accepted iterations, X <- X R^{-1}
+                              with X^T X = R^T R (X^T B X for Q1) formed from the stored
+                              X in FP64 (Cholesky QR, Alg. 2), the point evaluated again
+                              and the nonmonotone reference restarted there (C = E,
+                              Q = 1).  For reduced-precision storage (0 = never)          */
+  double energy_target;    /* stop (KS_STOP_ENERGY) once an accepted energy is <= this;
+                              -HUGE_VAL = off (default).  The reduced-precision modes
+                              stop on it: their gradient stalls at the float resolution
+                              of X above eps_g                                            */
 } ks_opt_params;
 
 typedef struct ks_result {
@@ -158,6 +170,18 @@ typedef struct ks_result {
   double seconds;          /* wall time of the call                                       */
   long long hartree_iters_total;
 } ks_result;
+
+/* Progress of a run after a step of the per-iteration calls below. */
+typedef struct ks_iter_info {
+  int k;                   /* accepted iterations so far                                  */
+  int nfe;                 /* energy evaluations so far                                   */
+  int backtracks;          /* rejected trial steps so far                                 */
+  int stop_reason;         /* KS_STOP_* (KS_STOP_NONE while the run goes on)              */
+  double energy;           /* E(X_k)                                                      */
+  double grad_norm;        /* ||grad E(X_k)||_F (the B-norm for KS_DISC_Q1)               */
+  double tau;              /* step of the last accepted trial (0 before the first)        */
+  double C;                /* reference value C_k of eq. (NMLS-Armijo)                    */
+} ks_iter_info;
 
 /* Phases of the device timeline measured by the optional timers (ks_enable_timers).
  * The single-kernel phases bracket exactly one kernel per occurrence. */
@@ -247,6 +271,56 @@ int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* 
  * these limits).  Returns KS_OK, or the first error other than KS_E_NOT_CONVERGED. */
 int ks_minimize_batch(ks_system* const* sys, int count, void* const* X_inout,
                       const ks_opt_params* o, ks_result* r, int* codes);
+
+/* ---- Alg. 3 one iteration at a time ------------------------------------------------------
+ * The loop of ks_minimize opened up: ks_minimize_begin does its set-up and first
+ * evaluation, ks_minimize_step one iteration of Alg. 3 (trial steps until one satisfies
+ * eq. (NMLS-Armijo) or the run stops), ks_minimize_end its finish.  The three calls run
+ * exactly the kernels and decisions of ks_minimize, so begin, any number of steps and end
+ * give ks_minimize's result bit for bit.  The run's state (the current iterate, its
+ * gradient and Gram blocks, the Hartree warm start, the line-search record C_k, Q_k, tau,
+ * and the counters) stays in the system's workspace between calls; ks_get_state copies it
+ * out and ks_set_state puts it back, on the same or another system of the same
+ * descriptor, so that a run resumed from a saved state continues bit for bit. */
+
+/* Starts a run from X0 (device n x ld block, as for ks_minimize; only read).  info (host,
+ * nullable) receives k = 0 and the first energy.  Errors as ks_minimize. */
+int ks_minimize_begin(ks_system* s, const void* X0, const ks_opt_params* o,
+                      ks_iter_info* info);
+
+/* One iteration: trial steps until one is accepted or a stopping rule fires; a stopped
+ * run returns at once.  info (host, nullable) receives the progress.  Errors: KS_E_INVAL
+ * (no run in progress), the device errors of ks_minimize (the run is then over). */
+int ks_minimize_step(ks_system* s, ks_iter_info* info);
+
+/* Ends the run: X_out (device n x ld block, nullable = not copied) receives the current
+ * iterate and r (host, nullable) the statistics, as ks_minimize returns them.  Returns
+ * KS_OK, KS_E_NOT_CONVERGED at max_iter, or the run's error. */
+int ks_minimize_end(ks_system* s, void* X_out, ks_result* r);
+
+/* Bytes of a saved run state of this system (header plus the device records above). */
+size_t ks_state_bytes(ks_system* s);
+
+/* Copies the state of the run in progress into buf (host or device memory of
+ * ks_state_bytes(s) bytes, owned by the caller).  Synchronous.  Errors: KS_E_INVAL (no run
+ * in progress), KS_E_HIP. */
+int ks_get_state(ks_system* s, void* buf);
+
+/* Makes the run saved in buf the run in progress of s (whose descriptor must give the same
+ * discretisation, precision, n and p; any run in progress is dropped).  Continue with
+ * ks_minimize_step / ks_minimize_end.  Errors: KS_E_INVAL (not a state, or one of another
+ * shape), KS_E_HIP. */
+int ks_set_state(ks_system* s, const void* buf);
+
+/* One trial step for each listed run in lockstep (1..16 systems, each with a run begun by
+ * ks_minimize_begin and inside the limits of ks_minimize_batch; runs that have stopped
+ * are skipped): one launch per kernel for all of them, as ks_minimize_batch does, on the
+ * first system's stream.  Each run takes the decisions of its lone trial, so stepping the
+ * batch to the end gives every member its lone ks_minimize result bit for bit.  info
+ * (host, count entries, nullable) receives every member's progress; info[i].k tells
+ * whether its trial was accepted.  Errors: KS_E_INVAL, KS_E_UNSUPPORTED (a run outside the
+ * limits; nothing is launched), the first member error. */
+int ks_batch_step(ks_system* const* sys, int count, ks_iter_info* info);
 
 /* ---- step-level calls (each is one step of ks_energy_grad) -------------------------- */
 

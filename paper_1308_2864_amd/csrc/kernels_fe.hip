@@ -123,8 +123,7 @@ __device__ inline void q1_sums(const Q1Plane& L, int r, int lx, int lc, double P
 template <typename T, bool kG, bool kEnergy>
 __global__ __launch_bounds__(256) void k_q1_apply(const T* __restrict__ X, T* __restrict__ Y,
                                                   T* __restrict__ BX,
-                                                  const double* __restrict__ veff,
-                                                  const double* __restrict__ vext, Grid gr,
+                                                  const double* __restrict__ veff, Grid gr,
                                                   int p, double scale, Q1Coef cf,
                                                   Partials pt) {
   __shared__ Q1Plane L[2];
@@ -133,7 +132,7 @@ __global__ __launch_bounds__(256) void k_q1_apply(const T* __restrict__ X, T* __
   const Q1Tiles nt = q1_tiles(gr, p);
   const size_t total = nt.total();
   const double h3 = gr.dV;
-  double kin = 0.0, ext = 0.0;
+  double kin = 0.0;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   for (size_t tile = lb; tile < total; tile += gridDim.x) {
     // tile -> (orbital tile, x tile, y tile, z chunk), orbital tile fastest
@@ -184,10 +183,7 @@ __global__ __launch_bounds__(256) void k_q1_apply(const T* __restrict__ X, T* __
           const size_t o = g * p + c;
           if (kG) Y[o] = (T)(scale * (0.5 * ax + h3 * veff[g] * s0));
           BX[o] = (T)bx;
-          if (kEnergy) {
-            kin += s0 * ax;
-            ext += h3 * vext[g] * s0 * s0;
-          }
+          if (kEnergy) kin += s0 * ax;
         }
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
@@ -200,9 +196,7 @@ __global__ __launch_bounds__(256) void k_q1_apply(const T* __restrict__ X, T* __
   }
   if (kEnergy) {
     kin = block_sum(kin, sh);
-    ext = block_sum(ext, sh);
     write_partial(pt, SL_KIN, lb, kin);
-    write_partial(pt, SL_EXT, lb, ext);
   }
 }
 
@@ -467,19 +461,19 @@ size_t q1_grad_lds(int p) {
 }
 
 template <typename T>
-void launch_q1_apply(const T* X, T* G, T* BX, const double* veff, const double* vext, Grid g,
+void launch_q1_apply(const T* X, T* G, T* BX, const double* veff, Grid g,
                      int p, double scale, Partials* pt, hipStream_t st) {
   const int nb = q1_apply_blocks(g, p);
   const Q1Coef cf = q1_coef(g.h);
   if (G && pt)
     hipLaunchKernelGGL((k_q1_apply<T, true, true>), dim3(nb), dim3(kBlock), 0, st, X, G, BX,
-                       veff, vext, g, p, scale, cf, *pt);
+                       veff, g, p, scale, cf, *pt);
   else if (G)
     hipLaunchKernelGGL((k_q1_apply<T, true, false>), dim3(nb), dim3(kBlock), 0, st, X, G, BX,
-                       veff, vext, g, p, scale, cf, Partials{nullptr, 0});
+                       veff, g, p, scale, cf, Partials{nullptr, 0});
   else
     hipLaunchKernelGGL((k_q1_apply<T, false, false>), dim3(nb), dim3(kBlock), 0, st, X, G, BX,
-                       veff, vext, g, p, scale, cf, Partials{nullptr, 0});
+                       veff, g, p, scale, cf, Partials{nullptr, 0});
 }
 
 void launch_mass_setup(double* tab, int N, double h, hipStream_t st) {
@@ -517,10 +511,10 @@ void launch_q1_grad(const Q1GradArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((k_q1_grad<double, false>), dim3(nb), dim3(kQ1Threads), lds, st, a);
 }
 
-template void launch_q1_apply<double>(const double*, double*, double*, const double*,
-                                      const double*, Grid, int, double, Partials*, hipStream_t);
-template void launch_q1_apply<float>(const float*, float*, float*, const double*, const double*,
-                                     Grid, int, double, Partials*, hipStream_t);
+template void launch_q1_apply<double>(const double*, double*, double*, const double*, Grid,
+                                      int, double, Partials*, hipStream_t);
+template void launch_q1_apply<float>(const float*, float*, float*, const double*, Grid, int,
+                                     double, Partials*, hipStream_t);
 template void launch_mass_solve<double>(const double*, double*, int, Grid, const double* const*,
                                         hipStream_t);
 template void launch_mass_solve<float>(const float*, float*, int, Grid, const double* const*,

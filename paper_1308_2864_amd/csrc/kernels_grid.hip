@@ -135,7 +135,10 @@ __global__ __launch_bounds__(256) void k_density(const T* __restrict__ X, int ld
   if (g < (size_t)n && sub == 0) rho[g] = scale * s;
 }
 
-// ---- Slater exchange, effective potential, Hartree/exchange energy partials ------------
+// ---- Slater exchange, effective potential, Hartree/exchange/external energy partials ---
+// The external energy h^3 sum V_ext rho is summed here, from the density of the evaluated
+// block (formed from its stored values), rather than as sum V_ext X^2 in the Hamiltonian
+// pass: the same number up to summation order, without a V_ext stream in the stencil.
 
 __device__ inline void k_xc_body(const XcArgs& ka, int ks_bid, int ks_nb) {
   const double* __restrict__ rho = ka.rho;
@@ -157,9 +160,10 @@ __device__ inline void k_xc_body(const XcArgs& ka, int ks_bid, int ks_nb) {
   // (3/4)(3/pi)^{1/3} and (3/pi)^{1/3}
   const double cv = cbrt(3.0 / kPi), cx = 0.75 * cv;
   const bool trivial = use_h && cg != nullptr && cg->bb == 0.0;  // rho == 0: V_H = 0
-  double eh = 0.0, ex = 0.0;
+  double eh = 0.0, ex = 0.0, ee = 0.0;
   for (size_t g = beg + threadIdx.x; g < end; g += blockDim.x) {
     const double r = rho[g];
+    const double ve = vext[g];
     const double h = (use_h && !trivial) ? vh[g] : 0.0;
     double vx = 0.0, e = 0.0;
     if (use_x) {
@@ -167,14 +171,17 @@ __device__ inline void k_xc_body(const XcArgs& ka, int ks_bid, int ks_nb) {
       vx = -cv * c;
       e = -cx * c;
     }
-    veff[g] = vext[g] + h + vx;
+    veff[g] = ve + h + vx;
     eh += r * h;
     ex += r * e;
+    ee += r * ve;
   }
   eh = block_sum(eh, sh);
   ex = block_sum(ex, sh);
+  ee = block_sum(ee, sh);
   write_partial(pt, SL_EH, lb, eh);
   write_partial(pt, SL_EX, lb, ex);
+  write_partial(pt, SL_EXT, lb, ee);
 }
 
 __global__ void k_xc(XcArgs ka) {
@@ -189,15 +196,20 @@ __global__ void k_xc_batch(BatchPtrs<XcArgs> b) {
 
 // ---- Hamiltonian on the orbital block -----------------------------------------------
 // Y = scale * ((1/2) L X + Diag(veff) X), L = -Laplacian_h (7 points, zero Dirichlet).
-// With pt: per-block partials of sum X.(LX) and sum vext X^2 (kinetic/external energy).
+// With pt: per-block partials of sum X.(LX) (kinetic energy).
 
-// A thread owns kW orbitals (a column pair when p, ld are even and the blocks are
-// pair-aligned) of one grid column (i, j) over kHxChunk consecutive planes.  The centre
-// values of those planes and of the two planes around them are loaded first, so the z
-// neighbours come from registers and each output needs only its four in-plane
-// neighbours; all loads are branch-free (clamped addresses, zero outside the grid).
-// Consecutive threads take consecutive orbitals of one point.
+// A lane owns kW orbitals (a column pair when p, ld are even and the blocks are
+// pair-aligned) of one grid column; consecutive lanes take consecutive orbitals of one
+// point, then the next point, so a wavefront covers 64 consecutive (point, orbital group)
+// entries of a plane and each of its loads is one contiguous segment.  A work item is such
+// a wavefront slice over a run of kRun planes (16, or 8 when runs of 16 would leave
+// wavefronts without an item), marched as in the Gram-fused form below: a software
+// pipeline kHxPlainDepth planes deep issues the loads of plane k + kHxPlainDepth (centre
+// one plane further, the four in-plane neighbours, V_eff) while plane k is computed, the
+// z neighbours come from registers, and the run is unrolled completely.  All loads are
+// branch-free (clamped addresses, zero outside the grid).
 constexpr int kHxChunk = 8;
+constexpr int kHxPlainDepth = 4;
 
 template <typename T, int kW>
 struct HxVec {
@@ -209,175 +221,222 @@ struct HxVec<T, 1> {
 };
 
 template <typename T, int kW>
-__device__ inline void hx_load(const T* ptr, bool ok, double (&v)[kW]) {
-  const typename HxVec<T, kW>::type w = *reinterpret_cast<const typename HxVec<T, kW>::type*>(ptr);
+__device__ inline double hx_elem(const typename HxVec<T, kW>::type& v, int e) {
   if constexpr (kW == 1) {
-    v[0] = ok ? (double)w : 0.0;
+    (void)e;
+    return (double)v;
   } else {
-#pragma unroll
-    for (int e = 0; e < kW; ++e) v[e] = ok ? (double)w[e] : 0.0;
+    return (double)v[e];
   }
 }
 
-template <typename T, bool kEnergy, int kW>
-__device__ inline void hx_items(const HxArgs<T>& ka, int lb, int nblk, double& kin,
-                                double& ext) {
+template <typename T, bool kEnergy, int kW, int kRun>
+__device__ inline void hx_items_run(const HxArgs<T>& ka, int lb, int nblk, double& kin) {
+  typedef typename HxVec<T, kW>::type V;
   const T* __restrict__ X = ka.X;
-  const int ldx = ka.ldx, ldy = ka.ldy;
   T* __restrict__ Y = ka.Y;
+  const int ldx = ka.ldx, ldy = ka.ldy;
   const double* __restrict__ veff = ka.veff;
-  const double* __restrict__ vext = ka.vext;
   const Grid gr = ka.gr;
-  const int nx = gr.nx, ny = gr.ny, nz = gr.nz;
+  const int nx = gr.nx, ny = gr.ny, nz = gr.nz, nxy = nx * ny;
   const int pw = ka.p / kW;
-  const int nzc = (nz + kHxChunk - 1) / kHxChunk;
-  const size_t work = (size_t)nx * ny * pw * nzc;
-  const ptrdiff_t sy = (ptrdiff_t)nx * ldx, sz = (ptrdiff_t)nx * ny * ldx;
+  const int cols = nxy * pw;  // (point, orbital group) entries per plane
+  const int groups = (cols + kWave - 1) / kWave;
+  const int items = groups * ((nz + kRun - 1) / kRun);
+  // element offsets fit 31 bits (n * ld < 2^31 is checked at system creation)
+  const int sy = nx * ldx, szx = nxy * ldx, szy = nxy * ldy;
   const double ih2 = gr.inv_h2, scale = ka.scale;
-  for (size_t t = (size_t)lb * blockDim.x + threadIdx.x; t < work;
-       t += (size_t)nblk * blockDim.x) {
-    const int c = (int)(t % (unsigned)pw) * kW;
-    size_t r = t / (unsigned)pw;
-    const int i = (int)(r % nx);
-    r /= nx;
-    const int j = (int)(r % ny);
-    const int k0 = (int)(r / ny) * kHxChunk;
-    const int k1 = min(k0 + kHxChunk, nz);
-    const T* col = X + (ptrdiff_t)(i + (size_t)nx * j) * ldx + c;
-    double zc[kHxChunk + 2][kW];
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int nwaves = nblk * (kBlock / kWave);
+  struct Stage {
+    V zn, xm, xp, ym, yp;
+    double ve;
+  };
+  for (int it = lb * (kBlock / kWave) + w; it < items; it += nwaves) {
+    const int zc = it / groups, grp = it - zc * groups;
+    const int t = grp * kWave + lane;
+    const bool live = t < cols;
+    const int tc = live ? t : 0;
+    const int col = tc / pw, c = (tc - col * pw) * kW;
+    const int i = col % nx, j = col / nx;
+    const int k0 = zc * kRun, k1 = min(k0 + kRun, nz);
+    const int o0 = col * ldx + c, oy = col * ldy + c;
+    const bool hxm = live && i > 0, hxp = live && i < nx - 1;
+    const bool hym = live && j > 0, hyp = live && j < ny - 1;
+    const int oxm = o0 - (hxm ? ldx : 0), oxp = o0 + (hxp ? ldx : 0);
+    const int oym = o0 - (hym ? sy : 0), oyp = o0 + (hyp ? sy : 0);
+    auto issue = [&](Stage& st, int k) {
+      const int kk = k < k1 ? k : k1 - 1;
+      const int kn = kk + 1 < nz ? kk + 1 : kk;
+      const int pk = kk * szx;
+      st.zn = *reinterpret_cast<const V*>(X + (o0 + kn * szx));
+      st.xm = *reinterpret_cast<const V*>(X + (oxm + pk));
+      st.xp = *reinterpret_cast<const V*>(X + (oxp + pk));
+      st.ym = *reinterpret_cast<const V*>(X + (oym + pk));
+      st.yp = *reinterpret_cast<const V*>(X + (oyp + pk));
+      st.ve = veff[col + nxy * kk];
+    };
+    V cm = *reinterpret_cast<const V*>(X + (o0 + (k0 > 0 ? k0 - 1 : k0) * szx));
+    V cc = *reinterpret_cast<const V*>(X + (o0 + k0 * szx));
+    Stage st[kHxPlainDepth];
 #pragma unroll
-    for (int u = 0; u < kHxChunk + 2; ++u) {
-      const int k = k0 - 1 + u;
-      const bool ok = k >= 0 && k < nz;
-      hx_load<T, kW>(col + (ok ? k * sz : 0), ok, zc[u]);
-    }
-    const bool hxm = i > 0, hxp = i < nx - 1, hym = j > 0, hyp = j < ny - 1;
+    for (int s = 0; s < kHxPlainDepth; ++s) issue(st[s], k0 + s);
 #pragma unroll
-    for (int u = 0; u < kHxChunk; ++u) {
+    for (int u = 0; u < kRun; ++u) {
       const int k = k0 + u;
-      if (k >= k1) break;
-      const T* xp = col + k * sz;
-      double a[kW], b[kW], cc[kW], d[kW];
-      hx_load<T, kW>(xp - (hxm ? ldx : 0), hxm, a);
-      hx_load<T, kW>(xp + (hxp ? ldx : 0), hxp, b);
-      hx_load<T, kW>(xp - (hym ? sy : 0), hym, cc);
-      hx_load<T, kW>(xp + (hyp ? sy : 0), hyp, d);
-      const size_t g = i + (size_t)nx * (j + (size_t)ny * k);
-      const double ve = veff[g];
-      double o[kW];
+      Stage& cur = st[u % kHxPlainDepth];
+      const bool kok = live && k < k1;  // k < k1 is uniform over the wavefront
+      const bool zmok = kok && k > 0, zpok = kok && k + 1 < nz;
+      V wv;
 #pragma unroll
       for (int e = 0; e < kW; ++e) {
-        const double cur = zc[u + 1][e];
-        const double nb = a[e] + b[e] + cc[e] + d[e] + zc[u][e] + zc[u + 2][e];
-        const double lx = (6.0 * cur - nb) * ih2;
-        o[e] = scale * (0.5 * lx + ve * cur);
-        if (kEnergy) {
-          kin += cur * lx;
-          ext += vext[g] * cur * cur;
-        }
+        const double z0 = kok ? hx_elem<T, kW>(cc, e) : 0.0;
+        const double nb = (hxm && kok ? hx_elem<T, kW>(cur.xm, e) : 0.0) +
+                          (hxp && kok ? hx_elem<T, kW>(cur.xp, e) : 0.0) +
+                          (hym && kok ? hx_elem<T, kW>(cur.ym, e) : 0.0) +
+                          (hyp && kok ? hx_elem<T, kW>(cur.yp, e) : 0.0) +
+                          (zmok ? hx_elem<T, kW>(cm, e) : 0.0) +
+                          (zpok ? hx_elem<T, kW>(cur.zn, e) : 0.0);
+        const double lx = (6.0 * z0 - nb) * ih2;
+        const T o = (T)(scale * (0.5 * lx + cur.ve * z0));
+        if constexpr (kW == 1) wv = o;
+        else wv[e] = o;
+        if (kEnergy) kin += z0 * lx;
       }
-      T* yp = Y + g * ldy + c;
-      if constexpr (kW == 1) {
-        *yp = (T)o[0];
-      } else {
-        typename HxVec<T, kW>::type w;
-#pragma unroll
-        for (int e = 0; e < kW; ++e) w[e] = (T)o[e];
-        *reinterpret_cast<typename HxVec<T, kW>::type*>(yp) = w;
-      }
+      if (kok) *reinterpret_cast<V*>(Y + (oy + k * szy)) = wv;
+      cm = cc;
+      cc = cur.zn;
+      if (u + kHxPlainDepth < kRun) issue(cur, k + kHxPlainDepth);
     }
   }
+}
+
+// Run length 16 when that still gives every wavefront of the launch an item, else 8.
+template <typename T, bool kEnergy, int kW>
+__device__ inline void hx_items(const HxArgs<T>& ka, int lb, int nblk, double& kin) {
+  const int nxy = ka.gr.nx * ka.gr.ny;
+  const int groups = (nxy * (ka.p / kW) + kWave - 1) / kWave;
+  if (groups * ((ka.gr.nz + 15) / 16) >= nblk * (kBlock / kWave))
+    hx_items_run<T, kEnergy, kW, 16>(ka, lb, nblk, kin);
+  else
+    hx_items_run<T, kEnergy, kW, 8>(ka, lb, nblk, kin);
 }
 
 // The Hamiltonian with the Gram blocks X^T X and X^T G of the same pass (p = 32, column
-// pairs, ld = 32).  A wavefront takes 4 grid columns x 16 column pairs, so on every plane
-// its lanes hold a 4-point slice of X and of G exactly as FP64 MFMA fragments with the grid
-// points as the contraction index: lane l holds point l / 16, columns 2 (l % 16) + e.  The
-// even and odd columns form two 16-column tiles each, so X^T G and X^T X are 4 + 4 tiles per
-// plane step (entry (m, n) of tile (a, b) is column pair (2 m + a, 2 n + b)).  The loop is
-// uniform over the wavefront (MFMAs need every lane); lanes past the grid or the z chunk
-// contribute zeros.
+// pairs, ld = 32).  A wavefront takes 4 consecutive grid columns x 16 column pairs, so on
+// every plane its lanes hold a 4-point slice of X and of G exactly as FP64 MFMA fragments
+// with the grid points as the contraction index: lane l holds point l / 16, columns
+// 2 (l % 16) + e.  The even and odd columns form two 16-column tiles each, so X^T G and
+// X^T X are 4 + 4 tiles per plane (entry (m, n) of tile (a, b) is column pair
+// (2 m + a, 2 n + b)).
+//
+// A work item is such a 4-column slice over a run of kRun consecutive planes (16, or 8 on
+// grids too small to give every wavefront an item), marched plane by plane with a software
+// pipeline kHxDepth planes deep: the loads of plane k + kHxDepth (its centre values one
+// plane further, its four in-plane neighbours and the two potentials) are issued while
+// plane k is computed, so a wavefront never waits for one plane's loads before it can issue
+// the next.  The run is unrolled completely (no register is carried around a loop, so no
+// copy has to wait for a load); the pipeline drains once per item.  The z neighbours come
+// from registers.  Items are ordered run-major, and blocks are remapped so that each XCD
+// owns a contiguous range of items: at 64^3 one XCD holds 16 rows x 32 planes, so most
+// halo rows and planes are read from its own L2.  Lanes past the grid and planes past the
+// grid contribute zeros; all control flow is uniform over the wavefront (MFMAs need every
+// lane).
 struct HxGramAcc {
   d4 xg[4], xx[4];  // tiles (a, b) at index 2 a + b
 };
 
-template <typename T>
+constexpr int kHxDepth = 3;
+
+template <typename T, int kRun>
 __device__ inline void hx_gram_items(const HxArgs<T>& ka, int lb, int nblk, double& kin,
-                                     double& ext, HxGramAcc& g) {
-  constexpr int kW = 2, pw = 16;
+                                     HxGramAcc& g) {
+  constexpr int ld = 32;
+  typedef typename HxVec<T, 2>::type V2;
   const T* __restrict__ X = ka.X;
-  constexpr int ld = 2 * pw;
   T* __restrict__ Y = ka.Y;
   const double* __restrict__ veff = ka.veff;
-  const double* __restrict__ vext = ka.vext;
   const Grid gr = ka.gr;
   const int nx = gr.nx, ny = gr.ny, nz = gr.nz;
-  const int nzc = (nz + kHxChunk - 1) / kHxChunk;
-  const size_t work = (size_t)nx * ny * pw * nzc;
-  const ptrdiff_t sy = (ptrdiff_t)nx * ld, sz = (ptrdiff_t)nx * ny * ld;
+  const int nxy = nx * ny;
+  const int groups = (nxy + 3) / 4;
+  const int items = groups * ((nz + kRun - 1) / kRun);
+  // element offsets fit 31 bits (n * ld < 2^31 is checked at system creation): each load is
+  // the uniform base pointer plus a 32-bit lane offset and a uniform plane offset
+  const int sy = nx * ld, sz = nxy * ld;
   const double ih2 = gr.inv_h2, scale = ka.scale;
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-  for (size_t tw = ((size_t)lb * (kBlock / kWave) + w) * kWave; tw < work;
-       tw += (size_t)nblk * kBlock) {
-    const size_t t0 = tw + lane;
-    const bool live = t0 < work;
-    const size_t t = live ? t0 : tw;
-    const int c = (int)(t % (unsigned)pw) * kW;
-    size_t r = t / (unsigned)pw;
-    const int i = (int)(r % nx);
-    r /= nx;
-    const int j = (int)(r % ny);
-    const int k0 = (int)(r / ny) * kHxChunk;
-    const int k1 = min(k0 + kHxChunk, nz);
-    const T* col = X + (ptrdiff_t)(i + (size_t)nx * j) * ld + c;
-    double zc[kHxChunk + 2][kW];
+  const int c = 2 * (lane % 16), q = lane / 16;
+  const int nwaves = nblk * (kBlock / kWave);
+  struct Stage {
+    V2 zn, xm, xp, ym, yp;  // centre of plane k + 1; in-plane neighbours of plane k
+    double ve;              // V_eff at plane k
+  };
+  for (int it = lb * (kBlock / kWave) + w; it < items; it += nwaves) {
+    const int zc = it / groups, grp = it - zc * groups;
+    const int col = grp * 4 + q;
+    const bool live = col < nxy;
+    const int colc = live ? col : 0;
+    const int i = colc % nx, j = colc / nx;
+    const int k0 = zc * kRun, k1 = min(k0 + kRun, nz);
+    const int o0 = colc * ld + c;
+    const bool hxm = live && i > 0, hxp = live && i < nx - 1;
+    const bool hym = live && j > 0, hyp = live && j < ny - 1;
+    const int oxm = o0 - (hxm ? ld : 0), oxp = o0 + (hxp ? ld : 0);
+    const int oym = o0 - (hym ? sy : 0), oyp = o0 + (hyp ? sy : 0);
+    // loads of output plane k (clamped to valid planes; masked where they are used)
+    auto issue = [&](Stage& st, int k) {
+      const int kk = k < k1 ? k : k1 - 1;
+      const int kn = kk + 1 < nz ? kk + 1 : kk;
+      const int pk = kk * sz;
+      st.zn = *reinterpret_cast<const V2*>(X + (o0 + kn * sz));
+      st.xm = *reinterpret_cast<const V2*>(X + (oxm + pk));
+      st.xp = *reinterpret_cast<const V2*>(X + (oxp + pk));
+      st.ym = *reinterpret_cast<const V2*>(X + (oym + pk));
+      st.yp = *reinterpret_cast<const V2*>(X + (oyp + pk));
+      st.ve = veff[colc + nxy * kk];
+    };
+    V2 cm = *reinterpret_cast<const V2*>(X + (o0 + (k0 > 0 ? k0 - 1 : k0) * sz));
+    V2 cc = *reinterpret_cast<const V2*>(X + (o0 + k0 * sz));
+    Stage st[kHxDepth];
 #pragma unroll
-    for (int u = 0; u < kHxChunk + 2; ++u) {
-      const int k = k0 - 1 + u;
-      const bool ok = k >= 0 && k < nz;
-      hx_load<T, kW>(col + (ok ? k * sz : 0), ok, zc[u]);
-    }
-    const bool hxm = i > 0, hxp = i < nx - 1, hym = j > 0, hyp = j < ny - 1;
+    for (int s = 0; s < kHxDepth; ++s) issue(st[s], k0 + s);
 #pragma unroll
-    for (int u = 0; u < kHxChunk; ++u) {
+    for (int u = 0; u < kRun; ++u) {
       const int k = k0 + u;
-      const bool ok = live && k < k1;
-      const int kk = ok ? k : k0;
-      const T* xp = col + kk * sz;
-      double a[kW], b[kW], cc[kW], d[kW];
-      hx_load<T, kW>(xp - (hxm ? ld : 0), hxm, a);
-      hx_load<T, kW>(xp + (hxp ? ld : 0), hxp, b);
-      hx_load<T, kW>(xp - (hym ? sy : 0), hym, cc);
-      hx_load<T, kW>(xp + (hyp ? sy : 0), hyp, d);
-      const size_t gp = i + (size_t)nx * (j + (size_t)ny * kk);
-      const double ve = veff[gp];
-      const double vx = vext[gp];
-      double xo[kW], go[kW];
-      typename HxVec<T, kW>::type wv;
+      Stage& cur = st[u % kHxDepth];
+      const bool kok = live && k < k1;  // k < k1 is uniform over the wavefront
+      const bool zmok = kok && k > 0, zpok = kok && k + 1 < nz;
+      double xo[2], go[2];
+      V2 wv;
 #pragma unroll
-      for (int e = 0; e < kW; ++e) {
-        const double cur = zc[u + 1][e];
-        const double nb = a[e] + b[e] + cc[e] + d[e] + zc[u][e] + zc[u + 2][e];
-        const double lx = (6.0 * cur - nb) * ih2;
-        const T o = (T)(scale * (0.5 * lx + ve * cur));
+      for (int e = 0; e < 2; ++e) {
+        const double z0 = kok ? (double)cc[e] : 0.0;
+        const double nb = (hxm && kok ? (double)cur.xm[e] : 0.0) +
+                          (hxp && kok ? (double)cur.xp[e] : 0.0) +
+                          (hym && kok ? (double)cur.ym[e] : 0.0) +
+                          (hyp && kok ? (double)cur.yp[e] : 0.0) +
+                          (zmok ? (double)cm[e] : 0.0) + (zpok ? (double)cur.zn[e] : 0.0);
+        const double lx = (6.0 * z0 - nb) * ih2;
+        const T o = (T)(scale * (0.5 * lx + cur.ve * z0));
         wv[e] = o;
-        if (ok) {
-          kin += cur * lx;
-          ext += vx * cur * cur;
-        }
-        xo[e] = ok ? cur : 0.0;
-        go[e] = ok ? (double)o : 0.0;
+        kin += z0 * lx;
+        xo[e] = z0;
+        go[e] = kok ? (double)o : 0.0;
       }
-      if (ok) *reinterpret_cast<typename HxVec<T, kW>::type*>(Y + gp * ld + c) = wv;
+      if (kok) *reinterpret_cast<V2*>(Y + (o0 + k * sz)) = wv;
 #pragma unroll
-      for (int ea = 0; ea < kW; ++ea)
+      for (int ea = 0; ea < 2; ++ea)
 #pragma unroll
-        for (int eb = 0; eb < kW; ++eb) {
+        for (int eb = 0; eb < 2; ++eb) {
           g.xg[2 * ea + eb] = __builtin_amdgcn_mfma_f64_16x16x4f64(xo[ea], go[eb],
                                                                     g.xg[2 * ea + eb], 0, 0, 0);
           g.xx[2 * ea + eb] = __builtin_amdgcn_mfma_f64_16x16x4f64(xo[ea], xo[eb],
                                                                     g.xx[2 * ea + eb], 0, 0, 0);
         }
+      cm = cc;
+      cc = cur.zn;
+      if (u + kHxDepth < kRun) issue(cur, k + kHxDepth);
     }
   }
 }
@@ -403,13 +462,16 @@ template <typename T, bool kEnergy, bool kGram>
 __device__ inline void k_hx_body(const HxArgs<T>& ka, int ks_bid, int ks_nb) {
   __shared__ double sh[kBlock / kWave];
   const int lb = xcd_remap(ks_bid, ks_nb);
-  double kin = 0.0, ext = 0.0;
+  double kin = 0.0;
   if constexpr (kGram) {
     __shared__ double red[3 * 4 * kWave];
     HxGramAcc g;
 #pragma unroll
     for (int q = 0; q < 4; ++q) g.xg[q] = g.xx[q] = d4{0.0, 0.0, 0.0, 0.0};
-    hx_gram_items<T>(ka, lb, ks_nb, kin, ext, g);
+    if (ka.zrun == 16)
+      hx_gram_items<T, 16>(ka, lb, ks_nb, kin, g);
+    else
+      hx_gram_items<T, 8>(ka, lb, ks_nb, kin, g);
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -439,27 +501,41 @@ __device__ inline void k_hx_body(const HxArgs<T>& ka, int ks_bid, int ks_nb) {
                      ((reinterpret_cast<uintptr_t>(ka.X) | reinterpret_cast<uintptr_t>(ka.Y)) &
                       kAl) == 0;
     if (vec)
-      hx_items<T, kEnergy, 2>(ka, lb, ks_nb, kin, ext);
+      hx_items<T, kEnergy, 2>(ka, lb, ks_nb, kin);
     else
-      hx_items<T, kEnergy, 1>(ka, lb, ks_nb, kin, ext);
+      hx_items<T, kEnergy, 1>(ka, lb, ks_nb, kin);
   }
   if (kEnergy) {
     kin = block_sum(kin, sh);
-    ext = block_sum(ext, sh);
     write_partial(ka.pt, SL_KIN, lb, kin);
-    write_partial(ka.pt, SL_EXT, lb, ext);
   }
 }
 
+// (three wavefronts per SIMD without the energy partials, two with them: the register
+// budgets in which the compiler keeps the pipelined loads without spilling)
 template <typename T, bool kEnergy, bool kGram = false>
-__global__ __launch_bounds__(256) void k_hx(HxArgs<T> ka) {
+__global__ __launch_bounds__(256, kEnergy ? 2 : 3) void k_hx(HxArgs<T> ka) {
   k_hx_body<T, kEnergy, kGram>(ka, blockIdx.x, gridDim.x);
 }
 
 template <typename T, bool kEnergy, bool kGram = false>
-__global__ __launch_bounds__(256) void k_hx_batch(BatchPtrs<HxArgs<T>> b) {
+__global__ __launch_bounds__(256, kEnergy ? 2 : 3) void k_hx_batch(BatchPtrs<HxArgs<T>> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
   k_hx_body<T, kEnergy, kGram>(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+}
+
+// The Gram-fused forms at two wavefronts per SIMD (at most 256 registers per lane): the
+// launch holds at most 512 blocks, so that is all the occupancy there is, and the register
+// budget bounds how far ahead the compiler hoists the pipelined loads.
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_hx_gram(HxArgs<T> ka) {
+  k_hx_body<T, true, true>(ka, blockIdx.x, gridDim.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_hx_gram_batch(BatchPtrs<HxArgs<T>> b) {
+  const int s = batch_system(b.off, b.S, blockIdx.x);
+  k_hx_body<T, true, true>(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
 }
 
 
@@ -528,28 +604,28 @@ void launch_xc(const double* rho, const double* vh, const double* vext, double* 
 }
 
 template <typename T>
-void launch_hx(const T* X, int ldx, T* Y, int ldy, const double* veff, const double* vext,
+void launch_hx(const T* X, int ldx, T* Y, int ldy, const double* veff,
                Grid g, int p, double scale, Partials* pt, double* gram_part, hipStream_t st) {
   if (gram_part) {
-    hipLaunchKernelGGL((k_hx<T, true, true>), dim3(hx_gram_blocks(g.n)), dim3(kBlock), 0, st,
-                       HxArgs<T>{X, ldx, Y, ldy, veff, vext, g, p, scale, *pt, gram_part});
+    hipLaunchKernelGGL((k_hx_gram<T>), dim3(hx_gram_blocks(g.n)), dim3(kBlock), 0, st,
+                       HxArgs<T>{X, ldx, Y, ldy, veff, g, p, scale, *pt, gram_part,
+                                 hx_zrun(g.nx * g.ny, g.nz)});
     return;
   }
   const int nb = hx_blocks(g.n, p);
   if (pt) {
     hipLaunchKernelGGL((k_hx<T, true>), dim3(nb), dim3(kBlock), 0, st,
-                       HxArgs<T>{X, ldx, Y, ldy, veff, vext, g, p, scale, *pt, nullptr});
+                       HxArgs<T>{X, ldx, Y, ldy, veff, g, p, scale, *pt, nullptr});
   } else {
     Partials none{nullptr, 0};
     hipLaunchKernelGGL((k_hx<T, false>), dim3(nb), dim3(kBlock), 0, st,
-                       HxArgs<T>{X, ldx, Y, ldy, veff, vext, g, p, scale, none, nullptr});
+                       HxArgs<T>{X, ldx, Y, ldy, veff, g, p, scale, none, nullptr});
   }
 }
-template void launch_hx<double>(const double*, int, double*, int, const double*,
-                                const double*, Grid, int, double, Partials*, double*,
-                                hipStream_t);
-template void launch_hx<float>(const float*, int, float*, int, const double*, const double*,
-                               Grid, int, double, Partials*, double*, hipStream_t);
+template void launch_hx<double>(const double*, int, double*, int, const double*, Grid, int,
+                                double, Partials*, double*, hipStream_t);
+template void launch_hx<float>(const float*, int, float*, int, const double*, Grid, int, double,
+                               Partials*, double*, hipStream_t);
 
 int hx_blocks(int n, int p) { return stream_blocks((size_t)n * p / (2 * kHxChunk) + 1); }
 
@@ -562,6 +638,14 @@ int hx_gram_blocks(int n) {
 
 bool hx_fuses_gram(int p) { return p == 32; }
 
+// Planes per work item of the Gram-fused Hamiltonian: 16, or 8 when runs of 16 would leave
+// wavefronts of its hx_gram_blocks(n) blocks without an item.
+int hx_zrun(int nxy, int nz) {
+  const int groups = (nxy + 3) / 4;
+  const int waves = hx_gram_blocks(nxy * nz) * (kBlock / kWave);
+  return groups * ((nz + 15) / 16) >= waves ? 16 : 8;
+}
+
 
 void launch_xc_batch(const BatchPtrs<XcArgs>& b, int blocks, hipStream_t st) {
   hipLaunchKernelGGL(k_xc_batch, dim3(blocks), dim3(kBlock), 0, st, b);
@@ -570,7 +654,7 @@ void launch_xc_batch(const BatchPtrs<XcArgs>& b, int blocks, hipStream_t st) {
 template <typename T>
 void launch_hx_batch(const BatchPtrs<HxArgs<T>>& b, int blocks, bool gram, hipStream_t st) {
   if (gram)
-    hipLaunchKernelGGL((k_hx_batch<T, true, true>), dim3(blocks), dim3(kBlock), 0, st, b);
+    hipLaunchKernelGGL((k_hx_gram_batch<T>), dim3(blocks), dim3(kBlock), 0, st, b);
   else
     hipLaunchKernelGGL((k_hx_batch<T, true>), dim3(blocks), dim3(kBlock), 0, st, b);
 }

@@ -804,7 +804,7 @@ __device__ inline void k_finish_eval_body(const FinishEvalArgs& ka, int ks_bid, 
   for (int sl = 0; sl < SL_COUNT; ++sl) sums[sl] = red[sl];
   EvalOut o;
   o.kinetic = 0.5 * f * red[SL_KIN];
-  o.external = f * red[SL_EXT];
+  o.external = dV * red[SL_EXT];  // h^3 sum V_ext rho
   o.hartree = 0.5 * dV * red[SL_EH];
   o.xc = dV * red[SL_EX];
   o.nuclear = *enuc;
@@ -814,6 +814,7 @@ __device__ inline void k_finish_eval_body(const FinishEvalArgs& ka, int ks_bid, 
   o.sy = red[SL_SY];
   o.yy = red[SL_YY];
   o.orth2 = acc;
+  o.defect2 = red[SL_DEFECT];
   if (cg) {
     o.cg_iters = cg->it;
     o.cg_relres = cg->bb > 0.0 ? sqrt(cg->rr / cg->bb) : 0.0;
@@ -878,12 +879,34 @@ __global__ void k_ls_init(const EvalOut* ev, LsState* ls, LsParams prm) {
   if (ev->nonfinite) {
     s.error = KS_E_NONFINITE;
     s.stop = KS_STOP_ERROR;
+  } else if (s.E <= prm.energy_target) {
+    s.stop = KS_STOP_ENERGY;
   } else if (sqrt(s.g2) <= prm.eps_g) {
     s.stop = KS_STOP_GRAD;
   } else if (prm.max_iter <= 0) {
     s.stop = KS_STOP_MAXIT;
   }
   if (s.error != 0) s.stop = KS_STOP_ERROR;
+  *ls = s;
+}
+
+__global__ void k_ls_restart(const EvalOut* ev, LsState* ls, LsParams prm) {
+  LsState s = *ls;
+  s.nfe += 1;
+  s.E = ev->total;
+  s.g2 = ev->g2;
+  s.C = s.E;
+  s.Q = 1.0;
+  s.h = 0;
+  s.tau = s.tau_bb;
+  s.accepted = 1;
+  if (ev->nonfinite) {
+    s.error = KS_E_NONFINITE;
+    s.stop = KS_STOP_ERROR;
+  } else if (s.stop == KS_STOP_NONE) {
+    if (s.E <= prm.energy_target) s.stop = KS_STOP_ENERGY;
+    else if (sqrt(s.g2) <= prm.eps_g) s.stop = KS_STOP_GRAD;
+  }
   *ls = s;
 }
 
@@ -899,6 +922,7 @@ __device__ void ls_judge(const EvalOut* ev, LsState* ls, const LsParams& prm,
   }
   s.hartree_pending = 0;
   s.nfe += 1;
+  if (ev->defect2 > kBf16Defect * kBf16Defect * ev->g2) s.bf16_off = 1;
   if (s.error != 0) {
     s.stop = KS_STOP_ERROR;
     *ls = s;
@@ -917,6 +941,7 @@ __device__ void ls_judge(const EvalOut* ev, LsState* ls, const LsParams& prm,
     }
     if (!ok) s.ls_fail += 1;
     s.accepted = 1;
+    s.tau_acc = s.tau;
     const double df = fabs(s.E - Et) / (fabs(s.E) + 1.0);
     s.df[0] = s.df[1];
     s.df[1] = s.df[2];
@@ -928,7 +953,9 @@ __device__ void ls_judge(const EvalOut* ev, LsState* ls, const LsParams& prm,
     s.E = Et;
     s.g2 = ev->g2;
     s.k += 1;
-    if (s.ndf >= 3 && (s.df[0] + s.df[1] + s.df[2]) / 3.0 < prm.stagnation_tol)
+    if (Et <= prm.energy_target)
+      s.stop = KS_STOP_ENERGY;
+    else if (s.ndf >= 3 && (s.df[0] + s.df[1] + s.df[2]) / 3.0 < prm.stagnation_tol)
       s.stop = KS_STOP_STAGNATION;
     else if (sqrt(s.g2) <= prm.eps_g)
       s.stop = KS_STOP_GRAD;
@@ -1054,6 +1081,43 @@ void launch_small_gemm_add(const double* A, const double* B, const double* W, do
   hipLaunchKernelGGL(k_small_gemm_add, dim3(t, t), dim3(256), 0, st, A, B, W, C, p, pp);
 }
 
+// One 16 x 16 tile of (xx W) per block as in k_small_gemm_add, then the block's sum of
+// (xg - xd + xx W)^2 over its tile, one partial per block in tile order.
+__global__ __launch_bounds__(256) void k_bf16_defect(const double* __restrict__ xg,
+                                                     const double* __restrict__ xd,
+                                                     const double* __restrict__ xx,
+                                                     const double* __restrict__ W, int p,
+                                                     int pp, double* __restrict__ part) {
+  __shared__ double Bs[16][17], Ws[16][17];
+  __shared__ double sh[kBlock / kWave];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int i = blockIdx.y * 16 + ty, j = blockIdx.x * 16 + tx;
+  double acc = 0.0;
+  for (int k0 = 0; k0 < p; k0 += 16) {
+    Bs[ty][tx] = (i < p && k0 + tx < p) ? xx[(size_t)i * pp + k0 + tx] : 0.0;
+    Ws[ty][tx] = (k0 + ty < p && j < p) ? W[(size_t)(k0 + ty) * pp + j] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc += Bs[ty][k] * Ws[k][tx];
+    __syncthreads();
+  }
+  const double d =
+      (i < p && j < p) ? xg[(size_t)i * pp + j] - xd[(size_t)i * pp + j] + acc : 0.0;
+  const double s = block_sum(d * d, sh);
+  if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
+int bf16_defect_blocks(int p) {
+  const int t = (p + 15) / 16;
+  return t * t;
+}
+
+void launch_bf16_defect(const double* xg, const double* xd, const double* xx, const double* W,
+                        int p, int pp, double* part, hipStream_t st) {
+  const int t = (p + 15) / 16;
+  hipLaunchKernelGGL(k_bf16_defect, dim3(t, t), dim3(256), 0, st, xg, xd, xx, W, p, pp, part);
+}
+
 void launch_qr_factor_next(const QrFactor2dArgs& a, hipStream_t st) {
   if (a.p <= 16)
     hipLaunchKernelGGL(k_qr_factor_2d<16>, dim3(1), dim3(qr_threads<16>()), 0, st, a);
@@ -1089,6 +1153,10 @@ void launch_set_scalar(double* dst, double v, hipStream_t st) {
 
 void launch_ls_init(const EvalOut* ev, LsState* ls, LsParams prm, hipStream_t st) {
   hipLaunchKernelGGL(k_ls_init, dim3(1), dim3(1), 0, st, ev, ls, prm);
+}
+
+void launch_ls_restart(const EvalOut* ev, LsState* ls, LsParams prm, hipStream_t st) {
+  hipLaunchKernelGGL(k_ls_restart, dim3(1), dim3(1), 0, st, ev, ls, prm);
 }
 
 

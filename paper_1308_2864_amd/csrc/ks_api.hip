@@ -55,8 +55,27 @@ constexpr int kGatherBytes = 512;  // CgState and LsState of one system (adjacen
 constexpr size_t kHostBytes = 1024 + (size_t)kMaxBatch * kGatherBytes;
 }  // namespace
 
+namespace ks {
+// State of one Alg. 3 run between its trials.  ks_minimize, the per-iteration calls, state
+// save and restore, and the lockstep runner all keep it in the system handle, so every
+// route takes the same decisions from the same device records.
+struct MinRun {
+  ks_opt_params prm{};
+  LsParams lp{};
+  bool qr = true;
+  int c = 0;
+  void* X_inout = nullptr;
+  std::chrono::steady_clock::time_point t0;
+  bool active = false;   // begun and not yet ended
+  bool queued = false;   // the QR factor of the next trial is already on the stream
+  bool records = false;  // the lockstep argument records of this run are on the device
+  int reorths = 0;       // re-orthonormalisations requested by reorth_every
+};
+}  // namespace ks
+
 struct ks_system {
   ks_system_desc d{};
+  ks::MinRun run;
   std::vector<double> R, Z;
   hipStream_t st = nullptr;
   Grid grid{};
@@ -85,6 +104,7 @@ struct ks_system {
   void *X[2] = {}, *G[2] = {}, *D[2] = {};  // float (FP32 modes) or double
   bool f32 = false;
   bool bf16 = false;  // KS_PREC_MIXED_BF16: float storage, Gram sub-products in bf16
+  bool bf16_on = true;  // a run switches it off once the bf16 X^T G error is too large
   int es = 8;  // bytes per orbital element
   double *gxg[2] = {}, *gxd[2] = {}, *W = nullptr, *A = nullptr, *B = nullptr;
   double *work = nullptr, *gram_part = nullptr, *spart = nullptr, *cgpart = nullptr;
@@ -321,22 +341,22 @@ void density(ks_system* s, const void* X, int ld, double* rho) {
 void hamiltonian(ks_system* s, const void* X, int ldx, void* Y, int ldy, const double* veff,
                  double scale, Partials* pt, double* gram_part = nullptr) {
   if (s->f32)
-    launch_hx<float>(static_cast<const float*>(X), ldx, static_cast<float*>(Y), ldy, veff, s->vext,
+    launch_hx<float>(static_cast<const float*>(X), ldx, static_cast<float*>(Y), ldy, veff,
                      s->grid, s->p, scale, pt, gram_part, s->st);
   else
     launch_hx<double>(static_cast<const double*>(X), ldx, static_cast<double*>(Y), ldy, veff,
-                      s->vext, s->grid, s->p, scale, pt, gram_part, s->st);
+                      s->grid, s->p, scale, pt, gram_part, s->st);
 }
 
 void q1_apply(ks_system* s, const void* X, void* G, void* BX, const double* veff, double scale,
               Partials* pt) {
   if (s->f32)
     launch_q1_apply<float>(static_cast<const float*>(X), static_cast<float*>(G),
-                           static_cast<float*>(BX), veff, s->vext, s->grid, s->p, scale, pt,
+                           static_cast<float*>(BX), veff, s->grid, s->p, scale, pt,
                            s->st);
   else
     launch_q1_apply<double>(static_cast<const double*>(X), static_cast<double*>(G),
-                            static_cast<double*>(BX), veff, s->vext, s->grid, s->p, scale, pt,
+                            static_cast<double*>(BX), veff, s->grid, s->p, scale, pt,
                             s->st);
 }
 
@@ -359,14 +379,18 @@ void gram(ks_system* s, const void* A, const void* B, int mask) {
 // sym_ab: A^T B is symmetric (X^T B X, D^T B D); beyond 64 columns only its blocks I <= J
 // are formed and mirrored
 // KS_PREC_MIXED_BF16 takes A^T B (the calls marked bf16_ok: X^T G) on the bf16 matrix
-// cores; every other product stays exact.  The retraction sees X^T G only through
-// X^T D + D^T X with X^T D = X^T G + (X^T X) W, W = -(X^T G)^T, where its rounding error
-// cancels to first order (X^T X = I), so the constraint does not drift; X^T X, D^T D and
-// the B-metric blocks enter the Cholesky factor directly and would.
+// cores; every other product stays exact.  X^T G sets only the weights W = -(X^T G)^T of
+// the direction D = G + X W.  The Cholesky factor of the retraction needs Y^T Y of the Y
+// actually formed, so with float storage X^T D (X^T B D) is a product of the stored D,
+// never X^T G + (X^T X) W: that sum misses the rounding of the stored D (about 1e-7 of
+// each entry, enough to put X off the manifold by 1e-4 at p = 130) and, with bf16 error d
+// in X^T G, the d + d^T that the true X^T D + D^T X carries.  Formed from D, the factor is
+// exact; d then only rotates X within its span to first order, which leaves the energy
+// unchanged.
 void gram_reduced(ks_system* s, const void* A, const void* B, int mask, double* out,
                   double* W, bool sym_ab = false, bool bf16_ok = false) {
   if (s->pp > 64) {
-    const int bf16_mask = s->bf16 && bf16_ok ? kGramAB : 0;
+    const int bf16_mask = s->bf16 && s->bf16_on && bf16_ok ? kGramAB : 0;
     launch_gram_full(A, B, s->f32, s->p, s->n, s->p, mask, s->gram_part, s->gsub, out, W,
                      s->st, sym_ab, bf16_mask);
     return;
@@ -677,7 +701,7 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
   const int mask2 = kGramAB | kGramBB;
   if (want_gxd && !fused) {
     tbeg(s, KS_PH_GRAM);
-    if (s->pp > 64) {
+    if (s->pp > 64 && !s->f32) {
       // X^T D = X^T G + (X^T X) W from the blocks already reduced; only D^T D is a pass
       const int pp2 = s->pp * s->pp;
       gram_reduced(s, Xs, s->D[idx], kGramBB, s->gxd[idx], nullptr);
@@ -688,14 +712,22 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
     }
     tend(s, KS_PH_GRAM);
   }
+  // the error of the bf16 X^T G, from the exact X^T D just formed
+  const bool defect = want_gxd && !fused && s->bf16 && s->bf16_on && s->pp > 64;
+  if (defect) {
+    const int pp2 = s->pp * s->pp;
+    launch_bf16_defect(s->gxg[idx] + pp2, s->gxd[idx] + pp2, s->gxg[idx], s->W, s->p, s->pp,
+                       s->spart + (size_t)SL_DEFECT * kPartStride, s->st);
+  }
   tbeg(s, KS_PH_SMALL);
   if (fused)
     launch_gram_reduce(s->gram_part, combine_blocks(s->n), s->pp, mask2, s->gxd[idx], nullptr,
                        s->st);
   int nblk[kMaxScalarSlots] = {};
-  nblk[SL_KIN] = nblk[SL_EXT] = hxg ? hx_gram_blocks(s->n) : hx_blocks(s->n, s->p);
-  nblk[SL_EH] = nblk[SL_EX] = scalar_blocks(s->n);
+  nblk[SL_KIN] = hxg ? hx_gram_blocks(s->n) : hx_blocks(s->n, s->p);
+  nblk[SL_EH] = nblk[SL_EX] = nblk[SL_EXT] = scalar_blocks(s->n);
   nblk[SL_DD] = nblk[SL_SS] = nblk[SL_SY] = nblk[SL_YY] = combine_partial_blocks(s->n, s->p);
+  nblk[SL_DEFECT] = defect ? bf16_defect_blocks(s->p) : 0;
   launch_finish_eval(s->spart, kPartStride, nblk, s->sums[idx], s->gxg[idx], s->p, s->pp, s->f,
                      s->grid.dV, s->enuc, s->use_h ? s->cg : nullptr, s->ev[idx],
                      judge ? s->ls : nullptr, judge, s->st);
@@ -750,7 +782,7 @@ int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd, const LsP
   tend(s, KS_PH_GRADIENT);
   if (want_gxd) {
     tbeg(s, KS_PH_GRAM);
-    if (s->pp > 64) {
+    if (s->pp > 64 && !s->f32) {
       // X^T BD = X^T G + (X^T B X) W from the blocks already reduced
       launch_small_gemm_add(s->gxg[idx] + pp2, s->feg[idx] + pp2, s->W, s->gxd[idx] + pp2,
                             s->p, s->pp, s->st);
@@ -761,11 +793,17 @@ int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd, const LsP
     gram_reduced(s, s->D[idx], s->BD[idx], kGramAB, s->gxd[idx] + pp2, nullptr, true);
     tend(s, KS_PH_GRAM);
   }
+  // the error of the bf16 X^T G, from the exact X^T B D and X^T B X
+  const bool defect = want_gxd && s->bf16 && s->bf16_on && s->pp > 64;
+  if (defect)
+    launch_bf16_defect(s->gxg[idx] + pp2, s->gxd[idx] + pp2, s->feg[idx] + pp2, s->W, s->p,
+                       s->pp, s->spart + (size_t)SL_DEFECT * kPartStride, s->st);
   tbeg(s, KS_PH_SMALL);
   int nblk[kMaxScalarSlots] = {};
-  nblk[SL_KIN] = nblk[SL_EXT] = q1_apply_blocks(s->grid, s->p);
-  nblk[SL_EH] = nblk[SL_EX] = scalar_blocks(s->n);
+  nblk[SL_KIN] = q1_apply_blocks(s->grid, s->p);
+  nblk[SL_EH] = nblk[SL_EX] = nblk[SL_EXT] = scalar_blocks(s->n);
   nblk[SL_DD] = nblk[SL_SS] = nblk[SL_SY] = nblk[SL_YY] = q1_grad_blocks(s->n, s->p);
+  nblk[SL_DEFECT] = defect ? bf16_defect_blocks(s->p) : 0;
   launch_finish_eval(s->spart, kPartStride, nblk, s->sums[idx], s->feg[idx] + pp2, s->p, s->pp,
                      s->f, s->grid.dV, s->enuc, s->use_h ? s->cg : nullptr, s->ev[idx],
                      judge ? s->ls : nullptr, judge, s->st);
@@ -773,13 +811,23 @@ int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd, const LsP
   return launch_check(s, "evaluate");
 }
 
-// X <- X R^{-1} with X^T B X = R^T R, in place on slot idx (uses slot 1 - idx as scratch).
-int b_orthonormalize(ks_system* s, int idx) {
+// Cholesky QR of slot idx in place (Alg. 2): X <- X R^{-1} with X^T X = R^T R (finite
+// differences) or X^T B X = R^T R (finite elements), the Gram block formed in FP64 from the
+// stored X.  Uses slot 1 - idx as scratch.
+int orthonormalize_slot(ks_system* s, int idx) {
   const int o = 1 - idx;
   const int pp2 = s->pp * s->pp;
-  q1_apply(s, s->X[idx], nullptr, s->BX[idx], nullptr, 1.0, nullptr);
-  gram_reduced(s, s->X[idx], s->BX[idx], kGramAB, s->feg[idx], nullptr, true);
-  // tau = 0: the factor reduces to the Cholesky of X^T B X; X^T D and D^T D are not used
+  const double* xx = nullptr;
+  if (s->q1) {
+    q1_apply(s, s->X[idx], nullptr, s->BX[idx], nullptr, 1.0, nullptr);
+    gram_reduced(s, s->X[idx], s->BX[idx], kGramAB, s->feg[idx], nullptr, true);
+    xx = s->feg[idx] + pp2;
+  } else {
+    gram_reduced(s, s->X[idx], s->X[idx], kGramAA, s->gxg[idx], nullptr);
+    xx = s->gxg[idx];
+  }
+  // tau = 0: the factor reduces to the Cholesky of the Gram block; X^T D and D^T D are not
+  // used
   launch_fill(s->gxd[idx], 0.0, 3 * (size_t)pp2, s->st);
   launch_set_scalar(s->tau_user, 0.0, s->st);
   int* hstat = host_int(s);
@@ -787,8 +835,8 @@ int b_orthonormalize(ks_system* s, int idx) {
   int rc = hip_check(s, hipMemcpyAsync(s->status, hstat, sizeof(int), hipMemcpyHostToDevice,
                                        s->st), "status upload");
   if (rc) return rc;
-  launch_qr_factor(s->feg[idx] + pp2, s->gxd[idx], s->p, s->pp, s->tau_user, s->A, s->B,
-                   s->work, s->status, s->st);
+  launch_qr_factor(xx, s->gxd[idx], s->p, s->pp, s->tau_user, s->A, s->B, s->work, s->status,
+                   s->st);
   CombineArgs ca{};
   ca.X = s->X[idx];
   ca.A = s->A;
@@ -803,7 +851,9 @@ int b_orthonormalize(ks_system* s, int idx) {
   if (rc) return rc;
   rc = readback(s, hstat, s->status);
   if (rc) return rc;
-  if (hstat[0] != 0) return fail(s, KS_E_NOT_SPD, "start block is rank deficient in the B metric");
+  if (hstat[0] != 0)
+    return fail(s, KS_E_NOT_SPD, s->q1 ? "block is rank deficient in the B metric"
+                                       : "block is rank deficient");
   return KS_OK;
 }
 
@@ -831,6 +881,7 @@ LsParams to_params(const ks_opt_params& o) {
   p.tau_max = o.tau_max;
   p.reorth_tol = o.reorth_tol;
   p.stagnation_tol = o.stagnation_tol;
+  p.energy_target = o.energy_target;
   p.max_iter = o.max_iter;
   p.bb_rule = o.bb_rule;
   p.h_max = o.h_max;
@@ -920,17 +971,6 @@ int capture_trial(ks_system* s, int c, bool qr, const LsParams& lp, const ks_opt
 
 namespace {
 
-// State of one Alg. 3 run between its steps (shared by ks_minimize and the batched runner,
-// so both take the same decisions from the same device records).
-struct MinRun {
-  ks_opt_params prm;
-  LsParams lp;
-  bool qr = true;
-  int c = 0;
-  void* X_inout = nullptr;
-  std::chrono::steady_clock::time_point t0;
-};
-
 // Validation, start block, first evaluation and line-search initialisation.
 int run_begin(ks_system* s, void* X_inout, const ks_opt_params* o, MinRun* m) {
   if (!s || !X_inout) return fail(s, KS_E_INVAL, "null argument");
@@ -942,11 +982,18 @@ int run_begin(ks_system* s, void* X_inout, const ks_opt_params* o, MinRun* m) {
     return fail(s, KS_E_INVAL, "unknown retraction");
   if (!(prm.delta > 0.0 && prm.delta < 1.0) || !(prm.tau0 > 0.0) || prm.h_max < 0)
     return fail(s, KS_E_INVAL, "bad line-search parameters");
+  if (prm.reorth_every < 0 || std::isnan(prm.energy_target))
+    return fail(s, KS_E_INVAL, "reorth_every must be >= 0 and energy_target not NaN");
   if (s->q1 && prm.retraction != KS_QR)
     return fail(s, KS_E_UNSUPPORTED, "finite elements use the QR retraction");
   m->lp = to_params(prm);
   m->qr = prm.retraction == KS_QR;
   m->X_inout = X_inout;
+  m->active = true;
+  m->queued = false;
+  m->records = false;
+  m->reorths = 0;
+  s->bf16_on = true;
   s->cg_total = 0;
   // each run starts from the same solver settings: its first trial queues one PCG
   // iteration after the exact step, and whether that iteration ran decides the rest
@@ -958,7 +1005,7 @@ int run_begin(ks_system* s, void* X_inout, const ks_opt_params* o, MinRun* m) {
   copy_block(s, s->X[c], s->p, X_inout, s->ld);
   if (s->q1) {
     // the start block needs full column rank only: make it B-orthonormal first
-    int rb = b_orthonormalize(s, c);
+    int rb = orthonormalize_slot(s, c);
     if (rb) return rb;
   }
   launch_ls_reset(s->ls, s->st);
@@ -1006,6 +1053,7 @@ int run_after_trial(ks_system* s, MinRun* m, bool cg_read) {
       drop_graphs(s);
     }
   }
+  if (hl->bf16_off) s->bf16_on = false;  // exact X^T G for the rest of the run
   if (hl->error) return KS_OK;
   if (hl->accepted) {
     m->c = t;
@@ -1014,12 +1062,71 @@ int run_after_trial(ks_system* s, MinRun* m, bool cg_read) {
   return KS_OK;
 }
 
-// Copies the result out and fills the statistics.
-int run_end(ks_system* s, MinRun* m, ks_result* r) {
+// reorth_every: the accepted iterate is re-orthonormalised in FP64 (Cholesky QR of its
+// stored values), evaluated again, and the nonmonotone reference restarts there.
+int run_reorth(ks_system* s, MinRun* m) {
+  const int c = m->c;
+  int rc = orthonormalize_slot(s, c);
+  if (rc) return rc;
+  rc = evaluate(s, c, false, -1, c, m->qr, !m->qr);
+  if (rc) return rc;
+  launch_ls_restart(s->ev[c], s->ls, m->lp, s->st);
+  m->reorths += 1;
+  m->queued = false;
+  return readback(s, host_ls(s), s->ls);
+}
+
+// One trial step of Alg. 3 from the current slot, judged on the device, then accepted or
+// rejected on the host side of the run (and, every reorth_every accepted iterations, the
+// re-orthonormalisation of the new iterate).
+int run_trial(ks_system* s, MinRun* m) {
+  LsState* hl = host_ls(s);
+  const int c = m->c;
+  const bool pcg = s->solver == KS_HARTREE_PCG_FD;
+  // graph replay from the second trial on (the first runs eagerly and initialises the
+  // launch attributes); the CG solver's host-side convergence checks cannot be captured
+  const bool replay = s->graphs && s->cap_st && (pcg || !s->use_h) && !s->timers &&
+                      hl->nfe > 1;
+  int rc = KS_OK;
+  if (replay && !s->gx[c]) {
+    rc = capture_trial(s, c, m->qr, m->lp, m->prm);
+    if (rc) return rc;
+  }
+  if (replay && s->gx[c]) {
+    rc = hip_check(s, hipGraphLaunch(s->gx[c], s->st), "graph launch");
+  } else {
+    rc = enqueue_trial(s, c, m->qr, m->lp, m->prm, m->queued);
+  }
+  m->queued = false;
+  if (rc) return rc;
+  const bool cg_read = pcg && s->use_h;
+  // eager QR runs queue the next trial's factor behind the record copy
+  const bool ahead = cg_read && m->qr && s->p <= 64 && !s->graphs;
+  if (ahead) rc = readback_cg_ls_ahead(s, c);
+  else rc = cg_read ? readback_cg_ls(s) : readback(s, hl, s->ls);
+  if (rc) return rc;
+  // a pending Hartree solve re-evaluates the trial first; the queued factor then returned
+  // without writing, and the next trial queues its own
+  m->queued = ahead && !hl->hartree_pending;
+  rc = run_after_trial(s, m, cg_read);
+  if (rc) return rc;
+  if (m->prm.reorth_every > 0 && hl->accepted && hl->stop == KS_STOP_NONE && !hl->error &&
+      hl->k % m->prm.reorth_every == 0)
+    return run_reorth(s, m);
+  return KS_OK;
+}
+
+// Copies the result out (into X_out when given, else the run's X_inout) and fills the
+// statistics.
+int run_end(ks_system* s, MinRun* m, ks_result* r, void* X_out = nullptr) {
   LsState* hl = host_ls(s);
   int* hint = host_int(s);
   drop_graphs(s);
-  copy_block(s, m->X_inout, s->ld, s->X[m->c], s->p);
+  m->active = false;
+  m->queued = false;
+  s->bf16_on = true;
+  if (!X_out) X_out = m->X_inout;
+  if (X_out) copy_block(s, X_out, s->ld, s->X[m->c], s->p);
   int rc = launch_check(s, "minimize");
   if (rc) return rc;
   EvalOut* he = host_ev(s);
@@ -1033,7 +1140,7 @@ int run_end(ks_system* s, MinRun* m, ks_result* r) {
     r->nfe = hl->nfe;
     r->backtracks = hl->backtracks;
     r->ls_fail = hl->ls_fail;
-    r->reorths = hint[1];
+    r->reorths = hint[1] + m->reorths;
     r->stop_reason = hl->stop;
     r->energy = he->total;
     r->grad_norm = std::sqrt(std::max(he->g2, 0.0));
@@ -1069,7 +1176,7 @@ static_assert(sizeof(QrFactor2dArgs) <= kRecSlot && sizeof(CombineArgs) <= kRecS
 
 bool batchable(const ks_system* s, const MinRun& m) {
   return !s->q1 && s->solver == KS_HARTREE_PCG_FD && s->use_h && m.qr && s->pp <= 32 &&
-         !s->timers;
+         !s->timers && m.prm.reorth_every == 0;
 }
 
 template <typename A>
@@ -1129,8 +1236,9 @@ void fill_typed(ks_system* s, std::vector<char>& buf, int c) {
                                s->use_x, s->cg, pt});
   const bool hxg = hx_fuses_gram(s->p);
   put_rec(buf, c, R_HX, HxArgs<T>{static_cast<const T*>(s->X[t]), s->p,
-                                  static_cast<T*>(s->G[t]), s->p, s->veff[t], s->vext, s->grid,
-                                  s->p, 2.0 * s->f, pt, hxg ? s->gram_part : nullptr});
+                                  static_cast<T*>(s->G[t]), s->p, s->veff[t], s->grid,
+                                  s->p, 2.0 * s->f, pt, hxg ? s->gram_part : nullptr,
+                                  hx_zrun(s->grid.nx * s->grid.ny, s->grid.nz)});
   put_rec(buf, c, R_GRAM1, GramArgs<T>{static_cast<const T*>(s->X[t]),
                                        static_cast<const T*>(s->G[t]), s->p, s->n, s->p,
                                        s->gram_part});
@@ -1162,9 +1270,8 @@ int upload_records(ks_system* s, const MinRun& m) {
     else fill_typed<double>(s, buf, c);
     const int t = 1 - c;
     int nblk[kMaxScalarSlots] = {};
-    nblk[SL_KIN] = nblk[SL_EXT] =
-        hx_fuses_gram(s->p) ? hx_gram_blocks(s->n) : hx_blocks(s->n, s->p);
-    nblk[SL_EH] = nblk[SL_EX] = scalar_blocks(s->n);
+    nblk[SL_KIN] = hx_fuses_gram(s->p) ? hx_gram_blocks(s->n) : hx_blocks(s->n, s->p);
+    nblk[SL_EH] = nblk[SL_EX] = nblk[SL_EXT] = scalar_blocks(s->n);
     nblk[SL_DD] = nblk[SL_SS] = nblk[SL_SY] = nblk[SL_YY] = combine_blocks(s->n);
     ScalarCounts sc{};
     for (int i = 0; i < SL_COUNT; ++i) sc.v[i] = nblk[i];
@@ -1175,7 +1282,9 @@ int upload_records(ks_system* s, const MinRun& m) {
   int rc = hip_check(s, hipMemcpyAsync(s->rec, buf.data(), kRecBytes, hipMemcpyHostToDevice,
                                        s->st), "record upload");
   if (rc) return rc;
-  return hip_check(s, hipStreamSynchronize(s->st), "record upload sync");
+  rc = hip_check(s, hipStreamSynchronize(s->st), "record upload sync");
+  if (rc == KS_OK) s->run.records = true;
+  return rc;
 }
 
 }  // namespace
@@ -1183,8 +1292,7 @@ int upload_records(ks_system* s, const MinRun& m) {
 namespace ks {
 
 struct BatchMember {
-  ks_system* s = nullptr;
-  MinRun m;
+  ks_system* s = nullptr;  // its run state is s->run
   bool queued = false;  // the QR factor of its next trial is already on the engine stream
   void* tag = nullptr;
   int code = KS_OK;
@@ -1193,6 +1301,7 @@ struct BatchMember {
 
 struct BatchEngine {
   hipStream_t st = nullptr;
+  bool finish = true;       // stopped runs are ended (result copied out) by the engine
   hipEvent_t ev = nullptr;  // end of the record copy of a tick
   std::vector<BatchMember*> act;
   std::vector<BatchMember*> fin;
@@ -1207,7 +1316,7 @@ BatchPtrs<A> table(const std::vector<BatchMember*>& g, int r, F blocks, int* tot
   int off = 0;
   for (int i = 0; i < b.S; ++i) {
     b.off[i] = off;
-    b.a[i] = rec_at<A>(g[i]->s, g[i]->m.c, r);
+    b.a[i] = rec_at<A>(g[i]->s, g[i]->s->run.c, r);
     off += blocks(g[i]->s);
   }
   b.off[b.S] = off;
@@ -1318,17 +1427,18 @@ int batch_add(BatchEngine* e, ks_system* s, void* X, const ks_opt_params* o, voi
   BatchMember* m = new BatchMember();
   m->s = s;
   m->tag = tag;
-  int rc = run_begin(s, X, o, &m->m);
-  if (rc == KS_OK && !batchable(s, m->m)) rc = fail(s, KS_E_UNSUPPORTED, "not batchable");
-  if (rc == KS_OK) rc = upload_records(s, m->m);
+  int rc = run_begin(s, X, o, &s->run);
+  if (rc == KS_OK && !batchable(s, s->run)) rc = fail(s, KS_E_UNSUPPORTED, "not batchable");
+  if (rc == KS_OK) rc = upload_records(s, s->run);
   if (rc != KS_OK) {
+    s->run.active = false;
     m->code = rc;
     e->fin.push_back(m);
     return rc;
   }
   const LsState* hl = host_ls(s);
   if (hl->stop != KS_STOP_NONE || hl->error) {
-    m->code = run_end(s, &m->m, &m->r);
+    m->code = run_end(s, &s->run, &m->r);
     e->fin.push_back(m);
     return KS_OK;
   }
@@ -1395,14 +1505,16 @@ int batch_tick(BatchEngine* e) {
   for (int i = 0; i < ga.S; ++i) {
     BatchMember* m = e->act[i];
     m->queued = !host_ls(m->s)->hartree_pending;
+    m->s->run.queued = false;  // the lone path's speculative factor is not in place
     m->s->cg_par = 0;  // the host state a lone trial leaves (no PCG iteration queued)
-    int code = run_after_trial(m->s, &m->m, true);
+    int code = run_after_trial(m->s, &m->s->run, true);
     const LsState* hl = host_ls(m->s);
     if (code != KS_OK) {
       m->code = code;
+      m->s->run.active = false;
       e->fin.push_back(m);
     } else if (hl->stop != KS_STOP_NONE || hl->error) {
-      m->code = run_end(m->s, &m->m, &m->r);
+      m->code = e->finish ? run_end(m->s, &m->s->run, &m->r) : KS_OK;
       e->fin.push_back(m);
     } else {
       keep.push_back(m);
@@ -1443,6 +1555,8 @@ void ks_default_params(ks_opt_params* o) {
   o->h_max = 20;
   o->reorth_tol = 1e-12;
   o->stagnation_tol = 1e-13;
+  o->reorth_every = 0;
+  o->energy_target = -HUGE_VAL;
 }
 
 const char* ks_status_string(int code) {
@@ -1651,10 +1765,14 @@ int ks_apply_hamiltonian(ks_system* s, const void* X, void* Y, const double* v_e
     q1_apply(s, s->X[t], s->G[t], s->BX[t], v_eff ? v_eff : s->veff[s->cur], 1.0, nullptr);
     copy_block(s, Y, s->ld, s->G[t], s->p);
   } else {
+    tbeg(s, KS_PH_HAMILTONIAN);
     hamiltonian(s, X, s->ld, Y, s->ld, v_eff ? v_eff : s->veff[s->cur], 1.0, nullptr);
+    tend(s, KS_PH_HAMILTONIAN);
   }
   int rc = launch_check(s, "hamiltonian");
-  return rc ? rc : hip_check(s, hipStreamSynchronize(s->st), "hamiltonian sync");
+  if (rc == KS_OK) rc = hip_check(s, hipStreamSynchronize(s->st), "hamiltonian sync");
+  if (rc == KS_OK && s->timers) harvest(s);
+  return rc;
 }
 
 int ks_get_potentials(ks_system* s, double* v_ext, double* v_h, double* v_eff) {
@@ -1790,42 +1908,241 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
 }
 
 int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* r) {
-  MinRun m;
-  int rc = run_begin(s, X_inout, o, &m);
-  if (rc) return rc;
-  LsState* hl = host_ls(s);
-  bool queued = false;  // the next trial's QR factor is already on the stream
-  while (hl->stop == KS_STOP_NONE && !hl->error) {
-    const int c = m.c;
-    const bool pcg = s->solver == KS_HARTREE_PCG_FD;
-    // graph replay from the second trial on (the first runs eagerly and initialises the
-    // launch attributes); the CG solver's host-side convergence checks cannot be captured
-    const bool replay = s->graphs && s->cap_st && (pcg || !s->use_h) && !s->timers &&
-                        hl->nfe > 1;
-    if (replay && !s->gx[c]) {
-      rc = capture_trial(s, c, m.qr, m.lp, m.prm);
-      if (rc) return rc;
-    }
-    if (replay && s->gx[c]) {
-      rc = hip_check(s, hipGraphLaunch(s->gx[c], s->st), "graph launch");
-    } else {
-      rc = enqueue_trial(s, c, m.qr, m.lp, m.prm, queued);
-    }
-    queued = false;
-    if (rc) return rc;
-    const bool cg_read = pcg && s->use_h;
-    // eager QR runs queue the next trial's factor behind the record copy
-    const bool ahead = cg_read && m.qr && s->p <= 64 && !s->graphs;
-    if (ahead) rc = readback_cg_ls_ahead(s, c);
-    else rc = cg_read ? readback_cg_ls(s) : readback(s, hl, s->ls);
-    if (rc) return rc;
-    // a pending Hartree solve re-evaluates the trial first; the queued factor then returned
-    // without writing, and the next trial queues its own
-    queued = ahead && !hl->hartree_pending;
-    rc = run_after_trial(s, &m, cg_read);
-    if (rc) return rc;
+  if (!s) return fail(s, KS_E_INVAL, "null system");
+  MinRun* m = &s->run;
+  int rc = run_begin(s, X_inout, o, m);
+  if (rc) {
+    m->active = false;
+    return rc;
   }
-  return run_end(s, &m, r);
+  LsState* hl = host_ls(s);
+  while (hl->stop == KS_STOP_NONE && !hl->error) {
+    rc = run_trial(s, m);
+    if (rc) {
+      m->active = false;
+      return rc;
+    }
+  }
+  return run_end(s, m, r);
+}
+
+namespace {
+
+void fill_info(ks_system* s, ks_iter_info* info) {
+  if (!info) return;
+  const LsState* hl = host_ls(s);
+  info->k = hl->k;
+  info->nfe = hl->nfe;
+  info->backtracks = hl->backtracks;
+  info->stop_reason = hl->stop;
+  info->energy = hl->E;
+  info->grad_norm = std::sqrt(std::max(hl->g2, 0.0));
+  info->tau = hl->tau_acc;
+  info->C = hl->C;
+}
+
+// The saved state of a run: this header, then the device records of the current slot.
+struct StateHeader {
+  uint64_t magic;
+  int version, disc, precision, n, p, es;
+  size_t bytes;
+  ks_opt_params prm;
+  int reorths, pcg_extra, pcg_probe, last_cg_iters;
+  long long cg_total;
+};
+constexpr uint64_t kStateMagic = 0x3145544154534b53ull;  // "KSSTATE1"
+constexpr size_t kStateHead = 512;
+static_assert(sizeof(StateHeader) <= kStateHead, "state header must fit its slot");
+
+struct Part {
+  void* ptr;
+  size_t bytes;
+};
+
+// Device records a trial from slot c reads (see enqueue_trial): the orbital blocks and
+// their Gram blocks, the warm-start Hartree potential, the evaluation summary and the
+// line-search state.
+std::vector<Part> state_parts(ks_system* s, int c) {
+  const size_t blk = (size_t)s->n * s->p * s->es, pp2 = (size_t)s->pp * s->pp;
+  std::vector<Part> v = {{s->X[c], blk}, {s->G[c], blk}, {s->D[c], blk},
+                         {s->vh[c], (size_t)s->n * sizeof(double)},
+                         {s->gxg[c], 3 * pp2 * sizeof(double)},
+                         {s->gxd[c], 3 * pp2 * sizeof(double)},
+                         {s->ev[c], sizeof(EvalOut)}, {s->ls, sizeof(LsState)},
+                         {s->reorth_count, sizeof(int)}};
+  if (s->q1) {
+    v.push_back({s->Gt[c], blk});
+    v.push_back({s->BX[c], blk});
+    v.push_back({s->BD[c], blk});
+    v.push_back({s->feg[c], 3 * pp2 * sizeof(double)});
+  }
+  return v;
+}
+
+size_t state_size(ks_system* s) {
+  size_t off = kStateHead;
+  for (const Part& q : state_parts(s, 0)) off += (q.bytes + 255) / 256 * 256;
+  return off;
+}
+
+}  // namespace
+
+int ks_minimize_begin(ks_system* s, const void* X0, const ks_opt_params* o, ks_iter_info* info) {
+  if (!s || !X0) return fail(s, KS_E_INVAL, "null argument");
+  MinRun* m = &s->run;
+  int rc = run_begin(s, const_cast<void*>(X0), o, m);
+  m->X_inout = nullptr;  // results leave through ks_minimize_end
+  if (rc) {
+    m->active = false;
+    return rc;
+  }
+  fill_info(s, info);
+  const LsState* hl = host_ls(s);
+  if (hl->error) return fail(s, hl->error, ks_status_string(hl->error));
+  return KS_OK;
+}
+
+int ks_minimize_step(ks_system* s, ks_iter_info* info) {
+  if (!s) return fail(s, KS_E_INVAL, "null system");
+  MinRun* m = &s->run;
+  if (!m->active) return fail(s, KS_E_INVAL, "no run in progress (ks_minimize_begin)");
+  LsState* hl = host_ls(s);
+  while (hl->stop == KS_STOP_NONE && !hl->error) {
+    int rc = run_trial(s, m);
+    if (rc) {
+      m->active = false;
+      return rc;
+    }
+    if (hl->accepted) break;
+  }
+  fill_info(s, info);
+  if (hl->error) return fail(s, hl->error, ks_status_string(hl->error));
+  return KS_OK;
+}
+
+int ks_minimize_end(ks_system* s, void* X_out, ks_result* r) {
+  if (!s) return fail(s, KS_E_INVAL, "null system");
+  if (!s->run.active) return fail(s, KS_E_INVAL, "no run in progress (ks_minimize_begin)");
+  return run_end(s, &s->run, r, X_out);
+}
+
+size_t ks_state_bytes(ks_system* s) { return s ? state_size(s) : 0; }
+
+int ks_get_state(ks_system* s, void* buf) {
+  if (!s || !buf) return fail(s, KS_E_INVAL, "null argument");
+  MinRun* m = &s->run;
+  if (!m->active) return fail(s, KS_E_INVAL, "no run in progress (ks_minimize_begin)");
+  StateHeader h{};
+  h.magic = kStateMagic;
+  h.version = 1;
+  h.disc = s->d.disc;
+  h.precision = s->d.precision;
+  h.n = s->n;
+  h.p = s->p;
+  h.es = s->es;
+  h.bytes = state_size(s);
+  h.prm = m->prm;
+  h.reorths = m->reorths;
+  h.pcg_extra = s->pcg_extra;
+  h.pcg_probe = s->pcg_probe ? 1 : 0;
+  h.last_cg_iters = s->last_cg_iters;
+  h.cg_total = s->cg_total;
+  char* dst = static_cast<char*>(buf);
+  hipError_t e = hipMemcpyAsync(dst, &h, sizeof(h), hipMemcpyDefault, s->st);
+  size_t off = kStateHead;
+  for (const Part& q : state_parts(s, m->c)) {
+    if (e == hipSuccess) e = hipMemcpyAsync(dst + off, q.ptr, q.bytes, hipMemcpyDefault, s->st);
+    off += (q.bytes + 255) / 256 * 256;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  return hip_check(s, e, "state copy");
+}
+
+int ks_set_state(ks_system* s, const void* buf) {
+  if (!s || !buf) return fail(s, KS_E_INVAL, "null argument");
+  StateHeader h{};
+  hipError_t e = hipMemcpyAsync(&h, buf, sizeof(h), hipMemcpyDefault, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  int rc = hip_check(s, e, "state header copy");
+  if (rc) return rc;
+  if (h.magic != kStateMagic || h.version != 1)
+    return fail(s, KS_E_INVAL, "not a saved run state");
+  if (h.disc != s->d.disc || h.precision != s->d.precision || h.n != s->n || h.p != s->p ||
+      h.es != s->es || h.bytes != state_size(s))
+    return fail(s, KS_E_INVAL, "saved state belongs to a system of another shape");
+  MinRun* m = &s->run;
+  const int c = s->cur;
+  const char* src = static_cast<const char*>(buf);
+  size_t off = kStateHead;
+  for (const Part& q : state_parts(s, c)) {
+    if (e == hipSuccess) e = hipMemcpyAsync(q.ptr, src + off, q.bytes, hipMemcpyDefault, s->st);
+    off += (q.bytes + 255) / 256 * 256;
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->host, s->cg,
+                       reinterpret_cast<char*>(s->ls + 1) - reinterpret_cast<char*>(s->cg),
+                       hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  rc = hip_check(s, e, "state copy");
+  if (rc) return rc;
+  drop_graphs(s);
+  m->prm = h.prm;
+  m->lp = to_params(h.prm);
+  m->qr = h.prm.retraction == KS_QR;
+  m->c = c;
+  m->X_inout = nullptr;
+  m->t0 = std::chrono::steady_clock::now();
+  m->active = true;
+  m->queued = false;
+  m->records = false;
+  m->reorths = h.reorths;
+  s->bf16_on = !host_ls(s)->bf16_off;
+  s->pcg_extra = h.pcg_extra;
+  s->pcg_probe = h.pcg_probe != 0;
+  s->last_cg_iters = h.last_cg_iters;
+  s->cg_total = h.cg_total;
+  return KS_OK;
+}
+
+int ks_batch_step(ks_system* const* sys, int count, ks_iter_info* info) {
+  if (!sys || count < 1 || count > kMaxBatch) return fail(nullptr, KS_E_INVAL, "bad batch");
+  for (int i = 0; i < count; ++i) {
+    if (!sys[i]) return fail(nullptr, KS_E_INVAL, "null system");
+    for (int j = 0; j < i; ++j)
+      if (sys[j] == sys[i]) return fail(nullptr, KS_E_INVAL, "a system is listed twice");
+    if (!sys[i]->run.active)
+      return fail(sys[i], KS_E_INVAL, "no run in progress (ks_minimize_begin)");
+    if (!batchable(sys[i], sys[i]->run))
+      return fail(sys[i], KS_E_UNSUPPORTED, "run outside the lockstep runner's limits");
+  }
+  BatchEngine e;
+  e.st = sys[0]->st;
+  e.finish = false;
+  int rc = KS_OK;
+  for (int i = 0; i < count && rc == KS_OK; ++i) {
+    ks_system* s = sys[i];
+    rc = hip_check(s, hipStreamSynchronize(s->st), "batch start");
+    if (rc == KS_OK && !s->run.records) rc = upload_records(s, s->run);
+    const LsState* hl = host_ls(s);
+    if (rc == KS_OK && hl->stop == KS_STOP_NONE && !hl->error) {
+      BatchMember* bm = new BatchMember();
+      bm->s = s;
+      e.act.push_back(bm);
+    }
+  }
+  if (rc == KS_OK && !e.act.empty()) rc = batch_tick(&e);
+  if (rc == KS_OK) rc = hip_check(sys[0], hipStreamSynchronize(e.st), "batch step sync");
+  for (auto* bm : e.act) delete bm;
+  for (auto* bm : e.fin) {
+    if (rc == KS_OK && bm->code != KS_OK) rc = bm->code;
+    delete bm;
+  }
+  e.act.clear();
+  e.fin.clear();
+  if (e.ev) (void)hipEventDestroy(e.ev);
+  e.ev = nullptr;
+  for (int i = 0; i < count; ++i) fill_info(sys[i], info ? info + i : nullptr);
+  return rc;
 }
 
 int ks_minimize_batch(ks_system* const* sys, int count, void* const* X_inout,

@@ -19,14 +19,15 @@ constexpr double kPi = 3.14159265358979323846;
 // Scalar reduction slots (sums over the grid of one evaluation).
 enum Slot : int {
   SL_KIN = 0,   // sum_g,i X_gi (L X)_gi
-  SL_EXT = 1,   // sum_g V_ext,g sum_i X_gi^2
+  SL_EXT = 1,   // sum_g V_ext,g rho_g
   SL_EH = 2,    // sum_g rho_g V_H,g
   SL_EX = 3,    // sum_g rho_g eps_x(rho_g)
   SL_DD = 4,    // ||D||_F^2, D = G - X G^T X
   SL_SS = 5,    // tr(S^T S),  S = X_t - X_k
   SL_SY = 6,    // tr(S^T Yd), Yd = D_t - D_k
   SL_YY = 7,    // tr(Yd^T Yd)
-  SL_COUNT = 8
+  SL_DEFECT = 8,  // ||X^T G (bf16) - X^T G (exact)||_F^2 (KS_PREC_MIXED_BF16, p > 64)
+  SL_COUNT = 9
 };
 
 // Conjugate-gradient state kept on the device (one solve at a time per system).
@@ -51,6 +52,7 @@ struct EvalOut {
   double g2;        // ||grad E||_F^2
   double ss, sy, yy;
   double orth2;     // ||X^T X - I||_F^2
+  double defect2;   // SL_DEFECT of this evaluation (0 unless measured)
   double cg_relres;
   int cg_iters;
   int nonfinite;
@@ -59,6 +61,7 @@ struct EvalOut {
 // Optimiser parameters and state of Alg. 3 on the device.
 struct LsParams {
   double tau0, rho1, delta, eta, eps_g, tau_min, tau_max, reorth_tol, stagnation_tol;
+  double energy_target;  // stop once an accepted energy is <= this (-inf: never)
   int max_iter, bb_rule, h_max, retraction;
 };
 
@@ -79,7 +82,14 @@ struct LsState {
   int backtracks, ls_fail, nfe, reorth_flag;
   int error;           // KS_E_* raised by a device step
   int hartree_pending; // the trial's Hartree solve had not converged: nothing was judged
+  double tau_acc;      // step of the last accepted trial (0 before the first)
+  int bf16_off;        // KS_PREC_MIXED_BF16: the bf16 X^T G error reached kBf16Defect of
+                       // ||grad E||; the run forms X^T G exactly from here on
 };
+
+// The bf16 X^T G of KS_PREC_MIXED_BF16 stays in use while its measured error is below this
+// fraction of ||grad E||_F (the error enters the direction and the BB sums as noise).
+constexpr double kBf16Defect = 0.05;
 
 // The device records are carved at 256-byte boundaries and mirrored at fixed offsets in a
 // 1 KiB pinned host buffer.
@@ -205,12 +215,12 @@ struct HxArgs {
   T* Y;
   int ldy;
   const double* veff;
-  const double* vext;
   Grid gr;
   int p;
   double scale;
   Partials pt;
   double* gram_part;  // optional (p = 32, ld = 32): partial X^T X, X^T G tiles
+  int zrun;           // planes per work item of the Gram-fused kernel (hx_zrun)
 };
 
 
@@ -227,14 +237,16 @@ void launch_density(const T* X, int ld, int n, int p, double scale, double* rho,
                     hipStream_t st);
 void launch_xc(const double* rho, const double* vh, const double* vext, double* veff,
                Grid g, int use_h, int use_x, const CgState* cg, Partials pt, hipStream_t st);
+// Y = scale ((1/2) L X + Diag(veff) X); with pt the per-block partials of sum X.(L X)
 template <typename T>
-void launch_hx(const T* X, int ldx, T* Y, int ldy, const double* veff, const double* vext,
-               Grid g, int p, double scale, Partials* pt, double* gram_part, hipStream_t st);
+void launch_hx(const T* X, int ldx, T* Y, int ldy, const double* veff, Grid g, int p,
+               double scale, Partials* pt, double* gram_part, hipStream_t st);
 int hx_blocks(int n, int p);  // blocks (and energy partials) of launch_hx
 // With gram_part (p = 32, ld = 32, pt given) launch_hx also forms the partial Gram tiles
 // X^T X and X^T G (products 0 and 1) with hx_gram_blocks(n) blocks.
 int hx_gram_blocks(int n);
 bool hx_fuses_gram(int p);
+int hx_zrun(int nxy, int nz);  // planes per work item of the Gram-fused launch
 void launch_xc_batch(const BatchPtrs<XcArgs>& b, int blocks, hipStream_t st);
 template <typename T>
 void launch_hx_batch(const BatchPtrs<HxArgs<T>>& b, int blocks, bool gram, hipStream_t st);
@@ -385,10 +397,10 @@ void launch_hartree_iter(double* x, double* r, const double* z, double* pa, doub
 
 // trilinear finite elements (kernels_fe.hip)
 // G = scale ((1/2) A X + h^3 Diag(veff) X) (with kG) and BX = B X; with pt the partials
-// sum X.(AX) and h^3 sum vext X^2.  Blocks are n x p.
+// sum X.(AX).  Blocks are n x p.
 template <typename T>
-void launch_q1_apply(const T* X, T* G, T* BX, const double* veff, const double* vext, Grid g,
-                     int p, double scale, Partials* pt, hipStream_t st);
+void launch_q1_apply(const T* X, T* G, T* BX, const double* veff, Grid g, int p, double scale,
+                     Partials* pt, hipStream_t st);
 // Tables of the constant-coefficient tridiagonal solve with the 1D mass matrix (2N doubles)
 void launch_mass_setup(double* tab, int N, double h, hipStream_t st);
 // out = B^{-1} in (in and out may be the same block)
@@ -538,6 +550,13 @@ struct FinishEvalArgs {
 void launch_grad_weights(const double* gram, int pp, double* W, hipStream_t st);
 void launch_qr_factor(const double* xx, const double* gxd, int p, int pp, const double* tau,
                       double* A, double* B, double* work, int* status, hipStream_t st);
+// Per-tile partials (ceil(p/16)^2 of them, written to part) of ||xg - (xd - xx W)||_F^2:
+// with xd = X^T D and xx = X^T X exact products of the stored blocks (X^T B D, X^T B X for
+// finite elements) and D = G + X W, xd - xx W is the exact X^T G, so this is the error of
+// the bf16 X^T G in xg.
+void launch_bf16_defect(const double* xg, const double* xd, const double* xx, const double* W,
+                        int p, int pp, double* part, hipStream_t st);
+int bf16_defect_blocks(int p);
 // C = A + B W (p x p blocks of stride pp, FP64; C may not alias B or W).
 void launch_small_gemm_add(const double* A, const double* B, const double* W, double* C, int p,
                            int pp, hipStream_t st);
@@ -566,4 +585,8 @@ struct GatherArgs {
 };
 void launch_gather(const GatherArgs& g, hipStream_t st);
 void launch_ls_init(const EvalOut* ev, LsState* ls, LsParams prm, hipStream_t st);
+// After the current iterate was re-orthonormalised and evaluated again (ev): the
+// nonmonotone reference restarts there (C = E, Q = 1); k, the step and the stagnation
+// history are kept, and the gradient and energy-target tests are applied to the new point.
+void launch_ls_restart(const EvalOut* ev, LsState* ls, LsParams prm, hipStream_t st);
 }  // namespace ks

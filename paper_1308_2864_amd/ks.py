@@ -33,9 +33,10 @@ KS_HARTREE_CG, KS_HARTREE_PCG_FD = 0, 1
 KS_QR, KS_WY = 0, 1
 KS_BB_ALT, KS_BB1, KS_BB2 = 0, 1, 2
 KS_STOP_NONE, KS_STOP_GRAD, KS_STOP_STAGNATION, KS_STOP_MAXIT, KS_STOP_ERROR = 0, 1, 2, 3, 4
+KS_STOP_ENERGY = 5
 PHASES = ["hartree", "xc", "hamiltonian", "gram", "gradient", "retract", "small", "density"]
 KS_NPHASES = len(PHASES)
-STOP_NAMES = {0: "none", 1: "grad", 2: "stagnation", 3: "maxit", 4: "error"}
+STOP_NAMES = {0: "none", 1: "grad", 2: "stagnation", 3: "maxit", 4: "error", 5: "energy"}
 
 
 class ks_system_desc(C.Structure):
@@ -67,6 +68,7 @@ class ks_opt_params(C.Structure):
         ("eps_g", C.c_double), ("max_iter", C.c_int), ("bb_rule", C.c_int),
         ("retraction", C.c_int), ("tau_min", C.c_double), ("tau_max", C.c_double),
         ("h_max", C.c_int), ("reorth_tol", C.c_double), ("stagnation_tol", C.c_double),
+        ("reorth_every", C.c_int), ("energy_target", C.c_double),
     ]
 
 
@@ -77,6 +79,15 @@ class ks_result(C.Structure):
         ("grad_norm", C.c_double), ("terms", ks_energy), ("seconds", C.c_double),
         ("hartree_iters_total", C.c_longlong),
     ]
+
+
+class ks_iter_info(C.Structure):
+    _fields_ = [("k", C.c_int), ("nfe", C.c_int), ("backtracks", C.c_int),
+                ("stop_reason", C.c_int), ("energy", C.c_double), ("grad_norm", C.c_double),
+                ("tau", C.c_double), ("C", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class ks_request(C.Structure):
@@ -123,6 +134,13 @@ def _load():
         "ks_enable_graphs": (ip, [vp, ip]),
         "ks_minimize_batch": (ip, [C.POINTER(vp), ip, C.POINTER(vp), C.POINTER(ks_opt_params),
                                    C.POINTER(ks_result), C.POINTER(ip)]),
+        "ks_minimize_begin": (ip, [vp, vp, C.POINTER(ks_opt_params), C.POINTER(ks_iter_info)]),
+        "ks_minimize_step": (ip, [vp, C.POINTER(ks_iter_info)]),
+        "ks_minimize_end": (ip, [vp, vp, C.POINTER(ks_result)]),
+        "ks_state_bytes": (C.c_size_t, [vp]),
+        "ks_get_state": (ip, [vp, vp]),
+        "ks_set_state": (ip, [vp, vp]),
+        "ks_batch_step": (ip, [C.POINTER(vp), ip, C.POINTER(ks_iter_info)]),
         "ks_timer_phases": (ip, [vp, C.c_uint]),
         "ks_server_create": (ip, [vp, C.c_size_t, ip, C.POINTER(vp)]),
         "ks_server_create_batched": (ip, [vp, C.c_size_t, ip, C.POINTER(vp)]),
@@ -153,6 +171,13 @@ def _ptr(t):
     if t is None:
         return None
     return C.c_void_p(t.data_ptr())
+
+
+def _addr(buf):
+    """Address of a numpy array (host) or torch tensor (device or host)."""
+    if isinstance(buf, np.ndarray):
+        return buf.ctypes.data
+    return buf.data_ptr()
 
 
 def _check(code, handle=None):
@@ -250,6 +275,36 @@ class KSSystem:
         r.code = code
         return r
 
+    def ks_minimize_begin(self, X0, params=None) -> ks_iter_info:
+        info = ks_iter_info()
+        _check(lib.ks_minimize_begin(self.h, _ptr(X0),
+                                     C.byref(params) if params is not None else None,
+                                     C.byref(info)), self.h)
+        return info
+
+    def ks_minimize_step(self) -> ks_iter_info:
+        info = ks_iter_info()
+        _check(lib.ks_minimize_step(self.h, C.byref(info)), self.h)
+        return info
+
+    def ks_minimize_end(self, X_out=None, check=True) -> ks_result:
+        r = ks_result()
+        code = lib.ks_minimize_end(self.h, _ptr(X_out), C.byref(r))
+        if check and code not in (KS_OK, KS_E_NOT_CONVERGED):
+            _check(code, self.h)
+        r.code = code
+        return r
+
+    def ks_state_bytes(self) -> int:
+        return int(lib.ks_state_bytes(self.h))
+
+    def ks_get_state(self, buf):
+        """buf: a host numpy uint8 array or a device torch uint8 tensor of ks_state_bytes()."""
+        _check(lib.ks_get_state(self.h, C.c_void_p(_addr(buf))), self.h)
+
+    def ks_set_state(self, buf):
+        _check(lib.ks_set_state(self.h, C.c_void_p(_addr(buf))), self.h)
+
     def ks_density(self, X, rho):
         _check(lib.ks_density(self.h, _ptr(X), _ptr(rho)), self.h)
 
@@ -329,6 +384,16 @@ def ks_gram_static(A, B, out, stream=None):
     st = stream or torch.cuda.current_stream(A.device)
     _check(lib.ks_gram_static(_ptr(A), _ptr(B), int(n), int(p), int(A.stride(0)), prec,
                               _ptr(out), C.c_void_p(st.cuda_stream)))
+
+
+def ks_batch_step(systems):
+    """One lockstep trial for every listed KSSystem with a run begun (see include/ks.h).
+    Returns the list of ks_iter_info."""
+    n = len(systems)
+    hs = (C.c_void_p * n)(*[s.h for s in systems])
+    infos = (ks_iter_info * n)()
+    _check(lib.ks_batch_step(hs, n, infos))
+    return list(infos)
 
 
 def ks_request_bytes(desc) -> int:

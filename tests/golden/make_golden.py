@@ -7,6 +7,7 @@ of the FP64 oracle (``oracle/``); nothing comes from the GPU path.
     python tests/golden/make_golden.py c1 0 qr 1e-7        # oracle minimisation of c1
     python tests/golden/make_golden.py c2 0 qr 1e-6 1e-13  # c2 with the Section 4.1 stops
     python tests/golden/make_golden.py gap c1              # spectral gap at the c1 minimiser
+    python tests/golden/make_golden.py wide 80             # minimum of the p = 80 system
 """
 import math
 import os
@@ -94,12 +95,44 @@ def add_gap(cfg, seed=0, kind="qr"):
     open(fn, "w").writelines(lines)
 
 
+def wide_run(p):
+    """Oracle minimum of the wide test system (tests/helpers.py WIDE) from its X0."""
+    import time
+    from oracle import optm
+    from paper_1308_2864_amd import synth
+    from tests.helpers import oracle_fd, wide_spec
+    spec = wide_spec(p)
+    orc = oracle_fd(spec)
+    X0 = synth.make_x0(spec, 1)
+    t = time.time()
+    res = optm.minimize(orc.energy_grad, X0, optm.Params(eps_g=1e-7, stagnation_tol=1e-16,
+                                                         max_iter=20000))
+    el = time.time() - t
+    fn = os.path.join(HERE, f"oracle_wide_p{p}.txt")
+    with open(fn, "w") as fh:
+        fh.write(f"# FP64 oracle, Alg. 3 (QR), system {spec.name} seed {tests_seed(p)} from "
+                 f"make_x0(spec, 1),\n")
+        fh.write(f"# eps_g = 1e-7, stagnation tol = 1e-16; stopped by {res.stop} after "
+                 f"{res.iters} iterations, {el:.0f} s.\n")
+        fh.write(f"E = {repr(float(res.E))}\n")
+        fh.write(f"gnorm = {repr(float(res.gnorm))}\n")
+        fh.write(f"iters = {res.iters}\n")
+    print(fn, res.E, res.gnorm, res.iters, res.stop, el)
+
+
+def tests_seed(p):
+    from tests.helpers import WIDE
+    return WIDE[p][3]
+
+
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "box"
     if what == "box":
         box()
     elif what == "gap":
         add_gap(sys.argv[2])
+    elif what == "wide":
+        wide_run(int(sys.argv[2]))
     else:
         oracle_run(what, int(sys.argv[2]) if len(sys.argv) > 2 else 0,
                    sys.argv[3] if len(sys.argv) > 3 else "qr",

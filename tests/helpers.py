@@ -29,3 +29,15 @@ def oracle_q1(spec, **kw):
     args = dict(f=spec.f, rc=spec.rc, ext=spec.ext, hartree=spec.hartree, xc=spec.xc)
     args.update(kw)
     return KSSystemQ1(spec.nx, spec.ny, spec.nz, spec.h, spec.lo, spec.p, spec.R, spec.Z, **args)
+
+
+# Systems with blocks wider than 64 columns (the 64-column sub-block products and, with
+# KS_PREC_MIXED_BF16, the bf16 X^T G): (N, p, nuclei, seed) on [-8, 8]^3.
+WIDE = {80: (14, 80, 4, 5), 130: (16, 130, 6, 5)}
+
+
+def wide_spec(p):
+    from paper_1308_2864_amd import synth
+    N, pp, M, seed = WIDE[p]
+    return synth.make_system(N, N, N, 16.0 / (N + 1), pp, M, seed=seed, cfg="c5",
+                             lo=(-8.0,) * 3, margin=3.0, zrange=(1, 4))

@@ -1,0 +1,204 @@
+"""Alg. 3 one iteration at a time through the C ABI: ks_minimize_begin/step/end give
+ks_minimize's result bit for bit; a run saved with ks_get_state after 10 iterations and
+resumed with ks_set_state (on another system handle) continues bit for bit; ks_batch_step
+steps lockstep batches to the lone results; the energy-target stop and the periodic
+re-orthonormalisation (reorth_every) behave as stated."""
+import numpy as np
+import pytest
+
+from paper_1308_2864_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def ks():
+    from paper_1308_2864_amd import ks as _ks
+    return _ks
+
+
+def _spec(N=18, p=6, M=3, seed=0):
+    return synth.make_system(N, N, N, 16.0 / (N + 1), p, M, seed=seed, cfg="c5",
+                             lo=(-8.0,) * 3, margin=3.0, zrange=(1, 4))
+
+
+CASES = [
+    # (name, discretisation, Hartree solver, retraction, precision)
+    ("fd-pcg-qr-fp64", "fd", "pcg", "qr", "fp64"),
+    ("fd-cg-wy-fp64", "fd", "cg", "wy", "fp64"),
+    ("fd-pcg-qr-fp32", "fd", "pcg", "qr", "fp32"),
+    ("q1-pcg-qr-fp64", "q1", "pcg", "qr", "fp64"),
+]
+
+
+def _make(K, case, spec=None):
+    _, disc, hs, ret, prec = case
+    spec = spec or _spec()
+    if disc == "q1":
+        spec = spec.copy(disc="q1")
+    s = K.system_from_spec(spec, hartree_solver=K.KS_HARTREE_PCG_FD if hs == "pcg"
+                           else K.KS_HARTREE_CG,
+                           precision=K.KS_PREC_FP32 if prec == "fp32" else K.KS_PREC_FP64)
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    X0 = torch.tensor(synth.make_x0(spec, 1), dtype=dt, device="cuda")
+    prm = K.ks_default_params(max_iter=400, retraction=K.KS_WY if ret == "wy" else K.KS_QR)
+    return s, X0, prm
+
+
+def _same(r1, X1, r2, X2):
+    assert (r1.iters, r1.nfe, r1.backtracks, r1.stop_reason) == \
+        (r2.iters, r2.nfe, r2.backtracks, r2.stop_reason)
+    assert r1.energy == r2.energy and r1.grad_norm == r2.grad_norm
+    assert r1.hartree_iters_total == r2.hartree_iters_total
+    assert np.array_equal(X1.cpu().numpy(), X2.cpu().numpy())
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_steps_equal_ks_minimize_bitwise(case):
+    K = ks()
+    print(f"# steps {case[0]}", flush=True)
+    s, X0, prm = _make(K, case)
+    X = X0.clone()
+    ref = s.ks_minimize(X, prm, check=False)
+    info = s.ks_minimize_begin(X0, prm)
+    assert info.k == 0 and info.stop_reason == K.KS_STOP_NONE
+    ks_seen = []
+    while info.stop_reason == K.KS_STOP_NONE:
+        info = s.ks_minimize_step()
+        ks_seen.append(info.k)
+    # one accepted iteration per step, energies non-increasing against C_k
+    assert ks_seen == list(range(1, len(ks_seen) + 1))
+    Xs = torch.empty_like(X0)
+    r = s.ks_minimize_end(Xs, check=False)
+    _same(ref, X, r, Xs)
+    assert info.energy == ref.energy
+    s.close()
+
+
+@pytest.mark.parametrize("case", CASES[:1] + CASES[3:], ids=["fd", "q1"])
+@pytest.mark.parametrize("where", ["host", "device"])
+def test_state_resumes_bitwise_on_another_handle(case, where):
+    K = ks()
+    print(f"# state {case[0]} {where}", flush=True)
+    s, X0, prm = _make(K, case)
+    X = X0.clone()
+    ref = s.ks_minimize(X, prm, check=False)
+    s.ks_minimize_begin(X0, prm)
+    for _ in range(10):
+        info = s.ks_minimize_step()
+    assert info.k == 10 and info.stop_reason == K.KS_STOP_NONE
+    nb = s.ks_state_bytes()
+    buf = np.zeros(nb, np.uint8) if where == "host" else \
+        torch.zeros(nb, dtype=torch.uint8, device="cuda")
+    s.ks_get_state(buf)
+    # the original handle goes on to the end
+    while s.ks_minimize_step().stop_reason == K.KS_STOP_NONE:
+        pass
+    Xa = torch.empty_like(X0)
+    ra = s.ks_minimize_end(Xa, check=False)
+    _same(ref, X, ra, Xa)
+    # a second handle of the same descriptor resumes from the saved state
+    s2, _, _ = _make(K, case)
+    s2.ks_set_state(buf)
+    while s2.ks_minimize_step().stop_reason == K.KS_STOP_NONE:
+        pass
+    Xb = torch.empty_like(X0)
+    rb = s2.ks_minimize_end(Xb, check=False)
+    assert rb.iters == ra.iters and rb.nfe == ra.nfe and rb.energy == ra.energy
+    assert rb.backtracks == ra.backtracks and rb.stop_reason == ra.stop_reason
+    assert np.array_equal(Xa.cpu().numpy(), Xb.cpu().numpy())
+    # a state of another shape is refused
+    s3 = K.system_from_spec(_spec(p=5), hartree_solver=K.KS_HARTREE_PCG_FD)
+    with pytest.raises(K.KSError) as ei:
+        s3.ks_set_state(buf)
+    assert ei.value.code == K.KS_E_INVAL
+    for h in (s, s2, s3):
+        h.close()
+
+
+def test_batch_step_reaches_the_lone_results_bitwise():
+    K = ks()
+    prm = K.ks_default_params(max_iter=300)
+    specs = [_spec(16, 3, 2, 0), _spec(20, 17, 4, 1), _spec(18, 32, 3, 2), _spec(24, 8, 5, 3)]
+    lone, systems, blocks = [], [], []
+    for i, sp in enumerate(specs):
+        prec = K.KS_PREC_FP32 if i == 1 else K.KS_PREC_FP64
+        dt = torch.float32 if i == 1 else torch.float64
+        X0 = torch.tensor(synth.make_x0(sp, 1), dtype=dt, device="cuda")
+        s = K.system_from_spec(sp, hartree_solver=K.KS_HARTREE_PCG_FD, precision=prec)
+        X = X0.clone()
+        lone.append((s.ks_minimize(X, prm, check=False), X.cpu().numpy()))
+        s.ks_minimize_begin(X0, prm)
+        systems.append(s)
+        blocks.append(torch.empty_like(X0))
+    ticks = 0
+    while True:
+        infos = K.ks_batch_step(systems)
+        ticks += 1
+        if all(i.stop_reason != K.KS_STOP_NONE for i in infos):
+            break
+        assert ticks < 5000
+    for i, s in enumerate(systems):
+        r = s.ks_minimize_end(blocks[i], check=False)
+        ref, Xref = lone[i]
+        assert (r.iters, r.nfe, r.energy, r.backtracks) == \
+            (ref.iters, ref.nfe, ref.energy, ref.backtracks), i
+        assert np.array_equal(blocks[i].cpu().numpy(), Xref), i
+        s.close()
+
+
+def test_batch_step_rejects_runs_it_cannot_take():
+    K = ks()
+    sp = _spec()
+    a = K.system_from_spec(sp, hartree_solver=K.KS_HARTREE_PCG_FD)
+    b = K.system_from_spec(sp, hartree_solver=K.KS_HARTREE_CG)
+    X0 = torch.tensor(synth.make_x0(sp, 1), dtype=torch.float64, device="cuda")
+    with pytest.raises(K.KSError):  # no run begun
+        K.ks_batch_step([a])
+    a.ks_minimize_begin(X0)
+    b.ks_minimize_begin(X0)
+    with pytest.raises(K.KSError) as ei:
+        K.ks_batch_step([a, b])
+    assert ei.value.code == K.KS_E_UNSUPPORTED
+    with pytest.raises(K.KSError):
+        K.ks_batch_step([a, a])
+
+
+def test_energy_target_stops_the_run():
+    K = ks()
+    s, X0, _ = _make(K, CASES[0])
+    full = s.ks_minimize(X0.clone(), K.ks_default_params(max_iter=2000), check=False)
+    target = full.energy + 1e-4
+    prm = K.ks_default_params(max_iter=2000, energy_target=target)
+    r = s.ks_minimize(X0.clone(), prm, check=False)
+    assert r.stop_reason == K.KS_STOP_ENERGY
+    assert r.energy <= target and r.iters < full.iters
+    # the same run stopped one iteration earlier is still above the target
+    r1 = s.ks_minimize(X0.clone(), K.ks_default_params(max_iter=r.iters - 1), check=False)
+    assert r1.energy > target
+    # a target the start already meets stops before the first iteration
+    r0 = s.ks_minimize(X0.clone(), K.ks_default_params(energy_target=1e9), check=False)
+    assert r0.stop_reason == K.KS_STOP_ENERGY and r0.iters == 0
+
+
+@pytest.mark.parametrize("disc", ["fd", "q1"])
+def test_reorth_every_keeps_the_constraint_and_restarts_the_reference(disc):
+    K = ks()
+    case = ("fp32-" + disc, disc, "pcg", "qr", "fp32")
+    s, X0, _ = _make(K, case)
+    prm = K.ks_default_params(max_iter=60, reorth_every=7, stagnation_tol=0.0, eps_g=0.0)
+    info = s.ks_minimize_begin(X0, prm)
+    C_prev = info.C
+    while info.stop_reason == K.KS_STOP_NONE:
+        info = s.ks_minimize_step()
+        if info.k % 7 == 0 and info.stop_reason == K.KS_STOP_NONE:
+            # the reference restarts at the re-orthonormalised point: C_k = E_k
+            assert info.C == info.energy, info.k
+        C_prev = info.C
+    X = torch.empty_like(X0)
+    r = s.ks_minimize_end(X, check=False)
+    assert r.iters == 60 and r.reorths == 60 // 7
+    assert r.terms.orth_error < 1e-5
+    del C_prev
+    s.close()
