@@ -39,7 +39,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from .fd import FDGrid, e_nuclear, v_ext_erf
-from .ks import CV, CX, Energy
+from .ks import CV, CX, Energy, eps_c_rs, pz_rs, v_c_rs
 
 
 def k1d(m, h):
@@ -80,8 +80,10 @@ class KSSystemQ1:
     """One synthetic Kohn-Sham system discretised by Q1 finite elements."""
 
     def __init__(self, nx, ny, nz, h, lo, p, R, Z, f=2.0, rc=0.5, ext=True, hartree=True,
-                 xc=True, v_ext_override=None, hartree_tol=1e-14, hartree_maxit=20000):
+                 xc=True, v_ext_override=None, hartree_tol=1e-14, hartree_maxit=20000,
+                 corr=False):
         self.grid = FDGrid(nx, ny, nz, h, lo)
+        self.use_corr = bool(corr)
         self.n = self.grid.n
         self.p = int(p)
         self.f = float(f)
@@ -150,6 +152,10 @@ class KSSystemQ1:
             exc = h3 * float(rho @ (-CX * np.cbrt(rho)))
         else:
             vx, exc = np.zeros(self.n), 0.0
+        if self.use_corr:
+            rs = pz_rs(rho)
+            vx = vx + v_c_rs(rs)
+            exc += h3 * float(rho @ eps_c_rs(rs))
         total = kinetic + external + hartree + exc + self.e_ii
         return Energy(total, kinetic, external, hartree, exc, self.e_ii, it, rel), rho, vh, vx
 

@@ -13,7 +13,12 @@ with the readings needed to make the printed formulas consistent:
   Dirichlet boundary (the paper's "L^dagger rho" without its 4 pi); it is computed
   by conjugate gradients started from the previous potential.
 * Exchange-correlation is the Slater (Dirac) local exchange, spin unpolarised:
-  eps_x(rho) = -(3/4)(3/pi)^{1/3} rho^{1/3},  v_x = d(rho eps_x)/d rho.
+  eps_x(rho) = -(3/4)(3/pi)^{1/3} rho^{1/3},  v_x = d(rho eps_x)/d rho; optionally
+  (``corr=True``) plus LDA correlation in the Perdew-Zunger (1981) parametrisation of the
+  Ceperley-Alder electron gas, unpolarised: with r_s = (3/(4 pi rho))^{1/3},
+  eps_c = gamma/(1 + beta1 sqrt(r_s) + beta2 r_s) for r_s >= 1 and
+  eps_c = A ln r_s + B + C r_s ln r_s + D r_s for r_s < 1, v_c = d(rho eps_c)/d rho
+  = eps_c - (r_s/3) d eps_c/d r_s.
 * E = (f/2) tr(X^T L X) + h^3 sum V_ext rho + (h^3/2) rho^T V_H
       + h^3 sum rho eps_x(rho) + E_II.
 * The exact partial derivative of that E is
@@ -31,6 +36,48 @@ from .fd import FDGrid, e_nuclear, v_ext_erf
 
 CX = 0.75 * (3.0 / math.pi) ** (1.0 / 3.0)   # eps_x = -CX rho^{1/3}
 CV = (3.0 / math.pi) ** (1.0 / 3.0)          # v_x  = -CV rho^{1/3}
+
+# Perdew-Zunger (1981) unpolarised correlation constants
+PZ_GAMMA, PZ_BETA1, PZ_BETA2 = -0.1423, 1.0529, 0.3334
+PZ_A, PZ_B, PZ_C, PZ_D = 0.0311, -0.048, 0.0020, -0.0116
+
+
+def pz_rs(rho):
+    """Wigner-Seitz radius r_s = (3/(4 pi rho))^{1/3} (inf where rho = 0)."""
+    rho = np.asarray(rho, dtype=np.float64)
+    with np.errstate(divide="ignore"):
+        return np.where(rho > 0.0, np.cbrt(3.0 / (4.0 * math.pi * np.where(rho > 0.0, rho, 1.0))),
+                        np.inf)
+
+
+def eps_c_rs(rs):
+    """Correlation energy per electron as a function of r_s (both branches)."""
+    rs = np.asarray(rs, dtype=np.float64)
+    hi = rs < 1.0
+    zero = np.isinf(rs)                 # rho = 0: no correlation energy
+    r = np.where(hi | zero, 1.0, rs)    # low-density branch argument
+    q = np.where(hi, rs, 1.0)           # high-density branch argument
+    low = np.where(zero, 0.0, PZ_GAMMA / (1.0 + PZ_BETA1 * np.sqrt(r) + PZ_BETA2 * r))
+    lnq = np.log(q)
+    high = PZ_A * lnq + PZ_B + PZ_C * q * lnq + PZ_D * q
+    return np.where(hi, high, low)
+
+
+def v_c_rs(rs):
+    """v_c = eps_c - (r_s/3) d eps_c/d r_s, the derivative written out per branch."""
+    rs = np.asarray(rs, dtype=np.float64)
+    hi = rs < 1.0
+    zero = np.isinf(rs)
+    r = np.where(hi | zero, 1.0, rs)
+    q = np.where(hi, rs, 1.0)
+    den = 1.0 + PZ_BETA1 * np.sqrt(r) + PZ_BETA2 * r
+    low = np.where(zero, 0.0,
+                   PZ_GAMMA * (1.0 + (7.0 / 6.0) * PZ_BETA1 * np.sqrt(r)
+                               + (4.0 / 3.0) * PZ_BETA2 * r) / (den * den))
+    lnq = np.log(q)
+    high = (PZ_A * lnq + (PZ_B - PZ_A / 3.0) + (2.0 / 3.0) * PZ_C * q * lnq
+            + (2.0 * PZ_D - PZ_C) / 3.0 * q)
+    return np.where(hi, high, low)
 
 
 @dataclasses.dataclass
@@ -55,7 +102,8 @@ class KSSystemFD:
     """
 
     def __init__(self, nx, ny, nz, h, lo, p, R, Z, f=2.0, rc=0.5, ext=True, hartree=True,
-                 xc=True, v_ext_override=None, hartree_tol=1e-14, hartree_maxit=20000):
+                 xc=True, v_ext_override=None, hartree_tol=1e-14, hartree_maxit=20000,
+                 corr=False):
         self.grid = FDGrid(nx, ny, nz, h, lo)
         self.n = self.grid.n
         self.p = int(p)
@@ -64,6 +112,7 @@ class KSSystemFD:
         self.Z = np.asarray(Z, dtype=np.float64).ravel()
         self.rc = float(rc)
         self.use_ext, self.use_hartree, self.use_xc = bool(ext), bool(hartree), bool(xc)
+        self.use_corr = bool(corr)
         if v_ext_override is not None:
             self.v_ext = np.asarray(v_ext_override, dtype=np.float64).copy()
             self.e_ii = 0.0
@@ -112,6 +161,14 @@ class KSSystemFD:
     def v_x(rho):
         return -CV * np.cbrt(rho)
 
+    @staticmethod
+    def eps_c(rho):
+        return eps_c_rs(pz_rs(rho))
+
+    @staticmethod
+    def v_c(rho):
+        return v_c_rs(pz_rs(rho))
+
     # -- energy and gradient ----------------------------------------------------------------
     def energy_terms(self, X, vh0=None):
         """Returns (Energy, rho, V_H, v_x)."""
@@ -129,6 +186,9 @@ class KSSystemFD:
             exc = dV * float(rho @ self.eps_x(rho))
         else:
             vx, exc = np.zeros(self.n), 0.0
+        if self.use_corr:
+            vx = vx + self.v_c(rho)
+            exc += dV * float(rho @ self.eps_c(rho))
         total = kinetic + external + hartree + exc + self.e_ii
         return Energy(total, kinetic, external, hartree, exc, self.e_ii, it, rel), rho, vh, vx
 

@@ -66,6 +66,7 @@ class SystemSpec:
     ext: bool = True
     hartree: bool = True
     xc: bool = True
+    corr: bool = False  # LDA correlation (Perdew-Zunger) on top of the exchange
     name: str = ""
 
     @property
