@@ -39,7 +39,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from .fd import FDGrid, e_nuclear, v_ext_erf
-from .ks import CV, CX, Energy, eps_c_rs, pz_rs, v_c_rs
+from .ks import C_TF, CV, CX, Energy, eps_c_rs, pz_rs, v_c_rs
 
 
 def k1d(m, h):
@@ -81,9 +81,13 @@ class KSSystemQ1:
 
     def __init__(self, nx, ny, nz, h, lo, p, R, Z, f=2.0, rc=0.5, ext=True, hartree=True,
                  xc=True, v_ext_override=None, hartree_tol=1e-14, hartree_maxit=20000,
-                 corr=False):
+                 corr=False, mu=1.0, tf=False, vext="erf"):
         self.grid = FDGrid(nx, ny, nz, h, lo)
         self.use_corr = bool(corr)
+        # orbital-free (TFW, Section 2.2): von Weizsaecker weight mu on the stiffness term
+        # and the Thomas-Fermi term C_TF int rho^{5/3} (nodal quadrature)
+        self.mu = float(mu)
+        self.use_tf = bool(tf)
         self.n = self.grid.n
         self.p = int(p)
         self.f = float(f)
@@ -96,6 +100,10 @@ class KSSystemQ1:
         if v_ext_override is not None:
             self.v_ext = np.asarray(v_ext_override, dtype=np.float64).copy()
             self.e_ii = 0.0
+        elif ext and vext == "gnh":
+            from .gnh import v_ext_gnh
+            self.v_ext = v_ext_gnh(self.grid.coords(), R, Z)
+            self.e_ii = e_nuclear(R, Z)
         elif ext:
             self.v_ext = v_ext_erf(self.grid.coords(), R, Z, float(rc))
             self.e_ii = e_nuclear(R, Z)
@@ -140,7 +148,9 @@ class KSSystemQ1:
     def energy_terms(self, X, vh0=None):
         h3 = self.h3
         rho = self.density(X)
-        kinetic = 0.5 * self.f * float(np.sum(X * (self.A @ X)))
+        kinetic = 0.5 * self.mu * self.f * float(np.sum(X * (self.A @ X)))
+        if self.use_tf:
+            kinetic += h3 * C_TF * float(np.sum(rho ** (5.0 / 3.0)))
         external = h3 * float(self.v_ext @ rho)
         if self.use_hartree:
             vh, it, rel = self.hartree_cg(rho, vh0)
@@ -156,6 +166,8 @@ class KSSystemQ1:
             rs = pz_rs(rho)
             vx = vx + v_c_rs(rs)
             exc += h3 * float(rho @ eps_c_rs(rs))
+        if self.use_tf:
+            vx = vx + (5.0 / 3.0) * C_TF * np.cbrt(rho) ** 2
         total = kinetic + external + hartree + exc + self.e_ii
         return Energy(total, kinetic, external, hartree, exc, self.e_ii, it, rel), rho, vh, vx
 
@@ -163,7 +175,7 @@ class KSSystemQ1:
         """Returns (Energy, E_X, V_H)."""
         en, rho, vh, vx = self.energy_terms(X, vh0)
         veff = self.v_ext + vh + vx
-        G = 2.0 * self.f * (0.5 * (self.A @ X) + self.h3 * veff[:, None] * X)
+        G = 2.0 * self.f * (0.5 * self.mu * (self.A @ X) + self.h3 * veff[:, None] * X)
         return en, G, vh
 
     def energy(self, X, vh0=None):
@@ -171,7 +183,7 @@ class KSSystemQ1:
 
     def hamiltonian(self, veff):
         """Sparse H = 1/2 A + h^3 Diag(veff): E_X = 2 f H X and H X = B X Lambda at a minimiser."""
-        return (0.5 * self.A + self.h3 * sp.diags(veff)).tocsr()
+        return (0.5 * self.mu * self.A + self.h3 * sp.diags(veff)).tocsr()
 
     def effective_potential(self, X, vh0=None):
         en, rho, vh, vx = self.energy_terms(X, vh0)

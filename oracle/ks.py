@@ -37,6 +37,9 @@ from .fd import FDGrid, e_nuclear, v_ext_erf
 CX = 0.75 * (3.0 / math.pi) ** (1.0 / 3.0)   # eps_x = -CX rho^{1/3}
 CV = (3.0 / math.pi) ** (1.0 / 3.0)          # v_x  = -CV rho^{1/3}
 
+# Thomas-Fermi kinetic energy density of Section 2.2 eq. (TFW): C_TF rho^{5/3}
+C_TF = 0.3 * (3.0 * math.pi ** 2) ** (2.0 / 3.0)
+
 # Perdew-Zunger (1981) unpolarised correlation constants
 PZ_GAMMA, PZ_BETA1, PZ_BETA2 = -0.1423, 1.0529, 0.3334
 PZ_A, PZ_B, PZ_C, PZ_D = 0.0311, -0.048, 0.0020, -0.0116
@@ -103,7 +106,7 @@ class KSSystemFD:
 
     def __init__(self, nx, ny, nz, h, lo, p, R, Z, f=2.0, rc=0.5, ext=True, hartree=True,
                  xc=True, v_ext_override=None, hartree_tol=1e-14, hartree_maxit=20000,
-                 corr=False):
+                 corr=False, mu=1.0, tf=False, vext="erf"):
         self.grid = FDGrid(nx, ny, nz, h, lo)
         self.n = self.grid.n
         self.p = int(p)
@@ -113,9 +116,17 @@ class KSSystemFD:
         self.rc = float(rc)
         self.use_ext, self.use_hartree, self.use_xc = bool(ext), bool(hartree), bool(xc)
         self.use_corr = bool(corr)
+        # orbital-free (TFW, Section 2.2): von Weizsaecker weight mu on the kinetic term and
+        # the Thomas-Fermi term C_TF int rho^{5/3}
+        self.mu = float(mu)
+        self.use_tf = bool(tf)
         if v_ext_override is not None:
             self.v_ext = np.asarray(v_ext_override, dtype=np.float64).copy()
             self.e_ii = 0.0
+        elif self.use_ext and vext == "gnh":
+            from .gnh import v_ext_gnh
+            self.v_ext = v_ext_gnh(self.grid.coords(), self.R, self.Z)
+            self.e_ii = e_nuclear(self.R, self.Z)
         elif self.use_ext:
             self.v_ext = v_ext_erf(self.grid.coords(), self.R, self.Z, self.rc)
             self.e_ii = e_nuclear(self.R, self.Z)
@@ -174,7 +185,9 @@ class KSSystemFD:
         """Returns (Energy, rho, V_H, v_x)."""
         dV = self.grid.dV
         rho = self.density(X)
-        kinetic = 0.5 * self.f * float(np.sum(X * self.grid.lap(X)))
+        kinetic = 0.5 * self.mu * self.f * float(np.sum(X * self.grid.lap(X)))
+        if self.use_tf:
+            kinetic += dV * C_TF * float(np.sum(rho ** (5.0 / 3.0)))
         external = dV * float(self.v_ext @ rho)
         if self.use_hartree:
             vh, it, rel = self.hartree_cg(rho, vh0)
@@ -189,6 +202,8 @@ class KSSystemFD:
         if self.use_corr:
             vx = vx + self.v_c(rho)
             exc += dV * float(rho @ self.eps_c(rho))
+        if self.use_tf:
+            vx = vx + (5.0 / 3.0) * C_TF * np.cbrt(rho) ** 2
         total = kinetic + external + hartree + exc + self.e_ii
         return Energy(total, kinetic, external, hartree, exc, self.e_ii, it, rel), rho, vh, vx
 
@@ -196,15 +211,15 @@ class KSSystemFD:
         """Returns (Energy, G = E_X, V_H)."""
         en, rho, vh, vx = self.energy_terms(X, vh0)
         veff = self.v_ext + vh + vx
-        G = 2.0 * self.f * (0.5 * self.grid.lap(X) + veff[:, None] * X)
+        G = 2.0 * self.f * (0.5 * self.mu * self.grid.lap(X) + veff[:, None] * X)
         return en, G, vh
 
     def energy(self, X, vh0=None):
         return self.energy_terms(X, vh0)[0].total
 
     def hamiltonian_apply(self, X, veff):
-        """H X with H = 1/2 L + Diag(veff)  (no 2f factor)."""
-        return 0.5 * self.grid.lap(X) + veff[:, None] * X
+        """H X with H = mu/2 L + Diag(veff)  (no 2f factor)."""
+        return 0.5 * self.mu * self.grid.lap(X) + veff[:, None] * X
 
     def effective_potential(self, X, vh0=None):
         en, rho, vh, vx = self.energy_terms(X, vh0)

@@ -67,6 +67,9 @@ class SystemSpec:
     hartree: bool = True
     xc: bool = True
     corr: bool = False  # LDA correlation (Perdew-Zunger) on top of the exchange
+    tf: bool = False    # Thomas-Fermi kinetic term (orbital-free TFW with p = 1)
+    mu: float = 1.0     # weight of the kinetic (von Weizsaecker) term
+    vext: str = "erf"   # nuclear potential: "erf" (smoothed Coulomb) or "gnh" (pseudopotential)
     name: str = ""
 
     @property
@@ -161,6 +164,51 @@ def make_x0(spec: SystemSpec, seed=0, cfg: Optional[str] = None, stream=1) -> np
     A = make_random_block(spec.n, spec.p, seed=seed, cfg=cfg, stream=stream)
     Q, _ = np.linalg.qr(A, mode="reduced")
     return np.ascontiguousarray(Q)
+
+
+# ---- orbital-free workloads ------------------------------------------------------------
+AL_LATTICE = 7.559  # bohr, the aluminium cell of the paper's orbital-free experiments
+AL_VALENCE = 3.0
+
+
+def al_cluster(cells: int, a: float = AL_LATTICE) -> np.ndarray:
+    """(M, 3) positions of an fcc aluminium cluster of cells^3 unit cells, surface sites
+    included: the points (i, j, k) a/2 with i + j + k even and 0 <= i, j, k <= 2 cells,
+    centred at the origin (14 atoms for 1 cell, 365 for 4, 1688 for 7)."""
+    idx = np.arange(2 * cells + 1)
+    I, J, K = np.meshgrid(idx, idx, idx, indexing="ij")
+    keep = (I + J + K) % 2 == 0
+    R = np.stack([I[keep], J[keep], K[keep]], axis=1).astype(np.float64) * (0.5 * a)
+    return R - 0.5 * cells * a
+
+
+def make_ofdft(cells: int, N: int, margin: float = 4.0, mu: float = 1.0,
+               disc: str = "q1") -> SystemSpec:
+    """Orbital-free TFW system (p = 1) of an fcc Al cluster in a cube with margin bohr of
+    vacuum on each side, N interior nodes per axis; GNH nuclei of valence 3, LDA exchange
+    and correlation, occupation = number of valence electrons."""
+    R = al_cluster(cells)
+    M = R.shape[0]
+    L = cells * AL_LATTICE + 2.0 * margin
+    h = L / (N + 1)
+    return SystemSpec(nx=N, ny=N, nz=N, h=h, lo=(-0.5 * L,) * 3, p=1, R=R,
+                      Z=np.full(M, AL_VALENCE), f=AL_VALENCE * M, disc=disc, corr=True,
+                      tf=True, mu=mu, vext="gnh", name=f"of-al{M}-{N}^3")
+
+
+def make_atomic_guess(spec: SystemSpec, width: float = 1.5) -> np.ndarray:
+    """(n, 1) start for p = 1: the square root of a superposition of Gaussians of the given
+    width at the nuclei (positive everywhere; normalised by the solver)."""
+    g = np.arange(spec.nx) + 1
+    x = spec.lo[0] + g * spec.h
+    y = spec.lo[1] + (np.arange(spec.ny) + 1) * spec.h
+    z = spec.lo[2] + (np.arange(spec.nz) + 1) * spec.h
+    Zc, Yc, Xc = np.meshgrid(z, y, x, indexing="ij")
+    dens = np.zeros(Xc.shape)
+    for a in range(spec.R.shape[0]):
+        r2 = (Xc - spec.R[a, 0]) ** 2 + (Yc - spec.R[a, 1]) ** 2 + (Zc - spec.R[a, 2]) ** 2
+        dens += np.exp(-r2 / width ** 2)
+    return np.ascontiguousarray(np.sqrt(dens).reshape(-1, 1))
 
 
 @dataclasses.dataclass

@@ -8,6 +8,7 @@ of the FP64 oracle (``oracle/``); nothing comes from the GPU path.
     python tests/golden/make_golden.py c2 0 qr 1e-6 1e-13  # c2 with the Section 4.1 stops
     python tests/golden/make_golden.py gap c1              # spectral gap at the c1 minimiser
     python tests/golden/make_golden.py wide 80             # minimum of the p = 80 system
+    python tests/golden/make_golden.py ofdft               # TFW Al14 on Q1 elements
 """
 import math
 import os
@@ -120,6 +121,40 @@ def wide_run(p):
     print(fn, res.E, res.gnorm, res.iters, res.stop, el)
 
 
+def ofdft_run(N=35, margin=3.0):
+    """Oracle TFW ground state of Al14 (one fcc cell, GNH nuclei) on Q1 elements, Alg. 3 with
+    the QR retraction in the B metric from the atomic-density guess, eps_g = 1e-8."""
+    import time
+    from oracle import fe, optm
+    from paper_1308_2864_amd import synth
+    from tests.helpers import oracle_q1
+    spec = synth.make_ofdft(1, N, margin=margin, disc="q1")
+    orc = oracle_q1(spec)
+    mf = fe.BStiefel(orc.B, orc.mass_solve)
+    x0 = synth.make_atomic_guess(spec)
+    x0 = x0 / math.sqrt(float(x0[:, 0] @ (orc.B @ x0[:, 0])))
+    t = time.time()
+    res = optm.minimize(orc.energy_grad, x0, optm.Params(eps_g=1e-8, stagnation_tol=0.0,
+                                                         max_iter=5000), manifold=mf)
+    el = time.time() - t
+    x = res.X[:, 0]
+    charge = spec.h ** 3 * float(orc.density(res.X).sum())
+    fn = os.path.join(HERE, "oracle_ofdft_q1.txt")
+    with open(fn, "w") as fh:
+        fh.write(f"# FP64 oracle, Alg. 3 (QR, B metric), TFW Al14 {spec.name}, h = {spec.h},\n")
+        fh.write(f"# mu = 1, GNH nuclei, LDA exchange-correlation, from make_atomic_guess;\n")
+        fh.write(f"# eps_g = 1e-8; stopped by {res.stop} after {res.iters} iterations, "
+                 f"{el:.0f} s; one sign: {bool(np.all(x > 0) or np.all(x < 0))}.\n")
+        fh.write(f"N = {N}\nmargin = {margin}\n")
+        fh.write(f"E = {repr(float(res.E))}\n")
+        fh.write(f"gnorm = {repr(float(res.gnorm))}\n")
+        fh.write(f"iters = {res.iters}\n")
+        fh.write(f"charge = {repr(charge)}\n")
+        for nm in ("kinetic", "external", "hartree", "xc", "nuclear"):
+            fh.write(f"{nm} = {repr(float(getattr(res.energy, nm)))}\n")
+    print(fn, res.E, res.gnorm, res.iters, res.stop, el)
+
+
 def tests_seed(p):
     from tests.helpers import WIDE
     return WIDE[p][3]
@@ -133,6 +168,8 @@ if __name__ == "__main__":
         add_gap(sys.argv[2])
     elif what == "wide":
         wide_run(int(sys.argv[2]))
+    elif what == "ofdft":
+        ofdft_run()
     else:
         oracle_run(what, int(sys.argv[2]) if len(sys.argv) > 2 else 0,
                    sys.argv[3] if len(sys.argv) > 3 else "qr",
