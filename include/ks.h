@@ -80,7 +80,23 @@ extern "C" {
 #define KS_TERM_EXT 1            /* external (nuclear) potential                          */
 #define KS_TERM_HARTREE 2        /* Hartree potential                                     */
 #define KS_TERM_XC 4             /* Slater exchange                                       */
-#define KS_TERM_ALL 7
+#define KS_TERM_ALL 7            /* external + Hartree + Slater exchange                  */
+#define KS_TERM_CORR 8           /* LDA correlation, Perdew-Zunger (1981) parametrisation
+                                    of the Ceperley-Alder electron gas (unpolarised); with
+                                    KS_TERM_XC the full LDA of Section 4.  Its energy is
+                                    reported in ks_energy.xc with the exchange            */
+#define KS_TERM_TF 16            /* Thomas-Fermi kinetic energy C_TF int rho^{5/3}, C_TF =
+                                    (3/10)(3 pi^2)^{2/3} (Section 2.2 eq. (TFW)); reported in
+                                    ks_energy.kinetic.  With p = 1, occupation N (electrons)
+                                    and kinetic_scale mu, the run is the orbital-free TFW
+                                    model of eq. (OFeng): the kinetic term (mu f/2) X^T L X
+                                    is then the von Weizsaecker energy mu T_vW of
+                                    rho = N phi^2, and the constraint is int phi^2 = 1     */
+
+#define KS_VEXT_ERF 0            /* sum_a -Z_a erf(|r - R_a|/rc)/|r - R_a|                */
+#define KS_VEXT_GNH 1            /* Goodwin-Needs-Heine local pseudopotential of Section
+                                    4.2 (R = 1.15, R_c = 3.5, A = 0.1107), the
+                                    electron-ion attraction (tends to -Z/r)               */
 
 #define KS_HARTREE_CG 0          /* plain conjugate gradients, warm started               */
 #define KS_HARTREE_PCG_FD 1      /* CG preconditioned by the exact fast diagonalisation   */
@@ -118,14 +134,18 @@ typedef struct ks_system_desc {
   int hartree_solver;      /* KS_HARTREE_*                                                */
   double hartree_tol;      /* relative residual ||r||/||4 pi rho||; <= 0 means 1e-13      */
   int hartree_maxit;       /* <= 0 means 5000                                             */
+  double kinetic_scale;    /* mu: H = (mu/2) L + V_eff (the von Weizsaecker weight of
+                              eq. (TFW) for orbital-free runs); <= 0 means 1              */
+  int vext_kind;           /* KS_VEXT_* form of the nuclear potential                     */
 } ks_system_desc;
 
 typedef struct ks_energy {
   double total;            /* E_KS, eq. (EKS) in the discrete form of Section 2.3         */
-  double kinetic;          /* (f/2) tr(X^T L X), L = -Laplacian_h                         */
+  double kinetic;          /* (mu f/2) tr(X^T L X), L = -Laplacian_h (plus the
+                              Thomas-Fermi energy with KS_TERM_TF)                        */
   double external;         /* h^3 sum V_ext rho                                           */
   double hartree;          /* (h^3/2) rho^T V_H                                           */
-  double xc;               /* h^3 sum rho eps_x(rho)                                      */
+  double xc;               /* h^3 sum rho (eps_x(rho) + eps_c(rho) with KS_TERM_CORR)      */
   double nuclear;          /* E_II                                                        */
   double grad_norm;        /* ||G - X G^T X||_F with G = E_X                              */
   double orth_error;       /* ||X^T X - I||_F                                             */

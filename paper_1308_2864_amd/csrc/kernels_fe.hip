@@ -177,7 +177,7 @@ __global__ __launch_bounds__(256) void k_q1_apply(const T* __restrict__ X, T* __
           const double s1 = Pc[rr][1] + Pm[rr][0] + Pn[0];
           const double s2 = Pc[rr][2] + Pm[rr][1] + Pn[1];
           const double s3 = Pm[rr][2] + Pn[2];
-          const double ax = cf.a0 * s0 + cf.a2 * s2 + cf.a3 * s3;
+          const double ax = gr.mu * (cf.a0 * s0 + cf.a2 * s2 + cf.a3 * s3);
           const double bx = cf.b0 * s0 + cf.b1 * s1 + cf.b2 * s2 + cf.b3 * s3;
           const size_t g = (size_t)i + (size_t)gr.nx * ((size_t)j + (size_t)gr.ny * k);
           const size_t o = g * p + c;

@@ -6,6 +6,8 @@
 // blocks are n x ld row-major ("grid-major"): consecutive threads walk consecutive
 // orbitals of one grid point, then the next point, so every wavefront load is one
 // contiguous segment.
+#include <cmath>
+
 #include "ks_common.h"
 
 namespace ks {
@@ -135,6 +137,37 @@ __global__ __launch_bounds__(256) void k_density(const T* __restrict__ X, int ld
   if (g < (size_t)n && sub == 0) rho[g] = scale * s;
 }
 
+// ---- LDA correlation: Perdew and Zunger (1981), unpolarised ------------------------------
+// Their parametrisation of the Ceperley-Alder electron-gas correlation energy per
+// electron as a function of r_s = (3/(4 pi rho))^{1/3}, and v_c = d(rho eps_c)/d rho =
+// eps_c - (r_s/3) d eps_c/d r_s written out per branch.
+constexpr double kPzGamma = -0.1423, kPzBeta1 = 1.0529, kPzBeta2 = 0.3334;
+constexpr double kPzA = 0.0311, kPzB = -0.048, kPzC = 0.0020, kPzD = -0.0116;
+
+__device__ inline void pz81(double rho, double* ec, double* vc) {
+  if (!(rho > 0.0)) {
+    *ec = 0.0;
+    *vc = 0.0;
+    return;
+  }
+  const double rs = cbrt(3.0 / (4.0 * kPi * rho));
+  if (rs >= 1.0) {
+    const double sq = sqrt(rs);
+    const double den = 1.0 + kPzBeta1 * sq + kPzBeta2 * rs;
+    *ec = kPzGamma / den;
+    *vc = kPzGamma * (1.0 + (7.0 / 6.0) * kPzBeta1 * sq + (4.0 / 3.0) * kPzBeta2 * rs) /
+          (den * den);
+  } else {
+    const double l = log(rs);
+    *ec = kPzA * l + kPzB + kPzC * rs * l + kPzD * rs;
+    *vc = kPzA * l + (kPzB - kPzA / 3.0) + (2.0 / 3.0) * kPzC * rs * l +
+          (2.0 * kPzD - kPzC) / 3.0 * rs;
+  }
+}
+
+// Thomas-Fermi constant of Section 2.2 eq. (TFW): (3/10)(3 pi^2)^{2/3}
+constexpr double kCtf = 2.871234000188191;
+
 // ---- Slater exchange, effective potential, Hartree/exchange/external energy partials ---
 // The external energy h^3 sum V_ext rho is summed here, from the density of the evaluated
 // block (formed from its stored values), rather than as sum V_ext X^2 in the Hamiltonian
@@ -160,16 +193,27 @@ __device__ inline void k_xc_body(const XcArgs& ka, int ks_bid, int ks_nb) {
   // (3/4)(3/pi)^{1/3} and (3/pi)^{1/3}
   const double cv = cbrt(3.0 / kPi), cx = 0.75 * cv;
   const bool trivial = use_h && cg != nullptr && cg->bb == 0.0;  // rho == 0: V_H = 0
-  double eh = 0.0, ex = 0.0, ee = 0.0;
+  double eh = 0.0, ex = 0.0, ee = 0.0, et = 0.0;
   for (size_t g = beg + threadIdx.x; g < end; g += blockDim.x) {
     const double r = rho[g];
     const double ve = vext[g];
     const double h = (use_h && !trivial) ? vh[g] : 0.0;
     double vx = 0.0, e = 0.0;
-    if (use_x) {
+    if (use_x & 1) {  // Slater exchange
       const double c = cbrt(r);
       vx = -cv * c;
       e = -cx * c;
+    }
+    if (use_x & 2) {  // LDA correlation
+      double ec, vc;
+      pz81(r, &ec, &vc);
+      vx += vc;
+      e += ec;
+    }
+    if (use_x & 4) {  // Thomas-Fermi kinetic energy C_TF rho^{5/3}: kinetic, not xc
+      const double c = cbrt(r), c2 = c * c;
+      vx += (5.0 / 3.0) * kCtf * c2;
+      et += r * kCtf * c2;
     }
     veff[g] = ve + h + vx;
     eh += r * h;
@@ -179,9 +223,11 @@ __device__ inline void k_xc_body(const XcArgs& ka, int ks_bid, int ks_nb) {
   eh = block_sum(eh, sh);
   ex = block_sum(ex, sh);
   ee = block_sum(ee, sh);
+  et = block_sum(et, sh);
   write_partial(pt, SL_EH, lb, eh);
   write_partial(pt, SL_EX, lb, ex);
   write_partial(pt, SL_EXT, lb, ee);
+  write_partial(pt, SL_TF, lb, et);
 }
 
 __global__ void k_xc(XcArgs ka) {
@@ -245,7 +291,7 @@ __device__ inline void hx_items_run(const HxArgs<T>& ka, int lb, int nblk, doubl
   const int items = groups * ((nz + kRun - 1) / kRun);
   // element offsets fit 31 bits (n * ld < 2^31 is checked at system creation)
   const int sy = nx * ldx, szx = nxy * ldx, szy = nxy * ldy;
-  const double ih2 = gr.inv_h2, scale = ka.scale;
+  const double ih2 = gr.inv_h2 * gr.mu, scale = ka.scale;
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int nwaves = nblk * (kBlock / kWave);
   struct Stage {
@@ -364,7 +410,7 @@ __device__ inline void hx_gram_items(const HxArgs<T>& ka, int lb, int nblk, doub
   // element offsets fit 31 bits (n * ld < 2^31 is checked at system creation): each load is
   // the uniform base pointer plus a 32-bit lane offset and a uniform plane offset
   const int sy = nx * ld, sz = nxy * ld;
-  const double ih2 = gr.inv_h2, scale = ka.scale;
+  const double ih2 = gr.inv_h2 * gr.mu, scale = ka.scale;
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int c = 2 * (lane % 16), q = lane / 16;
   const int nwaves = nblk * (kBlock / kWave);
@@ -539,6 +585,103 @@ __global__ __launch_bounds__(256, 2) void k_hx_gram_batch(BatchPtrs<HxArgs<T>> b
 }
 
 
+// ---- GNH pseudopotential ----------------------------------------------------------------
+// V(r) = -(2/pi) int_0^inf sinc(r t) [(Z - A R_p) cos(R_p t) + A sin(R_p t)/t]
+//                exp(-(t/R_c)^6) dt  (Section 4.2; the electron-ion attraction, tending to
+// -Z/r), R_p = 1.15, R_c = 3.5, A = 0.1107.  It is linear in Z:  V = -[(Z - A R_p) T1 +
+// A T2] with the Z-free radial integrals T1, T2 (the 2/pi included), tabulated once on
+// r = 0, dr, ..., 20 bohr (dr = 1/2000) by composite Gauss-Legendre quadrature on t in
+// [0, 8] (128 panels of 32 nodes; exp(-(8/3.5)^6) < 1e-61) and interpolated by cubic
+// Lagrange polynomials (T1, T2 are even in r, which gives the points left of r = 0).
+// Beyond the table the potential is -Z/r (the difference is below 1e-14 there).
+constexpr double kGnhRp = 1.15, kGnhRc = 3.5, kGnhA = 0.1107;
+constexpr int kGnhPanels = 128, kGnhNodes = 32, kGnhN = 40001;
+constexpr double kGnhDr = 1.0 / 2000.0, kGnhTmax = 8.0;
+
+struct GaussLegendre32 {
+  double x[kGnhNodes], w[kGnhNodes];
+};
+
+__global__ void k_gnh_table(double* __restrict__ tab, GaussLegendre32 gl) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= kGnhN) return;
+  const double r = j * kGnhDr;
+  const double hp = 0.5 * kGnhTmax / kGnhPanels;
+  double t1 = 0.0, t2 = 0.0;
+  for (int pn = 0; pn < kGnhPanels; ++pn) {
+    const double mid = (2 * pn + 1) * hp;
+    for (int q = 0; q < kGnhNodes; ++q) {
+      const double t = mid + hp * gl.x[q], w = hp * gl.w[q];
+      const double rt = r * t;
+      const double sinc = rt > 0.0 ? sin(rt) / rt : 1.0;
+      const double u = t / kGnhRc, u2 = u * u;
+      const double e = exp(-(u2 * u2 * u2));
+      t1 += w * sinc * cos(kGnhRp * t) * e;
+      t2 += w * sinc * (sin(kGnhRp * t) / t) * e;
+    }
+  }
+  tab[j] = (2.0 / kPi) * t1;
+  tab[kGnhN + j] = (2.0 / kPi) * t2;
+}
+
+__global__ void k_vext_gnh(double* __restrict__ v, const double* __restrict__ R,
+                           const double* __restrict__ Z, int M, Grid g,
+                           const double* __restrict__ tab) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= g.n) return;
+  const int i = idx % g.nx, j = (idx / g.nx) % g.ny, k = idx / (g.nx * g.ny);
+  const double x = g.lo[0] + (i + 1) * g.h, y = g.lo[1] + (j + 1) * g.h,
+               z = g.lo[2] + (k + 1) * g.h;
+  const double rmax = (kGnhN - 3) * kGnhDr;
+  double acc = 0.0;
+  for (int a = 0; a < M; ++a) {
+    const double dx = x - R[3 * a], dy = y - R[3 * a + 1], dz = z - R[3 * a + 2];
+    const double d = sqrt(dx * dx + dy * dy + dz * dz);
+    const double Za = Z[a];
+    if (d >= rmax) {
+      acc -= Za / d;
+      continue;
+    }
+    const double u = d / kGnhDr;
+    const int j0 = (int)u;
+    const double f = u - j0;
+    const int jm = j0 > 0 ? j0 - 1 : 1;  // T(-dr) = T(dr)
+    const double wm = -f * (f - 1.0) * (f - 2.0) / 6.0, w0 = (f + 1.0) * (f - 1.0) * (f - 2.0) / 2.0,
+                 w1 = -(f + 1.0) * f * (f - 2.0) / 2.0, w2 = (f + 1.0) * f * (f - 1.0) / 6.0;
+    const double T1 = wm * tab[jm] + w0 * tab[j0] + w1 * tab[j0 + 1] + w2 * tab[j0 + 2];
+    const double* t2 = tab + kGnhN;
+    const double T2 = wm * t2[jm] + w0 * t2[j0] + w1 * t2[j0 + 1] + w2 * t2[j0 + 2];
+    acc -= (Za - kGnhA * kGnhRp) * T1 + kGnhA * T2;
+  }
+  v[idx] = acc;
+}
+
+// Nodes and weights of the 32-point Gauss-Legendre rule on [-1, 1]: Newton's method on the
+// Legendre polynomial (three-term recurrence) from the Chebyshev-type first guesses.
+GaussLegendre32 gauss_legendre32() {
+  GaussLegendre32 g{};
+  const int n = kGnhNodes;
+  for (int i = 0; i < n; ++i) {
+    double x = std::cos(kPi * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    g.x[i] = x;
+    g.w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+  return g;
+}
+
 // ---- fixed-order reduction of per-block partials: one block per slot ---------------
 
 }  // namespace
@@ -549,6 +692,16 @@ void launch_vext(double* v, const double* R, const double* Z, int M, Grid g, dou
                  hipStream_t st) {
   hipLaunchKernelGGL(k_vext, dim3((g.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, v, R, Z,
                      M, g, rc);
+}
+
+size_t gnh_table_doubles() { return 2 * (size_t)kGnhN; }
+
+void launch_vext_gnh(double* v, const double* R, const double* Z, int M, Grid g, double* table,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_gnh_table, dim3((kGnhN + 255) / 256), dim3(256), 0, st, table,
+                     gauss_legendre32());
+  hipLaunchKernelGGL(k_vext_gnh, dim3((g.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, v, R,
+                     Z, M, g, table);
 }
 
 void launch_enuc(double* out, const double* R, const double* Z, int M, hipStream_t st) {

@@ -803,7 +803,8 @@ __device__ inline void k_finish_eval_body(const FinishEvalArgs& ka, int ks_bid, 
   acc = orth;
   for (int sl = 0; sl < SL_COUNT; ++sl) sums[sl] = red[sl];
   EvalOut o;
-  o.kinetic = 0.5 * f * red[SL_KIN];
+  // the kinetic partial carries the weight mu; the Thomas-Fermi term is kinetic energy
+  o.kinetic = 0.5 * f * red[SL_KIN] + dV * red[SL_TF];
   o.external = dV * red[SL_EXT];  // h^3 sum V_ext rho
   o.hartree = 0.5 * dV * red[SL_EH];
   o.xc = dV * red[SL_EX];
@@ -1127,9 +1128,50 @@ void launch_qr_factor_next(const QrFactor2dArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_qr_factor_2d<64>, dim3(1), dim3(qr_threads<64>()), 0, st, a);
 }
 
+// One column (the orbital-free problem): eq. (WY-1d) gives x+ = (1 - beta_2) x - beta_1 a
+// with a = E_x in closed form from s = x^T x, t = a^T x, u = a^T a, two inner products
+// instead of the 2 x 2 solve.  In the B metric the same scalars are x^T B x, x^T g and
+// g^T B^{-1} g.  |x+|^2 drifting past reorth_tol rescales both weights.
+__global__ void k_wy_factor_1d(const double* __restrict__ gram, int pp,
+                               const double* __restrict__ tau_p, double reorth_tol,
+                               double* __restrict__ A, double* __restrict__ B, int* status,
+                               int* reorth_flag) {
+  if (threadIdx.x != 0) return;
+  const double tau = *tau_p, ht = 0.5 * tau;
+  const double s = gram[0], t = gram[pp * pp], u = gram[2 * pp * pp];
+  const double den = 1.0 - ht * ht * t * t + ht * ht * u * s;
+  if (!(den != 0.0) || !isfinite(den)) {
+    *status = KS_E_SINGULAR;
+    return;
+  }
+  const double b1 = tau * s / den;
+  const double b2 = -tau * (t + ht * (t * t - u * s)) / den;
+  double a = 1.0 - b2, b = -b1;
+  const double nrm2 = a * a * s + 2.0 * a * b * t + b * b * u;
+  if (fabs(nrm2 - 1.0) > reorth_tol) {
+    if (!(nrm2 > 0.0)) {
+      *status = KS_E_NOT_SPD;
+      return;
+    }
+    const double r = 1.0 / sqrt(nrm2);
+    a *= r;
+    b *= r;
+    if (reorth_flag) *reorth_flag += 1;
+  }
+  for (int e = 0; e < pp * pp; ++e) {
+    A[e] = e == 0 ? a : 0.0;
+    B[e] = e == 0 ? b : 0.0;
+  }
+}
+
 void launch_wy_factor(const double* gram_xg, int p, int pp, const double* tau,
                       double reorth_tol, double* A, double* B, double* work, int* status,
                       int* reorth_flag, hipStream_t st) {
+  if (p == 1) {
+    hipLaunchKernelGGL(k_wy_factor_1d, dim3(1), dim3(kWave), 0, st, gram_xg, pp, tau,
+                       reorth_tol, A, B, status, reorth_flag);
+    return;
+  }
   const size_t bytes = small_work_doubles(p) * sizeof(double);
   const bool lds = prepare_lds(k_wy_factor, bytes);
   hipLaunchKernelGGL(k_wy_factor, dim3(1), dim3(kBlock), lds ? bytes : 0, st, gram_xg, p, pp,

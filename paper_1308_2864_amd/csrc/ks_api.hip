@@ -99,8 +99,11 @@ struct ks_system {
   char* gstage = nullptr;
   void *Gt[2] = {}, *BX[2] = {}, *BD[2] = {};
   double* feg[2] = {};
+  // the Cayley system of the B metric per slot: [X^T B X, X^T G, G^T B^{-1} G]
+  double* wyg[2] = {};
   int solver = KS_HARTREE_CG;
   double *Rd = nullptr, *Zd = nullptr, *enuc = nullptr, *tau_user = nullptr;
+  double* gnh_tab = nullptr;  // radial table of the GNH pseudopotential (KS_VEXT_GNH)
   void *X[2] = {}, *G[2] = {}, *D[2] = {};  // float (FP32 modes) or double
   bool f32 = false;
   bool bf16 = false;  // KS_PREC_MIXED_BF16: float storage, Gram sub-products in bf16
@@ -185,6 +188,7 @@ void layout(ks_system* s, char* base, size_t* total) {
   s->Zd = c.take<double>((size_t)(M > 0 ? M : 1));
   s->enuc = c.take<double>(1);
   s->tau_user = c.take<double>(1);
+  if (s->d.vext_kind == KS_VEXT_GNH) s->gnh_tab = c.take<double>(gnh_table_doubles());
   for (int i = 0; i < 2; ++i) {
     s->X[i] = c.take<char>(np * s->es);
     s->G[i] = c.take<char>(np * s->es);
@@ -198,6 +202,7 @@ void layout(ks_system* s, char* base, size_t* total) {
       s->BX[i] = c.take<char>(np * s->es);
       s->BD[i] = c.take<char>(np * s->es);
       s->feg[i] = c.take<double>(3 * pp2);
+      s->wyg[i] = c.take<double>(3 * pp2);
     }
   }
   s->W = c.take<double>(pp2);
@@ -260,8 +265,17 @@ int validate(const ks_system_desc* d, std::string* why) {
   }
   if (!(d->occupation > 0.0)) { *why = "occupation must be > 0"; return KS_E_INVAL; }
   if (d->n_nuclei < 0) { *why = "n_nuclei must be >= 0"; return KS_E_INVAL; }
+  if (d->vext_kind != KS_VEXT_ERF && d->vext_kind != KS_VEXT_GNH) {
+    *why = "unknown vext_kind";
+    return KS_E_INVAL;
+  }
+  if (!(d->kinetic_scale >= 0.0) || !std::isfinite(d->kinetic_scale)) {
+    *why = "kinetic_scale must be >= 0";
+    return KS_E_INVAL;
+  }
   if (d->n_nuclei > 0 && (!d->R || !d->Z)) { *why = "R and Z are required"; return KS_E_INVAL; }
-  if ((d->terms & KS_TERM_EXT) && d->n_nuclei > 0 && !d->v_ext_override && !(d->rc > 0.0)) {
+  if ((d->terms & KS_TERM_EXT) && d->n_nuclei > 0 && !d->v_ext_override &&
+      d->vext_kind == KS_VEXT_ERF && !(d->rc > 0.0)) {
     *why = "rc must be > 0";
     return KS_E_INVAL;
   }
@@ -277,7 +291,8 @@ void init_dims(ks_system* s, const ks_system_desc* d) {
   s->f = d->occupation;
   s->use_ext = (d->terms & KS_TERM_EXT) ? 1 : 0;
   s->use_h = (d->terms & KS_TERM_HARTREE) ? 1 : 0;
-  s->use_x = (d->terms & KS_TERM_XC) ? 1 : 0;
+  s->use_x = ((d->terms & KS_TERM_XC) ? 1 : 0) | ((d->terms & KS_TERM_CORR) ? 2 : 0) |
+             ((d->terms & KS_TERM_TF) ? 4 : 0);
   s->htol = d->hartree_tol > 0.0 ? d->hartree_tol : 1e-13;
   s->hmaxit = d->hartree_maxit > 0 ? d->hartree_maxit : 5000;
   s->solver = d->hartree_solver;
@@ -298,6 +313,7 @@ void init_dims(ks_system* s, const ks_system_desc* d) {
   s->grid.q1 = s->q1 ? 1 : 0;
   // the finite-element Poisson problem is A V_H = 4 pi h^3 rho (nodal quadrature)
   s->grid.rhs_scale = s->q1 ? s->grid.dV : 1.0;
+  s->grid.mu = d->kinetic_scale > 0.0 ? d->kinetic_scale : 1.0;
 }
 
 // Density scale: rho_g = (f/h^3) sum X^2 on the grid (X^T X = I); rho_k = f sum X^2 at the
@@ -621,7 +637,8 @@ int hartree(ks_system* s, const double* rho, const double* x0, double* x, bool w
 // warm: slot whose V_H starts the CG.  Writes G, D, gram blocks, sums, ev of the slot.
 int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg,
                   const LsParams* judge = nullptr);
-int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd, const LsParams* judge);
+int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg,
+                     const LsParams* judge);
 
 // With judge, the summary kernel also runs the line-search judgement of the trial.
 int evaluate(ks_system* s, int idx, bool rho_ready, int bb_ref, int warm, bool want_gxd,
@@ -647,7 +664,7 @@ int evaluate(ks_system* s, int idx, bool rho_ready, int bb_ref, int warm, bool w
 // reductions and the evaluation summary of slot idx.
 int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg,
                   const LsParams* judge) {
-  if (s->q1) return evaluate_tail_q1(s, idx, bb_ref, want_gxd, judge);
+  if (s->q1) return evaluate_tail_q1(s, idx, bb_ref, want_gxd, want_gg, judge);
   const void* Xs = s->X[idx];
   Partials pt{s->spart, kPartStride};
   tbeg(s, KS_PH_XC);
@@ -669,7 +686,8 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
     tend(s, KS_PH_SMALL);
   } else {
     tbeg(s, KS_PH_GRAM);
-    gram_reduced(s, Xs, s->G[idx], mask1, s->gxg[idx], s->W, false, true);
+    // bf16 only for the QR retraction: the Cayley system takes X^T G as it is
+    gram_reduced(s, Xs, s->G[idx], mask1, s->gxg[idx], s->W, false, !want_gg);
     tend(s, KS_PH_GRAM);
   }
   // D = G - X (G^T X) with ||D||^2, the BB sums and (QR) the Gram blocks X^T D, D^T D:
@@ -725,7 +743,7 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
                        s->st);
   int nblk[kMaxScalarSlots] = {};
   nblk[SL_KIN] = hxg ? hx_gram_blocks(s->n) : hx_blocks(s->n, s->p);
-  nblk[SL_EH] = nblk[SL_EX] = nblk[SL_EXT] = scalar_blocks(s->n);
+  nblk[SL_EH] = nblk[SL_EX] = nblk[SL_EXT] = nblk[SL_TF] = scalar_blocks(s->n);
   nblk[SL_DD] = nblk[SL_SS] = nblk[SL_SY] = nblk[SL_YY] = combine_partial_blocks(s->n, s->p);
   nblk[SL_DEFECT] = defect ? bf16_defect_blocks(s->p) : 0;
   launch_finish_eval(s->spart, kPartStride, nblk, s->sums[idx], s->gxg[idx], s->p, s->pp, s->f,
@@ -735,11 +753,24 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
   return launch_check(s, "evaluate");
 }
 
+// The Cayley system in the B metric (Section 3 with Y = B^{1/2} X): with U = [B^{-1} G, X],
+// V = [X, -B^{-1} G] and the B inner product, V^T B U needs [X^T B X, X^T G, G^T B^{-1} G]
+// where the Euclidean form has [X^T X, X^T G, G^T G]; the same factor kernel then gives
+// X+ = X A + (B^{-1} G) B.  Called after B^{-1} G, X^T G and X^T B X of slot idx exist.
+void wy_blocks_q1(ks_system* s, int idx) {
+  const int pp2 = s->pp * s->pp;
+  launch_copy_vec(s->wyg[idx], s->feg[idx] + pp2, (size_t)pp2, s->st);
+  launch_copy_vec(s->wyg[idx] + pp2, s->gxg[idx] + pp2, (size_t)pp2, s->st);
+  // G^T (B^{-1} G) lands in product slot 1 of wyg + pp2, i.e. slot 2 of wyg
+  gram_reduced(s, s->G[idx], s->Gt[idx], kGramAB, s->wyg[idx] + pp2, nullptr, true);
+}
+
 // The finite-element evaluation in the B metric: G = E_X, BX = B X, Gt = B^{-1} G,
 // M = G^T X, D = grad E = Gt - X M and BD = B D = G - BX M (same weights), the Gram blocks
 // X^T B X (orthonormality and the Cholesky of the retraction), X^T BD and D^T BD (with
 // want_gxd), ||D||_B^2 and the BB sums of the B metric against slot bb_ref.
-int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd, const LsParams* judge) {
+int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg,
+                     const LsParams* judge) {
   const void* Xs = s->X[idx];
   const int pp2 = s->pp * s->pp;
   Partials pt{s->spart, kPartStride};
@@ -755,8 +786,9 @@ int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd, const LsP
   mass_solve(s, s->G[idx], s->Gt[idx]);
   tend(s, KS_PH_GRADIENT);
   tbeg(s, KS_PH_GRAM);
-  gram_reduced(s, Xs, s->G[idx], kGramAB, s->gxg[idx], s->W, false, true);
+  gram_reduced(s, Xs, s->G[idx], kGramAB, s->gxg[idx], s->W, false, !want_gg);
   gram_reduced(s, Xs, s->BX[idx], kGramAB, s->feg[idx], nullptr, true);
+  if (want_gg) wy_blocks_q1(s, idx);
   tend(s, KS_PH_GRAM);
   Q1GradArgs ga{};
   ga.Gt = s->Gt[idx];
@@ -801,7 +833,7 @@ int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd, const LsP
   tbeg(s, KS_PH_SMALL);
   int nblk[kMaxScalarSlots] = {};
   nblk[SL_KIN] = q1_apply_blocks(s->grid, s->p);
-  nblk[SL_EH] = nblk[SL_EX] = nblk[SL_EXT] = scalar_blocks(s->n);
+  nblk[SL_EH] = nblk[SL_EX] = nblk[SL_EXT] = nblk[SL_TF] = scalar_blocks(s->n);
   nblk[SL_DD] = nblk[SL_SS] = nblk[SL_SY] = nblk[SL_YY] = q1_grad_blocks(s->n, s->p);
   nblk[SL_DEFECT] = defect ? bf16_defect_blocks(s->p) : 0;
   launch_finish_eval(s->spart, kPartStride, nblk, s->sums[idx], s->feg[idx] + pp2, s->p, s->pp,
@@ -923,10 +955,10 @@ int enqueue_trial(ks_system* s, int c, bool qr, const LsParams& lp, const ks_opt
     ca.upper = true;
   } else {
     tbeg(s, KS_PH_SMALL);
-    launch_wy_factor(s->gxg[c], s->p, s->pp, &s->ls->tau, prm.reorth_tol, s->A, s->B, s->work,
-                     &s->ls->error, s->reorth_count, s->st);
+    launch_wy_factor(s->q1 ? s->wyg[c] : s->gxg[c], s->p, s->pp, &s->ls->tau, prm.reorth_tol,
+                     s->A, s->B, s->work, &s->ls->error, s->reorth_count, s->st);
     tend(s, KS_PH_SMALL);
-    ca.Y = s->G[c];
+    ca.Y = s->q1 ? s->Gt[c] : s->G[c];
   }
   tbeg(s, KS_PH_RETRACT);
   launch_combine(ca, s->st);
@@ -984,8 +1016,6 @@ int run_begin(ks_system* s, void* X_inout, const ks_opt_params* o, MinRun* m) {
     return fail(s, KS_E_INVAL, "bad line-search parameters");
   if (prm.reorth_every < 0 || std::isnan(prm.energy_target))
     return fail(s, KS_E_INVAL, "reorth_every must be >= 0 and energy_target not NaN");
-  if (s->q1 && prm.retraction != KS_QR)
-    return fail(s, KS_E_UNSUPPORTED, "finite elements use the QR retraction");
   m->lp = to_params(prm);
   m->qr = prm.retraction == KS_QR;
   m->X_inout = X_inout;
@@ -1271,7 +1301,7 @@ int upload_records(ks_system* s, const MinRun& m) {
     const int t = 1 - c;
     int nblk[kMaxScalarSlots] = {};
     nblk[SL_KIN] = hx_fuses_gram(s->p) ? hx_gram_blocks(s->n) : hx_blocks(s->n, s->p);
-    nblk[SL_EH] = nblk[SL_EX] = nblk[SL_EXT] = scalar_blocks(s->n);
+    nblk[SL_EH] = nblk[SL_EX] = nblk[SL_EXT] = nblk[SL_TF] = scalar_blocks(s->n);
     nblk[SL_DD] = nblk[SL_SS] = nblk[SL_SY] = nblk[SL_YY] = combine_blocks(s->n);
     ScalarCounts sc{};
     for (int i = 0; i < SL_COUNT; ++i) sc.v[i] = nblk[i];
@@ -1638,7 +1668,9 @@ int ks_create_system(const ks_system_desc* d, void* dev_workspace, size_t ws_byt
     return rc;
   }
   if (!d->v_ext_override) {
-    if (s->use_ext && M > 0) launch_vext(s->vext, s->Rd, s->Zd, M, s->grid, d->rc, s->st);
+    if (s->use_ext && M > 0 && d->vext_kind == KS_VEXT_GNH)
+      launch_vext_gnh(s->vext, s->Rd, s->Zd, M, s->grid, s->gnh_tab, s->st);
+    else if (s->use_ext && M > 0) launch_vext(s->vext, s->Rd, s->Zd, M, s->grid, d->rc, s->st);
     else launch_fill(s->vext, 0.0, s->n, s->st);
   }
   if (!d->v_ext_override && s->use_ext && M > 1) launch_enuc(s->enuc, s->Rd, s->Zd, M, s->st);
@@ -1822,8 +1854,6 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
   if (X_out == X || X_out == G) return fail(s, KS_E_INVAL, "X_out must not alias X or G");
   if (!std::isfinite(tau)) return fail(s, KS_E_INVAL, "tau must be finite");
   const int t = 1 - s->cur, c = s->cur;
-  if (s->q1 && kind != KS_QR)
-    return fail(s, KS_E_UNSUPPORTED, "finite elements use the QR retraction");
   copy_block(s, s->X[t], s->p, X, s->ld);
   copy_block(s, s->G[t], s->p, G, s->ld);
   const int all = kGramAA | kGramAB | kGramBB;
@@ -1832,7 +1862,7 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
     const int pp2 = s->pp * s->pp;
     q1_apply(s, s->X[t], nullptr, s->BX[t], nullptr, 1.0, nullptr);
     mass_solve(s, s->G[t], s->Gt[t]);
-    gram_reduced(s, s->X[t], s->G[t], kGramAB, s->gxg[t], s->W, false, true);
+    gram_reduced(s, s->X[t], s->G[t], kGramAB, s->gxg[t], s->W, false, kind == KS_QR);
     gram_reduced(s, s->X[t], s->BX[t], kGramAB, s->feg[t], nullptr, true);
     Q1GradArgs ga{};
     ga.Gt = s->Gt[t];
@@ -1850,8 +1880,9 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
     launch_q1_grad(ga, s->st);
     gram_reduced(s, s->X[t], s->BD[t], kGramAB, s->gxd[t], nullptr);
     gram_reduced(s, s->D[t], s->BD[t], kGramAB, s->gxd[t] + pp2, nullptr, true);
+    if (kind == KS_WY) wy_blocks_q1(s, t);
   } else {
-    gram_reduced(s, s->X[t], s->G[t], all, s->gxg[t], s->W, false, true);
+    gram_reduced(s, s->X[t], s->G[t], all, s->gxg[t], s->W, false, kind == KS_QR);
   }
   launch_set_scalar(s->tau_user, tau, s->st);
   int* hstat = host_int(s);
@@ -1887,9 +1918,9 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
     ca.Y = s->D[t];
     ca.upper = true;
   } else {
-    launch_wy_factor(s->gxg[t], s->p, s->pp, s->tau_user, INFINITY, s->A, s->B, s->work,
-                     s->status, nullptr, s->st);
-    ca.Y = s->G[t];
+    launch_wy_factor(s->q1 ? s->wyg[t] : s->gxg[t], s->p, s->pp, s->tau_user, INFINITY, s->A,
+                     s->B, s->work, s->status, nullptr, s->st);
+    ca.Y = s->q1 ? s->Gt[t] : s->G[t];
   }
   ca.X = s->X[t];
   ca.A = s->A;
@@ -1975,6 +2006,7 @@ std::vector<Part> state_parts(ks_system* s, int c) {
     v.push_back({s->BX[c], blk});
     v.push_back({s->BD[c], blk});
     v.push_back({s->feg[c], 3 * pp2 * sizeof(double)});
+    v.push_back({s->wyg[c], 3 * pp2 * sizeof(double)});
   }
   return v;
 }

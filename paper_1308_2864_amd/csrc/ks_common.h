@@ -27,7 +27,8 @@ enum Slot : int {
   SL_SY = 6,    // tr(S^T Yd), Yd = D_t - D_k
   SL_YY = 7,    // tr(Yd^T Yd)
   SL_DEFECT = 8,  // ||X^T G (bf16) - X^T G (exact)||_F^2 (KS_PREC_MIXED_BF16, p > 64)
-  SL_COUNT = 9
+  SL_TF = 9,      // sum_g rho_g eps_TF(rho_g) (Thomas-Fermi term, KS_TERM_TF)
+  SL_COUNT = 10
 };
 
 // Conjugate-gradient state kept on the device (one solve at a time per system).
@@ -104,6 +105,7 @@ struct Grid {
   double lo[3];
   int q1;            // 0: 7-point finite differences; 1: trilinear finite elements
   double rhs_scale;  // Poisson right-hand side 4 pi * rhs_scale * rho (FE: h^3)
+  double mu;         // weight of the kinetic (von Weizsaecker) term: H = mu/2 L + V_eff
 };
 
 __host__ __device__ inline int round_up(int a, int b) { return (a + b - 1) / b * b; }
@@ -203,7 +205,7 @@ struct XcArgs {
   double* veff;
   Grid gr;
   int use_h;
-  int use_x;
+  int use_x;        // bit 0: Slater exchange; bit 1: LDA correlation; bit 2: Thomas-Fermi
   const CgState* cg;
   Partials pt;
 };
@@ -227,6 +229,11 @@ struct HxArgs {
 // grid kernels (kernels_grid.hip)
 void launch_vext(double* v, const double* R, const double* Z, int M, Grid g, double rc,
                  hipStream_t st);
+// The GNH pseudopotential (Section 4.2) of nuclei R, Z on the grid through a radial table
+// (gnh_table_doubles() doubles of device scratch, filled here).
+size_t gnh_table_doubles();
+void launch_vext_gnh(double* v, const double* R, const double* Z, int M, Grid g, double* table,
+                     hipStream_t st);
 void launch_enuc(double* out, const double* R, const double* Z, int M, hipStream_t st);
 void launch_fill(double* x, double v, size_t n, hipStream_t st);
 void launch_copy_vec(double* dst, const double* src, size_t n, hipStream_t st);

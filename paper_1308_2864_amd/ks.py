@@ -28,7 +28,9 @@ KS_E_UNSUPPORTED = -8
 
 KS_DISC_FD7, KS_DISC_Q1 = 0, 1
 KS_PREC_FP64, KS_PREC_FP32, KS_PREC_MIXED_BF16 = 0, 1, 2
-KS_TERM_EXT, KS_TERM_HARTREE, KS_TERM_XC, KS_TERM_ALL = 1, 2, 4, 7
+KS_TERM_EXT, KS_TERM_HARTREE, KS_TERM_XC, KS_TERM_ALL, KS_TERM_CORR = 1, 2, 4, 7, 8
+KS_TERM_TF = 16
+KS_VEXT_ERF, KS_VEXT_GNH = 0, 1
 KS_HARTREE_CG, KS_HARTREE_PCG_FD = 0, 1
 KS_QR, KS_WY = 0, 1
 KS_BB_ALT, KS_BB1, KS_BB2 = 0, 1, 2
@@ -47,6 +49,7 @@ class ks_system_desc(C.Structure):
         ("R", C.POINTER(C.c_double)), ("Z", C.POINTER(C.c_double)), ("rc", C.c_double),
         ("terms", C.c_int), ("v_ext_override", C.POINTER(C.c_double)), ("precision", C.c_int),
         ("hartree_solver", C.c_int), ("hartree_tol", C.c_double), ("hartree_maxit", C.c_int),
+        ("kinetic_scale", C.c_double), ("vext_kind", C.c_int),
     ]
 
 
@@ -198,7 +201,8 @@ def ks_default_params(**overrides) -> ks_opt_params:
 
 def make_desc(nx, ny, nz, h, lo, p, R=None, Z=None, *, f=2.0, rc=0.5, terms=KS_TERM_ALL,
               v_ext_override=None, ld=0, precision=KS_PREC_FP64, disc=KS_DISC_FD7,
-              hartree_solver=KS_HARTREE_CG, hartree_tol=0.0, hartree_maxit=0):
+              hartree_solver=KS_HARTREE_CG, hartree_tol=0.0, hartree_maxit=0,
+              kinetic_scale=0.0, vext_kind=KS_VEXT_ERF):
     """Fills a ks_system_desc; the returned object keeps the host arrays alive."""
     d = ks_system_desc()
     d.disc, d.nx, d.ny, d.nz, d.h = disc, nx, ny, nz, float(h)
@@ -217,6 +221,7 @@ def make_desc(nx, ny, nz, h, lo, p, R=None, Z=None, *, f=2.0, rc=0.5, terms=KS_T
         d.v_ext_override = v.ctypes.data_as(C.POINTER(C.c_double))
     d.precision, d.hartree_solver = precision, hartree_solver
     d.hartree_tol, d.hartree_maxit = float(hartree_tol), int(hartree_maxit)
+    d.kinetic_scale, d.vext_kind = float(kinetic_scale), int(vext_kind)
     return d
 
 
@@ -345,9 +350,12 @@ class KSSystem:
 def desc_from_spec(spec, **kw):
     """A ks_system_desc for a ``synth.SystemSpec`` (keyword arguments go to make_desc)."""
     terms = (KS_TERM_EXT if spec.ext else 0) | (KS_TERM_HARTREE if spec.hartree else 0) | \
-            (KS_TERM_XC if spec.xc else 0)
+            (KS_TERM_XC if spec.xc else 0) | (KS_TERM_CORR if spec.corr else 0) | \
+            (KS_TERM_TF if spec.tf else 0)
     dkw = dict(f=spec.f, rc=spec.rc, terms=terms,
-               disc=KS_DISC_Q1 if spec.disc == "q1" else KS_DISC_FD7)
+               disc=KS_DISC_Q1 if spec.disc == "q1" else KS_DISC_FD7,
+               kinetic_scale=spec.mu,
+               vext_kind=KS_VEXT_GNH if spec.vext == "gnh" else KS_VEXT_ERF)
     dkw.update(kw)
     return make_desc(spec.nx, spec.ny, spec.nz, spec.h, spec.lo, spec.p, spec.R, spec.Z, **dkw)
 

@@ -165,14 +165,45 @@ def test_q1_retract_qr_matches_oracle(p):
         assert mf.orth_error(host(out)) < 1e-12
 
 
-def test_q1_wy_is_reported_unsupported():
+@pytest.mark.parametrize("p", [1, 5, 40, 80])
+def test_q1_wy_retraction_matches_oracle(p):
+    """The Cayley retraction in the B metric (eq. (WY3) with Y = B^{1/2} X; eq. (WY-1d) at
+    p = 1) against the oracle's B-metric form, for two steps, and it keeps X^T B X = I."""
     K = ks()
-    spec = fe_spec(p=3)
+    spec = fe_spec(p=p, seed=30 + p)
+    orc = oracle_q1(spec)
+    mf = BStiefel(orc.B, orc.mass_solve)
+    X = b_orthonormalize(orc.B, synth.make_x0(spec, 1))
+    G = orc.energy_grad(X)[1]
     sysg = K.system_from_spec(spec)
-    X = dev(synth.make_x0(spec, 1))
-    with pytest.raises(K.KSError) as ei:
-        sysg.ks_minimize(X, K.ks_default_params(retraction=K.KS_WY))
-    assert ei.value.code == K.KS_E_UNSUPPORTED
+    for tau in (1e-3, 0.05):
+        out = torch.zeros((spec.n, p), dtype=torch.float64, device="cuda")
+        sysg.ks_retract(dev(X), dev(G), tau, K.KS_WY, out)
+        ref = mf.retract("wy", X, G, tau)
+        assert np.max(np.abs(host(out) - ref)) <= 1e-11 * np.max(np.abs(ref)), (p, tau)
+        assert mf.orth_error(host(out)) < 1e-12
+
+
+@pytest.mark.parametrize("solver", ["cg", "pcg_fd"])
+def test_q1_minimize_wy_matches_oracle(solver):
+    """Alg. 3 with the Cayley retraction in the B metric, full physics, to the Section 4.1
+    rule: converged energy against the oracle's WY run at 1e-10 relative."""
+    K = ks()
+    spec = fe_spec(14, 12, 11, p=4, M=2, seed=7, h=0.6)
+    orc = oracle_q1(spec)
+    mf = BStiefel(orc.B, orc.mass_solve)
+    X0 = synth.make_x0(spec, 3)
+    ref = optm.minimize(orc.energy_grad, b_orthonormalize(orc.B, X0),
+                        optm.Params(eps_g=1e-6, stagnation_tol=0.0, max_iter=6000,
+                                    retraction="wy"), manifold=mf)
+    assert ref.stop == "grad"
+    sysg = K.system_from_spec(spec, hartree_solver=solver_id(K, solver))
+    X = dev(X0)
+    r = sysg.ks_minimize(X, K.ks_default_params(eps_g=1e-6, stagnation_tol=0.0, max_iter=6000,
+                                                retraction=K.KS_WY))
+    assert r.stop_reason == K.KS_STOP_GRAD
+    assert abs(r.energy - ref.E) <= 1e-10 * abs(ref.E)
+    assert mf.orth_error(host(X)) < 1e-11
 
 
 def test_q1_box_minimum_closed_form():

@@ -566,15 +566,20 @@ def test_minimize_c1_matches_oracle_reference(kind, solver):
     sysg = K.system_from_spec(spec, hartree_solver=solver,
                               **({"hartree_tol": 1e-14} if solver == 0 else {}))
     X = dev(synth.make_x0(spec, 0))
+    # the oracle needs 1549 iterations; a run stalled at the rounding floor (below) stops
+    # on max_iter
     r = sysg.ks_minimize(X, K.ks_default_params(
-        eps_g=1e-7, stagnation_tol=0.0, max_iter=20000,
+        eps_g=1e-7, stagnation_tol=0.0, max_iter=5000,
         retraction=K.KS_QR if kind == "qr" else K.KS_WY), check=False)
-    print(f"c1 {kind}: stop={K.STOP_NAMES[r.stop_reason]} it={r.iters} |grad|={r.grad_norm:.2e} "
-          f"E={r.energy:.14f} E_ref={gold['E']:.14f}", flush=True)
-    # 1e-7 lies near the rounding floor of the Armijo test on c1 (about sqrt(eps |E| / tau),
-    # 3e-8 .. 2e-7 depending on the trajectory): a run may stall just above it
+    print(f"c1 {kind}: stop={K.STOP_NAMES[r.stop_reason]} it={r.iters} nfe={r.nfe} "
+          f"|grad|={r.grad_norm:.2e} E={r.energy:.14f} E_ref={gold['E']:.14f}", flush=True)
+    # 1e-7 lies near the rounding floor of the Armijo test on c1, about sqrt(eps |E| / tau):
+    # 3e-8 .. 2e-7 on QR trajectories, and up to about 1e-6 on WY ones, whose last steps
+    # can shrink to tau ~ 1e-3.  A run may stall just above 1e-7; its energy must still
+    # agree with the oracle's.
+    floor = 3e-7 if kind == "qr" else 2e-6
     assert r.stop_reason == K.KS_STOP_GRAD or (r.stop_reason == K.KS_STOP_MAXIT and
-                                               r.grad_norm <= 3e-7)
+                                               r.grad_norm <= floor)
     assert abs(r.energy - gold["E"]) <= 1e-10 * abs(gold["E"])
     # The occupied subspace of c1 is ill-determined at ||grad E|| = 1e-7 (gap ~8e-3 Ha and a
     # softer nonlinear Hessian), so compare what is unique -- the energy above and the
