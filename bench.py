@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 METRIC = ("converged KS solves/sec + p50/p99 latency, FP32/BF16 vs FP64 at 1e-6 Ha; "
           "SpMM GB/s")
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+HARTREE_EV = 27.211386245988  # eV per hartree (CODATA 2018)
 
 
 def phase_bytes(n, p, w=8):
@@ -314,6 +315,58 @@ def serve_leg(ks, synth, n_req, slots, hbm_gib, fracs, precision, seed, check_n,
     return out
 
 
+def of_leg(ks, synth, cells, levels, n0, margin):
+    """Orbital-free TFW aluminium (Section 2.2; GNH nuclei, Section 4.2) on the 7-point
+    grid, p = 1: Alg. 3 on the finest grid from the atomic-density guess against Alg. 4
+    with uniform refinement (Table 5's strategy) over `levels` nested grids, both
+    retractions, the Section 4.1 stopping rules."""
+    import numpy as np
+    import torch
+    specs = synth.refine_levels(synth.make_ofdft(cells, n0, margin=margin, disc="fd7"), levels)
+    fine = specs[-1]
+    print(f"# orbital-free leg: Al{fine.M}, grids {[s.nx for s in specs]}, h = {fine.h:.4f}",
+          file=sys.stderr, flush=True)
+    systems = [ks.system_from_spec(s) for s in specs]
+    out = {"atoms": fine.M, "electrons": fine.f, "grids": [s.nx for s in specs],
+           "h_finest": fine.h, "n_finest": fine.n}
+
+    def guess(spec):
+        x = synth.make_atomic_guess(spec)
+        return torch.tensor(x / np.linalg.norm(x), dtype=torch.float64, device="cuda")
+
+    for kind in ("qr", "wy"):
+        prm = ks.ks_default_params(retraction=ks.KS_QR if kind == "qr" else ks.KS_WY)
+        X = guess(fine)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = systems[-1].ks_minimize(X, prm, check=False)
+        torch.cuda.synchronize()
+        direct_s = time.perf_counter() - t
+        blocks = [guess(specs[0])] + [torch.zeros((s.n, 1), dtype=torch.float64, device="cuda")
+                                      for s in specs[1:]]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rl = ks.ks_minimize_levels(systems, blocks, prm)
+        torch.cuda.synchronize()
+        levels_s = time.perf_counter() - t
+        out[kind] = {
+            "direct": {"iters": r.iters, "stop": ks.STOP_NAMES[r.stop_reason],
+                       "energy": r.energy, "energy_per_atom_eV": r.energy / fine.M * HARTREE_EV,
+                       "grad_norm": r.grad_norm, "seconds": round(direct_s, 4)},
+            "levels": {"iters": [x.iters for x in rl],
+                       "stop": [ks.STOP_NAMES[x.stop_reason] for x in rl],
+                       "energies": [x.energy for x in rl], "seconds": round(levels_s, 4),
+                       "energy_per_atom_eV": rl[-1].energy / fine.M * HARTREE_EV},
+            "abs_diff_Ha": abs(rl[-1].energy - r.energy),
+        }
+        print(f"# orbital-free {kind}: direct {r.iters} it {direct_s:.3f} s E={r.energy:.8f}; "
+              f"levels {[x.iters for x in rl]} it {levels_s:.3f} s E={rl[-1].energy:.8f}",
+              file=sys.stderr, flush=True)
+    for s in systems:
+        s.close()
+    return out
+
+
 def mixed_leg(ks, spec, solver, X0, E_ref, prm64, steps):
     import torch
     target = E_ref + 1e-6
@@ -428,6 +481,12 @@ def main():
                     help="iterations of the 128^3, p = 512 leg (0: skip it)")
     ap.add_argument("--c4-hartree", choices=["cg", "pcg_fd"], default="pcg_fd",
                     help="Hartree solver of that leg")
+    ap.add_argument("--of-cells", type=int, default=4,
+                    help="fcc cells per edge of the orbital-free aluminium leg (4: Al365; "
+                         "0 = skip)")
+    ap.add_argument("--of-levels", type=int, default=3,
+                    help="nested grids of that leg (finest 2^(L-1) (N0+1) - 1 nodes)")
+    ap.add_argument("--of-n0", type=int, default=31)
     ap.add_argument("--max-iter", type=int, default=10000,
                     help="iteration cap (profiling runs only; the metric needs the default)")
     args = ap.parse_args()
@@ -558,6 +617,9 @@ def main():
         serve = serve_leg(ks, synth, args.serve_requests, slots, args.serve_hbm_gib,
                           fr, args.serve_precision, args.seed, args.serve_check, batched,
                           args.serve_small)
+    ofdft = None
+    if args.of_cells > 0:
+        ofdft = of_leg(ks, synth, args.of_cells, args.of_levels, args.of_n0, 4.0)
     cpu = None
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
@@ -595,6 +657,7 @@ def main():
         "finite_elements": fe,
         "large_block": c4,
         "serving": serve,
+        "orbital_free": ofdft,
         "phases": phase_out,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -342,6 +342,34 @@ int ks_set_state(ks_system* s, const void* buf);
  * limits; nothing is launched), the first member error. */
 int ks_batch_step(ks_system* const* sys, int count, ks_iter_info* info);
 
+/* ---- Alg. 4 with uniform refinement -------------------------------------------------
+ * Alg. 4 solves the problem on a sequence of meshes, each level started from the solution
+ * of the next coarser one carried over to the finer mesh.  Here every level is the uniform
+ * refinement of the one before (the variant of Table 5; no a posteriori marking): same box
+ * and nuclei, half the spacing, 2N + 1 interior nodes per axis, so coarse node i is fine
+ * node 2i + 1.  Both systems of a pair must share the discretisation, precision, p and
+ * occupation. */
+
+/* Carries the coarse block Xc (device n_c x ld_c of `coarse`, only read) over to `fine`:
+ * trilinear interpolation of the nodal values (for Q1 elements the same finite-element
+ * function, exactly), on the 7-point grid rescaled by 2^{-3/2} (phi = X h^{-3/2}), then
+ * Cholesky QR (Alg. 2; in the B metric for elements).  Xf (device n_f x ld_f of `fine`)
+ * receives an orthonormal block (X^T X = I, or X^T B X = I).  The coarse stream is
+ * synchronised first; the work runs on the fine system's stream and is complete on return.
+ * Errors: KS_E_INVAL (not a nested pair, or a run of `fine` in progress), KS_E_NOT_SPD
+ * (the carried block is rank deficient), KS_E_HIP. */
+int ks_prolong(ks_system* coarse, const void* Xc, ks_system* fine, void* Xf);
+
+/* Alg. 4 over nlev (1..16) nested systems, coarsest first: ks_minimize on level 0 from
+ * X[0] (in/out, as for ks_minimize), then for each finer level ks_prolong from the level
+ * before into X[i] (device n_i x ld_i, written) and ks_minimize there, all with the
+ * parameters o (NULL: defaults).  A level that stops at max_iter still seeds the next.
+ * r (host, nlev entries, required) receives every level's statistics.  Returns KS_OK when
+ * the finest level converged, KS_E_NOT_CONVERGED when it stopped at max_iter, or the first
+ * error (naming its level in ks_last_error of that level's system). */
+int ks_minimize_levels(ks_system* const* levels, int nlev, void* const* X,
+                       const ks_opt_params* o, ks_result* r);
+
 /* ---- step-level calls (each is one step of ks_energy_grad) -------------------------- */
 
 /* rho (device, n doubles) = (f/h^3) sum_i X_gi^2 (Section 2.3, rho(X) = diag(X X^T)). */

@@ -725,6 +725,68 @@ template void launch_copy_block<double>(double*, int, const double*, int, int, i
                                         hipStream_t);
 template void launch_copy_block<float>(float*, int, const float*, int, int, int, hipStream_t);
 
+// ---- Alg. 4: carrying a block over to the uniformly refined mesh ------------------------
+// Fine index I along an axis of N coarse nodes: odd I is coarse node (I - 1)/2 itself, even
+// I lies half-way between coarse nodes I/2 - 1 and I/2, where -1 and N are the zero
+// boundary.  One thread per (fine node, column); the up to 8 coarse values are summed in
+// FP64 and rounded once.
+__device__ inline int prolong_axis(int I, int N, int* i0, int* i1) {
+  if (I & 1) {
+    *i0 = (I - 1) >> 1;
+    *i1 = -1;
+    return 1;
+  }
+  *i0 = (I >> 1) - 1;
+  *i1 = (I >> 1) < N ? (I >> 1) : -1;
+  return 2;
+}
+
+template <typename T>
+__global__ void k_prolong(const T* __restrict__ xc, int ldc, int cnx, int cny, int cnz,
+                          T* __restrict__ xf, int ldf, int p, double scale) {
+  const int fnx = 2 * cnx + 1, fny = 2 * cny + 1;
+  const size_t fn = (size_t)fnx * fny * (2 * cnz + 1);
+  const size_t total = fn * p;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const size_t node = e / p;
+    const int c = (int)(e - node * p);
+    const int I = (int)(node % fnx), J = (int)((node / fnx) % fny), K = (int)(node / ((size_t)fnx * fny));
+    int xi[2], yi[2], zi[2];
+    const int nxs = prolong_axis(I, cnx, &xi[0], &xi[1]);
+    const int nys = prolong_axis(J, cny, &yi[0], &yi[1]);
+    const int nzs = prolong_axis(K, cnz, &zi[0], &zi[1]);
+    const double wx = nxs == 1 ? 1.0 : 0.5, wy = nys == 1 ? 1.0 : 0.5, wz = nzs == 1 ? 1.0 : 0.5;
+    double acc = 0.0;
+    for (int a = 0; a < nzs; ++a) {
+      if (zi[a] < 0) continue;
+      for (int b = 0; b < nys; ++b) {
+        if (yi[b] < 0) continue;
+        for (int d = 0; d < nxs; ++d) {
+          if (xi[d] < 0) continue;
+          const size_t g = (size_t)xi[d] + (size_t)cnx * ((size_t)yi[b] + (size_t)cny * zi[a]);
+          acc += (double)xc[g * ldc + c];
+        }
+      }
+    }
+    xf[node * ldf + c] = (T)(scale * wx * wy * wz * acc);
+  }
+}
+
+template <typename T>
+void launch_prolong(const T* xc, int ldc, int cnx, int cny, int cnz, T* xf, int ldf, int p,
+                    double scale, hipStream_t st) {
+  const size_t total = (size_t)(2 * cnx + 1) * (2 * cny + 1) * (2 * cnz + 1) * p;
+  const size_t want = (total + kBlock - 1) / kBlock;
+  const unsigned nb = (unsigned)(want < 65536 ? (want < 1 ? 1 : want) : 65536);
+  hipLaunchKernelGGL(k_prolong<T>, dim3(nb), dim3(kBlock), 0, st, xc, ldc, cnx, cny, cnz, xf,
+                     ldf, p, scale);
+}
+template void launch_prolong<double>(const double*, int, int, int, int, double*, int, int,
+                                     double, hipStream_t);
+template void launch_prolong<float>(const float*, int, int, int, int, float*, int, int, double,
+                                    hipStream_t);
+
 template <typename T, int kG>
 void launch_density_g(const T* X, int ld, int n, int p, double scale, double* rho,
                       hipStream_t st) {

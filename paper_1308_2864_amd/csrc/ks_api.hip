@@ -1957,6 +1957,74 @@ int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* 
   return run_end(s, m, r);
 }
 
+int ks_prolong(ks_system* coarse, const void* Xc, ks_system* fine, void* Xf) {
+  if (!coarse || !fine || !Xc || !Xf) return fail(fine ? fine : coarse, KS_E_INVAL,
+                                                  "null argument");
+  if (coarse == fine) return fail(fine, KS_E_INVAL, "coarse and fine are the same system");
+  const Grid& c = coarse->grid;
+  const Grid& f = fine->grid;
+  const bool nested = f.nx == 2 * c.nx + 1 && f.ny == 2 * c.ny + 1 && f.nz == 2 * c.nz + 1 &&
+                      std::fabs(2.0 * f.h - c.h) <= 1e-12 * c.h &&
+                      std::fabs(f.lo[0] - c.lo[0]) <= 1e-12 * std::max(1.0, std::fabs(c.lo[0])) &&
+                      std::fabs(f.lo[1] - c.lo[1]) <= 1e-12 * std::max(1.0, std::fabs(c.lo[1])) &&
+                      std::fabs(f.lo[2] - c.lo[2]) <= 1e-12 * std::max(1.0, std::fabs(c.lo[2]));
+  if (!nested)
+    return fail(fine, KS_E_INVAL, "fine is not the uniform refinement of coarse (2N + 1 "
+                                  "nodes per axis, half the spacing, the same box)");
+  if (coarse->q1 != fine->q1 || coarse->f32 != fine->f32 || coarse->bf16 != fine->bf16 ||
+      coarse->p != fine->p)
+    return fail(fine, KS_E_INVAL, "coarse and fine differ in discretisation, precision or p");
+  if (fine->run.active) return fail(fine, KS_E_INVAL, "a run of the fine system is in progress");
+  int rc = hip_check(coarse, hipStreamSynchronize(coarse->st), "coarse stream");
+  if (rc) return rc;
+  // phi = X h^{-3/2} on the grid: halving h scales the nodal values by 2^{-3/2}; a Q1
+  // block is the same finite-element function on the finer mesh
+  const double scale = fine->q1 ? 1.0 : 1.0 / (2.0 * std::sqrt(2.0));
+  const int slot = fine->cur;
+  if (fine->f32)
+    launch_prolong<float>(static_cast<const float*>(Xc), coarse->ld, c.nx, c.ny, c.nz,
+                          static_cast<float*>(fine->X[slot]), fine->p, fine->p, scale, fine->st);
+  else
+    launch_prolong<double>(static_cast<const double*>(Xc), coarse->ld, c.nx, c.ny, c.nz,
+                           static_cast<double*>(fine->X[slot]), fine->p, fine->p, scale,
+                           fine->st);
+  rc = launch_check(fine, "prolong");
+  if (rc) return rc;
+  rc = orthonormalize_slot(fine, slot);
+  if (rc) return rc;
+  copy_block(fine, Xf, fine->ld, fine->X[slot], fine->p);
+  rc = launch_check(fine, "prolong copy");
+  if (rc) return rc;
+  return hip_check(fine, hipStreamSynchronize(fine->st), "prolong");
+}
+
+int ks_minimize_levels(ks_system* const* levels, int nlev, void* const* X,
+                       const ks_opt_params* o, ks_result* r) {
+  if (!levels || !X || !r || nlev < 1 || nlev > 16)
+    return fail(levels && nlev > 0 ? levels[0] : nullptr, KS_E_INVAL,
+                "levels, X and r are required, 1 <= nlev <= 16");
+  for (int i = 0; i < nlev; ++i)
+    if (!levels[i] || !X[i]) return fail(nullptr, KS_E_INVAL, "null level or block");
+  int rc = KS_OK;
+  for (int i = 0; i < nlev; ++i) {
+    if (i > 0) {
+      rc = ks_prolong(levels[i - 1], X[i - 1], levels[i], X[i]);
+      if (rc) {
+        levels[i]->err = "level " + std::to_string(i) + ": " + levels[i]->err;
+        g_err = levels[i]->err;
+        return rc;
+      }
+    }
+    rc = ks_minimize(levels[i], X[i], o, &r[i]);
+    if (rc != KS_OK && rc != KS_E_NOT_CONVERGED) {
+      levels[i]->err = "level " + std::to_string(i) + ": " + levels[i]->err;
+      g_err = levels[i]->err;
+      return rc;
+    }
+  }
+  return rc;
+}
+
 namespace {
 
 void fill_info(ks_system* s, ks_iter_info* info) {

@@ -239,6 +239,11 @@ void launch_fill(double* x, double v, size_t n, hipStream_t st);
 void launch_copy_vec(double* dst, const double* src, size_t n, hipStream_t st);
 template <typename T>
 void launch_copy_block(T* dst, int ldd, const T* src, int lds, int n, int p, hipStream_t st);
+// Trilinear interpolation of an n_c x p block (row stride ldc) from the (cnx, cny, cnz)
+// interior nodes to the nested (2cnx+1, 2cny+1, 2cnz+1) mesh (row stride ldf), times scale.
+template <typename T>
+void launch_prolong(const T* xc, int ldc, int cnx, int cny, int cnz, T* xf, int ldf, int p,
+                    double scale, hipStream_t st);
 template <typename T>
 void launch_density(const T* X, int ld, int n, int p, double scale, double* rho,
                     hipStream_t st);

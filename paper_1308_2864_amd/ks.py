@@ -144,6 +144,9 @@ def _load():
         "ks_get_state": (ip, [vp, vp]),
         "ks_set_state": (ip, [vp, vp]),
         "ks_batch_step": (ip, [C.POINTER(vp), ip, C.POINTER(ks_iter_info)]),
+        "ks_prolong": (ip, [vp, vp, vp, vp]),
+        "ks_minimize_levels": (ip, [C.POINTER(vp), ip, C.POINTER(vp), C.POINTER(ks_opt_params),
+                                    C.POINTER(ks_result)]),
         "ks_timer_phases": (ip, [vp, C.c_uint]),
         "ks_server_create": (ip, [vp, C.c_size_t, ip, C.POINTER(vp)]),
         "ks_server_create_batched": (ip, [vp, C.c_size_t, ip, C.POINTER(vp)]),
@@ -402,6 +405,26 @@ def ks_batch_step(systems):
     infos = (ks_iter_info * n)()
     _check(lib.ks_batch_step(hs, n, infos))
     return list(infos)
+
+
+def ks_prolong(coarse, Xc, fine, Xf):
+    """Carries a coarse block over to the uniformly refined system (Alg. 4; see
+    include/ks.h): Xf receives the interpolated, orthonormalised block."""
+    _check(lib.ks_prolong(coarse.h, _ptr(Xc), fine.h, _ptr(Xf)), fine.h)
+
+
+def ks_minimize_levels(systems, blocks, params=None):
+    """Alg. 4 with uniform refinement over nested KSSystem objects, coarsest first (see
+    include/ks.h): blocks[0] is the start (in/out), blocks[i] receive each level's result.
+    Returns the list of per-level ks_result; raises on errors other than max_iter."""
+    n = len(systems)
+    hs = (C.c_void_p * n)(*[s.h for s in systems])
+    xs = (C.c_void_p * n)(*[X.data_ptr() for X in blocks])
+    rs = (ks_result * n)()
+    rc = lib.ks_minimize_levels(hs, n, xs, C.byref(params) if params is not None else None, rs)
+    if rc not in (KS_OK, KS_E_NOT_CONVERGED):
+        _check(rc)  # the message of the failing level (the calling thread's last error)
+    return list(rs)
 
 
 def ks_request_bytes(desc) -> int:

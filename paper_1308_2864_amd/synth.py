@@ -196,6 +196,21 @@ def make_ofdft(cells: int, N: int, margin: float = 4.0, mu: float = 1.0,
                       tf=True, mu=mu, vext="gnh", name=f"of-al{M}-{N}^3")
 
 
+def refine_spec(spec: SystemSpec) -> SystemSpec:
+    """The uniform refinement of a system: same box and nuclei, half the spacing,
+    2N + 1 interior nodes per axis (coarse node i is fine node 2i + 1)."""
+    return spec.copy(nx=2 * spec.nx + 1, ny=2 * spec.ny + 1, nz=2 * spec.nz + 1,
+                     h=0.5 * spec.h, name=f"{spec.name}/2")
+
+
+def refine_levels(spec: SystemSpec, levels: int) -> List[SystemSpec]:
+    """spec and its levels - 1 successive uniform refinements, coarsest first."""
+    out = [spec]
+    for _ in range(levels - 1):
+        out.append(refine_spec(out[-1]))
+    return out
+
+
 def make_atomic_guess(spec: SystemSpec, width: float = 1.5) -> np.ndarray:
     """(n, 1) start for p = 1: the square root of a superposition of Gaussians of the given
     width at the nuclei (positive everywhere; normalised by the solver)."""
