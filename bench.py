@@ -326,7 +326,7 @@ def of_leg(ks, synth, cells, levels, n0, margin):
     fine = specs[-1]
     print(f"# orbital-free leg: Al{fine.M}, grids {[s.nx for s in specs]}, h = {fine.h:.4f}",
           file=sys.stderr, flush=True)
-    systems = [ks.system_from_spec(s) for s in specs]
+    systems = [ks.system_from_spec(s, hartree_solver=ks.KS_HARTREE_PCG_FD) for s in specs]
     out = {"atoms": fine.M, "electrons": fine.f, "grids": [s.nx for s in specs],
            "h_finest": fine.h, "n_finest": fine.n}
 
@@ -342,6 +342,13 @@ def of_leg(ks, synth, cells, levels, n0, margin):
         r = systems[-1].ks_minimize(X, prm, check=False)
         torch.cuda.synchronize()
         direct_s = time.perf_counter() - t
+        # the same solve again with every phase timed (outside the timed solve)
+        systems[-1].ks_enable_timers(True)
+        systems[-1].ks_read_timers(reset=True)
+        systems[-1].ks_minimize(guess(fine), prm, check=False)
+        ph = {k: [round(v[0], 3), int(v[1])] for k, v in
+              systems[-1].ks_read_timers(reset=True).items() if v[1]}
+        systems[-1].ks_enable_timers(False)
         blocks = [guess(specs[0])] + [torch.zeros((s.n, 1), dtype=torch.float64, device="cuda")
                                       for s in specs[1:]]
         torch.cuda.synchronize()
@@ -352,14 +359,18 @@ def of_leg(ks, synth, cells, levels, n0, margin):
         out[kind] = {
             "direct": {"iters": r.iters, "stop": ks.STOP_NAMES[r.stop_reason],
                        "energy": r.energy, "energy_per_atom_eV": r.energy / fine.M * HARTREE_EV,
-                       "grad_norm": r.grad_norm, "seconds": round(direct_s, 4)},
+                       "grad_norm": r.grad_norm, "seconds": round(direct_s, 4),
+                       "evals": r.nfe, "hartree_iters": r.hartree_iters_total,
+                       "phases_ms_count": ph},
             "levels": {"iters": [x.iters for x in rl],
                        "stop": [ks.STOP_NAMES[x.stop_reason] for x in rl],
                        "energies": [x.energy for x in rl], "seconds": round(levels_s, 4),
                        "energy_per_atom_eV": rl[-1].energy / fine.M * HARTREE_EV},
             "abs_diff_Ha": abs(rl[-1].energy - r.energy),
         }
-        print(f"# orbital-free {kind}: direct {r.iters} it {direct_s:.3f} s E={r.energy:.8f}; "
+        print(f"# orbital-free {kind}: phases {ph}", file=sys.stderr, flush=True)
+        print(f"# orbital-free {kind}: direct {r.iters} it ({r.nfe} evals, Hartree "
+              f"{r.hartree_iters_total} it) {direct_s:.3f} s E={r.energy:.8f}; "
               f"levels {[x.iters for x in rl]} it {levels_s:.3f} s E={rl[-1].energy:.8f}",
               file=sys.stderr, flush=True)
     for s in systems:

@@ -132,7 +132,10 @@ typedef struct ks_system_desc {
   const double* v_ext_override; /* host, n values replacing the nuclear potential, or NULL */
   int precision;           /* KS_PREC_*                                                   */
   int hartree_solver;      /* KS_HARTREE_*                                                */
-  double hartree_tol;      /* relative residual ||r||/||4 pi rho||; <= 0 means 1e-13      */
+  double hartree_tol;      /* relative residual ||r||/||4 pi rho||; <= 0 means 1e-13.
+                              A KS_HARTREE_PCG_FD solve whose residual stops falling
+                              (3 iterations without a 4x decrease: the rounding floor,
+                              about eps cond(L)) also ends once it is within 100x of it */
   int hartree_maxit;       /* <= 0 means 5000                                             */
   double kinetic_scale;    /* mu: H = (mu/2) L + V_eff (the von Weizsaecker weight of
                               eq. (TFW) for orbital-free runs); <= 0 means 1              */

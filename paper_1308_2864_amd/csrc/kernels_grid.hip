@@ -63,16 +63,19 @@ __global__ void k_vext(double* __restrict__ v, const double* __restrict__ R,
   v[idx] = acc;
 }
 
+// E_II = sum over pairs a < b of Z_a Z_b / |R_a - R_b|: one block, thread t sums the rows
+// a = t, t + blockDim, ... and the block adds the row sums in a fixed order.
 __global__ void k_enuc(double* out, const double* R, const double* Z, int M) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  __shared__ double sh[kBlock / kWave];
   double e = 0.0;
-  for (int a = 0; a < M; ++a)
+  for (int a = threadIdx.x; a < M; a += blockDim.x)
     for (int b = a + 1; b < M; ++b) {
       const double dx = R[3 * a] - R[3 * b], dy = R[3 * a + 1] - R[3 * b + 1],
                    dz = R[3 * a + 2] - R[3 * b + 2];
       e += Z[a] * Z[b] / sqrt(dx * dx + dy * dy + dz * dz);
     }
-  *out = e;
+  e = block_sum(e, sh);
+  if (threadIdx.x == 0) *out = e;
 }
 
 __global__ void k_fill(double* x, double v, size_t n) {
@@ -705,7 +708,7 @@ void launch_vext_gnh(double* v, const double* R, const double* Z, int M, Grid g,
 }
 
 void launch_enuc(double* out, const double* R, const double* Z, int M, hipStream_t st) {
-  hipLaunchKernelGGL(k_enuc, dim3(1), dim3(64), 0, st, out, R, Z, M);
+  hipLaunchKernelGGL(k_enuc, dim3(1), dim3(kBlock), 0, st, out, R, Z, M);
 }
 
 void launch_fill(double* x, double v, size_t n, hipStream_t st) {

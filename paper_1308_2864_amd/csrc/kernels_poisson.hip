@@ -154,6 +154,8 @@ __device__ inline void k_fin_init_body(const FinInitArgs& ka, int ks_bid, int ks
     cs->tol2 = tol * tol;
     cs->alpha = cs->beta = cs->pq = 0.0;
     cs->rz = 0.0;
+    cs->rr_best = rr;
+    cs->stall = 0;
     cs->it = bb == 0.0 ? 0 : ka.it0;  // rho == 0: nothing was solved
     cs->maxit = maxit;
     cs->done = (bb == 0.0 || !isfinite(rr) || !isfinite(bb) || rr <= tol * tol * bb) ? 1 : 0;
@@ -295,7 +297,17 @@ __device__ inline void k_fin_upd_body(const FinUpdArgs& ka, int ks_bid, int ks_n
     if (!pcg) cs->beta = rr / cs->rr;
     cs->rr = rr;
     cs->it += 1;
-    cs->done = (!isfinite(rr) || rr <= cs->tol2 * cs->bb || cs->it >= cs->maxit) ? 1 : 0;
+    bool floor = false;
+    if (pcg) {
+      if (rr < 0.25 * cs->rr_best) {
+        cs->stall = 0;
+      } else {
+        cs->stall += 1;
+      }
+      cs->rr_best = fmin(cs->rr_best, rr);
+      floor = cs->stall >= kCgStall && rr <= kCgFloor * kCgFloor * cs->tol2 * cs->bb;
+    }
+    cs->done = (!isfinite(rr) || rr <= cs->tol2 * cs->bb || floor || cs->it >= cs->maxit) ? 1 : 0;
   }
 }
 

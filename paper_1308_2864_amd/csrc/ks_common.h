@@ -42,10 +42,18 @@ struct CgState {
   int it;          // iterations done
   int maxit;
   int done;        // 1 once converged or at maxit
-  int pad;
+  int stall;       // preconditioned iterations since r.r last fell below rr_best / 4
   unsigned int count;  // arrival counter of the last-block reduction
   unsigned int pad2;
+  double rr_best;  // smallest r.r of the preconditioned solve so far
 };
+
+// A preconditioned solve whose residual has stopped falling (kCgStall iterations without
+// a 4x decrease) has reached the rounding floor of its operator, about eps cond(L) of the
+// right-hand side, which for grids of 128^3 nodes lies just above the default tolerance;
+// it ends there if r.r <= kCgFloor^2 tol^2 b.b.
+constexpr int kCgStall = 3;
+constexpr double kCgFloor = 100.0;
 
 // Results of one energy/gradient evaluation, assembled on the device.
 struct EvalOut {
