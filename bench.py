@@ -461,6 +461,9 @@ def main():
     ap.add_argument("--hartree", choices=["cg", "pcg_fd"], default="pcg_fd")
     ap.add_argument("--graphs", type=int, default=0,
                     help="replay each trial step from a captured HIP graph (1) or launch eagerly")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="time the candidate launch shapes first (ks_autotune) and keep the "
+                         "fastest")
     ap.add_argument("--cpu-iters", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-steps", type=int, default=3,
@@ -519,6 +522,9 @@ def main():
           f"warmup={args.warmup}", file=sys.stderr, flush=True)
     solver = ks.KS_HARTREE_CG if args.hartree == "cg" else ks.KS_HARTREE_PCG_FD
     sysg = ks.system_from_spec(spec, hartree_solver=solver)
+    tune = sysg.ks_autotune() if args.autotune else None
+    if tune is not None:
+        print(f"# autotune: {tune}", file=sys.stderr, flush=True)
     if args.graphs:
         sysg.ks_enable_graphs(True)
     X0 = torch.tensor(X0h, dtype=torch.float64, device="cuda")
@@ -594,7 +600,7 @@ def main():
     ms, cnt = live[dom]
     avg_s = ms * 1e-3 / cnt
     achieved = pb[dom] / avg_s / 1e9
-    kernel_names = {"hamiltonian": "k_hx<double,true,true>", "gram": "k_gram<double,2,3>",
+    kernel_names = {"hamiltonian": "k_hx_gram<double>", "gram": "k_gram<double,2,3>",
                     "gradient": "k_combine<double,2,false,true,false,true,true,false>",
                     "retract": "k_combine<double,2,true,false,true,false,false,true>"}
     traffic = pmc_traffic(kernel_names[dom]) if args.hartree == "pcg_fd" else None
@@ -653,7 +659,8 @@ def main():
                    "grid": [spec.nx, spec.ny, spec.nz], "h": spec.h, "p": spec.p,
                    "nuclei": spec.M, "eps_g": prm.eps_g, "retraction": args.retraction,
                    "hartree": args.hartree,
-                   "seed": args.seed},
+                   "seed": args.seed,
+                   "launch_shapes": tune},
         "p50_ms": pct(50), "p99_ms": pct(99),
         "converged": converged,
         "iterations": iters,

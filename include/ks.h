@@ -225,6 +225,24 @@ typedef struct ks_phase_times {
   long long count[KS_NPHASES];  /* occurrences                                           */
 } ks_phase_times;
 
+/* Launch shapes chosen by ks_autotune (KS_TUNE_AUTO: the built-in rule applies). */
+#define KS_TUNE_AUTO (-99)
+typedef struct ks_tune_info {
+  int fd_plane_mode;   /* plane-transform mode of the fast-diagonalisation Hartree solver:
+                          2 whole plane per block, 1 16-column strips with S_y staged,
+                          0 strips, -1 strips with S_x read from L2; KS_TUNE_AUTO if not
+                          tuned (no fast-diagonalisation solver)                          */
+  int hx_zrun;         /* z-planes per work item of the Hamiltonian with fused Gram tiles
+                          (8 or 16), KS_TUNE_AUTO if not tuned (that kernel is used at
+                          p = 32 on the 7-point grid only)                                */
+  int cached;          /* 1: the choice came from the process-wide cache                 */
+  int n_fd, n_hx;      /* candidates timed (0 when cached)                               */
+  int fd_modes[4];     /* candidate modes and their mean time per solve, microseconds    */
+  double fd_us[4];
+  int hx_zruns[2];     /* candidate runs and their mean time per launch, microseconds    */
+  double hx_us[2];
+} ks_tune_info;
+
 typedef struct ks_system ks_system;
 
 /* ---- sizing and lifecycle -------------------------------------------------------------- */
@@ -344,6 +362,19 @@ int ks_set_state(ks_system* s, const void* buf);
  * whether its trial was accepted.  Errors: KS_E_INVAL, KS_E_UNSUPPORTED (a run outside the
  * limits; nothing is launched), the first member error. */
 int ks_batch_step(ks_system* const* sys, int count, ks_iter_info* info);
+
+/* ---- launch-shape autotuning ------------------------------------------------------------
+ * Times the candidate launch shapes of two kernels of an evaluation on this system's own
+ * buffers (the fast-diagonalisation plane transforms of the Hartree solve, every mode whose
+ * LDS fits; the Hamiltonian with fused Gram tiles, 8 or 16 planes per work item) and keeps
+ * the fastest for the system.  Choices are cached per (grid, p, precision, discretisation,
+ * Hartree solver) for the process: a later system of the same key takes them without
+ * timing (force = 1 times again).  The shapes change how sums split over blocks, so results
+ * can differ from untuned runs in the last bits (a saved state resumes bit for bit only on
+ * a handle with the same shapes).  Overwrites the system's Hartree warm start and orbital
+ * scratch: call it before a run, not during one.  out (host, nullable) receives the choice
+ * and the timings.  Errors: KS_E_INVAL (a run in progress), KS_E_HIP. */
+int ks_autotune(ks_system* s, int force, ks_tune_info* out);
 
 /* ---- Alg. 4 with uniform refinement -------------------------------------------------
  * Alg. 4 solves the problem on a sequence of meshes, each level started from the solution

@@ -827,7 +827,7 @@ void launch_hx(const T* X, int ldx, T* Y, int ldy, const double* veff,
   if (gram_part) {
     hipLaunchKernelGGL((k_hx_gram<T>), dim3(hx_gram_blocks(g.n)), dim3(kBlock), 0, st,
                        HxArgs<T>{X, ldx, Y, ldy, veff, g, p, scale, *pt, gram_part,
-                                 hx_zrun(g.nx * g.ny, g.nz)});
+                                 hx_zrun_of(g)});
     return;
   }
   const int nb = hx_blocks(g.n, p);
@@ -858,6 +858,10 @@ bool hx_fuses_gram(int p) { return p == 32; }
 
 // Planes per work item of the Gram-fused Hamiltonian: 16, or 8 when runs of 16 would leave
 // wavefronts of its hx_gram_blocks(n) blocks without an item.
+int hx_zrun_of(const Grid& g) {
+  return (g.hx_zrun == 8 || g.hx_zrun == 16) ? g.hx_zrun : hx_zrun(g.nx * g.ny, g.nz);
+}
+
 int hx_zrun(int nxy, int nz) {
   const int groups = (nxy + 3) / 4;
   const int waves = hx_gram_blocks(nxy * nz) * (kBlock / kWave);

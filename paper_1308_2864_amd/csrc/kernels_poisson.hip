@@ -761,6 +761,18 @@ size_t fd_plane_bytes(int nx, int ny, int mode) {
   return mode == kPlaneStripSy ? strip + (size_t)ny * ny * sizeof(double) : strip;
 }
 
+bool fd_plane_mode_fits(int nx, int ny, int mode) {
+  return (mode == kPlaneFull || mode == kPlaneStripSy || mode == kPlaneStrip ||
+          mode == kPlaneStripG) &&
+         fd_plane_bytes(nx, ny, mode) <= kFdLdsCap;
+}
+
+int fd_plane_mode_of(const Grid& g) {
+  return g.fd_mode != kTuneAuto && fd_plane_mode_fits(g.nx, g.ny, g.fd_mode)
+             ? g.fd_mode
+             : fd_plane_mode(g.nx, g.ny);
+}
+
 int fd_plane_mode(int nx, int ny) {
   if (fd_plane_bytes(nx, ny, kPlaneFull) <= kFdLdsCap) return kPlaneFull;
   if (fd_plane_bytes(nx, ny, kPlaneStripSy) <= kFdLdsCap) return kPlaneStripSy;
@@ -821,7 +833,7 @@ void fd_passes(const double* in, double* out, const double* add, double* tmp,
   const size_t lzs = lzb + (size_t)nz * nz * sizeof(double);
   const size_t cap = kFdLdsCap;
   const int threads = kFdWaves * kWave;
-  const int mode = fd_plane_mode(nx, ny);
+  const int mode = fd_plane_mode_of(g);
   auto plane = [&](const double* src, double* dst, const double* ad, const double* r,
                    double* pt) {
     launch_fd_plane(FdPlaneArgs{src, dst, fd.Sx, fd.Sy, nx, ny, r, pt, cs, ad}, nz, mode, st);
@@ -844,7 +856,7 @@ void fd_passes(const double* in, double* out, const double* add, double* tmp,
 void launch_fd_apply(const double* r, double* z, double* tmp, const FdOps& fd, Grid g,
                      const CgState* cs, double* part, hipStream_t st) {
   fd_passes(r, z, nullptr, tmp, fd, g, cs, r, part, st);
-  const int nb = fd_plane_blocks(g.nx, g.nz, fd_plane_mode(g.nx, g.ny));
+  const int nb = fd_plane_blocks(g.nx, g.nz, fd_plane_mode_of(g));
   hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kBlock), 0, st,
                      FinRzArgs{part, nb, const_cast<CgState*>(cs)});
 }
@@ -877,10 +889,11 @@ void launch_hartree_iter(double* x, double* r, const double* z, double* pa, doub
 
 int hartree_blocks(int n) { return cg_nblocks(n); }
 
-FdLaunch fd_launch(int nx, int ny, int nz) {
+FdLaunch fd_launch(const Grid& g) {
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
   const size_t nzp = (nz + 15) & ~15;
   FdLaunch l;
-  l.plane_mode = fd_plane_mode(nx, ny);
+  l.plane_mode = fd_plane_mode_of(g);
   l.z_bytes = nzp * kZCols * sizeof(double);
   l.z_bytes_staged = l.z_bytes + (size_t)nz * nz * sizeof(double);
   l.cap = kFdLdsCap;

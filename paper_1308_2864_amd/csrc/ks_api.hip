@@ -6,7 +6,10 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "ks_common.h"
@@ -1268,7 +1271,7 @@ void fill_typed(ks_system* s, std::vector<char>& buf, int c) {
   put_rec(buf, c, R_HX, HxArgs<T>{static_cast<const T*>(s->X[t]), s->p,
                                   static_cast<T*>(s->G[t]), s->p, s->veff[t], s->grid,
                                   s->p, 2.0 * s->f, pt, hxg ? s->gram_part : nullptr,
-                                  hx_zrun(s->grid.nx * s->grid.ny, s->grid.nz)});
+                                  hx_zrun_of(s->grid)});
   put_rec(buf, c, R_GRAM1, GramArgs<T>{static_cast<const T*>(s->X[t]),
                                        static_cast<const T*>(s->G[t]), s->p, s->n, s->p,
                                        s->gram_part});
@@ -1382,19 +1385,19 @@ void launch_trial_batch(const std::vector<BatchMember*>& g, hipStream_t st) {
   int mode = kPlaneFull;
   bool stage_z = true;
   for (auto* m : g) {
-    const FdLaunch l = fd_launch(m->s->grid.nx, m->s->grid.ny, m->s->grid.nz);
+    const FdLaunch l = fd_launch(m->s->grid);
     mode = std::min(mode, l.plane_mode);
     stage_z = stage_z && l.z_bytes_staged <= l.cap;
   }
   size_t lds_p = 0, lds_z = 0;
   for (auto* m : g) {
-    const FdLaunch l = fd_launch(m->s->grid.nx, m->s->grid.ny, m->s->grid.nz);
+    const FdLaunch l = fd_launch(m->s->grid);
     lds_p = std::max(lds_p, fd_plane_bytes(m->s->grid.nx, m->s->grid.ny, mode));
     lds_z = std::max(lds_z, stage_z ? l.z_bytes_staged : l.z_bytes);
   }
   auto pb = [mode](const ks_system* s) { return fd_plane_blocks(s->grid.nx, s->grid.nz, mode); };
   auto zb = [](const ks_system* s) {
-    return fd_launch(s->grid.nx, s->grid.ny, s->grid.nz).z_blocks;
+    return fd_launch(s->grid).z_blocks;
   };
   auto r0 = table<InitArgs>(g, R_RESID, hb, &tot);
   launch_init_batch(r0, tot, st);
@@ -1958,6 +1961,121 @@ int ks_minimize(ks_system* s, void* X_inout, const ks_opt_params* o, ks_result* 
     }
   }
   return run_end(s, m, r);
+}
+
+extern "C++" {
+namespace {
+using TuneKey = std::tuple<int, int, int, int, int, int, int>;
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tune;  // (fd_mode, hx_zrun)
+
+// Mean device time of fn() over reps launches on the system's stream, after two warm-ups.
+template <typename F>
+int time_us(ks_system* s, int reps, F fn, double* us) {
+  fn();
+  fn();
+  hipEvent_t a, b;
+  int rc = hip_check(s, hipEventCreate(&a), "tune event");
+  if (rc) return rc;
+  rc = hip_check(s, hipEventCreate(&b), "tune event");
+  if (rc) {
+    (void)hipEventDestroy(a);
+    return rc;
+  }
+  (void)hipEventRecord(a, s->st);
+  for (int i = 0; i < reps; ++i) fn();
+  (void)hipEventRecord(b, s->st);
+  rc = hip_check(s, hipEventSynchronize(b), "tune timing");
+  float ms = 0.0f;
+  if (!rc) rc = hip_check(s, hipEventElapsedTime(&ms, a, b), "tune timing");
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (!rc) rc = launch_check(s, "tune launches");
+  *us = 1e3 * (double)ms / reps;
+  return rc;
+}
+}  // namespace
+}  // extern "C++"
+
+int ks_autotune(ks_system* s, int force, ks_tune_info* out) {
+  if (!s) return fail(s, KS_E_INVAL, "null system");
+  if (s->run.active) return fail(s, KS_E_INVAL, "a run is in progress");
+  ks_tune_info info{};
+  info.fd_plane_mode = info.hx_zrun = KS_TUNE_AUTO;
+  const bool tune_fd = s->use_h && s->solver == KS_HARTREE_PCG_FD;
+  const bool tune_hx = !s->q1 && hx_fuses_gram(s->p);
+  const TuneKey key{s->grid.nx, s->grid.ny, s->grid.nz, s->p, s->f32 ? 1 : 0, s->q1 ? 1 : 0,
+                    s->solver};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end() && !force) {
+      s->grid.fd_mode = it->second.first;
+      s->grid.hx_zrun = it->second.second;
+      info.fd_plane_mode = tune_fd ? fd_plane_mode_of(s->grid) : KS_TUNE_AUTO;
+      info.hx_zrun = tune_hx ? hx_zrun_of(s->grid) : KS_TUNE_AUTO;
+      info.cached = 1;
+      if (out) *out = info;
+      return KS_OK;
+    }
+  }
+  const size_t nb = (size_t)s->n * sizeof(double);
+  const int reps = 10;
+  int rc = KS_OK;
+  if (tune_fd) {
+    for (double* v : {s->cg_r, s->cg_q, s->vh[0], s->vh[1]})
+      if (!rc) rc = hip_check(s, hipMemsetAsync(v, 0, nb, s->st), "tune clear");
+    double best = 0.0;
+    int best_mode = KS_TUNE_AUTO;
+    for (int mode : {kPlaneFull, kPlaneStripSy, kPlaneStrip, kPlaneStripG}) {
+      if (rc || !fd_plane_mode_fits(s->grid.nx, s->grid.ny, mode)) continue;
+      s->grid.fd_mode = mode;
+      double us = 0.0;
+      rc = time_us(s, reps, [&] {
+        launch_fd_correct(s->cg_r, s->vh[0], s->vh[1], s->cg_q, fd_ops(s), s->grid, s->st);
+      }, &us);
+      info.fd_modes[info.n_fd] = mode;
+      info.fd_us[info.n_fd++] = us;
+      if (best_mode == KS_TUNE_AUTO || us < best) {
+        best = us;
+        best_mode = mode;
+      }
+    }
+    s->grid.fd_mode = best_mode;
+    info.fd_plane_mode = best_mode;
+  }
+  if (tune_hx && !rc) {
+    const size_t xb = (size_t)s->n * s->p * s->es;
+    rc = hip_check(s, hipMemsetAsync(s->X[0], 0, xb, s->st), "tune clear");
+    if (!rc) rc = hip_check(s, hipMemsetAsync(s->veff[0], 0, nb, s->st), "tune clear");
+    Partials pt{s->spart, kPartStride};
+    double best = 0.0;
+    int best_z = KS_TUNE_AUTO;
+    for (int z : {16, 8}) {
+      if (rc) break;
+      s->grid.hx_zrun = z;
+      double us = 0.0;
+      rc = time_us(s, reps, [&] {
+        hamiltonian(s, s->X[0], s->p, s->G[0], s->p, s->veff[0], 1.0, &pt, s->gram_part);
+      }, &us);
+      info.hx_zruns[info.n_hx] = z;
+      info.hx_us[info.n_hx++] = us;
+      if (best_z == KS_TUNE_AUTO || us < best) {
+        best = us;
+        best_z = z;
+      }
+    }
+    s->grid.hx_zrun = best_z;
+    info.hx_zrun = best_z;
+  }
+  if (rc) return rc;
+  drop_graphs(s);  // captured launches carry the old shapes
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = {s->grid.fd_mode, s->grid.hx_zrun};
+  }
+  if (out) *out = info;
+  return KS_OK;
 }
 
 int ks_prolong(ks_system* coarse, const void* Xc, ks_system* fine, void* Xf) {

@@ -106,6 +106,8 @@ static_assert(sizeof(CgState) <= 256 && sizeof(LsState) <= 256 && sizeof(EvalOut
               "scalar records must fit their 256-byte slots");
 
 // Constants of the discretisation, passed by value to kernels.
+constexpr int kTuneAuto = -99;
+
 struct Grid {
   int nx, ny, nz;
   int n;
@@ -114,6 +116,9 @@ struct Grid {
   int q1;            // 0: 7-point finite differences; 1: trilinear finite elements
   double rhs_scale;  // Poisson right-hand side 4 pi * rhs_scale * rho (FE: h^3)
   double mu;         // weight of the kinetic (von Weizsaecker) term: H = mu/2 L + V_eff
+  // launch shapes chosen by ks_autotune (kTuneAuto: the built-in rule)
+  int fd_mode = kTuneAuto;  // plane-transform mode of the fast diagonalisation (kPlane*)
+  int hx_zrun = kTuneAuto;  // planes per work item of the Gram-fused Hamiltonian (8, 16)
 };
 
 __host__ __device__ inline int round_up(int a, int b) { return (a + b - 1) / b * b; }
@@ -267,6 +272,7 @@ int hx_blocks(int n, int p);  // blocks (and energy partials) of launch_hx
 int hx_gram_blocks(int n);
 bool hx_fuses_gram(int p);
 int hx_zrun(int nxy, int nz);  // planes per work item of the Gram-fused launch
+int hx_zrun_of(const Grid& g);  // the grid's tuned value, else hx_zrun
 void launch_xc_batch(const BatchPtrs<XcArgs>& b, int blocks, hipStream_t st);
 template <typename T>
 void launch_hx_batch(const BatchPtrs<HxArgs<T>>& b, int blocks, bool gram, hipStream_t st);
@@ -375,6 +381,8 @@ int hartree_blocks(int n);
 enum { kPlaneStripG = -1, kPlaneStrip = 0, kPlaneStripSy = 1, kPlaneFull = 2 };
 size_t fd_plane_bytes(int nx, int ny, int mode);
 int fd_plane_mode(int nx, int ny);  // the fastest mode whose LDS fits
+int fd_plane_mode_of(const Grid& g);  // the grid's tuned mode, else fd_plane_mode
+bool fd_plane_mode_fits(int nx, int ny, int mode);
 int fd_plane_blocks(int nx, int nz, int mode);
 bool fd_fits(int nx, int ny, int nz);  // the transforms' LDS fits for this grid
 struct FdLaunch {
@@ -382,7 +390,7 @@ struct FdLaunch {
   size_t z_bytes, z_bytes_staged, cap;
   int z_blocks;
 };
-FdLaunch fd_launch(int nx, int ny, int nz);
+FdLaunch fd_launch(const Grid& g);
 void launch_init_batch(const BatchPtrs<InitArgs>& b, int blocks, hipStream_t st);
 void launch_fin_init_batch(const BatchPtrs<FinInitArgs>& b, hipStream_t st);
 void launch_dir_batch(const BatchPtrs<DirArgs>& b, int blocks, hipStream_t st);

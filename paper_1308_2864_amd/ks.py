@@ -111,6 +111,23 @@ class ks_phase_times(C.Structure):
         return {name: (self.ms[i], self.count[i]) for i, name in enumerate(PHASES)}
 
 
+KS_TUNE_AUTO = -99
+
+
+class ks_tune_info(C.Structure):
+    _fields_ = [("fd_plane_mode", C.c_int), ("hx_zrun", C.c_int), ("cached", C.c_int),
+                ("n_fd", C.c_int), ("n_hx", C.c_int), ("fd_modes", C.c_int * 4),
+                ("fd_us", C.c_double * 4), ("hx_zruns", C.c_int * 2), ("hx_us", C.c_double * 2)]
+
+    def as_dict(self):
+        return {"fd_plane_mode": self.fd_plane_mode, "hx_zrun": self.hx_zrun,
+                "cached": bool(self.cached),
+                "fd_candidates_us": {int(self.fd_modes[i]): round(self.fd_us[i], 2)
+                                     for i in range(self.n_fd)},
+                "hx_candidates_us": {int(self.hx_zruns[i]): round(self.hx_us[i], 2)
+                                     for i in range(self.n_hx)}}
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
@@ -145,6 +162,7 @@ def _load():
         "ks_set_state": (ip, [vp, vp]),
         "ks_batch_step": (ip, [C.POINTER(vp), ip, C.POINTER(ks_iter_info)]),
         "ks_prolong": (ip, [vp, vp, vp, vp]),
+        "ks_autotune": (ip, [vp, ip, C.POINTER(ks_tune_info)]),
         "ks_minimize_levels": (ip, [C.POINTER(vp), ip, C.POINTER(vp), C.POINTER(ks_opt_params),
                                     C.POINTER(ks_result)]),
         "ks_timer_phases": (ip, [vp, C.c_uint]),
@@ -312,6 +330,13 @@ class KSSystem:
 
     def ks_set_state(self, buf):
         _check(lib.ks_set_state(self.h, C.c_void_p(_addr(buf))), self.h)
+
+    def ks_autotune(self, force=False) -> dict:
+        """Times the candidate launch shapes on this system and keeps the fastest (see
+        include/ks.h); returns the choice and the timings."""
+        t = ks_tune_info()
+        _check(lib.ks_autotune(self.h, int(bool(force)), C.byref(t)), self.h)
+        return t.as_dict()
 
     def ks_density(self, X, rho):
         _check(lib.ks_density(self.h, _ptr(X), _ptr(rho)), self.h)

@@ -1,0 +1,79 @@
+"""ks_autotune: the launch shapes it times are valid candidates, the fastest one is kept
+and cached per (grid, p, precision, discretisation, solver), a tuned solve reaches the
+untuned solve's minimum (the shapes change only how sums split over blocks), and lockstep
+batches of tuned systems still equal their lone runs bit for bit."""
+import numpy as np
+import pytest
+
+from paper_1308_2864_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def ks():
+    from paper_1308_2864_amd import ks as _ks
+    return _ks
+
+
+def _spec(N=24, p=32, M=4, seed=2):
+    return synth.make_system(N, N, N, 16.0 / (N + 1), p, M, seed=seed, cfg="c5",
+                             lo=(-8.0,) * 3, margin=3.0, zrange=(1, 4))
+
+
+def test_autotune_choices_cache_and_results():
+    K = ks()
+    spec = _spec()
+    a = K.system_from_spec(spec, hartree_solver=K.KS_HARTREE_PCG_FD)
+    info = a.ks_autotune(force=True)
+    print("autotune:", info, flush=True)
+    assert not info["cached"]
+    assert info["fd_plane_mode"] in info["fd_candidates_us"]
+    assert info["fd_candidates_us"][info["fd_plane_mode"]] == min(info["fd_candidates_us"].values())
+    assert set(info["hx_candidates_us"]) == {8, 16}
+    assert info["hx_zrun"] in (8, 16)
+    assert info["hx_candidates_us"][info["hx_zrun"]] == min(info["hx_candidates_us"].values())
+    # a second system of the same key takes the cached choice without timing
+    b = K.system_from_spec(spec, hartree_solver=K.KS_HARTREE_PCG_FD)
+    ib = b.ks_autotune()
+    assert ib["cached"] and ib["fd_plane_mode"] == info["fd_plane_mode"]
+    assert ib["hx_zrun"] == info["hx_zrun"]
+    # tuned and untuned solves reach the same minimum
+    c = K.system_from_spec(spec, hartree_solver=K.KS_HARTREE_PCG_FD)
+    prm = K.ks_default_params(eps_g=1e-7, stagnation_tol=0.0, max_iter=4000)
+    X0 = torch.tensor(synth.make_x0(spec, 1), dtype=torch.float64, device="cuda")
+    ra = a.ks_minimize(X0.clone(), prm, check=False)
+    rc = c.ks_minimize(X0.clone(), prm, check=False)
+    print(f"tuned E={ra.energy:.13f} ({ra.iters} it), default E={rc.energy:.13f} "
+          f"({rc.iters} it)", flush=True)
+    assert ra.stop_reason == K.KS_STOP_GRAD and rc.stop_reason == K.KS_STOP_GRAD
+    assert abs(ra.energy - rc.energy) <= 1e-10 * abs(rc.energy)
+    # a run in progress refuses tuning
+    a.ks_minimize_begin(X0)
+    with pytest.raises(K.KSError) as ei:
+        a.ks_autotune()
+    assert ei.value.code == K.KS_E_INVAL
+    for s in (a, b, c):
+        s.close()
+
+
+def test_tuned_batch_equals_tuned_lone_runs_bitwise():
+    K = ks()
+    prm = K.ks_default_params(max_iter=200)
+    specs = [_spec(20, 32, 3, 5), _spec(24, 12, 4, 6), _spec(18, 32, 2, 7)]
+    lone, systems, blocks = [], [], []
+    for sp in specs:
+        s = K.system_from_spec(sp, hartree_solver=K.KS_HARTREE_PCG_FD)
+        s.ks_autotune(force=True)
+        X0 = torch.tensor(synth.make_x0(sp, 1), dtype=torch.float64, device="cuda")
+        X = X0.clone()
+        lone.append((s.ks_minimize(X, prm, check=False), X.cpu().numpy()))
+        systems.append(s)
+        blocks.append(X0.clone())
+    res, codes = K.ks_minimize_batch(systems, blocks, prm)
+    for i, s in enumerate(systems):
+        r, Xr = lone[i]
+        assert (res[i].iters, res[i].nfe, res[i].energy) == (r.iters, r.nfe, r.energy), i
+        assert np.array_equal(blocks[i].cpu().numpy(), Xr), i
+        s.close()
