@@ -98,3 +98,28 @@ def test_bf16_retraction_keeps_orthonormality():
         s.close()
         assert r.terms.orth_error < 2e-6, (mode, r.terms.orth_error)
     assert abs(out["bf16"].energy - out["fp32"].energy) < 1e-3 * abs(out["fp32"].energy)
+
+
+def test_q1_bf16_keeps_b_orthonormality():
+    """Q1 elements (the B metric) at p = 80: the bf16 X^T G of KS_PREC_MIXED_BF16 moves only
+    the direction; every retraction's factor comes from the stored blocks, so X^T B X = I
+    holds to float level after a few steps, and the energies track FP32 storage."""
+    from oracle.fe import q1_matrices
+    K = ks()
+    spec = synth.make_system(18, 16, 14, 0.5, 80, 4, seed=9, zrange=(1, 3), margin=1.5,
+                             min_spacing=1.0).copy(disc="q1")
+    B = q1_matrices(spec.nx, spec.ny, spec.nz, spec.h)[1]
+    X0 = torch.tensor(synth.make_x0(spec, 1), dtype=torch.float32, device="cuda")
+    out = {}
+    for mode, prec in (("fp32", K.KS_PREC_FP32), ("bf16", K.KS_PREC_MIXED_BF16)):
+        s = K.system_from_spec(spec, hartree_solver=K.KS_HARTREE_PCG_FD, precision=prec)
+        X = X0.clone()
+        r = s.ks_minimize(X, K.ks_default_params(max_iter=8), check=False)
+        s.close()
+        Xh = X.double().cpu().numpy()
+        orth = np.linalg.norm(Xh.T @ (B @ Xh) - np.eye(spec.p))
+        print(f"q1 {mode}: E={r.energy:.8f} ({r.iters} it) ||X^T B X - I|| = {orth:.2e}",
+              flush=True)
+        assert r.iters == 8 and orth < 1e-5, (mode, orth)
+        out[mode] = r
+    assert abs(out["bf16"].energy - out["fp32"].energy) < 1e-3 * abs(out["fp32"].energy)
