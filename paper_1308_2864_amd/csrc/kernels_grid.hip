@@ -196,8 +196,18 @@ __device__ inline void k_xc_body(const XcArgs& ka, int ks_bid, int ks_nb) {
   // (3/4)(3/pi)^{1/3} and (3/pi)^{1/3}
   const double cv = cbrt(3.0 / kPi), cx = 0.75 * cv;
   const bool trivial = use_h && cg != nullptr && cg->bb == 0.0;  // rho == 0: V_H = 0
-  double eh = 0.0, ex = 0.0, ee = 0.0, et = 0.0;
+  double eh = 0.0, ex = 0.0, ee = 0.0, et = 0.0, rr = 0.0, bb = 0.0;
+  const bool cg_check = ka.cg_check != 0;
   for (size_t g = beg + threadIdx.x; g < end; g += blockDim.x) {
+    if (cg_check) {
+      // the residual test of the Hartree solve, as the CG start forms it
+      const int gi = (int)g;
+      const int i = gi % gr.nx, j = (gi / gr.nx) % gr.ny, k = gi / (gr.nx * gr.ny);
+      const double b = poisson_rhs(rho, gi, gr);
+      const double ri = b - op_apply(vh, nullptr, 0.0, gi, i, j, k, gr);
+      rr += ri * ri;
+      bb += b * b;
+    }
     const double r = rho[g];
     const double ve = vext[g];
     const double h = (use_h && !trivial) ? vh[g] : 0.0;
@@ -231,6 +241,12 @@ __device__ inline void k_xc_body(const XcArgs& ka, int ks_bid, int ks_nb) {
   write_partial(pt, SL_EX, lb, ex);
   write_partial(pt, SL_EXT, lb, ee);
   write_partial(pt, SL_TF, lb, et);
+  if (cg_check) {
+    rr = block_sum(rr, sh);
+    bb = block_sum(bb, sh);
+    write_partial(pt, SL_CGRR, lb, rr);
+    write_partial(pt, SL_CGBB, lb, bb);
+  }
 }
 
 __global__ void k_xc(XcArgs ka) {
@@ -816,9 +832,10 @@ template void launch_density<float>(const float*, int, int, int, double, double*
 int scalar_blocks(int n) { return stream_blocks((size_t)n); }
 
 void launch_xc(const double* rho, const double* vh, const double* vext, double* veff, Grid g,
-               int use_h, int use_x, const CgState* cg, Partials pt, hipStream_t st) {
+               int use_h, int use_x, const CgState* cg, Partials pt, hipStream_t st,
+               bool cg_check) {
   hipLaunchKernelGGL(k_xc, dim3(scalar_blocks(g.n)), dim3(kBlock), 0, st,
-                     XcArgs{rho, vh, vext, veff, g, use_h, use_x, cg, pt});
+                     XcArgs{rho, vh, vext, veff, g, use_h, use_x, cg, pt, cg_check ? 1 : 0});
 }
 
 template <typename T>

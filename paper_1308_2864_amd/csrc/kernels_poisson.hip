@@ -44,41 +44,6 @@ __device__ inline void range_of(int n, int lb, int nb, int* beg, int* end) {
   *end = (int)(e < n ? e : n);
 }
 
-// (Op u)_g for u = z + beta po (po may be null): the 7-point -Laplacian_h, or for finite
-// elements the Q1 stiffness stencil (centre 8h/3, edges -h/6, corners -h/12, faces 0).
-__device__ inline double op_apply(const double* __restrict__ z, const double* __restrict__ po,
-                                  double beta, int g, int i, int j, int k, const Grid& gr) {
-  const int sy = gr.nx, sz = gr.nx * gr.ny;
-  auto u = [&](int o) { return po ? z[g + o] + beta * po[g + o] : z[g + o]; };
-  if (!gr.q1) {
-    double nb = 0.0;
-    if (i > 0) nb += u(-1);
-    if (i < gr.nx - 1) nb += u(1);
-    if (j > 0) nb += u(-sy);
-    if (j < gr.ny - 1) nb += u(sy);
-    if (k > 0) nb += u(-sz);
-    if (k < gr.nz - 1) nb += u(sz);
-    return (6.0 * u(0) - nb) * gr.inv_h2;
-  }
-  double s[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int dz = -1; dz <= 1; ++dz) {
-    if (k + dz < 0 || k + dz >= gr.nz) continue;
-#pragma unroll
-    for (int dy = -1; dy <= 1; ++dy) {
-      if (j + dy < 0 || j + dy >= gr.ny) continue;
-#pragma unroll
-      for (int dx = -1; dx <= 1; ++dx) {
-        if (i + dx < 0 || i + dx >= gr.nx) continue;
-        const int cls = (dx != 0) + (dy != 0) + (dz != 0);
-        if (cls == 1) continue;
-        s[cls] += u(dz * sz + dy * sy + dx);
-      }
-    }
-  }
-  return (8.0 * gr.h / 3.0) * s[0] - (gr.h / 6.0) * s[2] - (gr.h / 12.0) * s[3];
-}
-
 // part layout: [4][kCgBlocksMax]
 __device__ inline void put2(double* part, int lb, double a, double b, double* sh, int sa,
                             int sb) {
@@ -115,7 +80,7 @@ __device__ inline void k_init_body(const InitArgs& ka, int ks_bid, int ks_nb) {
   double rr = 0.0, bb = 0.0;
   for (int g = beg + threadIdx.x; g < end; g += blockDim.x) {
     const int i = g % gr.nx, j = (g / gr.nx) % gr.ny, k = g / (gr.nx * gr.ny);
-    const double b = 4.0 * kPi * gr.rhs_scale * rho[g];
+    const double b = poisson_rhs(rho, g, gr);
     const double ri = x0 ? b - op_apply(x0, nullptr, 0.0, g, i, j, k, gr) : b;
     if (x) x[g] = x0 ? x0[g] : 0.0;
     r[g] = ri;
@@ -134,6 +99,7 @@ __global__ void k_init_batch(BatchPtrs<InitArgs> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
   k_init_body(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
 }
+
 
 
 __device__ inline void k_fin_init_body(const FinInitArgs& ka, int ks_bid, int ks_nb) {
@@ -166,10 +132,6 @@ __global__ void k_fin_init(FinInitArgs ka) {
   k_fin_init_body(ka, blockIdx.x, gridDim.x);
 }
 
-__global__ void k_fin_init_batch(BatchPtrs<FinInitArgs> b) {
-  const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_fin_init_body(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
-}
 
 
 // pn = z + beta po ; q = L pn ; partial pn.q (slot 2).  z = r for plain CG.
@@ -399,7 +361,6 @@ constexpr int kPlaneWaves = 4;
 
 template <bool kStageSy, bool kStageSx>
 __device__ inline void k_fd_plane_body(const FdPlaneArgs& ka, int ks_bid, int ks_nb) {
-  const double* __restrict__ in = ka.in;
   double* __restrict__ out = ka.out;
   const double* __restrict__ Sx = ka.Sxg;
   const double* __restrict__ Sy = ka.Syg;
@@ -422,7 +383,7 @@ __device__ inline void k_fd_plane_body(const FdPlaneArgs& ka, int ks_bid, int ks
       [&](int e) {
         const int j = e / nxp, m = e % nxp;
         const bool ok = j < ny && m < nx;
-        const double v = in[ok ? base + (size_t)j * nx + m : base];
+        const double v = ka.in[ok ? base + (size_t)j * nx + m : base];
         return ok ? v : 0.0;
       },
       [&](int e, double v) { P[(e / nxp) * sp + e % nxp] = v; });
@@ -506,7 +467,6 @@ __global__ __launch_bounds__(256) void k_fd_plane_batch(BatchPtrs<FdPlaneArgs> b
 constexpr int kFullWaves = 16;
 
 __device__ inline void k_fd_plane_full_body(const FdPlaneArgs& ka, int ks_bid, int ks_nb) {
-  const double* __restrict__ in = ka.in;
   double* __restrict__ out = ka.out;
   const double* __restrict__ Sx = ka.Sxg;
   const double* __restrict__ Sy = ka.Syg;
@@ -530,7 +490,7 @@ __device__ inline void k_fd_plane_full_body(const FdPlaneArgs& ka, int ks_bid, i
       [&](int e) {
         const int j = e / nxp, m = e % nxp;
         const bool ok = j < ny && m < nx;
-        const double v = in[ok ? base + (size_t)j * nx + m : base];
+        const double v = ka.in[ok ? base + (size_t)j * nx + m : base];
         return ok ? v : 0.0;
       },
       [&](int e, double v) { P[(e / nxp) * sp + e % nxp] = v; });
@@ -887,6 +847,10 @@ void launch_hartree_iter(double* x, double* r, const double* z, double* pa, doub
 
 // ---- batched launches (one launch for the systems of a BatchPtrs table) ---------------
 
+void launch_init_batch(const BatchPtrs<InitArgs>& b, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_batch, dim3(blocks), dim3(kBlock), 0, st, b);
+}
+
 int hartree_blocks(int n) { return cg_nblocks(n); }
 
 FdLaunch fd_launch(const Grid& g) {
@@ -901,12 +865,6 @@ FdLaunch fd_launch(const Grid& g) {
   return l;
 }
 
-void launch_init_batch(const BatchPtrs<InitArgs>& b, int blocks, hipStream_t st) {
-  hipLaunchKernelGGL(k_init_batch, dim3(blocks), dim3(kBlock), 0, st, b);
-}
-void launch_fin_init_batch(const BatchPtrs<FinInitArgs>& b, hipStream_t st) {
-  hipLaunchKernelGGL(k_fin_init_batch, dim3(b.S), dim3(kBlock), 0, st, b);
-}
 void launch_dir_batch(const BatchPtrs<DirArgs>& b, int blocks, hipStream_t st) {
   hipLaunchKernelGGL(k_dir_batch, dim3(blocks), dim3(kBlock), 0, st, b);
 }

@@ -802,6 +802,23 @@ __device__ inline void k_finish_eval_body(const FinishEvalArgs& ka, int ks_bid, 
   if (threadIdx.x != 0) return;
   acc = orth;
   for (int sl = 0; sl < SL_COUNT; ++sl) sums[sl] = red[sl];
+  if (ka.cgw) {
+    // the CG start of the Hartree solve whose residual the exchange pass measured (the
+    // exact step counts as iteration 1)
+    CgState* cs = ka.cgw;
+    const double rr = red[SL_CGRR], bb = red[SL_CGBB];
+    const double tol = ka.htol;
+    cs->rr = rr;
+    cs->bb = bb;
+    cs->tol2 = tol * tol;
+    cs->alpha = cs->beta = cs->pq = 0.0;
+    cs->rz = 0.0;
+    cs->rr_best = rr;
+    cs->stall = 0;
+    cs->it = bb == 0.0 ? 0 : 1;
+    cs->maxit = ka.hmaxit;
+    cs->done = (bb == 0.0 || !isfinite(rr) || !isfinite(bb) || rr <= tol * tol * bb) ? 1 : 0;
+  }
   EvalOut o;
   // the kinetic partial carries the weight mu; the Thomas-Fermi term is kinetic energy
   o.kinetic = 0.5 * f * red[SL_KIN] + dV * red[SL_TF];
@@ -1181,12 +1198,13 @@ void launch_wy_factor(const double* gram_xg, int p, int pp, const double* tau,
 void launch_finish_eval(const double* part, int stride, const int* nblk, double* sums,
                         const double* gram_xx, int p, int pp, double f, double dV,
                         const double* enuc, const CgState* cg, EvalOut* out, LsState* ls,
-                        const LsParams* prm, hipStream_t st) {
+                        const LsParams* prm, hipStream_t st, CgState* cgw, double htol,
+                        int hmaxit) {
   ScalarCounts nb{};
   for (int i = 0; i < SL_COUNT; ++i) nb.v[i] = nblk[i];
   hipLaunchKernelGGL(k_finish_eval, dim3(1), dim3(kFinishThreads), 0, st,
                      FinishEvalArgs{part, stride, nb, sums, gram_xx, p, pp, f, dV, enuc, cg, out,
-                         ls, prm ? *prm : LsParams{}});
+                         ls, prm ? *prm : LsParams{}, cgw, htol, hmaxit});
 }
 
 void launch_set_scalar(double* dst, double v, hipStream_t st) {

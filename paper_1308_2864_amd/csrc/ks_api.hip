@@ -49,7 +49,7 @@ namespace {
 constexpr int kPartStride = 4096;  // >= blocks of every streaming kernel
 // argument records of the batched trial kernels: one 256-byte slot per kernel and parity
 enum Rec {
-  R_QR, R_RETRACT, R_RESID, R_PLANE1, R_FDZ, R_PLANE2, R_INIT, R_FIN_INIT, R_XC, R_HX, R_GRAM1,
+  R_QR, R_RETRACT, R_RESID, R_PLANE1, R_FDZ, R_PLANE2, R_XC, R_HX, R_GRAM1,
   R_RED1, R_GRAD, R_RED2, R_FINISH, R_QR_NEXT, R_COUNT
 };
 constexpr size_t kRecSlot = 256;
@@ -128,6 +128,8 @@ struct ks_system {
   std::string err;
   int last_cg_iters = 0;
   int pcg_extra = 0;     // PCG iterations queued after the exact step of a trial's solve
+  bool fuse_cg = false;  // the next exchange pass measures the Hartree residual (see hartree)
+  bool cg_fused = false;  // the last evaluation measured it there (its r was not stored)
   bool pcg_probe = false;  // the first trial of a run queues one to see whether it is needed
   long long cg_total = 0;
   // optional phase timers
@@ -610,7 +612,7 @@ int hartree_iterate(ks_system* s, double* x, int first_chunk, bool wait, int* it
 }
 
 int hartree(ks_system* s, const double* rho, const double* x0, double* x, bool wait,
-            int* iters, double* relres) {
+            int* iters, double* relres, bool fuse = false) {
   tbeg(s, KS_PH_HARTREE);
   s->cg_par = 0;
   if (s->solver == KS_HARTREE_PCG_FD) {
@@ -620,6 +622,14 @@ int hartree(ks_system* s, const double* rho, const double* x0, double* x, bool w
     // PCG iterations (for a queued trial the caller does that: hartree_pending).
     launch_cg_residual(rho, x0, s->cg_r, s->cg_p[0], s->grid, s->cgpart, s->st);
     launch_fd_correct(s->cg_r, x0, x, s->cg_q, fd_ops(s), s->grid, s->st);
+    if (fuse && s->pcg_extra == 0) {
+      // a trial that queues no continuation: its exchange pass measures the residual and
+      // the evaluation summary writes the CG start (one pass and one launch fewer)
+      s->fuse_cg = true;
+      tmark(s, KS_PH_HARTREE);
+      tcommit(s, KS_PH_HARTREE);
+      return launch_check(s, "hartree");
+    }
     launch_hartree_init(rho, x, nullptr, s->cg_r, s->cg_p[0], s->cg, s->htol, s->hmaxit, 1,
                         s->grid, s->cgpart, s->st);
     // pcg_extra: a run whose exact steps miss the tolerance (large grids: eps cond(L) above
@@ -657,7 +667,8 @@ int evaluate(ks_system* s, int idx, bool rho_ready, int bb_ref, int warm, bool w
   int rc = launch_check(s, "density");
   if (rc) return rc;
   if (s->use_h) {
-    rc = hartree(s, s->rho, s->vh[warm], s->vh[idx], wait_hartree, nullptr, nullptr);
+    rc = hartree(s, s->rho, s->vh[warm], s->vh[idx], wait_hartree, nullptr, nullptr,
+                 judge != nullptr);
     if (rc) return rc;
   }
   return evaluate_tail(s, idx, bb_ref, want_gxd, want_gg, judge);
@@ -670,9 +681,12 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
   if (s->q1) return evaluate_tail_q1(s, idx, bb_ref, want_gxd, want_gg, judge);
   const void* Xs = s->X[idx];
   Partials pt{s->spart, kPartStride};
+  const bool fuse_cg = s->fuse_cg;
+  s->fuse_cg = false;
+  s->cg_fused = fuse_cg;
   tbeg(s, KS_PH_XC);
   launch_xc(s->rho, s->vh[idx], s->vext, s->veff[idx], s->grid, s->use_h, s->use_x,
-            s->use_h ? s->cg : nullptr, pt, s->st);
+            s->use_h && !fuse_cg ? s->cg : nullptr, pt, s->st, fuse_cg);
   tend(s, KS_PH_XC);
   // Gram blocks of [X, G]: X^T X and X^T G (and G^T G for the Cayley system); at p = 32
   // without G^T G the Hamiltonian pass forms them itself
@@ -749,9 +763,11 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
   nblk[SL_EH] = nblk[SL_EX] = nblk[SL_EXT] = nblk[SL_TF] = scalar_blocks(s->n);
   nblk[SL_DD] = nblk[SL_SS] = nblk[SL_SY] = nblk[SL_YY] = combine_partial_blocks(s->n, s->p);
   nblk[SL_DEFECT] = defect ? bf16_defect_blocks(s->p) : 0;
+  nblk[SL_CGRR] = nblk[SL_CGBB] = fuse_cg ? scalar_blocks(s->n) : 0;
   launch_finish_eval(s->spart, kPartStride, nblk, s->sums[idx], s->gxg[idx], s->p, s->pp, s->f,
                      s->grid.dV, s->enuc, s->use_h ? s->cg : nullptr, s->ev[idx],
-                     judge ? s->ls : nullptr, judge, s->st);
+                     judge ? s->ls : nullptr, judge, s->st, fuse_cg ? s->cg : nullptr, s->htol,
+                     s->hmaxit);
   tend(s, KS_PH_SMALL);
   return launch_check(s, "evaluate");
 }
@@ -777,9 +793,12 @@ int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want
   const void* Xs = s->X[idx];
   const int pp2 = s->pp * s->pp;
   Partials pt{s->spart, kPartStride};
+  const bool fuse_cg = s->fuse_cg;
+  s->fuse_cg = false;
+  s->cg_fused = fuse_cg;
   tbeg(s, KS_PH_XC);
   launch_xc(s->rho, s->vh[idx], s->vext, s->veff[idx], s->grid, s->use_h, s->use_x,
-            s->use_h ? s->cg : nullptr, pt, s->st);
+            s->use_h && !fuse_cg ? s->cg : nullptr, pt, s->st, fuse_cg);
   tend(s, KS_PH_XC);
   tbeg(s, KS_PH_HAMILTONIAN);
   q1_apply(s, Xs, s->G[idx], s->BX[idx], s->veff[idx], 2.0 * s->f, &pt);
@@ -839,9 +858,11 @@ int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want
   nblk[SL_EH] = nblk[SL_EX] = nblk[SL_EXT] = nblk[SL_TF] = scalar_blocks(s->n);
   nblk[SL_DD] = nblk[SL_SS] = nblk[SL_SY] = nblk[SL_YY] = q1_grad_blocks(s->n, s->p);
   nblk[SL_DEFECT] = defect ? bf16_defect_blocks(s->p) : 0;
+  nblk[SL_CGRR] = nblk[SL_CGBB] = fuse_cg ? scalar_blocks(s->n) : 0;
   launch_finish_eval(s->spart, kPartStride, nblk, s->sums[idx], s->feg[idx] + pp2, s->p, s->pp,
                      s->f, s->grid.dV, s->enuc, s->use_h ? s->cg : nullptr, s->ev[idx],
-                     judge ? s->ls : nullptr, judge, s->st);
+                     judge ? s->ls : nullptr, judge, s->st, fuse_cg ? s->cg : nullptr, s->htol,
+                     s->hmaxit);
   tend(s, KS_PH_SMALL);
   return launch_check(s, "evaluate");
 }
@@ -1069,6 +1090,13 @@ int run_after_trial(ks_system* s, MinRun* m, bool cg_read) {
       s->pcg_extra = 1;
       drop_graphs(s);
     }
+    // a residual measured in the exchange pass left only its norm: the CG start is formed
+    // again from the trial's V_H; then PCG iterations until the solve converges
+    if (s->cg_fused) {
+      s->cg_par = 0;
+      launch_hartree_init(s->rho, s->vh[t], nullptr, s->cg_r, s->cg_p[0], s->cg, s->htol,
+                          s->hmaxit, 1, s->grid, s->cgpart, s->st);
+    }
     int rc = hartree_iterate(s, s->vh[t], 2, true, nullptr, nullptr);
     if (rc) return rc;
     rc = evaluate_tail(s, t, c, m->qr, !m->qr, &m->lp);
@@ -1226,7 +1254,6 @@ template <typename T>
 void fill_typed(ks_system* s, std::vector<char>& buf, int c) {
   const int t = 1 - c;
   Partials pt{s->spart, kPartStride};
-  const int hb = hartree_blocks(s->n);
   // retraction: X_t = X_c A + D_c B with the density (QR weights)
   put_rec(buf, c, R_QR, QrFactor2dArgs{s->gxg[c], s->gxd[c], s->p, s->pp, &s->ls->tau, s->A,
                                         s->B, &s->ls->error});
@@ -1261,12 +1288,10 @@ void fill_typed(ks_system* s, std::vector<char>& buf, int c) {
                                  s->grid.nx, s->grid.ny, s->grid.nz, nullptr});
   put_rec(buf, c, R_PLANE2, FdPlaneArgs{s->cg_q, s->vh[t], fd.Sx, fd.Sy, s->grid.nx, s->grid.ny,
                                         nullptr, nullptr, nullptr, s->vh[c]});
-  put_rec(buf, c, R_INIT, InitArgs{s->rho, s->vh[t], nullptr, s->cg_r, s->cg_p[0], s->grid,
-                                   s->cgpart});
-  put_rec(buf, c, R_FIN_INIT, FinInitArgs{s->cgpart, hb, s->cg, s->htol, s->hmaxit, 1});
-  // evaluation of slot t
+  // evaluation of slot t; the exchange pass measures the Hartree residual (the summary
+  // writes the CG start), as a lone trial that queues no continuation does
   put_rec(buf, c, R_XC, XcArgs{s->rho, s->vh[t], s->vext, s->veff[t], s->grid, s->use_h,
-                               s->use_x, s->cg, pt});
+                               s->use_x, nullptr, pt, 1});
   const bool hxg = hx_fuses_gram(s->p);
   put_rec(buf, c, R_HX, HxArgs<T>{static_cast<const T*>(s->X[t]), s->p,
                                   static_cast<T*>(s->G[t]), s->p, s->veff[t], s->grid,
@@ -1306,11 +1331,13 @@ int upload_records(ks_system* s, const MinRun& m) {
     nblk[SL_KIN] = hx_fuses_gram(s->p) ? hx_gram_blocks(s->n) : hx_blocks(s->n, s->p);
     nblk[SL_EH] = nblk[SL_EX] = nblk[SL_EXT] = nblk[SL_TF] = scalar_blocks(s->n);
     nblk[SL_DD] = nblk[SL_SS] = nblk[SL_SY] = nblk[SL_YY] = combine_blocks(s->n);
+    nblk[SL_CGRR] = nblk[SL_CGBB] = scalar_blocks(s->n);
     ScalarCounts sc{};
     for (int i = 0; i < SL_COUNT; ++i) sc.v[i] = nblk[i];
     put_rec(buf, c, R_FINISH, FinishEvalArgs{s->spart, kPartStride, sc, s->sums[t], s->gxg[t],
                                              s->p, s->pp, s->f, s->grid.dV, s->enuc, s->cg,
-                                             s->ev[t], s->ls, m.lp});
+                                             s->ev[t], s->ls, m.lp, s->cg, s->htol,
+                                             s->hmaxit});
   }
   int rc = hip_check(s, hipMemcpyAsync(s->rec, buf.data(), kRecBytes, hipMemcpyHostToDevice,
                                        s->st), "record upload");
@@ -1380,7 +1407,6 @@ void launch_trial_batch(const std::vector<BatchMember*>& g, hipStream_t st) {
   auto cb = [](const ks_system* s) { return combine_blocks(s->n); };
   auto rt = table<CombineArgs>(g, R_RETRACT, cb, &tot);
   launch_combine_retract_batch<T>(rt, pp, tot, st);
-  auto hb = [](const ks_system* s) { return hartree_blocks(s->n); };
   // one plane mode for the group (the slowest any member needs), LDS for the largest
   int mode = kPlaneFull;
   bool stage_z = true;
@@ -1399,6 +1425,7 @@ void launch_trial_batch(const std::vector<BatchMember*>& g, hipStream_t st) {
   auto zb = [](const ks_system* s) {
     return fd_launch(s->grid).z_blocks;
   };
+  auto hb = [](const ks_system* s) { return hartree_blocks(s->n); };
   auto r0 = table<InitArgs>(g, R_RESID, hb, &tot);
   launch_init_batch(r0, tot, st);
   auto p1 = table<FdPlaneArgs>(g, R_PLANE1, pb, &tot);
@@ -1407,9 +1434,6 @@ void launch_trial_batch(const std::vector<BatchMember*>& g, hipStream_t st) {
   launch_fd_z_batch(fz, tot, stage_z, lds_z, st);
   auto p2 = table<FdPlaneArgs>(g, R_PLANE2, pb, &tot);
   launch_fd_plane_batch(p2, tot, mode, lds_p, st);
-  auto in = table<InitArgs>(g, R_INIT, hb, &tot);
-  launch_init_batch(in, tot, st);
-  launch_fin_init_batch(table<FinInitArgs>(g, R_FIN_INIT, one, &tot), st);
   auto sb = [](const ks_system* s) { return scalar_blocks(s->n); };
   auto xc = table<XcArgs>(g, R_XC, sb, &tot);
   launch_xc_batch(xc, tot, st);
@@ -1540,6 +1564,7 @@ int batch_tick(BatchEngine* e) {
     m->queued = !host_ls(m->s)->hartree_pending;
     m->s->run.queued = false;  // the lone path's speculative factor is not in place
     m->s->cg_par = 0;  // the host state a lone trial leaves (no PCG iteration queued)
+    m->s->cg_fused = true;  // the batched exchange pass measured the Hartree residual
     int code = run_after_trial(m->s, &m->s->run, true);
     const LsState* hl = host_ls(m->s);
     if (code != KS_OK) {
@@ -1967,6 +1992,7 @@ extern "C++" {
 namespace {
 using TuneKey = std::tuple<int, int, int, int, int, int, int>;
 std::mutex g_tune_mu;
+constexpr double kTuneMargin = 0.03;  // a candidate must beat the built-in shape by 3%
 std::map<TuneKey, std::pair<int, int>> g_tune;  // (fd_mode, hx_zrun)
 
 // Mean device time of fn() over reps launches on the system's stream, after two warm-ups.
@@ -2027,6 +2053,8 @@ int ks_autotune(ks_system* s, int force, ks_tune_info* out) {
       if (!rc) rc = hip_check(s, hipMemsetAsync(v, 0, nb, s->st), "tune clear");
     double best = 0.0;
     int best_mode = KS_TUNE_AUTO;
+    const int dflt = fd_plane_mode(s->grid.nx, s->grid.ny);
+    double dflt_us = 0.0;
     for (int mode : {kPlaneFull, kPlaneStripSy, kPlaneStrip, kPlaneStripG}) {
       if (rc || !fd_plane_mode_fits(s->grid.nx, s->grid.ny, mode)) continue;
       s->grid.fd_mode = mode;
@@ -2036,11 +2064,15 @@ int ks_autotune(ks_system* s, int force, ks_tune_info* out) {
       }, &us);
       info.fd_modes[info.n_fd] = mode;
       info.fd_us[info.n_fd++] = us;
+      if (mode == dflt) dflt_us = us;
       if (best_mode == KS_TUNE_AUTO || us < best) {
         best = us;
         best_mode = mode;
       }
     }
+    // a shape replaces the built-in rule only when it is clearly faster (timing noise must
+    // not flip the choice, which changes the last bits of the results)
+    if (!rc && dflt_us > 0.0 && best > (1.0 - kTuneMargin) * dflt_us) best_mode = dflt;
     s->grid.fd_mode = best_mode;
     info.fd_plane_mode = best_mode;
   }
@@ -2051,6 +2083,8 @@ int ks_autotune(ks_system* s, int force, ks_tune_info* out) {
     Partials pt{s->spart, kPartStride};
     double best = 0.0;
     int best_z = KS_TUNE_AUTO;
+    const int dflt = hx_zrun(s->grid.nx * s->grid.ny, s->grid.nz);
+    double dflt_us = 0.0;
     for (int z : {16, 8}) {
       if (rc) break;
       s->grid.hx_zrun = z;
@@ -2060,11 +2094,13 @@ int ks_autotune(ks_system* s, int force, ks_tune_info* out) {
       }, &us);
       info.hx_zruns[info.n_hx] = z;
       info.hx_us[info.n_hx++] = us;
+      if (z == dflt) dflt_us = us;
       if (best_z == KS_TUNE_AUTO || us < best) {
         best = us;
         best_z = z;
       }
     }
+    if (!rc && dflt_us > 0.0 && best > (1.0 - kTuneMargin) * dflt_us) best_z = dflt;
     s->grid.hx_zrun = best_z;
     info.hx_zrun = best_z;
   }

@@ -28,7 +28,9 @@ enum Slot : int {
   SL_YY = 7,    // tr(Yd^T Yd)
   SL_DEFECT = 8,  // ||X^T G (bf16) - X^T G (exact)||_F^2 (KS_PREC_MIXED_BF16, p > 64)
   SL_TF = 9,      // sum_g rho_g eps_TF(rho_g) (Thomas-Fermi term, KS_TERM_TF)
-  SL_COUNT = 10
+  SL_CGRR = 10,   // r.r of the Hartree residual checked inside the exchange pass
+  SL_CGBB = 11,   // b.b, b = 4 pi rho (same pass)
+  SL_COUNT = 12
 };
 
 // Conjugate-gradient state kept on the device (one solve at a time per system).
@@ -122,6 +124,47 @@ struct Grid {
 };
 
 __host__ __device__ inline int round_up(int a, int b) { return (a + b - 1) / b * b; }
+
+// (Op u)_g for u = z + beta po (po may be null): the 7-point -Laplacian_h, or for finite
+// elements the Q1 stiffness stencil (centre 8h/3, edges -h/6, corners -h/12, faces 0).
+__device__ inline double op_apply(const double* __restrict__ z, const double* __restrict__ po,
+                                  double beta, int g, int i, int j, int k, const Grid& gr) {
+  const int sy = gr.nx, sz = gr.nx * gr.ny;
+  auto u = [&](int o) { return po ? z[g + o] + beta * po[g + o] : z[g + o]; };
+  if (!gr.q1) {
+    double nb = 0.0;
+    if (i > 0) nb += u(-1);
+    if (i < gr.nx - 1) nb += u(1);
+    if (j > 0) nb += u(-sy);
+    if (j < gr.ny - 1) nb += u(sy);
+    if (k > 0) nb += u(-sz);
+    if (k < gr.nz - 1) nb += u(sz);
+    return (6.0 * u(0) - nb) * gr.inv_h2;
+  }
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz) {
+    if (k + dz < 0 || k + dz >= gr.nz) continue;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      if (j + dy < 0 || j + dy >= gr.ny) continue;
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        if (i + dx < 0 || i + dx >= gr.nx) continue;
+        const int cls = (dx != 0) + (dy != 0) + (dz != 0);
+        if (cls == 1) continue;
+        s[cls] += u(dz * sz + dy * sy + dx);
+      }
+    }
+  }
+  return (8.0 * gr.h / 3.0) * s[0] - (gr.h / 6.0) * s[2] - (gr.h / 12.0) * s[3];
+}
+
+// The Poisson right-hand side 4 pi rhs_scale rho_g and the residual b - (Op x0)_g, in the one
+// form every kernel that measures a Hartree residual uses (so their values agree bitwise).
+__device__ inline double poisson_rhs(const double* __restrict__ rho, int g, const Grid& gr) {
+  return 4.0 * kPi * gr.rhs_scale * rho[g];
+}
 
 // Blocks are dispatched round-robin over the 8 XCDs; map them so that each XCD gets
 // one contiguous range of logical blocks (neighbouring grid planes share an L2).
@@ -221,6 +264,10 @@ struct XcArgs {
   int use_x;        // bit 0: Slater exchange; bit 1: LDA correlation; bit 2: Thomas-Fermi
   const CgState* cg;
   Partials pt;
+  // with cg_check: the residual test of the Hartree solve in the same pass (r.r and b.b of
+  // r = b - L V_H to the SL_CGRR, SL_CGBB partials; a solve that fails it is restarted
+  // from the CG start by the host, which forms r again)
+  int cg_check;
 };
 
 template <typename T>
@@ -261,7 +308,8 @@ template <typename T>
 void launch_density(const T* X, int ld, int n, int p, double scale, double* rho,
                     hipStream_t st);
 void launch_xc(const double* rho, const double* vh, const double* vext, double* veff,
-               Grid g, int use_h, int use_x, const CgState* cg, Partials pt, hipStream_t st);
+               Grid g, int use_h, int use_x, const CgState* cg, Partials pt, hipStream_t st,
+               bool cg_check = false);
 // Y = scale ((1/2) L X + Diag(veff) X); with pt the per-block partials of sum X.(L X)
 template <typename T>
 void launch_hx(const T* X, int ldx, T* Y, int ldy, const double* veff, Grid g, int p,
@@ -391,13 +439,12 @@ struct FdLaunch {
   int z_blocks;
 };
 FdLaunch fd_launch(const Grid& g);
-void launch_init_batch(const BatchPtrs<InitArgs>& b, int blocks, hipStream_t st);
-void launch_fin_init_batch(const BatchPtrs<FinInitArgs>& b, hipStream_t st);
 void launch_dir_batch(const BatchPtrs<DirArgs>& b, int blocks, hipStream_t st);
 void launch_fin_dir_batch(const BatchPtrs<FinDirArgs>& b, hipStream_t st);
 void launch_upd_batch(const BatchPtrs<UpdArgs>& b, int blocks, hipStream_t st);
 void launch_fin_upd_batch(const BatchPtrs<FinUpdArgs>& b, hipStream_t st);
 void launch_fin_rz_batch(const BatchPtrs<FinRzArgs>& b, hipStream_t st);
+void launch_init_batch(const BatchPtrs<InitArgs>& b, int blocks, hipStream_t st);
 void launch_fd_plane_batch(const BatchPtrs<FdPlaneArgs>& b, int blocks, int mode, size_t lds,
                            hipStream_t st);
 void launch_fd_z_batch(const BatchPtrs<FdZArgs>& b, int blocks, bool staged, size_t lds,
@@ -572,6 +619,11 @@ struct FinishEvalArgs {
   EvalOut* out;
   LsState* ls;
   LsParams prm;
+  // with cgw: the CG start of a solve whose residual was measured in the exchange pass
+  // (SL_CGRR, SL_CGBB) is written here before the judgement reads it
+  CgState* cgw;
+  double htol;
+  int hmaxit;
 };
 
 
@@ -601,7 +653,8 @@ void launch_compact_gram(const double* gram, int pp, int p, double* out, hipStre
 void launch_finish_eval(const double* part, int stride, const int* nblk, double* sums,
                         const double* gram_xx, int p, int pp, double f, double dV,
                         const double* enuc, const CgState* cg, EvalOut* out, LsState* ls,
-                        const LsParams* prm, hipStream_t st);
+                        const LsParams* prm, hipStream_t st, CgState* cgw = nullptr,
+                        double htol = 0.0, int hmaxit = 0);
 void launch_set_scalar(double* dst, double v, hipStream_t st);
 void launch_qr_factor_batch(const BatchPtrs<QrFactor2dArgs>& b, int p_max, hipStream_t st);
 void launch_finish_eval_batch(const BatchPtrs<FinishEvalArgs>& b, hipStream_t st);

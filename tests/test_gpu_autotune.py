@@ -29,11 +29,14 @@ def test_autotune_choices_cache_and_results():
     info = a.ks_autotune(force=True)
     print("autotune:", info, flush=True)
     assert not info["cached"]
-    assert info["fd_plane_mode"] in info["fd_candidates_us"]
-    assert info["fd_candidates_us"][info["fd_plane_mode"]] == min(info["fd_candidates_us"].values())
-    assert set(info["hx_candidates_us"]) == {8, 16}
-    assert info["hx_zrun"] in (8, 16)
-    assert info["hx_candidates_us"][info["hx_zrun"]] == min(info["hx_candidates_us"].values())
+    # the kept shape is the fastest candidate, or the built-in one when nothing beats it by
+    # the 3% margin
+    fd = info["fd_candidates_us"]
+    assert info["fd_plane_mode"] in fd
+    assert fd[info["fd_plane_mode"]] <= min(fd.values()) / (1.0 - 0.03) + 1e-9
+    hx = info["hx_candidates_us"]
+    assert set(hx) == {8, 16} and info["hx_zrun"] in (8, 16)
+    assert hx[info["hx_zrun"]] <= min(hx.values()) / (1.0 - 0.03) + 1e-9
     # a second system of the same key takes the cached choice without timing
     b = K.system_from_spec(spec, hartree_solver=K.KS_HARTREE_PCG_FD)
     ib = b.ks_autotune()

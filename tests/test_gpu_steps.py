@@ -202,3 +202,30 @@ def test_reorth_every_keeps_the_constraint_and_restarts_the_reference(disc):
     assert r.terms.orth_error < 1e-5
     del C_prev
     s.close()
+
+
+def test_pending_hartree_solves_lone_and_batched_agree():
+    """A Hartree tolerance the exact fast-diagonalisation step cannot meet (1e-14 on a 24^3
+    grid, below eps cond(L)): every trial's solve is finished on the host by PCG iterations
+    from a fresh CG start at the trial's V_H (the exchange pass that measured the residual
+    left only its norm), alone and inside a lockstep batch, with the same bits."""
+    K = ks()
+    prm = K.ks_default_params(max_iter=60)
+    specs = [_spec(24, 6, 3, 4), _spec(16, 4, 2, 5)]
+    lone, systems, blocks = [], [], []
+    for sp in specs:
+        s = K.system_from_spec(sp, hartree_solver=K.KS_HARTREE_PCG_FD, hartree_tol=1e-14)
+        X0 = torch.tensor(synth.make_x0(sp, 1), dtype=torch.float64, device="cuda")
+        X = X0.clone()
+        r = s.ks_minimize(X, prm, check=False)
+        lone.append((r, X.cpu().numpy()))
+        systems.append(s)
+        blocks.append(X0.clone())
+    assert lone[0][0].hartree_iters_total > lone[0][0].nfe  # continuations ran
+    res, codes = K.ks_minimize_batch(systems, blocks, prm)
+    for i, s in enumerate(systems):
+        r, Xr = lone[i]
+        assert codes[i] in (K.KS_OK, K.KS_E_NOT_CONVERGED)
+        assert (res[i].iters, res[i].nfe, res[i].energy) == (r.iters, r.nfe, r.energy), i
+        assert np.array_equal(blocks[i].cpu().numpy(), Xr), i
+        s.close()
