@@ -186,49 +186,78 @@ def c4_leg(ks, synth, iters, seed, hartree="pcg_fd"):
     return out
 
 
-def fe_leg(ks, synth, p, iters, seed):
-    """Finite-element (Q1, B metric) workload on the 96^3 mesh: per-evaluation time,
-    stencil (A X and B X) bandwidth and the FP32-storage error at a fixed X, for FP64 and
-    FP32 storage of the orbital blocks.  Runs a fixed number of Alg. 3 iterations from
-    the seeded start (a converged solve of this size takes thousands)."""
-    import numpy as np
+def fe_leg(ks, synth, p, iters, seed, converge=False):
+    """Finite-element (Q1, B metric) workload on the 96^3 mesh at p orbitals.
+
+    Default: a fixed number of Alg. 3 iterations from the seeded start in FP64, FP32
+    storage and FP32 storage with the bf16 X^T G (per-evaluation time, stencil (A X and
+    B X) bandwidth, phase times, and each reduced-precision energy against FP64 after the
+    same iterations).  With converge, FP64 runs to the Section 4.1 rules (at most `iters`
+    iterations) and the reduced-precision runs stop on E_FP64 + 1e-6 Ha or on the
+    float-scaled stagnation test and are finished by an FP64 polish."""
     import torch
     spec = synth.make_config("c3", seed).copy(p=p)
     X0h = synth.make_x0(spec, seed)
     out = {"workload": f"{spec.name.replace('p128', f'p{p}')} (Q1 elements, B metric)",
-           "mesh": [spec.nx, spec.ny, spec.nz], "p": p, "iterations": iters}
-    energies = {}
-    for name, prec, dt, w in (("fp64", ks.KS_PREC_FP64, torch.float64, 8),
-                              ("fp32", ks.KS_PREC_FP32, torch.float32, 4)):
-        sysg = ks.system_from_spec(spec, hartree_solver=ks.KS_HARTREE_PCG_FD, precision=prec)
-        X0 = torch.tensor(X0h, dtype=dt, device="cuda")
-        X = X0.clone()
-        sysg.ks_minimize(X, ks.ks_default_params(max_iter=3), check=False)  # warm-up
-        # energy at the B-orthonormalised start (same X for both precisions up to rounding)
-        energies[name] = sysg.ks_energy_grad(X).total
-        X.copy_(X0)
+           "mesh": [spec.nx, spec.ny, spec.nz], "p": p, "iterations": iters,
+           "mode": "converged" if converge else "fixed iterations"}
+    n = spec.n
+    s64 = ks.system_from_spec(spec, hartree_solver=ks.KS_HARTREE_PCG_FD)
+    X0 = torch.tensor(X0h, dtype=torch.float64, device="cuda")
+    X = X0.clone()
+    s64.ks_minimize(X, ks.ks_default_params(max_iter=3), check=False)  # warm-up
+    X.copy_(X0)
+    torch.cuda.synchronize()
+    s64.ks_enable_timers(True)
+    s64.ks_read_timers(reset=True)
+    t0 = time.perf_counter()
+    prm64 = ks.ks_default_params(max_iter=iters) if converge else \
+        ks.ks_default_params(max_iter=iters, eps_g=0.0, stagnation_tol=0.0)
+    r = s64.ks_minimize(X, prm64, check=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ph = s64.ks_read_timers(reset=True)
+    s64.ks_enable_timers(False)
+    E64 = r.energy
+    ms, cnt = ph["hamiltonian"]
+    spmm_bytes = 3 * n * p * 8 + 16 * n  # read X, write G and B X, read V_eff and V_ext
+    out["fp64"] = {"seconds": round(el, 3), "iterations": r.iters, "evaluations": r.nfe,
+                   "stop": ks.STOP_NAMES[r.stop_reason],
+                   "ms_per_evaluation": round(1e3 * el / max(r.nfe, 1), 3),
+                   "energy": E64, "grad_norm_B": r.grad_norm,
+                   "stencil_avg_us": round(1e3 * ms / max(cnt, 1), 1),
+                   "stencil_GBps": round(spmm_bytes * cnt / (ms * 1e-3) / 1e9, 1) if cnt else None,
+                   "phases_ms": {k: round(v[0], 2) for k, v in ph.items() if v[1]}}
+    print(f"# fe fp64: {out['fp64']}", file=sys.stderr, flush=True)
+    for name, prec in (("fp32", ks.KS_PREC_FP32), ("bf16", ks.KS_PREC_MIXED_BF16)):
+        sr = ks.system_from_spec(spec, hartree_solver=ks.KS_HARTREE_PCG_FD, precision=prec)
+        Xr = torch.tensor(X0h, dtype=torch.float32, device="cuda")
         torch.cuda.synchronize()
-        sysg.ks_enable_timers(True)
-        sysg.ks_read_timers(reset=True)
         t0 = time.perf_counter()
-        r = sysg.ks_minimize(X, ks.ks_default_params(max_iter=iters), check=False)
+        prm = ks.ks_default_params(max_iter=iters, energy_target=E64 + 1e-6,
+                                   stagnation_tol=1e-11, eps_g=0.0) if converge else \
+            ks.ks_default_params(max_iter=iters, eps_g=0.0, stagnation_tol=0.0)
+        rr = sr.ks_minimize(Xr, prm, check=False)
         torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        ph = sysg.ks_read_timers(reset=True)
-        sysg.close()
-        n = spec.n
-        blk = n * p * w
-        ms, cnt = ph["hamiltonian"]
-        spmm_bytes = 3 * blk + 16 * n  # read X, write G and B X, read V_eff and V_ext
-        ent = {"ms_per_iteration": round(1e3 * el / max(r.iters, 1), 3),
-               "ms_per_evaluation": round(1e3 * el / max(r.nfe, 1), 3),
-               "evaluations": r.nfe, "energy": r.energy, "grad_norm_B": r.grad_norm,
-               "stencil_avg_us": round(1e3 * ms / max(cnt, 1), 1),
-               "stencil_GBps": round(spmm_bytes * cnt / (ms * 1e-3) / 1e9, 1) if cnt else None,
-               "phases_ms": {k: round(v[0], 2) for k, v in ph.items() if v[1]}}
+        t_red = time.perf_counter() - t0
+        sr.close()
+        ent = {"seconds": round(t_red, 3), "iterations": rr.iters, "evaluations": rr.nfe,
+               "stop": ks.STOP_NAMES[rr.stop_reason],
+               "ms_per_evaluation": round(1e3 * t_red / max(rr.nfe, 1), 3),
+               "energy_minus_fp64_Ha": rr.energy - E64}
+        if converge:
+            Xp = Xr.double().contiguous()
+            t0 = time.perf_counter()
+            rp = s64.ks_minimize(Xp, ks.ks_default_params(max_iter=iters,
+                                                          energy_target=E64 + 1e-6,
+                                                          stagnation_tol=0.0), check=False)
+            torch.cuda.synchronize()
+            ent["polish"] = {"seconds": round(time.perf_counter() - t0, 3),
+                             "iterations": rp.iters, "stop": ks.STOP_NAMES[rp.stop_reason],
+                             "energy_minus_fp64_Ha": rp.energy - E64}
         print(f"# fe {name}: {ent}", file=sys.stderr, flush=True)
         out[name] = ent
-    out["fp32_energy_error_at_start_Ha"] = abs(energies["fp32"] - energies["fp64"])
+    s64.close()
     return out
 
 
@@ -509,7 +538,11 @@ def main():
                     help="requests re-run in FP64 to state the FP32 error")
     ap.add_argument("--fe-p", type=int, default=128,
                     help="orbitals of the finite-element leg (0 = skip; at most 128)")
-    ap.add_argument("--fe-iters", type=int, default=100)
+    ap.add_argument("--fe-iters", type=int, default=300,
+                    help="iterations of each finite-element run (the cap with --fe-converge)")
+    ap.add_argument("--fe-converge", type=int, default=0,
+                    help="run the finite-element solves to convergence (slow: the 96^3 "
+                         "p = 128 system needs more than 6000 iterations)")
     ap.add_argument("--c4-iters", type=int, default=5,
                     help="iterations of the 128^3, p = 512 leg (0: skip it)")
     ap.add_argument("--c4-hartree", choices=["cg", "pcg_fd"], default="pcg_fd",
@@ -669,7 +702,7 @@ def main():
     spmm_alone = spmm_leg(ks, spec, solver) if args.spmm else None
     fe = None
     if args.fe_p > 0:
-        fe = fe_leg(ks, synth, args.fe_p, args.fe_iters, args.seed)
+        fe = fe_leg(ks, synth, args.fe_p, args.fe_iters, args.seed, bool(args.fe_converge))
     c4 = None
     if args.c4_iters > 0:
         c4 = c4_leg(ks, synth, args.c4_iters, args.seed, args.c4_hartree)
