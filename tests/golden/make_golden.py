@@ -9,6 +9,7 @@ of the FP64 oracle (``oracle/``); nothing comes from the GPU path.
     python tests/golden/make_golden.py gap c1              # spectral gap at the c1 minimiser
     python tests/golden/make_golden.py wide 80             # minimum of the p = 80 system
     python tests/golden/make_golden.py ofdft               # TFW Al14 on Q1 elements
+    python tests/golden/make_golden.py subspace c2         # c2 occupied subspace (tight run)
 """
 import math
 import os
@@ -155,6 +156,53 @@ def ofdft_run(N=35, margin=3.0):
     print(fn, res.E, res.gnorm, res.iters, res.stop, el)
 
 
+def subspace_run(cfg="c2", seed=0, eps_g=5e-6, stagnation_tol=1e-16):
+    """Rotation-invariant summaries of the oracle's occupied subspace at a tight c2
+    minimiser (Section 2.3, eq. (disKS)): the spectral gap lambda_{p+1} - lambda_p of
+    H(rho*) (Lanczos, scipy eigsh), the Ritz values of X^T H X, and V^T P V with P = X X^T
+    for two seeded unit vectors V (the subspace itself is too large to store)."""
+    import time
+    from oracle import optm
+    from oracle.ks import KSSystemFD
+    from paper_1308_2864_amd import synth
+    spec = synth.make_config(cfg, seed)
+    sysk = KSSystemFD(spec.nx, spec.ny, spec.nz, spec.h, spec.lo, spec.p, spec.R, spec.Z,
+                      f=spec.f, rc=spec.rc)
+    t = time.time()
+
+    def progress(k, E, g):
+        if k % 100 == 0:
+            print(f"  k={k} E={E:.12f} |grad|={g:.3e} t={time.time() - t:.0f}s", flush=True)
+
+    res = optm.minimize(sysk.energy_grad, synth.make_x0(spec, seed),
+                        optm.Params(eps_g=eps_g, stagnation_tol=stagnation_tol,
+                                    max_iter=20000), callback=progress)
+    X = res.X
+    veff = sysk.effective_potential(X)
+    T = X.T @ sysk.hamiltonian_apply(X, veff)
+    ritz = np.linalg.eigvalsh(0.5 * (T + T.T))
+    gap = spectral_gap(sysk, X)
+    V = np.random.default_rng(123).standard_normal((spec.n, 2))
+    V /= np.linalg.norm(V, axis=0)
+    VPV = (X.T @ V).T @ (X.T @ V)
+    fn = os.path.join(HERE, f"oracle_{cfg}_s{seed}_subspace.txt")
+    with open(fn, "w") as fh:
+        fh.write(f"# FP64 oracle, Alg. 3 (QR), config {cfg} seed {seed}, eps_g = {eps_g}, "
+                 f"stagnation tol = {stagnation_tol};\n# stopped by {res.stop} after "
+                 f"{res.iters} iterations, {time.time() - t:.0f} s.  ritz_i: eigenvalues of "
+                 f"X^T H X (H = (1/2) L + V_eff);\n# gap: lambda_(p+1) - lambda_p of H(rho*); "
+                 f"vpv_ab: V^T X X^T V for V = two unit N(0,1) columns, default_rng(123).\n")
+        fh.write(f"E = {repr(float(res.E))}\n")
+        fh.write(f"gnorm = {repr(float(res.gnorm))}\n")
+        fh.write(f"gap = {repr(float(gap))}\n")
+        for i, v in enumerate(ritz):
+            fh.write(f"ritz_{i} = {repr(float(v))}\n")
+        for a in range(2):
+            for b in range(2):
+                fh.write(f"vpv_{a}{b} = {repr(float(VPV[a, b]))}\n")
+    print(fn, res.E, res.gnorm, res.iters, res.stop, gap)
+
+
 def tests_seed(p):
     from tests.helpers import WIDE
     return WIDE[p][3]
@@ -170,6 +218,8 @@ if __name__ == "__main__":
         wide_run(int(sys.argv[2]))
     elif what == "ofdft":
         ofdft_run()
+    elif what == "subspace":
+        subspace_run(sys.argv[2] if len(sys.argv) > 2 else "c2")
     else:
         oracle_run(what, int(sys.argv[2]) if len(sys.argv) > 2 else 0,
                    sys.argv[3] if len(sys.argv) > 3 else "qr",
