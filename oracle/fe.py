@@ -81,7 +81,7 @@ class KSSystemQ1:
 
     def __init__(self, nx, ny, nz, h, lo, p, R, Z, f=2.0, rc=0.5, ext=True, hartree=True,
                  xc=True, v_ext_override=None, hartree_tol=1e-14, hartree_maxit=20000,
-                 corr=False, mu=1.0, tf=False, vext="erf"):
+                 corr=False, mu=1.0, tf=False, vext="erf", hartree_bc="zero"):
         self.grid = FDGrid(nx, ny, nz, h, lo)
         self.use_corr = bool(corr)
         # orbital-free (TFW, Section 2.2): von Weizsaecker weight mu on the stiffness term
@@ -112,6 +112,15 @@ class KSSystemQ1:
             self.e_ii = 0.0
         self.hartree_tol = float(hartree_tol)
         self.hartree_maxit = int(hartree_maxit)
+        # Hartree boundary: zero Dirichlet, or the monopole values of the electron count
+        self.v_bc, self.e_bc = np.zeros(self.n), 0.0
+        if hartree_bc == "monopole" and self.use_hartree:
+            from .boundary import monopole_potential
+            self.v_bc, self.e_bc, _ = monopole_potential(
+                lambda b: self.hartree_cg(b / (4.0 * math.pi * self.h3))[0], nx, ny, nz, h,
+                lo, R, Z, self.f * self.p, "q1")
+        elif hartree_bc not in ("zero", "monopole"):
+            raise ValueError(hartree_bc)
 
     def density(self, X):
         """Nodal density rho_k = f sum_i X_ki^2."""
@@ -154,7 +163,7 @@ class KSSystemQ1:
         external = h3 * float(self.v_ext @ rho)
         if self.use_hartree:
             vh, it, rel = self.hartree_cg(rho, vh0)
-            hartree = 0.5 * h3 * float(rho @ vh)
+            hartree = 0.5 * h3 * float(rho @ vh) + h3 * float(rho @ self.v_bc) + self.e_bc
         else:
             vh, it, rel, hartree = np.zeros(self.n), 0, 0.0, 0.0
         if self.use_xc:
@@ -174,7 +183,7 @@ class KSSystemQ1:
     def energy_grad(self, X, vh0=None):
         """Returns (Energy, E_X, V_H)."""
         en, rho, vh, vx = self.energy_terms(X, vh0)
-        veff = self.v_ext + vh + vx
+        veff = self.v_ext + vh + self.v_bc + vx
         G = 2.0 * self.f * (0.5 * self.mu * (self.A @ X) + self.h3 * veff[:, None] * X)
         return en, G, vh
 
@@ -187,7 +196,7 @@ class KSSystemQ1:
 
     def effective_potential(self, X, vh0=None):
         en, rho, vh, vx = self.energy_terms(X, vh0)
-        return self.v_ext + vh + vx
+        return self.v_ext + vh + self.v_bc + vx
 
 
 class BStiefel:

@@ -106,7 +106,7 @@ class KSSystemFD:
 
     def __init__(self, nx, ny, nz, h, lo, p, R, Z, f=2.0, rc=0.5, ext=True, hartree=True,
                  xc=True, v_ext_override=None, hartree_tol=1e-14, hartree_maxit=20000,
-                 corr=False, mu=1.0, tf=False, vext="erf"):
+                 corr=False, mu=1.0, tf=False, vext="erf", hartree_bc="zero"):
         self.grid = FDGrid(nx, ny, nz, h, lo)
         self.n = self.grid.n
         self.p = int(p)
@@ -135,6 +135,16 @@ class KSSystemFD:
             self.e_ii = 0.0
         self.hartree_tol = float(hartree_tol)
         self.hartree_maxit = int(hartree_maxit)
+        # Hartree boundary: zero Dirichlet, or the monopole values of the electron count
+        # (oracle/boundary.py): a fixed potential v_bc and an energy constant e_bc
+        self.v_bc, self.e_bc = np.zeros(self.n), 0.0
+        if hartree_bc == "monopole" and self.use_hartree:
+            from .boundary import monopole_potential
+            self.v_bc, self.e_bc, _ = monopole_potential(
+                lambda b: self.hartree_cg(b / (4.0 * math.pi))[0], nx, ny, nz, h, lo,
+                self.R, self.Z, self.f * self.p, "fd7")
+        elif hartree_bc not in ("zero", "monopole"):
+            raise ValueError(hartree_bc)
 
     # -- density (Section 2.3: rho(X) = diag(X X^T)) --------------------------------------
     def density(self, X):
@@ -191,7 +201,7 @@ class KSSystemFD:
         external = dV * float(self.v_ext @ rho)
         if self.use_hartree:
             vh, it, rel = self.hartree_cg(rho, vh0)
-            hartree = 0.5 * dV * float(rho @ vh)
+            hartree = 0.5 * dV * float(rho @ vh) + dV * float(rho @ self.v_bc) + self.e_bc
         else:
             vh, it, rel, hartree = np.zeros(self.n), 0, 0.0, 0.0
         if self.use_xc:
@@ -210,7 +220,7 @@ class KSSystemFD:
     def energy_grad(self, X, vh0=None):
         """Returns (Energy, G = E_X, V_H)."""
         en, rho, vh, vx = self.energy_terms(X, vh0)
-        veff = self.v_ext + vh + vx
+        veff = self.v_ext + vh + self.v_bc + vx
         G = 2.0 * self.f * (0.5 * self.mu * self.grid.lap(X) + veff[:, None] * X)
         return en, G, vh
 
@@ -223,4 +233,4 @@ class KSSystemFD:
 
     def effective_potential(self, X, vh0=None):
         en, rho, vh, vx = self.energy_terms(X, vh0)
-        return self.v_ext + vh + vx
+        return self.v_ext + vh + self.v_bc + vx

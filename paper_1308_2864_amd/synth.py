@@ -70,6 +70,7 @@ class SystemSpec:
     tf: bool = False    # Thomas-Fermi kinetic term (orbital-free TFW with p = 1)
     mu: float = 1.0     # weight of the kinetic (von Weizsaecker) term
     vext: str = "erf"   # nuclear potential: "erf" (smoothed Coulomb) or "gnh" (pseudopotential)
+    hartree_bc: str = "zero"  # Hartree boundary: "zero" Dirichlet or "monopole" values
     name: str = ""
 
     @property
@@ -183,7 +184,7 @@ def al_cluster(cells: int, a: float = AL_LATTICE) -> np.ndarray:
 
 
 def make_ofdft(cells: int, N: int, margin: float = 4.0, mu: float = 1.0,
-               disc: str = "q1") -> SystemSpec:
+               disc: str = "q1", hartree_bc: str = "zero") -> SystemSpec:
     """Orbital-free TFW system (p = 1) of an fcc Al cluster in a cube with margin bohr of
     vacuum on each side, N interior nodes per axis; GNH nuclei of valence 3, LDA exchange
     and correlation, occupation = number of valence electrons."""
@@ -193,7 +194,8 @@ def make_ofdft(cells: int, N: int, margin: float = 4.0, mu: float = 1.0,
     h = L / (N + 1)
     return SystemSpec(nx=N, ny=N, nz=N, h=h, lo=(-0.5 * L,) * 3, p=1, R=R,
                       Z=np.full(M, AL_VALENCE), f=AL_VALENCE * M, disc=disc, corr=True,
-                      tf=True, mu=mu, vext="gnh", name=f"of-al{M}-{N}^3")
+                      tf=True, mu=mu, vext="gnh", hartree_bc=hartree_bc,
+                      name=f"of-al{M}-{N}^3")
 
 
 def refine_spec(spec: SystemSpec) -> SystemSpec:

@@ -6,7 +6,8 @@ from oracle.ks import KSSystemFD
 
 def oracle_fd(spec, **kw):
     args = dict(f=spec.f, rc=spec.rc, ext=spec.ext, hartree=spec.hartree, xc=spec.xc,
-                corr=spec.corr, mu=spec.mu, tf=spec.tf, vext=spec.vext)
+                corr=spec.corr, mu=spec.mu, tf=spec.tf, vext=spec.vext,
+                hartree_bc=spec.hartree_bc)
     args.update(kw)
     return KSSystemFD(spec.nx, spec.ny, spec.nz, spec.h, spec.lo, spec.p, spec.R, spec.Z, **args)
 
@@ -28,7 +29,8 @@ def box_energy_closed_form(nx, ny, nz, h, p, f=2.0):
 def oracle_q1(spec, **kw):
     from oracle.fe import KSSystemQ1
     args = dict(f=spec.f, rc=spec.rc, ext=spec.ext, hartree=spec.hartree, xc=spec.xc,
-                corr=spec.corr, mu=spec.mu, tf=spec.tf, vext=spec.vext)
+                corr=spec.corr, mu=spec.mu, tf=spec.tf, vext=spec.vext,
+                hartree_bc=spec.hartree_bc)
     args.update(kw)
     return KSSystemQ1(spec.nx, spec.ny, spec.nz, spec.h, spec.lo, spec.p, spec.R, spec.Z, **args)
 
