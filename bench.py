@@ -361,12 +361,14 @@ def serve_leg(ks, synth, n_req, slots, hbm_gib, fracs, precision, seed, check_n,
 
 def of_leg(ks, synth, cells, levels, n0, margin):
     """Orbital-free TFW aluminium (Section 2.2; GNH nuclei, Section 4.2) on the 7-point
-    grid, p = 1: Alg. 3 on the finest grid from the atomic-density guess against Alg. 4
-    with uniform refinement (Table 5's strategy) over `levels` nested grids, both
-    retractions, the Section 4.1 stopping rules."""
+    grid, p = 1, with the monopole Hartree boundary: Alg. 3 on the finest grid from the
+    atomic-density guess against Alg. 4 with uniform refinement (Table 5's strategy) over
+    `levels` nested grids, both retractions, the Section 4.1 stopping rules; energy per atom
+    and binding energy per atom against one atom at the same spacing."""
     import numpy as np
     import torch
-    specs = synth.refine_levels(synth.make_ofdft(cells, n0, margin=margin, disc="fd7"), levels)
+    specs = synth.refine_levels(synth.make_ofdft(cells, n0, margin=margin, disc="fd7",
+                                                 hartree_bc="monopole"), levels)
     fine = specs[-1]
     print(f"# orbital-free leg: Al{fine.M}, grids {[s.nx for s in specs]}, h = {fine.h:.4f}",
           file=sys.stderr, flush=True)
@@ -417,6 +419,19 @@ def of_leg(ks, synth, cells, levels, n0, margin):
               f"{r.hartree_iters_total} it) {direct_s:.3f} s E={r.energy:.8f}; "
               f"levels {[x.iters for x in rl]} it {levels_s:.3f} s E={rl[-1].energy:.8f}",
               file=sys.stderr, flush=True)
+    # one atom at the same spacing (63^3 nodes), for the binding energy per atom
+    # E_b = (E_0 - N E_s) / N of Tables 4 and 5
+    atom = synth.make_ofdft(0, 63, margin=32.0 * fine.h, disc="fd7", hartree_bc="monopole")
+    sa = ks.system_from_spec(atom, hartree_solver=ks.KS_HARTREE_PCG_FD)
+    ra = sa.ks_minimize(guess(atom), ks.ks_default_params(), check=False)
+    sa.close()
+    e0 = out["qr"]["direct"]["energy"]
+    out["single_atom"] = {"energy_Ha": ra.energy, "energy_eV": ra.energy * HARTREE_EV,
+                          "iters": ra.iters, "stop": ks.STOP_NAMES[ra.stop_reason]}
+    out["binding_energy_per_atom_eV"] = (e0 - fine.M * ra.energy) / fine.M * HARTREE_EV
+    print(f"# orbital-free: E_s = {ra.energy * HARTREE_EV:.4f} eV, E_0/N = "
+          f"{e0 / fine.M * HARTREE_EV:.4f} eV, E_b = {out['binding_energy_per_atom_eV']:.4f} eV",
+          file=sys.stderr, flush=True)
     for s in systems:
         s.close()
     return out

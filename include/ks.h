@@ -98,6 +98,16 @@ extern "C" {
                                     4.2 (R = 1.15, R_c = 3.5, A = 0.1107), the
                                     electron-ion attraction (tends to -Z/r)               */
 
+/* Boundary values of the Hartree potential (Section 2.3 poses the Poisson problem on the
+ * box): zero Dirichlet (a grounded box), or the monopole values Q/|r_b - c| of the electron
+ * count Q = f p about the nuclear-charge centre c, which a finite charged cluster needs for
+ * free-space electrostatics.  The monopole option adds the fixed harmonic potential V_bc
+ * (Q times the harmonic extension of 1/|r_b - c|, computed once at creation with the
+ * system's Hartree solver) to V_eff, and h^3 sum rho V_bc - (1/2) Q V_bc(c) to E_H; E_X
+ * remains the exact derivative of the reported energy. */
+#define KS_HBC_ZERO 0
+#define KS_HBC_MONOPOLE 1
+
 #define KS_HARTREE_CG 0          /* plain conjugate gradients, warm started               */
 #define KS_HARTREE_PCG_FD 1      /* CG preconditioned by the exact fast diagonalisation   */
 
@@ -140,6 +150,7 @@ typedef struct ks_system_desc {
   double kinetic_scale;    /* mu: H = (mu/2) L + V_eff (the von Weizsaecker weight of
                               eq. (TFW) for orbital-free runs); <= 0 means 1              */
   int vext_kind;           /* KS_VEXT_* form of the nuclear potential                     */
+  int hartree_bc;          /* KS_HBC_* boundary values of the Hartree potential           */
 } ks_system_desc;
 
 typedef struct ks_energy {
@@ -147,7 +158,7 @@ typedef struct ks_energy {
   double kinetic;          /* (mu f/2) tr(X^T L X), L = -Laplacian_h (plus the
                               Thomas-Fermi energy with KS_TERM_TF)                        */
   double external;         /* h^3 sum V_ext rho                                           */
-  double hartree;          /* (h^3/2) rho^T V_H                                           */
+  double hartree;          /* (h^3/2) rho^T V_H (+ the monopole boundary terms)           */
   double xc;               /* h^3 sum rho (eps_x(rho) + eps_c(rho) with KS_TERM_CORR)      */
   double nuclear;          /* E_II                                                        */
   double grad_norm;        /* ||G - X G^T X||_F with G = E_X                              */

@@ -196,7 +196,7 @@ __device__ inline void k_xc_body(const XcArgs& ka, int ks_bid, int ks_nb) {
   // (3/4)(3/pi)^{1/3} and (3/pi)^{1/3}
   const double cv = cbrt(3.0 / kPi), cx = 0.75 * cv;
   const bool trivial = use_h && cg != nullptr && cg->bb == 0.0;  // rho == 0: V_H = 0
-  double eh = 0.0, ex = 0.0, ee = 0.0, et = 0.0, rr = 0.0, bb = 0.0;
+  double eh = 0.0, ex = 0.0, ee = 0.0, et = 0.0, rr = 0.0, bb = 0.0, eb = 0.0;
   const bool cg_check = ka.cg_check != 0;
   for (size_t g = beg + threadIdx.x; g < end; g += blockDim.x) {
     if (cg_check) {
@@ -228,7 +228,12 @@ __device__ inline void k_xc_body(const XcArgs& ka, int ks_bid, int ks_nb) {
       vx += (5.0 / 3.0) * kCtf * c2;
       et += r * kCtf * c2;
     }
-    veff[g] = ve + h + vx;
+    double vb = 0.0;
+    if (ka.vbc) {
+      vb = ka.vbc[g];
+      eb += r * vb;
+    }
+    veff[g] = ve + h + vb + vx;
     eh += r * h;
     ex += r * e;
     ee += r * ve;
@@ -241,6 +246,10 @@ __device__ inline void k_xc_body(const XcArgs& ka, int ks_bid, int ks_nb) {
   write_partial(pt, SL_EX, lb, ex);
   write_partial(pt, SL_EXT, lb, ee);
   write_partial(pt, SL_TF, lb, et);
+  if (ka.vbc) {
+    eb = block_sum(eb, sh);
+    write_partial(pt, SL_EBC, lb, eb);
+  }
   if (cg_check) {
     rr = block_sum(rr, sh);
     bb = block_sum(bb, sh);
@@ -833,9 +842,71 @@ int scalar_blocks(int n) { return stream_blocks((size_t)n); }
 
 void launch_xc(const double* rho, const double* vh, const double* vext, double* veff, Grid g,
                int use_h, int use_x, const CgState* cg, Partials pt, hipStream_t st,
-               bool cg_check) {
+               bool cg_check, const double* vbc) {
   hipLaunchKernelGGL(k_xc, dim3(scalar_blocks(g.n)), dim3(kBlock), 0, st,
-                     XcArgs{rho, vh, vext, veff, g, use_h, use_x, cg, pt, cg_check ? 1 : 0});
+                     XcArgs{rho, vh, vext, veff, g, use_h, use_x, cg, pt, cg_check ? 1 : 0,
+                            vbc});
+}
+
+// ---- monopole boundary of the Hartree potential -----------------------------------------
+__device__ inline double bc_value(const Grid& g, int i, int j, int k, double Q, double cx,
+                                  double cy, double cz) {
+  const double dx = g.lo[0] + (i + 1) * g.h - cx, dy = g.lo[1] + (j + 1) * g.h - cy,
+               dz = g.lo[2] + (k + 1) * g.h - cz;
+  return Q / sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+__global__ void k_bc_rhs(double* __restrict__ out, Grid g, double Q, double cx, double cy,
+                         double cz) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= g.n) return;
+  const int i = idx % g.nx, j = (idx / g.nx) % g.ny, k = idx / (g.nx * g.ny);
+  double acc = 0.0;
+  if (i == 0 || j == 0 || k == 0 || i == g.nx - 1 || j == g.ny - 1 || k == g.nz - 1) {
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int a = i + dx, b = j + dy, c = k + dz;
+          if (a >= 0 && a < g.nx && b >= 0 && b < g.ny && c >= 0 && c < g.nz) continue;
+          const int cls = (dx != 0) + (dy != 0) + (dz != 0);
+          double w = 0.0;
+          if (!g.q1) w = cls == 1 ? g.inv_h2 : 0.0;
+          else w = cls == 2 ? g.h / 6.0 : (cls == 3 ? g.h / 12.0 : 0.0);
+          if (w != 0.0) acc += w * bc_value(g, a, b, c, Q, cx, cy, cz);
+        }
+  }
+  out[idx] = acc / (4.0 * kPi * g.rhs_scale);
+}
+
+__global__ void k_bc_point(const double* __restrict__ v, Grid g, double Q, double cx,
+                           double cy, double cz, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double ux = (cx - g.lo[0]) / g.h - 1.0, uy = (cy - g.lo[1]) / g.h - 1.0,
+               uz = (cz - g.lo[2]) / g.h - 1.0;
+  const int bx = (int)floor(ux), by = (int)floor(uy), bz = (int)floor(uz);
+  const double tx = ux - bx, ty = uy - by, tz = uz - bz;
+  double acc = 0.0;
+  for (int dk = 0; dk < 2; ++dk)
+    for (int dj = 0; dj < 2; ++dj)
+      for (int di = 0; di < 2; ++di) {
+        const int i = bx + di, j = by + dj, k = bz + dk;
+        const double w = (di ? tx : 1.0 - tx) * (dj ? ty : 1.0 - ty) * (dk ? tz : 1.0 - tz);
+        const bool in = i >= 0 && i < g.nx && j >= 0 && j < g.ny && k >= 0 && k < g.nz;
+        const double val = in ? v[i + g.nx * (j + g.ny * k)] : bc_value(g, i, j, k, Q, cx, cy, cz);
+        acc += w * val;
+      }
+  *out = -0.5 * Q * acc;
+}
+
+void launch_bc_rhs(double* out, Grid g, double Q, double cx, double cy, double cz,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_bc_rhs, dim3((g.n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, out, g, Q,
+                     cx, cy, cz);
+}
+
+void launch_bc_point(const double* v, Grid g, double Q, double cx, double cy, double cz,
+                     double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_bc_point, dim3(1), dim3(kWave), 0, st, v, g, Q, cx, cy, cz, out);
 }
 
 template <typename T>

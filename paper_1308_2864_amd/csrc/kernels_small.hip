@@ -823,7 +823,7 @@ __device__ inline void k_finish_eval_body(const FinishEvalArgs& ka, int ks_bid, 
   // the kinetic partial carries the weight mu; the Thomas-Fermi term is kinetic energy
   o.kinetic = 0.5 * f * red[SL_KIN] + dV * red[SL_TF];
   o.external = dV * red[SL_EXT];  // h^3 sum V_ext rho
-  o.hartree = 0.5 * dV * red[SL_EH];
+  o.hartree = 0.5 * dV * red[SL_EH] + dV * red[SL_EBC] + (ka.ebc ? *ka.ebc : 0.0);
   o.xc = dV * red[SL_EX];
   o.nuclear = *enuc;
   o.total = o.kinetic + o.external + o.hartree + o.xc + o.nuclear;
@@ -1199,12 +1199,12 @@ void launch_finish_eval(const double* part, int stride, const int* nblk, double*
                         const double* gram_xx, int p, int pp, double f, double dV,
                         const double* enuc, const CgState* cg, EvalOut* out, LsState* ls,
                         const LsParams* prm, hipStream_t st, CgState* cgw, double htol,
-                        int hmaxit) {
+                        int hmaxit, const double* ebc) {
   ScalarCounts nb{};
   for (int i = 0; i < SL_COUNT; ++i) nb.v[i] = nblk[i];
   hipLaunchKernelGGL(k_finish_eval, dim3(1), dim3(kFinishThreads), 0, st,
                      FinishEvalArgs{part, stride, nb, sums, gram_xx, p, pp, f, dV, enuc, cg, out,
-                         ls, prm ? *prm : LsParams{}, cgw, htol, hmaxit});
+                         ls, prm ? *prm : LsParams{}, cgw, htol, hmaxit, ebc});
 }
 
 void launch_set_scalar(double* dst, double v, hipStream_t st) {

@@ -47,12 +47,12 @@ void set_thread_error(const char* msg) { g_err = msg ? msg : ""; }
 
 namespace {
 constexpr int kPartStride = 4096;  // >= blocks of every streaming kernel
-// argument records of the batched trial kernels: one 256-byte slot per kernel and parity
+// argument records of the batched trial kernels: one 320-byte slot per kernel and parity
 enum Rec {
   R_QR, R_RETRACT, R_RESID, R_PLANE1, R_FDZ, R_PLANE2, R_XC, R_HX, R_GRAM1,
   R_RED1, R_GRAD, R_RED2, R_FINISH, R_QR_NEXT, R_COUNT
 };
-constexpr size_t kRecSlot = 256;
+constexpr size_t kRecSlot = 320;
 constexpr size_t kRecBytes = 2 * R_COUNT * kRecSlot;
 constexpr int kGatherBytes = 512;  // CgState and LsState of one system (adjacent)
 constexpr size_t kHostBytes = 1024 + (size_t)kMaxBatch * kGatherBytes;
@@ -107,6 +107,8 @@ struct ks_system {
   int solver = KS_HARTREE_CG;
   double *Rd = nullptr, *Zd = nullptr, *enuc = nullptr, *tau_user = nullptr;
   double* gnh_tab = nullptr;  // radial table of the GNH pseudopotential (KS_VEXT_GNH)
+  double* vbc = nullptr;      // monopole boundary potential of the Hartree problem
+  double* ebc = nullptr;      // its energy constant -(1/2) Q V_bc(c)
   void *X[2] = {}, *G[2] = {}, *D[2] = {};  // float (FP32 modes) or double
   bool f32 = false;
   bool bf16 = false;  // KS_PREC_MIXED_BF16: float storage, Gram sub-products in bf16
@@ -194,6 +196,10 @@ void layout(ks_system* s, char* base, size_t* total) {
   s->enuc = c.take<double>(1);
   s->tau_user = c.take<double>(1);
   if (s->d.vext_kind == KS_VEXT_GNH) s->gnh_tab = c.take<double>(gnh_table_doubles());
+  if (s->d.hartree_bc == KS_HBC_MONOPOLE && (s->d.terms & KS_TERM_HARTREE)) {
+    s->vbc = c.take<double>(n);
+    s->ebc = c.take<double>(1);
+  }
   for (int i = 0; i < 2; ++i) {
     s->X[i] = c.take<char>(np * s->es);
     s->G[i] = c.take<char>(np * s->es);
@@ -270,6 +276,10 @@ int validate(const ks_system_desc* d, std::string* why) {
   }
   if (!(d->occupation > 0.0)) { *why = "occupation must be > 0"; return KS_E_INVAL; }
   if (d->n_nuclei < 0) { *why = "n_nuclei must be >= 0"; return KS_E_INVAL; }
+  if (d->hartree_bc != KS_HBC_ZERO && d->hartree_bc != KS_HBC_MONOPOLE) {
+    *why = "unknown hartree_bc";
+    return KS_E_INVAL;
+  }
   if (d->vext_kind != KS_VEXT_ERF && d->vext_kind != KS_VEXT_GNH) {
     *why = "unknown vext_kind";
     return KS_E_INVAL;
@@ -686,7 +696,7 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
   s->cg_fused = fuse_cg;
   tbeg(s, KS_PH_XC);
   launch_xc(s->rho, s->vh[idx], s->vext, s->veff[idx], s->grid, s->use_h, s->use_x,
-            s->use_h && !fuse_cg ? s->cg : nullptr, pt, s->st, fuse_cg);
+            s->use_h && !fuse_cg ? s->cg : nullptr, pt, s->st, fuse_cg, s->vbc);
   tend(s, KS_PH_XC);
   // Gram blocks of [X, G]: X^T X and X^T G (and G^T G for the Cayley system); at p = 32
   // without G^T G the Hamiltonian pass forms them itself
@@ -764,10 +774,11 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
   nblk[SL_DD] = nblk[SL_SS] = nblk[SL_SY] = nblk[SL_YY] = combine_partial_blocks(s->n, s->p);
   nblk[SL_DEFECT] = defect ? bf16_defect_blocks(s->p) : 0;
   nblk[SL_CGRR] = nblk[SL_CGBB] = fuse_cg ? scalar_blocks(s->n) : 0;
+  nblk[SL_EBC] = s->vbc ? scalar_blocks(s->n) : 0;
   launch_finish_eval(s->spart, kPartStride, nblk, s->sums[idx], s->gxg[idx], s->p, s->pp, s->f,
                      s->grid.dV, s->enuc, s->use_h ? s->cg : nullptr, s->ev[idx],
                      judge ? s->ls : nullptr, judge, s->st, fuse_cg ? s->cg : nullptr, s->htol,
-                     s->hmaxit);
+                     s->hmaxit, s->ebc);
   tend(s, KS_PH_SMALL);
   return launch_check(s, "evaluate");
 }
@@ -798,7 +809,7 @@ int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want
   s->cg_fused = fuse_cg;
   tbeg(s, KS_PH_XC);
   launch_xc(s->rho, s->vh[idx], s->vext, s->veff[idx], s->grid, s->use_h, s->use_x,
-            s->use_h && !fuse_cg ? s->cg : nullptr, pt, s->st, fuse_cg);
+            s->use_h && !fuse_cg ? s->cg : nullptr, pt, s->st, fuse_cg, s->vbc);
   tend(s, KS_PH_XC);
   tbeg(s, KS_PH_HAMILTONIAN);
   q1_apply(s, Xs, s->G[idx], s->BX[idx], s->veff[idx], 2.0 * s->f, &pt);
@@ -859,12 +870,39 @@ int evaluate_tail_q1(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want
   nblk[SL_DD] = nblk[SL_SS] = nblk[SL_SY] = nblk[SL_YY] = q1_grad_blocks(s->n, s->p);
   nblk[SL_DEFECT] = defect ? bf16_defect_blocks(s->p) : 0;
   nblk[SL_CGRR] = nblk[SL_CGBB] = fuse_cg ? scalar_blocks(s->n) : 0;
+  nblk[SL_EBC] = s->vbc ? scalar_blocks(s->n) : 0;
   launch_finish_eval(s->spart, kPartStride, nblk, s->sums[idx], s->feg[idx] + pp2, s->p, s->pp,
                      s->f, s->grid.dV, s->enuc, s->use_h ? s->cg : nullptr, s->ev[idx],
                      judge ? s->ls : nullptr, judge, s->st, fuse_cg ? s->cg : nullptr, s->htol,
-                     s->hmaxit);
+                     s->hmaxit, s->ebc);
   tend(s, KS_PH_SMALL);
   return launch_check(s, "evaluate");
+}
+
+// Monopole boundary values of the Hartree problem (KS_HBC_MONOPOLE): V_bc is the solution
+// of the interior system whose right-hand side carries the boundary values Q/|r_b - c|
+// (Q = f p electrons, c the nuclear-charge centre, or the box centre without nuclei),
+// formed with the system's own Hartree solver; then the energy constant -(1/2) Q V_bc(c).
+int setup_monopole(ks_system* s) {
+  double c[3] = {0.0, 0.0, 0.0}, zs = 0.0;
+  for (size_t a = 0; a < s->Z.size(); ++a) {
+    zs += s->Z[a];
+    for (int d = 0; d < 3; ++d) c[d] += s->Z[a] * s->R[3 * a + d];
+  }
+  const int dims[3] = {s->grid.nx, s->grid.ny, s->grid.nz};
+  for (int d = 0; d < 3; ++d)
+    c[d] = zs != 0.0 ? c[d] / zs : s->grid.lo[d] + 0.5 * (dims[d] + 1) * s->grid.h;
+  const double Q = s->f * s->p;
+  launch_bc_rhs(s->rho, s->grid, Q, c[0], c[1], c[2], s->st);
+  int it = 0;
+  double rr = 0.0;
+  int rc = hartree(s, s->rho, nullptr, s->vbc, true, &it, &rr);
+  if (rc) return rc;
+  const CgState* hc = host_cg(s);
+  if (rr > s->htol && !(hc->stall >= kCgStall && rr <= kCgFloor * s->htol))
+    return fail(s, KS_E_NOT_CONVERGED, "monopole boundary potential: Hartree solve did not converge");
+  launch_bc_point(s->vbc, s->grid, Q, c[0], c[1], c[2], s->ebc, s->st);
+  return launch_check(s, "monopole boundary");
 }
 
 // Cholesky QR of slot idx in place (Alg. 2): X <- X R^{-1} with X^T X = R^T R (finite
@@ -1291,7 +1329,7 @@ void fill_typed(ks_system* s, std::vector<char>& buf, int c) {
   // evaluation of slot t; the exchange pass measures the Hartree residual (the summary
   // writes the CG start), as a lone trial that queues no continuation does
   put_rec(buf, c, R_XC, XcArgs{s->rho, s->vh[t], s->vext, s->veff[t], s->grid, s->use_h,
-                               s->use_x, nullptr, pt, 1});
+                               s->use_x, nullptr, pt, 1, s->vbc});
   const bool hxg = hx_fuses_gram(s->p);
   put_rec(buf, c, R_HX, HxArgs<T>{static_cast<const T*>(s->X[t]), s->p,
                                   static_cast<T*>(s->G[t]), s->p, s->veff[t], s->grid,
@@ -1332,12 +1370,13 @@ int upload_records(ks_system* s, const MinRun& m) {
     nblk[SL_EH] = nblk[SL_EX] = nblk[SL_EXT] = nblk[SL_TF] = scalar_blocks(s->n);
     nblk[SL_DD] = nblk[SL_SS] = nblk[SL_SY] = nblk[SL_YY] = combine_blocks(s->n);
     nblk[SL_CGRR] = nblk[SL_CGBB] = scalar_blocks(s->n);
+    nblk[SL_EBC] = s->vbc ? scalar_blocks(s->n) : 0;
     ScalarCounts sc{};
     for (int i = 0; i < SL_COUNT; ++i) sc.v[i] = nblk[i];
     put_rec(buf, c, R_FINISH, FinishEvalArgs{s->spart, kPartStride, sc, s->sums[t], s->gxg[t],
                                              s->p, s->pp, s->f, s->grid.dV, s->enuc, s->cg,
                                              s->ev[t], s->ls, m.lp, s->cg, s->htol,
-                                             s->hmaxit});
+                                             s->hmaxit, s->ebc});
   }
   int rc = hip_check(s, hipMemcpyAsync(s->rec, buf.data(), kRecBytes, hipMemcpyHostToDevice,
                                        s->st), "record upload");
@@ -1716,6 +1755,7 @@ int ks_create_system(const ks_system_desc* d, void* dev_workspace, size_t ws_byt
   // the CG arrival counter must start at zero
   launch_fill(reinterpret_cast<double*>(s->cg), 0.0, sizeof(CgState) / sizeof(double), s->st);
   rc = launch_check(s, "setup");
+  if (rc == KS_OK && s->vbc) rc = setup_monopole(s);
   if (rc == KS_OK) rc = hip_check(s, hipStreamSynchronize(s->st), "setup sync");
   if (rc) {
     std::string m = s->err;

@@ -30,7 +30,8 @@ enum Slot : int {
   SL_TF = 9,      // sum_g rho_g eps_TF(rho_g) (Thomas-Fermi term, KS_TERM_TF)
   SL_CGRR = 10,   // r.r of the Hartree residual checked inside the exchange pass
   SL_CGBB = 11,   // b.b, b = 4 pi rho (same pass)
-  SL_COUNT = 12
+  SL_EBC = 12,    // sum_g rho_g V_bc,g (monopole Hartree boundary, KS_HBC_MONOPOLE)
+  SL_COUNT = 13
 };
 
 // Conjugate-gradient state kept on the device (one solve at a time per system).
@@ -268,6 +269,7 @@ struct XcArgs {
   // r = b - L V_H to the SL_CGRR, SL_CGBB partials; a solve that fails it is restarted
   // from the CG start by the host, which forms r again)
   int cg_check;
+  const double* vbc;  // monopole boundary potential added to V_eff (nullptr: none)
 };
 
 template <typename T>
@@ -309,7 +311,15 @@ void launch_density(const T* X, int ld, int n, int p, double scale, double* rho,
                     hipStream_t st);
 void launch_xc(const double* rho, const double* vh, const double* vext, double* veff,
                Grid g, int use_h, int use_x, const CgState* cg, Partials pt, hipStream_t st,
-               bool cg_check = false);
+               bool cg_check = false, const double* vbc = nullptr);
+// Monopole boundary of the Hartree potential: the interior right-hand side of the boundary
+// values Q/|r_b - c|, divided by 4 pi rhs_scale so that the Hartree solver's own right-hand
+// side 4 pi rhs_scale x reproduces it (7-point: face neighbours / h^2; Q1: edge neighbours
+// h/6, corners h/12); then out = -(1/2) Q V(c) by trilinear interpolation of V at c.
+void launch_bc_rhs(double* out, Grid g, double Q, double cx, double cy, double cz,
+                   hipStream_t st);
+void launch_bc_point(const double* v, Grid g, double Q, double cx, double cy, double cz,
+                     double* out, hipStream_t st);
 // Y = scale ((1/2) L X + Diag(veff) X); with pt the per-block partials of sum X.(L X)
 template <typename T>
 void launch_hx(const T* X, int ldx, T* Y, int ldy, const double* veff, Grid g, int p,
@@ -624,6 +634,7 @@ struct FinishEvalArgs {
   CgState* cgw;
   double htol;
   int hmaxit;
+  const double* ebc;  // the constant -(1/2) Q V_bc(c) of the monopole boundary (or nullptr)
 };
 
 
@@ -654,7 +665,7 @@ void launch_finish_eval(const double* part, int stride, const int* nblk, double*
                         const double* gram_xx, int p, int pp, double f, double dV,
                         const double* enuc, const CgState* cg, EvalOut* out, LsState* ls,
                         const LsParams* prm, hipStream_t st, CgState* cgw = nullptr,
-                        double htol = 0.0, int hmaxit = 0);
+                        double htol = 0.0, int hmaxit = 0, const double* ebc = nullptr);
 void launch_set_scalar(double* dst, double v, hipStream_t st);
 void launch_qr_factor_batch(const BatchPtrs<QrFactor2dArgs>& b, int p_max, hipStream_t st);
 void launch_finish_eval_batch(const BatchPtrs<FinishEvalArgs>& b, hipStream_t st);

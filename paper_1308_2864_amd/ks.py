@@ -49,7 +49,7 @@ class ks_system_desc(C.Structure):
         ("R", C.POINTER(C.c_double)), ("Z", C.POINTER(C.c_double)), ("rc", C.c_double),
         ("terms", C.c_int), ("v_ext_override", C.POINTER(C.c_double)), ("precision", C.c_int),
         ("hartree_solver", C.c_int), ("hartree_tol", C.c_double), ("hartree_maxit", C.c_int),
-        ("kinetic_scale", C.c_double), ("vext_kind", C.c_int),
+        ("kinetic_scale", C.c_double), ("vext_kind", C.c_int), ("hartree_bc", C.c_int),
     ]
 
 
@@ -112,6 +112,7 @@ class ks_phase_times(C.Structure):
 
 
 KS_TUNE_AUTO = -99
+KS_HBC_ZERO, KS_HBC_MONOPOLE = 0, 1
 
 
 class ks_tune_info(C.Structure):
@@ -223,7 +224,7 @@ def ks_default_params(**overrides) -> ks_opt_params:
 def make_desc(nx, ny, nz, h, lo, p, R=None, Z=None, *, f=2.0, rc=0.5, terms=KS_TERM_ALL,
               v_ext_override=None, ld=0, precision=KS_PREC_FP64, disc=KS_DISC_FD7,
               hartree_solver=KS_HARTREE_CG, hartree_tol=0.0, hartree_maxit=0,
-              kinetic_scale=0.0, vext_kind=KS_VEXT_ERF):
+              kinetic_scale=0.0, vext_kind=KS_VEXT_ERF, hartree_bc=0):
     """Fills a ks_system_desc; the returned object keeps the host arrays alive."""
     d = ks_system_desc()
     d.disc, d.nx, d.ny, d.nz, d.h = disc, nx, ny, nz, float(h)
@@ -243,6 +244,7 @@ def make_desc(nx, ny, nz, h, lo, p, R=None, Z=None, *, f=2.0, rc=0.5, terms=KS_T
     d.precision, d.hartree_solver = precision, hartree_solver
     d.hartree_tol, d.hartree_maxit = float(hartree_tol), int(hartree_maxit)
     d.kinetic_scale, d.vext_kind = float(kinetic_scale), int(vext_kind)
+    d.hartree_bc = int(hartree_bc)
     return d
 
 
@@ -383,7 +385,8 @@ def desc_from_spec(spec, **kw):
     dkw = dict(f=spec.f, rc=spec.rc, terms=terms,
                disc=KS_DISC_Q1 if spec.disc == "q1" else KS_DISC_FD7,
                kinetic_scale=spec.mu,
-               vext_kind=KS_VEXT_GNH if spec.vext == "gnh" else KS_VEXT_ERF)
+               vext_kind=KS_VEXT_GNH if spec.vext == "gnh" else KS_VEXT_ERF,
+               hartree_bc=KS_HBC_MONOPOLE if spec.hartree_bc == "monopole" else KS_HBC_ZERO)
     dkw.update(kw)
     return make_desc(spec.nx, spec.ny, spec.nz, spec.h, spec.lo, spec.p, spec.R, spec.Z, **dkw)
 

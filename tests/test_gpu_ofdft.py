@@ -158,3 +158,71 @@ def test_ofdft_minimize_q1_matches_golden(kind):
     s.ks_density(X, rho)
     assert abs(spec.h ** 3 * float(rho.sum()) - g["charge"]) <= 1e-6 * g["charge"]
     s.close()
+
+
+@pytest.mark.parametrize("disc", ["fd7", "q1"])
+def test_monopole_boundary_energy_grad_matches_oracle(disc):
+    """KS_HBC_MONOPOLE: the boundary potential V_bc (formed once at creation with the
+    system's Hartree solver), its energy terms and the gradient against the oracle."""
+    K = ks()
+    spec = synth.make_ofdft(1, 15, margin=2.5, disc=disc, hartree_bc="monopole")
+    print(f"# monopole energy {disc}", flush=True)
+    s = K.system_from_spec(spec, hartree_solver=K.KS_HARTREE_PCG_FD, hartree_tol=1e-14)
+    orc = oracle_fd(spec) if disc == "fd7" else oracle_q1(spec)
+    x = _guess(spec, orc.B if disc == "q1" else None)
+    X = dev(x)
+    G = torch.zeros_like(X)
+    e = s.ks_energy_grad(X, G)
+    en, Gr, _ = orc.energy_grad(x)
+    for t in TERMS:
+        a, b = getattr(e, t), float(getattr(en, t))
+        assert abs(a - b) <= 1e-10 * max(1.0, abs(en.total)), (t, a, b)
+    assert np.max(np.abs(host(G) - Gr)) <= 1e-9 * np.max(np.abs(Gr))
+    # V_eff includes the boundary potential
+    veff = torch.zeros(spec.n, dtype=torch.float64, device="cuda")
+    s.ks_get_potentials(v_eff=veff)
+    assert np.max(np.abs(host(veff) - orc.effective_potential(x))) <= 1e-9 * \
+        np.max(np.abs(orc.effective_potential(x)))
+    s.close()
+
+
+def test_monopole_kohn_sham_system_matches_oracle():
+    """The boundary option on a Kohn-Sham system (p = 5, erf nuclei, plain CG)."""
+    K = ks()
+    spec = synth.make_system(17, 13, 11, 0.55, 5, 3, seed=25, zrange=(1, 4), margin=1.5,
+                             min_spacing=1.0).copy(hartree_bc="monopole")
+    s = K.system_from_spec(spec, hartree_solver=K.KS_HARTREE_CG, hartree_tol=1e-14)
+    X0 = synth.make_x0(spec, 2)
+    X = dev(X0)
+    G = torch.zeros_like(X)
+    e = s.ks_energy_grad(X, G)
+    orc = oracle_fd(spec)
+    en, Gr, _ = orc.energy_grad(X0)
+    for t in TERMS:
+        a, b = getattr(e, t), float(getattr(en, t))
+        assert abs(a - b) <= 1e-10 * max(1.0, abs(en.total)), (t, a, b)
+    assert np.max(np.abs(host(G) - Gr)) <= 1e-9 * np.max(np.abs(Gr))
+    s.close()
+
+
+@pytest.mark.parametrize("kind", ["qr", "wy"])
+def test_ofdft_minimize_fd_monopole_matches_oracle(kind):
+    """Al14 with the monopole boundary: the converged energy (about -1.7 Ha per atom, the
+    scale of one atom's energy) equals the oracle's to 1e-10 relative."""
+    K = ks()
+    spec = synth.make_ofdft(1, 17, margin=2.5, disc="fd7", hartree_bc="monopole")
+    orc = oracle_fd(spec)
+    x0 = _guess(spec)
+    ref = optm.minimize(orc.energy_grad, x0, optm.Params(eps_g=1e-8, stagnation_tol=0.0,
+                                                         max_iter=3000, retraction=kind))
+    assert ref.stop == "grad"
+    s = K.system_from_spec(spec, hartree_tol=1e-14)
+    X = dev(x0)
+    r = s.ks_minimize(X, K.ks_default_params(eps_g=1e-8, stagnation_tol=0.0, max_iter=3000,
+                                             retraction=K.KS_WY if kind == "wy" else K.KS_QR))
+    print(f"OFDFT monopole {kind}: gpu E={r.energy:.12f} ({r.iters} it) oracle E={ref.E:.12f}"
+          f" ({ref.iters} it), {r.energy / spec.M:.4f} Ha/atom", flush=True)
+    assert r.stop_reason == K.KS_STOP_GRAD
+    assert abs(r.energy - ref.E) <= 1e-10 * abs(ref.E)
+    assert -2.5 < r.energy / spec.M < -1.0
+    s.close()
