@@ -568,6 +568,8 @@ def main():
     ap.add_argument("--of-levels", type=int, default=3,
                     help="nested grids of that leg (finest 2^(L-1) (N0+1) - 1 nodes)")
     ap.add_argument("--of-n0", type=int, default=31)
+    ap.add_argument("--of-margin", type=float, default=4.0,
+                    help="vacuum margin (bohr) around the orbital-free cluster")
     ap.add_argument("--max-iter", type=int, default=10000,
                     help="iteration cap (profiling runs only; the metric needs the default)")
     args = ap.parse_args()
@@ -731,7 +733,7 @@ def main():
                           args.serve_small)
     ofdft = None
     if args.of_cells > 0:
-        ofdft = of_leg(ks, synth, args.of_cells, args.of_levels, args.of_n0, 4.0)
+        ofdft = of_leg(ks, synth, args.of_cells, args.of_levels, args.of_n0, args.of_margin)
     cpu = None
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
