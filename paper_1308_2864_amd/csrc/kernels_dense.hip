@@ -19,6 +19,7 @@
 // then fixed-order cross-wave and cross-block reductions), so results are bitwise
 // reproducible run to run.
 #include <algorithm>
+#include <cstring>
 
 #include <hip/hip_ext.h>
 #include <type_traits>
@@ -712,9 +713,12 @@ int gram_chunks(int n, int pp) {
 
 // partial tiles of the Gram launches and of the gradient combine's fused Gram tiles (blocks
 // wider than 64 columns reduce 64-column sub-products one at a time)
+size_t wide_gram_part_doubles(int n);
+
 size_t gram_part_doubles(int n, int pp) {
   const size_t w = std::min(pp, 64);
-  return (size_t)std::max(gram_chunks(n, pp), combine_blocks(n)) * 3 * w * w;
+  const size_t sub = (size_t)std::max(gram_chunks(n, pp), combine_blocks(n)) * 3 * w * w;
+  return pp > 64 ? std::max(sub, wide_gram_part_doubles(n)) : sub;
 }
 
 void launch_gram(const void* A, const void* B, bool f32, int ld, int n, int p, int mask,
@@ -743,11 +747,389 @@ int combine_blocks(int n) {
 
 
 // ---- blocks wider than 64 columns ------------------------------------------------------
-// The products run as 64-column sub-blocks of the kernels above.  A Gram product is formed
-// per pair of column blocks (X[:, I]^T Y[:, J], reduced, then placed into the p_p x p_p
-// result), and the combine runs per output column block J, accumulating its contraction
-// blocks I in place (the diagonal block last, so that the gradient epilogue sees X, X_k
-// and D_k at the output columns).  The density of a retraction is formed afterwards.
+// Output tiles of 128 x 128, so that every operand value loaded feeds 128 products (the
+// 64-column kernels above feed 64, which leaves a p = 512 product bound by HBM).
+//
+// Gram: one launch forms every requested product.  Block b owns one output tile of one
+// product over one chunk of grid rows; its four wavefronts own the four 64 x 64 quarters
+// of the tile and walk the same rows (4 per MFMA step).  The partial tiles are summed over
+// the chunks in a fixed order by a second kernel, which also mirrors the symmetric
+// products (only their tiles I <= J are formed) and writes W = -(A^T B)^T.
+//
+// Combine: persistent blocks.  A unit is one row tile (128 grid rows) times one output
+// column tile; block g takes one unit per round.  Within a round the units of one row tile
+// sit on the same XCD (blocks g = x mod 8 share XCD x), so a row of X and Y is fetched from
+// HBM about once per round and served to its column tiles from that XCD's L2.  Each
+// wavefront owns a 32-row strip of the unit (two 16-row MFMA tiles by eight 16-column
+// tiles); the weights go through LDS in slabs of 16 contraction rows x 128 columns, double
+// buffered, one barrier per slab.  The contraction index of MFMA step s in lane group q is
+// comb_col(s, q), so each lane reads column pairs of its row.
+constexpr int kWT = 128;             // edge of an output tile
+constexpr int kWK = 16;              // contraction rows of a combine weight slab
+constexpr int kWideResident = 512;   // blocks of a wide launch (two per CU)
+constexpr int kWideMaxTiles = 48;    // 3 products x 4 x 4 tiles (p <= 512)
+
+struct WideGramArgs {
+  const void* A;
+  const void* B;
+  int ld, n, p;
+  int nch, ntiles;
+  double* part;  // [nch][ntiles][128][128]
+  signed char tp[kWideMaxTiles], ti[kWideMaxTiles], tj[kWideMaxTiles];
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gram_wide(WideGramArgs a) {
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);  // the tiles of one chunk share an XCD
+  const int chunk = lb / a.ntiles, tile = lb % a.ntiles;
+  const int prod = a.tp[tile];
+  const T* __restrict__ L = static_cast<const T*>(prod == 2 ? a.B : a.A);
+  const T* __restrict__ R = static_cast<const T*>(prod == 0 ? a.A : a.B);
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int q = lane / 16, c = lane % 16;
+  const int ld = a.ld, n = a.n, p = a.p;
+  const int ci = a.ti[tile] * kWT + 64 * (w >> 1) + c;  // L column of fragment 0
+  const int cj = a.tj[tile] * kWT + 64 * (w & 1) + c;   // R column of fragment 0
+  const int ngroups = (n + 3) / 4;
+  const int per = (ngroups + a.nch - 1) / a.nch;
+  const int g_beg = chunk * per, g_end = min(ngroups, g_beg + per);
+  bool oki[4], okj[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    oki[f] = ci + 16 * f < p;
+    okj[f] = cj + 16 * f < p;
+  }
+  d4 acc[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+  constexpr int kU = 2;  // row groups per batch; two batches in flight
+  struct Batch {
+    T l[kU][4], r[kU][4];
+  };
+  auto load = [&](Batch& b, int g0) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int row = 4 * (g0 + u) + q;
+      const bool rok = g0 + u < g_end && row < n;
+      const size_t roff = (size_t)(rok ? row : 0) * ld;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        // branch-free: clamped address, then select (a guarded load would make the
+        // compiler wait for every load in flight before the products)
+        const bool ol = rok && oki[f], orr = rok && okj[f];
+        const T vl = L[ol ? roff + ci + 16 * f : 0];
+        const T vr = R[orr ? roff + cj + 16 * f : 0];
+        b.l[u][f] = ol ? vl : T(0);
+        b.r[u][f] = orr ? vr : T(0);
+      }
+    }
+  };
+  auto products = [&](const Batch& b, int g0) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (g0 + u >= g_end) break;
+      double fl[4], fr[4];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        fl[f] = (double)b.l[u][f];
+        fr[f] = (double)b.r[u][f];
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[4 * x + y] = mfma16(fl[x], fr[y], acc[4 * x + y]);
+    }
+  };
+  int g0 = g_beg;
+  Batch f0, f1;
+  if (g0 < g_end) load(f0, g0);
+  while (g0 < g_end) {
+    if (g0 + kU < g_end) load(f1, g0 + kU);
+    products(f0, g0);
+    g0 += kU;
+    if (g0 >= g_end) break;
+    if (g0 + kU < g_end) load(f0, g0 + kU);
+    products(f1, g0);
+    g0 += kU;
+  }
+  double* o = a.part + (size_t)lb * kWT * kWT;
+  const int r0 = 64 * (w >> 1), c0 = 64 * (w & 1);
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        o[(size_t)(r0 + 16 * x + q + 4 * r) * kWT + c0 + 16 * y + c] = acc[4 * x + y][r];
+}
+
+// Row chunks of a wide Gram launch: one block per (chunk, tile) and at most
+// kWideResident blocks, each chunk at least 16 row groups.
+int wide_gram_nch(int n, int ntiles) {
+  const int ngroups = (n + 3) / 4;
+  const int nch = std::max(1, kWideResident / std::max(1, ntiles));
+  return std::min(nch, std::max(1, (ngroups + 15) / 16));
+}
+
+size_t wide_gram_part_doubles(int n) {
+  const int ngroups = (n + 3) / 4;
+  const size_t units = std::min<size_t>(kWideResident,
+                                        (size_t)kWideMaxTiles * std::max(1, (ngroups + 15) / 16));
+  return std::max<size_t>(units, kWideMaxTiles) * kWT * kWT;
+}
+
+struct WideReduceArgs {
+  const double* part;
+  int nch, ntiles, pp, mask, sym;  // sym: bit per product, only its tiles I <= J exist
+  double* out;                     // [3][pp][pp]
+  double* W;                       // optional: -(A^T B)^T
+  signed char lut[3][4][4];        // tile index of (product, I, J)
+};
+
+__global__ __launch_bounds__(256) void k_gram_wide_reduce(WideReduceArgs a) {
+  const int pp = a.pp, per = pp * pp;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 3 * per) return;
+  const int prod = e / per, ij = e % per, i = ij / pp, j = ij % pp;
+  if (!((a.mask >> prod) & 1)) return;
+  const bool mir = ((a.sym >> prod) & 1) && i > j;
+  const int si = mir ? j : i, sj = mir ? i : j;
+  const int tile = a.lut[prod][si / kWT][sj / kWT];
+  const double* src = a.part + (size_t)tile * kWT * kWT + (si % kWT) * kWT + sj % kWT;
+  const size_t cs = (size_t)a.ntiles * kWT * kWT;
+  constexpr int kU = 8;
+  double s = 0.0;
+  for (int c0 = 0; c0 < a.nch; c0 += kU) {
+    double v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) v[u] = c0 + u < a.nch ? src[(size_t)(c0 + u) * cs] : 0.0;
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (c0 + u < a.nch) s += v[u];
+  }
+  a.out[e] = s;
+  if (a.W && prod == 1) a.W[(size_t)j * pp + i] = -s;
+}
+
+template <typename T, bool kHasY, bool kHasC0, bool kGrad, bool kVec>
+__global__ __launch_bounds__(256) void k_combine_wide(CombineArgs a, int nct) {
+  __shared__ double wl[2][kWK * kWT];
+  __shared__ double sh[kBlock / kWave];
+  const T* __restrict__ X = static_cast<const T*>(a.X);
+  const T* __restrict__ Y = static_cast<const T*>(a.Y);
+  const T* __restrict__ C0 = static_cast<const T*>(a.C0);
+  const T* __restrict__ Xk = static_cast<const T*>(a.Xk);
+  const T* __restrict__ Dk = static_cast<const T*>(a.Dk);
+  T* __restrict__ out = static_cast<T*>(a.out);
+  const int ld = a.ld, n = a.n, p = a.p, pp = round_up(p, 16);
+  const int pk = a.pk ? a.pk : p, lda = a.lda ? a.lda : pp;
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int q = lane / 16, c = lane % 16;
+  const int nrt = (n + kWT - 1) / kWT;
+  const int G = gridDim.x, xcd = blockIdx.x % kXcds, m = blockIdx.x / kXcds;
+  const int R = G / nct;  // row tiles per round (G is a multiple of 8 nct)
+  d4 sums = {0.0, 0.0, 0.0, 0.0};
+
+  for (int round = 0; round * R < nrt; ++round) {
+    const int rt = round * R + (m / nct) * kXcds + xcd;
+    const int J = (m % nct + round) % nct;  // rotates, so upper-triangular work balances
+    if (rt >= nrt) continue;
+    const int roww = rt * kWT + 32 * w;  // first row of this wavefront's strip
+    const int J0 = J * kWT;
+    const int kmax = a.upper ? min(pk, J0 + kWT) : pk;
+    const int nsx = (kmax + kWK - 1) / kWK;
+    const int ns = kHasY ? 2 * nsx : nsx;
+
+    // Operand loads are branch-free and select nothing: a select right after a load makes
+    // the compiler wait for it before the products of the current slab.  Rows past n are
+    // read from row 0 (their outputs are never stored); columns past the contraction read
+    // the row's first element and meet zero weights (finite x 0 = 0).
+    auto load_x = [&](T (&dst)[2][4], int si) {
+      const T* src = (kHasY && si >= nsx) ? Y : X;
+      const int k0 = (si % nsx) * kWK;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int row = roww + 16 * t + c;
+        const size_t roff = (size_t)(row < n ? row : 0) * ld;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int col = k0 + 8 * j + 2 * q;
+          if constexpr (kVec) {
+            typedef T t2 __attribute__((ext_vector_type(2)));
+            const t2 v = *reinterpret_cast<const t2*>(src + roff + (col < pk ? col : 0));
+            dst[t][2 * j] = v[0];
+            dst[t][2 * j + 1] = v[1];
+          } else {
+#pragma unroll
+            for (int e = 0; e < 2; ++e) dst[t][2 * j + e] = src[roff + (col + e < pk ? col + e : 0)];
+          }
+        }
+      }
+    };
+    constexpr int kWPer = kWK * kWT / kBlock;  // weight values per thread and slab
+    // weights: raw values now, the zero padding is applied when they go to LDS
+    auto load_w = [&](double (&dst)[kWPer], int si) {
+      const double* src = (kHasY && si >= nsx) ? a.B : a.A;
+      const int k0 = (si % nsx) * kWK;
+#pragma unroll
+      for (int u = 0; u < kWPer; ++u) {
+        const int e = threadIdx.x + kBlock * u;
+        const int kk = k0 + e / kWT, col = J0 + e % kWT;
+        dst[u] = src[kk < pk && col < p ? (size_t)kk * lda + col : 0];
+      }
+    };
+    auto store_w = [&](const double (&src)[kWPer], int si, int buf) {
+      const int k0 = (si % nsx) * kWK;
+#pragma unroll
+      for (int u = 0; u < kWPer; ++u) {
+        const int e = threadIdx.x + kBlock * u;
+        const bool ok = k0 + e / kWT < pk && J0 + e % kWT < p;
+        wl[buf][e] = ok ? src[u] : 0.0;
+      }
+    };
+
+    d4 acc[2][8];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[t][u] = d4{0.0, 0.0, 0.0, 0.0};
+    // Slab si + 1 is loaded while slab si is multiplied.  The loads are unconditional (the
+    // last slab reloads itself) so that the compiler can count them exactly and wait only
+    // for the older ones; the scheduling barriers keep the loads ahead of the products and
+    // the LDS stores and register moves (which wait for the new loads) behind them.
+    T xc[2][4];
+    {
+      double w0[kWPer];
+      load_x(xc, 0);
+      load_w(w0, 0);
+      store_w(w0, 0, 0);
+    }
+    __syncthreads();
+    for (int si = 0; si < ns; ++si) {
+      const int sn = si + 1 < ns ? si + 1 : si;
+      T xn[2][4];
+      double wn[kWPer];
+      load_x(xn, sn);
+      load_w(wn, sn);
+      __builtin_amdgcn_sched_barrier(0);
+      const double* wb = wl[si & 1];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int kr = comb_col(s, q);
+        double bw[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) bw[u] = wb[kr * kWT + 16 * u + c];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const double xa = (double)xc[t][s];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc[t][u] = mfma16(xa, bw[u], acc[t][u]);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      store_w(wn, sn, (si + 1) & 1);
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) xc[t][e] = xn[t][e];
+      __syncthreads();
+    }
+
+    // epilogue: lane (q, c), register r of tile (t, u) is row roww + 16 t + q + 4 r,
+    // column J0 + 16 u + c
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = roww + 16 * t + q + 4 * r;
+        const bool rok = row < n;
+        const size_t roff = (size_t)(rok ? row : 0) * ld;
+        T c0v[8], xv[8], xkv[8], dkv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int col = J0 + 16 * u + c;
+          const bool ok = rok && col < p;
+          const size_t idx = ok ? roff + col : 0;
+          if constexpr (kHasC0) c0v[u] = C0[idx];
+          if constexpr (kGrad) {
+            xv[u] = X[idx];
+            xkv[u] = Xk[idx];
+            dkv[u] = Dk[idx];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int col = J0 + 16 * u + c;
+          const bool ok = rok && col < p;
+          double x = acc[t][u][r];
+          if constexpr (kHasC0) x += (double)c0v[u];
+          x = ok ? (double)(T)x : 0.0;  // the epilogue sees the stored value
+          if (ok) out[roff + col] = (T)x;
+          if constexpr (kGrad) {
+            const double sd = ok ? (double)xv[u] - (double)xkv[u] : 0.0;
+            const double yd = ok ? x - (double)dkv[u] : 0.0;
+            sums[0] += x * x;
+            sums[1] += sd * sd;
+            sums[2] += sd * yd;
+            sums[3] += yd * yd;
+          }
+        }
+      }
+  }
+  if constexpr (kGrad) {
+    const double dd = block_sum(sums[0], sh);
+    const double ss = block_sum(sums[1], sh);
+    const double sy = block_sum(sums[2], sh);
+    const double yy = block_sum(sums[3], sh);
+    if (threadIdx.x == 0) {
+      const int st = a.pt.stride;
+      a.pt.buf[(size_t)SL_DD * st + blockIdx.x] = dd;
+      a.pt.buf[(size_t)SL_SS * st + blockIdx.x] = ss;
+      a.pt.buf[(size_t)SL_SY * st + blockIdx.x] = sy;
+      a.pt.buf[(size_t)SL_YY * st + blockIdx.x] = yy;
+    }
+  }
+}
+
+// Blocks of a wide combine: a multiple of 8 x (column tiles), at most kWideResident, and
+// no more row tiles per round than there are.
+int wide_combine_grid(int n, int p) {
+  const int nct = (round_up(p, 16) + kWT - 1) / kWT;
+  const int nrt = (n + kWT - 1) / kWT;
+  const int k = std::max(1, std::min(kWideResident / (kXcds * nct), (nrt + kXcds - 1) / kXcds));
+  return kXcds * nct * k;
+}
+
+template <typename T, bool kHasY, bool kHasC0, bool kGrad>
+void launch_combine_wide_v(const CombineArgs& a, hipStream_t st) {
+  const int nct = (round_up(a.p, 16) + kWT - 1) / kWT;
+  const int G = wide_combine_grid(a.n, a.p);
+  constexpr uintptr_t kAl = 2 * sizeof(T) - 1;
+  const bool vec = ((a.ld | (a.pk ? a.pk : a.p)) & 1) == 0 &&
+                   ((reinterpret_cast<uintptr_t>(a.X) | reinterpret_cast<uintptr_t>(a.Y)) &
+                    kAl) == 0;
+  if (vec)
+    hipLaunchKernelGGL((k_combine_wide<T, kHasY, kHasC0, kGrad, true>), dim3(G), dim3(kBlock), 0,
+                       st, a, nct);
+  else
+    hipLaunchKernelGGL((k_combine_wide<T, kHasY, kHasC0, kGrad, false>), dim3(G), dim3(kBlock),
+                       0, st, a, nct);
+}
+
+template <typename T>
+void launch_combine_wide(const CombineArgs& a, hipStream_t st) {
+  const bool y = a.Y != nullptr, c0 = a.C0 != nullptr, gr = a.Xk != nullptr;
+  if (y && !c0 && !gr) launch_combine_wide_v<T, true, false, false>(a, st);
+  else if (!y && c0 && gr) launch_combine_wide_v<T, false, true, true>(a, st);
+  else if (!y && c0 && !gr) launch_combine_wide_v<T, false, true, false>(a, st);
+  else if (y && c0 && !gr) launch_combine_wide_v<T, true, true, false>(a, st);
+  else launch_combine_wide_v<T, false, false, false>(a, st);
+  if (a.rho)
+    launch_density<T>(static_cast<const T*>(a.out), a.ld, a.n, a.p, a.rho_scale, a.rho, st);
+}
+
+// The 64-column sub-product path remains for the bf16 products (KS_PREC_MIXED_BF16): their
+// matrix cores are fast enough that the re-reads are all the time they take.
 constexpr int kSubCols = 64;
 
 __global__ void k_gram_place(const double* __restrict__ sub, double* __restrict__ out, int pp,
@@ -764,44 +1146,6 @@ __global__ void k_gram_place(const double* __restrict__ sub, double* __restrict_
 
 int sub_blocks(int p) { return (p + kSubCols - 1) / kSubCols; }
 
-template <typename T>
-void launch_combine_tiled(const CombineArgs& a, hipStream_t st) {
-  const int p = a.p, pp = round_up(p, 16), nb = sub_blocks(p), nbk = combine_blocks(a.n);
-  auto off = [](const void* ptr, int col) -> const void* {
-    return ptr ? static_cast<const T*>(ptr) + col : nullptr;
-  };
-  for (int J = 0; J < nb; ++J) {
-    int order[16], no = 0;
-    for (int I = 0; I < nb; ++I)
-      if (I != J && (!a.upper || I < J)) order[no++] = I;
-    order[no++] = J;
-    for (int k = 0; k < no; ++k) {
-      const int I = order[k];
-      CombineArgs c{};
-      c.X = off(a.X, kSubCols * I);
-      c.Y = off(a.Y, kSubCols * I);
-      c.A = a.A + (size_t)kSubCols * I * pp + kSubCols * J;
-      c.B = a.B ? a.B + (size_t)kSubCols * I * pp + kSubCols * J : nullptr;
-      c.C0 = k == 0 ? off(a.C0, kSubCols * J) : off(a.out, kSubCols * J);
-      c.out = const_cast<void*>(off(a.out, kSubCols * J));
-      c.ld = a.ld;
-      c.n = a.n;
-      c.p = std::min(kSubCols, p - kSubCols * J);
-      c.pk = std::min(kSubCols, p - kSubCols * I);
-      c.lda = pp;
-      c.f32 = a.f32;
-      if (k == no - 1 && a.Xk) {
-        c.Xk = off(a.Xk, kSubCols * J);
-        c.Dk = off(a.Dk, kSubCols * J);
-        c.pt = Partials{a.pt.buf + (size_t)J * nbk, a.pt.stride};
-      }
-      launch_combine_tt<T, 4>(c, st);
-    }
-  }
-  if (a.rho)
-    launch_density<T>(static_cast<const T*>(a.out), a.ld, a.n, p, a.rho_scale, a.rho, st);
-}
-
 void set_launch_events(hipEvent_t start, hipEvent_t stop) {
   g_launch_start = start;
   g_launch_stop = stop;
@@ -809,8 +1153,8 @@ void set_launch_events(hipEvent_t start, hipEvent_t stop) {
 
 void launch_combine(const CombineArgs& a, hipStream_t st) {
   if (round_up(a.p, 16) > kSubCols) {
-    if (a.f32) launch_combine_tiled<float>(a, st);
-    else launch_combine_tiled<double>(a, st);
+    if (a.f32) launch_combine_wide<float>(a, st);
+    else launch_combine_wide<double>(a, st);
     return;
   }
   if (a.f32) launch_combine_p<float>(a, st);
@@ -818,7 +1162,7 @@ void launch_combine(const CombineArgs& a, hipStream_t st) {
 }
 
 int combine_partial_blocks(int n, int p) {
-  return combine_blocks(n) * (round_up(p, 16) > kSubCols ? sub_blocks(p) : 1);
+  return round_up(p, 16) > kSubCols ? wide_combine_grid(n, p) : combine_blocks(n);
 }
 
 // ---- BF16 Gram sub-product (KS_PREC_MIXED_BF16) ---------------------------------------
@@ -913,38 +1257,70 @@ template <typename T>
 void launch_gram_full_t(const T* A, const T* B, int ld, int n, int p, int mask,
                         double* partials, double* sub, double* out, double* W, hipStream_t st,
                         bool sym_ab, int bf16_mask) {
-  const int pp = round_up(p, 16), nb = sub_blocks(p), nch = gram_chunks(n, kSubCols);
-  const size_t lds = (size_t)3 * 4 * 64 * sizeof(double);
-  for (int prod = 0; prod < 3; ++prod) {
-    if (!((mask >> prod) & 1)) continue;
-    const T* L = prod == 2 ? B : A;
-    const T* R = prod == 0 ? A : B;
-    // A^T A and B^T B, and A^T B when the caller knows it is symmetric (X^T B X, D^T B D
-    // in the B metric): the blocks I <= J only, mirrored
-    const bool sym = prod != 1 || sym_ab;
-    for (int I = 0; I < nb; ++I)
-      for (int J = sym ? I : 0; J < nb; ++J) {
-        const int pa = std::min(kSubCols, p - kSubCols * I);
-        const int pb = std::min(kSubCols, p - kSubCols * J);
-        bool done = false;
-        if constexpr (std::is_same<T, float>::value) {
-          if ((bf16_mask >> prod) & 1) {
-            hipLaunchKernelGGL(k_gram_bf16, dim3(nch), dim3(256), lds, st,
-                               GramArgs<float>{L + kSubCols * I, R + kSubCols * J, ld, n, pa,
-                                               partials, pb});
-            done = true;
-          }
+  const int pp = round_up(p, 16);
+  // A^T A and B^T B, and A^T B when the caller knows it is symmetric (X^T B X, D^T B D
+  // in the B metric): the tiles I <= J only, mirrored
+  const int wide = mask & ~bf16_mask;
+  if (wide) {
+    WideGramArgs ga{};
+    WideReduceArgs ra{};
+    std::memset(ra.lut, -1, sizeof(ra.lut));
+    const int nb = (pp + kWT - 1) / kWT;
+    int nt = 0;
+    for (int prod = 0; prod < 3; ++prod) {
+      if (!((wide >> prod) & 1)) continue;
+      const bool sym = prod != 1 || sym_ab;
+      if (sym) ra.sym |= 1 << prod;
+      for (int I = 0; I < nb; ++I)
+        for (int J = sym ? I : 0; J < nb; ++J) {
+          ga.tp[nt] = (signed char)prod;
+          ga.ti[nt] = (signed char)I;
+          ga.tj[nt] = (signed char)J;
+          ra.lut[prod][I][J] = (signed char)nt;
+          ++nt;
         }
-        if (!done)
-          hipLaunchKernelGGL((k_gram<T, 4, kPAB>), dim3(nch), dim3(256), lds, st,
-                             GramArgs<T>{L + kSubCols * I, R + kSubCols * J, ld, n, pa, partials,
-                                         pb});
-        launch_gram_reduce(partials, nch, kSubCols, kPAB, sub, nullptr, st);
-        hipLaunchKernelGGL(k_gram_place, dim3(kSubCols * kSubCols / 256), dim3(256), 0, st,
-                           sub + kSubCols * kSubCols, out + (size_t)prod * pp * pp, pp,
-                           kSubCols * I, kSubCols * J, sym && I != J ? 1 : 0,
-                           prod == 1 ? W : nullptr);
-      }
+    }
+    ga.A = A;
+    ga.B = B;
+    ga.ld = ld;
+    ga.n = n;
+    ga.p = p;
+    ga.ntiles = nt;
+    ga.nch = wide_gram_nch(n, nt);
+    ga.part = partials;
+    hipLaunchKernelGGL(k_gram_wide<T>, dim3(ga.nch * nt), dim3(kBlock), 0, st, ga);
+    ra.part = partials;
+    ra.nch = ga.nch;
+    ra.ntiles = nt;
+    ra.pp = pp;
+    ra.mask = wide;
+    ra.out = out;
+    ra.W = (wide & kPAB) ? W : nullptr;
+    hipLaunchKernelGGL(k_gram_wide_reduce, dim3((3 * pp * pp + kBlock - 1) / kBlock),
+                       dim3(kBlock), 0, st, ra);
+  }
+  if constexpr (std::is_same<T, float>::value) {
+    const int nsb = sub_blocks(p), nch = gram_chunks(n, kSubCols);
+    const size_t lds = (size_t)3 * 4 * 64 * sizeof(double);
+    for (int prod = 0; prod < 3; ++prod) {
+      if (!((mask & bf16_mask) >> prod & 1)) continue;
+      const float* L = prod == 2 ? B : A;
+      const float* R = prod == 0 ? A : B;
+      const bool sym = prod != 1 || sym_ab;
+      for (int I = 0; I < nsb; ++I)
+        for (int J = sym ? I : 0; J < nsb; ++J) {
+          const int pa = std::min(kSubCols, p - kSubCols * I);
+          const int pb = std::min(kSubCols, p - kSubCols * J);
+          hipLaunchKernelGGL(k_gram_bf16, dim3(nch), dim3(256), lds, st,
+                             GramArgs<float>{L + kSubCols * I, R + kSubCols * J, ld, n, pa,
+                                             partials, pb});
+          launch_gram_reduce(partials, nch, kSubCols, kPAB, sub, nullptr, st);
+          hipLaunchKernelGGL(k_gram_place, dim3(kSubCols * kSubCols / 256), dim3(256), 0, st,
+                             sub + kSubCols * kSubCols, out + (size_t)prod * pp * pp, pp,
+                             kSubCols * I, kSubCols * J, sym && I != J ? 1 : 0,
+                             prod == 1 ? W : nullptr);
+        }
+    }
   }
 }
 
