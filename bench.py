@@ -146,7 +146,7 @@ def c4_leg(ks, synth, iters, seed, hartree="pcg_fd"):
     n, p = spec.n, spec.p
     solver = ks.KS_HARTREE_CG if hartree == "cg" else ks.KS_HARTREE_PCG_FD
     out = {"workload": f"{spec.name} (FP64, FP32 storage, FP32 storage with BF16 Gram, "
-                       f"{hartree} Hartree)",
+                       f"FP32 storage on the FP32 matrix cores, {hartree} Hartree)",
            "grid": [spec.nx, spec.ny, spec.nz], "n": n, "p": p, "iterations": iters}
     t0 = time.perf_counter()
     X0 = torch.tensor(synth.make_random_block(n, p, seed=seed, cfg="c4"), dtype=torch.float64,
@@ -154,7 +154,8 @@ def c4_leg(ks, synth, iters, seed, hartree="pcg_fd"):
     energies = {}
     for name, prec, dt in (("fp64", ks.KS_PREC_FP64, torch.float64),
                            ("fp32", ks.KS_PREC_FP32, torch.float32),
-                           ("bf16", ks.KS_PREC_MIXED_BF16, torch.float32)):
+                           ("bf16", ks.KS_PREC_MIXED_BF16, torch.float32),
+                           ("fp32_mfma", ks.KS_PREC_FP32_MFMA, torch.float32)):
         sysg = ks.system_from_spec(spec, hartree_solver=solver, precision=prec)
         if name == "fp64":
             zero = torch.zeros_like(X0)
@@ -181,6 +182,7 @@ def c4_leg(ks, synth, iters, seed, hartree="pcg_fd"):
         out[name] = ent
     out["fp32_energy_error_vs_fp64_Ha"] = abs(energies["fp32"] - energies["fp64"])
     out["bf16_energy_error_vs_fp64_Ha"] = abs(energies["bf16"] - energies["fp64"])
+    out["fp32_mfma_energy_error_vs_fp64_Ha"] = abs(energies["fp32_mfma"] - energies["fp64"])
     del X0
     torch.cuda.empty_cache()
     return out

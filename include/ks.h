@@ -76,6 +76,14 @@ extern "C" {
                                     float rounding of its entries.  The gradient norm then
                                     carries the bf16 error of X^T G: stop on
                                     energy_target.  Not accepted by the server.          */
+#define KS_PREC_FP32_MFMA 3      /* as FP32, and the block combines of blocks wider than
+                                    64 columns (retraction X A + Y B, direction
+                                    G + X W) run on the fp32 matrix cores: weights
+                                    rounded to float, fp32 sums over chains of 64
+                                    contraction indices, FP64 across chains, so an entry
+                                    is off by at most (64 + 4) 2^-24 of the sum of
+                                    |products| before its float store.  Gram blocks as
+                                    in FP32.  Not accepted by the server.                */
 
 #define KS_TERM_EXT 1            /* external (nuclear) potential                          */
 #define KS_TERM_HARTREE 2        /* Hartree potential                                     */
@@ -438,7 +446,8 @@ int ks_apply_hamiltonian(ks_system* s, const void* X, void* Y, const double* v_e
 int ks_get_potentials(ks_system* s, double* v_ext, double* v_h, double* v_eff);
 
 /* Gram blocks of two device n x ld blocks A, B: out (device, 3*p*p doubles, row-major
- * p x p each) = [A^T A, A^T B, B^T B].  The tall-skinny products of Section 3. */
+ * p x p each) = [A^T A, A^T B, B^T B].  The tall-skinny products of Section 3, summed in
+ * FP64 (KS_PREC_MIXED_BF16 above 64 columns: A^T B in bf16 with fp32 sums). */
 int ks_gram(ks_system* s, const void* A, const void* B, double* out);
 
 /* ---- no-allocation variant ------------------------------------------------------------ */

@@ -778,6 +778,21 @@ struct WideGramArgs {
   signed char tp[kWideMaxTiles], ti[kWideMaxTiles], tj[kWideMaxTiles];
 };
 
+typedef float fx4 __attribute__((ext_vector_type(4)));
+
+__device__ inline fx4 mfma16f(float a, float b, fx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// FP32 matrix-core combine (kMc, float storage only): the MFMA sums run in fp32 over a
+// chain of 64 contraction indices and are added into FP64 accumulators after it, so a
+// rounding error is at most (64 + 4) 2^-24 of the chain's sum of |products|.  The fp32
+// result tile is laid out as lane l, register r = row 4 (l / 16) + r, column l % 16 (the
+// FP64 tile has row l / 16 + 4 r).  (An fp32 Gram with FP64 chain sums was measured
+// slower than the FP64 one on float data: its FP64 accumulators leave too few registers
+// for the loads in flight.)
+constexpr int kMcSlabs = 4;  // 4 weight slabs = 64 contraction indices per fp32 chain
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_gram_wide(WideGramArgs a) {
   const int lb = xcd_remap(blockIdx.x, gridDim.x);  // the tiles of one chunk share an XCD
@@ -911,9 +926,11 @@ __global__ __launch_bounds__(256) void k_gram_wide_reduce(WideReduceArgs a) {
   if (a.W && prod == 1) a.W[(size_t)j * pp + i] = -s;
 }
 
-template <typename T, bool kHasY, bool kHasC0, bool kGrad, bool kVec>
+template <typename T, bool kHasY, bool kHasC0, bool kGrad, bool kVec, bool kMc = false>
 __global__ __launch_bounds__(256) void k_combine_wide(CombineArgs a, int nct) {
-  __shared__ double wl[2][kWK * kWT];
+  static_assert(!kMc || std::is_same<T, float>::value, "fp32 matrix cores take float data");
+  using WT = typename std::conditional<kMc, float, double>::type;  // staged weights
+  __shared__ WT wl[2][kWK * kWT];
   __shared__ double sh[kBlock / kWave];
   const T* __restrict__ X = static_cast<const T*>(a.X);
   const T* __restrict__ Y = static_cast<const T*>(a.Y);
@@ -984,15 +1001,19 @@ __global__ __launch_bounds__(256) void k_combine_wide(CombineArgs a, int nct) {
       for (int u = 0; u < kWPer; ++u) {
         const int e = threadIdx.x + kBlock * u;
         const bool ok = k0 + e / kWT < pk && J0 + e % kWT < p;
-        wl[buf][e] = ok ? src[u] : 0.0;
+        wl[buf][e] = ok ? (WT)src[u] : WT(0);
       }
     };
 
     d4 acc[2][8];
+    fx4 acc32[2][8];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc[t][u] = d4{0.0, 0.0, 0.0, 0.0};
+      for (int u = 0; u < 8; ++u) {
+        acc[t][u] = d4{0.0, 0.0, 0.0, 0.0};
+        acc32[t][u] = fx4{0.f, 0.f, 0.f, 0.f};
+      }
     // Slab si + 1 is loaded while slab si is multiplied.  The loads are unconditional (the
     // last slab reloads itself) so that the compiler can count them exactly and wait only
     // for the older ones; the scheduling barriers keep the loads ahead of the products and
@@ -1012,18 +1033,36 @@ __global__ __launch_bounds__(256) void k_combine_wide(CombineArgs a, int nct) {
       load_x(xn, sn);
       load_w(wn, sn);
       __builtin_amdgcn_sched_barrier(0);
-      const double* wb = wl[si & 1];
+      const WT* wb = wl[si & 1];
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int kr = comb_col(s, q);
-        double bw[8];
+        WT bw[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) bw[u] = wb[kr * kWT + 16 * u + c];
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-          const double xa = (double)xc[t][s];
+          if constexpr (kMc) {
 #pragma unroll
-          for (int u = 0; u < 8; ++u) acc[t][u] = mfma16(xa, bw[u], acc[t][u]);
+            for (int u = 0; u < 8; ++u) acc32[t][u] = mfma16f(xc[t][s], bw[u], acc32[t][u]);
+          } else {
+            const double xa = (double)xc[t][s];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[t][u] = mfma16(xa, bw[u], acc[t][u]);
+          }
+        }
+      }
+      if constexpr (kMc) {
+        // chains end at fixed slabs (and at the last one)
+        if ((si + 1) % kMcSlabs == 0 || si + 1 == ns) {
+#pragma unroll
+          for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) acc[t][u][r] += (double)acc32[t][u][r];
+              acc32[t][u] = fx4{0.f, 0.f, 0.f, 0.f};
+            }
         }
       }
       __builtin_amdgcn_sched_barrier(0);
@@ -1035,13 +1074,13 @@ __global__ __launch_bounds__(256) void k_combine_wide(CombineArgs a, int nct) {
       __syncthreads();
     }
 
-    // epilogue: lane (q, c), register r of tile (t, u) is row roww + 16 t + q + 4 r,
-    // column J0 + 16 u + c
+    // epilogue: lane (q, c), register r of tile (t, u) is row roww + 16 t + q + 4 r
+    // (fp32 tiles: + 4 q + r), column J0 + 16 u + c
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = roww + 16 * t + q + 4 * r;
+        const int row = roww + 16 * t + (kMc ? 4 * q + r : q + 4 * r);
         const bool rok = row < n;
         const size_t roff = (size_t)(rok ? row : 0) * ld;
         T c0v[8], xv[8], xkv[8], dkv[8];
@@ -1100,8 +1139,8 @@ int wide_combine_grid(int n, int p) {
   return kXcds * nct * k;
 }
 
-template <typename T, bool kHasY, bool kHasC0, bool kGrad>
-void launch_combine_wide_v(const CombineArgs& a, hipStream_t st) {
+template <typename T, bool kHasY, bool kHasC0, bool kGrad, bool kMc>
+void launch_combine_wide_m(const CombineArgs& a, hipStream_t st) {
   const int nct = (round_up(a.p, 16) + kWT - 1) / kWT;
   const int G = wide_combine_grid(a.n, a.p);
   constexpr uintptr_t kAl = 2 * sizeof(T) - 1;
@@ -1109,11 +1148,19 @@ void launch_combine_wide_v(const CombineArgs& a, hipStream_t st) {
                    ((reinterpret_cast<uintptr_t>(a.X) | reinterpret_cast<uintptr_t>(a.Y)) &
                     kAl) == 0;
   if (vec)
-    hipLaunchKernelGGL((k_combine_wide<T, kHasY, kHasC0, kGrad, true>), dim3(G), dim3(kBlock), 0,
-                       st, a, nct);
+    hipLaunchKernelGGL((k_combine_wide<T, kHasY, kHasC0, kGrad, true, kMc>), dim3(G),
+                       dim3(kBlock), 0, st, a, nct);
   else
-    hipLaunchKernelGGL((k_combine_wide<T, kHasY, kHasC0, kGrad, false>), dim3(G), dim3(kBlock),
-                       0, st, a, nct);
+    hipLaunchKernelGGL((k_combine_wide<T, kHasY, kHasC0, kGrad, false, kMc>), dim3(G),
+                       dim3(kBlock), 0, st, a, nct);
+}
+
+template <typename T, bool kHasY, bool kHasC0, bool kGrad>
+void launch_combine_wide_v(const CombineArgs& a, hipStream_t st) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (a.mc) return launch_combine_wide_m<T, kHasY, kHasC0, kGrad, true>(a, st);
+  }
+  launch_combine_wide_m<T, kHasY, kHasC0, kGrad, false>(a, st);
 }
 
 template <typename T>

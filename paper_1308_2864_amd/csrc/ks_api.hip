@@ -112,6 +112,7 @@ struct ks_system {
   void *X[2] = {}, *G[2] = {}, *D[2] = {};  // float (FP32 modes) or double
   bool f32 = false;
   bool bf16 = false;  // KS_PREC_MIXED_BF16: float storage, Gram sub-products in bf16
+  bool mc = false;    // KS_PREC_FP32_MFMA: float storage, wide products on fp32 matrix cores
   bool bf16_on = true;  // a run switches it off once the bf16 X^T G error is too large
   int es = 8;  // bytes per orbital element
   double *gxg[2] = {}, *gxd[2] = {}, *W = nullptr, *A = nullptr, *B = nullptr;
@@ -245,8 +246,9 @@ int validate(const ks_system_desc* d, std::string* why) {
     return KS_E_UNSUPPORTED;
   }
   if (d->precision != KS_PREC_FP64 && d->precision != KS_PREC_FP32 &&
-      d->precision != KS_PREC_MIXED_BF16) {
-    *why = "precision must be KS_PREC_FP64, KS_PREC_FP32 or KS_PREC_MIXED_BF16";
+      d->precision != KS_PREC_MIXED_BF16 && d->precision != KS_PREC_FP32_MFMA) {
+    *why = "precision must be KS_PREC_FP64, KS_PREC_FP32, KS_PREC_MIXED_BF16 or "
+           "KS_PREC_FP32_MFMA";
     return KS_E_UNSUPPORTED;
   }
   if (d->hartree_solver != KS_HARTREE_CG && d->hartree_solver != KS_HARTREE_PCG_FD) {
@@ -312,7 +314,8 @@ void init_dims(ks_system* s, const ks_system_desc* d) {
   s->hmaxit = d->hartree_maxit > 0 ? d->hartree_maxit : 5000;
   s->solver = d->hartree_solver;
   s->bf16 = d->precision == KS_PREC_MIXED_BF16;
-  s->f32 = d->precision == KS_PREC_FP32 || s->bf16;
+  s->mc = d->precision == KS_PREC_FP32_MFMA;
+  s->f32 = d->precision == KS_PREC_FP32 || s->bf16 || s->mc;
   s->es = s->f32 ? 4 : 8;
   s->R.assign(d->R ? d->R : nullptr, d->R ? d->R + 3 * d->n_nuclei : nullptr);
   s->Z.assign(d->Z ? d->Z : nullptr, d->Z ? d->Z + d->n_nuclei : nullptr);
@@ -730,6 +733,7 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
   ca.pt = pt;
   ca.gram_part = fused ? s->gram_part : nullptr;
   ca.f32 = s->f32;
+  ca.mc = s->mc;
   ca.ld = s->p;
   ca.n = s->n;
   ca.p = s->p;
@@ -938,6 +942,7 @@ int orthonormalize_slot(ks_system* s, int idx) {
   ca.n = s->n;
   ca.p = s->p;
   ca.f32 = s->f32;
+  ca.mc = s->mc;
   ca.out = s->X[o];
   launch_combine(ca, s->st);
   copy_block(s, s->X[idx], s->p, s->X[o], s->p);
@@ -1003,6 +1008,7 @@ int enqueue_trial(ks_system* s, int c, bool qr, const LsParams& lp, const ks_opt
   ca.rho = s->rho;
   ca.rho_scale = rho_scale(s);
   ca.f32 = s->f32;
+  ca.mc = s->mc;
   ca.ld = s->p;
   ca.n = s->n;
   ca.p = s->p;
@@ -1966,6 +1972,7 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
   ca.n = s->n;
   ca.p = s->p;
   ca.f32 = s->f32;
+  ca.mc = s->mc;
   if (kind == KS_QR && s->q1) {
     launch_qr_factor(s->feg[t] + s->pp * s->pp, s->gxd[t], s->p, s->pp, s->tau_user, s->A, s->B,
                      s->work, s->status, s->st);
@@ -1974,6 +1981,7 @@ int ks_retract(ks_system* s, const void* X, const void* G, double tau, int kind,
   } else if (kind == KS_QR) {
     CombineArgs cd{};
     cd.f32 = s->f32;
+    cd.mc = s->mc;
     cd.X = s->X[t];
     cd.A = s->W;
     cd.C0 = s->G[t];

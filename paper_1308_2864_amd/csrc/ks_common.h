@@ -561,6 +561,8 @@ struct CombineArgs {
   bool upper;                           // A and B are upper triangular (QR retraction)
   int lda;                              // row stride of A and B (0: p_p of the launch)
   int pk;                               // columns of X and Y to contract over (0: p)
+  bool mc;                              // float data, blocks wider than 64 columns: fp32
+                                        // matrix cores with FP64 sums across chains
 };
 void launch_combine(const CombineArgs& a, hipStream_t st);
 // Events for the next single-kernel combine launch of this host thread: that launch records

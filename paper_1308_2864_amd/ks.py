@@ -27,7 +27,7 @@ KS_E_NOT_CONVERGED = -7
 KS_E_UNSUPPORTED = -8
 
 KS_DISC_FD7, KS_DISC_Q1 = 0, 1
-KS_PREC_FP64, KS_PREC_FP32, KS_PREC_MIXED_BF16 = 0, 1, 2
+KS_PREC_FP64, KS_PREC_FP32, KS_PREC_MIXED_BF16, KS_PREC_FP32_MFMA = 0, 1, 2, 3
 KS_TERM_EXT, KS_TERM_HARTREE, KS_TERM_XC, KS_TERM_ALL, KS_TERM_CORR = 1, 2, 4, 7, 8
 KS_TERM_TF = 16
 KS_VEXT_ERF, KS_VEXT_GNH = 0, 1
@@ -462,7 +462,7 @@ def ks_request_bytes(desc) -> int:
     ws = ks_workspace_bytes(desc)
     if ws == 0:
         raise KSError(KS_E_INVAL, lib.ks_last_error(None).decode())
-    es = 4 if desc.precision in (KS_PREC_FP32, KS_PREC_MIXED_BF16) else 8
+    es = 4 if desc.precision in (KS_PREC_FP32, KS_PREC_MIXED_BF16, KS_PREC_FP32_MFMA) else 8
     x = desc.nx * desc.ny * desc.nz * desc.p * es  # the server keeps blocks dense
     return (ws + 255) // 256 * 256 + (x + 255) // 256 * 256
 
@@ -491,7 +491,7 @@ class KSServer:
         self._out = {}
 
     def ks_server_submit(self, rid, desc, X0, params=None, want_X=False):
-        dt = np.float32 if desc.precision in (KS_PREC_FP32, KS_PREC_MIXED_BF16) else np.float64
+        dt = np.float32 if desc.precision in (KS_PREC_FP32, KS_PREC_MIXED_BF16, KS_PREC_FP32_MFMA) else np.float64
         X0 = np.ascontiguousarray(X0, dtype=dt)
         n = desc.nx * desc.ny * desc.nz
         if X0.shape != (n, desc.p):

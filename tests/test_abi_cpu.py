@@ -123,11 +123,15 @@ def test_request_footprint_covers_system_and_orbitals():
         assert nb % 256 == 0
 
 
-def test_bf16_mode_is_accepted_with_fp32_storage():
-    """KS_PREC_MIXED_BF16 stores the orbital blocks in float like KS_PREC_FP32 (only the Gram
-    sub-products differ), so both need the same workspace."""
+def test_bf16_and_fp32_mfma_modes_are_accepted_with_fp32_storage():
+    """KS_PREC_MIXED_BF16 and KS_PREC_FP32_MFMA store the orbital blocks in float like
+    KS_PREC_FP32 (only the wide products differ), so all three need the same workspace; an
+    unknown mode is refused."""
     from paper_1308_2864_amd import ks
     ds = [ks.make_desc(16, 16, 16, 16 / 17, (-8, -8, -8), 100, [[0, 0, 0]], [2], precision=pr)
-          for pr in (ks.KS_PREC_FP32, ks.KS_PREC_MIXED_BF16, ks.KS_PREC_FP64)]
-    b32, b16, b64 = (ks.ks_workspace_bytes(d) for d in ds)
-    assert b32 == b16 > 0 and b64 > b32
+          for pr in (ks.KS_PREC_FP32, ks.KS_PREC_MIXED_BF16, ks.KS_PREC_FP32_MFMA,
+                     ks.KS_PREC_FP64)]
+    b32, b16, bmc, b64 = (ks.ks_workspace_bytes(d) for d in ds)
+    assert b32 == b16 == bmc > 0 and b64 > b32
+    bad = ks.make_desc(16, 16, 16, 16 / 17, (-8, -8, -8), 100, [[0, 0, 0]], [2], precision=4)
+    assert ks.ks_workspace_bytes(bad) == 0

@@ -37,7 +37,7 @@ def _golden(p):
 
 
 @pytest.mark.parametrize("p", [80, 130])
-@pytest.mark.parametrize("mode", ["bf16", "fp32"])
+@pytest.mark.parametrize("mode", ["bf16", "fp32", "fp32mc"])
 def test_reduced_precision_reaches_the_oracle_minimum(p, mode):
     """Float storage carries an energy noise of about 1e-9 of |E| per evaluation, so its
     Armijo tests stall once tau ||grad E||^2 falls to that level, which at p = 130 is a few
@@ -49,7 +49,8 @@ def test_reduced_precision_reaches_the_oracle_minimum(p, mode):
     E_ref = _golden(p)["E"]
     spec = wide_spec(p)
     print(f"# mixed {mode} p={p}", flush=True)
-    prec = K.KS_PREC_MIXED_BF16 if mode == "bf16" else K.KS_PREC_FP32
+    prec = {"bf16": K.KS_PREC_MIXED_BF16, "fp32": K.KS_PREC_FP32,
+            "fp32mc": K.KS_PREC_FP32_MFMA}[mode]
     s = K.system_from_spec(spec, hartree_solver=K.KS_HARTREE_PCG_FD, precision=prec)
     X = torch.tensor(synth.make_x0(spec, 1), dtype=torch.float32, device="cuda")
     prm = K.ks_default_params(max_iter=8000, energy_target=E_ref + 1e-6, stagnation_tol=1e-11,
@@ -74,7 +75,10 @@ def test_reduced_precision_reaches_the_oracle_minimum(p, mode):
           f"{K.STOP_NAMES[rp.stop_reason]} after {rp.iters} it, {rp.energy - E_ref:.2e}; "
           f"FP64 alone {full.iters} it", flush=True)
     assert r.stop_reason in (K.KS_STOP_ENERGY, K.KS_STOP_STAGNATION)
-    assert e_start - E_ref < 5e-5
+    # KS_PREC_FP32_MFMA: X^T G and the direction combine carry the fp32 chain errors (about
+    # sqrt(64) float roundings of each chain's products against one rounding of G in FP32
+    # storage), so its Armijo tests stall about ten times higher
+    assert e_start - E_ref < (5e-4 if mode == "fp32mc" else 5e-5)
     assert rp.stop_reason == K.KS_STOP_ENERGY and abs(rp.energy - E_ref) <= 1e-6
     assert full.stop_reason == K.KS_STOP_ENERGY
     assert rp.iters < full.iters / 2
@@ -123,3 +127,74 @@ def test_q1_bf16_keeps_b_orthonormality():
         assert r.iters == 8 and orth < 1e-5, (mode, orth)
         out[mode] = r
     assert abs(out["bf16"].energy - out["fp32"].energy) < 1e-3 * abs(out["fp32"].energy)
+
+
+def _small(p, seed):
+    return synth.make_system(13, 11, 10, 0.55, p, 3, seed=seed, zrange=(1, 3), margin=1.5,
+                             min_spacing=1.0)
+
+
+def _devf(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+
+
+@pytest.mark.parametrize("p", [80, 130, 200])
+def test_fp32_mfma_combine_within_chain_bound(p):
+    """KS_PREC_FP32_MFMA runs the block combines of blocks wider than 64 columns on the fp32
+    matrix cores (weights rounded to float, fp32 sums over chains of 64 contraction
+    indices, FP64 across chains); its Gram blocks are those of FP32 storage.  At tau = 0
+    the QR retraction is X R^{-1} with R the Cholesky factor of X^T X, so FP32 storage and
+    the fp32 matrix cores differ only in the combine: each entry within
+    (64 + 4) 2^-24 (|X| |R^{-1}|) plus the float rounding of both stored results.  X is a
+    seeded non-orthonormal float block (n = 1430, not a multiple of the 128-row tiles; one,
+    two and two ragged 128-column tiles)."""
+    K = ks()
+    spec = _small(p, 90 + p)
+    rng = np.random.default_rng(p)
+    X = (rng.standard_normal((spec.n, p)) / np.sqrt(spec.n)).astype(np.float32)
+    X[:, 0] += 0.05  # not orthonormal
+    res = {}
+    for name, prec in (("fp32", K.KS_PREC_FP32), ("mc", K.KS_PREC_FP32_MFMA)):
+        s = K.system_from_spec(spec, precision=prec)
+        out = torch.zeros((spec.n, p), dtype=torch.float32, device="cuda")
+        zero = torch.zeros_like(out)
+        s.ks_retract(_devf(X), zero, 0.0, K.KS_QR, out)
+        s.close()
+        res[name] = out.cpu().numpy().astype(np.float64)
+    Xd = X.astype(np.float64)
+    Rinv = np.linalg.inv(np.linalg.cholesky(Xd.T @ Xd).T)
+    u = 2.0 ** -24
+    bound = 68 * u * (np.abs(Xd) @ np.abs(Rinv)) + u * (np.abs(res["fp32"]) + np.abs(res["mc"]))
+    err = np.abs(res["mc"] - res["fp32"])
+    print(f"fp32 mfma combine p={p}: max err / bound {np.max(err / bound):.3f}, max rel "
+          f"{np.max(err) / np.max(np.abs(res['fp32'])):.2e}", flush=True)
+    assert np.all(err <= bound)
+    # the exact result X R^{-1} is orthonormal; both stay so to float level
+    assert np.linalg.norm(res["mc"].T @ res["mc"] - np.eye(p)) < 1e-4
+
+
+@pytest.mark.parametrize("p", [100, 200])
+def test_fp32_mfma_retraction_tracks_oracle(p):
+    """The QR retraction of KS_PREC_FP32_MFMA (Gram blocks and combine on the fp32 matrix
+    cores) against the oracle's on the same float inputs.  The Gram entries of the
+    orthonormal X are off by at most 68 2^-24 ~ 4e-6 (the bound above with |X|^T |X| of
+    order one), which moves the Cholesky factor by as much, and the combine's chains add at
+    most the same relative error: 1e-5 of the largest entry; the result is orthonormal to
+    that level."""
+    from oracle import stiefel
+    from tests.helpers import oracle_fd
+    K = ks()
+    spec = _small(p, 95 + p)
+    X = synth.make_x0(spec, 5).astype(np.float32)
+    _, G, _ = oracle_fd(spec).energy_grad(X.astype(np.float64))
+    G = G.astype(np.float32)
+    s = K.system_from_spec(spec, precision=K.KS_PREC_FP32_MFMA)
+    out = torch.zeros((spec.n, spec.p), dtype=torch.float32, device="cuda")
+    s.ks_retract(_devf(X), _devf(G), 0.05, K.KS_QR, out)
+    s.close()
+    ref = stiefel.retract_qr(X.astype(np.float64), G.astype(np.float64), 0.05)
+    got = out.cpu().numpy().astype(np.float64)
+    rel = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    orth = np.linalg.norm(got.T @ got - np.eye(p))
+    print(f"fp32 mfma retract p={p}: max rel {rel:.2e}, ||X^T X - I|| {orth:.2e}", flush=True)
+    assert rel <= 1e-5 and orth <= 1e-4
