@@ -764,6 +764,63 @@ def test_minimize_c2_matches_tight_oracle_reference():
     assert abs(r.energy - gold["E"]) <= 1e-10 * abs(gold["E"])
     assert r.terms.orth_error < 1e-12
 
+def test_c2_occupied_subspace_gap_gated():
+    """The c2 occupied subspace (Section 2.3, eq. (disKS)), gated by the spectral gap.  The
+    oracle reference (tests/golden/oracle_c2_s0_subspace.txt) stops at ||grad E|| = 3.5e-6
+    and stores the gap lambda_(p+1) - lambda_p = 8.9e-4 Ha of H(rho*), the Ritz values of
+    X^T H X and V^T X X^T V for two seeded unit vectors V.  By the Davis-Kahan sin-theta
+    theorem a block with residual R = H X - X (X^T H X) spans the invariant subspace P* to
+    ||sin theta||_F <= ||R||_F / (gap - ||R||_F), and ||X X^T - P*||_F = sqrt(2) of that.
+    At the oracle's stop that is ~1e-3, so the GPU runs on to ||grad E|| <= 1e-9, where the
+    bound falls below the 1e-6 of ||X X^T - Y Y^T||_F; against the oracle:
+    * the energy to 1e-10 relative (second order in the subspace error on both sides);
+    * V^T (P_gpu - P_oracle) V: for unit V drawn independently of the problem each entry
+      has spread ||P_gpu - P_oracle||_F / n, so it stays within 5 sqrt(2) (||R_gpu||_F +
+      ||R_oracle||_F) / (gap n), with ||R_oracle||_F = ||grad E|| / (2 f) from the stored
+      gradient norm;
+    * the Ritz values to 1e-5: each lies within its run's residual of an eigenvalue of its
+      own H(rho), and the two densities differ at first order in the oracle's subspace error
+      (measured 3e-6)."""
+    K = ks()
+    gold = _golden("oracle_c2_s0_subspace.txt")
+    if gold is None:
+        pytest.skip("c2 subspace reference not generated")
+    spec = synth.make_config("c2", 0)
+    p, n = spec.p, spec.n
+    sysg = K.system_from_spec(spec, hartree_solver=K.KS_HARTREE_PCG_FD, hartree_tol=1e-14)
+    X = dev(synth.make_x0(spec, 0))
+    r = sysg.ks_minimize(X, K.ks_default_params(eps_g=1e-9, stagnation_tol=0.0,
+                                                max_iter=20000), check=False)
+    Y = torch.empty_like(X)
+    sysg.ks_apply_hamiltonian(X, Y)
+    sysg.close()
+    Xh, Yh = host(X), host(Y)
+    T = Xh.T @ Yh
+    T = 0.5 * (T + T.T)
+    theta = np.linalg.eigvalsh(T)
+    R = np.linalg.norm(Yh - Xh @ T)
+    gap = gold["gap"]
+    dk = R / (gap - R)
+    V = np.random.default_rng(123).standard_normal((n, 2))
+    V /= np.linalg.norm(V, axis=0)
+    XV = Xh.T @ V
+    vpv = XV.T @ XV
+    vpv_o = np.array([[gold["vpv_00"], gold["vpv_01"]], [gold["vpv_10"], gold["vpv_11"]]])
+    ritz_o = np.array([gold[f"ritz_{i}"] for i in range(p)])
+    r_orc = gold["gnorm"] / (2 * spec.f)
+    vbar = 5 * math.sqrt(2) * (R + r_orc) / (gap * n)
+    print(f"c2 subspace: {r.iters} it, |grad| {r.grad_norm:.2e}, ||R||_F {R:.2e}, "
+          f"Davis-Kahan ||sin theta||_F <= {dk:.2e}; dE {r.energy - gold['E']:.2e}; "
+          f"max dRitz {np.max(np.abs(theta - ritz_o)):.2e}; max dVPV "
+          f"{np.max(np.abs(vpv - vpv_o)):.2e} (bar {vbar:.2e})", flush=True)
+    assert r.stop_reason == K.KS_STOP_GRAD
+    assert math.sqrt(2) * dk <= 1e-6
+    assert abs(r.energy - gold["E"]) <= 1e-10 * abs(gold["E"])
+    assert np.max(np.abs(vpv - vpv_o)) <= vbar
+    assert np.max(np.abs(theta - ritz_o)) <= 1e-5
+    assert r.terms.orth_error < 1e-12
+
+
 @pytest.mark.parametrize("p", [80, 130])
 def test_bf16_gram_matches_rounded_oracle(p):
     """KS_PREC_MIXED_BF16 forms A^T B (X^T G) of blocks wider than 64 columns on the bf16
