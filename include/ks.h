@@ -536,7 +536,10 @@ void ks_server_destroy(ks_server* sv);
  * trial instead of about thirty.  The kernels and their arguments are the same, so the
  * results are bitwise those of the eager run.  Replay needs the KS_HARTREE_PCG_FD solver
  * (or no Hartree term) and timers off; otherwise the run is eager.  The instantiated
- * graphs live for one ks_minimize call.  Errors: KS_E_INVAL, KS_E_HIP. */
+ * graphs live for one ks_minimize call.  In ks_minimize_batch, when every member has
+ * graphs on, a lockstep tick whose members all have their factor queued is captured once
+ * per ordered membership and replayed (the launches read each member's current slot from
+ * device memory), again bitwise equal to the eager tick.  Errors: KS_E_INVAL, KS_E_HIP. */
 int ks_enable_graphs(ks_system* s, int on);
 
 /* ---- instrumentation ------------------------------------------------------------------ */

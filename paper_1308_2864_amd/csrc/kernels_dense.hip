@@ -210,7 +210,7 @@ __global__ __launch_bounds__(256) void k_gram(GramArgs<T> ka) {
 template <typename T, int kT, int kMask>
 __global__ __launch_bounds__(256) void k_gram_batch(BatchPtrs<GramArgs<T>> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_gram_body<T, kT, kMask>(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+  k_gram_body<T, kT, kMask>(batch_arg(b, s), blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
 }
 
 
@@ -280,7 +280,7 @@ __global__ __launch_bounds__(kRedSlots * kRedLanes) void k_gram_reduce(GramReduc
 __global__ __launch_bounds__(kRedSlots * kRedLanes) void k_gram_reduce_batch(
     BatchPtrs<GramReduceArgs> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_gram_reduce_body(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+  k_gram_reduce_body(batch_arg(b, s), blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
 }
 
 
@@ -590,7 +590,7 @@ template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad,
           bool kGram2 = false, bool kUpper = false>
 __global__ __launch_bounds__(256) void k_combine_batch(BatchPtrs<CombineArgs> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_combine_body<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2, kUpper>(*b.a[s], blockIdx.x - b.off[s],
+  k_combine_body<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2, kUpper>(batch_arg(b, s), blockIdx.x - b.off[s],
                                                             b.off[s + 1] - b.off[s]);
 }
 
@@ -603,8 +603,7 @@ constexpr size_t combine_lds_bytes() {
 }
 
 void set_lds_attr(const void* k, size_t bytes) {
-  if (bytes > 32768)
-    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (bytes > 32768) set_dyn_lds_once(k, (int)bytes);
 }
 
 template <typename T, int kT, int kMask>

@@ -499,8 +499,7 @@ void launch_q1_grad(const Q1GradArgs& a, hipStream_t st) {
                                : reinterpret_cast<const void*>(k_q1_grad<float, false>))
                         : (vec ? reinterpret_cast<const void*>(k_q1_grad<double, true>)
                                : reinterpret_cast<const void*>(k_q1_grad<double, false>));
-  if (lds > 65536)
-    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kQ1LdsCap);
+  if (lds > 65536) set_dyn_lds_once(k, (int)kQ1LdsCap);
   if (a.f32 && vec)
     hipLaunchKernelGGL((k_q1_grad<float, true>), dim3(nb), dim3(kQ1Threads), lds, st, a);
   else if (a.f32)

@@ -264,7 +264,7 @@ __global__ void k_xc(XcArgs ka) {
 
 __global__ void k_xc_batch(BatchPtrs<XcArgs> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_xc_body(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+  k_xc_body(batch_arg(b, s), blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
 }
 
 
@@ -595,7 +595,7 @@ __global__ __launch_bounds__(256, kEnergy ? 2 : 3) void k_hx(HxArgs<T> ka) {
 template <typename T, bool kEnergy, bool kGram = false>
 __global__ __launch_bounds__(256, kEnergy ? 2 : 3) void k_hx_batch(BatchPtrs<HxArgs<T>> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_hx_body<T, kEnergy, kGram>(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+  k_hx_body<T, kEnergy, kGram>(batch_arg(b, s), blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
 }
 
 // The Gram-fused forms at two wavefronts per SIMD (at most 256 registers per lane): the
@@ -609,7 +609,7 @@ __global__ __launch_bounds__(256, 2) void k_hx_gram(HxArgs<T> ka) {
 template <typename T>
 __global__ __launch_bounds__(256, 2) void k_hx_gram_batch(BatchPtrs<HxArgs<T>> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_hx_body<T, true, true>(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+  k_hx_body<T, true, true>(batch_arg(b, s), blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
 }
 
 

@@ -97,7 +97,7 @@ __global__ void k_init(InitArgs ka) {
 
 __global__ void k_init_batch(BatchPtrs<InitArgs> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_init_body(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+  k_init_body(batch_arg(b, s), blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
 }
 
 
@@ -172,7 +172,7 @@ __global__ void k_dir(DirArgs ka) {
 
 __global__ void k_dir_batch(BatchPtrs<DirArgs> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_dir_body(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+  k_dir_body(batch_arg(b, s), blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
 }
 
 
@@ -200,7 +200,7 @@ __global__ void k_fin_dir(FinDirArgs ka) {
 
 __global__ void k_fin_dir_batch(BatchPtrs<FinDirArgs> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_fin_dir_body(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+  k_fin_dir_body(batch_arg(b, s), blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
 }
 
 
@@ -239,7 +239,7 @@ __global__ void k_upd(UpdArgs ka) {
 
 __global__ void k_upd_batch(BatchPtrs<UpdArgs> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_upd_body(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+  k_upd_body(batch_arg(b, s), blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
 }
 
 
@@ -279,7 +279,7 @@ __global__ void k_fin_upd(FinUpdArgs ka) {
 
 __global__ void k_fin_upd_batch(BatchPtrs<FinUpdArgs> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_fin_upd_body(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+  k_fin_upd_body(batch_arg(b, s), blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
 }
 
 
@@ -306,7 +306,7 @@ __global__ void k_fin_rz(FinRzArgs ka) {
 
 __global__ void k_fin_rz_batch(BatchPtrs<FinRzArgs> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_fin_rz_body(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+  k_fin_rz_body(batch_arg(b, s), blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
 }
 
 
@@ -456,7 +456,7 @@ __global__ __launch_bounds__(256) void k_fd_plane(FdPlaneArgs ka) {
 template <bool kStageSy, bool kStageSx>
 __global__ __launch_bounds__(256) void k_fd_plane_batch(BatchPtrs<FdPlaneArgs> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_fd_plane_body<kStageSy, kStageSx>(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+  k_fd_plane_body<kStageSy, kStageSx>(batch_arg(b, s), blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
 }
 
 
@@ -563,7 +563,7 @@ __global__ __launch_bounds__(kFullWaves * kWave) void k_fd_plane_full(FdPlaneArg
 __global__ __launch_bounds__(kFullWaves * kWave) void k_fd_plane_full_batch(
     BatchPtrs<FdPlaneArgs> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_fd_plane_full_body(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+  k_fd_plane_full_body(batch_arg(b, s), blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
 }
 
 
@@ -676,7 +676,7 @@ __global__ __launch_bounds__(512) void k_fd_z(FdZArgs ka) {
 template <bool kStageS>
 __global__ __launch_bounds__(512) void k_fd_z_batch(BatchPtrs<FdZArgs> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_fd_z_body<kStageS>(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+  k_fd_z_body<kStageS>(batch_arg(b, s), blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
 }
 
 
@@ -706,8 +706,7 @@ constexpr size_t kFdLdsCap = 150 * 1024;  // stay inside the 160 KiB of LDS of a
 // Raises the dynamic-LDS limit of a kernel to the cap.  The value does not depend on the
 // grid, so concurrent callers on several host threads all set the same value.
 void set_lds(const void* k, size_t bytes) {
-  if (bytes > 32768)
-    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFdLdsCap);
+  if (bytes > 32768) set_dyn_lds_once(k, (int)kFdLdsCap);
 }
 }  // namespace
 

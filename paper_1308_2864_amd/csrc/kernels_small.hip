@@ -13,6 +13,9 @@
 //    threshold (Section 4.1), the Cholesky QR of X+ is folded into the weights.
 //  * Barzilai-Borwein step (eq. (bb-1)), nonmonotone Armijo test and reference-value
 //    update (eq. (NMLS-Armijo)), stopping rules of Section 4.1.
+#include <mutex>
+#include <vector>
+#include <algorithm>
 #include "ks_common.h"
 #include "../../include/ks.h"
 
@@ -614,7 +617,7 @@ template <int P>
 __global__ __launch_bounds__(qr_threads<P>()) void k_qr_factor_2d_batch(
     BatchPtrs<QrFactor2dArgs> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_qr_factor_2d_body<P, qr_threads<P>()>(*b.a[s], blockIdx.x - b.off[s],
+  k_qr_factor_2d_body<P, qr_threads<P>()>(batch_arg(b, s), blockIdx.x - b.off[s],
                                           b.off[s + 1] - b.off[s]);
 }
 
@@ -851,7 +854,7 @@ __global__ __launch_bounds__(1024) void k_finish_eval(FinishEvalArgs ka) {
 
 __global__ __launch_bounds__(1024) void k_finish_eval_batch(BatchPtrs<FinishEvalArgs> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_finish_eval_body(*b.a[s], blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
+  k_finish_eval_body(batch_arg(b, s), blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
 }
 
 
@@ -1011,9 +1014,7 @@ bool prepare_lds(K kernel, size_t bytes) {
   // the limit set is the same for every size, so concurrent host threads agree on it
   if (bytes + 8192 > dyn_lds_limit()) return false;
   if (bytes > 32768)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(dyn_lds_limit() - 8192));
+    set_dyn_lds_once(reinterpret_cast<const void*>(kernel), (int)(dyn_lds_limit() - 8192));
   return true;
 }
 
@@ -1064,9 +1065,8 @@ void launch_qr_factor(const double* xx, const double* gxd, int p, int pp, const 
   const size_t bytes = (size_t)p * p * sizeof(double);
   const bool lds = bytes + kQrWideStatic <= dyn_lds_limit();
   if (lds && bytes > 32768)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_qr_factor_wide),
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(dyn_lds_limit() - kQrWideStatic));
+    set_dyn_lds_once(reinterpret_cast<const void*>(k_qr_factor_wide),
+                     (int)(dyn_lds_limit() - kQrWideStatic));
   hipLaunchKernelGGL(k_qr_factor_wide, dim3(1), dim3(kQrWideThreads), lds ? bytes : 0, st, xx,
                      gxd, p, pp, tau, A, B, lds ? nullptr : work, status);
 }
@@ -1246,6 +1246,16 @@ __global__ void k_gather(GatherArgs g) {
 
 void launch_gather(const GatherArgs& g, hipStream_t st) {
   hipLaunchKernelGGL(k_gather, dim3(g.S), dim3(64), 0, st, g);
+}
+
+
+void set_dyn_lds_once(const void* k, int bytes) {
+  static std::mutex mu;
+  static std::vector<const void*> done;
+  std::lock_guard<std::mutex> lock(mu);
+  if (std::find(done.begin(), done.end(), k) != done.end()) return;
+  (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  done.push_back(k);
 }
 
 }  // namespace ks

@@ -1410,18 +1410,32 @@ struct BatchEngine {
   hipEvent_t ev = nullptr;  // end of the record copy of a tick
   std::vector<BatchMember*> act;
   std::vector<BatchMember*> fin;
+  // Graph replay of a tick's trial launches (every member has graphs enabled and its
+  // factor queued): captured for one ordered membership and replayed while it lasts; the
+  // launches find each member's records through its current slot in par_dev.
+  hipGraphExec_t gexec = nullptr;
+  std::vector<const ks_system*> gkey;
+  int* par_dev = nullptr;
+  int* par_host = nullptr;       // pinned staging of par_dev
+  hipStream_t cap_st = nullptr;  // capture stream (the engine stream may be the null stream)
 };
 
 namespace {
 
+// The launch table of record kind r for group g.  par (device, one int per member of g):
+// the records are addressed by the slot in par at run time (graph replay); otherwise by
+// each member's current slot now.
 template <typename A, typename F>
-BatchPtrs<A> table(const std::vector<BatchMember*>& g, int r, F blocks, int* total) {
+BatchPtrs<A> table(const std::vector<BatchMember*>& g, int r, F blocks, int* total,
+                   const int* par = nullptr) {
   BatchPtrs<A> b{};
   b.S = (int)g.size();
+  b.par = par;
+  b.rstride = (int)(R_COUNT * kRecSlot);
   int off = 0;
   for (int i = 0; i < b.S; ++i) {
     b.off[i] = off;
-    b.a[i] = rec_at<A>(g[i]->s, g[i]->s->run.c, r);
+    b.a[i] = rec_at<A>(g[i]->s, par ? 0 : g[i]->s->run.c, r);
     off += blocks(g[i]->s);
   }
   b.off[b.S] = off;
@@ -1432,8 +1446,10 @@ BatchPtrs<A> table(const std::vector<BatchMember*>& g, int r, F blocks, int* tot
 int one(const ks_system*) { return 1; }
 
 // One trial of every member of g (same precision and p_p), then their records back.
+// par: see table (graph capture; every member's factor is then already queued).
 template <typename T>
-void launch_trial_batch(const std::vector<BatchMember*>& g, hipStream_t st) {
+void launch_trial_batch(const std::vector<BatchMember*>& g, hipStream_t st,
+                        const int* par = nullptr) {
   int tot = 0;
   const int pp = g[0]->s->pp;
   int pmax = 0;
@@ -1450,7 +1466,7 @@ void launch_trial_batch(const std::vector<BatchMember*>& g, hipStream_t st) {
     launch_qr_factor_batch(qr, pf <= 16 ? 16 : 32, st);
   }
   auto cb = [](const ks_system* s) { return combine_blocks(s->n); };
-  auto rt = table<CombineArgs>(g, R_RETRACT, cb, &tot);
+  auto rt = table<CombineArgs>(g, R_RETRACT, cb, &tot, par);
   launch_combine_retract_batch<T>(rt, pp, tot, st);
   // one plane mode for the group (the slowest any member needs), LDS for the largest
   int mode = kPlaneFull;
@@ -1471,37 +1487,37 @@ void launch_trial_batch(const std::vector<BatchMember*>& g, hipStream_t st) {
     return fd_launch(s->grid).z_blocks;
   };
   auto hb = [](const ks_system* s) { return hartree_blocks(s->n); };
-  auto r0 = table<InitArgs>(g, R_RESID, hb, &tot);
+  auto r0 = table<InitArgs>(g, R_RESID, hb, &tot, par);
   launch_init_batch(r0, tot, st);
-  auto p1 = table<FdPlaneArgs>(g, R_PLANE1, pb, &tot);
+  auto p1 = table<FdPlaneArgs>(g, R_PLANE1, pb, &tot, par);
   launch_fd_plane_batch(p1, tot, mode, lds_p, st);
-  auto fz = table<FdZArgs>(g, R_FDZ, zb, &tot);
+  auto fz = table<FdZArgs>(g, R_FDZ, zb, &tot, par);
   launch_fd_z_batch(fz, tot, stage_z, lds_z, st);
-  auto p2 = table<FdPlaneArgs>(g, R_PLANE2, pb, &tot);
+  auto p2 = table<FdPlaneArgs>(g, R_PLANE2, pb, &tot, par);
   launch_fd_plane_batch(p2, tot, mode, lds_p, st);
   auto sb = [](const ks_system* s) { return scalar_blocks(s->n); };
-  auto xc = table<XcArgs>(g, R_XC, sb, &tot);
+  auto xc = table<XcArgs>(g, R_XC, sb, &tot, par);
   launch_xc_batch(xc, tot, st);
   // the members of a group agree on whether the Hamiltonian forms the [X, G] Gram blocks
   const bool hxg = hx_fuses_gram(g[0]->s->p);
   auto hxb = [hxg](const ks_system* s) {
     return hxg ? hx_gram_blocks(s->n) : hx_blocks(s->n, s->p);
   };
-  auto hx = table<HxArgs<T>>(g, R_HX, hxb, &tot);
+  auto hx = table<HxArgs<T>>(g, R_HX, hxb, &tot, par);
   launch_hx_batch<T>(hx, tot, hxg, st);
   auto gb = [](const ks_system* s) { return s->gram_nchunks; };
   auto rb = [](const ks_system* s) { return gram_reduce_blocks(s->pp); };
   if (!hxg) {
-    auto g1 = table<GramArgs<T>>(g, R_GRAM1, gb, &tot);
+    auto g1 = table<GramArgs<T>>(g, R_GRAM1, gb, &tot, par);
     launch_gram_batch<T>(g1, pp, kGramAA | kGramAB, tot, st);
   }
-  auto r1 = table<GramReduceArgs>(g, R_RED1, rb, &tot);
+  auto r1 = table<GramReduceArgs>(g, R_RED1, rb, &tot, par);
   launch_gram_reduce_batch(r1, tot, st);
-  auto gd = table<CombineArgs>(g, R_GRAD, cb, &tot);
+  auto gd = table<CombineArgs>(g, R_GRAD, cb, &tot, par);
   launch_combine_grad_batch<T>(gd, pp, tot, st);
-  auto r2 = table<GramReduceArgs>(g, R_RED2, rb, &tot);
+  auto r2 = table<GramReduceArgs>(g, R_RED2, rb, &tot, par);
   launch_gram_reduce_batch(r2, tot, st);
-  launch_finish_eval_batch(table<FinishEvalArgs>(g, R_FINISH, one, &tot), st);
+  launch_finish_eval_batch(table<FinishEvalArgs>(g, R_FINISH, one, &tot, par), st);
 }
 
 }  // namespace
@@ -1515,6 +1531,10 @@ BatchEngine* batch_create(hipStream_t st) {
 void batch_destroy(BatchEngine* e) {
   if (!e) return;
   if (e->ev) (void)hipEventDestroy(e->ev);
+  if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
+  if (e->par_dev) (void)hipFree(e->par_dev);
+  if (e->par_host) (void)hipHostFree(e->par_host);
+  if (e->cap_st) (void)hipStreamDestroy(e->cap_st);
   for (auto* m : e->act) delete m;
   for (auto* m : e->fin) delete m;
   delete e;
@@ -1548,6 +1568,51 @@ int batch_add(BatchEngine* e, ks_system* s, void* X, const ks_opt_params* o, voi
   return KS_OK;
 }
 
+// The trial launches and the record gather of a tick as a graph: captured when the ordered
+// membership differs from the captured one, then replayed after the members' current slots
+// are copied to par_dev.
+int batch_replay(BatchEngine* e, const std::vector<std::vector<BatchMember*>>& groups,
+                 const GatherArgs& ga) {
+  ks_system* lead = e->act[0]->s;
+  std::vector<const ks_system*> key;
+  for (auto* m : e->act) key.push_back(m->s);
+  hipError_t he = hipSuccess;
+  if (!e->par_dev) {
+    he = hipMalloc(reinterpret_cast<void**>(&e->par_dev), kMaxBatch * sizeof(int));
+    if (he == hipSuccess)
+      he = hipHostMalloc(reinterpret_cast<void**>(&e->par_host), kMaxBatch * sizeof(int));
+    if (he == hipSuccess) he = hipStreamCreateWithFlags(&e->cap_st, hipStreamNonBlocking);
+    if (he != hipSuccess) return hip_check(lead, he, "batch graph buffers");
+  }
+  int nm = 0;
+  for (auto& g : groups)
+    for (auto* m : g) e->par_host[nm++] = m->s->run.c;
+  he = hipMemcpyAsync(e->par_dev, e->par_host, (size_t)nm * sizeof(int),
+                      hipMemcpyHostToDevice, e->st);
+  if (he == hipSuccess && (!e->gexec || key != e->gkey)) {
+    if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
+    e->gexec = nullptr;
+    e->gkey.clear();
+    hipGraph_t graph = nullptr;
+    he = hipStreamBeginCapture(e->cap_st, hipStreamCaptureModeThreadLocal);
+    if (he == hipSuccess) {
+      int base = 0;
+      for (auto& g : groups) {
+        if (g[0]->s->f32) launch_trial_batch<float>(g, e->cap_st, e->par_dev + base);
+        else launch_trial_batch<double>(g, e->cap_st, e->par_dev + base);
+        base += (int)g.size();
+      }
+      launch_gather(ga, e->cap_st);
+      he = hipStreamEndCapture(e->cap_st, &graph);
+    }
+    if (he == hipSuccess) he = hipGraphInstantiate(&e->gexec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (he == hipSuccess) e->gkey = key;
+  }
+  if (he == hipSuccess) he = hipGraphLaunch(e->gexec, e->st);
+  return hip_check(lead, he, "batch graph replay");
+}
+
 // One trial for every active member; members that stop move to the finished list.
 int batch_tick(BatchEngine* e) {
   if (e->act.empty()) return KS_OK;
@@ -1564,18 +1629,25 @@ int batch_tick(BatchEngine* e) {
       }
     if (!placed) groups.push_back({m});
   }
-  for (auto& g : groups) {
-    if (g[0]->s->f32) launch_trial_batch<float>(g, e->st);
-    else launch_trial_batch<double>(g, e->st);
-  }
-  // the CG and line-search records of all members in one copy
+  // the CG and line-search records of all members come back in one copy
   ks_system* lead = e->act[0]->s;
   GatherArgs ga{};
   ga.S = (int)e->act.size();
   ga.bytes = kGatherBytes;
   for (int i = 0; i < ga.S; ++i) ga.src[i] = reinterpret_cast<const char*>(e->act[i]->s->cg);
   ga.dst = lead->gstage;
-  launch_gather(ga, e->st);
+  bool replay = true;
+  for (auto* m : e->act) replay = replay && m->s->graphs && m->queued;
+  if (replay) {
+    const int rc0 = batch_replay(e, groups, ga);
+    if (rc0) return rc0;
+  } else {
+    for (auto& g : groups) {
+      if (g[0]->s->f32) launch_trial_batch<float>(g, e->st);
+      else launch_trial_batch<double>(g, e->st);
+    }
+    launch_gather(ga, e->st);
+  }
   char* hstage = static_cast<char*>(lead->host) + 1024;
   hipError_t he = hipMemcpyAsync(hstage, lead->gstage, (size_t)ga.S * kGatherBytes,
                                  hipMemcpyDeviceToHost, e->st);

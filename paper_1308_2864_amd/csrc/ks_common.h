@@ -226,7 +226,19 @@ struct BatchPtrs {
   int S;
   int off[kMaxBatch + 1];
   const A* a[kMaxBatch];
+  // With par: a[s] is the slot-0 record of system s and its record for the current slot
+  // par[s] (device memory, read at run time) lies par[s] * rstride bytes further, so that a
+  // captured launch serves every slot pattern.
+  const int* par;
+  int rstride;
 };
+
+template <typename A>
+__device__ inline const A& batch_arg(const BatchPtrs<A>& b, int s) {
+  const char* p = reinterpret_cast<const char*>(b.a[s]);
+  if (b.par) p += (size_t)b.par[s] * b.rstride;
+  return *reinterpret_cast<const A*>(p);
+}
 
 __device__ inline int batch_system(const int* off, int S, int b) {
   int s = 0;
@@ -512,6 +524,12 @@ void set_thread_error(const char* msg);
 // device (or managed) memory; a query the runtime refuses leaves no pending error.
 bool device_range(const void* ptr, size_t bytes);
 int q1_apply_blocks(Grid g, int p);
+
+// Raises kernel k's dynamic-LDS limit to bytes the first time it is asked for that kernel
+// and does nothing afterwards (each call site always asks the same value), so launches
+// made later, for instance while a stream is being captured into a graph, issue no
+// runtime call besides the launch.  Thread-safe.
+void set_dyn_lds_once(const void* k, int bytes);
 
 // dense kernels (kernels_dense.hip)
 // Argument records of the Gram kernels (see BatchPtrs).

@@ -36,10 +36,13 @@ def _lone(K, spec, prec, prm):
     return r, X.cpu().numpy()
 
 
+@pytest.mark.parametrize("graphs", [False, True])
 @pytest.mark.parametrize("tau0", [1e-3, 20.0])
-def test_batch_equals_lone_runs_bitwise(tau0):
+def test_batch_equals_lone_runs_bitwise(tau0, graphs):
     """tau0 = 20: first steps far too long, rejected and backtracked (the QR factors queued
-    behind each tick's record copy then take the current points' blocks)."""
+    behind each tick's record copy then take the current points' blocks).  graphs: every
+    member has graphs enabled, so the ticks are captured per membership and replayed with
+    the members' slots read from device memory; the lone runs stay eager."""
     K = ks()
     prm = K.ks_default_params(max_iter=300, tau0=tau0)
     specs = _specs()
@@ -48,6 +51,8 @@ def test_batch_equals_lone_runs_bitwise(tau0):
     for spec, prec in zip(specs, precs):
         systems.append(K.system_from_spec(spec, hartree_solver=K.KS_HARTREE_PCG_FD,
                                           precision=prec))
+        if graphs:
+            systems[-1].ks_enable_graphs(True)
         dt = torch.float32 if prec == K.KS_PREC_FP32 else torch.float64
         blocks.append(torch.tensor(synth.make_x0(spec, 1), dtype=dt, device="cuda"))
     torch.cuda.synchronize()
