@@ -925,8 +925,13 @@ __global__ __launch_bounds__(256) void k_gram_wide_reduce(WideReduceArgs a) {
   if (a.W && prod == 1) a.W[(size_t)j * pp + i] = -s;
 }
 
+// Two blocks per CU (256 registers per lane) so that one block's epilogue and slab loads
+// overlap the other's products; the gradient form (four more operands in its epilogue)
+// and the fp32-matrix-core form (fp32 and FP64 accumulators) do not fit and run one
+// block per CU.
 template <typename T, bool kHasY, bool kHasC0, bool kGrad, bool kVec, bool kMc = false>
-__global__ __launch_bounds__(256) void k_combine_wide(CombineArgs a, int nct) {
+__global__ __launch_bounds__(256, (kMc || kGrad) ? 1 : 2) void k_combine_wide(CombineArgs a,
+                                                                             int nct) {
   static_assert(!kMc || std::is_same<T, float>::value, "fp32 matrix cores take float data");
   using WT = typename std::conditional<kMc, float, double>::type;  // staged weights
   __shared__ WT wl[2][kWK * kWT];
@@ -1082,12 +1087,13 @@ __global__ __launch_bounds__(256) void k_combine_wide(CombineArgs a, int nct) {
         const int row = roww + 16 * t + (kMc ? 4 * q + r : q + 4 * r);
         const bool rok = row < n;
         const size_t roff = (size_t)(rok ? row : 0) * ld;
+        // the row's operands are all loaded before its first store (a store between loads
+        // would make each load wait for the one before)
         T c0v[8], xv[8], xkv[8], dkv[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const int col = J0 + 16 * u + c;
-          const bool ok = rok && col < p;
-          const size_t idx = ok ? roff + col : 0;
+          const size_t idx = rok && col < p ? roff + col : 0;
           if constexpr (kHasC0) c0v[u] = C0[idx];
           if constexpr (kGrad) {
             xv[u] = X[idx];
