@@ -816,7 +816,7 @@ __global__ __launch_bounds__(256) void k_gram_wide(WideGramArgs a) {
   d4 acc[16];
 #pragma unroll
   for (int t = 0; t < 16; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-  constexpr int kU = 2;  // row groups per batch; two batches in flight
+  constexpr int kU = sizeof(T) == 4 ? 4 : 3;  // row groups per batch; two batches in flight
   struct Batch {
     T l[kU][4], r[kU][4];
   };
