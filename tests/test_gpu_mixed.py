@@ -138,7 +138,7 @@ def _devf(a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
 
 
-@pytest.mark.parametrize("p", [80, 130, 200])
+@pytest.mark.parametrize("p", [80, 97, 130, 200])
 def test_fp32_mfma_combine_within_chain_bound(p):
     """KS_PREC_FP32_MFMA runs the block combines of blocks wider than 64 columns on the fp32
     matrix cores (weights rounded to float, fp32 sums over chains of 64 contraction

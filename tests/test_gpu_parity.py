@@ -71,9 +71,10 @@ def test_gram_blocks(p):
         assert np.max(np.abs(g - ref)) <= 1e-13 * np.max(np.abs(ref)) * math.sqrt(spec.n)
 
 
-@pytest.mark.parametrize("p", [80, 130])
+@pytest.mark.parametrize("p", [80, 97, 130, 257])
 def test_gram_blocks_wide(p):
-    """More than 64 columns: the products run as 64-column sub-products (ragged last block)."""
+    """More than 64 columns: one launch forms the products on 128 x 128 output tiles over
+    row chunks (ragged last tile; odd p takes element loads; n = 1320 rows)."""
     spec = spec_small(12, 11, 10, p=p, seed=p)
     sysg = ks().system_from_spec(spec)
     rng = np.random.default_rng(p)
@@ -292,10 +293,11 @@ def test_retract(kind, p):
 
 
 @pytest.mark.parametrize("kind", ["qr", "wy"])
-@pytest.mark.parametrize("p", [80, 130])
+@pytest.mark.parametrize("p", [80, 97, 130])
 def test_retract_wide(kind, p):
-    """More than 64 columns: the combine accumulates 64-column contraction blocks per output
-    block; the density follows from the finished block."""
+    """More than 64 columns: the persistent combine forms 128-row x 128-column output tiles
+    over weight slabs of 16 contraction rows (n = 1320: a ragged last row tile; odd p takes
+    element loads); the density follows from the finished block."""
     K = ks()
     spec = spec_small(12, 11, 10, p=p, seed=40 + p)
     sysg = K.system_from_spec(spec)
