@@ -313,7 +313,9 @@ __device__ inline int comb_col(int s, int q) { return 8 * (s >> 1) + 2 * q + (s 
 
 // Loads the lane's elements of rows g0 + c (zero outside n x p).  kVec: column pairs as
 // one load (p, ld even, 2-element aligned base).
-template <typename T, int kT, bool kVec>
+// kNT: a stream read here for the last time (non-temporal: it should not displace blocks
+// the next kernels read again from the last-level cache)
+template <typename T, int kT, bool kVec, bool kNT = false>
 __device__ inline void comb_load(const T* __restrict__ base, int ld, int n, int p, int row,
                                  int q, CombineFrag<kT>& f) {
   const bool rok = row < n;
@@ -324,7 +326,10 @@ __device__ inline void comb_load(const T* __restrict__ base, int ld, int n, int 
     if constexpr (kVec) {
       const bool ok = rok && c0 < p;
       typedef T t2 __attribute__((ext_vector_type(2)));
-      const t2 w = *reinterpret_cast<const t2*>(base + (ok ? roff + c0 : 0));
+      const t2* src = reinterpret_cast<const t2*>(base + (ok ? roff + c0 : 0));
+      t2 w;
+      if constexpr (kNT) w = __builtin_nontemporal_load(src);
+      else w = *src;
       f.v[2 * j] = ok ? (double)w[0] : 0.0;
       f.v[2 * j + 1] = ok ? (double)w[1] : 0.0;
     } else {
@@ -397,10 +402,11 @@ __device__ inline void combine_tiles(const CombineArgs& a, double* lds, int t_be
     const int row = tile * 16 + c;
     comb_load<T, kT, kVec>(aX, ld, n, pk, row, q, f.x);
     if constexpr (kHasY) comb_load<T, kT, kVec>(aY, ld, n, pk, row, q, f.y);
-    if constexpr (kHasC0) comb_load<T, kT, kVec>(aC0, ld, n, p, row, q, f.c0);
+    // the gradient form reads G, X_k and D_k for the last time in the trial
+    if constexpr (kHasC0) comb_load<T, kT, kVec, kGrad>(aC0, ld, n, p, row, q, f.c0);
     if constexpr (kGrad) {
-      comb_load<T, kT, kVec>(aXk, ld, n, p, row, q, f.xk);
-      comb_load<T, kT, kVec>(aDk, ld, n, p, row, q, f.dk);
+      comb_load<T, kT, kVec, true>(aXk, ld, n, p, row, q, f.xk);
+      comb_load<T, kT, kVec, true>(aDk, ld, n, p, row, q, f.dk);
     }
   };
   auto compute = [&](const Tile& f, int tile) {
