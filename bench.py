@@ -130,6 +130,82 @@ def cpu_baseline(spec, X0, gpu_iters, iters):
     }
 
 
+def c1_leg(ks, synth, reps=5):
+    """The small configuration (24^3 grid, h = 0.64, p = 4, two nuclei, Section 4.1
+    stopping rules) solved to the end on both sides: the GPU (reps solves from the seeded
+    X0, resident in HBM; the configured plain CG Hartree and the fast-diagonalisation
+    solver) and the FP64 oracle (plain CG) on the host, with all its BLAS threads and with
+    one.  Iterations, time to solution and the energy difference."""
+    import torch
+    import numpy as np
+    from oracle import optm
+    from oracle.ks import KSSystemFD
+    spec = synth.make_config("c1", 0)
+    X0h = synth.make_x0(spec, 0)
+    X0 = torch.tensor(X0h, dtype=torch.float64, device="cuda")
+    prm = ks.ks_default_params()
+
+    def gpu_solve(solver):
+        s = ks.system_from_spec(spec, hartree_solver=solver)
+        X = X0.clone()
+        s.ks_minimize(X, prm, check=False)  # warm-up
+        times, r = [], None
+        for _ in range(reps):
+            X.copy_(X0)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = s.ks_minimize(X, prm, check=False)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t)
+        s.close()
+        return {"s_per_solve": round(min(times), 4), "solves_per_s": round(1.0 / min(times), 2),
+                "iterations": r.iters, "stop": ks.STOP_NAMES[r.stop_reason],
+                "hartree_iters": r.hartree_iters_total, "energy": r.energy}
+
+    # the configured plain CG (every CG iteration is a few launches on a 13824-point grid,
+    # so the solve is launch-bound) and the fast-diagonalisation solver
+    gpu = gpu_solve(ks.KS_HARTREE_CG)
+    gpu_fd = gpu_solve(ks.KS_HARTREE_PCG_FD)
+    print(f"# c1 gpu (cg): {gpu}", file=sys.stderr, flush=True)
+    print(f"# c1 gpu (pcg_fd): {gpu_fd}", file=sys.stderr, flush=True)
+    orc = KSSystemFD(spec.nx, spec.ny, spec.nz, spec.h, spec.lo, spec.p, spec.R, spec.Z,
+                     f=spec.f, rc=spec.rc)
+
+    def progress(k, E, g):
+        if k % 200 == 0:
+            print(f"# c1 oracle k={k} E={E:.10f} |grad|={g:.2e}", file=sys.stderr, flush=True)
+
+    def solve():
+        t = time.perf_counter()
+        res = optm.minimize(orc.energy_grad, np.array(X0h), optm.Params(), callback=progress)
+        return res, time.perf_counter() - t
+
+    out = {"workload": f"{spec.name} (FP64, QR, Section 4.1 stops)", "gpu_cg": gpu,
+           "gpu_pcg_fd": gpu_fd}
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        threadpool_limits, cores = None, os.cpu_count() or 1
+    res, el = solve()
+    out["oracle_all_threads"] = {"cores": int(cores), "s_per_solve": round(el, 2),
+                                 "iterations": res.iters, "stop": res.stop,
+                                 "energy_minus_gpu_Ha": res.E - gpu["energy"]}
+    print(f"# c1 oracle ({cores} threads): {out['oracle_all_threads']}", file=sys.stderr,
+          flush=True)
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            res1, el1 = solve()
+        out["oracle_one_thread"] = {"cores": 1, "s_per_solve": round(el1, 2),
+                                    "iterations": res1.iters, "stop": res1.stop}
+        print(f"# c1 oracle (1 thread): {out['oracle_one_thread']}", file=sys.stderr,
+              flush=True)
+    best_cpu = min(el, out.get("oracle_one_thread", {}).get("s_per_solve", el))
+    out["gpu_speedup_vs_fastest_oracle"] = {"cg": round(best_cpu / gpu["s_per_solve"], 1),
+                                            "pcg_fd": round(best_cpu / gpu_fd["s_per_solve"], 1)}
+    return out
+
+
 def c4_leg(ks, synth, iters, seed, hartree="pcg_fd"):
     """The largest single-system workload (128^3 grid, n = 2097152, p = 512): seconds per
     iteration of Alg. 3 for FP64 and FP32 storage of the orbital blocks and for FP32 storage
@@ -560,6 +636,9 @@ def main():
     ap.add_argument("--fe-converge", type=int, default=0,
                     help="run the finite-element solves to convergence (slow: the 96^3 "
                          "p = 128 system needs more than 6000 iterations)")
+    ap.add_argument("--c1-leg", type=int, default=0,
+                    help="1: also solve the small c1 configuration to the end on the GPU and "
+                         "with the CPU oracle (all threads and one; a few minutes of CPU)")
     ap.add_argument("--c4-iters", type=int, default=5,
                     help="iterations of the 128^3, p = 512 leg (0: skip it)")
     ap.add_argument("--c4-hartree", choices=["cg", "pcg_fd"], default="pcg_fd",
@@ -736,6 +815,7 @@ def main():
     ofdft = None
     if args.of_cells > 0:
         ofdft = of_leg(ks, synth, args.of_cells, args.of_levels, args.of_n0, args.of_margin)
+    c1 = c1_leg(ks, synth) if args.c1_leg else None
     cpu = None
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
@@ -779,6 +859,7 @@ def main():
         "phases": phase_out,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "c1_time_to_solution": c1,
     }
     print(json.dumps(out), flush=True)
 
