@@ -1546,6 +1546,11 @@ int batch_size(const BatchEngine* e) { return (int)e->act.size(); }
 // or that stops at once, goes straight to the finished list.
 int batch_add(BatchEngine* e, ks_system* s, void* X, const ks_opt_params* o, void* tag) {
   if ((int)e->act.size() >= kMaxBatch) return KS_E_INVAL;
+  // a captured tick names its members' buffers: a new member (possibly a new system at the
+  // address of a destroyed one) always means a new capture
+  if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
+  e->gexec = nullptr;
+  e->gkey.clear();
   BatchMember* m = new BatchMember();
   m->s = s;
   m->tag = tag;
