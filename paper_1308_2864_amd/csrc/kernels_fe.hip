@@ -288,28 +288,17 @@ constexpr int kQ1Waves = kQ1Threads / kWave;
 constexpr int kQ1MaxBlocks = 1024;
 constexpr size_t kQ1LdsCap = 150 * 1024;
 
-// v[e] = A[row][k + e] for e < 4, zero beyond n rows or p columns (k is a multiple of 4;
-// with kVec, p is one too and the four entries are in or out together)
-template <typename T, bool kVec>
-__device__ inline void q1_load4(const T* __restrict__ A, size_t row, int n, int p, int k,
-                                double v[4]) {
-  if (kVec) {
-    if (row < (size_t)n && k < p) {
-      const T* q = A + row * p + k;
+// v[e] = A[row][k + e] for e < 4 as stored, from a clamped address (row 0 past n, entry 0
+// of the row past p): no guard and no select, so a prefetch into v stays in flight
+template <typename T>
+__device__ inline void q1_load4_raw(const T* __restrict__ A, size_t row, int n, int p, int k,
+                                    T v[4]) {
+  const size_t r0 = (row < (size_t)n ? row : 0) * p;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) v[e] = (double)q[e];
-    } else {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) v[e] = 0.0;
-    }
-  } else {
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-      v[e] = (row < (size_t)n && k + e < p) ? (double)A[row * p + k + e] : 0.0;
-  }
+  for (int e = 0; e < 4; ++e) v[e] = A[r0 + (k + e < p ? k + e : 0)];
 }
 
-template <typename T, bool kVec>
+template <typename T>
 __global__ __launch_bounds__(kQ1Threads) void k_q1_grad(Q1GradArgs a) {
   extern __shared__ double Ws[];
   __shared__ double sh[4][kQ1Waves];
@@ -353,57 +342,77 @@ __global__ __launch_bounds__(kQ1Threads) void k_q1_grad(Q1GradArgs a) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) ax[t] = ab[t] = d4{0.0, 0.0, 0.0, 0.0};
     const size_t row = g0 + lr;
-    double xa[4], ba[4];
-    q1_load4<T, kVec>(X, row, n, p, 4 * lq, xa);
-    q1_load4<T, kVec>(BX, row, n, p, 4 * lq, ba);
+    // Operand loads are unconditional and select nothing (a guarded or selected load makes
+    // the compiler wait for it before the current slice's products): rows past n read row
+    // 0 (their products land in rows that are never stored) and entries past p read the
+    // row's first entry, which meets the zero rows of the staged weights.
+    T xa[4], ba[4];
+    q1_load4_raw<T>(X, row, n, p, 4 * lq, xa);
+    q1_load4_raw<T>(BX, row, n, p, 4 * lq, ba);
     for (int k0 = 0; k0 < pp; k0 += 16) {
-      const bool more = k0 + 16 < pp;
-      double xn[4], bn[4];
-      if (more) {
-        q1_load4<T, kVec>(X, row, n, p, k0 + 16 + 4 * lq, xn);
-        q1_load4<T, kVec>(BX, row, n, p, k0 + 16 + 4 * lq, bn);
-      }
+      const int kn = k0 + 16 < pp ? k0 + 16 : k0;  // the last slice reloads itself
+      T xn[4], bn[4];
+      q1_load4_raw<T>(X, row, n, p, kn + 4 * lq, xn);
+      q1_load4_raw<T>(BX, row, n, p, kn + 4 * lq, bn);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const double* wr = Ws + (size_t)(k0 + 4 * lq + e) * wc + c0 + lr;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const double w = wr[16 * t];
-          ax[t] = mfma16(xa[e], w, ax[t]);
-          ab[t] = mfma16(ba[e], w, ab[t]);
+          ax[t] = mfma16((double)xa[e], w, ax[t]);
+          ab[t] = mfma16((double)ba[e], w, ab[t]);
         }
       }
-      if (more) {
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          xa[e] = xn[e];
-          ba[e] = bn[e];
-        }
+      for (int e = 0; e < 4; ++e) {
+        xa[e] = xn[e];
+        ba[e] = bn[e];
       }
     }
-    // one column tile at a time keeps the epilogue's loads few in flight
+    // one column tile at a time keeps the epilogue's loads few in flight; the four rows of
+    // a tile are loaded together (clamped addresses, no guard) before any of them is used
     const int ntv = min(4, (p - c0 + 15) / 16);  // tiles holding columns below p
 #pragma unroll 1
     for (int t = 0; t < ntv; ++t) {
       const d4 vx = t == 0 ? ax[0] : t == 1 ? ax[1] : t == 2 ? ax[2] : ax[3];
       const d4 vb = t == 0 ? ab[0] : t == 1 ? ab[1] : t == 2 ? ab[2] : ab[3];
       const int j = c0 + 16 * t + lr;
+      size_t o[4];
+      bool ok[4];
+      T gt[4], gg[4], x[4], xc[4], bx[4], bxc[4], dc[4], bdc[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const size_t g = g0 + lq + 4 * r;
-        if (g >= (size_t)n || j >= p) continue;
-        const size_t o = g * p + j;
-        const T dT = (T)((double)Gt[o] + vx[r]);
-        const T bT = (T)((double)G[o] + vb[r]);
-        D[o] = dT;
-        BD[o] = bT;
+        ok[r] = g < (size_t)n && j < p;
+        o[r] = ok[r] ? g * p + j : 0;
+        gt[r] = Gt[o[r]];
+        gg[r] = G[o[r]];
+        if (ref) {
+          x[r] = X[o[r]];
+          xc[r] = Xc[o[r]];
+          bx[r] = BX[o[r]];
+          bxc[r] = BXc[o[r]];
+          dc[r] = Dc[o[r]];
+          bdc[r] = BDc[o[r]];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (!ok[r]) continue;
+        const T dT = (T)((double)gt[r] + vx[r]);
+        const T bT = (T)((double)gg[r] + vb[r]);
+        D[o[r]] = dT;
+        BD[o[r]] = bT;
         const double d = (double)dT, bd = (double)bT;
         dd += d * bd;
         if (ref) {
-          const double sdx = (double)X[o] - (double)Xc[o];
-          const double bs = (double)BX[o] - (double)BXc[o];
-          const double y = d - (double)Dc[o];
-          const double by = bd - (double)BDc[o];
+          const double sdx = (double)x[r] - (double)xc[r];
+          const double bs = (double)bx[r] - (double)bxc[r];
+          const double y = d - (double)dc[r];
+          const double by = bd - (double)bdc[r];
           ss += sdx * bs;
           sy += sdx * by;
           yy += y * by;
@@ -494,20 +503,13 @@ void launch_q1_grad(const Q1GradArgs& a, hipStream_t st) {
   const int nb = q1_grad_blocks(a.n, a.p);
   const size_t lds = q1_grad_lds(a.p);
   // the limit set does not depend on p, so concurrent callers agree on it
-  const bool vec = a.p % 4 == 0;
-  const void* k = a.f32 ? (vec ? reinterpret_cast<const void*>(k_q1_grad<float, true>)
-                               : reinterpret_cast<const void*>(k_q1_grad<float, false>))
-                        : (vec ? reinterpret_cast<const void*>(k_q1_grad<double, true>)
-                               : reinterpret_cast<const void*>(k_q1_grad<double, false>));
+  const void* k = a.f32 ? reinterpret_cast<const void*>(k_q1_grad<float>)
+                        : reinterpret_cast<const void*>(k_q1_grad<double>);
   if (lds > 65536) set_dyn_lds_once(k, (int)kQ1LdsCap);
-  if (a.f32 && vec)
-    hipLaunchKernelGGL((k_q1_grad<float, true>), dim3(nb), dim3(kQ1Threads), lds, st, a);
-  else if (a.f32)
-    hipLaunchKernelGGL((k_q1_grad<float, false>), dim3(nb), dim3(kQ1Threads), lds, st, a);
-  else if (vec)
-    hipLaunchKernelGGL((k_q1_grad<double, true>), dim3(nb), dim3(kQ1Threads), lds, st, a);
+  if (a.f32)
+    hipLaunchKernelGGL(k_q1_grad<float>, dim3(nb), dim3(kQ1Threads), lds, st, a);
   else
-    hipLaunchKernelGGL((k_q1_grad<double, false>), dim3(nb), dim3(kQ1Threads), lds, st, a);
+    hipLaunchKernelGGL(k_q1_grad<double>, dim3(nb), dim3(kQ1Threads), lds, st, a);
 }
 
 template void launch_q1_apply<double>(const double*, double*, double*, const double*, Grid,
