@@ -798,8 +798,15 @@ __device__ inline fx4 mfma16f(float a, float b, fx4 c) {
 // for the loads in flight.)
 constexpr int kMcSlabs = 4;  // 4 weight slabs = 64 contraction indices per fp32 chain
 
+// The block stages slabs of kGramSlab rows of its two column blocks (L[:, I], R[:, J]:
+// 16 x 256 values) in LDS, double buffered: thread t loads column t of every row of the
+// next slab (coalesced, 16 loads in flight per thread) while the wavefronts multiply the
+// current one from LDS, so a whole slab's MFMA time covers the loads.
+constexpr int kGramSlab = 16;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_gram_wide(WideGramArgs a) {
+__global__ __launch_bounds__(256, 2) void k_gram_wide(WideGramArgs a) {
+  __shared__ double sl[2][kGramSlab][2 * kWT];
   const int lb = xcd_remap(blockIdx.x, gridDim.x);  // the tiles of one chunk share an XCD
   const int chunk = lb / a.ntiles, tile = lb % a.ntiles;
   const int prod = a.tp[tile];
@@ -808,69 +815,63 @@ __global__ __launch_bounds__(256) void k_gram_wide(WideGramArgs a) {
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int q = lane / 16, c = lane % 16;
   const int ld = a.ld, n = a.n, p = a.p;
-  const int ci = a.ti[tile] * kWT + 64 * (w >> 1) + c;  // L column of fragment 0
-  const int cj = a.tj[tile] * kWT + 64 * (w & 1) + c;   // R column of fragment 0
   const int ngroups = (n + 3) / 4;
   const int per = (ngroups + a.nch - 1) / a.nch;
-  const int g_beg = chunk * per, g_end = min(ngroups, g_beg + per);
-  bool oki[4], okj[4];
+  const int r_beg = 4 * min(ngroups, chunk * per);
+  const int r_end = min(n, 4 * min(ngroups, chunk * per + per));
+  const int nslab = (r_end - r_beg + kGramSlab - 1) / kGramSlab;
+  // staging: thread t owns slab column t (L side below 128, R side above)
+  const int t = threadIdx.x;
+  const T* __restrict__ S = t < kWT ? L : R;
+  const int scol = (t < kWT ? a.ti[tile] : a.tj[tile]) * kWT + (t % kWT);
+  const bool cok = scol < p;
+  const int scl = cok ? scol : 0;
+  auto load = [&](T (&v)[kGramSlab], int sidx) {
+    const int r0 = r_beg + sidx * kGramSlab;
 #pragma unroll
-  for (int f = 0; f < 4; ++f) {
-    oki[f] = ci + 16 * f < p;
-    okj[f] = cj + 16 * f < p;
-  }
+    for (int u = 0; u < kGramSlab; ++u) {
+      const int row = r0 + u;
+      v[u] = S[(size_t)(row < r_end ? row : r_beg) * ld + scl];  // raw, clamped
+    }
+  };
+  auto store = [&](const T (&v)[kGramSlab], int sidx, int buf) {
+    const int r0 = r_beg + sidx * kGramSlab;
+#pragma unroll
+    for (int u = 0; u < kGramSlab; ++u)
+      sl[buf][u][t] = (cok && r0 + u < r_end) ? (double)v[u] : 0.0;
+  };
   d4 acc[16];
 #pragma unroll
-  for (int t = 0; t < 16; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-  constexpr int kU = sizeof(T) == 4 ? 4 : 3;  // row groups per batch; two batches in flight
-  struct Batch {
-    T l[kU][4], r[kU][4];
-  };
-  auto load = [&](Batch& b, int g0) {
+  for (int i = 0; i < 16; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+  const int li = 64 * (w >> 1) + c, rj = kWT + 64 * (w & 1) + c;
+  if (nslab > 0) {
+    T v[kGramSlab];
+    load(v, 0);
+    store(v, 0, 0);
+    __syncthreads();
+    for (int si = 0; si < nslab; ++si) {
+      const int sn = si + 1 < nslab ? si + 1 : si;  // the last slab reloads itself
+      load(v, sn);
+      __builtin_amdgcn_sched_barrier(0);
+      const double(*b)[2 * kWT] = sl[si & 1];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int row = 4 * (g0 + u) + q;
-      const bool rok = g0 + u < g_end && row < n;
-      const size_t roff = (size_t)(rok ? row : 0) * ld;
+      for (int g = 0; g < kGramSlab / 4; ++g) {
+        const int row = 4 * g + q;
+        double fl[4], fr[4];
 #pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        // branch-free: clamped address, then select (a guarded load would make the
-        // compiler wait for every load in flight before the products)
-        const bool ol = rok && oki[f], orr = rok && okj[f];
-        const T vl = L[ol ? roff + ci + 16 * f : 0];
-        const T vr = R[orr ? roff + cj + 16 * f : 0];
-        b.l[u][f] = ol ? vl : T(0);
-        b.r[u][f] = orr ? vr : T(0);
+        for (int f = 0; f < 4; ++f) {
+          fl[f] = b[row][li + 16 * f];
+          fr[f] = b[row][rj + 16 * f];
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) acc[4 * x + y] = mfma16(fl[x], fr[y], acc[4 * x + y]);
       }
+      __builtin_amdgcn_sched_barrier(0);
+      if (si + 1 < nslab) store(v, sn, (si + 1) & 1);
+      __syncthreads();
     }
-  };
-  auto products = [&](const Batch& b, int g0) {
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      if (g0 + u >= g_end) break;
-      double fl[4], fr[4];
-#pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        fl[f] = (double)b.l[u][f];
-        fr[f] = (double)b.r[u][f];
-      }
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[4 * x + y] = mfma16(fl[x], fr[y], acc[4 * x + y]);
-    }
-  };
-  int g0 = g_beg;
-  Batch f0, f1;
-  if (g0 < g_end) load(f0, g0);
-  while (g0 < g_end) {
-    if (g0 + kU < g_end) load(f1, g0 + kU);
-    products(f0, g0);
-    g0 += kU;
-    if (g0 >= g_end) break;
-    if (g0 + kU < g_end) load(f0, g0 + kU);
-    products(f1, g0);
-    g0 += kU;
   }
   double* o = a.part + (size_t)lb * kWT * kWT;
   const int r0 = 64 * (w >> 1), c0 = 64 * (w & 1);
