@@ -717,7 +717,7 @@ int gram_chunks(int n, int pp) {
 }
 
 // partial tiles of the Gram launches and of the gradient combine's fused Gram tiles (blocks
-// wider than 64 columns reduce 64-column sub-products one at a time)
+// wider than 64 columns: the partial 128 x 128 tiles of the wide Gram)
 size_t wide_gram_part_doubles(int n);
 
 size_t gram_part_doubles(int n, int pp) {
@@ -753,7 +753,7 @@ int combine_blocks(int n) {
 
 // ---- blocks wider than 64 columns ------------------------------------------------------
 // Output tiles of 128 x 128, so that every operand value loaded feeds 128 products (the
-// 64-column kernels above feed 64, which leaves a p = 512 product bound by HBM).
+// 64-column products feed 64, which leaves a p = 512 product bound by HBM).
 //
 // Gram: one launch forms every requested product.  Block b owns one output tile of one
 // product over one chunk of grid rows; its four wavefronts own the four 64 x 64 quarters

@@ -223,7 +223,7 @@ void layout(ks_system* s, char* base, size_t* total) {
   s->work = c.take<double>(small_work_doubles(s->p));
   s->gram_nchunks = gram_chunks(s->n, s->pp);
   s->gram_part = c.take<double>(gram_part_doubles(s->n, s->pp));
-  s->gsub = c.take<double>(3 * 64 * 64);  // one reduced 64-column sub-product (p > 64)
+  s->gsub = c.take<double>(3 * 64 * 64);  // one reduced 64-column bf16 sub-product (p > 64)
   s->spart = c.take<double>((size_t)SL_COUNT * kPartStride);
   s->cgpart = c.take<double>(hartree_part_doubles());
   s->cg = c.take<CgState>(1);
@@ -409,8 +409,8 @@ void gram(ks_system* s, const void* A, const void* B, int mask) {
 }
 
 // Gram products of [A, B] (mask) reduced into out (and W = -(A^T B)^T with W); blocks wider
-// than 64 columns run as 64-column sub-products.
-// sym_ab: A^T B is symmetric (X^T B X, D^T B D); beyond 64 columns only its blocks I <= J
+// than 64 columns run on 128 x 128 output tiles (bf16 products: 64-column sub-products).
+// sym_ab: A^T B is symmetric (X^T B X, D^T B D); beyond 64 columns only its tiles I <= J
 // are formed and mirrored
 // KS_PREC_MIXED_BF16 takes A^T B (the calls marked bf16_ok: X^T G) on the bf16 matrix
 // cores; every other product stays exact.  X^T G sets only the weights W = -(X^T G)^T of

@@ -586,8 +586,8 @@ void launch_combine(const CombineArgs& a, hipStream_t st);
 // Events for the next single-kernel combine launch of this host thread: that launch records
 // them from its own dispatch (its exact start and end), and clears them.
 void set_launch_events(hipEvent_t start, hipEvent_t stop);
-// Blocks of scalar partials a combine launch sequence writes per slot (more than one set
-// of blocks when p > 64: one per 64-column output block).
+// Blocks of scalar partials a combine launch writes per slot (the persistent blocks of the
+// wide combine when p > 64).
 int combine_partial_blocks(int n, int p);
 // Reduced Gram products (mask over A^T A, A^T B, B^T B) of blocks wider than 64 columns,
 // written into out (3 x p_p x p_p, products outside the mask untouched) and, with W,

@@ -35,7 +35,7 @@ def oracle_q1(spec, **kw):
     return KSSystemQ1(spec.nx, spec.ny, spec.nz, spec.h, spec.lo, spec.p, spec.R, spec.Z, **args)
 
 
-# Systems with blocks wider than 64 columns (the 64-column sub-block products and, with
+# Systems with blocks wider than 64 columns (the 128 x 128-tile wide kernels and, with
 # KS_PREC_MIXED_BF16, the bf16 X^T G): (N, p, nuclei, seed) on [-8, 8]^3.
 WIDE = {80: (14, 80, 4, 5), 130: (16, 130, 6, 5)}
 

@@ -46,7 +46,7 @@ def test_workspace_sizing_and_descriptor_validation():
     # bigger p, bigger workspace
     d2 = ks.make_desc(24, 24, 24, 0.64, (-8, -8, -8), 32, [[0, 0, 0]], [2])
     assert ks.ks_workspace_bytes(d2) > nb
-    # blocks of up to 512 orbitals (wider than 64 run as 64-column sub-blocks)
+    # blocks of up to 512 orbitals (wider than 64 take the 128 x 128-tile kernels)
     assert ks.ks_workspace_bytes(ks.make_desc(8, 8, 8, 0.5, (0, 0, 0), 65)) > 0
     assert ks.ks_workspace_bytes(ks.make_desc(16, 16, 16, 0.5, (0, 0, 0), 512)) > 0
     for bad in (dict(p=0), dict(p=513), dict(nx=0), dict(h=0.0), dict(f=0.0)):

@@ -254,9 +254,9 @@ def test_q1_minimize_matches_oracle(solver):
 
 @pytest.mark.parametrize("p", [80, 128])
 def test_q1_minimize_wide_p_first_steps_match_oracle(p):
-    """p = 80 (a full 64-column block and a ragged one) and p = 128 (two full column groups
-    of the MFMA gradient, the wide factor in LDS): five steps of Alg. 3 in the B metric
-    against the oracle's five."""
+    """p = 80 (one ragged 128-column tile of the wide kernels) and p = 128 (one full tile,
+    two full column groups of the MFMA gradient, the wide factor in LDS): five steps of
+    Alg. 3 in the B metric against the oracle's five."""
     K = ks()
     spec = fe_spec(16, 14, 13, p=p, M=6, seed=12, h=0.6)
     orc = oracle_q1(spec)

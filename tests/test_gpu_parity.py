@@ -436,9 +436,9 @@ def test_minimize_p32_first_steps_match_oracle(kind):
 
 @pytest.mark.parametrize("kind", ["qr", "wy"])
 def test_minimize_wide_p_first_steps_match_oracle(kind):
-    """p = 100 (two 64-column blocks, the second ragged): six steps of Alg. 3 against the
-    oracle's six steps (Gram sub-products, tiled combines, the one-workgroup factorisations
-    for p > 64)."""
+    """p = 100 (one ragged 128-column tile of the wide kernels): six steps of Alg. 3 against
+    the oracle's six steps (wide Gram and combine, the one-workgroup factorisations for
+    p > 64)."""
     K = ks()
     spec = synth.make_system(14, 13, 12, 0.6, 100, 8, seed=6, zrange=(2, 4), margin=1.5,
                              min_spacing=1.0)
@@ -458,7 +458,7 @@ def test_minimize_wide_p_first_steps_match_oracle(kind):
 
 
 def test_minimize_p512_first_steps_match_oracle():
-    """p = 512, the widest block (eight 64-column blocks; the factor in global memory):
+    """p = 512, the widest block (four 128-column tiles; the factor in global memory):
     three steps of Alg. 3 against the oracle's three on a 16^3 grid."""
     K = ks()
     spec = synth.make_system(16, 16, 16, 0.6, 512, 8, seed=9, zrange=(2, 4), margin=1.5,
@@ -654,7 +654,7 @@ def devf(a):
 def test_fp32_energy_grad_matches_oracle_on_rounded_input(p):
     """Energies are computed in FP64 from the FP32 data, so they match the oracle applied to
     the FP32-rounded X to FP64 accuracy; G and grad E are rounded to FP32 on store.  p = 100
-    takes the 64-column sub-block Gram and combine kernels in FP32 storage."""
+    takes the wide Gram and combine kernels in FP32 storage."""
     K = ks()
     spec = spec_small(p=p, seed=50)
     X = synth.make_x0(spec, 4).astype(np.float32)
@@ -694,7 +694,7 @@ def test_fp32_retract_matches_oracle_on_rounded_input(kind, p):
 
 
 def test_fp32_wide_p_first_steps_track_oracle():
-    """FP32 storage at p = 100 (64-column sub-blocks, X^T D from the reduced blocks): four
+    """FP32 storage at p = 100 (wide kernels, X^T D as a Gram pass of the stored D): four
     steps of Alg. 3 from the float-rounded start stay within the float rounding of the FP64
     oracle's four steps (each retraction rounds X to float: ~6e-8 relative)."""
     K = ks()
