@@ -1248,6 +1248,16 @@ void launch_gather(const GatherArgs& g, hipStream_t st) {
   hipLaunchKernelGGL(k_gather, dim3(g.S), dim3(64), 0, st, g);
 }
 
+namespace {
+__global__ void k_set_ints(int* __restrict__ dst, IntList l) {
+  if ((int)threadIdx.x < l.n) dst[threadIdx.x] = l.v[threadIdx.x];
+}
+}  // namespace
+
+void launch_set_ints(int* dst, const IntList& l, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_ints, dim3(1), dim3(64), 0, st, dst, l);
+}
+
 
 void set_dyn_lds_once(const void* k, int bytes) {
   static std::mutex mu;

@@ -100,6 +100,7 @@ struct ks_system {
   // staging area for the scalar records of a whole batch (used when this system leads)
   char* rec = nullptr;
   char* gstage = nullptr;
+  int* slots = nullptr;  // record slots of the members of a replayed batch tick (lead only)
   void *Gt[2] = {}, *BX[2] = {}, *BD[2] = {};
   double* feg[2] = {};
   // the Cayley system of the B metric per slot: [X^T B X, X^T G, G^T B^{-1} G]
@@ -232,6 +233,7 @@ void layout(ks_system* s, char* base, size_t* total) {
   s->reorth_count = c.take<int>(1);
   s->rec = c.take<char>(kRecBytes);
   s->gstage = c.take<char>((size_t)kMaxBatch * kGatherBytes);
+  s->slots = c.take<int>(kMaxBatch);
   *total = c.off + 256;
 }
 
@@ -1412,12 +1414,10 @@ struct BatchEngine {
   std::vector<BatchMember*> fin;
   // Graph replay of a tick's trial launches (every member has graphs enabled and its
   // factor queued): captured for one ordered membership and replayed while it lasts; the
-  // launches find each member's records through its current slot in par_dev.
+  // launches find each member's records through its current slot, kept in the lead
+  // member's workspace (slots) and captured on the lead's capture stream.
   hipGraphExec_t gexec = nullptr;
   std::vector<const ks_system*> gkey;
-  int* par_dev = nullptr;
-  int* par_host = nullptr;       // pinned staging of par_dev
-  hipStream_t cap_st = nullptr;  // capture stream (the engine stream may be the null stream)
 };
 
 namespace {
@@ -1532,9 +1532,6 @@ void batch_destroy(BatchEngine* e) {
   if (!e) return;
   if (e->ev) (void)hipEventDestroy(e->ev);
   if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
-  if (e->par_dev) (void)hipFree(e->par_dev);
-  if (e->par_host) (void)hipHostFree(e->par_host);
-  if (e->cap_st) (void)hipStreamDestroy(e->cap_st);
   for (auto* m : e->act) delete m;
   for (auto* m : e->fin) delete m;
   delete e;
@@ -1575,40 +1572,34 @@ int batch_add(BatchEngine* e, ks_system* s, void* X, const ks_opt_params* o, voi
 
 // The trial launches and the record gather of a tick as a graph: captured when the ordered
 // membership differs from the captured one, then replayed after the members' current slots
-// are copied to par_dev.
+// are written to the lead member's slot array.  The membership key holds the lead, so a
+// replayed graph always reads the slot array it was captured with.
 int batch_replay(BatchEngine* e, const std::vector<std::vector<BatchMember*>>& groups,
                  const GatherArgs& ga) {
   ks_system* lead = e->act[0]->s;
   std::vector<const ks_system*> key;
   for (auto* m : e->act) key.push_back(m->s);
-  hipError_t he = hipSuccess;
-  if (!e->par_dev) {
-    he = hipMalloc(reinterpret_cast<void**>(&e->par_dev), kMaxBatch * sizeof(int));
-    if (he == hipSuccess)
-      he = hipHostMalloc(reinterpret_cast<void**>(&e->par_host), kMaxBatch * sizeof(int));
-    if (he == hipSuccess) he = hipStreamCreateWithFlags(&e->cap_st, hipStreamNonBlocking);
-    if (he != hipSuccess) return hip_check(lead, he, "batch graph buffers");
-  }
-  int nm = 0;
+  IntList sl{};
   for (auto& g : groups)
-    for (auto* m : g) e->par_host[nm++] = m->s->run.c;
-  he = hipMemcpyAsync(e->par_dev, e->par_host, (size_t)nm * sizeof(int),
-                      hipMemcpyHostToDevice, e->st);
+    for (auto* m : g) sl.v[sl.n++] = m->s->run.c;
+  launch_set_ints(lead->slots, sl, e->st);
+  hipError_t he = hipGetLastError();
   if (he == hipSuccess && (!e->gexec || key != e->gkey)) {
     if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
     e->gexec = nullptr;
     e->gkey.clear();
     hipGraph_t graph = nullptr;
-    he = hipStreamBeginCapture(e->cap_st, hipStreamCaptureModeThreadLocal);
+    hipStream_t cs = lead->cap_st;
+    he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (he == hipSuccess) {
       int base = 0;
       for (auto& g : groups) {
-        if (g[0]->s->f32) launch_trial_batch<float>(g, e->cap_st, e->par_dev + base);
-        else launch_trial_batch<double>(g, e->cap_st, e->par_dev + base);
+        if (g[0]->s->f32) launch_trial_batch<float>(g, cs, lead->slots + base);
+        else launch_trial_batch<double>(g, cs, lead->slots + base);
         base += (int)g.size();
       }
-      launch_gather(ga, e->cap_st);
-      he = hipStreamEndCapture(e->cap_st, &graph);
+      launch_gather(ga, cs);
+      he = hipStreamEndCapture(cs, &graph);
     }
     if (he == hipSuccess) he = hipGraphInstantiate(&e->gexec, graph, nullptr, nullptr, 0);
     if (graph) (void)hipGraphDestroy(graph);
@@ -1642,7 +1633,7 @@ int batch_tick(BatchEngine* e) {
   for (int i = 0; i < ga.S; ++i) ga.src[i] = reinterpret_cast<const char*>(e->act[i]->s->cg);
   ga.dst = lead->gstage;
   bool replay = true;
-  for (auto* m : e->act) replay = replay && m->s->graphs && m->queued;
+  for (auto* m : e->act) replay = replay && m->s->graphs && m->s->cap_st && m->queued;
   if (replay) {
     const int rc0 = batch_replay(e, groups, ga);
     if (rc0) return rc0;

@@ -696,6 +696,12 @@ struct GatherArgs {
   char* dst;
 };
 void launch_gather(const GatherArgs& g, hipStream_t st);
+// Writes n (at most kMaxBatch) integers, passed by value, to dst[0..n) on the device.
+struct IntList {
+  int n;
+  int v[kMaxBatch];
+};
+void launch_set_ints(int* dst, const IntList& l, hipStream_t st);
 void launch_ls_init(const EvalOut* ev, LsState* ls, LsParams prm, hipStream_t st);
 // After the current iterate was re-orthonormalised and evaluated again (ev): the
 // nonmonotone reference restarts there (C = E, Q = 1); k, the step and the stagnation
