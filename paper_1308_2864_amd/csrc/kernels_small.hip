@@ -483,14 +483,29 @@ void launch_qr_factor_blocked(const double* xx, const double* gxd, int p, int pp
   hipLaunchKernelGGL(k_wf_store, dim3(sb), dim3(256), 0, st, W, p, pp, tau, A, B, flag);
 }
 
-// Element-parallel variant for p <= P (P = 16, 32, 64): the P x P matrix Y^T Y lives in
-// registers, a few elements per thread (qr_threads threads), and both the
-// right-looking Cholesky and the back substitution for R^{-1} run as p rank-1 steps in
-// which every thread updates its own elements; a step costs two barriers instead of a
-// serial loop over a column.  Rows/columns k are broadcast through LDS, double-buffered
-// by step parity.
-template <int P, int kThreads>
-__device__ inline void k_qr_factor_2d_body(const QrFactor2dArgs& ka, int ks_bid, int ks_nb) {
+// Factor for p <= P (P = 16, 32, 64) by elimination on the augmented matrix [M | I]
+// (M = Y^T Y padded to P x P with the identity, whose factor is the identity, so the padding
+// leaves the p x p result unchanged and needs no guards).  Step k eliminates below the
+// pivot with row k of the partly eliminated array: x[r][.] -= M'[k][r] x[k][.] / M'[k][k]
+// for r > k (M'[r][k] = M'[k][r] by symmetry: the row operation of M = L D L^T).  After P
+// steps the identity half holds L^{-1}; with R = D^{1/2} L^T (M = R^T R, R upper),
+// R^{-1} = L^{-T} D^{-1/2}, so no back substitution is needed:
+// W[i][j] = (L^{-1})[j][i] / sqrt(d_j).
+// Only the upper triangle of M' and the strict lower triangle of L^{-1} (whose diagonal stays
+// 1 and upper part 0) are ever needed, and together they fill one P x P square: element
+// (r, c) is M'[r][c] for r <= c and L^{-1}[r][c] for r > c, kE elements per thread.  Row k
+// of the square is then exactly the multiplier row of step k; its owners publish it (two
+// buffers by step parity, so a step needs one barrier) and the owner of the pivot also
+// publishes 1 / M'[k][k] and makes the pivot test.
+template <int P>
+constexpr int qr_factor_threads() {
+  return P * P < 1024 ? P * P : 1024;
+}
+
+template <int P>
+__device__ inline void k_qr_factor_aug_body(const QrFactor2dArgs& ka) {
+  constexpr int kT = qr_factor_threads<P>();
+  constexpr int kE = P * P / kT;
   const double* xx = ka.xx;
   const double* gxd = ka.gxd;
   if (ka.sel) {
@@ -503,122 +518,105 @@ __device__ inline void k_qr_factor_2d_body(const QrFactor2dArgs& ka, int ks_bid,
       gxd = ka.gxd_rej;
     }
   }
-  int p = ka.p;
-  int pp = ka.pp;
-  const double* __restrict__ tau_p = ka.tau_p;
-  double* __restrict__ A = ka.A;
-  double* __restrict__ B = ka.B;
-  int* status = ka.status;
-  (void)ks_bid;
-  (void)ks_nb;
-
-  constexpr int kT = kThreads;       // threads
-  constexpr int kE = P * P / kT;     // elements per thread
+  const int p = ka.p, pp = ka.pp;
   __shared__ double row[2][P];
-  __shared__ double dg[P];
-  __shared__ double Rs[P][P + 1];
+  __shared__ double rinv[2];
+  __shared__ double Ws[P][P + 1];
   __shared__ int bad;
   const int t = threadIdx.x;
-  const double tau = *tau_p;
+  const double tau = *ka.tau_p;
   const double* XD = gxd + pp * pp;
   const double* DD = gxd + 2 * pp * pp;
-  int ei[kE], ej[kE];
-  double a[kE];
-#pragma unroll
-  for (int q = 0; q < kE; ++q) {
-    const int e = t + q * kT;
-    ei[q] = e / P;
-    ej[q] = e % P;
-    const int i = ei[q], j = ej[q];
-    a[q] = (i < p && j < p) ? xx[i * pp + j] - tau * (XD[i * pp + j] + XD[j * pp + i]) +
-                                  tau * tau * DD[i * pp + j]
-                            : 0.0;
-    if (i == j && i < p) dg[i] = a[q];
-  }
   if (t == 0) bad = 0;
-  __syncthreads();
-  // Cholesky M = R^T R (upper R): step k takes the pivot, scales row k, updates the rest
-  for (int k = 0; k < p; ++k) {
-    double* rk = row[k & 1];
-#pragma unroll
-    for (int q = 0; q < kE; ++q)
-      if (ei[q] == k && ej[q] == k) {
-        const double d = a[q];
-        if (!(d > kPivotTol * dg[k]) || !isfinite(d)) bad = 1;
-        a[q] = sqrt(d);
-        rk[k] = a[q];
-      }
-    __syncthreads();
-    const double rkk = rk[k];
-#pragma unroll
-    for (int q = 0; q < kE; ++q)
-      if (ei[q] == k && ej[q] > k && ej[q] < p) {
-        a[q] /= rkk;
-        rk[ej[q]] = a[q];
-      }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kE; ++q)
-      if (ei[q] > k && ej[q] >= ei[q] && ej[q] < p) a[q] -= rk[ei[q]] * rk[ej[q]];
-  }
-  __syncthreads();
-  if (bad) {
-    if (t == 0) *status = KS_E_NOT_SPD;
-    return;
-  }
-  // R to LDS (upper part), then R W = I by back substitution over rows m = p-1 .. 0:
-  // S_ij starts at delta_ij; row m of W is S_mj / R_mm, and every row above subtracts
-  // R_im W_mj.
-#pragma unroll
-  for (int q = 0; q < kE; ++q) Rs[ei[q]][ej[q]] = (ej[q] >= ei[q]) ? a[q] : 0.0;
-  double w[kE];
-#pragma unroll
-  for (int q = 0; q < kE; ++q) w[q] = (ei[q] == ej[q]) ? 1.0 : 0.0;
-  __syncthreads();
-  for (int m = p - 1; m >= 0; --m) {
-    double* wm = row[m & 1];
-    const double rmm = Rs[m][m];
-#pragma unroll
-    for (int q = 0; q < kE; ++q)
-      if (ei[q] == m) {
-        w[q] = (ej[q] >= m && ej[q] < p) ? w[q] / rmm : 0.0;
-        wm[ej[q]] = w[q];
-      }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kE; ++q)
-      if (ei[q] < m && ej[q] >= m && ej[q] < p) w[q] -= Rs[ei[q]][m] * wm[ej[q]];
-  }
+  // the pivot test of row r against the diagonal entry of M
+  auto test = [&](double d, double d0) {
+    if (!(d > kPivotTol * d0) || !isfinite(d)) bad = 1;
+  };
+  // M = X^T X - tau (X^T D + D^T X) + tau^2 D^T D (upper triangle); L^{-1} starts at 0
+  double x[kE], d0[kE];
 #pragma unroll
   for (int q = 0; q < kE; ++q) {
-    const int i = ei[q], j = ej[q];
-    if (i < pp && j < pp) {
-      const double v = (i < p && j < p && j >= i) ? w[q] : 0.0;
-      A[i * pp + j] = v;
-      B[i * pp + j] = -tau * v;
+    const int e = t + q * kT, r = e / P, c = e % P;
+    const bool in = r < p && c < p;
+    const int a = in ? r * pp + c : 0, b = in ? c * pp + r : 0;
+    const double m = xx[a] - tau * (XD[a] + XD[b]) + tau * tau * DD[a];
+    x[q] = r > c ? 0.0 : (in ? m : (r == c ? 1.0 : 0.0));
+    d0[q] = x[q];
+  }
+  __syncthreads();  // bad = 0 before any test
+#pragma unroll
+  for (int q = 0; q < kE; ++q) {
+    const int e = t + q * kT, r = e / P, c = e % P;
+    if (r == 0) {
+      row[0][c] = x[q];
+      if (c == 0) {
+        rinv[0] = 1.0 / x[q];
+        test(x[q], d0[q]);
+      }
     }
   }
+  __syncthreads();
+  // kept a loop: unrolled, the body (run once per launch) would be bound by instruction fetch
+#pragma unroll 1
+  for (int k = 0; k < P - 1; ++k) {
+    const double* rk = row[k & 1];
+    double* rn = row[(k + 1) & 1];
+    const double dinv = rinv[k & 1];
+#pragma unroll
+    for (int q = 0; q < kE; ++q) {
+      const int e = t + q * kT, r = e / P, c = e % P;
+      if (r > k) {
+        // x[k][c]: M'[k][c] (c >= k), or L^{-1}[k][c]: published (c < k), 1 (c = k), 0
+        const double v = rk[c];
+        const double xk = (r <= c || c < k) ? v : (c == k ? 1.0 : 0.0);
+        x[q] = fma(-rk[r] * dinv, xk, x[q]);
+        if (r == k + 1) {
+          rn[c] = x[q];
+          if (c == r) {
+            rinv[(k + 1) & 1] = 1.0 / x[q];
+            test(x[q], d0[q]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (t == 0) *ka.status = KS_E_NOT_SPD;
+    return;
+  }
+  // W[c][r] = L^{-1}[r][c] / sqrt(d_r) for r > c and 1 / sqrt(d_r) on the diagonal; the
+  // pivots d_r sit on the diagonal of the square (row[.] no longer needed: reuse for them)
+#pragma unroll
+  for (int q = 0; q < kE; ++q) {
+    const int e = t + q * kT, r = e / P, c = e % P;
+    if (r == c) Ws[r][P] = 1.0 / sqrt(x[q]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kE; ++q) {
+    const int e = t + q * kT, r = e / P, c = e % P;
+    const double sr = Ws[r][P];
+    Ws[c][r] = r > c ? x[q] * sr : (r == c ? sr : 0.0);
+  }
+  __syncthreads();
+  for (int e = t; e < pp * pp; e += kT) {
+    const int i = e / pp, j = e % pp;
+    const double v = (i < p && j < p) ? Ws[i][j] : 0.0;
+    ka.A[e] = v;
+    ka.B[e] = -tau * v;
+  }
 }
 
-// Threads of the factor block for P: one element per thread up to 32 x 32 (measured on
-// P = 32: 1024 threads of one element, 19.5 us, beat 256 threads of four, 31 us), four
-// per thread at P = 64.
 template <int P>
-constexpr int qr_threads() {
-  return P * P < 1024 ? P * P : 1024;
+__global__ __launch_bounds__(qr_factor_threads<P>()) void k_qr_factor_aug(QrFactor2dArgs ka) {
+  k_qr_factor_aug_body<P>(ka);
 }
 
 template <int P>
-__global__ __launch_bounds__(qr_threads<P>()) void k_qr_factor_2d(QrFactor2dArgs ka) {
-  k_qr_factor_2d_body<P, qr_threads<P>()>(ka, blockIdx.x, gridDim.x);
-}
-
-template <int P>
-__global__ __launch_bounds__(qr_threads<P>()) void k_qr_factor_2d_batch(
+__global__ __launch_bounds__(qr_factor_threads<P>()) void k_qr_factor_aug_batch(
     BatchPtrs<QrFactor2dArgs> b) {
-  const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_qr_factor_2d_body<P, qr_threads<P>()>(batch_arg(b, s), blockIdx.x - b.off[s],
-                                          b.off[s + 1] - b.off[s]);
+  k_qr_factor_aug_body<P>(batch_arg(b, blockIdx.x));
 }
 
 
@@ -1042,17 +1040,17 @@ void launch_grad_weights(const double* gram, int pp, double* W, hipStream_t st) 
 void launch_qr_factor(const double* xx, const double* gxd, int p, int pp, const double* tau,
                       double* A, double* B, double* work, int* status, hipStream_t st) {
   if (p <= 16) {
-    hipLaunchKernelGGL(k_qr_factor_2d<16>, dim3(1), dim3(qr_threads<16>()), 0, st,
+    hipLaunchKernelGGL(k_qr_factor_aug<16>, dim3(1), dim3(qr_factor_threads<16>()), 0, st,
                        QrFactor2dArgs{xx, gxd, p, pp, tau, A, B, status});
     return;
   }
   if (p <= 32) {
-    hipLaunchKernelGGL(k_qr_factor_2d<32>, dim3(1), dim3(qr_threads<32>()), 0, st,
+    hipLaunchKernelGGL(k_qr_factor_aug<32>, dim3(1), dim3(qr_factor_threads<32>()), 0, st,
                        QrFactor2dArgs{xx, gxd, p, pp, tau, A, B, status});
     return;
   }
   if (p <= 64) {
-    hipLaunchKernelGGL(k_qr_factor_2d<64>, dim3(1), dim3(qr_threads<64>()), 0, st,
+    hipLaunchKernelGGL(k_qr_factor_aug<64>, dim3(1), dim3(qr_factor_threads<64>()), 0, st,
                        QrFactor2dArgs{xx, gxd, p, pp, tau, A, B, status});
     return;
   }
@@ -1138,11 +1136,11 @@ void launch_bf16_defect(const double* xg, const double* xd, const double* xx, co
 
 void launch_qr_factor_next(const QrFactor2dArgs& a, hipStream_t st) {
   if (a.p <= 16)
-    hipLaunchKernelGGL(k_qr_factor_2d<16>, dim3(1), dim3(qr_threads<16>()), 0, st, a);
+    hipLaunchKernelGGL(k_qr_factor_aug<16>, dim3(1), dim3(qr_factor_threads<16>()), 0, st, a);
   else if (a.p <= 32)
-    hipLaunchKernelGGL(k_qr_factor_2d<32>, dim3(1), dim3(qr_threads<32>()), 0, st, a);
+    hipLaunchKernelGGL(k_qr_factor_aug<32>, dim3(1), dim3(qr_factor_threads<32>()), 0, st, a);
   else
-    hipLaunchKernelGGL(k_qr_factor_2d<64>, dim3(1), dim3(qr_threads<64>()), 0, st, a);
+    hipLaunchKernelGGL(k_qr_factor_aug<64>, dim3(1), dim3(qr_factor_threads<64>()), 0, st, a);
 }
 
 // One column (the orbital-free problem): eq. (WY-1d) gives x+ = (1 - beta_2) x - beta_1 a
@@ -1224,11 +1222,11 @@ void launch_ls_restart(const EvalOut* ev, LsState* ls, LsParams prm, hipStream_t
 
 void launch_qr_factor_batch(const BatchPtrs<QrFactor2dArgs>& b, int p_max, hipStream_t st) {
   if (p_max <= 16)
-    hipLaunchKernelGGL(k_qr_factor_2d_batch<16>, dim3(b.S), dim3(qr_threads<16>()), 0, st, b);
+    hipLaunchKernelGGL(k_qr_factor_aug_batch<16>, dim3(b.S), dim3(qr_factor_threads<16>()), 0, st, b);
   else if (p_max <= 32)
-    hipLaunchKernelGGL(k_qr_factor_2d_batch<32>, dim3(b.S), dim3(qr_threads<32>()), 0, st, b);
+    hipLaunchKernelGGL(k_qr_factor_aug_batch<32>, dim3(b.S), dim3(qr_factor_threads<32>()), 0, st, b);
   else
-    hipLaunchKernelGGL(k_qr_factor_2d_batch<64>, dim3(b.S), dim3(qr_threads<64>()), 0, st, b);
+    hipLaunchKernelGGL(k_qr_factor_aug_batch<64>, dim3(b.S), dim3(qr_factor_threads<64>()), 0, st, b);
 }
 
 void launch_finish_eval_batch(const BatchPtrs<FinishEvalArgs>& b, hipStream_t st) {
