@@ -417,7 +417,7 @@ __device__ inline void hx_items(const HxArgs<T>& ka, int lb, int nblk, double& k
 // grid contribute zeros; all control flow is uniform over the wavefront (MFMAs need every
 // lane).
 struct HxGramAcc {
-  d4 xg[4], xx[4];  // tiles (a, b) at index 2 a + b
+  d4 xg[4], xx[4];  // tiles (a, b) at index 2 a + b; xx[2] = xx[1]^T is not formed
 };
 
 constexpr int kHxDepth = 3;
@@ -505,8 +505,9 @@ __device__ inline void hx_gram_items(const HxArgs<T>& ka, int lb, int nblk, doub
         for (int eb = 0; eb < 2; ++eb) {
           g.xg[2 * ea + eb] = __builtin_amdgcn_mfma_f64_16x16x4f64(xo[ea], go[eb],
                                                                     g.xg[2 * ea + eb], 0, 0, 0);
-          g.xx[2 * ea + eb] = __builtin_amdgcn_mfma_f64_16x16x4f64(xo[ea], xo[eb],
-                                                                    g.xx[2 * ea + eb], 0, 0, 0);
+          if (ea <= eb)  // X^T X is symmetric: tile (1, 0) is tile (0, 1) transposed
+            g.xx[2 * ea + eb] = __builtin_amdgcn_mfma_f64_16x16x4f64(xo[ea], xo[eb],
+                                                                      g.xx[2 * ea + eb], 0, 0, 0);
         }
       cm = cc;
       cc = cur.zn;
@@ -550,7 +551,7 @@ __device__ inline void k_hx_body(const HxArgs<T>& ka, int ks_bid, int ks_nb) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       hx_reduce_tile(g.xg[q], red, w, lane);
-      hx_reduce_tile(g.xx[q], red, w, lane);
+      if (q != 2) hx_reduce_tile(g.xx[q], red, w, lane);
     }
     if (w == 0) {
       // tile (a, b), lane (lr, lc), register r: entry (2 (lr + 4 r) + a, 2 lc + b)
@@ -564,8 +565,10 @@ __device__ inline void k_hx_body(const HxArgs<T>& ka, int ks_bid, int ks_nb) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = 2 * (lr + 4 * r) + ea, col = 2 * lc + eb;
-          o0[row * pp + col] = g.xx[q][r];
           o1[row * pp + col] = g.xg[q][r];
+          if (q == 2) continue;
+          o0[row * pp + col] = g.xx[q][r];
+          if (q == 1) o0[col * pp + row] = g.xx[q][r];  // tile (1, 0)
         }
       }
     }

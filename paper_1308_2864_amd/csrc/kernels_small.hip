@@ -722,7 +722,8 @@ __global__ void k_grad_weights(const double* __restrict__ gram, int pp, double* 
 }
 
 // ---- evaluation summary ----------------------------------------------------------------
-__device__ void ls_judge(const EvalOut* ev, LsState* ls, const LsParams& prm, const CgState* cg);
+__device__ void ls_judge(const EvalOut* ev, LsState* ls, LsState s, const LsParams& prm,
+                         bool cg_pending);
 
 // The evaluation summary: sums the per-block partials of every scalar slot (fixed
 // order), forms the energy terms, ||X^T X - I||_F (or X^T B X) from the Gram block and,
@@ -749,6 +750,20 @@ __device__ inline void k_finish_eval_body(const FinishEvalArgs& ka, int ks_bid, 
 
   __shared__ double sh[kFinishThreads / kWave];
   __shared__ double red[SL_COUNT];
+  // the records thread 0 works on at the end, loaded now: their loads overlap the sums
+  LsState s0{};
+  double cg_rr = 0.0, cg_bb = 0.0, en = 0.0;
+  int cg_it = 0, cg_done = 1;
+  if (threadIdx.x == 0) {
+    if (ls) s0 = *ls;
+    if (cg) {
+      cg_rr = cg->rr;
+      cg_bb = cg->bb;
+      cg_it = cg->it;
+      cg_done = cg->done;
+    }
+    en = *enuc;
+  }
   // all slots in one sweep: each thread keeps SL_COUNT running sums, so its loads of the
   // different slots are independent and overlap
   int mx = 0;
@@ -816,9 +831,17 @@ __device__ inline void k_finish_eval_body(const FinishEvalArgs& ka, int ks_bid, 
     cs->rz = 0.0;
     cs->rr_best = rr;
     cs->stall = 0;
-    cs->it = bb == 0.0 ? 0 : 1;
+    const int it = bb == 0.0 ? 0 : 1;
+    const int done = (bb == 0.0 || !isfinite(rr) || !isfinite(bb) || rr <= tol * tol * bb) ? 1 : 0;
+    cs->it = it;
     cs->maxit = ka.hmaxit;
-    cs->done = (bb == 0.0 || !isfinite(rr) || !isfinite(bb) || rr <= tol * tol * bb) ? 1 : 0;
+    cs->done = done;
+    if (cg == cs) {  // the record read below is the one just written
+      cg_rr = rr;
+      cg_bb = bb;
+      cg_it = it;
+      cg_done = done;
+    }
   }
   EvalOut o;
   // the kinetic partial carries the weight mu; the Thomas-Fermi term is kinetic energy
@@ -826,7 +849,7 @@ __device__ inline void k_finish_eval_body(const FinishEvalArgs& ka, int ks_bid, 
   o.external = dV * red[SL_EXT];  // h^3 sum V_ext rho
   o.hartree = 0.5 * dV * red[SL_EH] + dV * red[SL_EBC] + (ka.ebc ? *ka.ebc : 0.0);
   o.xc = dV * red[SL_EX];
-  o.nuclear = *enuc;
+  o.nuclear = en;
   o.total = o.kinetic + o.external + o.hartree + o.xc + o.nuclear;
   o.g2 = red[SL_DD];
   o.ss = red[SL_SS];
@@ -835,15 +858,15 @@ __device__ inline void k_finish_eval_body(const FinishEvalArgs& ka, int ks_bid, 
   o.orth2 = acc;
   o.defect2 = red[SL_DEFECT];
   if (cg) {
-    o.cg_iters = cg->it;
-    o.cg_relres = cg->bb > 0.0 ? sqrt(cg->rr / cg->bb) : 0.0;
+    o.cg_iters = cg_it;
+    o.cg_relres = cg_bb > 0.0 ? sqrt(cg_rr / cg_bb) : 0.0;
   } else {
     o.cg_iters = 0;
     o.cg_relres = 0.0;
   }
   o.nonfinite = (!isfinite(o.total) || !isfinite(o.g2)) ? 1 : 0;
   *out = o;
-  if (ls) ls_judge(&o, ls, prm, cg);
+  if (ls) ls_judge(&o, ls, s0, prm, cg && !cg_done);
 }
 
 __global__ __launch_bounds__(1024) void k_finish_eval(FinishEvalArgs ka) {
@@ -929,10 +952,10 @@ __global__ void k_ls_restart(const EvalOut* ev, LsState* ls, LsParams prm) {
   *ls = s;
 }
 
-__device__ void ls_judge(const EvalOut* ev, LsState* ls, const LsParams& prm,
-                         const CgState* cg) {
-  LsState s = *ls;
-  if (cg && !cg->done) {
+// s: the record as read from ls at the start of the calling kernel.
+__device__ void ls_judge(const EvalOut* ev, LsState* ls, LsState s, const LsParams& prm,
+                         bool cg_pending) {
+  if (cg_pending) {
     // the Hartree potential of this trial is not converged yet: the host finishes the
     // solve, re-evaluates the trial and judges it again
     s.hartree_pending = 1;

@@ -2109,6 +2109,7 @@ namespace {
 using TuneKey = std::tuple<int, int, int, int, int, int, int>;
 std::mutex g_tune_mu;
 constexpr double kTuneMargin = 0.03;  // a candidate must beat the built-in shape by 3%
+constexpr int kTuneRounds = 3;
 std::map<TuneKey, std::pair<int, int>> g_tune;  // (fd_mode, hx_zrun)
 
 // Mean device time of fn() over reps launches on the system's stream, after two warm-ups.
@@ -2171,13 +2172,24 @@ int ks_autotune(ks_system* s, int force, ks_tune_info* out) {
     int best_mode = KS_TUNE_AUTO;
     const int dflt = fd_plane_mode(s->grid.nx, s->grid.ny);
     double dflt_us = 0.0;
-    for (int mode : {kPlaneFull, kPlaneStripSy, kPlaneStrip, kPlaneStripG}) {
-      if (rc || !fd_plane_mode_fits(s->grid.nx, s->grid.ny, mode)) continue;
-      s->grid.fd_mode = mode;
-      double us = 0.0;
-      rc = time_us(s, reps, [&] {
-        launch_fd_correct(s->cg_r, s->vh[0], s->vh[1], s->cg_q, fd_ops(s), s->grid, s->st);
-      }, &us);
+    // interleaved rounds, the fastest round of each candidate: a single timing per
+    // candidate mixes clock ramp-up and noise of a few percent into the comparison
+    const int modes[4] = {kPlaneFull, kPlaneStripSy, kPlaneStrip, kPlaneStripG};
+    double tmin[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int round = 0; round < kTuneRounds && !rc; ++round)
+      for (int m = 0; m < 4 && !rc; ++m) {
+        if (!fd_plane_mode_fits(s->grid.nx, s->grid.ny, modes[m])) continue;
+        s->grid.fd_mode = modes[m];
+        double us = 0.0;
+        rc = time_us(s, reps, [&] {
+          launch_fd_correct(s->cg_r, s->vh[0], s->vh[1], s->cg_q, fd_ops(s), s->grid, s->st);
+        }, &us);
+        if (round == 0 || us < tmin[m]) tmin[m] = us;
+      }
+    for (int m = 0; m < 4 && !rc; ++m) {
+      const int mode = modes[m];
+      if (!fd_plane_mode_fits(s->grid.nx, s->grid.ny, mode)) continue;
+      const double us = tmin[m];
       info.fd_modes[info.n_fd] = mode;
       info.fd_us[info.n_fd++] = us;
       if (mode == dflt) dflt_us = us;
@@ -2201,13 +2213,20 @@ int ks_autotune(ks_system* s, int force, ks_tune_info* out) {
     int best_z = KS_TUNE_AUTO;
     const int dflt = hx_zrun(s->grid.nx * s->grid.ny, s->grid.nz);
     double dflt_us = 0.0;
-    for (int z : {16, 8}) {
-      if (rc) break;
-      s->grid.hx_zrun = z;
-      double us = 0.0;
-      rc = time_us(s, reps, [&] {
-        hamiltonian(s, s->X[0], s->p, s->G[0], s->p, s->veff[0], 1.0, &pt, s->gram_part);
-      }, &us);
+    const int zs[2] = {16, 8};
+    double tmin[2] = {0.0, 0.0};
+    for (int round = 0; round < kTuneRounds && !rc; ++round)
+      for (int m = 0; m < 2 && !rc; ++m) {
+        s->grid.hx_zrun = zs[m];
+        double us = 0.0;
+        rc = time_us(s, reps, [&] {
+          hamiltonian(s, s->X[0], s->p, s->G[0], s->p, s->veff[0], 1.0, &pt, s->gram_part);
+        }, &us);
+        if (round == 0 || us < tmin[m]) tmin[m] = us;
+      }
+    for (int m = 0; m < 2 && !rc; ++m) {
+      const int z = zs[m];
+      const double us = tmin[m];
       info.hx_zruns[info.n_hx] = z;
       info.hx_us[info.n_hx++] = us;
       if (z == dflt) dflt_us = us;
