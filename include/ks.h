@@ -386,8 +386,9 @@ int ks_batch_step(ks_system* const* sys, int count, ks_iter_info* info);
  * Times the candidate launch shapes of two kernels of an evaluation on this system's own
  * buffers (the fast-diagonalisation plane transforms of the Hartree solve, every mode whose
  * LDS fits; the Hamiltonian with fused Gram tiles, 8 or 16 planes per work item) and keeps
- * the fastest for the system when it beats the built-in shape by more than 3% (so timing
- * noise cannot flip the choice).  Choices are cached per (grid, p, precision, discretisation,
+ * the fastest for the system when it beats the built-in shape by more than 10% (each
+ * candidate's best of three interleaved timing rounds; smaller differences are within the
+ * run-to-run spread of these timings and must not flip the choice).  Choices are cached per (grid, p, precision, discretisation,
  * Hartree solver) for the process: a later system of the same key takes them without
  * timing (force = 1 times again).  The shapes change how sums split over blocks, so results
  * can differ from untuned runs in the last bits (a saved state resumes bit for bit only on

@@ -215,69 +215,61 @@ __global__ __launch_bounds__(256) void k_gram_batch(BatchPtrs<GramArgs<T>> b) {
 
 
 // out[prod][i][j] = sum over the chunk partials, for the products in mask; the other
-// products are left untouched.  Block = 4 output slots x kRedLanes chunk lanes; chunk lane c
-// sums chunks c, c + kRedLanes, ... (loaded kRedU at a time, all in flight together) and the
-// lane sums are added in lane order, so the result is the same on every run.  Symmetric
-// products read the mirrored upper tile.  With W != nullptr also W = -(product 1)^T.
-constexpr int kRedSlots = 4;
-constexpr int kRedLanes = 64;
+// products are left untouched.  Block = kRedCols consecutive entries of one row of one
+// product x kRedGroups chunk groups: a wavefront's load covers whole 128-byte lines of
+// four chunks.  Group g sums chunks g, g + kRedGroups, ... (loaded kRedU at a time, all in
+// flight together) and the group sums are added in group order, so the result is the same
+// on every run.  Symmetric products are summed on their upper 16 x 16 tiles (and the
+// diagonal tiles) and written to both mirrored places.  With W != nullptr also
+// W = -(product 1)^T.
+constexpr int kRedCols = 16;
+constexpr int kRedGroups = 64;
 constexpr int kRedU = 8;
 
 __device__ inline void k_gram_reduce_body(const GramReduceArgs& ka, int ks_bid, int ks_nb) {
-  const double* __restrict__ part = ka.part;
-  int nchunks = ka.nchunks;
-  int pp = ka.pp;
-  int mask = ka.mask;
-  double* __restrict__ out = ka.out;
-  double* __restrict__ W = ka.W;
+  const int pp = ka.pp, nchunks = ka.nchunks;
   (void)ks_nb;
-
-  __shared__ double red[kRedSlots][kRedLanes + 1];
-  const int sl = threadIdx.x % kRedSlots, cl = threadIdx.x / kRedSlots;
   const int per = pp * pp;
-  const int e = ks_bid * kRedSlots + sl;
-  double s = 0.0;
-  int prod = 0, i = 0, j = 0;
-  bool live = false;
-  if (e < 3 * per) {
-    prod = e / per;
-    const int ij = e % per;
-    i = ij / pp;
-    j = ij % pp;
-    live = (mask >> prod) & 1;
-    if (live) {
-      const int src = (prod != 1 && (i / 16) > (j / 16)) ? j * pp + i : ij;
-      const double* q = part + (size_t)prod * per + src;
-      const size_t cs = (size_t)3 * per;
-      for (int c0 = cl; c0 < nchunks; c0 += kRedLanes * kRedU) {
-        double v[kRedU];
+  const int e0 = ks_bid * kRedCols;  // first entry of the block (pp is a multiple of 16)
+  if (e0 >= 3 * per) return;
+  const int prod = e0 / per, ij0 = e0 % per, i = ij0 / pp, j0 = ij0 % pp;
+  if (!((ka.mask >> prod) & 1)) return;
+  const bool sym = prod != 1;
+  if (sym && i / 16 > j0 / 16) return;  // a lower tile: written as the mirror
+  __shared__ double red[kRedGroups][kRedCols + 1];
+  const int c = threadIdx.x % kRedCols, g = threadIdx.x / kRedCols;
+  const double* __restrict__ q = ka.part + (size_t)prod * per + ij0 + c;
+  const size_t cs = (size_t)3 * per;
+  double sum = 0.0;
+  for (int c0 = g; c0 < nchunks; c0 += kRedGroups * kRedU) {
+    double v[kRedU];
 #pragma unroll
-        for (int u = 0; u < kRedU; ++u) {
-          const int c = c0 + kRedLanes * u;
-          const double x = q[(size_t)(c < nchunks ? c : 0) * cs];
-          v[u] = c < nchunks ? x : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < kRedU; ++u)
-          if (c0 + kRedLanes * u < nchunks) s += v[u];
-      }
+    for (int u = 0; u < kRedU; ++u) {
+      const int ch = c0 + kRedGroups * u;
+      v[u] = q[(size_t)(ch < nchunks ? ch : 0) * cs];
     }
+#pragma unroll
+    for (int u = 0; u < kRedU; ++u)
+      if (c0 + kRedGroups * u < nchunks) sum += v[u];
   }
-  red[sl][cl] = s;
+  red[g][c] = sum;
   __syncthreads();
-  if (cl == 0 && e < 3 * per && live) {
+  if (g == 0) {
     double t = 0.0;
-    for (int c = 0; c < kRedLanes; ++c) t += red[sl][c];
-    out[e] = t;
-    if (W && prod == 1) W[j * pp + i] = -t;
+    for (int k = 0; k < kRedGroups; ++k) t += red[k][c];
+    const int j = j0 + c;
+    double* out = ka.out + (size_t)prod * per;
+    out[i * pp + j] = t;
+    if (sym && i / 16 < j / 16) out[j * pp + i] = t;
+    if (ka.W && prod == 1) ka.W[j * pp + i] = -t;
   }
 }
 
-__global__ __launch_bounds__(kRedSlots * kRedLanes) void k_gram_reduce(GramReduceArgs ka) {
+__global__ __launch_bounds__(kRedCols * kRedGroups) void k_gram_reduce(GramReduceArgs ka) {
   k_gram_reduce_body(ka, blockIdx.x, gridDim.x);
 }
 
-__global__ __launch_bounds__(kRedSlots * kRedLanes) void k_gram_reduce_batch(
+__global__ __launch_bounds__(kRedCols * kRedGroups) void k_gram_reduce_batch(
     BatchPtrs<GramReduceArgs> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
   k_gram_reduce_body(batch_arg(b, s), blockIdx.x - b.off[s], b.off[s + 1] - b.off[s]);
@@ -738,7 +730,7 @@ void launch_gram(const void* A, const void* B, bool f32, int ld, int n, int p, i
 
 void launch_gram_reduce(const double* partials, int nchunks, int pp, int mask, double* out,
                         double* W, hipStream_t st) {
-  hipLaunchKernelGGL(k_gram_reduce, dim3(gram_reduce_blocks(pp)), dim3(kRedSlots * kRedLanes), 0,
+  hipLaunchKernelGGL(k_gram_reduce, dim3(gram_reduce_blocks(pp)), dim3(kRedCols * kRedGroups), 0,
                      st,
                      GramReduceArgs{partials, nchunks, pp, mask, out, W});
 }
@@ -1414,10 +1406,10 @@ template void launch_gram_batch<double>(const BatchPtrs<GramArgs<double>>&, int,
 template void launch_gram_batch<float>(const BatchPtrs<GramArgs<float>>&, int, int, int,
                                        hipStream_t);
 
-int gram_reduce_blocks(int pp) { return (3 * pp * pp + kRedSlots - 1) / kRedSlots; }
+int gram_reduce_blocks(int pp) { return 3 * pp * pp / kRedCols; }
 
 void launch_gram_reduce_batch(const BatchPtrs<GramReduceArgs>& b, int blocks, hipStream_t st) {
-  hipLaunchKernelGGL(k_gram_reduce_batch, dim3(blocks), dim3(kRedSlots * kRedLanes), 0, st,
+  hipLaunchKernelGGL(k_gram_reduce_batch, dim3(blocks), dim3(kRedCols * kRedGroups), 0, st,
                      b);
 }
 

@@ -2108,7 +2108,10 @@ extern "C++" {
 namespace {
 using TuneKey = std::tuple<int, int, int, int, int, int, int>;
 std::mutex g_tune_mu;
-constexpr double kTuneMargin = 0.03;  // a candidate must beat the built-in shape by 3%
+// a candidate must beat the built-in shape by 10%: tuning-time timings of the Hartree passes
+// vary by several percent from run to run and have ranked shapes against the times the
+// same kernels take inside a solve
+constexpr double kTuneMargin = 0.10;
 constexpr int kTuneRounds = 3;
 std::map<TuneKey, std::pair<int, int>> g_tune;  // (fd_mode, hx_zrun)
 

@@ -30,13 +30,13 @@ def test_autotune_choices_cache_and_results():
     print("autotune:", info, flush=True)
     assert not info["cached"]
     # the kept shape is the fastest candidate, or the built-in one when nothing beats it by
-    # the 3% margin
+    # the 10% margin
     fd = info["fd_candidates_us"]
     assert info["fd_plane_mode"] in fd
-    assert fd[info["fd_plane_mode"]] <= min(fd.values()) / (1.0 - 0.03) + 1e-9
+    assert fd[info["fd_plane_mode"]] <= min(fd.values()) / (1.0 - 0.10) + 1e-9
     hx = info["hx_candidates_us"]
     assert set(hx) == {8, 16} and info["hx_zrun"] in (8, 16)
-    assert hx[info["hx_zrun"]] <= min(hx.values()) / (1.0 - 0.03) + 1e-9
+    assert hx[info["hx_zrun"]] <= min(hx.values()) / (1.0 - 0.10) + 1e-9
     # a second system of the same key takes the cached choice without timing
     b = K.system_from_spec(spec, hartree_solver=K.KS_HARTREE_PCG_FD)
     ib = b.ks_autotune()
