@@ -27,13 +27,16 @@ HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
 HARTREE_EV = 27.211386245988  # eV per hartree (CODATA 2018)
 
 
-def phase_bytes(n, p, w=8):
-    """Algorithmic HBM bytes of one occurrence of each single-kernel phase."""
+def phase_bytes(n, p, w=8, qr=True):
+    """Algorithmic HBM bytes of one occurrence of each single-kernel phase.  FP64 QR runs
+    with p <= 32 take the BB sums without X_k in the gradient pass (the retraction forms
+    ||s||^2 and <s, D_k>, the gradient <D_k, D>); otherwise the gradient pass reads X_k."""
     np_ = n * p * w
+    bbr = qr and w == 8 and p <= 32
     return {
         "hamiltonian": 2 * np_ + 8 * n,    # read X, write G, read V_eff
         "gram": 2 * np_,                   # read X and G (or D)
-        "gradient": 5 * np_,               # read G, X, X_k, D_k; write D
+        "gradient": (4 if bbr else 5) * np_,  # read G, X, D_k (and X_k); write D
         "retract": 3 * np_ + 8 * n,        # read X, Y; write X+ and rho
     }
 
@@ -712,7 +715,7 @@ def main():
     sysg.ks_read_timers(reset=True)
     step(0)
     phases = sysg.ks_read_timers(reset=True)
-    pb = phase_bytes(spec.n, spec.p)
+    pb = phase_bytes(spec.n, spec.p, qr=args.retraction == "qr")
     single = [k for k in pb if phases[k][1] > 0]
     # a phase may launch its kernel more than once per evaluation (beyond 32 columns the
     # Gram phase forms [X, G] and [X, D] products with two launches): rank phases by the
@@ -773,7 +776,9 @@ def main():
     avg_s = ms * 1e-3 / cnt
     achieved = pb[dom] / avg_s / 1e9
     kernel_names = {"hamiltonian": "k_hx_gram<double>", "gram": "k_gram<double,2,3>",
-                    "gradient": "k_combine<double,2,false,true,false,true,true,false>",
+                    "gradient": ("k_combine<double,2,false,true,false,true,true,false,true>"
+                                 if args.retraction == "qr" and spec.p <= 32 else
+                                 "k_combine<double,2,false,true,false,true,true,false>"),
                     "retract": "k_combine<double,2,true,false,true,false,false,true>"}
     traffic = pmc_traffic(kernel_names[dom]) if args.hartree == "pcg_fd" else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,

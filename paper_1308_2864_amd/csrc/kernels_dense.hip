@@ -370,7 +370,7 @@ struct Gram2Acc {
 };
 
 template <typename T, int kT, bool kVec, bool kHasY, bool kHasC0, bool kRho, bool kGrad,
-          bool kGram2, bool kUpper>
+          bool kGram2, bool kUpper, bool kBBR>
 __device__ inline void combine_tiles(const CombineArgs& a, double* lds, int t_beg, int t_end,
                                      d4& sums, Gram2Acc<kT>& g2) {
   const T* aX = static_cast<const T*>(a.X);
@@ -397,7 +397,7 @@ __device__ inline void combine_tiles(const CombineArgs& a, double* lds, int t_be
     // the gradient form reads G, X_k and D_k for the last time in the trial
     if constexpr (kHasC0) comb_load<T, kT, kVec, kGrad>(aC0, ld, n, p, row, q, f.c0);
     if constexpr (kGrad) {
-      comb_load<T, kT, kVec, true>(aXk, ld, n, p, row, q, f.xk);
+      if constexpr (!kBBR) comb_load<T, kT, kVec, true>(aXk, ld, n, p, row, q, f.xk);
       comb_load<T, kT, kVec, true>(aDk, ld, n, p, row, q, f.dk);
     }
   };
@@ -443,13 +443,22 @@ __device__ inline void combine_tiles(const CombineArgs& a, double* lds, int t_be
         v[e] = x;
         dv[s] = x;
         if constexpr (kRho) sq += x * x;
-        if constexpr (kGrad) {
+        if constexpr (kGrad && kBBR) {
+          sums[0] += x * x;
+          sums[3] += f.dk.v[s] * x;  // <D_k, D_t>
+        } else if constexpr (kGrad) {
           const double sd = f.x.v[s] - f.xk.v[s];
           const double yd = x - f.dk.v[s];
           sums[0] += x * x;
           sums[1] += sd * sd;
           sums[2] += sd * yd;
           sums[3] += yd * yd;
+        } else if constexpr (kHasY && !kHasC0) {
+          if (a.bbr) {  // the retraction's part of the BB sums: s = X_t - X_k, <s, D_k>
+            const double sd = x - f.x.v[s];
+            sums[1] += sd * sd;
+            sums[2] += sd * f.y.v[s];
+          }
         }
       }
       const int c0 = 8 * j + 2 * q;
@@ -516,7 +525,7 @@ __device__ inline void combine_tiles(const CombineArgs& a, double* lds, int t_be
 }
 
 template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad,
-          bool kGram2 = false, bool kUpper = false>
+          bool kGram2 = false, bool kUpper = false, bool kBBR = false>
 __device__ inline void k_combine_body(const CombineArgs& a, int ks_bid, int ks_nb) {
   extern __shared__ double lds[];            // permuted weights Wp = [A; B]: kK x kPP
   __shared__ double sh[kBlock / kWave];
@@ -537,10 +546,10 @@ __device__ inline void k_combine_body(const CombineArgs& a, int ks_bid, int ks_n
 #pragma unroll
   for (int t = 0; t < Gram2Acc<kT>::kN; ++t) g2.t[t] = d4{0.0, 0.0, 0.0, 0.0};
   if (vec)
-    combine_tiles<T, kT, true, kHasY, kHasC0, kRho, kGrad, kGram2, kUpper>(a, lds, t_beg, t_end, sums,
+    combine_tiles<T, kT, true, kHasY, kHasC0, kRho, kGrad, kGram2, kUpper, kBBR>(a, lds, t_beg, t_end, sums,
                                                                    g2);
   else
-    combine_tiles<T, kT, false, kHasY, kHasC0, kRho, kGrad, kGram2, kUpper>(a, lds, t_beg, t_end, sums,
+    combine_tiles<T, kT, false, kHasY, kHasC0, kRho, kGrad, kGram2, kUpper, kBBR>(a, lds, t_beg, t_end, sums,
                                                                     g2);
   if constexpr (kGram2) {
     // fixed-order sum over the block's waves, then this block's partial tiles (chunk lb)
@@ -563,7 +572,15 @@ __device__ inline void k_combine_body(const CombineArgs& a, int ks_bid, int ks_n
         for (int tj = ti; tj < kT; ++tj) put_tile<kPP>(a.gram_part, lb, 2, ti, tj, g2.t[g++], lr, lc);
     }
   }
-  if (kGrad) {
+  if (kGrad && kBBR) {
+    const double dd = block_sum(sums[0], sh);
+    const double cr = block_sum(sums[3], sh);
+    if (threadIdx.x == 0) {
+      const int st = a.pt.stride;
+      a.pt.buf[(size_t)SL_DD * st + lb] = dd;
+      a.pt.buf[(size_t)SL_YY * st + lb] = cr;
+    }
+  } else if (kGrad) {
     const double dd = block_sum(sums[0], sh);
     const double ss = block_sum(sums[1], sh);
     const double sy = block_sum(sums[2], sh);
@@ -575,20 +592,28 @@ __device__ inline void k_combine_body(const CombineArgs& a, int ks_bid, int ks_n
       a.pt.buf[(size_t)SL_SY * st + lb] = sy;
       a.pt.buf[(size_t)SL_YY * st + lb] = yy;
     }
+  } else if (kHasY && !kHasC0 && a.bbr) {
+    const double ss = block_sum(sums[1], sh);
+    const double sk = block_sum(sums[2], sh);
+    if (threadIdx.x == 0) {
+      const int st = a.pt.stride;
+      a.pt.buf[(size_t)SL_SS * st + lb] = ss;
+      a.pt.buf[(size_t)SL_SY * st + lb] = sk;
+    }
   }
 }
 
 template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad,
-          bool kGram2 = false, bool kUpper = false>
+          bool kGram2 = false, bool kUpper = false, bool kBBR = false>
 __global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
-  k_combine_body<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2, kUpper>(a, blockIdx.x, gridDim.x);
+  k_combine_body<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2, kUpper, kBBR>(a, blockIdx.x, gridDim.x);
 }
 
 template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad,
-          bool kGram2 = false, bool kUpper = false>
+          bool kGram2 = false, bool kUpper = false, bool kBBR = false>
 __global__ __launch_bounds__(256) void k_combine_batch(BatchPtrs<CombineArgs> b) {
   const int s = batch_system(b.off, b.S, blockIdx.x);
-  k_combine_body<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2, kUpper>(batch_arg(b, s), blockIdx.x - b.off[s],
+  k_combine_body<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2, kUpper, kBBR>(batch_arg(b, s), blockIdx.x - b.off[s],
                                                             b.off[s + 1] - b.off[s]);
 }
 
@@ -632,12 +657,12 @@ void launch_gram_t(const T* A, const T* B, int ld, int n, int p, int mask, doubl
 thread_local hipEvent_t g_launch_start = nullptr, g_launch_stop = nullptr;
 
 template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad,
-          bool kGram2 = false, bool kUpper = false>
+          bool kGram2 = false, bool kUpper = false, bool kBBR = false>
 void launch_combine_t(const CombineArgs& a, hipStream_t st) {
   constexpr size_t lds = combine_lds_bytes<kT, kHasY, kGram2>();
   // function-local static initialisation runs once even when several host threads launch
   static const bool attr = (set_lds_attr(reinterpret_cast<const void*>(
-                                k_combine<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2, kUpper>),
+                                k_combine<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2, kUpper, kBBR>),
                                 lds),
                             true);
   (void)attr;
@@ -645,12 +670,12 @@ void launch_combine_t(const CombineArgs& a, hipStream_t st) {
     // the dispatch itself records the events: the kernel's own start and end
     hipEvent_t e0 = g_launch_start, e1 = g_launch_stop;
     g_launch_start = g_launch_stop = nullptr;
-    hipExtLaunchKernelGGL((k_combine<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2, kUpper>),
+    hipExtLaunchKernelGGL((k_combine<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2, kUpper, kBBR>),
                           dim3(combine_blocks(a.n)), dim3(256), (std::uint32_t)lds, st, e0, e1,
                           0u, a);
     return;
   }
-  hipLaunchKernelGGL((k_combine<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2, kUpper>),
+  hipLaunchKernelGGL((k_combine<T, kT, kHasY, kHasC0, kRho, kGrad, kGram2, kUpper, kBBR>),
                      dim3(combine_blocks(a.n)), dim3(256), lds, st, a);
 }
 
@@ -664,6 +689,10 @@ void launch_combine_tt(const CombineArgs& a, hipStream_t st) {
   if (y && !c0 && rho && !gr) return launch_combine_t<T, kT, true, false, true, false>(a, st);
   if (y && !c0 && !rho && !gr) return launch_combine_t<T, kT, true, false, false, false>(a, st);
   if constexpr (kT <= 2) {
+    if constexpr (std::is_same<T, double>::value) {
+      if (!y && c0 && !rho && gr && a.gram_part && a.bbr)
+        return launch_combine_t<T, kT, false, true, false, true, true, false, true>(a, st);
+    }
     if (!y && c0 && !rho && gr && a.gram_part)
       return launch_combine_t<T, kT, false, true, false, true, true>(a, st);
   }
@@ -1421,16 +1450,19 @@ void combine_batch_retract_t(const BatchPtrs<CombineArgs>& b, int blocks, hipStr
                      dim3(blocks), dim3(256), lds, st, b);
 }
 
+// FP64 batches take the BB sums without X_k (CombineArgs::bbr), as lone FP64 runs do
 template <typename T, int kT>
 void combine_batch_grad_t(const BatchPtrs<CombineArgs>& b, int blocks, hipStream_t st) {
   constexpr size_t lds = combine_lds_bytes<kT, false, true>();
-  static const bool attr = (set_lds_attr(reinterpret_cast<const void*>(
-                                k_combine_batch<T, kT, false, true, false, true, true>),
-                                lds),
-                            true);
+  constexpr bool kB = std::is_same<T, double>::value;
+  static const bool attr =
+      (set_lds_attr(reinterpret_cast<const void*>(
+                        k_combine_batch<T, kT, false, true, false, true, true, false, kB>),
+                    lds),
+       true);
   (void)attr;
-  hipLaunchKernelGGL((k_combine_batch<T, kT, false, true, false, true, true>), dim3(blocks),
-                     dim3(256), lds, st, b);
+  hipLaunchKernelGGL((k_combine_batch<T, kT, false, true, false, true, true, false, kB>),
+                     dim3(blocks), dim3(256), lds, st, b);
 }
 
 template <typename T>

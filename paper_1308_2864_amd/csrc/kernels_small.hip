@@ -598,6 +598,8 @@ __device__ inline void k_qr_factor_aug_body(const QrFactor2dArgs& ka) {
     const int e = t + q * kT, r = e / P, c = e % P;
     const double sr = Ws[r][P];
     Ws[c][r] = r > c ? x[q] * sr : (r == c ? sr : 0.0);
+    // R[r][c] = M'[r][c] / sqrt(d_r) on and above the diagonal
+    if (ka.R && r < pp && c < pp) ka.R[r * pp + c] = (r <= c && r < p && c < p) ? x[q] * sr : 0.0;
   }
   __syncthreads();
   for (int e = t; e < pp * pp; e += kT) {
@@ -783,35 +785,41 @@ __device__ inline void k_finish_eval_body(const FinishEvalArgs& ka, int ks_bid, 
 #pragma unroll
     for (int sl = 0; sl < SL_COUNT; ++sl) v[sl] += (i < nb.v[sl]) ? x[sl] : 0.0;
   }
-  double acc = 0.0;
+  double acc = 0.0, racc = 0.0;
+  const bool bbr = ka.bbr_R != nullptr && ls != nullptr;
   for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
     const int i = e / p, j = e % p;
     const double d = xx[i * pp + j] - (i == j ? 1.0 : 0.0);
     acc += d * d;
+    // sum_ij (I - R)_ij (X_t^T D_t)_ij for the BB sums of a QR trial
+    if (bbr) racc += ((i == j ? 1.0 : 0.0) - ka.bbr_R[i * pp + j]) * ka.bbr_xtd[i * pp + j];
   }
-  // all SL_COUNT + 1 block sums at once: independent shuffle trees per wavefront, one
+  // all SL_COUNT + 2 block sums at once: independent shuffle trees per wavefront, one
   // barrier, then one thread per value adds the wavefront sums in wavefront order
   constexpr int kNW = kFinishThreads / kWave;
-  __shared__ double wsum[SL_COUNT + 1][kNW];
+  __shared__ double wsum[SL_COUNT + 2][kNW];
   const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) {
 #pragma unroll
     for (int sl = 0; sl < SL_COUNT; ++sl) v[sl] += __shfl_down(v[sl], o, kWave);
     acc += __shfl_down(acc, o, kWave);
+    racc += __shfl_down(racc, o, kWave);
   }
   if (lane == 0) {
 #pragma unroll
     for (int sl = 0; sl < SL_COUNT; ++sl) wsum[sl][wv] = v[sl];
     wsum[SL_COUNT][wv] = acc;
+    wsum[SL_COUNT + 1][wv] = racc;
   }
   __syncthreads();
-  __shared__ double orth;
-  if (threadIdx.x <= SL_COUNT) {
+  __shared__ double orth, rxd;
+  if (threadIdx.x <= SL_COUNT + 1) {
     double t = 0.0;
     for (int i = 0; i < kNW; ++i) t += wsum[threadIdx.x][i];
     if (threadIdx.x < SL_COUNT) red[threadIdx.x] = t;
-    else orth = t;
+    else if (threadIdx.x == SL_COUNT) orth = t;
+    else rxd = t;
   }
   __syncthreads();
   (void)sh;
@@ -852,9 +860,20 @@ __device__ inline void k_finish_eval_body(const FinishEvalArgs& ka, int ks_bid, 
   o.nuclear = en;
   o.total = o.kinetic + o.external + o.hartree + o.xc + o.nuclear;
   o.g2 = red[SL_DD];
-  o.ss = red[SL_SS];
-  o.sy = red[SL_SY];
-  o.yy = red[SL_YY];
+  if (bbr) {
+    // QR trial X_t = (X_k - tau D_k) R^{-1}: with s = X_t - X_k = X_t (I - R) - tau D_k and
+    // y = D_t - D_k, from ||s||^2 and <s, D_k> (retraction pass) and c = <D_k, D_t>
+    // (gradient pass): <s, D_t> = sum (I - R) o (X_t^T D_t) - tau c,
+    // ||y||^2 = ||D_t||^2 - 2 c + ||D_k||^2
+    const double cr = red[SL_YY];
+    o.ss = red[SL_SS];
+    o.sy = rxd - s0.tau * cr - red[SL_SY];
+    o.yy = red[SL_DD] - 2.0 * cr + s0.g2;
+  } else {
+    o.ss = red[SL_SS];
+    o.sy = red[SL_SY];
+    o.yy = red[SL_YY];
+  }
   o.orth2 = acc;
   o.defect2 = red[SL_DEFECT];
   if (cg) {
@@ -1061,20 +1080,24 @@ void launch_grad_weights(const double* gram, int pp, double* W, hipStream_t st) 
 }
 
 void launch_qr_factor(const double* xx, const double* gxd, int p, int pp, const double* tau,
-                      double* A, double* B, double* work, int* status, hipStream_t st) {
+                      double* A, double* B, double* work, int* status, hipStream_t st,
+                      double* R) {
   if (p <= 16) {
     hipLaunchKernelGGL(k_qr_factor_aug<16>, dim3(1), dim3(qr_factor_threads<16>()), 0, st,
-                       QrFactor2dArgs{xx, gxd, p, pp, tau, A, B, status});
+                       QrFactor2dArgs{xx, gxd, p, pp, tau, A, B, status, nullptr, nullptr,
+                                      nullptr, R});
     return;
   }
   if (p <= 32) {
     hipLaunchKernelGGL(k_qr_factor_aug<32>, dim3(1), dim3(qr_factor_threads<32>()), 0, st,
-                       QrFactor2dArgs{xx, gxd, p, pp, tau, A, B, status});
+                       QrFactor2dArgs{xx, gxd, p, pp, tau, A, B, status, nullptr, nullptr,
+                                      nullptr, R});
     return;
   }
   if (p <= 64) {
     hipLaunchKernelGGL(k_qr_factor_aug<64>, dim3(1), dim3(qr_factor_threads<64>()), 0, st,
-                       QrFactor2dArgs{xx, gxd, p, pp, tau, A, B, status});
+                       QrFactor2dArgs{xx, gxd, p, pp, tau, A, B, status, nullptr, nullptr,
+                                      nullptr, R});
     return;
   }
   if (p > 128) {
@@ -1220,12 +1243,14 @@ void launch_finish_eval(const double* part, int stride, const int* nblk, double*
                         const double* gram_xx, int p, int pp, double f, double dV,
                         const double* enuc, const CgState* cg, EvalOut* out, LsState* ls,
                         const LsParams* prm, hipStream_t st, CgState* cgw, double htol,
-                        int hmaxit, const double* ebc) {
+                        int hmaxit, const double* ebc, const double* bbr_R,
+                        const double* bbr_xtd) {
   ScalarCounts nb{};
   for (int i = 0; i < SL_COUNT; ++i) nb.v[i] = nblk[i];
   hipLaunchKernelGGL(k_finish_eval, dim3(1), dim3(kFinishThreads), 0, st,
                      FinishEvalArgs{part, stride, nb, sums, gram_xx, p, pp, f, dV, enuc, cg, out,
-                         ls, prm ? *prm : LsParams{}, cgw, htol, hmaxit, ebc});
+                         ls, prm ? *prm : LsParams{}, cgw, htol, hmaxit, ebc, bbr_R,
+                         bbr_xtd});
 }
 
 void launch_set_scalar(double* dst, double v, hipStream_t st) {

@@ -119,6 +119,7 @@ struct ks_system {
   double *gxg[2] = {}, *gxd[2] = {}, *W = nullptr, *A = nullptr, *B = nullptr;
   double *work = nullptr, *gram_part = nullptr, *spart = nullptr, *cgpart = nullptr;
   double* gsub = nullptr;
+  double* Rq = nullptr;  // the Cholesky factor R of the last QR trial (BB sums without X_k)
   double* sums[2] = {};
   CgState* cg = nullptr;
   EvalOut* ev[2] = {};
@@ -221,6 +222,7 @@ void layout(ks_system* s, char* base, size_t* total) {
   s->W = c.take<double>(pp2);
   s->A = c.take<double>(pp2);
   s->B = c.take<double>(pp2);
+  s->Rq = c.take<double>(pp2);
   s->work = c.take<double>(small_work_doubles(s->p));
   s->gram_nchunks = gram_chunks(s->n, s->pp);
   s->gram_part = c.take<double>(gram_part_doubles(s->n, s->pp));
@@ -450,6 +452,11 @@ void harvest(ks_system* s);
 
 // The CG and line-search records with one copy and one synchronisation (they are
 // adjacent on the device, see layout()).
+// QR trials of FP64 runs on the 7-point grid with p_p <= 32 take their BB sums without a
+// pass over X_k (CombineArgs::bbr): the retraction sums ||s||^2 and <s, D_k>, the gradient
+// pass <D_k, D_t>, and the summary combines them with R and X_t^T D_t.
+bool bbr_ok(const ks_system* s) { return !s->q1 && !s->f32 && s->pp <= 32; }
+
 int readback_cg_ls(ks_system* s) {
   const size_t bytes = reinterpret_cast<char*>(s->ls + 1) - reinterpret_cast<char*>(s->cg);
   hipError_t e = hipMemcpyAsync(s->host, s->cg, bytes, hipMemcpyDeviceToHost, s->st);
@@ -486,6 +493,7 @@ int readback_cg_ls_ahead(ks_system* s, int c) {
     a.sel = s->ls;
     a.xx_rej = s->q1 ? s->feg[c] + pp2 : s->gxg[c];
     a.gxd_rej = s->gxd[c];
+    a.R = bbr_ok(s) ? s->Rq : nullptr;
     tbeg(s, KS_PH_SMALL);
     launch_qr_factor_next(a, s->st);
     tend(s, KS_PH_SMALL);
@@ -725,7 +733,10 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
   // D = G - X (G^T X) with ||D||^2, the BB sums and (QR) the Gram blocks X^T D, D^T D:
   // up to 32 columns they come out of the same kernel, wider blocks take a Gram launch
   const bool fused = want_gxd && s->pp <= 32;
+  // a QR trial (want_gxd) judged here: BB sums without X_k
+  const bool bbr = bb_ref >= 0 && want_gxd && judge != nullptr && bbr_ok(s);
   CombineArgs ca{};
+  ca.bbr = bbr;
   ca.X = Xs;
   ca.A = s->W;
   ca.C0 = s->G[idx];
@@ -784,7 +795,8 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
   launch_finish_eval(s->spart, kPartStride, nblk, s->sums[idx], s->gxg[idx], s->p, s->pp, s->f,
                      s->grid.dV, s->enuc, s->use_h ? s->cg : nullptr, s->ev[idx],
                      judge ? s->ls : nullptr, judge, s->st, fuse_cg ? s->cg : nullptr, s->htol,
-                     s->hmaxit, s->ebc);
+                     s->hmaxit, s->ebc, bbr ? s->Rq : nullptr,
+                     bbr ? s->gxd[idx] + s->pp * s->pp : nullptr);
   tend(s, KS_PH_SMALL);
   return launch_check(s, "evaluate");
 }
@@ -1018,11 +1030,14 @@ int enqueue_trial(ks_system* s, int c, bool qr, const LsParams& lp, const ks_opt
     if (!queued) {
       tbeg(s, KS_PH_SMALL);
       launch_qr_factor(s->q1 ? s->feg[c] + s->pp * s->pp : s->gxg[c], s->gxd[c], s->p, s->pp,
-                       &s->ls->tau, s->A, s->B, s->work, &s->ls->error, s->st);
+                       &s->ls->tau, s->A, s->B, s->work, &s->ls->error, s->st,
+                       bbr_ok(s) ? s->Rq : nullptr);
       tend(s, KS_PH_SMALL);
     }
     ca.Y = s->D[c];
     ca.upper = true;
+    ca.bbr = bbr_ok(s);
+    ca.pt = Partials{s->spart, kPartStride};
   } else {
     tbeg(s, KS_PH_SMALL);
     launch_wy_factor(s->q1 ? s->wyg[c] : s->gxg[c], s->p, s->pp, &s->ls->tau, prm.reorth_tol,
@@ -1301,13 +1316,14 @@ void fill_typed(ks_system* s, std::vector<char>& buf, int c) {
   const int t = 1 - c;
   Partials pt{s->spart, kPartStride};
   // retraction: X_t = X_c A + D_c B with the density (QR weights)
+  double* rq = bbr_ok(s) ? s->Rq : nullptr;
   put_rec(buf, c, R_QR, QrFactor2dArgs{s->gxg[c], s->gxd[c], s->p, s->pp, &s->ls->tau, s->A,
-                                        s->B, &s->ls->error});
+                                        s->B, &s->ls->error, nullptr, nullptr, nullptr, rq});
   // the factor of the trial after a trial from slot c, queued before the host reads the
   // record: slot t when that trial is accepted, slot c otherwise (QrFactor2dArgs::sel)
   put_rec(buf, c, R_QR_NEXT, QrFactor2dArgs{s->gxg[t], s->gxd[t], s->p, s->pp, &s->ls->tau,
                                              s->A, s->B, &s->ls->error, s->ls, s->gxg[c],
-                                             s->gxd[c]});
+                                             s->gxd[c], rq});
   CombineArgs rt{};
   rt.X = s->X[c];
   rt.A = s->A;
@@ -1321,6 +1337,8 @@ void fill_typed(ks_system* s, std::vector<char>& buf, int c) {
   rt.n = s->n;
   rt.p = s->p;
   rt.f32 = s->f32;
+  rt.bbr = bbr_ok(s);
+  rt.pt = pt;
   put_rec(buf, c, R_RETRACT, rt);
   // Hartree: V_H of slot t = V_H(c) + L^{-1}(b - L V_H(c)) by the fast diagonalisation,
   // then the CG start that measures its residual (a solve that misses the tolerance is
@@ -1362,6 +1380,7 @@ void fill_typed(ks_system* s, std::vector<char>& buf, int c) {
   gd.n = s->n;
   gd.p = s->p;
   gd.f32 = s->f32;
+  gd.bbr = bbr_ok(s);  // the FP64 batch kernel always takes this form
   put_rec(buf, c, R_GRAD, gd);
   put_rec(buf, c, R_RED2, GramReduceArgs{s->gram_part, combine_blocks(s->n), s->pp,
                                          kGramAB | kGramBB, s->gxd[t], nullptr});
@@ -1381,10 +1400,12 @@ int upload_records(ks_system* s, const MinRun& m) {
     nblk[SL_EBC] = s->vbc ? scalar_blocks(s->n) : 0;
     ScalarCounts sc{};
     for (int i = 0; i < SL_COUNT; ++i) sc.v[i] = nblk[i];
+    const bool bbr = bbr_ok(s);
     put_rec(buf, c, R_FINISH, FinishEvalArgs{s->spart, kPartStride, sc, s->sums[t], s->gxg[t],
                                              s->p, s->pp, s->f, s->grid.dV, s->enuc, s->cg,
                                              s->ev[t], s->ls, m.lp, s->cg, s->htol,
-                                             s->hmaxit, s->ebc});
+                                             s->hmaxit, s->ebc, bbr ? s->Rq : nullptr,
+                                             bbr ? s->gxd[t] + s->pp * s->pp : nullptr});
   }
   int rc = hip_check(s, hipMemcpyAsync(s->rec, buf.data(), kRecBytes, hipMemcpyHostToDevice,
                                        s->st), "record upload");

@@ -581,6 +581,10 @@ struct CombineArgs {
   int pk;                               // columns of X and Y to contract over (0: p)
   bool mc;                              // float data, blocks wider than 64 columns: fp32
                                         // matrix cores with FP64 sums across chains
+  // BB sums of a QR trial without a pass over X_k (FP64, p_p <= 32).  Retraction: also the
+  // partials of ||s||^2 (SL_SS) and <s, D_k> (SL_SY), s = out - X (X = X_k, Y = D_k).
+  // Gradient: X_k is not read; the partials are ||D||^2 (SL_DD) and <D_k, D> (SL_YY).
+  bool bbr;
 };
 void launch_combine(const CombineArgs& a, hipStream_t st);
 // Events for the next single-kernel combine launch of this host thread: that launch records
@@ -632,6 +636,7 @@ struct QrFactor2dArgs {
   const LsState* sel;
   const double* xx_rej;
   const double* gxd_rej;
+  double* R;  // optional (p <= 64): the Cholesky factor R itself, p_p x p_p, zero below
 };
 
 struct FinishEvalArgs {
@@ -655,12 +660,17 @@ struct FinishEvalArgs {
   double htol;
   int hmaxit;
   const double* ebc;  // the constant -(1/2) Q V_bc(c) of the monopole boundary (or nullptr)
+  // BB sums of a QR trial without X_k in the gradient pass (with ls; see CombineArgs::bbr):
+  // R (p_p x p_p, the trial's Cholesky factor) and X_t^T D_t (p_p x p_p)
+  const double* bbr_R;
+  const double* bbr_xtd;
 };
 
 
 void launch_grad_weights(const double* gram, int pp, double* W, hipStream_t st);
 void launch_qr_factor(const double* xx, const double* gxd, int p, int pp, const double* tau,
-                      double* A, double* B, double* work, int* status, hipStream_t st);
+                      double* A, double* B, double* work, int* status, hipStream_t st,
+                      double* R = nullptr);
 // Per-tile partials (ceil(p/16)^2 of them, written to part) of ||xg - (xd - xx W)||_F^2:
 // with xd = X^T D and xx = X^T X exact products of the stored blocks (X^T B D, X^T B X for
 // finite elements) and D = G + X W, xd - xx W is the exact X^T G, so this is the error of
@@ -685,7 +695,8 @@ void launch_finish_eval(const double* part, int stride, const int* nblk, double*
                         const double* gram_xx, int p, int pp, double f, double dV,
                         const double* enuc, const CgState* cg, EvalOut* out, LsState* ls,
                         const LsParams* prm, hipStream_t st, CgState* cgw = nullptr,
-                        double htol = 0.0, int hmaxit = 0, const double* ebc = nullptr);
+                        double htol = 0.0, int hmaxit = 0, const double* ebc = nullptr,
+                        const double* bbr_R = nullptr, const double* bbr_xtd = nullptr);
 void launch_set_scalar(double* dst, double v, hipStream_t st);
 void launch_qr_factor_batch(const BatchPtrs<QrFactor2dArgs>& b, int p_max, hipStream_t st);
 void launch_finish_eval_batch(const BatchPtrs<FinishEvalArgs>& b, hipStream_t st);
