@@ -778,8 +778,8 @@ def main():
     kernel_names = {"hamiltonian": "k_hx_gram<double>", "gram": "k_gram<double,2,3>",
                     "gradient": ("k_combine<double,2,false,true,false,true,true,false,true>"
                                  if args.retraction == "qr" and spec.p <= 32 else
-                                 "k_combine<double,2,false,true,false,true,true,false>"),
-                    "retract": "k_combine<double,2,true,false,true,false,false,true>"}
+                                 "k_combine<double,2,false,true,false,true,true,false,false>"),
+                    "retract": "k_combine<double,2,true,false,true,false,false,true,false>"}
     traffic = pmc_traffic(kernel_names[dom]) if args.hartree == "pcg_fd" else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
