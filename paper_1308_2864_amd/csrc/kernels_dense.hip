@@ -241,7 +241,9 @@ __device__ inline void k_gram_reduce_body(const GramReduceArgs& ka, int ks_bid, 
   const double* __restrict__ q = ka.part + (size_t)prod * per + ij0 + c;
   const size_t cs = (size_t)3 * per;
   double sum = 0.0;
-  for (int c0 = g; c0 < nchunks; c0 += kRedGroups * kRedU) {
+  const bool formula = prod == 1 && ka.xd_xx != nullptr;  // X^T G + (X^T X) W, group g: k = g
+  if (formula && g < pp) sum = ka.xd_xx[i * pp + g] * ka.xd_W[g * pp + j0 + c];
+  for (int c0 = g; !formula && c0 < nchunks; c0 += kRedGroups * kRedU) {
     double v[kRedU];
 #pragma unroll
     for (int u = 0; u < kRedU; ++u) {
@@ -258,6 +260,7 @@ __device__ inline void k_gram_reduce_body(const GramReduceArgs& ka, int ks_bid, 
     double t = 0.0;
     for (int k = 0; k < kRedGroups; ++k) t += red[k][c];
     const int j = j0 + c;
+    if (formula) t += ka.xd_xg[i * pp + j];
     double* out = ka.out + (size_t)prod * per;
     out[i * pp + j] = t;
     if (sym && i / 16 < j / 16) out[j * pp + i] = t;
@@ -489,7 +492,7 @@ __device__ inline void combine_tiles(const CombineArgs& a, double* lds, int t_be
       double* ds = xs + 16 * kGS;
 #pragma unroll
       for (int s2 = 0; s2 < kS; ++s2) {
-        xs[c * kGS + comb_col(s2, q)] = f.x.v[s2];
+        if constexpr (!kBBR) xs[c * kGS + comb_col(s2, q)] = f.x.v[s2];
         ds[c * kGS + comb_col(s2, q)] = dv[s2];
       }
 #pragma unroll
@@ -497,14 +500,19 @@ __device__ inline void combine_tiles(const CombineArgs& a, double* lds, int t_be
         double fa[kT], fd[kT];
 #pragma unroll
         for (int t = 0; t < kT; ++t) {
-          fa[t] = xs[(4 * kk + q) * kGS + 16 * t + c];
+          if constexpr (!kBBR) fa[t] = xs[(4 * kk + q) * kGS + 16 * t + c];
           fd[t] = ds[(4 * kk + q) * kGS + 16 * t + c];
         }
         int g = 0;
+        // kBBR: X^T D is formed from X^T G, X^T X and W by the reduction instead
+        if constexpr (!kBBR) {
 #pragma unroll
-        for (int ti = 0; ti < kT; ++ti)
+          for (int ti = 0; ti < kT; ++ti)
 #pragma unroll
-          for (int tj = 0; tj < kT; ++tj, ++g) g2.t[g] = mfma16(fa[ti], fd[tj], g2.t[g]);
+            for (int tj = 0; tj < kT; ++tj, ++g) g2.t[g] = mfma16(fa[ti], fd[tj], g2.t[g]);
+        } else {
+          g = kT * kT;
+        }
 #pragma unroll
         for (int ti = 0; ti < kT; ++ti)
 #pragma unroll
@@ -558,14 +566,20 @@ __device__ inline void k_combine_body(const CombineArgs& a, int ks_bid, int ks_n
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     __syncthreads();  // every wave is done with its LDS patch
 #pragma unroll
-    for (int t = 0; t < Gram2Acc<kT>::kN; ++t) wave_reduce_tile(g2.t[t], red, w, lane);
+    for (int t = kBBR ? kT * kT : 0; t < Gram2Acc<kT>::kN; ++t)
+      wave_reduce_tile(g2.t[t], red, w, lane);
     if (w == 0) {
       const int lr = lane / 16, lc = lane % 16;
       int g = 0;
+      if constexpr (!kBBR) {
 #pragma unroll
-      for (int ti = 0; ti < kT; ++ti)
+        for (int ti = 0; ti < kT; ++ti)
 #pragma unroll
-        for (int tj = 0; tj < kT; ++tj) put_tile<kPP>(a.gram_part, lb, 1, ti, tj, g2.t[g++], lr, lc);
+          for (int tj = 0; tj < kT; ++tj)
+            put_tile<kPP>(a.gram_part, lb, 1, ti, tj, g2.t[g++], lr, lc);
+      } else {
+        g = kT * kT;
+      }
 #pragma unroll
       for (int ti = 0; ti < kT; ++ti)
 #pragma unroll
@@ -758,10 +772,11 @@ void launch_gram(const void* A, const void* B, bool f32, int ld, int n, int p, i
 }
 
 void launch_gram_reduce(const double* partials, int nchunks, int pp, int mask, double* out,
-                        double* W, hipStream_t st) {
+                        double* W, hipStream_t st, const double* xd_xg, const double* xd_xx,
+                        const double* xd_W) {
   hipLaunchKernelGGL(k_gram_reduce, dim3(gram_reduce_blocks(pp)), dim3(kRedCols * kRedGroups), 0,
                      st,
-                     GramReduceArgs{partials, nchunks, pp, mask, out, W});
+                     GramReduceArgs{partials, nchunks, pp, mask, out, W, xd_xg, xd_xx, xd_W});
 }
 
 int combine_blocks(int n) {

@@ -782,9 +782,14 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
                        s->spart + (size_t)SL_DEFECT * kPartStride, s->st);
   }
   tbeg(s, KS_PH_SMALL);
-  if (fused)
+  if (fused) {
+    // after the gradient pass of a QR trial (bbr), X^T D = X^T G + (X^T X) W comes from the
+    // reduced blocks; that pass formed only D^T D
+    const int pp2 = s->pp * s->pp;
     launch_gram_reduce(s->gram_part, combine_blocks(s->n), s->pp, mask2, s->gxd[idx], nullptr,
-                       s->st);
+                       s->st, bbr ? s->gxg[idx] + pp2 : nullptr, bbr ? s->gxg[idx] : nullptr,
+                       bbr ? s->W : nullptr);
+  }
   int nblk[kMaxScalarSlots] = {};
   nblk[SL_KIN] = hxg ? hx_gram_blocks(s->n) : hx_blocks(s->n, s->p);
   nblk[SL_EH] = nblk[SL_EX] = nblk[SL_EXT] = nblk[SL_TF] = scalar_blocks(s->n);
@@ -1382,8 +1387,11 @@ void fill_typed(ks_system* s, std::vector<char>& buf, int c) {
   gd.f32 = s->f32;
   gd.bbr = bbr_ok(s);  // the FP64 batch kernel always takes this form
   put_rec(buf, c, R_GRAD, gd);
+  const bool bbr = bbr_ok(s);  // the FP64 gradient kernel forms only D^T D
   put_rec(buf, c, R_RED2, GramReduceArgs{s->gram_part, combine_blocks(s->n), s->pp,
-                                         kGramAB | kGramBB, s->gxd[t], nullptr});
+                                         kGramAB | kGramBB, s->gxd[t], nullptr,
+                                         bbr ? s->gxg[t] + s->pp * s->pp : nullptr,
+                                         bbr ? s->gxg[t] : nullptr, bbr ? s->W : nullptr});
 }
 
 int upload_records(ks_system* s, const MinRun& m) {

@@ -551,6 +551,11 @@ struct GramReduceArgs {
   int mask;
   double* out;
   double* W;
+  // optional (p <= 64): product 1 (X^T D of D = G + X W) formed as X^T G + (X^T X) W from
+  // these reduced blocks instead of from partials
+  const double* xd_xg;
+  const double* xd_xx;
+  const double* xd_W;
 };
 
 
@@ -562,7 +567,8 @@ void launch_gram(const void* A, const void* B, bool f32, int ld, int n, int p, i
                  double* partials, int nchunks, hipStream_t st);
 // out: [3][pp][pp]; products outside mask are not written; W (nullable) = -(A^T B)^T
 void launch_gram_reduce(const double* partials, int nchunks, int pp, int mask, double* out,
-                        double* W, hipStream_t st);
+                        double* W, hipStream_t st, const double* xd_xg = nullptr,
+                        const double* xd_xx = nullptr, const double* xd_W = nullptr);
 struct CombineArgs {
   // orbital blocks are float when f32, else double; weights and sums are double
   const void* X; const double* A;       // X (n x ld) times A (pp x pp)
