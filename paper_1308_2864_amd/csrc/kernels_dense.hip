@@ -586,35 +586,36 @@ __device__ inline void k_combine_body(const CombineArgs& a, int ks_bid, int ks_n
         for (int tj = ti; tj < kT; ++tj) put_tile<kPP>(a.gram_part, lb, 2, ti, tj, g2.t[g++], lr, lc);
     }
   }
+  // the block sums with one barrier (block_sum_n: each in block_sum's order)
+  __shared__ double shn[4 * (kBlock / kWave)];
   if (kGrad && kBBR) {
-    const double dd = block_sum(sums[0], sh);
-    const double cr = block_sum(sums[3], sh);
+    double v[2] = {sums[0], sums[3]};
+    block_sum_n<2>(v, shn);
     if (threadIdx.x == 0) {
       const int st = a.pt.stride;
-      a.pt.buf[(size_t)SL_DD * st + lb] = dd;
-      a.pt.buf[(size_t)SL_YY * st + lb] = cr;
+      a.pt.buf[(size_t)SL_DD * st + lb] = v[0];
+      a.pt.buf[(size_t)SL_YY * st + lb] = v[1];
     }
   } else if (kGrad) {
-    const double dd = block_sum(sums[0], sh);
-    const double ss = block_sum(sums[1], sh);
-    const double sy = block_sum(sums[2], sh);
-    const double yy = block_sum(sums[3], sh);
+    double v[4] = {sums[0], sums[1], sums[2], sums[3]};
+    block_sum_n<4>(v, shn);
     if (threadIdx.x == 0) {
       const int st = a.pt.stride;
-      a.pt.buf[(size_t)SL_DD * st + lb] = dd;
-      a.pt.buf[(size_t)SL_SS * st + lb] = ss;
-      a.pt.buf[(size_t)SL_SY * st + lb] = sy;
-      a.pt.buf[(size_t)SL_YY * st + lb] = yy;
+      a.pt.buf[(size_t)SL_DD * st + lb] = v[0];
+      a.pt.buf[(size_t)SL_SS * st + lb] = v[1];
+      a.pt.buf[(size_t)SL_SY * st + lb] = v[2];
+      a.pt.buf[(size_t)SL_YY * st + lb] = v[3];
     }
   } else if (kHasY && !kHasC0 && a.bbr) {
-    const double ss = block_sum(sums[1], sh);
-    const double sk = block_sum(sums[2], sh);
+    double v[2] = {sums[1], sums[2]};
+    block_sum_n<2>(v, shn);
     if (threadIdx.x == 0) {
       const int st = a.pt.stride;
-      a.pt.buf[(size_t)SL_SS * st + lb] = ss;
-      a.pt.buf[(size_t)SL_SY * st + lb] = sk;
+      a.pt.buf[(size_t)SL_SS * st + lb] = v[0];
+      a.pt.buf[(size_t)SL_SY * st + lb] = v[1];
     }
   }
+  (void)sh;
 }
 
 template <typename T, int kT, bool kHasY, bool kHasC0, bool kRho, bool kGrad,

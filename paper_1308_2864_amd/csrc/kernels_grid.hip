@@ -238,24 +238,20 @@ __device__ inline void k_xc_body(const XcArgs& ka, int ks_bid, int ks_nb) {
     ex += r * e;
     ee += r * ve;
   }
-  eh = block_sum(eh, sh);
-  ex = block_sum(ex, sh);
-  ee = block_sum(ee, sh);
-  et = block_sum(et, sh);
-  write_partial(pt, SL_EH, lb, eh);
-  write_partial(pt, SL_EX, lb, ex);
-  write_partial(pt, SL_EXT, lb, ee);
-  write_partial(pt, SL_TF, lb, et);
-  if (ka.vbc) {
-    eb = block_sum(eb, sh);
-    write_partial(pt, SL_EBC, lb, eb);
-  }
+  // all block sums with one barrier (each in block_sum's order)
+  __shared__ double shn[7 * (kBlock / kWave)];
+  double v[7] = {eh, ex, ee, et, eb, rr, bb};
+  block_sum_n<7>(v, shn);
+  write_partial(pt, SL_EH, lb, v[0]);
+  write_partial(pt, SL_EX, lb, v[1]);
+  write_partial(pt, SL_EXT, lb, v[2]);
+  write_partial(pt, SL_TF, lb, v[3]);
+  if (ka.vbc) write_partial(pt, SL_EBC, lb, v[4]);
   if (cg_check) {
-    rr = block_sum(rr, sh);
-    bb = block_sum(bb, sh);
-    write_partial(pt, SL_CGRR, lb, rr);
-    write_partial(pt, SL_CGBB, lb, bb);
+    write_partial(pt, SL_CGRR, lb, v[5]);
+    write_partial(pt, SL_CGBB, lb, v[6]);
   }
+  (void)sh;
 }
 
 __global__ void k_xc(XcArgs ka) {

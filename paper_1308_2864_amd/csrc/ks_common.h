@@ -212,6 +212,33 @@ __device__ inline double block_sum(double v, double* sh) {
   return s;
 }
 
+// block_sum of N values at once (one barrier): each value is summed in the same order as
+// block_sum sums it, so the results are bitwise those of N block_sum calls.  sh holds
+// N * (blockDim.x / kWave) doubles; the sums are valid in thread 0, whose values v[] are
+// replaced by them.
+template <int N>
+__device__ inline void block_sum_n(double (&v)[N], double* sh) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] += __shfl_down(v[k], o, kWave);
+  }
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) sh[k * nw + w] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double s = 0.0;
+      for (int i = 0; i < nw; ++i) s += sh[k * nw + i];
+      v[k] = s;
+    }
+  }
+}
+
 // ------------------------------------------------------------------------------------
 // Batched launches.  A batched kernel runs the body of a single-system kernel for up to
 // kMaxBatch systems in one launch: system s owns blocks [off[s], off[s+1]) and its
