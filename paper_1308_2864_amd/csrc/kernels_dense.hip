@@ -389,9 +389,26 @@ __device__ inline void combine_tiles(const CombineArgs& a, double* lds, int t_be
   const int ld = a.ld, p = a.p, n = a.n;
   const int pk = a.pk ? a.pk : a.p;  // columns of X and Y (the contraction) to read
 
-  // operands of one tile
+  // operands of one tile (v0: the warm start and its six neighbours at the lane's row)
   struct Tile {
     CombineFrag<kT> x, y, c0, xk, dk;
+    double v0[7];
+  };
+  const bool resid = kRho && a.resid != nullptr;
+  auto load_v0 = [&](Tile& f, int row) {
+    // x0 at row and its neighbours in the order of the Laplacian's sum (-x, +x, -y, +y,
+    // -z, +z); a neighbour outside the grid is not summed (zero Dirichlet values)
+    const int r = row < n ? row : n - 1;
+    const int nx = a.gnx, ny = a.gny, sy = nx, sz = nx * ny;
+    const int i = r % nx, j = (r / nx) % ny, k = r / sz;
+    const double* x0 = a.resid_x0;
+    f.v0[0] = x0[r];
+    f.v0[1] = i > 0 ? x0[r - 1] : 0.0;
+    f.v0[2] = i < nx - 1 ? x0[r + 1] : 0.0;
+    f.v0[3] = j > 0 ? x0[r - sy] : 0.0;
+    f.v0[4] = j < ny - 1 ? x0[r + sy] : 0.0;
+    f.v0[5] = k > 0 ? x0[r - sz] : 0.0;
+    f.v0[6] = k < a.gnz - 1 ? x0[r + sz] : 0.0;
   };
   auto load = [&](Tile& f, int tile) {
     const int row = tile * 16 + c;
@@ -402,6 +419,9 @@ __device__ inline void combine_tiles(const CombineArgs& a, double* lds, int t_be
     if constexpr (kGrad) {
       if constexpr (!kBBR) comb_load<T, kT, kVec, true>(aXk, ld, n, p, row, q, f.xk);
       comb_load<T, kT, kVec, true>(aDk, ld, n, p, row, q, f.dk);
+    }
+    if constexpr (kRho) {
+      if (resid) load_v0(f, row);
     }
   };
   auto compute = [&](const Tile& f, int tile) {
@@ -481,7 +501,24 @@ __device__ inline void combine_tiles(const CombineArgs& a, double* lds, int t_be
     if constexpr (kRho) {
       sq += __shfl_xor(sq, 16, kWave);
       sq += __shfl_xor(sq, 32, kWave);
-      if (q == 0 && rok) a.rho[row] = a.rho_scale * sq;
+      const double rv = a.rho_scale * sq;
+      if (q == 0 && rok) a.rho[row] = rv;
+      if (resid && q == 0 && rok) {
+        // b - L x0 with the CG start's arithmetic: b = 4 pi rhs_scale rho,
+        // L x0 = (6 x0 - sum of neighbours) / h^2
+        const double* v = f.v0;
+        const int nx = a.gnx, ny = a.gny, sz = nx * ny;
+        const int i = row % nx, j = (row / nx) % ny, k = row / sz;
+        double nb = 0.0;
+        if (i > 0) nb += v[1];
+        if (i < nx - 1) nb += v[2];
+        if (j > 0) nb += v[3];
+        if (j < ny - 1) nb += v[4];
+        if (k > 0) nb += v[5];
+        if (k < a.gnz - 1) nb += v[6];
+        const double b = 4.0 * kPi * a.rhs_scale * rv;
+        a.resid[row] = b - (6.0 * v[0] - nb) * a.inv_h2;
+      }
     }
     if constexpr (kGram2) {
       // X^T D and D^T D of the tile: the grid rows must be the contraction index, so the

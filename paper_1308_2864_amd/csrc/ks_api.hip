@@ -136,6 +136,7 @@ struct ks_system {
   bool fuse_cg = false;  // the next exchange pass measures the Hartree residual (see hartree)
   bool cg_fused = false;  // the last evaluation measured it there (its r was not stored)
   bool pcg_probe = false;  // the first trial of a run queues one to see whether it is needed
+  bool resid_ready = false;  // the retraction formed the next Hartree solve's first residual
   long long cg_total = 0;
   // optional phase timers
   struct Pending {
@@ -643,7 +644,9 @@ int hartree(ks_system* s, const double* rho, const double* x0, double* x, bool w
     // preconditioner: x = x0 + L^{-1}(b - L x0).  The CG start then measures the residual
     // of x and counts the iteration; only a solve that misses the tolerance continues with
     // PCG iterations (for a queued trial the caller does that: hartree_pending).
-    launch_cg_residual(rho, x0, s->cg_r, s->cg_p[0], s->grid, s->cgpart, s->st);
+    // (a trial's retraction forms r = b - L x0 with its density: CombineArgs::resid)
+    if (!s->resid_ready) launch_cg_residual(rho, x0, s->cg_r, s->cg_p[0], s->grid, s->cgpart, s->st);
+    s->resid_ready = false;
     launch_fd_correct(s->cg_r, x0, x, s->cg_q, fd_ops(s), s->grid, s->st);
     if (fuse && s->pcg_extra == 0) {
       // a trial that queues no continuation: its exchange pass measures the residual and
@@ -1016,6 +1019,17 @@ namespace {
 // judgement, all on the device.  Nothing in it waits for the host, so it can be captured
 // into a graph; with the plain CG Hartree solver the evaluation waits for convergence.
 // queued: the QR factor of this trial was already queued by readback_cg_ls_ahead.
+// Fields of a retraction combine that also forms r = 4 pi rhs_scale rho - L x0.
+void set_resid(CombineArgs& ca, const ks_system* s, const double* x0) {
+  ca.resid = s->cg_r;
+  ca.resid_x0 = x0;
+  ca.gnx = s->grid.nx;
+  ca.gny = s->grid.ny;
+  ca.gnz = s->grid.nz;
+  ca.inv_h2 = s->grid.inv_h2;
+  ca.rhs_scale = s->grid.rhs_scale;
+}
+
 int enqueue_trial(ks_system* s, int c, bool qr, const LsParams& lp, const ks_opt_params& prm,
                   bool queued = false) {
   const int t = 1 - c;
@@ -1050,11 +1064,17 @@ int enqueue_trial(ks_system* s, int c, bool qr, const LsParams& lp, const ks_opt
     tend(s, KS_PH_SMALL);
     ca.Y = s->q1 ? s->Gt[c] : s->G[c];
   }
+  const bool pcg = s->solver == KS_HARTREE_PCG_FD;
+  if (pcg && s->use_h && !s->q1) {
+    // the first residual of the trial's Hartree solve, from its warm start V_H(c)
+    set_resid(ca, s, s->vh[c]);
+    s->resid_ready = true;
+  }
   tbeg(s, KS_PH_RETRACT);
   launch_combine(ca, s->st);
   tend(s, KS_PH_RETRACT);
-  const bool pcg = s->solver == KS_HARTREE_PCG_FD;
   int rc = evaluate(s, t, true, c, c, qr, !qr, !pcg, &lp);
+  s->resid_ready = false;  // consumed by that solve (or dropped with an error)
   if (rc) return rc;
   return launch_check(s, "line search");
 }
@@ -1344,6 +1364,7 @@ void fill_typed(ks_system* s, std::vector<char>& buf, int c) {
   rt.f32 = s->f32;
   rt.bbr = bbr_ok(s);
   rt.pt = pt;
+  set_resid(rt, s, s->vh[c]);  // the first residual of the Hartree solve (no k_init launch)
   put_rec(buf, c, R_RETRACT, rt);
   // Hartree: V_H of slot t = V_H(c) + L^{-1}(b - L V_H(c)) by the fast diagonalisation,
   // then the CG start that measures its residual (a solve that misses the tolerance is
@@ -1516,8 +1537,7 @@ void launch_trial_batch(const std::vector<BatchMember*>& g, hipStream_t st,
     return fd_launch(s->grid).z_blocks;
   };
   auto hb = [](const ks_system* s) { return hartree_blocks(s->n); };
-  auto r0 = table<InitArgs>(g, R_RESID, hb, &tot, par);
-  launch_init_batch(r0, tot, st);
+  (void)hb;  // the retraction formed each member's first Hartree residual
   auto p1 = table<FdPlaneArgs>(g, R_PLANE1, pb, &tot, par);
   launch_fd_plane_batch(p1, tot, mode, lds_p, st);
   auto fz = table<FdZArgs>(g, R_FDZ, zb, &tot, par);

@@ -618,6 +618,12 @@ struct CombineArgs {
   // partials of ||s||^2 (SL_SS) and <s, D_k> (SL_SY), s = out - X (X = X_k, Y = D_k).
   // Gradient: X_k is not read; the partials are ||D||^2 (SL_DD) and <D_k, D> (SL_YY).
   bool bbr;
+  // optional with rho (7-point grid): resid = 4 pi rhs_scale rho - L resid_x0, the first
+  // residual of the next Hartree solve from its warm start (the arithmetic of the CG start)
+  double* resid;
+  const double* resid_x0;
+  int gnx, gny, gnz;
+  double inv_h2, rhs_scale;
 };
 void launch_combine(const CombineArgs& a, hipStream_t st);
 // Events for the next single-kernel combine launch of this host thread: that launch records
