@@ -766,65 +766,46 @@ __device__ inline void k_finish_eval_body(const FinishEvalArgs& ka, int ks_bid, 
     }
     en = *enuc;
   }
-  // all slots in one sweep: each thread keeps SL_COUNT running sums, so its loads of the
-  // different slots are independent and overlap
-  int mx = 0;
-#pragma unroll
-  for (int sl = 0; sl < SL_COUNT; ++sl) mx = nb.v[sl] > mx ? nb.v[sl] : mx;
-  double v[SL_COUNT];
-#pragma unroll
-  for (int sl = 0; sl < SL_COUNT; ++sl) v[sl] = 0.0;
-  for (int i = threadIdx.x; i < mx; i += blockDim.x) {
-    // clamped, unconditional loads: no branch separates them, so they issue together
-    double x[SL_COUNT];
-#pragma unroll
-    for (int sl = 0; sl < SL_COUNT; ++sl) {
-      const int n = nb.v[sl];
-      x[sl] = n > 0 ? part[(size_t)sl * stride + (i < n ? i : n - 1)] : 0.0;
-    }
-#pragma unroll
-    for (int sl = 0; sl < SL_COUNT; ++sl) v[sl] += (i < nb.v[sl]) ? x[sl] : 0.0;
-  }
-  double acc = 0.0, racc = 0.0;
-  const bool bbr = ka.bbr_R != nullptr && ls != nullptr;
-  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
-    const int i = e / p, j = e % p;
-    const double d = xx[i * pp + j] - (i == j ? 1.0 : 0.0);
-    acc += d * d;
-    // sum_ij (I - R)_ij (X_t^T D_t)_ij for the BB sums of a QR trial
-    if (bbr) racc += ((i == j ? 1.0 : 0.0) - ka.bbr_R[i * pp + j]) * ka.bbr_xtd[i * pp + j];
-  }
-  // all SL_COUNT + 2 block sums at once: independent shuffle trees per wavefront, one
-  // barrier, then one thread per value adds the wavefront sums in wavefront order
+  // one wavefront per value: slot w < SL_COUNT of the partials, then ||X^T X - I||_F^2 and
+  // (bbr) sum_ij (I - R)_ij (X_t^T D_t)_ij; each lane sums its entries in order, then one
+  // shuffle tree (a loop per wavefront keeps the code short: it runs once per launch and
+  // would otherwise wait on instruction fetch)
   constexpr int kNW = kFinishThreads / kWave;
-  __shared__ double wsum[SL_COUNT + 2][kNW];
+  static_assert(kNW >= SL_COUNT + 2, "one wavefront per value");
+  __shared__ double wres[kNW];
   const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  const bool bbr = ka.bbr_R != nullptr && ls != nullptr;
+  double v = 0.0;
+  if (wv < SL_COUNT) {
+    int n = 0;
 #pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) {
+    for (int sl = 0; sl < SL_COUNT; ++sl)
+      if (sl == wv) n = nb.v[sl];
+    const double* __restrict__ q = part + (size_t)wv * stride;
+#pragma unroll 8
+    for (int i = lane; i < n; i += kWave) v += q[i];
+  } else if (wv == SL_COUNT) {
+    for (int e = lane; e < p * p; e += kWave) {
+      const int i = e / p, j = e % p;
+      const double d = xx[i * pp + j] - (i == j ? 1.0 : 0.0);
+      v += d * d;
+    }
+  } else if (wv == SL_COUNT + 1 && bbr) {
+    for (int e = lane; e < p * p; e += kWave) {
+      const int i = e / p, j = e % p;
+      v += ((i == j ? 1.0 : 0.0) - ka.bbr_R[i * pp + j]) * ka.bbr_xtd[i * pp + j];
+    }
+  }
 #pragma unroll
-    for (int sl = 0; sl < SL_COUNT; ++sl) v[sl] += __shfl_down(v[sl], o, kWave);
-    acc += __shfl_down(acc, o, kWave);
-    racc += __shfl_down(racc, o, kWave);
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int sl = 0; sl < SL_COUNT; ++sl) wsum[sl][wv] = v[sl];
-    wsum[SL_COUNT][wv] = acc;
-    wsum[SL_COUNT + 1][wv] = racc;
-  }
-  __syncthreads();
-  __shared__ double orth, rxd;
-  if (threadIdx.x <= SL_COUNT + 1) {
-    double t = 0.0;
-    for (int i = 0; i < kNW; ++i) t += wsum[threadIdx.x][i];
-    if (threadIdx.x < SL_COUNT) red[threadIdx.x] = t;
-    else if (threadIdx.x == SL_COUNT) orth = t;
-    else rxd = t;
-  }
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
+  if (lane == 0) wres[wv] = v;
   __syncthreads();
   (void)sh;
   if (threadIdx.x != 0) return;
-  acc = orth;
+#pragma unroll
+  for (int sl = 0; sl < SL_COUNT; ++sl) red[sl] = wres[sl];
+  const double orth = wres[SL_COUNT], rxd = wres[SL_COUNT + 1];
+  double acc = orth;
   for (int sl = 0; sl < SL_COUNT; ++sl) sums[sl] = red[sl];
   if (ka.cgw) {
     // the CG start of the Hartree solve whose residual the exchange pass measured (the
