@@ -238,18 +238,30 @@ __device__ inline void k_xc_body(const XcArgs& ka, int ks_bid, int ks_nb) {
     ex += r * e;
     ee += r * ve;
   }
-  // all block sums with one barrier (each in block_sum's order)
-  __shared__ double shn[7 * (kBlock / kWave)];
-  double v[7] = {eh, ex, ee, et, eb, rr, bb};
-  block_sum_n<7>(v, shn);
-  write_partial(pt, SL_EH, lb, v[0]);
-  write_partial(pt, SL_EX, lb, v[1]);
-  write_partial(pt, SL_EXT, lb, v[2]);
-  write_partial(pt, SL_TF, lb, v[3]);
-  if (ka.vbc) write_partial(pt, SL_EBC, lb, v[4]);
-  if (cg_check) {
-    write_partial(pt, SL_CGRR, lb, v[5]);
-    write_partial(pt, SL_CGBB, lb, v[6]);
+  // the seven block sums: the values go through LDS and wavefront w sums values w and
+  // w + 4 (each lane over four threads in thread order, then one shuffle tree), so the
+  // code holds one tree instead of seven (it runs once per launch: instruction fetch)
+  constexpr int kNV = 7;
+  __shared__ double tv[kNV][kBlock];
+  tv[0][threadIdx.x] = eh;
+  tv[1][threadIdx.x] = ex;
+  tv[2][threadIdx.x] = ee;
+  tv[3][threadIdx.x] = et;
+  tv[4][threadIdx.x] = eb;
+  tv[5][threadIdx.x] = rr;
+  tv[6][threadIdx.x] = bb;
+  __syncthreads();
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  constexpr int kSlots[kNV] = {SL_EH, SL_EX, SL_EXT, SL_TF, SL_EBC, SL_CGRR, SL_CGBB};
+#pragma unroll 1
+  for (int k = w; k < kNV; k += kBlock / kWave) {
+    double v = 0.0;
+#pragma unroll
+    for (int i = lane; i < kBlock; i += kWave) v += tv[k][i];
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
+    const bool wanted = k < 4 || (k == 4 && ka.vbc) || (k > 4 && cg_check);
+    if (lane == 0 && wanted) pt.buf[(size_t)kSlots[k] * pt.stride + lb] = v;
   }
   (void)sh;
 }
