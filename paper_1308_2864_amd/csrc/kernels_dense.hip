@@ -506,16 +506,11 @@ __device__ inline void combine_tiles(const CombineArgs& a, double* lds, int t_be
       if (resid && q == 0 && rok) {
         // b - L x0 with the CG start's arithmetic: b = 4 pi rhs_scale rho,
         // L x0 = (6 x0 - sum of neighbours) / h^2
+        // (a neighbour outside the grid was loaded as 0.0, and adding it changes no sum)
         const double* v = f.v0;
-        const int nx = a.gnx, ny = a.gny, sz = nx * ny;
-        const int i = row % nx, j = (row / nx) % ny, k = row / sz;
         double nb = 0.0;
-        if (i > 0) nb += v[1];
-        if (i < nx - 1) nb += v[2];
-        if (j > 0) nb += v[3];
-        if (j < ny - 1) nb += v[4];
-        if (k > 0) nb += v[5];
-        if (k < a.gnz - 1) nb += v[6];
+#pragma unroll
+        for (int e = 1; e < 7; ++e) nb += v[e];
         const double b = 4.0 * kPi * a.rhs_scale * rv;
         a.resid[row] = b - (6.0 * v[0] - nb) * a.inv_h2;
       }

@@ -867,6 +867,13 @@ __device__ inline void k_finish_eval_body(const FinishEvalArgs& ka, int ks_bid, 
   o.nonfinite = (!isfinite(o.total) || !isfinite(o.g2)) ? 1 : 0;
   *out = o;
   if (ls) ls_judge(&o, ls, s0, prm, cg && !cg_done);
+  if (ka.mirror) {
+    // this thread's own writes above are the latest values of the records it copies
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2* src = static_cast<const d2*>(ka.mirror_src);
+    d2* dst = static_cast<d2*>(ka.mirror);
+    for (int i = 0; i < ka.mirror_bytes / 16; ++i) dst[i] = src[i];
+  }
 }
 
 __global__ __launch_bounds__(1024) void k_finish_eval(FinishEvalArgs ka) {
@@ -1225,13 +1232,14 @@ void launch_finish_eval(const double* part, int stride, const int* nblk, double*
                         const double* enuc, const CgState* cg, EvalOut* out, LsState* ls,
                         const LsParams* prm, hipStream_t st, CgState* cgw, double htol,
                         int hmaxit, const double* ebc, const double* bbr_R,
-                        const double* bbr_xtd) {
+                        const double* bbr_xtd, void* mirror, const void* mirror_src,
+                        int mirror_bytes) {
   ScalarCounts nb{};
   for (int i = 0; i < SL_COUNT; ++i) nb.v[i] = nblk[i];
   hipLaunchKernelGGL(k_finish_eval, dim3(1), dim3(kFinishThreads), 0, st,
                      FinishEvalArgs{part, stride, nb, sums, gram_xx, p, pp, f, dV, enuc, cg, out,
                          ls, prm ? *prm : LsParams{}, cgw, htol, hmaxit, ebc, bbr_R,
-                         bbr_xtd});
+                         bbr_xtd, mirror, mirror_src, mirror_bytes});
 }
 
 void launch_set_scalar(double* dst, double v, hipStream_t st) {

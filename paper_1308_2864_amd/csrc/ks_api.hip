@@ -130,6 +130,8 @@ struct ks_system {
   int gram_nchunks = 1;
   // pinned host mirror of the scalar records
   void* host = nullptr;
+  void* host_dev = nullptr;     // the device's address of host (kernels write the mirror)
+  bool mirror_written = false;  // the last summary wrote the CG and line-search records there
   std::string err;
   int last_cg_iters = 0;
   int pcg_extra = 0;     // PCG iterations queued after the exact step of a trial's solve
@@ -478,7 +480,11 @@ int readback_cg_ls_ahead(ks_system* s, int c) {
   const int t = 1 - c;
   const int pp2 = s->pp * s->pp;
   const size_t bytes = reinterpret_cast<char*>(s->ls + 1) - reinterpret_cast<char*>(s->cg);
-  hipError_t e = hipMemcpyAsync(s->host, s->cg, bytes, hipMemcpyDeviceToHost, s->st);
+  // the summary kernel of the trial wrote the records into the host mirror itself
+  hipError_t e = s->mirror_written
+                     ? hipSuccess
+                     : hipMemcpyAsync(s->host, s->cg, bytes, hipMemcpyDeviceToHost, s->st);
+  s->mirror_written = false;
   if (e == hipSuccess && !s->ev_rb) e = hipEventCreateWithFlags(&s->ev_rb, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventRecord(s->ev_rb, s->st);
   if (e == hipSuccess) {
@@ -800,11 +806,16 @@ int evaluate_tail(ks_system* s, int idx, int bb_ref, bool want_gxd, bool want_gg
   nblk[SL_DEFECT] = defect ? bf16_defect_blocks(s->p) : 0;
   nblk[SL_CGRR] = nblk[SL_CGBB] = fuse_cg ? scalar_blocks(s->n) : 0;
   nblk[SL_EBC] = s->vbc ? scalar_blocks(s->n) : 0;
+  // a judged trial also writes its CG and line-search records into the host mirror
+  const bool mirror = judge != nullptr && s->host_dev != nullptr;
   launch_finish_eval(s->spart, kPartStride, nblk, s->sums[idx], s->gxg[idx], s->p, s->pp, s->f,
                      s->grid.dV, s->enuc, s->use_h ? s->cg : nullptr, s->ev[idx],
                      judge ? s->ls : nullptr, judge, s->st, fuse_cg ? s->cg : nullptr, s->htol,
                      s->hmaxit, s->ebc, bbr ? s->Rq : nullptr,
-                     bbr ? s->gxd[idx] + s->pp * s->pp : nullptr);
+                     bbr ? s->gxd[idx] + s->pp * s->pp : nullptr,
+                     mirror ? s->host_dev : nullptr, s->cg,
+                     (int)(reinterpret_cast<char*>(s->ls + 1) - reinterpret_cast<char*>(s->cg)));
+  s->mirror_written = mirror;
   tend(s, KS_PH_SMALL);
   return launch_check(s, "evaluate");
 }
@@ -1842,6 +1853,10 @@ int ks_create_system(const ks_system_desc* d, void* dev_workspace, size_t ws_byt
     return fail(nullptr, KS_E_HIP, "pinned host buffer");
   }
   std::memset(s->host, 0, kHostBytes);
+  if (hipHostGetDevicePointer(&s->host_dev, s->host, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    s->host_dev = nullptr;  // the records are then copied
+  }
   const int M = d->n_nuclei;
   hipError_t e = hipSuccess;
   if (M > 0) {

@@ -703,6 +703,11 @@ struct FinishEvalArgs {
   // R (p_p x p_p, the trial's Cholesky factor) and X_t^T D_t (p_p x p_p)
   const double* bbr_R;
   const double* bbr_xtd;
+  // optional: mirror_bytes (a multiple of 16) from mirror_src copied to mirror (host memory
+  // mapped for the device) at the end, after the records are written
+  void* mirror;
+  const void* mirror_src;
+  int mirror_bytes;
 };
 
 
@@ -735,7 +740,9 @@ void launch_finish_eval(const double* part, int stride, const int* nblk, double*
                         const double* enuc, const CgState* cg, EvalOut* out, LsState* ls,
                         const LsParams* prm, hipStream_t st, CgState* cgw = nullptr,
                         double htol = 0.0, int hmaxit = 0, const double* ebc = nullptr,
-                        const double* bbr_R = nullptr, const double* bbr_xtd = nullptr);
+                        const double* bbr_R = nullptr, const double* bbr_xtd = nullptr,
+                        void* mirror = nullptr, const void* mirror_src = nullptr,
+                        int mirror_bytes = 0);
 void launch_set_scalar(double* dst, double v, hipStream_t st);
 void launch_qr_factor_batch(const BatchPtrs<QrFactor2dArgs>& b, int p_max, hipStream_t st);
 void launch_finish_eval_batch(const BatchPtrs<FinishEvalArgs>& b, hipStream_t st);
