@@ -33,7 +33,8 @@
  * - Memory.  The caller owns every device buffer, including the workspace handed
  *   to ks_create_system; the library never allocates or frees device memory.
  *   The library allocates a 9 KiB pinned host buffer per system for scalar
- *   read-back (freed by ks_destroy_system).
+ *   read-back (freed by ks_destroy_system); the device writes the records of a line-search
+ *   trial into it directly.
  * - Streams.  Work of a system is issued on the HIP stream given at creation.  All
  *   calls below return after that stream has finished the call's work
  *   (synchronous), unless stated otherwise.  One system handle must not be used
