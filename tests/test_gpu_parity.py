@@ -413,9 +413,11 @@ def test_minimize_matches_oracle_pcg_fd(kind):
 
 @pytest.mark.parametrize("kind", ["qr", "wy"])
 def test_minimize_p32_first_steps_match_oracle(kind):
-    """p = 32 (c2's width): the Hamiltonian pass forms X^T X and X^T G itself (QR) and the
-    gradient combine forms X^T D and D^T D; eight steps of Alg. 3 from the same start follow
-    the oracle's eight steps (the trajectories agree to rounding this early)."""
+    """p = 32 (c2's width): the Hamiltonian pass forms X^T X and X^T G itself (QR), the
+    gradient combine forms D^T D (X^T D = X^T G + (X^T X) W from the reduced blocks) and the
+    BB sums come without a pass over X_k (Section 3 eq. (bb-1) through the QR factor of the
+    trial); eight steps of Alg. 3 from the same start follow the oracle's eight steps (the
+    trajectories agree to rounding this early)."""
     K = ks()
     spec = synth.make_system(16, 14, 12, 0.6, 32, 6, seed=4, zrange=(2, 4), margin=1.5,
                              min_spacing=1.0)
@@ -428,6 +430,32 @@ def test_minimize_p32_first_steps_match_oracle(kind):
     ref = optm.minimize(orc.energy_grad, X0, optm.Params(eps_g=1e-12, stagnation_tol=0.0,
                                                          max_iter=8, retraction=kind))
     assert r.iters == ref.iters == 8 and r.nfe == ref.nfe
+    assert abs(r.energy - ref.E) <= 1e-12 * abs(ref.E)
+    assert abs(r.grad_norm - ref.gnorm) <= 1e-8 * ref.gnorm
+    assert np.max(np.abs(host(X) - ref.X)) <= 1e-9
+    assert r.terms.orth_error < 1e-12
+
+
+@pytest.mark.parametrize("p", [13, 24])
+def test_minimize_ragged_p_first_steps_match_oracle(p):
+    """Widths that leave padded columns in the last 16-column tile (p_p = 16 and 32): the
+    QR trial's BB sums from the retraction and gradient passes and the factor R, and X^T D
+    formed from the reduced blocks, with the padded rows and columns of R, W and the Gram
+    blocks zero; six steps of Alg. 3 follow the oracle's six steps."""
+    K = ks()
+    spec = synth.make_system(14, 13, 12, 0.6, p, 5, seed=11, zrange=(2, 4), margin=1.5,
+                             min_spacing=1.0)
+    X0 = synth.make_x0(spec, 3)
+    sysg = K.system_from_spec(spec, hartree_solver=K.KS_HARTREE_PCG_FD)
+    X = dev(X0)
+    r = sysg.ks_minimize(X, K.ks_default_params(eps_g=1e-12, stagnation_tol=0.0, max_iter=6,
+                                                retraction=K.KS_QR))
+    orc = oracle_fd(spec)
+    ref = optm.minimize(orc.energy_grad, X0, optm.Params(eps_g=1e-12, stagnation_tol=0.0,
+                                                         max_iter=6, retraction="qr"))
+    print(f"p={p}: gpu E={r.energy:.15f} nfe={r.nfe}, oracle E={ref.E:.15f} nfe={ref.nfe}",
+          flush=True)
+    assert r.iters == ref.iters == 6 and r.nfe == ref.nfe
     assert abs(r.energy - ref.E) <= 1e-12 * abs(ref.E)
     assert abs(r.grad_norm - ref.gnorm) <= 1e-8 * ref.gnorm
     assert np.max(np.abs(host(X) - ref.X)) <= 1e-9
